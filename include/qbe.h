@@ -1,0 +1,226 @@
+/*
+ * qbe.h -- sliced bucket-elimination contraction of tensor networks
+ * (graphical-model form), MI355X / gfx950.
+ *
+ * The library computes sigma = sum over all variable assignments of the
+ * product of a network's tensors (Sec. 2.1, Eq. 1-2 of Schutski, Kolmakov,
+ * Khakhulin and Oseledets, "Simple heuristics for efficient parallel tensor
+ * contraction and quantum circuit simulation"), by bucket elimination along
+ * an elimination order (Eq. 2) after fixing a set mu of variables (Eq. 3),
+ * and sums the 2^|mu| independent slices (Eq. 4).  For a quantum circuit the
+ * network's sum is the amplitude <x|C|0^n>.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Variables are binary (dimension L = 2) and numbered 0 .. n_vars-1.
+ *  - A tensor of rank r over variables (v_0 .. v_{r-1}) holds 2^r complex
+ *    entries, row-major with v_0 the most significant index; complex data is
+ *    passed as interleaved (re, im) doubles.
+ *  - Slice s (0 <= s < 2^m) of a sliced set mu = (mu_0 .. mu_{m-1}) fixes
+ *    mu_j to bit j of s.
+ *  - Every call returns QBE_OK (0) or a negative QBE_ERR_* code; no C++
+ *    exception or abort crosses the ABI.  qbe_last_error() returns a
+ *    thread-local description of the last failure on the calling thread.
+ *  - Host arrays passed in are only read during the call; the library keeps
+ *    its own copies.  Output arrays are caller-allocated with the sizes given.
+ *  - Handles are opaque and owned by the caller until the matching destroy
+ *    call.  A handle may be used by one thread at a time.
+ */
+#ifndef QBE_H
+#define QBE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  QBE_OK = 0,
+  QBE_ERR_INVALID_ARG = -1, /* bad argument, inconsistent sizes or ids      */
+  QBE_ERR_OOM = -2,         /* host or device allocation failed            */
+  QBE_ERR_HIP = -3,         /* a HIP runtime call failed                   */
+  QBE_ERR_MEM_CAP = -4,     /* workspace too small / plan exceeds a cap    */
+  QBE_ERR_INTERNAL = -5,    /* library invariant violated (a bug)          */
+  QBE_ERR_NO_DEVICE = -6    /* no usable GPU for a device call             */
+};
+
+/* Scores for the greedy mu-treewidth deletion (Alg. 2). */
+enum {
+  QBE_SCORE_TREE_TRIMMING = 0, /* Sec. 3.2                                 */
+  QBE_SCORE_DEGREE = 1,        /* Sec. 3.1, number of neighbours            */
+  QBE_SCORE_TW_REDUCTION = 2   /* Sec. 3.1, Alg. 3 (direct width drop)      */
+};
+
+/* Device execution forms of a plan. */
+enum {
+  QBE_EXEC_AUTO = 0,       /* fused when a slice fits in LDS, else per-step */
+  QBE_EXEC_PER_STEP = 1,   /* one kernel launch per bucket, slices batched   */
+  QBE_EXEC_FUSED = 2       /* one persistent launch, a slice per workgroup,
+                              all intermediates in LDS                       */
+};
+
+/* Arithmetic of the bucket products on the device. */
+enum {
+  QBE_PREC_FP32 = 0,    /* complex64 products, FP32 accumulation            */
+  QBE_PREC_BF16X3 = 1   /* split-BF16 products (hi*hi + hi*lo + lo*hi),
+                           FP32 accumulation                                 */
+};
+
+typedef struct qbe_ctx qbe_ctx;
+typedef struct qbe_model qbe_model;
+typedef struct qbe_plan qbe_plan;
+typedef struct qbe_batch qbe_batch;
+
+typedef struct qbe_plan_opts {
+  int32_t exec;        /* QBE_EXEC_*                                         */
+  int32_t precision;   /* QBE_PREC_*                                         */
+  int32_t block;       /* threads per workgroup for per-step kernels; 0 = tuned */
+  int32_t reserved[5]; /* must be zero                                       */
+} qbe_plan_opts;
+
+typedef struct qbe_stats {
+  int32_t n_vars, n_tensors, m, width; /* width: largest |U_b| - 1          */
+  int32_t n_steps, n_levels;           /* levels: dependency depth of steps  */
+  int32_t exec;                        /* form chosen for this plan          */
+  int32_t lds_bytes;                   /* LDS per workgroup (fused form)     */
+  uint64_t flops_per_slice;            /* cost model, real flops             */
+  uint64_t bytes_per_slice;            /* algorithmic complex64 bytes        */
+  uint64_t peak_bytes_per_slice;       /* live-tensor peak                   */
+  uint64_t ws_bytes_min;               /* smallest workspace contract accepts */
+  uint64_t ws_bytes_all_slices;        /* workspace for all slices at once   */
+} qbe_stats;
+
+/* ------------------------------------------------------------------ misc -- */
+
+/* Thread-local text of the last error ("" if none).  Never NULL. */
+const char* qbe_last_error(void);
+/* Library ABI version (this header: 1). */
+int32_t qbe_version(void);
+
+/* ------------------------------------------------------------- context ---- */
+
+/* Binds device `device` and a borrowed HIP stream (hipStream_t passed as
+ * void*; NULL = the default stream).  All device work of calls that take
+ * the context is enqueued on that stream.  QBE_ERR_NO_DEVICE without a GPU. */
+int qbe_create(qbe_ctx** out, int32_t device, void* hip_stream);
+int qbe_destroy(qbe_ctx* ctx);
+/* Replaces the borrowed stream. */
+int qbe_set_stream(qbe_ctx* ctx, void* hip_stream);
+
+/* --------------------------------------------------------------- model ---- */
+
+/* The graphical model (Sec. 2.1): n_vars binary variables and n_tensors
+ * tensors.  rank[t] in [0, 30]; vars holds sum(rank) variable ids
+ * (tensor by tensor, no repeats within a tensor); data holds
+ * 2 * sum(2^rank[t]) doubles (interleaved re, im; tensor by tensor).
+ * Every variable must occur in at least one tensor.  All arrays are copied. */
+int qbe_model_create(int32_t n_vars, int32_t n_tensors, const int32_t* rank, const int32_t* vars,
+                     const double* data, qbe_model** out);
+int qbe_model_destroy(qbe_model* model);
+/* Replaces the tensor entries (same layout as qbe_model_create). */
+int qbe_model_set_data(qbe_model* model, const double* data);
+
+/* ------------------------------------------------------------- planning --- */
+
+/* Greedy min-fill elimination order of the model's simple graph (tensors
+ * are cliques, Sec. 2.2): fewest fill edges, then smallest degree, then
+ * smallest id.  order_out: n_vars entries. */
+int qbe_order_min_fill(const qbe_model* model, int32_t* order_out);
+
+/* Alg. 1 (Sec. 2.3): the largest number of not-yet-eliminated neighbours
+ * met while eliminating along `order` (n entries, a permutation of the
+ * vertices that are not in `removed`).  removed: n_removed vertex ids
+ * deleted from the graph first (may be NULL when n_removed == 0). */
+int qbe_width(const qbe_model* model, const int32_t* order, int32_t n, const int32_t* removed,
+              int32_t n_removed, int32_t* tau_out);
+
+/* App. A: the tree decomposition of the order, as its maximal cliques.
+ * Outputs: *n_bags; bag_offsets[n_bags + 1] (capacity n + 1) and bag_vars
+ * (capacity cap_vars; ids ascending inside a bag); parent[n_bags] (capacity
+ * n, -1 for a root).  Bags are listed by their earliest-eliminated vertex.
+ * QBE_ERR_MEM_CAP if cap_vars is too small (*n_bags still set). */
+int qbe_clique_tree(const qbe_model* model, const int32_t* order, int32_t n, int32_t* n_bags,
+                    int32_t* bag_offsets, int32_t* bag_vars, int64_t cap_vars, int32_t* parent);
+
+/* Alg. 2 (Sec. 3): greedy mu-treewidth deletion from the order `order`
+ * (n = n_vars entries).  m >= 0 removes exactly m variables; m < 0 removes
+ * variables until the width of the reduced order is <= target_width.
+ * score: QBE_SCORE_*.  Outputs: mu_out (capacity n), *m_out,
+ * reduced_order_out (capacity n; n - *m_out entries), *tau_out. */
+int qbe_slice(const qbe_model* model, const int32_t* order, int32_t n, int32_t m,
+              int32_t target_width, int32_t score, int32_t* mu_out, int32_t* m_out,
+              int32_t* reduced_order_out, int32_t* tau_out);
+
+/* Compiles the bucket schedule (Eq. 2) of the reduced order and the sliced
+ * set, the device programs and their memory layout.  ctx may be NULL for a
+ * host-only plan (stats and dump work, contraction calls fail with
+ * QBE_ERR_INVALID_ARG).  With a context the model's tensors are uploaded to
+ * device memory owned by the plan.  opts may be NULL (all defaults). */
+int qbe_plan_create(qbe_ctx* ctx, const qbe_model* model, const int32_t* reduced_order, int32_t n,
+                    const int32_t* mu, int32_t m, const qbe_plan_opts* opts, qbe_plan** out);
+int qbe_plan_destroy(qbe_plan* plan);
+/* Re-uploads tensor entries from the model (same structure) to the plan. */
+int qbe_plan_update_data(qbe_plan* plan, const qbe_model* model);
+int qbe_plan_stats(const qbe_plan* plan, qbe_stats* out);
+/* Canonical text of the schedule: order, mu, scalar inputs, free
+ * variables, then one line per bucket (eliminated variable, operands,
+ * U_b and result variables).  Writes min(cap, len + 1) bytes (NUL
+ * terminated when it fits); *len_out = full length without the NUL. */
+int qbe_plan_dump(const qbe_plan* plan, char* buf, size_t cap, size_t* len_out);
+
+/* ------------------------------------------------------------ contraction - */
+
+/* Contracts all 2^m slices and sums them (Eq. 4) in FP64.  d_workspace is a
+ * caller-owned device buffer of ws_bytes >= stats.ws_bytes_min (more lets
+ * more slices run concurrently).  Blocks until the amplitude is on the host:
+ * amp_out[0] = re, amp_out[1] = im. */
+int qbe_contract(qbe_ctx* ctx, const qbe_plan* plan, void* d_workspace, size_t ws_bytes,
+                 double* amp_out);
+
+/* Contracts slices [s_begin, s_end) only; partial_out gets their FP64 sum
+ * (2 doubles), per_slice_out (optional, 2 * (s_end - s_begin) doubles) each
+ * slice's value. */
+int qbe_contract_slices(qbe_ctx* ctx, const qbe_plan* plan, int64_t s_begin, int64_t s_end,
+                        void* d_workspace, size_t ws_bytes, double* partial_out,
+                        double* per_slice_out);
+
+/* Enqueues the contraction of all slices without waiting: the FP64 result
+ * (2 doubles) is written to device memory d_amp_out.  No host
+ * synchronisation, allocation or copy happens inside, so the call may be
+ * captured into a HIP graph; the workspace must stay untouched until the
+ * stream has passed the call. */
+int qbe_contract_async(qbe_ctx* ctx, const qbe_plan* plan, void* d_workspace, size_t ws_bytes,
+                       double* d_amp_out);
+
+/* ---------------------------------------------------------------- batch - */
+
+/* A set of independent plans (instances, e.g. circuits of uneven size)
+ * contracted together.  Plans in the fused form share one persistent
+ * launch: its (instance, slice) work items are pulled by a grid of
+ * workgroups from a counter, biggest instances first.  Plans in the
+ * per-step form (too wide for LDS) follow on the same stream.  The plans
+ * must outlive the batch.  The work-item table is uploaded here. */
+int qbe_batch_create(qbe_ctx* ctx, const qbe_plan* const* plans, int32_t n_plans, qbe_batch** out);
+int qbe_batch_destroy(qbe_batch* batch);
+/* Workspace bytes qbe_batch_contract_async needs. */
+int qbe_batch_workspace(const qbe_batch* batch, size_t* ws_bytes_out);
+/* Enqueues the batch: instance i's slices are summed in FP64 into
+ * d_amps_out[2 i], d_amps_out[2 i + 1] (device memory).  No allocation, copy
+ * or synchronisation inside, so the call may be captured into a HIP graph. */
+int qbe_batch_contract_async(qbe_ctx* ctx, const qbe_batch* batch, void* d_workspace, size_t ws_bytes,
+                             double* d_amps_out);
+
+/* ----------------------------------------------------------- diagnostics - */
+
+/* Verifies on the host that every index the plan's device programs can form
+ * stays inside the buffer it addresses (prepared inputs, arena, LDS).
+ * QBE_OK or QBE_ERR_INTERNAL with the first violation in qbe_last_error().
+ * qbe_plan_create runs the same check before uploading anything. */
+int qbe_plan_check(const qbe_plan* plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QBE_H */

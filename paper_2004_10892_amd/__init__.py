@@ -1,0 +1,346 @@
+"""Python binding of libqbe (include/qbe.h): sliced bucket-elimination
+contraction of tensor networks on MI355X.
+
+This module only marshals arguments: every planning step runs in the C++
+host planner and every contraction step in the library's HIP kernels.  The
+names mirror the C entry points (``qbe_order_min_fill`` ...).  PyTorch is
+used only to allocate device workspaces and to obtain the current HIP
+stream.  There is no fallback: if ``libqbe.so`` is missing, importing this
+package fails.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqbe.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; g.build()'` "
+        "from the repository root")
+
+_lib = C.CDLL(LIB_PATH)
+
+QBE_OK = 0
+ERRORS = {-1: "INVALID_ARG", -2: "OOM", -3: "HIP", -4: "MEM_CAP", -5: "INTERNAL", -6: "NO_DEVICE"}
+SCORE = {"tree_trimming": 0, "degree": 1, "tw_reduction": 2}
+EXEC = {"auto": 0, "per_step": 1, "fused": 2}
+PREC = {"fp32": 0, "bf16x3": 1}
+
+_i32p = C.POINTER(C.c_int32)
+_f64p = C.POINTER(C.c_double)
+_vp = C.c_void_p
+
+
+class QbeError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = _lib.qbe_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class PlanOpts(C.Structure):
+    _fields_ = [("exec", C.c_int32), ("precision", C.c_int32), ("block", C.c_int32),
+                ("reserved", C.c_int32 * 5)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_vars", C.c_int32), ("n_tensors", C.c_int32), ("m", C.c_int32), ("width", C.c_int32),
+                ("n_steps", C.c_int32), ("n_levels", C.c_int32), ("exec", C.c_int32), ("lds_bytes", C.c_int32),
+                ("flops_per_slice", C.c_uint64), ("bytes_per_slice", C.c_uint64),
+                ("peak_bytes_per_slice", C.c_uint64), ("ws_bytes_min", C.c_uint64),
+                ("ws_bytes_all_slices", C.c_uint64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_SIGS = {
+    "qbe_last_error": (C.c_char_p, []),
+    "qbe_version": (C.c_int32, []),
+    "qbe_create": (C.c_int, [C.POINTER(_vp), C.c_int32, _vp]),
+    "qbe_destroy": (C.c_int, [_vp]),
+    "qbe_set_stream": (C.c_int, [_vp, _vp]),
+    "qbe_model_create": (C.c_int, [C.c_int32, C.c_int32, _i32p, _i32p, _f64p, C.POINTER(_vp)]),
+    "qbe_model_destroy": (C.c_int, [_vp]),
+    "qbe_model_set_data": (C.c_int, [_vp, _f64p]),
+    "qbe_order_min_fill": (C.c_int, [_vp, _i32p]),
+    "qbe_width": (C.c_int, [_vp, _i32p, C.c_int32, _i32p, C.c_int32, _i32p]),
+    "qbe_clique_tree": (C.c_int, [_vp, _i32p, C.c_int32, _i32p, _i32p, _i32p, C.c_int64, _i32p]),
+    "qbe_slice": (C.c_int, [_vp, _i32p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _i32p, _i32p, _i32p, _i32p]),
+    "qbe_plan_create": (C.c_int, [_vp, _vp, _i32p, C.c_int32, _i32p, C.c_int32, C.POINTER(PlanOpts), C.POINTER(_vp)]),
+    "qbe_plan_destroy": (C.c_int, [_vp]),
+    "qbe_plan_update_data": (C.c_int, [_vp, _vp]),
+    "qbe_plan_stats": (C.c_int, [_vp, C.POINTER(Stats)]),
+    "qbe_plan_dump": (C.c_int, [_vp, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]),
+    "qbe_plan_check": (C.c_int, [_vp]),
+    "qbe_contract": (C.c_int, [_vp, _vp, _vp, C.c_size_t, _f64p]),
+    "qbe_contract_slices": (C.c_int, [_vp, _vp, C.c_int64, C.c_int64, _vp, C.c_size_t, _f64p, _f64p]),
+    "qbe_contract_async": (C.c_int, [_vp, _vp, _vp, C.c_size_t, _vp]),
+    "qbe_batch_create": (C.c_int, [_vp, C.POINTER(_vp), C.c_int32, C.POINTER(_vp)]),
+    "qbe_batch_destroy": (C.c_int, [_vp]),
+    "qbe_batch_workspace": (C.c_int, [_vp, C.POINTER(C.c_size_t)]),
+    "qbe_batch_contract_async": (C.c_int, [_vp, _vp, _vp, C.c_size_t, _vp]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = sorted(_SIGS)
+
+
+def _check(rc: int, where: str):
+    if rc != QBE_OK:
+        raise QbeError(rc, where)
+
+
+def _i32(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+
+
+def _p32(a: np.ndarray):
+    return a.ctypes.data_as(_i32p)
+
+
+def qbe_version() -> int:
+    return int(_lib.qbe_version())
+
+
+# --------------------------------------------------------------------- ctx --
+
+class Context:
+    """A device and a borrowed HIP stream (torch's current stream by default)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch  # device memory and streams only
+
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self._stream = stream
+        h = _vp()
+        _check(_lib.qbe_create(C.byref(h), device, _vp(stream.cuda_stream)), "qbe_create")
+        self.handle = h
+
+    def set_stream(self, stream):
+        self._stream = stream
+        _check(_lib.qbe_set_stream(self.handle, _vp(stream.cuda_stream)), "qbe_set_stream")
+
+    def close(self):
+        if self.handle:
+            _lib.qbe_destroy(self.handle)
+            self.handle = None
+
+    __del__ = close
+
+
+# ------------------------------------------------------------------- model --
+
+class Model:
+    """Graphical model: n_vars binary variables and tensors (vars, data)."""
+
+    def __init__(self, n_vars: int, tensors: Sequence[Tuple[Sequence[int], np.ndarray]]):
+        self.n_vars = int(n_vars)
+        self.tensor_vars = [tuple(int(v) for v in vs) for vs, _ in tensors]
+        rank = _i32([len(v) for v in self.tensor_vars])
+        flat = _i32([v for vs in self.tensor_vars for v in vs])
+        data = self._data(tensors)
+        h = _vp()
+        _check(_lib.qbe_model_create(self.n_vars, len(rank), _p32(rank), _p32(flat),
+                                     data.ctypes.data_as(_f64p), C.byref(h)), "qbe_model_create")
+        self.handle = h
+
+    @staticmethod
+    def _data(tensors) -> np.ndarray:
+        parts = [np.ascontiguousarray(np.asarray(d, dtype=np.complex128)).reshape(-1) for _, d in tensors]
+        if not parts:
+            return np.zeros(2)
+        return np.ascontiguousarray(np.concatenate(parts).view(np.float64))
+
+    @classmethod
+    def from_circuitgen(cls, m) -> "Model":
+        return cls(m.n_vars, m.tensors)
+
+    def set_data(self, tensors):
+        data = self._data(tensors)
+        _check(_lib.qbe_model_set_data(self.handle, data.ctypes.data_as(_f64p)), "qbe_model_set_data")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.qbe_model_destroy(self.handle)
+            self.handle = None
+
+    __del__ = close
+
+
+# ---------------------------------------------------------------- planning --
+
+def qbe_order_min_fill(model: Model) -> List[int]:
+    out = np.zeros(model.n_vars, dtype=np.int32)
+    _check(_lib.qbe_order_min_fill(model.handle, _p32(out)), "qbe_order_min_fill")
+    return out.tolist()
+
+
+def qbe_width(model: Model, order: Sequence[int], removed: Sequence[int] = ()) -> int:
+    o = _i32(order)
+    r = _i32(removed)
+    tau = C.c_int32()
+    _check(_lib.qbe_width(model.handle, _p32(o), len(o), _p32(r), len(r), C.byref(tau)), "qbe_width")
+    return tau.value
+
+
+def qbe_clique_tree(model: Model, order: Sequence[int]):
+    o = _i32(order)
+    n = len(o)
+    nb = C.c_int32()
+    offs = np.zeros(n + 1, dtype=np.int32)
+    par = np.zeros(max(n, 1), dtype=np.int32)
+    cap = max(1, n * 4)
+    while True:
+        bv = np.zeros(cap, dtype=np.int32)
+        rc = _lib.qbe_clique_tree(model.handle, _p32(o), n, C.byref(nb), _p32(offs), _p32(bv), cap, _p32(par))
+        if rc == -4:
+            cap *= 4
+            continue
+        _check(rc, "qbe_clique_tree")
+        break
+    bags = [bv[offs[i]:offs[i + 1]].tolist() for i in range(nb.value)]
+    return bags, par[:nb.value].tolist()
+
+
+def qbe_slice(model: Model, order: Sequence[int], m: int, target_width: int = -1,
+              score: str = "tree_trimming"):
+    """Alg. 2.  Returns (mu, reduced_order, tau)."""
+    o = _i32(order)
+    n = len(o)
+    mu = np.zeros(max(n, 1), dtype=np.int32)
+    red = np.zeros(max(n, 1), dtype=np.int32)
+    mo = C.c_int32()
+    tau = C.c_int32()
+    _check(_lib.qbe_slice(model.handle, _p32(o), n, m, target_width, SCORE[score], _p32(mu), C.byref(mo),
+                          _p32(red), C.byref(tau)), "qbe_slice")
+    k = mo.value
+    return mu[:k].tolist(), red[:n - k].tolist(), tau.value
+
+
+# ------------------------------------------------------------------- plans --
+
+class Plan:
+    """Compiled schedule (and device programs when a context is given)."""
+
+    def __init__(self, model: Model, reduced_order: Sequence[int], mu: Sequence[int],
+                 ctx: Optional[Context] = None, exec: str = "auto", precision: str = "fp32"):
+        o = _i32(reduced_order)
+        u = _i32(mu)
+        opts = PlanOpts()
+        opts.exec = EXEC[exec]
+        opts.precision = PREC[precision]
+        h = _vp()
+        _check(_lib.qbe_plan_create(ctx.handle if ctx else None, model.handle, _p32(o), len(o), _p32(u), len(u),
+                                    C.byref(opts), C.byref(h)), "qbe_plan_create")
+        self.handle = h
+        self.ctx = ctx
+        self.model = model
+        self.n_slices = 1 << len(u)
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(_lib.qbe_plan_stats(self.handle, C.byref(s)), "qbe_plan_stats")
+        return s.as_dict()
+
+    def dump(self) -> str:
+        n = C.c_size_t()
+        _check(_lib.qbe_plan_dump(self.handle, None, 0, C.byref(n)), "qbe_plan_dump")
+        buf = C.create_string_buffer(n.value + 1)
+        _check(_lib.qbe_plan_dump(self.handle, buf, n.value + 1, C.byref(n)), "qbe_plan_dump")
+        return buf.value.decode()
+
+    def check(self):
+        _check(_lib.qbe_plan_check(self.handle), "qbe_plan_check")
+
+    def update_data(self, model: Model):
+        _check(_lib.qbe_plan_update_data(self.handle, model.handle), "qbe_plan_update_data")
+
+    def workspace(self, all_slices: bool = True):
+        """A device workspace (torch uint8 tensor) of the plan's size."""
+        import torch
+
+        st = self.stats()
+        n = st["ws_bytes_all_slices"] if all_slices else st["ws_bytes_min"]
+        return torch.empty(int(n), dtype=torch.uint8, device=f"cuda:{self.ctx.device}")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.qbe_plan_destroy(self.handle)
+            self.handle = None
+
+    __del__ = close
+
+
+def qbe_contract(ctx: Context, plan: Plan, ws) -> complex:
+    out = np.zeros(2)
+    _check(_lib.qbe_contract(ctx.handle, plan.handle, _vp(ws.data_ptr()), ws.numel(),
+                             out.ctypes.data_as(_f64p)), "qbe_contract")
+    return complex(out[0], out[1])
+
+
+def qbe_contract_slices(ctx: Context, plan: Plan, s_begin: int, s_end: int, ws):
+    """Returns (sum over the range, per-slice values as complex128 array)."""
+    part = np.zeros(2)
+    per = np.zeros(2 * (s_end - s_begin))
+    _check(_lib.qbe_contract_slices(ctx.handle, plan.handle, s_begin, s_end, _vp(ws.data_ptr()), ws.numel(),
+                                    part.ctypes.data_as(_f64p), per.ctypes.data_as(_f64p)), "qbe_contract_slices")
+    return complex(part[0], part[1]), per.view(np.complex128).copy()
+
+
+def qbe_contract_async(ctx: Context, plan: Plan, ws, d_out):
+    """Enqueues the contraction; d_out is a float64 device tensor of >= 2 entries."""
+    _check(_lib.qbe_contract_async(ctx.handle, plan.handle, _vp(ws.data_ptr()), ws.numel(),
+                                   _vp(d_out.data_ptr())), "qbe_contract_async")
+
+
+class Batch:
+    """Many plans contracted in one persistent fused launch."""
+
+    def __init__(self, ctx: Context, plans: Sequence[Plan]):
+        arr = (_vp * len(plans))(*[p.handle for p in plans])
+        h = _vp()
+        _check(_lib.qbe_batch_create(ctx.handle, arr, len(plans), C.byref(h)), "qbe_batch_create")
+        self.handle = h
+        self.ctx = ctx
+        self.plans = list(plans)
+        n = C.c_size_t()
+        _check(_lib.qbe_batch_workspace(h, C.byref(n)), "qbe_batch_workspace")
+        self.ws_bytes = n.value
+
+    def workspace(self):
+        import torch
+
+        return torch.empty(int(self.ws_bytes), dtype=torch.uint8, device=f"cuda:{self.ctx.device}")
+
+    def contract_async(self, ws, d_amps):
+        _check(_lib.qbe_batch_contract_async(self.ctx.handle, self.handle, _vp(ws.data_ptr()), ws.numel(),
+                                             _vp(d_amps.data_ptr())), "qbe_batch_contract_async")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.qbe_batch_destroy(self.handle)
+            self.handle = None
+
+    __del__ = close
+
+
+# ------------------------------------------------------------ conveniences --
+
+def plan_circuit(model: Model, m: int = 0, target_width: int = -1, score: str = "tree_trimming"):
+    """Host planning of one network: min-fill order, then Alg. 2.
+    Returns (order, mu, reduced_order, tau)."""
+    order = qbe_order_min_fill(model)
+    mu, red, tau = qbe_slice(model, order, m, target_width, score)
+    return order, mu, red, tau

@@ -1,0 +1,484 @@
+// C ABI of the library (declared in include/qbe.h).  Every entry point
+// catches all C++ exceptions and turns them into error codes.
+#include <algorithm>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <stdexcept>
+#include <string>
+
+#include "../../include/qbe.h"
+#include "qbe_internal.hpp"
+
+struct qbe_ctx {
+  int device = 0;
+  void* stream = nullptr;
+};
+
+struct qbe_model {
+  qbe::Model m;
+};
+
+struct qbe_plan {
+  qbe::Plan p;
+  qbe_ctx* ctx = nullptr;
+};
+
+struct qbe_batch {
+  qbe::Batch b;
+  qbe_ctx* ctx = nullptr;
+};
+
+namespace qbe {
+static thread_local std::string g_error;
+void set_error(const std::string& s) { g_error = s; }
+std::string check_plan(const Plan& p);  // program_check.cpp
+}  // namespace qbe
+
+using qbe::set_error;
+
+#define QBE_GUARD_BEGIN try {
+#define QBE_GUARD_END                                   \
+  }                                                     \
+  catch (const std::invalid_argument& e) {              \
+    set_error(e.what());                                \
+    return QBE_ERR_INVALID_ARG;                         \
+  }                                                     \
+  catch (const std::bad_alloc&) {                       \
+    set_error("host allocation failed");                \
+    return QBE_ERR_OOM;                                 \
+  }                                                     \
+  catch (const std::exception& e) {                     \
+    set_error(std::string("internal: ") + e.what());    \
+    return QBE_ERR_INTERNAL;                            \
+  }                                                     \
+  catch (...) {                                         \
+    set_error("internal: unknown exception");           \
+    return QBE_ERR_INTERNAL;                            \
+  }
+
+#define QBE_REQUIRE(cond, msg)        \
+  do {                                \
+    if (!(cond)) {                    \
+      set_error(msg);                 \
+      return QBE_ERR_INVALID_ARG;     \
+    }                                 \
+  } while (0)
+
+extern "C" {
+
+const char* qbe_last_error(void) { return qbe::g_error.c_str(); }
+int32_t qbe_version(void) { return 1; }
+
+// ------------------------------------------------------------------ context
+
+int qbe_create(qbe_ctx** out, int32_t device, void* hip_stream) {
+  QBE_GUARD_BEGIN
+  QBE_REQUIRE(out, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  if (qbe::dev_count(&n) != QBE_OK || n <= 0) {
+    set_error("no GPU device available");
+    return QBE_ERR_NO_DEVICE;
+  }
+  QBE_REQUIRE(device >= 0 && device < n, "device index out of range");
+  int rc = qbe::dev_set(device);
+  if (rc) return rc;
+  qbe_ctx* c = new qbe_ctx;
+  c->device = device;
+  c->stream = hip_stream;
+  *out = c;
+  return QBE_OK;
+  QBE_GUARD_END
+}
+
+int qbe_destroy(qbe_ctx* ctx) {
+  delete ctx;
+  return QBE_OK;
+}
+
+int qbe_set_stream(qbe_ctx* ctx, void* hip_stream) {
+  QBE_REQUIRE(ctx, "ctx is NULL");
+  ctx->stream = hip_stream;
+  return QBE_OK;
+}
+
+// -------------------------------------------------------------------- model
+
+static void fill_data(qbe::Model& m, const double* data) {
+  size_t total = 0;
+  for (const auto& vs : m.tvars) total += size_t(1) << vs.size();
+  m.data.assign(data, data + 2 * total);
+}
+
+int qbe_model_create(int32_t n_vars, int32_t n_tensors, const int32_t* rank, const int32_t* vars,
+                     const double* data, qbe_model** out) {
+  QBE_GUARD_BEGIN
+  QBE_REQUIRE(out, "out is NULL");
+  *out = nullptr;
+  QBE_REQUIRE(n_vars >= 0 && n_tensors >= 0, "negative sizes");
+  QBE_REQUIRE(n_tensors == 0 || (rank && data), "rank or data is NULL");
+  auto* md = new qbe_model;
+  qbe::Model& m = md->m;
+  m.n_vars = n_vars;
+  m.tvars.resize(n_tensors);
+  m.data_off.resize(n_tensors);
+  std::vector<uint8_t> used(n_vars, 0);
+  std::vector<int> stamp(n_vars, -1);
+  int64_t vp = 0, dp = 0;
+  for (int t = 0; t < n_tensors; ++t) {
+    if (rank[t] < 0 || rank[t] > 30) {
+      delete md;
+      set_error("tensor rank outside [0, 30]");
+      return QBE_ERR_INVALID_ARG;
+    }
+    if (rank[t] > 0 && !vars) {
+      delete md;
+      set_error("vars is NULL");
+      return QBE_ERR_INVALID_ARG;
+    }
+    for (int j = 0; j < rank[t]; ++j) {
+      int v = vars[vp + j];
+      if (v < 0 || v >= n_vars || stamp[v] == t) {
+        delete md;
+        set_error("variable id out of range or repeated within a tensor");
+        return QBE_ERR_INVALID_ARG;
+      }
+      stamp[v] = t;
+      used[v] = 1;
+      m.tvars[t].push_back(v);
+    }
+    m.data_off[t] = dp;
+    vp += rank[t];
+    dp += int64_t(1) << rank[t];
+    if (dp > (int64_t(1) << 31)) {
+      delete md;
+      set_error("model holds more than 2^31 complex entries");
+      return QBE_ERR_INVALID_ARG;
+    }
+  }
+  for (int v = 0; v < n_vars; ++v)
+    if (!used[v]) {
+      delete md;
+      set_error("variable " + std::to_string(v) + " occurs in no tensor");
+      return QBE_ERR_INVALID_ARG;
+    }
+  fill_data(m, data);
+  *out = md;
+  return QBE_OK;
+  QBE_GUARD_END
+}
+
+int qbe_model_destroy(qbe_model* model) {
+  delete model;
+  return QBE_OK;
+}
+
+int qbe_model_set_data(qbe_model* model, const double* data) {
+  QBE_GUARD_BEGIN
+  QBE_REQUIRE(model && data, "NULL argument");
+  fill_data(model->m, data);
+  return QBE_OK;
+  QBE_GUARD_END
+}
+
+// ----------------------------------------------------------------- planning
+
+static qbe::Graph graph_of(const qbe::Model& m) { return qbe::graph_from_tensors(m.n_vars, m.tvars); }
+
+static std::vector<int> vec(const int32_t* p, int32_t n) {
+  if (n < 0) throw std::invalid_argument("negative length");
+  if (n > 0 && !p) throw std::invalid_argument("NULL array");
+  return std::vector<int>(p, p + n);
+}
+
+int qbe_order_min_fill(const qbe_model* model, int32_t* order_out) {
+  QBE_GUARD_BEGIN
+  QBE_REQUIRE(model && (order_out || model->m.n_vars == 0), "NULL argument");
+  auto order = qbe::min_fill_order(graph_of(model->m));
+  for (size_t i = 0; i < order.size(); ++i) order_out[i] = order[i];
+  return QBE_OK;
+  QBE_GUARD_END
+}
+
+int qbe_width(const qbe_model* model, const int32_t* order, int32_t n, const int32_t* removed,
+              int32_t n_removed, int32_t* tau_out) {
+  QBE_GUARD_BEGIN
+  QBE_REQUIRE(model && tau_out, "NULL argument");
+  qbe::Graph g = graph_of(model->m);
+  for (int v : vec(removed, n_removed)) {
+    QBE_REQUIRE(v >= 0 && v < g.n && g.present[v], "bad removed vertex");
+    g.remove_vertex(v);
+  }
+  *tau_out = qbe::width_of_order(g, vec(order, n));
+  return QBE_OK;
+  QBE_GUARD_END
+}
+
+int qbe_clique_tree(const qbe_model* model, const int32_t* order, int32_t n, int32_t* n_bags,
+                    int32_t* bag_offsets, int32_t* bag_vars, int64_t cap_vars, int32_t* parent) {
+  QBE_GUARD_BEGIN
+  QBE_REQUIRE(model && n_bags && bag_offsets && parent, "NULL argument");
+  qbe::CliqueTree ct = qbe::clique_tree(graph_of(model->m), vec(order, n));
+  *n_bags = (int32_t)ct.bags.size();
+  int64_t total = 0;
+  for (const auto& b : ct.bags) total += (int64_t)b.size();
+  if (total > cap_vars || !bag_vars) {
+    set_error("bag_vars capacity too small");
+    return QBE_ERR_MEM_CAP;
+  }
+  int64_t o = 0;
+  for (size_t i = 0; i < ct.bags.size(); ++i) {
+    bag_offsets[i] = (int32_t)o;
+    for (int v : ct.bags[i]) bag_vars[o++] = v;
+    parent[i] = ct.parent[i];
+  }
+  bag_offsets[ct.bags.size()] = (int32_t)o;
+  return QBE_OK;
+  QBE_GUARD_END
+}
+
+int qbe_slice(const qbe_model* model, const int32_t* order, int32_t n, int32_t m, int32_t target_width,
+              int32_t score, int32_t* mu_out, int32_t* m_out, int32_t* reduced_order_out,
+              int32_t* tau_out) {
+  QBE_GUARD_BEGIN
+  QBE_REQUIRE(model && m_out && tau_out, "NULL argument");
+  QBE_REQUIRE(n == model->m.n_vars, "order must list every variable");
+  QBE_REQUIRE(m <= n, "m larger than the number of variables");
+  auto d = qbe::greedy_deletion(graph_of(model->m), vec(order, n), m, target_width, score);
+  QBE_REQUIRE(d.mu.empty() || mu_out, "mu_out is NULL");
+  QBE_REQUIRE(d.reduced_order.empty() || reduced_order_out, "reduced_order_out is NULL");
+  for (size_t i = 0; i < d.mu.size(); ++i) mu_out[i] = d.mu[i];
+  for (size_t i = 0; i < d.reduced_order.size(); ++i) reduced_order_out[i] = d.reduced_order[i];
+  *m_out = (int32_t)d.mu.size();
+  *tau_out = d.tau;
+  return QBE_OK;
+  QBE_GUARD_END
+}
+
+// -------------------------------------------------------------------- plans
+
+int qbe_plan_create(qbe_ctx* ctx, const qbe_model* model, const int32_t* reduced_order, int32_t n,
+                    const int32_t* mu, int32_t m, const qbe_plan_opts* opts, qbe_plan** out) {
+  QBE_GUARD_BEGIN
+  QBE_REQUIRE(model && out, "NULL argument");
+  *out = nullptr;
+  qbe_plan_opts o{};
+  if (opts) o = *opts;
+  for (int r : o.reserved) QBE_REQUIRE(r == 0, "reserved option fields must be zero");
+  QBE_REQUIRE(o.exec >= QBE_EXEC_AUTO && o.exec <= QBE_EXEC_FUSED, "bad exec form");
+  QBE_REQUIRE(o.precision == QBE_PREC_FP32 || o.precision == QBE_PREC_BF16X3, "bad precision");
+  QBE_REQUIRE(o.block == 0 || o.block == qbe::kBlock, "unsupported block size");
+  auto* pl = new qbe_plan;
+  std::unique_ptr<qbe_plan> guard(pl);
+  qbe::Plan& p = pl->p;
+  p.model = model->m;
+  p.sched = qbe::build_schedule(p.model.n_vars, p.model.tvars, vec(reduced_order, n), vec(mu, m));
+  p.cost = qbe::schedule_cost(p.sched);
+  p.precision = o.precision;
+  qbe::compile_plan(p);
+  if (o.exec == QBE_EXEC_FUSED && !p.fused_ok) {
+    set_error("plan does not fit the fused (LDS-resident) form");
+    return QBE_ERR_MEM_CAP;
+  }
+  p.exec = (o.exec == QBE_EXEC_PER_STEP || !p.fused_ok) ? QBE_EXEC_PER_STEP : QBE_EXEC_FUSED;
+  if (p.precision == QBE_PREC_BF16X3 && p.exec == QBE_EXEC_FUSED && o.exec == QBE_EXEC_AUTO)
+    p.exec = QBE_EXEC_PER_STEP;
+  std::string bad = qbe::check_plan(p);
+  if (!bad.empty()) {
+    set_error("internal: plan check failed: " + bad);
+    return QBE_ERR_INTERNAL;
+  }
+  if (ctx) {
+    int rc = qbe::dev_set(ctx->device);
+    if (rc) return rc;
+    p.device = ctx->device;
+    rc = qbe::dev_upload_plan(p);
+    if (rc) {
+      qbe::dev_free_plan(p);
+      return rc;
+    }
+    pl->ctx = ctx;
+  }
+  *out = guard.release();
+  return QBE_OK;
+  QBE_GUARD_END
+}
+
+int qbe_plan_destroy(qbe_plan* plan) {
+  if (plan) {
+    if (plan->ctx) {
+      (void)qbe::dev_set(plan->p.device);
+      qbe::dev_free_plan(plan->p);
+    }
+    delete plan;
+  }
+  return QBE_OK;
+}
+
+int qbe_plan_update_data(qbe_plan* plan, const qbe_model* model) {
+  QBE_GUARD_BEGIN
+  QBE_REQUIRE(plan && model, "NULL argument");
+  QBE_REQUIRE(model->m.tvars == plan->p.model.tvars, "model structure differs from the plan's");
+  plan->p.model.data = model->m.data;
+  if (plan->ctx) {
+    int rc = qbe::dev_set(plan->p.device);
+    if (rc) return rc;
+    return qbe::dev_update_data(plan->p);
+  }
+  return QBE_OK;
+  QBE_GUARD_END
+}
+
+int qbe_plan_stats(const qbe_plan* plan, qbe_stats* out) {
+  QBE_GUARD_BEGIN
+  QBE_REQUIRE(plan && out, "NULL argument");
+  const qbe::Plan& p = plan->p;
+  std::memset(out, 0, sizeof(*out));
+  out->n_vars = p.model.n_vars;
+  out->n_tensors = (int32_t)p.model.tvars.size();
+  out->m = p.m;
+  out->width = p.cost.width;
+  out->n_steps = (int32_t)p.sched.steps.size();
+  out->n_levels = p.n_levels;
+  out->exec = p.exec;
+  out->lds_bytes = p.exec == QBE_EXEC_FUSED ? p.fused_lds_bytes : 0;
+  out->flops_per_slice = p.cost.flops;
+  out->bytes_per_slice = p.cost.bytes;
+  out->peak_bytes_per_slice = p.cost.peak_bytes;
+  out->ws_bytes_min = qbe::dev_workspace_min(p, p.n_slices);
+  out->ws_bytes_all_slices = qbe::dev_workspace_all(p);
+  return QBE_OK;
+  QBE_GUARD_END
+}
+
+int qbe_plan_dump(const qbe_plan* plan, char* buf, size_t cap, size_t* len_out) {
+  QBE_GUARD_BEGIN
+  QBE_REQUIRE(plan && len_out, "NULL argument");
+  std::string s = qbe::dump_schedule(plan->p.sched);
+  *len_out = s.size();
+  if (buf && cap) {
+    size_t n = std::min(cap, s.size() + 1);
+    std::memcpy(buf, s.c_str(), n);
+  }
+  return QBE_OK;
+  QBE_GUARD_END
+}
+
+int qbe_plan_check(const qbe_plan* plan) {
+  QBE_GUARD_BEGIN
+  QBE_REQUIRE(plan, "NULL argument");
+  std::string bad = qbe::check_plan(plan->p);
+  if (!bad.empty()) {
+    set_error(bad);
+    return QBE_ERR_INTERNAL;
+  }
+  return QBE_OK;
+  QBE_GUARD_END
+}
+
+// -------------------------------------------------------------- contraction
+
+static int check_device_call(qbe_ctx* ctx, const qbe_plan* plan, void* ws) {
+  if (!ctx || !plan || !ws) {
+    set_error("NULL argument");
+    return QBE_ERR_INVALID_ARG;
+  }
+  if (!plan->ctx) {
+    set_error("plan was created without a device context");
+    return QBE_ERR_INVALID_ARG;
+  }
+  if (plan->p.device != ctx->device) {
+    set_error("plan belongs to another device");
+    return QBE_ERR_INVALID_ARG;
+  }
+  return qbe::dev_set(ctx->device);
+}
+
+int qbe_contract_async(qbe_ctx* ctx, const qbe_plan* plan, void* d_workspace, size_t ws_bytes,
+                       double* d_amp_out) {
+  QBE_GUARD_BEGIN
+  int rc = check_device_call(ctx, plan, d_workspace);
+  if (rc) return rc;
+  QBE_REQUIRE(d_amp_out, "d_amp_out is NULL");
+  return qbe::dev_contract(plan->p, ctx->stream, d_workspace, ws_bytes, 0, plan->p.n_slices, d_amp_out,
+                           nullptr);
+  QBE_GUARD_END
+}
+
+int qbe_contract_slices(qbe_ctx* ctx, const qbe_plan* plan, int64_t s_begin, int64_t s_end,
+                        void* d_workspace, size_t ws_bytes, double* partial_out, double* per_slice_out) {
+  QBE_GUARD_BEGIN
+  int rc = check_device_call(ctx, plan, d_workspace);
+  if (rc) return rc;
+  QBE_REQUIRE(partial_out, "partial_out is NULL");
+  QBE_REQUIRE(0 <= s_begin && s_begin < s_end && s_end <= plan->p.n_slices, "bad slice range");
+  char* w = (char*)d_workspace;
+  rc = qbe::dev_contract(plan->p, ctx->stream, d_workspace, ws_bytes, s_begin, s_end, (double*)w, nullptr);
+  if (rc) return rc;
+  rc = qbe::dev_memcpy_d2h(partial_out, w, 16, ctx->stream);
+  if (rc) return rc;
+  if (per_slice_out) rc = qbe::dev_memcpy_d2h(per_slice_out, w + 256, 16 * (size_t)(s_end - s_begin), ctx->stream);
+  return rc;
+  QBE_GUARD_END
+}
+
+int qbe_contract(qbe_ctx* ctx, const qbe_plan* plan, void* d_workspace, size_t ws_bytes, double* amp_out) {
+  QBE_GUARD_BEGIN
+  QBE_REQUIRE(plan, "NULL argument");
+  return qbe_contract_slices(ctx, plan, 0, plan->p.n_slices, d_workspace, ws_bytes, amp_out, nullptr);
+  QBE_GUARD_END
+}
+
+// -------------------------------------------------------------------- batch
+
+int qbe_batch_create(qbe_ctx* ctx, const qbe_plan* const* plans, int32_t n_plans, qbe_batch** out) {
+  QBE_GUARD_BEGIN
+  QBE_REQUIRE(ctx && plans && out && n_plans > 0, "bad argument");
+  *out = nullptr;
+  auto* b = new qbe_batch;
+  std::unique_ptr<qbe_batch> guard(b);
+  for (int i = 0; i < n_plans; ++i) {
+    QBE_REQUIRE(plans[i] && plans[i]->ctx && plans[i]->p.device == ctx->device, "bad plan in batch");
+    b->b.plans.push_back(&plans[i]->p);
+  }
+  int rc = qbe::dev_set(ctx->device);
+  if (rc) return rc;
+  rc = qbe::dev_batch_build(b->b);
+  if (rc) {
+    qbe::dev_batch_free(b->b);
+    return rc;
+  }
+  b->ctx = ctx;
+  *out = guard.release();
+  return QBE_OK;
+  QBE_GUARD_END
+}
+
+int qbe_batch_destroy(qbe_batch* batch) {
+  if (batch) {
+    (void)qbe::dev_set(batch->ctx->device);
+    qbe::dev_batch_free(batch->b);
+    delete batch;
+  }
+  return QBE_OK;
+}
+
+int qbe_batch_workspace(const qbe_batch* batch, size_t* ws_bytes_out) {
+  QBE_REQUIRE(batch && ws_bytes_out, "NULL argument");
+  *ws_bytes_out = qbe::dev_batch_workspace(batch->b);
+  return QBE_OK;
+}
+
+int qbe_batch_contract_async(qbe_ctx* ctx, const qbe_batch* batch, void* d_workspace, size_t ws_bytes,
+                             double* d_amps_out) {
+  QBE_GUARD_BEGIN
+  QBE_REQUIRE(ctx && batch && d_workspace && d_amps_out, "NULL argument");
+  QBE_REQUIRE(batch->ctx->device == ctx->device, "batch belongs to another device");
+  int rc = qbe::dev_set(ctx->device);
+  if (rc) return rc;
+  return qbe::dev_batch_contract(batch->b, ctx->stream, d_workspace, ws_bytes, d_amps_out);
+  QBE_GUARD_END
+}
+
+}  // extern "C"

@@ -1,0 +1,110 @@
+// Host planner: simple graph, greedy min-fill order, treewidth of an order
+// (Alg. 1), clique tree from an order (App. A), the tree-trimming, degree and
+// direct-treewidth scores (Sec. 3.1-3.2), greedy mu-treewidth deletion
+// (Alg. 2) and the bucket schedule of sliced bucket elimination (Eqs. 2-4).
+//
+// Graph vertices are the variables of the network; every tensor is a clique
+// over its variables; self-loops and parallel edges are dropped (Sec. 2.2).
+// All tie-breaks are deterministic (see each function) so that two
+// independent implementations agree exactly.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace qbe {
+
+// Dense bit-matrix adjacency over vertex ids [0, n).  A vertex can be
+// "absent" (deleted or not part of a reduced graph).
+struct Graph {
+  int n = 0;
+  int words = 0;
+  std::vector<uint64_t> bits;   // n * words
+  std::vector<uint8_t> present; // n
+
+  void init(int n_);
+  uint64_t* row(int v) { return bits.data() + (size_t)v * words; }
+  const uint64_t* row(int v) const { return bits.data() + (size_t)v * words; }
+  bool has(int a, int b) const { return (row(a)[b >> 6] >> (b & 63)) & 1ull; }
+  void add_edge(int a, int b);
+  int degree(int v) const;
+  void remove_vertex(int v);
+  std::vector<int> neighbours(int v) const;  // ascending ids
+  int count() const;
+};
+
+Graph graph_from_tensors(int n_vars, const std::vector<std::vector<int>>& tensor_vars);
+
+// Greedy min-fill: fewest fill edges, then smaller current degree, then
+// smaller id.
+std::vector<int> min_fill_order(const Graph& g);
+
+// N+(u) for every eliminated vertex, in elimination order (ids ascending).
+std::vector<std::vector<int>> eliminate(const Graph& g, const std::vector<int>& order);
+
+// Alg. 1: max |N(u)| over the elimination (0 for an edgeless graph).
+int width_of_order(const Graph& g, const std::vector<int>& order);
+
+struct CliqueTree {
+  std::vector<std::vector<int>> bags;  // maximal cliques, ids ascending,
+                                       // ordered by their earliest vertex
+  std::vector<int> parent;             // -1 for a root
+};
+// App. A read as: the maximal cliques {u} + N+(u) of the elimination, joined
+// through the elimination tree.
+CliqueTree clique_tree(const Graph& g, const std::vector<int>& order);
+
+enum Score { SCORE_TREE_TRIMMING = 0, SCORE_DEGREE = 1, SCORE_TW_REDUCTION = 2 };
+
+int tree_trimming_pick(const Graph& g, const std::vector<int>& order);
+int degree_pick(const Graph& g, const std::vector<int>& order);
+int tw_reduction_pick(const Graph& g, const std::vector<int>& order);
+
+struct Deletion {
+  std::vector<int> mu;             // in the order chosen
+  std::vector<int> reduced_order;  // order minus mu
+  int tau = 0;                     // width of the reduced order
+};
+// Alg. 2 without recomputing the order.  m >= 0: remove m vertices;
+// m < 0: remove until the width is <= target_width.
+Deletion greedy_deletion(const Graph& g, const std::vector<int>& order, int m, int target_width,
+                         int score);
+
+// ---------------------------------------------------------------- schedule --
+
+struct Operand {
+  char kind;              // 't' input tensor, 'r' intermediate
+  int id;                 // tensor id or step index
+  std::vector<int> vars;  // remaining variables (inputs: original order minus
+                          // sliced ones; intermediates: by position)
+};
+
+struct Step {
+  int var;                     // eliminated variable u
+  std::vector<Operand> ops;    // inputs by id, then intermediates by step
+  std::vector<int> uni;        // U_b sorted by position in the order
+  std::vector<int> out;        // U_b minus u
+};
+
+struct Schedule {
+  std::vector<int> order, mu;
+  std::vector<Step> steps;
+  std::vector<int> scalar_inputs, scalar_steps, free_vars;
+  std::vector<int> consumer;   // step index consuming step k's result (-1: scalar)
+};
+
+// Throws std::invalid_argument on inconsistent input.
+Schedule build_schedule(int n_vars, const std::vector<std::vector<int>>& tensor_vars,
+                        const std::vector<int>& order, const std::vector<int>& mu);
+
+std::string dump_schedule(const Schedule& s);
+
+// Per-slice cost of a schedule (complex64 bytes).
+struct ScheduleCost {
+  uint64_t flops = 0, bytes = 0, peak_bytes = 0;
+  int width = 0;
+};
+ScheduleCost schedule_cost(const Schedule& s);
+
+}  // namespace qbe

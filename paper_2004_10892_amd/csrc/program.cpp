@@ -1,0 +1,399 @@
+// Plan compiler: turns a bucket schedule into device programs.
+//
+// Layout decisions (host side; the device only moves and multiplies data):
+//  * Every tensor's remaining variables are stored sorted by position in the
+//    reduced order, earliest variable most significant.  The eliminated
+//    variable u of bucket b is the earliest variable of U_b, so in the
+//    bucket's union index X = (u << r_b) | x it is the top bit, and every
+//    operand's index is the bit-extraction of X by the operand's mask.
+//  * Input tensors are prepared on the device from the model's complex128
+//    entries by a gather map computed here: per-step form -- one copy per
+//    assignment of the tensor's own sliced variables; fused form -- a block
+//    of slice-invariant tensors and one block per slice of the rest, so that
+//    a workgroup fills its LDS with two contiguous copies.
+//  * Intermediates live in an arena laid out by simulating the schedule
+//    (first fit; per-slice units scaled by the slice-group size).
+#include <algorithm>
+#include <map>
+#include <stdexcept>
+
+#include "qbe_internal.hpp"
+
+namespace qbe {
+
+namespace {
+
+struct Arena {
+  // free list of [begin, end) in elements
+  std::map<int64_t, int64_t> free_;  // begin -> end
+  int64_t top = 0;
+  int64_t alloc(int64_t size, int64_t align) {
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      int64_t b = (it->first + align - 1) / align * align;
+      if (b + size <= it->second) {
+        int64_t e = it->second, s0 = it->first;
+        free_.erase(it);
+        if (s0 < b) free_[s0] = b;
+        if (b + size < e) free_[b + size] = e;
+        return b;
+      }
+    }
+    int64_t b = (top + align - 1) / align * align;
+    if (top < b) release(top, b - top);
+    top = b + size;
+    return b;
+  }
+  void release(int64_t b, int64_t size) {
+    int64_t e = b + size;
+    auto nx = free_.lower_bound(b);
+    if (nx != free_.end() && nx->first == e) {
+      e = nx->second;
+      free_.erase(nx);
+    }
+    auto pv = free_.lower_bound(b);
+    if (pv != free_.begin()) {
+      --pv;
+      if (pv->second == b) {
+        b = pv->first;
+        free_.erase(pv);
+      }
+    }
+    free_[b] = e;
+  }
+};
+
+int64_t align_for(int64_t size) { return std::min<int64_t>(64, size); }
+
+// Mask of `vars` (sorted by position) inside the union `uni` (sorted by
+// position, uni[0] is the top bit).
+uint32_t union_mask(const std::vector<int>& uni, const std::vector<int>& vars) {
+  uint32_t m = 0;
+  const int nu = (int)uni.size();
+  for (int v : vars) {
+    auto it = std::find(uni.begin(), uni.end(), v);
+    if (it == uni.end()) throw std::logic_error("operand variable outside its bucket");
+    m |= 1u << (nu - 1 - (int)(it - uni.begin()));
+  }
+  return m;
+}
+
+struct InputInfo {
+  std::vector<int> canon;     // remaining variables sorted by position
+  std::vector<int> slice_js;  // mu indices j of the tensor's sliced variables (ascending)
+  uint32_t smask = 0;
+};
+
+// Raw (model) element index of tensor t for an assignment given as a
+// function of the variable.
+template <class F>
+int64_t raw_index(const Model& md, int t, F&& value_of) {
+  const auto& vs = md.tvars[t];
+  const int r = (int)vs.size();
+  int64_t idx = 0;
+  for (int j = 0; j < r; ++j) idx |= (int64_t)value_of(vs[j]) << (r - 1 - j);
+  return md.data_off[t] + idx;
+}
+
+}  // namespace
+
+void compile_plan(Plan& p) {
+  const Model& md = p.model;
+  const Schedule& s = p.sched;
+  const int nt = (int)md.tvars.size();
+  p.m = (int)s.mu.size();
+  if (p.m > 40) throw std::invalid_argument("at most 40 sliced variables");
+  p.n_slices = int64_t(1) << p.m;
+  std::vector<int> pos(md.n_vars, -1), muj(md.n_vars, -1);
+  for (size_t i = 0; i < s.order.size(); ++i) pos[s.order[i]] = (int)i;
+  for (int j = 0; j < p.m; ++j) muj[s.mu[j]] = j;
+  if (p.m > 32)
+    for (int j = 32; j < p.m; ++j) (void)j;  // slice ids above 2^32 handled as int64 below
+
+  std::vector<InputInfo> in(nt);
+  for (int t = 0; t < nt; ++t) {
+    for (int v : md.tvars[t]) {
+      if (muj[v] >= 0)
+        in[t].slice_js.push_back(muj[v]);
+      else
+        in[t].canon.push_back(v);
+    }
+    std::sort(in[t].canon.begin(), in[t].canon.end(), [&](int a, int b) { return pos[a] < pos[b]; });
+    std::sort(in[t].slice_js.begin(), in[t].slice_js.end());
+    for (int j : in[t].slice_js) {
+      if (j >= 32) throw std::invalid_argument("a tensor may not hold a sliced variable of index >= 32");
+      in[t].smask |= 1u << j;
+    }
+    if (in[t].canon.size() > 30) throw std::invalid_argument("tensor rank above 30");
+  }
+
+  // ---------------- prepared inputs, per-step layout: versions per tensor
+  std::vector<int64_t> step_base(nt);
+  p.step_map.clear();
+  for (int t = 0; t < nt; ++t) {
+    step_base[t] = (int64_t)p.step_map.size();
+    const int r = (int)in[t].canon.size();
+    const int ns = (int)in[t].slice_js.size();
+    for (int64_t ver = 0; ver < (int64_t(1) << ns); ++ver)
+      for (int64_t y = 0; y < (int64_t(1) << r); ++y) {
+        auto val = [&](int v) -> int {
+          if (muj[v] >= 0) {
+            int k = (int)(std::find(in[t].slice_js.begin(), in[t].slice_js.end(), muj[v]) -
+                          in[t].slice_js.begin());
+            return (int)((ver >> k) & 1);
+          }
+          int c = (int)(std::find(in[t].canon.begin(), in[t].canon.end(), v) - in[t].canon.begin());
+          return (int)((y >> (r - 1 - c)) & 1);
+        };
+        int64_t ri = raw_index(md, t, val);
+        if (ri > INT32_MAX) throw std::invalid_argument("model data too large");
+        p.step_map.push_back((int32_t)ri);
+      }
+  }
+  p.step_elems = (int64_t)p.step_map.size();
+
+  // ---------------- per-step launches and arena
+  const int nsteps = (int)s.steps.size();
+  std::vector<int64_t> out_off(nsteps, -1);
+  Arena arena;
+  p.steps.clear();
+  p.scalar_arena.clear();
+  auto input_op = [&](int t, const std::vector<int>& uni) {
+    StepOp o{};
+    o.base = step_base[t];
+    o.is_input = 1;
+    o.rank = (int)in[t].canon.size();
+    o.mask = union_mask(uni, in[t].canon);
+    o.smask = in[t].smask;
+    return o;
+  };
+  for (int k = 0; k < nsteps; ++k) {
+    const Step& st = s.steps[k];
+    if (st.uni.size() > 31) throw std::invalid_argument("bucket union above 31 variables");
+    const int rb = (int)st.out.size();
+    std::vector<StepOp> ops;
+    for (const auto& op : st.ops) {
+      if (op.kind == 't') {
+        ops.push_back(input_op(op.id, st.uni));
+      } else {
+        StepOp o{};
+        o.base = out_off[op.id];
+        o.is_input = 0;
+        o.rank = (int)op.vars.size();
+        o.mask = union_mask(st.uni, op.vars);
+        ops.push_back(o);
+      }
+    }
+    // Buckets with more operands than one launch takes: multiply groups of
+    // operands into partial products over their own variables first (the sum
+    // over u happens only in the last launch).  A partial product keeps u.
+    std::vector<std::pair<int64_t, int64_t>> temps;  // arena blocks to free
+    while ((int)ops.size() > kMaxOps) {
+      std::vector<StepOp> grp(ops.begin(), ops.begin() + kMaxOps);
+      uint32_t gm = 0;
+      for (auto& o : grp) gm |= o.mask;
+      // variables of the partial product, as bits of the union index
+      const int pr = __builtin_popcount(gm);
+      // re-express each member's mask inside the partial product's index
+      StepProg sp{};
+      sp.out_rank = -pr;  // negative: product without summation, out index = pext(X, gm)
+      int64_t sz = int64_t(1) << pr;
+      int64_t off = arena.alloc(sz, align_for(sz));
+      temps.push_back({off, sz});
+      sp.out_base = off;
+      sp.n_ops = kMaxOps;
+      for (int i = 0; i < kMaxOps; ++i) {
+        StepOp o = grp[i];
+        uint32_t nm = 0;
+        int bit = 0;
+        for (int b = 0; b < 32; ++b)
+          if ((gm >> b) & 1) {
+            if ((o.mask >> b) & 1) nm |= 1u << bit;
+            ++bit;
+          }
+        o.mask = nm;
+        sp.ops[i] = o;
+      }
+      p.steps.push_back(sp);
+      StepOp po{};
+      po.base = off;
+      po.is_input = 0;
+      po.rank = pr;
+      po.mask = gm;
+      std::vector<StepOp> rest(ops.begin() + kMaxOps, ops.end());
+      rest.insert(rest.begin(), po);
+      ops.swap(rest);
+    }
+    StepProg sp{};
+    sp.out_rank = rb;
+    const int64_t osz = int64_t(1) << rb;
+    out_off[k] = arena.alloc(osz, align_for(osz));
+    sp.out_base = out_off[k];
+    sp.n_ops = (int)ops.size();
+    for (size_t i = 0; i < ops.size(); ++i) sp.ops[i] = ops[i];
+    p.steps.push_back(sp);
+    for (auto& tb : temps) arena.release(tb.first, tb.second);
+    for (const auto& op : st.ops)
+      if (op.kind == 'r') arena.release(out_off[op.id], int64_t(1) << op.vars.size());
+    if (rb == 0) p.scalar_arena.push_back(out_off[k]);
+  }
+  p.arena_per_slice = std::max<int64_t>(arena.top, 1);
+  // scalar results of steps must stay allocated: they were never released
+  // (a rank-0 result has no consumer step).
+  p.scalar_inputs_base.clear();
+  p.scalar_inputs_smask.clear();
+  for (int t : s.scalar_inputs) {
+    p.scalar_inputs_base.push_back(step_base[t]);
+    p.scalar_inputs_smask.push_back(in[t].smask);
+  }
+
+  // ---------------- levels (dependency depth)
+  std::vector<int> level(nsteps, 0);
+  int n_levels = 0;
+  for (int k = 0; k < nsteps; ++k) {
+    int l = 0;
+    for (const auto& op : s.steps[k].ops)
+      if (op.kind == 'r') l = std::max(l, level[op.id] + 1);
+    level[k] = l;
+    n_levels = std::max(n_levels, l + 1);
+  }
+  p.n_levels = n_levels;
+
+  // ---------------- fused form
+  p.fused_ok = false;
+  p.fused_prog.clear();
+  p.fused_map.clear();
+  p.fused_elems = 0;
+  p.fused_lds_bytes = 0;
+  bool eligible = p.m <= 24;
+  for (const auto& st : s.steps)
+    if (st.uni.size() > 14) eligible = false;
+  if (eligible) {
+    // LDS element offsets of the inputs
+    std::vector<int64_t> lds_in(nt, -1);
+    int64_t inv = 0, dep = 0;
+    for (int t = 0; t < nt; ++t)
+      if (in[t].smask == 0) {
+        lds_in[t] = inv;
+        inv += int64_t(1) << in[t].canon.size();
+      }
+    for (int t = 0; t < nt; ++t)
+      if (in[t].smask != 0) {
+        lds_in[t] = inv + dep;
+        dep += int64_t(1) << in[t].canon.size();
+      }
+    // arena by levels: all results of a level are live while the level runs
+    std::vector<std::vector<int>> by_level(n_levels);
+    for (int k = 0; k < nsteps; ++k) by_level[level[k]].push_back(k);
+    Arena la;
+    std::vector<int64_t> lds_out(nsteps, -1);
+    for (int l = 0; l < n_levels; ++l) {
+      for (int k : by_level[l]) {
+        int64_t sz = int64_t(1) << s.steps[k].out.size();
+        lds_out[k] = la.alloc(sz, 1);
+      }
+      for (int k : by_level[l])
+        for (const auto& op : s.steps[k].ops)
+          if (op.kind == 'r') la.release(lds_out[op.id], int64_t(1) << op.vars.size());
+    }
+    const int64_t arena0 = inv + dep;
+    const int64_t data_elems = arena0 + la.top;
+    // program
+    std::vector<uint32_t> prog(kHdr, 0);
+    std::vector<uint32_t> lvl_begin, lvl_elems, stepw, opw, scal;
+    std::vector<int> step_order;
+    for (int l = 0; l < n_levels; ++l) {
+      lvl_begin.push_back((uint32_t)step_order.size());
+      int64_t e = 0;
+      for (int k : by_level[l]) {
+        step_order.push_back(k);
+        e += int64_t(1) << s.steps[k].out.size();
+      }
+      lvl_elems.push_back((uint32_t)e);
+    }
+    lvl_begin.push_back((uint32_t)step_order.size());
+    bool fits = data_elems < 65536;
+    for (int l = 0; l < n_levels && fits; ++l) {
+      int64_t e = 0;
+      for (uint32_t i = lvl_begin[l]; i < lvl_begin[l + 1]; ++i) {
+        int k = step_order[i];
+        const Step& st = s.steps[k];
+        int64_t out = arena0 + lds_out[k];
+        uint32_t w0 = (uint32_t)out | ((uint32_t)st.out.size() << 16) | ((uint32_t)st.ops.size() << 21);
+        uint32_t w1 = (uint32_t)opw.size() | ((uint32_t)e << 16);
+        if (opw.size() > 65535 || e > 65535 || st.ops.size() > 2047) fits = false;
+        stepw.push_back(w0);
+        stepw.push_back(w1);
+        for (const auto& op : st.ops) {
+          int64_t off;
+          std::vector<int> vars;
+          if (op.kind == 't') {
+            off = lds_in[op.id];
+            vars = in[op.id].canon;
+          } else {
+            off = arena0 + lds_out[op.id];
+            vars = op.vars;
+          }
+          uint32_t mk = union_mask(st.uni, vars);
+          opw.push_back((uint32_t)off | (mk << 16));
+        }
+        e += int64_t(1) << st.out.size();
+      }
+    }
+    for (int t : s.scalar_inputs) scal.push_back((uint32_t)lds_in[t]);
+    for (int k : s.scalar_steps) scal.push_back((uint32_t)(arena0 + lds_out[k]));
+    prog.insert(prog.end(), lvl_begin.begin(), lvl_begin.end());
+    prog.insert(prog.end(), lvl_elems.begin(), lvl_elems.end());
+    prog.insert(prog.end(), stepw.begin(), stepw.end());
+    prog.insert(prog.end(), opw.begin(), opw.end());
+    prog.insert(prog.end(), scal.begin(), scal.end());
+    if (prog.size() % 2) prog.push_back(0);  // data region 8-byte aligned
+    prog[FH_WORDS] = (uint32_t)prog.size();
+    prog[FH_LEVELS] = (uint32_t)n_levels;
+    prog[FH_STEPS] = (uint32_t)nsteps;
+    prog[FH_OPS] = (uint32_t)opw.size();
+    prog[FH_SCALARS] = (uint32_t)scal.size();
+    prog[FH_FREE] = (uint32_t)s.free_vars.size();
+    prog[FH_INV_ELEMS] = (uint32_t)inv;
+    prog[FH_DEP_ELEMS] = (uint32_t)dep;
+    prog[FH_DATA_ELEMS] = (uint32_t)data_elems;
+    prog[FH_INV_SRC] = 0;
+    prog[FH_DEP_SRC] = (uint32_t)inv;
+    prog[FH_N_SLICES] = (uint32_t)std::min<int64_t>(p.n_slices, UINT32_MAX);
+    const int64_t lds_bytes = (int64_t)prog.size() * 4 + data_elems * 8;
+    const int64_t prep_elems = inv + dep * p.n_slices;
+    if (fits && lds_bytes <= kFusedLdsMax && prep_elems < (int64_t(1) << 31)) {
+      p.fused_ok = true;
+      p.fused_prog = std::move(prog);
+      p.fused_lds_bytes = (int)lds_bytes;
+      // gather map: invariant block, then one block per slice
+      p.fused_map.reserve(prep_elems);
+      for (int t = 0; t < nt; ++t)
+        if (in[t].smask == 0) {
+          const int r = (int)in[t].canon.size();
+          for (int64_t y = 0; y < (int64_t(1) << r); ++y) {
+            auto val = [&](int v) -> int {
+              int c = (int)(std::find(in[t].canon.begin(), in[t].canon.end(), v) - in[t].canon.begin());
+              return (int)((y >> (r - 1 - c)) & 1);
+            };
+            p.fused_map.push_back((int32_t)raw_index(md, t, val));
+          }
+        }
+      for (int64_t sl = 0; sl < p.n_slices; ++sl)
+        for (int t = 0; t < nt; ++t)
+          if (in[t].smask != 0) {
+            const int r = (int)in[t].canon.size();
+            for (int64_t y = 0; y < (int64_t(1) << r); ++y) {
+              auto val = [&](int v) -> int {
+                if (muj[v] >= 0) return (int)((sl >> muj[v]) & 1);
+                int c = (int)(std::find(in[t].canon.begin(), in[t].canon.end(), v) - in[t].canon.begin());
+                return (int)((y >> (r - 1 - c)) & 1);
+              };
+              p.fused_map.push_back((int32_t)raw_index(md, t, val));
+            }
+          }
+      p.fused_elems = (int64_t)p.fused_map.size();
+    }
+  }
+}
+
+}  // namespace qbe

@@ -1,0 +1,160 @@
+"""Host planner behind the C ABI vs the CPU oracle: orders, widths, clique
+trees, deletion sets and bucket schedules must agree exactly.  Runs on the
+CPU (no device calls)."""
+import os
+import re
+
+import numpy as np
+import pytest
+from hypothesis import given, settings, strategies as st
+
+import paper_2004_10892_amd as qbe
+from circuitgen import (batch_instances, circuit_model, random_grid_circuit, random_network, toy_network)
+from oracle import contract as C
+from oracle import cost as K
+from oracle import planner as P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    header = open(os.path.join(ROOT, "include", "qbe.h")).read()
+    declared = set(re.findall(r"^\s*(?:int|int32_t|const char\*)\s+(qbe_\w+)\s*\(", header, re.M))
+    assert len(declared) >= 20
+    for name in declared:
+        assert hasattr(qbe._lib, name), name
+    assert declared == set(qbe.EXPORTED)
+    assert qbe.qbe_version() == 1
+
+
+def oracle_plan(mod, m, score="tree_trimming"):
+    tv = [v for v, _ in mod.tensors]
+    adj = P.simple_graph(mod.n_vars, tv)
+    order = P.min_fill_order(adj)
+    mu, g, pi, tau = P.greedy_treewidth_deletion(adj, order, m, score=score)
+    return adj, order, mu, pi, tau, C.bucket_schedule(mod.n_vars, tv, pi, mu)
+
+
+CIRCUITS = [(3, 3, 6, s, 2) for s in range(8)] + [(4, 4, 10, s, 3) for s in range(8)] + \
+           [(5, 5, 16, s, 6) for s in range(4)] + [(4, 6, 12, s, 4) for s in range(4)] + \
+           [(6, 6, 16, 0, 8), (7, 7, 24, 0, 10)]
+
+
+@pytest.mark.parametrize("rows,cols,depth,seed,m", CIRCUITS)
+def test_plans_bit_exact_on_circuits(rows, cols, depth, seed, m):
+    circ = random_grid_circuit(rows, cols, depth, seed)
+    mod = circuit_model(circ)
+    adj, order, mu, pi, tau, sched = oracle_plan(mod, m)
+    qm = qbe.Model.from_circuitgen(mod)
+    assert qbe.qbe_order_min_fill(qm) == order
+    assert qbe.qbe_width(qm, order) == P.treewidth_from_order(adj, order)
+    bags, parent = qbe.qbe_clique_tree(qm, order)
+    obags, oparent = P.clique_tree(adj, order)
+    assert bags == [sorted(b) for b in obags]
+    assert parent == oparent
+    qmu, qpi, qtau = qbe.qbe_slice(qm, order, m)
+    assert (qmu, qpi, qtau) == (mu, pi, tau)
+    assert qbe.qbe_width(qm, pi, removed=mu) == tau
+    plan = qbe.Plan(qm, pi, mu)
+    assert plan.dump() == C.schedule_dump(sched)
+    stats = plan.stats()
+    cost = K.schedule_cost(sched)
+    assert stats["flops_per_slice"] == cost.flops_per_slice
+    assert stats["bytes_per_slice"] == cost.bytes_per_slice
+    assert stats["peak_bytes_per_slice"] == cost.peak_bytes
+    assert stats["width"] == cost.width
+    plan.check()
+
+
+@pytest.mark.parametrize("score", ["degree", "tw_reduction"])
+def test_other_scores_bit_exact(score):
+    for seed in range(4):
+        mod = circuit_model(random_grid_circuit(3, 4, 8, seed))
+        _, order, mu, pi, tau, _ = oracle_plan(mod, 3, score=score)
+        qm = qbe.Model.from_circuitgen(mod)
+        assert qbe.qbe_slice(qm, order, 3, score=score) == (mu, pi, tau)
+
+
+def test_target_width_mode():
+    mod = circuit_model(random_grid_circuit(5, 5, 16, 1))
+    tv = [v for v, _ in mod.tensors]
+    adj = P.simple_graph(mod.n_vars, tv)
+    order = P.min_fill_order(adj)
+    mu, _, pi, tau = P.greedy_treewidth_deletion(adj, order, -1, target_width=6)
+    qm = qbe.Model.from_circuitgen(mod)
+    assert qbe.qbe_slice(qm, order, -1, target_width=6) == (mu, pi, tau)
+    assert tau <= 6
+
+
+@settings(max_examples=60, deadline=None)
+@given(st.integers(2, 12), st.integers(1, 16), st.integers(1, 4), st.integers(0, 10**6), st.integers(0, 4))
+def test_random_networks_bit_exact(n, t, r, seed, m):
+    net = random_network(n, t, r, seed)
+    m = min(m, n)
+    adj, order, mu, pi, tau, sched = oracle_plan(net, m)
+    qm = qbe.Model(net.n_vars, net.tensors)
+    assert qbe.qbe_order_min_fill(qm) == order
+    assert qbe.qbe_slice(qm, order, m) == (mu, pi, tau)
+    plan = qbe.Plan(qm, pi, mu)
+    assert plan.dump() == C.schedule_dump(sched)
+    plan.check()
+
+
+def test_toy_dump_through_abi_is_eq2():
+    net = toy_network(0)
+    qm = qbe.Model(net.n_vars, net.tensors)
+    plan = qbe.Plan(qm, [0, 1, 2, 3, 4, 5], [])
+    gold = "".join(l for l in open(os.path.join(ROOT, "tests", "golden", "toy_eq2_schedule.txt"))
+                   if not l.startswith("#"))
+    assert plan.dump() == gold
+    assert qbe.qbe_slice(qm, [0, 1, 2, 3, 4, 5], 1) == ([2], [0, 1, 3, 4, 5], 1)
+
+
+def test_fused_form_chosen_for_small_slices_and_per_step_for_large():
+    mod = circuit_model(random_grid_circuit(5, 5, 16, 1))
+    qm = qbe.Model.from_circuitgen(mod)
+    _, mu, pi, _ = qbe.plan_circuit(qm, m=6)
+    st_ = qbe.Plan(qm, pi, mu).stats()
+    assert st_["exec"] == qbe.EXEC["fused"] and 0 < st_["lds_bytes"] <= 64 * 1024
+    mod7 = circuit_model(random_grid_circuit(7, 7, 24, 0))
+    q7 = qbe.Model.from_circuitgen(mod7)
+    _, mu7, pi7, tau7 = qbe.plan_circuit(q7, m=10)
+    st7 = qbe.Plan(q7, pi7, mu7).stats()
+    assert st7["exec"] == qbe.EXEC["per_step"] and st7["width"] == tau7
+    with pytest.raises(qbe.QbeError):
+        qbe.Plan(q7, pi7, mu7, exec="fused")
+
+
+def test_batch_instance_plans_are_sound():
+    for (r, c, d, m, seed) in batch_instances(24):
+        qm = qbe.Model.from_circuitgen(circuit_model(random_grid_circuit(r, c, d, seed)))
+        _, mu, pi, _ = qbe.plan_circuit(qm, m=m)
+        plan = qbe.Plan(qm, pi, mu)
+        plan.check()
+
+
+def test_invalid_arguments_return_errors():
+    net = toy_network(0)
+    with pytest.raises(qbe.QbeError, match="INVALID_ARG"):
+        qbe.Model(3, [((0, 0), np.ones((2, 2)))])          # repeated variable
+    with pytest.raises(qbe.QbeError, match="INVALID_ARG"):
+        qbe.Model(4, [((0, 1), np.ones((2, 2)))])          # variables 2, 3 unused
+    with pytest.raises(qbe.QbeError, match="INVALID_ARG"):
+        qbe.Model(2, [((0, 5), np.ones((2, 2)))])          # id out of range
+    qm = qbe.Model(net.n_vars, net.tensors)
+    with pytest.raises(qbe.QbeError, match="INVALID_ARG"):
+        qbe.qbe_width(qm, [0, 1, 2])                       # not a permutation
+    with pytest.raises(qbe.QbeError, match="INVALID_ARG"):
+        qbe.Plan(qm, [0, 1, 2, 3, 4], [])                  # variable 5 missing
+    with pytest.raises(qbe.QbeError, match="INVALID_ARG"):
+        qbe.Plan(qm, [0, 1, 2, 3, 4, 5], [2])              # sliced and ordered
+    with pytest.raises(qbe.QbeError, match="INVALID_ARG"):
+        qbe.qbe_slice(qm, [0, 1, 2, 3, 4, 5], 7)           # more than n
+
+
+def test_no_device_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    rc = qbe._lib.qbe_create(qbe.C.byref(qbe._vp()), 0, None)
+    assert rc == -6
