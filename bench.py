@@ -1,0 +1,258 @@
+"""Benchmark: amplitudes per second of sliced bucket-elimination contraction
+on one MI355X.
+
+Headline workload: a 5x5 grid circuit of depth 16 (seed 1, bitstring from the
+seed), 6 variables sliced by the tree-trimming heuristic (64 slices), one
+amplitude per step.  The chosen form (one persistent fused launch, replayed
+from a HIP graph) is timed next to the plain FP32 form (one launch per bucket,
+slices batched) and next to the CPU oracle.  Extra lines: a 7x7 depth-24
+circuit with 1024 slices (the HBM-bound per-step kernels) and a batch of 512
+uneven instances.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extra]
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "amplitudes/sec + MFMA util, chosen vs plain FP32 form at rel err ≤1e-5"
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+SEEDS = {"grid4x4_d10_m0": 0, "grid5x5_d16_m6": 1, "grid7x7_d24_m10": 0}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def golden(name):
+    with open(os.path.join(ROOT, "tests", "golden", "amplitudes.json")) as f:
+        g = json.load(f)[name]
+    return complex(*g["oracle"])
+
+
+def build_plan(qbe, ctx, name, form):
+    from circuitgen import WORKLOADS, circuit_model, random_grid_circuit
+    r, c, d, m = WORKLOADS[name]
+    mod = circuit_model(random_grid_circuit(r, c, d, SEEDS[name]))
+    qm = qbe.Model.from_circuitgen(mod)
+    t0 = time.perf_counter()
+    order, mu, pi, tau = qbe.plan_circuit(qm, m=m)   # min-fill order + tree-trimming (Alg. 2)
+    qbe.Plan(qm, pi, mu, exec=form).close()          # schedule + device programs, host only
+    t1 = time.perf_counter()
+    plan = qbe.Plan(qm, pi, mu, ctx=ctx, exec=form)  # again, plus upload and input preparation
+    t2 = time.perf_counter()
+    return plan, (t1 - t0) * 1e3, {"rows": r, "cols": c, "depth": d, "m": m, "seed": SEEDS[name],
+                                  "width": tau, "n_vars": mod.n_vars, "n_tensors": len(mod.tensors),
+                                  "device_setup_ms": (t2 - t1) * 1e3}
+
+
+def timed(torch, fn, steps, warmup):
+    """Runs fn warmup + steps times; returns (wall ms per step, event ms per step)."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return (t1 - t0) * 1e3 / steps, e0.elapsed_time(e1) / steps
+
+
+def graph_of(torch, qbe, ctx, fn):
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        ctx.set_stream(s)
+        fn()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        ctx.set_stream(torch.cuda.current_stream())
+        fn()
+    ctx.set_stream(torch.cuda.current_stream())
+    return g
+
+
+def cpu_baseline(name, budget_s=12.0):
+    """The oracle as it stands, on the host: whole amplitudes of the same
+    workload, repeated until the time budget is spent."""
+    from circuitgen import WORKLOADS, circuit_model, random_grid_circuit
+    from oracle import contract as C
+    from oracle import planner as P
+    r, c, d, m = WORKLOADS[name]
+    mod = circuit_model(random_grid_circuit(r, c, d, SEEDS[name]))
+    tv = [v for v, _ in mod.tensors]
+    adj = P.simple_graph(mod.n_vars, tv)
+    order = P.min_fill_order(adj)
+    mu, _, pi, _ = P.greedy_treewidth_deletion(adj, order, m)
+    sched = C.bucket_schedule(mod.n_vars, tv, pi, mu)
+    n = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        C.contract(mod.tensors, sched)
+        n += 1
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "amplitudes/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} whole amplitudes of {name} (all {1 << m} slices each), numpy complex128 "
+                      f"einsum in one process; host has {os.cpu_count()} logical CPUs"}
+
+
+def bench_hbm(torch, qbe, ctx, steps):
+    """7x7 depth-24 circuit, 1024 slices, per-step form: HBM-bound kernels."""
+    name = "grid7x7_d24_m10"
+    plan, plan_ms, cfg = build_plan(qbe, ctx, name, "per_step")
+    st = plan.stats()
+    ws = torch.empty(int(st["ws_bytes_all_slices"]), dtype=torch.uint8, device="cuda")
+    out = torch.zeros(2, dtype=torch.float64, device="cuda")
+    fn = lambda: qbe.qbe_contract_async(ctx, plan, ws, out)  # noqa: E731
+    wall, ev = timed(torch, fn, steps, 1)
+    got = complex(*out.cpu().numpy())
+    want = golden(name)
+    bytes_amp = st["bytes_per_slice"] * plan.n_slices
+    flops_amp = st["flops_per_slice"] * plan.n_slices
+    return {"workload": name, "form": "per_step", "ms_per_amplitude": ev, "amplitudes_per_s": 1e3 / ev,
+            "rel_err": abs(got - want) / abs(want), "planning_ms": plan_ms, "config": cfg,
+            "roofline": {"bound": "hbm", "achieved": bytes_amp / (ev * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": bytes_amp / (ev * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                         "algorithmic_bytes": bytes_amp, "algorithmic_flops": flops_amp,
+                         "note": "all per-step launches of one amplitude; bytes from the cost model"}}
+
+
+def bench_batch(torch, qbe, ctx, steps):
+    """512 uneven instances: one batched call vs one launch per bucket."""
+    from circuitgen import batch_instances, circuit_model, random_grid_circuit
+    t0 = time.perf_counter()
+    plans_b, plans_p, scale = [], [], []
+    for (r, c, d, m, seed) in batch_instances(512):
+        scale.append(2.0 ** (-(r * c) / 2))  # typical |amplitude| of an n-qubit random circuit
+        qm = qbe.Model.from_circuitgen(circuit_model(random_grid_circuit(r, c, d, seed)))
+        _, mu, pi, _ = qbe.plan_circuit(qm, m=m)
+        plans_b.append(qbe.Plan(qm, pi, mu, ctx=ctx))
+        plans_p.append(qbe.Plan(qm, pi, mu, ctx=ctx, exec="per_step"))
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    batch = qbe.Batch(ctx, plans_b)
+    ws = batch.workspace()
+    amps = torch.zeros(2 * len(plans_b), dtype=torch.float64, device="cuda")
+    g = graph_of(torch, qbe, ctx, lambda: batch.contract_async(ws, amps))
+    wall_b, ev_b = timed(torch, g.replay, steps, 2)
+    res_b = amps.cpu().numpy().copy()
+    wsp = torch.empty(max(int(p.stats()["ws_bytes_all_slices"]) for p in plans_p), dtype=torch.uint8, device="cuda")
+    outp = torch.zeros(2 * len(plans_p), dtype=torch.float64, device="cuda")
+
+    def plain():
+        for i, p in enumerate(plans_p):
+            qbe.qbe_contract_async(ctx, p, wsp, outp[2 * i:])
+    wall_p, ev_p = timed(torch, plain, max(1, steps // 4), 1)
+    res_p = outp.cpu().numpy()
+    import numpy as np
+    a, b = res_b.view(np.complex128), res_p.view(np.complex128)
+    n_fused = sum(p.stats()["exec"] == 2 for p in plans_b)
+    return {"workload": "batch512_grid4-6_d10-20_m0-6", "instances": len(plans_b), "fused_instances": n_fused,
+            "batched_ms": ev_b, "batched_amplitudes_per_s": len(plans_b) / (ev_b * 1e-3),
+            "plain_ms": ev_p, "plain_amplitudes_per_s": len(plans_p) / (ev_p * 1e-3),
+            "speedup": ev_p / ev_b, "planning_ms_total": plan_ms,
+            "max_diff_batched_vs_plain": float(np.max(np.abs(a - b) / np.maximum(np.abs(b), np.asarray(scale)))),
+            "note_diff": "|batched - plain| / max(|plain|, 2^(-n/2)): exact-zero amplitudes of shallow "
+                         "circuits are compared on the scale of a typical amplitude"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-extra", action="store_true", help="skip the 7x7 and batch lines")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--only", choices=["hbm", "batch"], help="run just one extra workload (profiling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: the contraction runs on a single MI355X "
+              f"(--gpus {args.gpus} is not supported)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2004_10892_amd as qbe
+
+    name = "grid5x5_d16_m6"
+    ctx = qbe.Context(0)
+    want = golden(name)
+    if args.only == "hbm":
+        print(json.dumps(bench_hbm(torch, qbe, ctx, args.steps)), flush=True)
+        return
+    if args.only == "batch":
+        print(json.dumps(bench_batch(torch, qbe, ctx, args.steps)), flush=True)
+        return
+
+    # chosen form: fused persistent launch under a HIP graph
+    plan, plan_ms, cfg = build_plan(qbe, ctx, name, "fused")
+    st = plan.stats()
+    ws = plan.workspace()
+    out = torch.zeros(2, dtype=torch.float64, device="cuda")
+    g = graph_of(torch, qbe, ctx, lambda: qbe.qbe_contract_async(ctx, plan, ws, out))
+    log(f"[bench] {name}: width {st['width']} levels {st['n_levels']} lds {st['lds_bytes']} B")
+    wall, ev = timed(torch, g.replay, args.steps, args.warmup)
+    got = complex(*out.cpu().numpy())
+    err = abs(got - want) / abs(want)
+    log(f"[bench] chosen: {ev * 1e3:.2f} us/amplitude (wall {wall * 1e3:.2f}), rel err {err:.2e}")
+
+    # plain FP32 form: one launch per bucket
+    plan_p, plan_p_ms, _ = build_plan(qbe, ctx, name, "per_step")
+    ws_p = plan_p.workspace()
+    out_p = torch.zeros(2, dtype=torch.float64, device="cuda")
+    wall_p, ev_p = timed(torch, lambda: qbe.qbe_contract_async(ctx, plan_p, ws_p, out_p),
+                         max(1, args.steps // 4), max(1, args.warmup // 4))
+    got_p = complex(*out_p.cpu().numpy())
+    err_p = abs(got_p - want) / abs(want)
+    log(f"[bench] plain: {ev_p * 1e3:.2f} us/amplitude, rel err {err_p:.2e}")
+
+    flops_launch = st["flops_per_slice"] * plan.n_slices
+    achieved = flops_launch / (ev * 1e-3) / 1e12
+    line = {
+        "metric": METRIC, "value": 1e3 / ev, "unit": "amplitudes/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ev, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+        "config": dict({"workload": name, "form": "fused+hipgraph", "slices": plan.n_slices}, **cfg),
+        "rel_err": err, "mfma_util": 0.0,
+        "planning_ms": plan_ms,
+        "amplitudes_per_s_with_planning": 1e3 / (ev + plan_ms),
+        "note_planning": "host planning per circuit (min-fill, tree-trimming, schedule and program "
+                         "compilation); the plan is cached across amplitudes in the timed loop",
+        "plain_fp32": {"form": "per_step", "ms_per_step": ev_p, "value": 1e3 / ev_p, "rel_err": err_p,
+                       "launches_per_step": st["n_steps"] + 2},
+        "speedup_vs_plain": ev_p / ev,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "fused_kernel", "algorithmic_flops_per_launch": flops_launch,
+                     "note": "LDS-resident: every operand and intermediate stays on chip; the step is "
+                             "bounded by the chain of dependent bucket levels, not by HBM"},
+    }
+    if not args.no_cpu:
+        log("[bench] cpu baseline (oracle) ...")
+        line["cpu_baseline"] = cpu_baseline(name)
+    if not args.no_extra:
+        log("[bench] 7x7 d24 per-step ...")
+        line["hbm_workload"] = bench_hbm(torch, qbe, ctx, 5)
+        log("[bench] batch of 512 ...")
+        line["batch_workload"] = bench_batch(torch, qbe, ctx, 20)
+    print(json.dumps(line), flush=True)
+    if err > 1e-5 or err_p > 1e-5:
+        sys.exit(1)
+
+
+if __name__ == "__main__":
+    main()

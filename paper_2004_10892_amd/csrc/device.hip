@@ -209,103 +209,166 @@ __global__ __launch_bounds__(256) void reduce_kernel(const double2* __restrict__
 
 struct FusedItem {
   uint32_t plan;   // index into the plan tables
-  uint32_t pad;
+  uint32_t words;  // program words of that plan
   int64_t slice;
 };
 
 struct FusedArgs {
   const uint32_t* prog0;              // one-plan mode (items == nullptr)
   const float2* prep0;
+  uint32_t words0;                    // one-plan mode: program words
   const uint32_t* const* progs;       // batch mode: per plan
   const float2* const* preps;
   const FusedItem* items;             // batch mode: the work items
+  const int64_t* ranges;              // batch mode: (begin, end) items per plan
   int64_t s_begin;                    // one-plan mode: slice of item 0
   int64_t n_items;
-  uint32_t* counter;                  // work counter, zeroed before launch
+  uint32_t* state;                    // [0] work counter, [1] exits, [2 + p] items done
   double2* out;                       // per item
+  double2* amps;                      // per plan: the slice sum (when reduce_here)
+  int32_t reduce_here;                // 1: the last workgroup of a plan sums its items
 };
 
-__global__ void reset_counter_kernel(uint32_t* c) { *c = 0u; }
+// Loads the first 8 words of a record.
+__device__ __forceinline__ void load_record(const uint32_t* rec, uint32_t S, uint4& r0, uint4& r1) {
+  const uint4* q = reinterpret_cast<const uint4*>(rec);
+  r0 = q[0];
+  if (S > 4) r1 = q[1];
+}
 
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+
+// A pointer every lane holds the same value of, moved to scalar registers so
+// that loads through it with uniform offsets become scalar loads.
+template <class T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Product over the operands of one record, for u = 0 (a0) and u = 1 (a1),
+// multiplied as a balanced tree to keep the dependent chain short.
+__device__ __forceinline__ void record_product(const float2* data, const uint4& c0, const uint4& c1, uint32_t S,
+                                               const uint32_t* rec, float2& a0, float2& a1) {
+  const float2 x1 = data[c0.y & 0xFFFFu], y1 = data[c0.y >> 16];
+  const float2 x2 = data[c0.z & 0xFFFFu], y2 = data[c0.z >> 16];
+  const float2 x3 = data[c0.w & 0xFFFFu], y3 = data[c0.w >> 16];
+  a0 = cmul(x1, cmul(x2, x3));
+  a1 = cmul(y1, cmul(y2, y3));
+  if (S > 4) {
+    const float2 x4 = data[c1.x & 0xFFFFu], y4 = data[c1.x >> 16];
+    const float2 x5 = data[c1.y & 0xFFFFu], y5 = data[c1.y >> 16];
+    const float2 x6 = data[c1.z & 0xFFFFu], y6 = data[c1.z >> 16];
+    const float2 x7 = data[c1.w & 0xFFFFu], y7 = data[c1.w >> 16];
+    a0 = cmul(a0, cmul(cmul(x4, x5), cmul(x6, x7)));
+    a1 = cmul(a1, cmul(cmul(y4, y5), cmul(y6, y7)));
+    if (S > 8) {
+      const uint4* q = reinterpret_cast<const uint4*>(rec);
+      for (uint32_t c = 2; c < S / 4; ++c) {
+        const uint4 w = q[c];
+        a0 = cmul(a0, cmul(cmul(data[w.x & 0xFFFFu], data[w.y & 0xFFFFu]),
+                           cmul(data[w.z & 0xFFFFu], data[w.w & 0xFFFFu])));
+        a1 = cmul(a1, cmul(cmul(data[w.x >> 16], data[w.y >> 16]), cmul(data[w.z >> 16], data[w.w >> 16])));
+      }
+    }
+  }
+}
+
+// kProgLds: the plan's program is copied into LDS (ahead of the tensor
+// entries) whenever the workgroup switches plans, and records are read from
+// there; otherwise records are read from device memory with a one-level
+// prefetch.  Header and level-table words are always read from device memory
+// with uniform addresses, so they land in scalar registers.
+//
+// Work distribution: in one-plan mode workgroup b takes items b, b + grid,
+// ...; in batch mode items are pulled from a counter (uneven sizes).
+template <bool kProgLds>
 __global__ __launch_bounds__(kBlock) void fused_kernel(FusedArgs a) {
-  extern __shared__ uint32_t lds[];
+  extern __shared__ uint4 lds4[];
   __shared__ int64_t s_item;
-  __shared__ uint32_t s_plan;
+  __shared__ uint32_t s_flag, s_plan;
   const int tid = threadIdx.x;
   if (tid == 0) s_plan = 0xFFFFFFFFu;
+  int64_t next = blockIdx.x;
   for (;;) {
-    __syncthreads();
-    if (tid == 0) {
-      const uint32_t it = atomicAdd(a.counter, 1u);
-      s_item = (int64_t)it < a.n_items ? (int64_t)it : -1;
+    int64_t item;
+    if (a.items) {
+      __syncthreads();
+      if (tid == 0) {
+        const uint32_t it = atomicAdd(&a.state[0], 1u);
+        s_item = (int64_t)it < a.n_items ? (int64_t)it : -1;
+      }
+      __syncthreads();
+      item = __builtin_amdgcn_readfirstlane((int)s_item);
+    } else {
+      __syncthreads();
+      item = next < a.n_items ? next : -1;
+      next += gridDim.x;
     }
-    __syncthreads();
-    const int64_t item = s_item;
     if (item < 0) break;
-    uint32_t plan = 0;
+    uint32_t plan = 0, words = a.words0;
     int64_t slice = a.s_begin + item;
-    const uint32_t* prog = a.prog0;
+    const uint32_t* gprog = a.prog0;
     const float2* prep = a.prep0;
     if (a.items) {
       const FusedItem wi = a.items[item];
-      plan = wi.plan;
-      slice = wi.slice;
-      prog = a.progs[plan];
+      plan = __builtin_amdgcn_readfirstlane(wi.plan);
+      words = __builtin_amdgcn_readfirstlane(wi.words);
+      slice = __builtin_amdgcn_readfirstlane((int)wi.slice);
+      gprog = a.progs[plan];
       prep = a.preps[plan];
     }
-    if (plan != s_plan) {  // s_plan is read by every lane: the branch is uniform
-      const uint32_t words = prog[FH_WORDS];
-      for (uint32_t i = tid; i < words; i += kBlock) lds[i] = prog[i];
-      __syncthreads();
-      if (tid == 0) s_plan = plan;
+    gprog = uniform_ptr(gprog);
+    prep = uniform_ptr(prep);
+    const uint32_t* rprog = gprog;  // where records are read from
+    float2* data = reinterpret_cast<float2*>(lds4);
+    if (kProgLds) {
+      if (plan != __builtin_amdgcn_readfirstlane(s_plan)) {
+        const uint4* src = reinterpret_cast<const uint4*>(gprog);
+        for (uint32_t i = tid; i < words / 4; i += kBlock) lds4[i] = src[i];
+      }
+      rprog = reinterpret_cast<const uint32_t*>(lds4);
+      data = reinterpret_cast<float2*>(lds4 + words / 4);
     }
-    const uint32_t words = lds[FH_WORDS];
-    const uint32_t n_levels = lds[FH_LEVELS];
-    const uint32_t n_steps = lds[FH_STEPS];
-    const uint32_t n_ops = lds[FH_OPS];
-    const uint32_t n_scal = lds[FH_SCALARS];
-    const uint32_t inv = lds[FH_INV_ELEMS], dep = lds[FH_DEP_ELEMS];
-    const uint32_t* lvl_begin = lds + kHdr;
-    const uint32_t* lvl_elems = lvl_begin + n_levels + 1;
-    const uint32_t* stepw = lvl_elems + n_levels;
-    const uint32_t* opw = stepw + 2 * n_steps;
-    const uint32_t* scal = opw + n_ops;
-    float2* data = reinterpret_cast<float2*>(lds + words);
-    const float2* dsrc = prep + lds[FH_DEP_SRC] + slice * (int64_t)dep;
-    for (uint32_t i = tid; i < inv; i += kBlock) data[i] = prep[i];
-    for (uint32_t i = tid; i < dep; i += kBlock) data[inv + i] = dsrc[i];
+    // inputs of this slice into LDS, the constant 1 at offset 0
+    const uint32_t inv = gprog[FH_INV_ELEMS], dep = gprog[FH_DEP_ELEMS];
+    const float2* dsrc = prep + gprog[FH_DEP_SRC] + slice * (int64_t)dep;
+    if (tid == 0) data[0] = make_float2(1.f, 0.f);
+    for (uint32_t i = tid; i < inv; i += kBlock) data[1 + i] = prep[i];
+    for (uint32_t i = tid; i < dep; i += kBlock) data[1 + inv + i] = dsrc[i];
     __syncthreads();
+    if (kProgLds && tid == 0) s_plan = plan;  // read again only after the next barrier
+    const uint32_t n_levels = gprog[FH_LEVELS];
+    // level table: LDS copy when the program is there, else scalar loads
+    const uint32_t* lv = rprog + kHdr;
+    uint4 p0 = make_uint4(0, 0, 0, 0), p1 = make_uint4(0, 0, 0, 0);
+    uint4 nxt = n_levels > 0 ? *reinterpret_cast<const uint4*>(lv) : make_uint4(0, 0, 0, 0);
+    if (n_levels > 0 && (uint32_t)tid < uni(nxt.y)) load_record(rprog + uni(nxt.x) + (size_t)tid * uni(nxt.z), uni(nxt.z), p0, p1);
     for (uint32_t l = 0; l < n_levels; ++l) {
-      const uint32_t E = lvl_elems[l];
-      const uint32_t b0 = lvl_begin[l], b1 = lvl_begin[l + 1];
+      const uint32_t base = uni(nxt.x), E = uni(nxt.y), S = uni(nxt.z);
+      uint4 c0 = p0, c1 = p1;
+      if (l + 1 < n_levels) {
+        nxt = reinterpret_cast<const uint4*>(lv)[l + 1];
+        const uint32_t nb = uni(nxt.x), nE = uni(nxt.y), nS = uni(nxt.z);
+        if ((uint32_t)tid < nE) load_record(rprog + nb + (size_t)tid * nS, nS, p0, p1);
+      }
       for (uint32_t f = tid; f < E; f += kBlock) {
-        uint32_t lo = b0, hi = b1 - 1;
-        while (lo < hi) {
-          const uint32_t mid = (lo + hi + 1) >> 1;
-          if ((stepw[2 * mid + 1] >> 16) <= f)
-            lo = mid;
-          else
-            hi = mid - 1;
-        }
-        const uint32_t w0 = stepw[2 * lo], w1 = stepw[2 * lo + 1];
-        const uint32_t out_off = w0 & 0xFFFFu, r = (w0 >> 16) & 31u, nops = w0 >> 21;
-        const uint32_t op0 = w1 & 0xFFFFu, x = f - (w1 >> 16);
-        float2 a0 = make_float2(1.f, 0.f), a1 = make_float2(1.f, 0.f);
-        for (uint32_t i = 0; i < nops; ++i) {
-          const uint32_t ow = opw[op0 + i];
-          const uint32_t mask = ow >> 16;
-          const float2* t = data + (ow & 0xFFFFu);
-          const uint32_t idx = pext32(x, mask);
-          a0 = cmul(a0, t[idx]);
-          const uint32_t up = ((mask >> r) & 1u) ? (1u << (__builtin_popcount(mask) - 1)) : 0u;
-          a1 = cmul(a1, t[idx + up]);
-        }
-        data[out_off + x] = make_float2(a0.x + a1.x, a0.y + a1.y);
+        const uint32_t* rec = rprog + base + (size_t)f * S;
+        if (f != (uint32_t)tid) load_record(rec, S, c0, c1);
+        float2 a0, a1;
+        record_product(data, c0, c1, S, rec, a0, a1);
+        data[c0.x & 0xFFFFu] = (c0.x >> 16) & kRecNoSum ? a0 : cadd(a0, a1);
       }
       __syncthreads();
     }
     if (tid == 0) {
-      double re = (double)(1u << lds[FH_FREE]), im = 0.0;
+      double re = (double)(1u << gprog[FH_FREE]), im = 0.0;
+      const uint32_t* scal = gprog + gprog[FH_SCALAR_OFF];
+      const uint32_t n_scal = gprog[FH_SCALARS];
       for (uint32_t j = 0; j < n_scal; ++j) {
         const float2 v = data[scal[j]];
         const double vr = v.x, vi = v.y;
@@ -314,6 +377,64 @@ __global__ __launch_bounds__(kBlock) void fused_kernel(FusedArgs a) {
         re = nr;
       }
       a.out[item] = make_double2(re, im);
+      s_flag = 0u;
+      if (a.reduce_here) {
+        // publish the value and count it (release); the plan's last item
+        // sums them all (acquire)
+        int64_t b = 0, e = a.n_items;
+        if (a.ranges) {
+          b = a.ranges[2 * plan];
+          e = a.ranges[2 * plan + 1];
+        }
+        const uint32_t done =
+            __hip_atomic_fetch_add(&a.state[2 + plan], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+        if ((int64_t)done == e - b) s_flag = 1u;
+      }
+    }
+    __syncthreads();
+    if (s_flag) {
+      // last item of this plan: fixed-order FP64 sum of its items (same order
+      // as reduce_kernel), then re-arm the plan's counter for the next launch.
+      // The scratch overwrites LDS; no item of this plan remains.
+      __threadfence();
+      int64_t b = 0, e = a.n_items;
+      if (a.ranges) {
+        b = a.ranges[2 * plan];
+        e = a.ranges[2 * plan + 1];
+      }
+      double* sre = reinterpret_cast<double*>(lds4);
+      double* sim = sre + kBlock;
+      double re = 0.0, im = 0.0;
+      for (int64_t i = b + tid; i < e; i += kBlock) {
+        const double2 v = a.out[i];
+        re += v.x;
+        im += v.y;
+      }
+      sre[tid] = re;
+      sim[tid] = im;
+      __syncthreads();
+      for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (tid < w) {
+          sre[tid] += sre[tid + w];
+          sim[tid] += sim[tid + w];
+        }
+        __syncthreads();
+      }
+      if (tid == 0) {
+        a.amps[plan] = make_double2(sre[0], sim[0]);
+        a.state[2 + plan] = 0u;
+        s_plan = 0xFFFFFFFFu;
+      }
+    }
+  }
+  if (a.items) {
+    // the last workgroup to leave re-arms the work counter
+    if (tid == 0) {
+      const uint32_t left = __hip_atomic_fetch_add(&a.state[1], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+      if (left == gridDim.x) {
+        a.state[0] = 0u;
+        a.state[1] = 0u;
+      }
     }
   }
 }
@@ -369,8 +490,8 @@ static int run_prep(Plan& p) {
 }
 
 void dev_free_plan(Plan& p) {
-  void** ptrs[] = {&p.d_raw,      &p.d_step_map,   &p.d_step_in,   &p.d_fused_map,
-                   &p.d_fused_in, &p.d_fused_prog, &p.d_scalar_tab};
+  void** ptrs[] = {&p.d_raw,      &p.d_step_map,   &p.d_step_in,    &p.d_fused_map,
+                   &p.d_fused_in, &p.d_fused_prog, &p.d_scalar_tab, &p.d_state};
   for (void** q : ptrs) {
     if (*q) (void)hipFree(*q);
     *q = nullptr;
@@ -410,6 +531,8 @@ int dev_upload_plan(Plan& p) {
       std::memcpy(tab.data() + o, p.scalar_inputs_smask.data(), p.scalar_inputs_smask.size() * 4);
     if ((rc = upload(&p.d_scalar_tab, tab.data(), tab.size()))) return rc;
   }
+  if ((rc = dmalloc(&p.d_state, 256))) return rc;
+  QBE_HIP(hipMemset(p.d_state, 0, 256));
   if (p.fused_ok) {
     if ((rc = upload(&p.d_fused_map, p.fused_map.data(), p.fused_map.size() * 4))) return rc;
     if ((rc = dmalloc(&p.d_fused_in, p.fused_elems * 8))) return rc;
@@ -482,6 +605,23 @@ static int launch_step(const Plan& p, const StepProg& sp, float2* arena, int64_t
   return QBE_OK;
 }
 
+static int launch_fused(bool prog_lds, int grid, int lds_bytes, hipStream_t st, const FusedArgs& a) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    QBE_HIP(hipFuncSetAttribute((const void*)fused_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                kFusedLdsMax));
+    QBE_HIP(hipFuncSetAttribute((const void*)fused_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                kFusedLdsMax));
+    attr_set = true;
+  }
+  if (prog_lds)
+    fused_kernel<true><<<grid, kBlock, lds_bytes, st>>>(a);
+  else
+    fused_kernel<false><<<grid, kBlock, lds_bytes, st>>>(a);
+  QBE_HIP(hipGetLastError());
+  return QBE_OK;
+}
+
 static int fused_grid(int lds_bytes, int64_t n_items) {
   const int per_cu = std::max(1, std::min(8, (160 * 1024) / std::max(lds_bytes, 1)));
   return (int)std::max<int64_t>(1, std::min<int64_t>(n_items, (int64_t)n_cus() * per_cu));
@@ -498,18 +638,19 @@ int dev_contract(const Plan& p, void* stream, void* ws, size_t ws_bytes, int64_t
     return QBE_ERR_MEM_CAP;
   }
   if (p.exec == QBE_EXEC_FUSED) {
-    uint32_t* counter = (uint32_t*)(w + 64);
-    reset_counter_kernel<<<1, 1, 0, st>>>(counter);
-    QBE_HIP(hipGetLastError());
     FusedArgs a{};
     a.prog0 = (const uint32_t*)p.d_fused_prog;
     a.prep0 = (const float2*)p.d_fused_in;
     a.s_begin = s_begin;
     a.n_items = n;
-    a.counter = counter;
+    a.state = (uint32_t*)p.d_state;
     a.out = per_slice;
-    fused_kernel<<<fused_grid(p.fused_lds_bytes, n), kBlock, p.fused_lds_bytes, st>>>(a);
-    QBE_HIP(hipGetLastError());
+    a.amps = (double2*)d_partial_out;
+    a.words0 = (uint32_t)p.fused_prog.size();
+    a.reduce_here = n <= kInKernelReduceMax ? 1 : 0;
+    int rc = launch_fused(p.fused_prog_in_lds, fused_grid(p.fused_lds_bytes, n), p.fused_lds_bytes, st, a);
+    if (rc) return rc;
+    if (a.reduce_here) return QBE_OK;
   } else {
     const int64_t per_slice_bytes = p.arena_per_slice * 8;
     const int64_t G = std::min<int64_t>(n, (int64_t)((ws_bytes - ws_head(n)) / per_slice_bytes));
@@ -554,6 +695,8 @@ int dev_batch_build(Batch& b) {
   b.lds_bytes = 0;
   b.wide.clear();
   b.wide_ws = 0;
+  b.prog_in_lds = true;
+  int data_bytes = 0;
   for (int i = 0; i < np; ++i) {
     const Plan& p = *b.plans[i];
     if (p.exec != QBE_EXEC_FUSED) {
@@ -564,8 +707,11 @@ int dev_batch_build(Batch& b) {
     progs[i] = (const uint32_t*)p.d_fused_prog;
     preps[i] = (const float2*)p.d_fused_in;
     b.lds_bytes = std::max(b.lds_bytes, p.fused_lds_bytes);
+    b.prog_in_lds = b.prog_in_lds && p.fused_prog_in_lds;
+    data_bytes = std::max(data_bytes, (int)std::max<int64_t>(8 * (int64_t)p.fused_prog[FH_DATA_ELEMS], 256 * 16));
     idx.push_back(i);
   }
+  if (!b.prog_in_lds) b.lds_bytes = data_bytes;
   // biggest work items first, so the tail of the persistent grid is short
   std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) {
     return b.plans[x]->cost.flops > b.plans[y]->cost.flops;
@@ -574,7 +720,8 @@ int dev_batch_build(Batch& b) {
   std::vector<int64_t> ranges(2 * np, 0);
   for (int i : idx) {
     ranges[2 * i] = (int64_t)items.size();
-    for (int64_t s = 0; s < b.plans[i]->n_slices; ++s) items.push_back(FusedItem{(uint32_t)i, 0u, s});
+    const uint32_t words = (uint32_t)b.plans[i]->fused_prog.size();
+    for (int64_t s = 0; s < b.plans[i]->n_slices; ++s) items.push_back(FusedItem{(uint32_t)i, words, s});
     ranges[2 * i + 1] = (int64_t)items.size();
   }
   b.n_items = (int64_t)items.size();
@@ -584,11 +731,16 @@ int dev_batch_build(Batch& b) {
   if ((rc = upload(&b.d_preps, preps.data(), np * sizeof(void*)))) return rc;
   if ((rc = upload(&b.d_items, items.data(), items.size() * sizeof(FusedItem)))) return rc;
   if ((rc = upload(&b.d_ranges, ranges.data(), ranges.size() * 8))) return rc;
+  if ((rc = dmalloc(&b.d_state, (2 + (size_t)np) * 4))) return rc;
+  QBE_HIP(hipMemset(b.d_state, 0, (2 + (size_t)np) * 4));
+  b.reduce_here = true;
+  for (int i : idx)
+    if (b.plans[i]->n_slices > kInKernelReduceMax) b.reduce_here = false;
   return QBE_OK;
 }
 
 void dev_batch_free(Batch& b) {
-  void** ptrs[] = {&b.d_progs, &b.d_preps, &b.d_items, &b.d_ranges};
+  void** ptrs[] = {&b.d_progs, &b.d_preps, &b.d_items, &b.d_ranges, &b.d_state};
   for (void** q : ptrs) {
     if (*q) (void)hipFree(*q);
     *q = nullptr;
@@ -607,23 +759,25 @@ int dev_batch_contract(const Batch& b, void* stream, void* ws, size_t ws_bytes, 
   }
   char* w = (char*)ws;
   if (b.n_items > 0) {
-    uint32_t* counter = (uint32_t*)(w + 64);
     double2* per_item = (double2*)(w + 256);
-    reset_counter_kernel<<<1, 1, 0, st>>>(counter);
-    QBE_HIP(hipGetLastError());
     FusedArgs a{};
     a.progs = (const uint32_t* const*)b.d_progs;
     a.preps = (const float2* const*)b.d_preps;
     a.items = (const FusedItem*)b.d_items;
+    a.ranges = (const int64_t*)b.d_ranges;
     a.n_items = b.n_items;
-    a.counter = counter;
+    a.state = (uint32_t*)b.d_state;
     a.out = per_item;
-    fused_kernel<<<fused_grid(b.lds_bytes, b.n_items), kBlock, b.lds_bytes, st>>>(a);
-    QBE_HIP(hipGetLastError());
-    // one reduction block per plan; blocks of per-step plans see an empty range
-    reduce_kernel<<<(unsigned)b.plans.size(), 256, 0, st>>>(per_item, (const int64_t*)b.d_ranges, 0,
-                                                             (double2*)d_amps);
-    QBE_HIP(hipGetLastError());
+    a.amps = (double2*)d_amps;
+    a.reduce_here = b.reduce_here ? 1 : 0;
+    int rc = launch_fused(b.prog_in_lds, fused_grid(b.lds_bytes, b.n_items), b.lds_bytes, st, a);
+    if (rc) return rc;
+    if (!b.reduce_here) {
+      // one reduction block per plan; blocks of per-step plans see an empty range
+      reduce_kernel<<<(unsigned)b.plans.size(), 256, 0, st>>>(per_item, (const int64_t*)b.d_ranges, 0,
+                                                               (double2*)d_amps);
+      QBE_HIP(hipGetLastError());
+    }
   }
   char* wide_ws = w + ws_head(b.n_items);
   for (int i : b.wide) {

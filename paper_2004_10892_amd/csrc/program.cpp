@@ -266,19 +266,19 @@ void compile_plan(Plan& p) {
   p.fused_lds_bytes = 0;
   bool eligible = p.m <= 24;
   for (const auto& st : s.steps)
-    if (st.uni.size() > 14) eligible = false;
+    if (st.uni.size() > 15) eligible = false;
   if (eligible) {
-    // LDS element offsets of the inputs
+    // LDS element offsets of the inputs (after the constant 1 at 0)
     std::vector<int64_t> lds_in(nt, -1);
     int64_t inv = 0, dep = 0;
     for (int t = 0; t < nt; ++t)
       if (in[t].smask == 0) {
-        lds_in[t] = inv;
+        lds_in[t] = 1 + inv;
         inv += int64_t(1) << in[t].canon.size();
       }
     for (int t = 0; t < nt; ++t)
       if (in[t].smask != 0) {
-        lds_in[t] = inv + dep;
+        lds_in[t] = 1 + inv + dep;
         dep += int64_t(1) << in[t].canon.size();
       }
     // arena by levels: all results of a level are live while the level runs
@@ -295,76 +295,79 @@ void compile_plan(Plan& p) {
         for (const auto& op : s.steps[k].ops)
           if (op.kind == 'r') la.release(lds_out[op.id], int64_t(1) << op.vars.size());
     }
-    const int64_t arena0 = inv + dep;
+    const int64_t arena0 = 1 + inv + dep;
     const int64_t data_elems = arena0 + la.top;
-    // program
-    std::vector<uint32_t> prog(kHdr, 0);
-    std::vector<uint32_t> lvl_begin, lvl_elems, stepw, opw, scal;
-    std::vector<int> step_order;
-    for (int l = 0; l < n_levels; ++l) {
-      lvl_begin.push_back((uint32_t)step_order.size());
-      int64_t e = 0;
-      for (int k : by_level[l]) {
-        step_order.push_back(k);
-        e += int64_t(1) << s.steps[k].out.size();
-      }
-      lvl_elems.push_back((uint32_t)e);
-    }
-    lvl_begin.push_back((uint32_t)step_order.size());
-    bool fits = data_elems < 65536;
-    for (int l = 0; l < n_levels && fits; ++l) {
-      int64_t e = 0;
-      for (uint32_t i = lvl_begin[l]; i < lvl_begin[l + 1]; ++i) {
-        int k = step_order[i];
-        const Step& st = s.steps[k];
-        int64_t out = arena0 + lds_out[k];
-        uint32_t w0 = (uint32_t)out | ((uint32_t)st.out.size() << 16) | ((uint32_t)st.ops.size() << 21);
-        uint32_t w1 = (uint32_t)opw.size() | ((uint32_t)e << 16);
-        if (opw.size() > 65535 || e > 65535 || st.ops.size() > 2047) fits = false;
-        stepw.push_back(w0);
-        stepw.push_back(w1);
-        for (const auto& op : st.ops) {
-          int64_t off;
-          std::vector<int> vars;
-          if (op.kind == 't') {
-            off = lds_in[op.id];
-            vars = in[op.id].canon;
-          } else {
-            off = arena0 + lds_out[op.id];
-            vars = op.vars;
-          }
-          uint32_t mk = union_mask(st.uni, vars);
-          opw.push_back((uint32_t)off | (mk << 16));
-        }
-        e += int64_t(1) << st.out.size();
-      }
-    }
-    for (int t : s.scalar_inputs) scal.push_back((uint32_t)lds_in[t]);
-    for (int k : s.scalar_steps) scal.push_back((uint32_t)(arena0 + lds_out[k]));
-    prog.insert(prog.end(), lvl_begin.begin(), lvl_begin.end());
-    prog.insert(prog.end(), lvl_elems.begin(), lvl_elems.end());
-    prog.insert(prog.end(), stepw.begin(), stepw.end());
-    prog.insert(prog.end(), opw.begin(), opw.end());
-    prog.insert(prog.end(), scal.begin(), scal.end());
-    if (prog.size() % 2) prog.push_back(0);  // data region 8-byte aligned
-    prog[FH_WORDS] = (uint32_t)prog.size();
-    prog[FH_LEVELS] = (uint32_t)n_levels;
-    prog[FH_STEPS] = (uint32_t)nsteps;
-    prog[FH_OPS] = (uint32_t)opw.size();
-    prog[FH_SCALARS] = (uint32_t)scal.size();
-    prog[FH_FREE] = (uint32_t)s.free_vars.size();
-    prog[FH_INV_ELEMS] = (uint32_t)inv;
-    prog[FH_DEP_ELEMS] = (uint32_t)dep;
-    prog[FH_DATA_ELEMS] = (uint32_t)data_elems;
-    prog[FH_INV_SRC] = 0;
-    prog[FH_DEP_SRC] = (uint32_t)inv;
-    prog[FH_N_SLICES] = (uint32_t)std::min<int64_t>(p.n_slices, UINT32_MAX);
-    const int64_t lds_bytes = (int64_t)prog.size() * 4 + data_elems * 8;
+    const int64_t lds_bytes = std::max<int64_t>(data_elems * 8, 256 * 16);
     const int64_t prep_elems = inv + dep * p.n_slices;
-    if (fits && lds_bytes <= kFusedLdsMax && prep_elems < (int64_t(1) << 31)) {
+    if (data_elems < 65536 && lds_bytes <= kFusedLdsMax && prep_elems < (int64_t(1) << 31)) {
+      std::vector<uint32_t> prog(kHdr, 0);
+      const size_t lvl_at = prog.size();
+      prog.resize(lvl_at + 4 * (size_t)n_levels, 0);
+      while (prog.size() % 4) prog.push_back(0);
+      for (int l = 0; l < n_levels; ++l) {
+        uint32_t K = 1;
+        int64_t E = 0;
+        for (int k : by_level[l]) {
+          K = std::max<uint32_t>(K, (uint32_t)s.steps[k].ops.size());
+          E += int64_t(1) << s.steps[k].out.size();
+        }
+        const uint32_t S = (1 + K + 3) / 4 * 4;
+        prog[lvl_at + 4 * l + 0] = (uint32_t)prog.size();
+        prog[lvl_at + 4 * l + 1] = (uint32_t)E;
+        prog[lvl_at + 4 * l + 2] = S;
+        prog[lvl_at + 4 * l + 3] = K;
+        for (int k : by_level[l]) {
+          const Step& st = s.steps[k];
+          const int r = (int)st.out.size();
+          // operand LDS offsets, masks and u-strides
+          std::vector<uint32_t> off, mk, up;
+          for (const auto& op : st.ops) {
+            const std::vector<int>& vars = op.kind == 't' ? in[op.id].canon : op.vars;
+            off.push_back((uint32_t)(op.kind == 't' ? lds_in[op.id] : arena0 + lds_out[op.id]));
+            const uint32_t m_ = union_mask(st.uni, vars);
+            mk.push_back(m_);
+            up.push_back(((m_ >> r) & 1u) ? (1u << (__builtin_popcount(m_) - 1)) : 0u);
+          }
+          for (uint32_t x = 0; x < (1u << r); ++x) {
+            const size_t at = prog.size();
+            prog.resize(at + S, 0);
+            prog[at] = (uint32_t)(arena0 + lds_out[k] + x);
+            for (size_t i = 0; i < st.ops.size(); ++i) {
+              uint32_t e = 0, bit = 0;
+              for (uint32_t mm = mk[i]; mm; mm &= mm - 1, ++bit) e |= ((x >> __builtin_ctz(mm)) & 1u) << bit;
+              const uint32_t i0 = off[i] + e, i1 = i0 + up[i];
+              prog[at + 1 + i] = i0 | (i1 << 16);
+            }
+          }
+        }
+      }
+      const uint32_t scal_at = (uint32_t)prog.size();
+      uint32_t n_scal = 0;
+      for (int t : s.scalar_inputs) {
+        prog.push_back((uint32_t)lds_in[t]);
+        ++n_scal;
+      }
+      for (int k : s.scalar_steps) {
+        prog.push_back((uint32_t)(arena0 + lds_out[k]));
+        ++n_scal;
+      }
+      while (prog.size() % 4) prog.push_back(0);  // whole 16-byte rows for the LDS copy
+      prog[FH_WORDS] = (uint32_t)prog.size();
+      prog[FH_LEVELS] = (uint32_t)n_levels;
+      prog[FH_SCALARS] = n_scal;
+      prog[FH_SCALAR_OFF] = scal_at;
+      prog[FH_FREE] = (uint32_t)s.free_vars.size();
+      prog[FH_INV_ELEMS] = (uint32_t)inv;
+      prog[FH_DEP_ELEMS] = (uint32_t)dep;
+      prog[FH_DATA_ELEMS] = (uint32_t)data_elems;
+      prog[FH_DEP_SRC] = (uint32_t)inv;
+      prog[FH_N_SLICES] = (uint32_t)std::min<int64_t>(p.n_slices, UINT32_MAX);
       p.fused_ok = true;
+      // records travel to LDS with the inputs when both fit
+      const int64_t with_prog = (int64_t)prog.size() * 4 + data_elems * 8;
+      p.fused_prog_in_lds = with_prog <= kFusedLdsMax;
+      p.fused_lds_bytes = (int)(p.fused_prog_in_lds ? std::max<int64_t>(with_prog, lds_bytes) : lds_bytes);
       p.fused_prog = std::move(prog);
-      p.fused_lds_bytes = (int)lds_bytes;
       // gather map: invariant block, then one block per slice
       p.fused_map.reserve(prep_elems);
       for (int t = 0; t < nt; ++t)

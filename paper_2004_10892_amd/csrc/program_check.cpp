@@ -2,6 +2,7 @@
 // plan can form is checked against the size of the buffer it reads or
 // writes, before anything is uploaded or launched.  Returns "" when the plan
 // is sound, otherwise a description of the first violation.
+#include <algorithm>
 #include <string>
 
 #include "qbe_internal.hpp"
@@ -62,44 +63,43 @@ std::string check_plan(const Plan& p) {
   // fused program
   if (p.fused_ok) {
     const auto& w = p.fused_prog;
-    if (w.size() < (size_t)kHdr || w[FH_WORDS] != w.size()) return "fused header";
-    const uint32_t nl = w[FH_LEVELS], ns = w[FH_STEPS], no = w[FH_OPS], nsc = w[FH_SCALARS];
-    const size_t need = kHdr + (nl + 1) + nl + 2 * (size_t)ns + no + nsc;
-    if (need > w.size()) return "fused program truncated";
+    if (w.size() < (size_t)kHdr || w[FH_WORDS] != w.size() || w.size() % 4) return "fused header";
+    const uint32_t nl = w[FH_LEVELS], nsc = w[FH_SCALARS], so = w[FH_SCALAR_OFF];
     const uint32_t inv = w[FH_INV_ELEMS], dep = w[FH_DEP_ELEMS], data = w[FH_DATA_ELEMS];
-    if ((int64_t)w.size() * 4 + (int64_t)data * 8 != p.fused_lds_bytes) return "fused LDS size";
+    {
+      const int64_t base = std::max<int64_t>((int64_t)data * 8, 256 * 16);
+      const int64_t want = p.fused_prog_in_lds ? std::max<int64_t>(base, (int64_t)w.size() * 4 + (int64_t)data * 8) : base;
+      if (want != p.fused_lds_bytes) return "fused LDS size";
+    }
     if (p.fused_lds_bytes > kFusedLdsMax) return "fused LDS above budget";
+    if (data >= 65536) return "fused data above 16-bit offsets";
     if (w[FH_DEP_SRC] != inv) return "fused dependent block offset";
     if ((int64_t)inv + (int64_t)dep * p.n_slices != p.fused_elems) return "fused prepared size";
-    if (inv + dep > data) return "fused inputs above data size";
-    const uint32_t* lb = w.data() + kHdr;
-    const uint32_t* le = lb + nl + 1;
-    const uint32_t* sw = le + nl;
-    const uint32_t* ow = sw + 2 * ns;
-    const uint32_t* sc = ow + no;
-    if (lb[0] != 0 || lb[nl] != ns) return "fused level ranges";
+    if (1 + inv + dep > data) return "fused inputs above data size";
+    if ((int64_t)kHdr + 4 * (int64_t)nl > (int64_t)w.size()) return "fused level table truncated";
+    if ((int64_t)so + nsc > (int64_t)w.size()) return "fused scalar list truncated";
+    const uint32_t* lv = w.data() + kHdr;
+    int64_t expect_base = (kHdr + 4 * (int64_t)nl + 3) / 4 * 4;
     for (uint32_t l = 0; l < nl; ++l) {
-      if (lb[l] >= lb[l + 1]) return "empty or unordered level";
-      int64_t e = 0;
-      for (uint32_t j = lb[l]; j < lb[l + 1]; ++j) {
-        const uint32_t w0 = sw[2 * j], w1 = sw[2 * j + 1];
-        const uint32_t out = w0 & 0xFFFFu, r = (w0 >> 16) & 31u, nop = w0 >> 21;
-        const uint32_t op0 = w1 & 0xFFFFu, eb = w1 >> 16;
-        if (eb != e) return fail("fused element ranges", eb, e);
-        if (out < inv + dep || (int64_t)out + (int64_t(1) << r) > data) return "fused result outside the arena";
-        if (nop < 1 || (int64_t)op0 + nop > no) return "fused operand range";
-        for (uint32_t i = 0; i < nop; ++i) {
-          const uint32_t off = ow[op0 + i] & 0xFFFFu, mask = ow[op0 + i] >> 16;
-          if ((mask >> (r + 1)) != 0) return "fused operand mask outside the union";
-          const int rank = __builtin_popcount(mask);
-          if ((int64_t)off + (int64_t(1) << rank) > data) return "fused operand outside LDS data";
+      const uint32_t base = lv[4 * l], E = lv[4 * l + 1], S = lv[4 * l + 2], K = lv[4 * l + 3];
+      if (base != expect_base) return fail("fused record base", base, expect_base);
+      if (base % 4 || S % 4 || S < 1 + K || E == 0) return "fused level shape";
+      if ((int64_t)base + (int64_t)E * S > (int64_t)w.size()) return "fused records truncated";
+      for (uint32_t f = 0; f < E; ++f) {
+        const uint32_t* rec = w.data() + base + (size_t)f * S;
+        const uint32_t out = rec[0] & 0xFFFFu;
+        if (out < 1 + inv + dep || out >= data) return "fused result outside the arena";
+        for (uint32_t j = 1; j < S; ++j) {
+          if ((rec[j] & 0xFFFFu) >= data || (rec[j] >> 16) >= data) return "fused operand outside LDS data";
+          if (j > K && rec[j] != 0) return "fused padding word not the constant";
         }
-        e += int64_t(1) << r;
       }
-      if (e != le[l]) return "fused level element count";
+      expect_base += (int64_t)E * S;
     }
+    if (expect_base != so) return "fused scalar list offset";
+    if ((int64_t)so + nsc + 3 < (int64_t)w.size()) return "fused program tail";
     for (uint32_t j = 0; j < nsc; ++j)
-      if (sc[j] >= data) return "fused scalar outside LDS data";
+      if (w[so + j] >= data) return "fused scalar outside LDS data";
   }
   return "";
 }

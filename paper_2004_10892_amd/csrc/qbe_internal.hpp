@@ -18,8 +18,12 @@ constexpr int kMaxOps = 8;
 constexpr int kBlock = 256;
 // Low index bits handled inside one workgroup tile by the per-step kernel.
 constexpr int kLoBits = 8;
-// LDS budget of one fused workgroup (bytes): program + tensors.
-constexpr int kFusedLdsMax = 64 * 1024 - 256;
+// LDS budget of one fused workgroup (bytes): tensor entries, plus the
+// program's records when they fit too (gfx950: 160 KB per workgroup).
+constexpr int kFusedLdsMax = 160 * 1024 - 256;
+// Largest slice count whose FP64 sum the fused kernel does itself (the
+// last workgroup of a plan); above it a separate reduction kernel runs.
+constexpr int64_t kInKernelReduceMax = 8192;
 
 struct Model {
   int n_vars = 0;
@@ -50,29 +54,37 @@ struct StepProg {
 
 // --------------------------------------------------------- fused (LDS) form --
 
-// Word layout of a fused program (uint32 words), all offsets in elements:
+// A fused program lives in device memory (uint32 words); the workgroup keeps
+// only tensor entries in LDS.  LDS data layout (complex64 elements):
+//   [0]                         the constant 1 (padding operand)
+//   [1, 1 + inv)                slice-invariant input tensors
+//   [1 + inv, 1 + inv + dep)    this slice's copies of slice-dependent inputs
+//   [1 + inv + dep, data)       intermediates (arena, reused level by level)
+// Program words:
 //   header[kHdr]
-//   level_begin[n_levels + 1]    step index ranges per level
-//   level_elems[n_levels]        elements computed per level
-//   steps[2 * n_steps]           w0 = out_off | out_rank << 16 | n_ops << 21
-//                                w1 = op0 | elem_begin << 16
-//   ops[n_ops]                   off | mask << 16
-//   scalars[n_scalars]           LDS offsets of the slice's scalar factors
+//   levels[4 * n_levels]        (record base, elements E, stride S, operands K)
+//   records                     level by level, E records of S words each
+//                               (S a multiple of 4, S >= 1 + K):
+//                                 w0    = result offset | flags << 16
+//                                 w1..K = i0 | i1 << 16: LDS offsets of the
+//                                         operand entry for u = 0 and u = 1
+//                                 rest  = 0 (the constant 1, both halves)
+//   scalars[n_scalars]          LDS offsets of the slice's scalar factors
 enum FusedHdr {
   FH_WORDS = 0,       // total program words
   FH_LEVELS,          // n_levels
-  FH_STEPS,           // n_steps
-  FH_OPS,             // n_ops
   FH_SCALARS,         // n_scalars
+  FH_SCALAR_OFF,      // word offset of the scalar list
   FH_FREE,            // variables in no tensor (factor 2 each)
-  FH_INV_ELEMS,       // slice-invariant input elements (LDS [0, inv))
-  FH_DEP_ELEMS,       // per-slice input elements (LDS [inv, inv + dep))
-  FH_DATA_ELEMS,      // total LDS data elements
-  FH_INV_SRC,         // element offset of the invariant block (prepared)
-  FH_DEP_SRC,         // element offset of slice 0's block (prepared)
-  FH_N_SLICES,        // 2^m
+  FH_INV_ELEMS,       // slice-invariant input elements
+  FH_DEP_ELEMS,       // per-slice input elements
+  FH_DATA_ELEMS,      // total LDS data elements (including the constant)
+  FH_DEP_SRC,         // element offset of slice 0's block in the prepared buffer
+  FH_N_SLICES,        // 2^m (saturated)
   kHdr = 16
 };
+// Flag of a record's first word: product without the sum over u.
+constexpr uint32_t kRecNoSum = 1u;
 
 struct Plan {
   // host side
@@ -100,7 +112,8 @@ struct Plan {
   std::vector<uint32_t> fused_prog;
   std::vector<int32_t> fused_map;       // prepared fused buffer gather map
   int64_t fused_elems = 0;
-  int fused_lds_bytes = 0;
+  int fused_lds_bytes = 0;              // LDS of one workgroup
+  bool fused_prog_in_lds = false;       // records copied to LDS per slice
 
   // device side (owned)
   int device = -1;
@@ -111,6 +124,7 @@ struct Plan {
   void* d_fused_in = nullptr;   // complex64 prepared inputs, fused layout
   void* d_fused_prog = nullptr;
   void* d_scalar_tab = nullptr; // int64 arena offsets, int64 input bases, uint32 smasks
+  void* d_state = nullptr;      // uint32[4]: work counter, exits, items done (fused)
 };
 
 // A set of plans contracted together in one fused launch.
@@ -124,7 +138,10 @@ struct Batch {
   void* d_progs = nullptr;   // const uint32_t* per plan
   void* d_preps = nullptr;   // const float2* per plan
   void* d_items = nullptr;   // FusedItem per item
-  void* d_ranges = nullptr;  // int64 item_begin (n_plans + 1)
+  void* d_ranges = nullptr;  // int64 (begin, end) per plan
+  void* d_state = nullptr;   // uint32[2 + n_plans]: work, exits, items done per plan
+  bool reduce_here = true;   // the fused kernel sums each plan's items itself
+  bool prog_in_lds = true;   // every fused plan's records fit in LDS with its data
 };
 
 // Plan compilation (program.cpp).

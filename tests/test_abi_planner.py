@@ -115,7 +115,7 @@ def test_fused_form_chosen_for_small_slices_and_per_step_for_large():
     qm = qbe.Model.from_circuitgen(mod)
     _, mu, pi, _ = qbe.plan_circuit(qm, m=6)
     st_ = qbe.Plan(qm, pi, mu).stats()
-    assert st_["exec"] == qbe.EXEC["fused"] and 0 < st_["lds_bytes"] <= 64 * 1024
+    assert st_["exec"] == qbe.EXEC["fused"] and 0 < st_["lds_bytes"] <= 160 * 1024
     mod7 = circuit_model(random_grid_circuit(7, 7, 24, 0))
     q7 = qbe.Model.from_circuitgen(mod7)
     _, mu7, pi7, tau7 = qbe.plan_circuit(q7, m=10)
