@@ -117,6 +117,10 @@ def bench_hbm(torch, qbe, ctx, steps):
     st = plan.stats()
     ws = torch.empty(int(st["ws_bytes_all_slices"]), dtype=torch.uint8, device="cuda")
     out = torch.zeros(2, dtype=torch.float64, device="cuda")
+    t0 = time.perf_counter()
+    plan.autotune(ws)
+    tune_ms = (time.perf_counter() - t0) * 1e3
+    cfg["autotune_ms"] = tune_ms
     fn = lambda: qbe.qbe_contract_async(ctx, plan, ws, out)  # noqa: E731
     wall, ev = timed(torch, fn, steps, 1)
     got = complex(*out.cpu().numpy())

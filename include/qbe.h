@@ -170,6 +170,15 @@ int qbe_plan_stats(const qbe_plan* plan, qbe_stats* out);
  * terminated when it fits); *len_out = full length without the NUL. */
 int qbe_plan_dump(const qbe_plan* plan, char* buf, size_t cap, size_t* len_out);
 
+/* Autotuner for the per-step form: times each bucket kernel whose launch
+ * covers at least min_elems result entries in every candidate tile shape
+ * (tiles per thread in {1, 2, 4} x workgroups per compute unit in {4, 8, 16,
+ * 32}) on the device, with the workspace the contraction will use, and keeps
+ * the fastest shape in the plan.  Blocks until done.  Plans in the fused form
+ * have nothing to tune (QBE_OK).  The workspace contents are overwritten. */
+int qbe_plan_autotune(qbe_ctx* ctx, qbe_plan* plan, void* d_workspace, size_t ws_bytes,
+                      int64_t min_elems);
+
 /* ------------------------------------------------------------ contraction - */
 
 /* Contracts all 2^m slices and sums them (Eq. 4) in FP64.  d_workspace is a

@@ -79,6 +79,7 @@ _SIGS = {
     "qbe_plan_stats": (C.c_int, [_vp, C.POINTER(Stats)]),
     "qbe_plan_dump": (C.c_int, [_vp, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]),
     "qbe_plan_check": (C.c_int, [_vp]),
+    "qbe_plan_autotune": (C.c_int, [_vp, _vp, _vp, C.c_size_t, C.c_int64]),
     "qbe_contract": (C.c_int, [_vp, _vp, _vp, C.c_size_t, _f64p]),
     "qbe_contract_slices": (C.c_int, [_vp, _vp, C.c_int64, C.c_int64, _vp, C.c_size_t, _f64p, _f64p]),
     "qbe_contract_async": (C.c_int, [_vp, _vp, _vp, C.c_size_t, _vp]),
@@ -266,6 +267,11 @@ class Plan:
 
     def update_data(self, model: Model):
         _check(_lib.qbe_plan_update_data(self.handle, model.handle), "qbe_plan_update_data")
+
+    def autotune(self, ws, min_elems: int = 1 << 20):
+        """Times the large per-step launches in each tile shape; keeps the best."""
+        _check(_lib.qbe_plan_autotune(self.ctx.handle, self.handle, _vp(ws.data_ptr()), ws.numel(), min_elems),
+               "qbe_plan_autotune")
 
     def workspace(self, all_slices: bool = True):
         """A device workspace (torch uint8 tensor) of the plan's size."""

@@ -395,6 +395,15 @@ static int check_device_call(qbe_ctx* ctx, const qbe_plan* plan, void* ws) {
   return qbe::dev_set(ctx->device);
 }
 
+int qbe_plan_autotune(qbe_ctx* ctx, qbe_plan* plan, void* d_workspace, size_t ws_bytes, int64_t min_elems) {
+  QBE_GUARD_BEGIN
+  int rc = check_device_call(ctx, plan, d_workspace);
+  if (rc) return rc;
+  if (plan->p.exec != QBE_EXEC_PER_STEP) return QBE_OK;
+  return qbe::dev_autotune(plan->p, ctx->stream, d_workspace, ws_bytes, min_elems);
+  QBE_GUARD_END
+}
+
 int qbe_contract_async(qbe_ctx* ctx, const qbe_plan* plan, void* d_workspace, size_t ws_bytes,
                        double* d_amp_out) {
   QBE_GUARD_BEGIN

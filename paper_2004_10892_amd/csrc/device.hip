@@ -85,7 +85,9 @@ struct StepLaunch {
   int64_t n_tiles;
 };
 
-template <int K>
+// EPT: tiles whose operand loads are all issued before any of them is
+// used (more bytes in flight per thread).
+template <int K, int EPT>
 __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch a) {
   const int tid = threadIdx.x;
   const int r = a.r, lo = a.lo;
@@ -104,40 +106,56 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch a) {
     hi_mask[i] = (m >> lo) & ((1u << hib) - 1u);
     u_part[i] = (a.sum_u && ((m >> r) & 1u)) ? (1u << (a.rank[i] - 1)) : 0u;
   }
-  for (int64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
-    int64_t g;
-    uint32_t x_hi;
-    if (hib > 0) {
-      g = tile >> hib;
-      x_hi = (uint32_t)(tile & ((int64_t(1) << hib) - 1));
-    } else {
-      g = tile * spt + g_sub;
-      x_hi = 0;
-      if (g >= a.G) continue;
-    }
-    const int64_t s = a.s0 + g;
-    const float2* p[K];
+  for (int64_t t0 = (int64_t)blockIdx.x * EPT; t0 < a.n_tiles; t0 += (int64_t)gridDim.x * EPT) {
+    float2 v0[EPT][K], v1[EPT][K];
+    int64_t oidx[EPT];
+    bool ok[EPT];
 #pragma unroll
-    for (int i = 0; i < K; ++i) {
-      int64_t base;
-      if (a.gstride[i] != 0)
-        base = g * a.gstride[i];
-      else
-        base = (int64_t)pext32((uint32_t)s, a.smask[i]) << a.rank[i];
-      base += (int64_t)(pext32(x_hi, hi_mask[i]) << lo_cnt[i]) + lo_part[i];
-      p[i] = a.src[i] + base;
-    }
-    float2 acc = p[0][0];
+    for (int e = 0; e < EPT; ++e) {
+      const int64_t tile = t0 + e;
+      int64_t g;
+      uint32_t x_hi;
+      if (hib > 0) {
+        g = tile >> hib;
+        x_hi = (uint32_t)(tile & ((int64_t(1) << hib) - 1));
+        ok[e] = tile < a.n_tiles;
+      } else {
+        g = tile * spt + g_sub;
+        x_hi = 0;
+        ok[e] = tile < a.n_tiles && g < a.G;
+      }
+      oidx[e] = (g << r) + ((int64_t)x_hi << lo) + x_lo;
+      if (ok[e]) {
+        const int64_t s = a.s0 + g;
 #pragma unroll
-    for (int i = 1; i < K; ++i) acc = cmul(acc, p[i][0]);
-    if (a.sum_u) {
-      float2 t = p[0][u_part[0]];
-#pragma unroll
-      for (int i = 1; i < K; ++i) t = cmul(t, p[i][u_part[i]]);
-      acc.x += t.x;
-      acc.y += t.y;
+        for (int i = 0; i < K; ++i) {
+          int64_t base;
+          if (a.gstride[i] != 0)
+            base = g * a.gstride[i];
+          else
+            base = (int64_t)pext32((uint32_t)s, a.smask[i]) << a.rank[i];
+          base += (int64_t)(pext32(x_hi, hi_mask[i]) << lo_cnt[i]) + lo_part[i];
+          const float2* q = a.src[i] + base;
+          v0[e][i] = q[0];
+          v1[e][i] = q[u_part[i]];
+        }
+      }
     }
-    a.out[(g << r) + ((int64_t)x_hi << lo) + x_lo] = acc;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      if (!ok[e]) continue;
+      float2 acc = v0[e][0];
+#pragma unroll
+      for (int i = 1; i < K; ++i) acc = cmul(acc, v0[e][i]);
+      if (a.sum_u) {
+        float2 t = v1[e][0];
+#pragma unroll
+        for (int i = 1; i < K; ++i) t = cmul(t, v1[e][i]);
+        acc.x += t.x;
+        acc.y += t.y;
+      }
+      a.out[oidx[e]] = acc;
+    }
   }
 }
 
@@ -343,18 +361,22 @@ __global__ __launch_bounds__(kBlock) void fused_kernel(FusedArgs a) {
     __syncthreads();
     if (kProgLds && tid == 0) s_plan = plan;  // read again only after the next barrier
     const uint32_t n_levels = gprog[FH_LEVELS];
-    // level table: LDS copy when the program is there, else scalar loads
-    const uint32_t* lv = rprog + kHdr;
+    // level table (LDS copy when the program is there), read two levels
+    // ahead of use so that neither it nor the record prefetch waits
+    const uint4* lv = reinterpret_cast<const uint4*>(rprog + kHdr);
     uint4 p0 = make_uint4(0, 0, 0, 0), p1 = make_uint4(0, 0, 0, 0);
-    uint4 nxt = n_levels > 0 ? *reinterpret_cast<const uint4*>(lv) : make_uint4(0, 0, 0, 0);
-    if (n_levels > 0 && (uint32_t)tid < uni(nxt.y)) load_record(rprog + uni(nxt.x) + (size_t)tid * uni(nxt.z), uni(nxt.z), p0, p1);
+    uint4 t1 = make_uint4(0, 0, 0, 0), t2 = make_uint4(0, 0, 0, 0);
+    uint4 t0 = n_levels > 0 ? lv[0] : make_uint4(0, 0, 0, 0);
+    if (n_levels > 1) t1 = lv[1];
+    if (n_levels > 0 && (uint32_t)tid < uni(t0.y))
+      load_record(rprog + uni(t0.x) + (size_t)tid * uni(t0.z), uni(t0.z), p0, p1);
     for (uint32_t l = 0; l < n_levels; ++l) {
-      const uint32_t base = uni(nxt.x), E = uni(nxt.y), S = uni(nxt.z);
+      const uint32_t base = uni(t0.x), E = uni(t0.y), S = uni(t0.z);
       uint4 c0 = p0, c1 = p1;
       if (l + 1 < n_levels) {
-        nxt = reinterpret_cast<const uint4*>(lv)[l + 1];
-        const uint32_t nb = uni(nxt.x), nE = uni(nxt.y), nS = uni(nxt.z);
+        const uint32_t nb = uni(t1.x), nE = uni(t1.y), nS = uni(t1.z);
         if ((uint32_t)tid < nE) load_record(rprog + nb + (size_t)tid * nS, nS, p0, p1);
+        if (l + 2 < n_levels) t2 = lv[l + 2];
       }
       for (uint32_t f = tid; f < E; f += kBlock) {
         const uint32_t* rec = rprog + base + (size_t)f * S;
@@ -363,19 +385,30 @@ __global__ __launch_bounds__(kBlock) void fused_kernel(FusedArgs a) {
         record_product(data, c0, c1, S, rec, a0, a1);
         data[c0.x & 0xFFFFu] = (c0.x >> 16) & kRecNoSum ? a0 : cadd(a0, a1);
       }
+      t0 = t1;
+      t1 = t2;
       __syncthreads();
     }
-    if (tid == 0) {
-      double re = (double)(1u << gprog[FH_FREE]), im = 0.0;
-      const uint32_t* scal = gprog + gprog[FH_SCALAR_OFF];
+    if (tid < 64) {
+      // product of the slice's scalar factors: lane j holds factor j (and
+      // j + 64, ...), then a fixed binary tree across the wave, in FP64
+      const uint32_t* scal = rprog + gprog[FH_SCALAR_OFF];
       const uint32_t n_scal = gprog[FH_SCALARS];
-      for (uint32_t j = 0; j < n_scal; ++j) {
+      double re = tid == 0 ? (double)(1u << gprog[FH_FREE]) : 1.0, im = 0.0;
+      for (uint32_t j = tid; j < n_scal; j += 64) {
         const float2 v = data[scal[j]];
         const double vr = v.x, vi = v.y;
         const double nr = re * vr - im * vi;
         im = re * vi + im * vr;
         re = nr;
       }
+      for (int w = 1; w < 64; w <<= 1) {
+        const double orr = __shfl_down(re, w, 64), oi = __shfl_down(im, w, 64);
+        const double nr = re * orr - im * oi;
+        im = re * oi + im * orr;
+        re = nr;
+      }
+    if (tid == 0) {
       a.out[item] = make_double2(re, im);
       s_flag = 0u;
       if (a.reduce_here) {
@@ -391,6 +424,7 @@ __global__ __launch_bounds__(kBlock) void fused_kernel(FusedArgs a) {
         if ((int64_t)done == e - b) s_flag = 1u;
       }
     }
+    }
     __syncthreads();
     if (s_flag) {
       // last item of this plan: fixed-order FP64 sum of its items (same order
@@ -403,22 +437,27 @@ __global__ __launch_bounds__(kBlock) void fused_kernel(FusedArgs a) {
         e = a.ranges[2 * plan + 1];
       }
       double* sre = reinterpret_cast<double*>(lds4);
-      double* sim = sre + kBlock;
+      double* sim = sre + kBlock / 64;
       double re = 0.0, im = 0.0;
       for (int64_t i = b + tid; i < e; i += kBlock) {
         const double2 v = a.out[i];
         re += v.x;
         im += v.y;
       }
-      sre[tid] = re;
-      sim[tid] = im;
+      for (int w = 32; w > 0; w >>= 1) {
+        re += __shfl_down(re, w, 64);
+        im += __shfl_down(im, w, 64);
+      }
+      if ((tid & 63) == 0) {
+        sre[tid >> 6] = re;
+        sim[tid >> 6] = im;
+      }
       __syncthreads();
-      for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if (tid < w) {
-          sre[tid] += sre[tid + w];
-          sim[tid] += sim[tid + w];
+      if (tid == 0) {
+        for (int k = 1; k < kBlock / 64; ++k) {
+          sre[0] += sre[k];
+          sim[0] += sim[k];
         }
-        __syncthreads();
       }
       if (tid == 0) {
         a.amps[plan] = make_double2(sre[0], sim[0]);
@@ -564,7 +603,7 @@ size_t dev_workspace_all(const Plan& p) {
 }
 
 static int launch_step(const Plan& p, const StepProg& sp, float2* arena, int64_t G, int64_t s0,
-                       hipStream_t st) {
+                       hipStream_t st, int ept = 0, int wg_per_cu = 0) {
   StepLaunch a{};
   const bool sum_u = sp.out_rank >= 0;
   const int r = sum_u ? sp.out_rank : -sp.out_rank;
@@ -591,18 +630,81 @@ static int launch_step(const Plan& p, const StepProg& sp, float2* arena, int64_t
   }
   const int hib = r - a.lo;
   a.n_tiles = hib > 0 ? (G << hib) : (G + (kBlock >> a.lo) - 1) / (kBlock >> a.lo);
-  const int grid = (int)std::min<int64_t>(a.n_tiles, (int64_t)n_cus() * 16);
-  switch (sp.n_ops) {
-#define QBE_CASE(K) \
-  case K: step_kernel<K><<<grid, kBlock, 0, st>>>(a); break;
-    QBE_CASE(1) QBE_CASE(2) QBE_CASE(3) QBE_CASE(4) QBE_CASE(5) QBE_CASE(6) QBE_CASE(7) QBE_CASE(8)
-#undef QBE_CASE
+  if (ept <= 0) ept = sp.ept > 0 ? sp.ept : 1;
+  if (wg_per_cu <= 0) wg_per_cu = sp.wg_per_cu > 0 ? sp.wg_per_cu : 16;
+  const int64_t want = (a.n_tiles + ept - 1) / ept;
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)n_cus() * wg_per_cu));
+#define QBE_CASE(KK, EE) \
+  case KK * 16 + EE: step_kernel<KK, EE><<<grid, kBlock, 0, st>>>(a); break;
+#define QBE_KS(KK) QBE_CASE(KK, 1) QBE_CASE(KK, 2) QBE_CASE(KK, 4)
+  switch (sp.n_ops * 16 + ept) {
+    QBE_KS(1) QBE_KS(2) QBE_KS(3) QBE_KS(4) QBE_KS(5) QBE_KS(6) QBE_KS(7) QBE_KS(8)
     default:
-      set_error("bucket with an unsupported operand count");
+      set_error("per-step launch with an unsupported operand count or tile factor");
       return QBE_ERR_INTERNAL;
   }
+#undef QBE_KS
+#undef QBE_CASE
   QBE_HIP(hipGetLastError());
   return QBE_OK;
+}
+
+// Autotuner: times every large per-step launch of the plan on the device in
+// each candidate tile shape (tiles per thread x workgroups per CU) and keeps
+// the fastest.  Runs the plan's own schedule on a slice group of G slices, so
+// the data it reads are the intermediates of the group's slices.
+int dev_autotune(Plan& p, void* stream, void* ws, size_t ws_bytes, int64_t min_elems) {
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t n = p.n_slices;
+  if (ws_bytes < dev_workspace_min(p, 1)) {
+    set_error("workspace too small");
+    return QBE_ERR_MEM_CAP;
+  }
+  const int64_t per_slice_bytes = p.arena_per_slice * 8;
+  const int64_t G = std::min<int64_t>(n, (int64_t)((ws_bytes - ws_head(1)) / per_slice_bytes));
+  float2* arena = (float2*)((char*)ws + ws_head(1));
+  hipEvent_t e0, e1;
+  QBE_HIP(hipEventCreate(&e0));
+  QBE_HIP(hipEventCreate(&e1));
+  const int epts[] = {1, 2, 4};
+  const int wgs[] = {4, 8, 16, 32};
+  int rc = QBE_OK;
+  for (StepProg& sp : p.steps) {
+    const int r = sp.out_rank >= 0 ? sp.out_rank : -sp.out_rank;
+    if ((G << r) >= min_elems) {
+      float best = 1e30f;
+      int be = 1, bw = 16;
+      for (int e : epts)
+        for (int w : wgs) {
+          float total = 0.f;
+          for (int rep = 0; rep < 3 && rc == QBE_OK; ++rep) {
+            if (hipEventRecord(e0, st) != hipSuccess) rc = QBE_ERR_HIP;
+            if (rc == QBE_OK) rc = launch_step(p, sp, arena, G, 0, st, e, w);
+            if (rc == QBE_OK && hipEventRecord(e1, st) != hipSuccess) rc = QBE_ERR_HIP;
+            if (rc == QBE_OK && hipEventSynchronize(e1) != hipSuccess) rc = QBE_ERR_HIP;
+            float ms = 0.f;
+            if (rc == QBE_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = QBE_ERR_HIP;
+            if (rep > 0) total += ms;  // first run warms caches and code
+          }
+          if (rc != QBE_OK) break;
+          if (total < best) {
+            best = total;
+            be = e;
+            bw = w;
+          }
+        }
+      sp.ept = be;
+      sp.wg_per_cu = bw;
+    } else {
+      // launch-bound: the first configuration is as good as any
+      rc = launch_step(p, sp, arena, G, 0, st);
+    }
+    if (rc != QBE_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc == QBE_ERR_HIP) set_error("autotune: HIP event call failed");
+  return rc;
 }
 
 static int launch_fused(bool prog_lds, int grid, int lds_bytes, hipStream_t st, const FusedArgs& a) {

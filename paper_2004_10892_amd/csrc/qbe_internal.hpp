@@ -46,9 +46,12 @@ struct StepOp {
 };
 
 struct StepProg {
-  int32_t out_rank;   // r_b (0 for a scalar result)
+  int32_t out_rank;   // r_b (0 for a scalar result); negative: a partial
+                      // product over -out_rank variables without the sum
   int64_t out_base;   // arena offset (per-slice unit)
   int32_t n_ops;
+  int32_t ept = 0;        // tiles per thread per pass (0: default)
+  int32_t wg_per_cu = 0;  // workgroups per compute unit (0: default)
   StepOp ops[kMaxOps];
 };
 
@@ -158,6 +161,7 @@ int dev_contract(const Plan& p, void* stream, void* ws, size_t ws_bytes, int64_t
                  int64_t s_end, double* d_partial_out, double* d_per_slice /*may be null*/);
 size_t dev_workspace_min(const Plan& p, int64_t n_slices_in_call);
 size_t dev_workspace_all(const Plan& p);
+int dev_autotune(Plan& p, void* stream, void* ws, size_t ws_bytes, int64_t min_elems);
 int dev_batch_build(Batch& b);
 void dev_batch_free(Batch& b);
 size_t dev_batch_workspace(const Batch& b);

@@ -104,6 +104,9 @@ def test_7x7_d24_sampled_slices_and_full_amplitude(qbe, ctx):
     ws_all = torch.empty(min(st["ws_bytes_all_slices"], 64 << 30), dtype=torch.uint8, device="cuda")
     total = qbe.qbe_contract(ctx, plan, ws_all)
     assert rel(total, complex(*gold["oracle"])) <= TOL
+    _say("case 7x7 autotuned")
+    plan.autotune(ws_all)  # tile shapes change, the arithmetic per entry does not
+    assert qbe.qbe_contract(ctx, plan, ws_all) == total
 
 
 @pytest.mark.parametrize("seed", range(6))
