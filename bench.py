@@ -37,16 +37,16 @@ def golden(name):
     return complex(*g["oracle"])
 
 
-def build_plan(qbe, ctx, name, form):
+def build_plan(qbe, ctx, name, form, precision="fp32"):
     from circuitgen import WORKLOADS, circuit_model, random_grid_circuit
     r, c, d, m = WORKLOADS[name]
     mod = circuit_model(random_grid_circuit(r, c, d, SEEDS[name]))
     qm = qbe.Model.from_circuitgen(mod)
     t0 = time.perf_counter()
     order, mu, pi, tau = qbe.plan_circuit(qm, m=m)   # min-fill order + tree-trimming (Alg. 2)
-    qbe.Plan(qm, pi, mu, exec=form).close()          # schedule + device programs, host only
+    qbe.Plan(qm, pi, mu, exec=form, precision=precision).close()  # schedule + programs, host only
     t1 = time.perf_counter()
-    plan = qbe.Plan(qm, pi, mu, ctx=ctx, exec=form)  # again, plus upload and input preparation
+    plan = qbe.Plan(qm, pi, mu, ctx=ctx, exec=form, precision=precision)  # plus upload and prep
     t2 = time.perf_counter()
     return plan, (t1 - t0) * 1e3, {"rows": r, "cols": c, "depth": d, "m": m, "seed": SEEDS[name],
                                   "width": tau, "n_vars": mod.n_vars, "n_tensors": len(mod.tensors),
@@ -110,10 +110,11 @@ def cpu_baseline(name, budget_s=12.0):
                       f"einsum in one process; host has {os.cpu_count()} logical CPUs"}
 
 
-def bench_hbm(torch, qbe, ctx, steps):
-    """7x7 depth-24 circuit, 1024 slices, per-step form: HBM-bound kernels."""
+def bench_hbm(torch, qbe, ctx, steps, precision="fp32"):
+    """7x7 depth-24 circuit, 1024 slices, per-step form: HBM-bound kernels
+    (outer-product buckets on MFMA, in FP32 or split-BF16)."""
     name = "grid7x7_d24_m10"
-    plan, plan_ms, cfg = build_plan(qbe, ctx, name, "per_step")
+    plan, plan_ms, cfg = build_plan(qbe, ctx, name, "per_step", precision)
     st = plan.stats()
     ws = torch.empty(int(st["ws_bytes_all_slices"]), dtype=torch.uint8, device="cuda")
     out = torch.zeros(2, dtype=torch.float64, device="cuda")
@@ -127,7 +128,8 @@ def bench_hbm(torch, qbe, ctx, steps):
     want = golden(name)
     bytes_amp = st["bytes_per_slice"] * plan.n_slices
     flops_amp = st["flops_per_slice"] * plan.n_slices
-    return {"workload": name, "form": "per_step", "ms_per_amplitude": ev, "amplitudes_per_s": 1e3 / ev,
+    return {"workload": name, "form": "per_step", "precision": precision, "mfma_buckets": st["n_mfma_steps"],
+            "ms_per_amplitude": ev, "amplitudes_per_s": 1e3 / ev,
             "rel_err": abs(got - want) / abs(want), "planning_ms": plan_ms, "config": cfg,
             "roofline": {"bound": "hbm", "achieved": bytes_amp / (ev * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": bytes_amp / (ev * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
@@ -197,6 +199,7 @@ def main():
     want = golden(name)
     if args.only == "hbm":
         print(json.dumps(bench_hbm(torch, qbe, ctx, args.steps)), flush=True)
+        print(json.dumps(bench_hbm(torch, qbe, ctx, args.steps, "bf16x3")), flush=True)
         return
     if args.only == "batch":
         print(json.dumps(bench_batch(torch, qbe, ctx, args.steps)), flush=True)
@@ -251,6 +254,8 @@ def main():
     if not args.no_extra:
         log("[bench] 7x7 d24 per-step ...")
         line["hbm_workload"] = bench_hbm(torch, qbe, ctx, 5)
+        log("[bench] 7x7 d24 per-step, split-BF16 ...")
+        line["hbm_workload_bf16x3"] = bench_hbm(torch, qbe, ctx, 5, "bf16x3")
         log("[bench] batch of 512 ...")
         line["batch_workload"] = bench_batch(torch, qbe, ctx, 20)
     print(json.dumps(line), flush=True)

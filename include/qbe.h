@@ -64,8 +64,10 @@ enum {
 /* Arithmetic of the bucket products on the device. */
 enum {
   QBE_PREC_FP32 = 0,    /* complex64 products, FP32 accumulation            */
-  QBE_PREC_BF16X3 = 1   /* split-BF16 products (hi*hi + hi*lo + lo*hi),
-                           FP32 accumulation                                 */
+  QBE_PREC_BF16X3 = 1   /* split-BF16 products (hi*hi + hi*lo + lo*hi) with
+                           FP32 accumulation in the MFMA outer-product
+                           buckets of the per-step form; other buckets stay
+                           FP32.  Not available in the fused form.           */
 };
 
 typedef struct qbe_ctx qbe_ctx;
@@ -90,6 +92,9 @@ typedef struct qbe_stats {
   uint64_t peak_bytes_per_slice;       /* live-tensor peak                   */
   uint64_t ws_bytes_min;               /* smallest workspace contract accepts */
   uint64_t ws_bytes_all_slices;        /* workspace for all slices at once   */
+  int32_t n_mfma_steps;                /* per-step form: outer-product buckets
+                                          run as MFMA tiles                   */
+  int32_t precision;                   /* QBE_PREC_* of the plan             */
 } qbe_stats;
 
 /* ------------------------------------------------------------------ misc -- */

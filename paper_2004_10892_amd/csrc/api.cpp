@@ -277,6 +277,10 @@ int qbe_plan_create(qbe_ctx* ctx, const qbe_model* model, const int32_t* reduced
   p.cost = qbe::schedule_cost(p.sched);
   p.precision = o.precision;
   qbe::compile_plan(p);
+  if (o.exec == QBE_EXEC_FUSED && o.precision == QBE_PREC_BF16X3) {
+    set_error("the fused form computes in FP32 only");
+    return QBE_ERR_INVALID_ARG;
+  }
   if (o.exec == QBE_EXEC_FUSED && !p.fused_ok) {
     set_error("plan does not fit the fused (LDS-resident) form");
     return QBE_ERR_MEM_CAP;
@@ -348,6 +352,10 @@ int qbe_plan_stats(const qbe_plan* plan, qbe_stats* out) {
   out->peak_bytes_per_slice = p.cost.peak_bytes;
   out->ws_bytes_min = qbe::dev_workspace_min(p, p.n_slices);
   out->ws_bytes_all_slices = qbe::dev_workspace_all(p);
+  out->n_mfma_steps = 0;
+  for (const auto& sp : p.steps)
+    if (sp.mm_a >= 0) ++out->n_mfma_steps;
+  out->precision = p.precision;
   return QBE_OK;
   QBE_GUARD_END
 }

@@ -159,6 +159,133 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch a) {
   }
 }
 
+// ------------------------------------------------- outer-product buckets --
+//
+// A bucket whose result variables all belong to two operands A and B (both
+// holding u; any other operand holds only u) is a batched complex product
+//   R[c, m, n] = sum_u A[c, m, u] B[c, n, u] w(u)
+// over the variables of A only (m), of B only (n) and of both (c).  One
+// wavefront computes a 16 x 16 tile of (m, n) with two MFMAs, for the real
+// and the imaginary part, on the lowest four m- and n-variables of the
+// result; the tile loop runs over the slices and the remaining variables.
+// Real K = 4 stacks (Re, Im) x (u = 0, 1):
+//   Re R = [Re A0, Re A1, -Im A0, -Im A1] . [Re B0; Re B1; Im B0; Im B1]
+//   Im R = [Re A0, Re A1,  Im A0,  Im A1] . [Im B0; Im B1; Re B0; Re B1]
+// FP32 form: v_mfma_f32_16x16x4f32.  Split-BF16 form: each real entry is
+// split into hi + lo bfloat16 parts and one v_mfma_f32_16x16x16bf16 sums
+// hi*hi + hi*lo + lo*hi over K = 16 = [hi | hi | lo | 0] . [hi ; lo ; hi ; 0],
+// accumulating in FP32.
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef short shortx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t pdep32(uint32_t v, uint32_t m) {
+  uint32_t r = 0;
+  int k = 0;
+  while (m) {
+    const int b = __builtin_ctz(m);
+    r |= ((v >> k) & 1u) << b;
+    ++k;
+    m &= m - 1;
+  }
+  return r;
+}
+
+// Round-to-nearest-even conversion to bfloat16 (finite inputs).
+__device__ __forceinline__ uint32_t bf16_bits(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ float bf16_value(uint32_t b) { return __uint_as_float(b << 16); }
+
+struct MmLaunch {
+  float2* out;
+  const float2* src[2];     // A, B
+  int64_t gs[2];            // elements between slices (0: input tensor)
+  uint32_t sm[2];           // input slice masks
+  int32_t rk[2];            // ranks
+  uint32_t mk[2];           // masks over X (u = bit r)
+  const float2* usrc[kMaxOps];  // rank-1 operands on u
+  int64_t ugs[kMaxOps];
+  uint32_t usm[kMaxOps];
+  int32_t n_u;
+  uint32_t mtile, ntile, rest;  // result-bit masks: 4 m bits, 4 n bits, the others
+  int32_t r;
+  int64_t s0, G, n_tiles;
+};
+
+template <bool kBf16>
+__global__ __launch_bounds__(kBlock) void mm_kernel(MmLaunch a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int64_t n_waves = (int64_t)gridDim.x * (kBlock / 64);
+  const int r = a.r;
+  const uint32_t ubit = 1u << r;
+  const int row = lane & 15, grp = lane >> 4;
+  const uint32_t xm = pdep32((uint32_t)row, a.mtile), xn = pdep32((uint32_t)row, a.ntile);
+  const uint32_t ao0 = pext32(xm, a.mk[0]), ao1 = pext32(xm | ubit, a.mk[0]);
+  const uint32_t bo0 = pext32(xn, a.mk[1]), bo1 = pext32(xn | ubit, a.mk[1]);
+  uint32_t oo[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) oo[i] = pdep32((uint32_t)(4 * grp + i), a.mtile) | xn;
+  const int rb = r - 8;
+  for (int64_t t = wave; t < a.n_tiles; t += n_waves) {
+    const int64_t g = t >> rb;
+    const uint32_t xt = pdep32((uint32_t)(t & ((int64_t(1) << rb) - 1)), a.rest);
+    const int64_t s = a.s0 + g;
+    int64_t base[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      base[j] = a.gs[j] ? g * a.gs[j] : ((int64_t)pext32((uint32_t)s, a.sm[j]) << a.rk[j]);
+      base[j] += pext32(xt, a.mk[j]);
+    }
+    float2 A0 = a.src[0][base[0] + ao0], A1 = a.src[0][base[0] + ao1];
+    const float2 B0 = a.src[1][base[1] + bo0], B1 = a.src[1][base[1] + bo1];
+    for (int j = 0; j < a.n_u; ++j) {
+      const int64_t ub = a.ugs[j] ? g * a.ugs[j] : ((int64_t)pext32((uint32_t)s, a.usm[j]) << 1);
+      A0 = cmul(A0, a.usrc[j][ub]);
+      A1 = cmul(A1, a.usrc[j][ub + 1]);
+    }
+    floatx4 cre = {0.f, 0.f, 0.f, 0.f}, cim = {0.f, 0.f, 0.f, 0.f};
+    if (!kBf16) {
+      // lane holds real-K entry k = grp of its row (A) and of its column (B)
+      const float2 Av = (grp & 1) ? A1 : A0;
+      const float2 Bv = (grp & 1) ? B1 : B0;
+      const float a1 = (grp >> 1) ? -Av.y : Av.x, a2 = (grp >> 1) ? Av.y : Av.x;
+      const float b1 = (grp >> 1) ? Bv.y : Bv.x, b2 = (grp >> 1) ? Bv.x : Bv.y;
+      cre = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, cre, 0, 0, 0);
+      cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, b2, cim, 0, 0, 0);
+    } else {
+      // lane holds the four real-K entries of its row / column, as the part
+      // its group stands for (A: hi, hi, lo, 0; B: hi, lo, hi, 0)
+      const float ra1[4] = {A0.x, A1.x, -A0.y, -A1.y}, ra2[4] = {A0.x, A1.x, A0.y, A1.y};
+      const float rb1[4] = {B0.x, B1.x, B0.y, B1.y}, rb2[4] = {B0.y, B1.y, B0.x, B1.x};
+      shortx4 pa1, pa2, pb1, pb2;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        uint32_t h, w;
+        h = bf16_bits(ra1[v]);
+        w = grp == 2 ? bf16_bits(ra1[v] - bf16_value(h)) : h;
+        pa1[v] = (short)(grp == 3 ? 0u : w);
+        h = bf16_bits(ra2[v]);
+        w = grp == 2 ? bf16_bits(ra2[v] - bf16_value(h)) : h;
+        pa2[v] = (short)(grp == 3 ? 0u : w);
+        h = bf16_bits(rb1[v]);
+        w = grp == 1 ? bf16_bits(rb1[v] - bf16_value(h)) : h;
+        pb1[v] = (short)(grp == 3 ? 0u : w);
+        h = bf16_bits(rb2[v]);
+        w = grp == 1 ? bf16_bits(rb2[v] - bf16_value(h)) : h;
+        pb2[v] = (short)(grp == 3 ? 0u : w);
+      }
+      cre = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(pa1, pb1, cre, 0, 0, 0);
+      cim = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(pa2, pb2, cim, 0, 0, 0);
+    }
+    const int64_t ob = (g << r) | xt;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a.out[ob | oo[i]] = make_float2(cre[i], cim[i]);
+  }
+}
+
 // Per-slice product of the scalar factors, in FP64.
 struct FinalizeArgs {
   const float2* arena;
@@ -627,6 +754,47 @@ static int launch_step(const Plan& p, const StepProg& sp, float2* arena, int64_t
     }
     a.mask[i] = o.mask;
     a.rank[i] = o.rank;
+  }
+  if (sp.mm_a >= 0 && sum_u && r >= 8) {
+    MmLaunch m{};
+    m.out = a.out;
+    const int idx[2] = {sp.mm_a, sp.mm_b};
+    for (int j = 0; j < 2; ++j) {
+      m.src[j] = a.src[idx[j]];
+      m.gs[j] = a.gstride[idx[j]];
+      m.sm[j] = a.smask[idx[j]];
+      m.rk[j] = a.rank[idx[j]];
+      m.mk[j] = a.mask[idx[j]];
+    }
+    for (int i = 0; i < sp.n_ops; ++i) {
+      if (i == sp.mm_a || i == sp.mm_b) continue;
+      m.usrc[m.n_u] = a.src[i];
+      m.ugs[m.n_u] = a.gstride[i];
+      m.usm[m.n_u] = a.smask[i];
+      ++m.n_u;
+    }
+    const uint32_t xmask = (1u << r) - 1u;
+    uint32_t oa = m.mk[0] & xmask & ~m.mk[1], ob = m.mk[1] & xmask & ~m.mk[0];
+    for (int k = 0; k < 4; ++k) {
+      m.mtile |= oa & (~oa + 1u);
+      oa &= oa - 1u;
+      m.ntile |= ob & (~ob + 1u);
+      ob &= ob - 1u;
+    }
+    m.rest = xmask & ~m.mtile & ~m.ntile;
+    m.r = r;
+    m.s0 = s0;
+    m.G = G;
+    m.n_tiles = G << (r - 8);
+    if (wg_per_cu <= 0) wg_per_cu = sp.wg_per_cu > 0 ? sp.wg_per_cu : 8;
+    const int64_t want = (m.n_tiles + 3) / 4;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)n_cus() * wg_per_cu));
+    if (p.precision == QBE_PREC_BF16X3)
+      mm_kernel<true><<<grid, kBlock, 0, st>>>(m);
+    else
+      mm_kernel<false><<<grid, kBlock, 0, st>>>(m);
+    QBE_HIP(hipGetLastError());
+    return QBE_OK;
   }
   const int hib = r - a.lo;
   a.n_tiles = hib > 0 ? (G << hib) : (G + (kBlock >> a.lo) - 1) / (kBlock >> a.lo);

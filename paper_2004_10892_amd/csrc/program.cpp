@@ -225,6 +225,26 @@ void compile_plan(Plan& p) {
     }
     StepProg sp{};
     sp.out_rank = rb;
+    {
+      // outer-product shape: two operands hold x bits (and u), the rest only u
+      const uint32_t ubit = 1u << rb, xmask = ubit - 1u;
+      int big[2] = {-1, -1}, nbig = 0;
+      bool ok = (int)ops.size() <= kMaxOps;
+      for (size_t i = 0; i < ops.size() && ok; ++i) {
+        if (ops[i].mask & xmask) {
+          if (nbig < 2 && (ops[i].mask & ubit)) big[nbig++] = (int)i; else ok = false;
+        } else if (ops[i].mask != ubit) {
+          ok = false;
+        }
+      }
+      if (ok && nbig == 2) {
+        const uint32_t ma = ops[big[0]].mask & xmask, mb = ops[big[1]].mask & xmask;
+        if (__builtin_popcount(ma & ~mb) >= 4 && __builtin_popcount(mb & ~ma) >= 4 && ((ma | mb) == xmask)) {
+          sp.mm_a = big[0];
+          sp.mm_b = big[1];
+        }
+      }
+    }
     const int64_t osz = int64_t(1) << rb;
     out_off[k] = arena.alloc(osz, align_for(osz));
     sp.out_base = out_off[k];

@@ -35,6 +35,20 @@ std::string check_plan(const Plan& p) {
     if (sp.n_ops < 1 || sp.n_ops > kMaxOps) return "operand count";
     if (sp.out_base < 0 || sp.out_base + (int64_t(1) << r) > p.arena_per_slice)
       return fail("result outside the arena", sp.out_base + (int64_t(1) << r), p.arena_per_slice);
+    if (sp.mm_a >= 0) {
+      // the MFMA tile kernel's assumptions
+      if (!sum_u || r < 8 || sp.mm_b < 0 || sp.mm_a == sp.mm_b || sp.mm_a >= sp.n_ops || sp.mm_b >= sp.n_ops)
+        return "outer-product bucket shape";
+      const uint32_t ubit = 1u << r, xm = ubit - 1u;
+      const uint32_t ma = sp.ops[sp.mm_a].mask, mb = sp.ops[sp.mm_b].mask;
+      if (!(ma & ubit) || !(mb & ubit)) return "outer-product operand without u";
+      if (((ma | mb) & xm) != xm) return "outer-product result variable outside A and B";
+      if (__builtin_popcount(ma & ~mb & xm) < 4 || __builtin_popcount(mb & ~ma & xm) < 4)
+        return "outer-product tile needs four private variables per side";
+      for (int i = 0; i < sp.n_ops; ++i)
+        if (i != sp.mm_a && i != sp.mm_b && (sp.ops[i].mask != ubit || sp.ops[i].rank != 1))
+          return "outer-product extra operand not a rank-1 tensor on u";
+    }
     for (int i = 0; i < sp.n_ops; ++i) {
       const StepOp& o = sp.ops[i];
       if (__builtin_popcount(o.mask) != o.rank) return "operand mask and rank disagree";

@@ -52,6 +52,10 @@ struct StepProg {
   int32_t n_ops;
   int32_t ept = 0;        // tiles per thread per pass (0: default)
   int32_t wg_per_cu = 0;  // workgroups per compute unit (0: default)
+  // Outer-product buckets (two operands A, B holding u, the others only u)
+  // run on MFMA in 16 x 16 result tiles: indices of A and B in ops, -1 if
+  // the bucket is not of that shape.
+  int32_t mm_a = -1, mm_b = -1;
   StepOp ops[kMaxOps];
 };
 
