@@ -158,6 +158,24 @@ int qbe_slice(const qbe_model* model, const int32_t* order, int32_t n, int32_t m
               int32_t target_width, int32_t score, int32_t* mu_out, int32_t* m_out,
               int32_t* reduced_order_out, int32_t* tau_out);
 
+/* Exact cost (the project's cost model for Sec. 4's per-subtask memory and
+ * FLOPs) of contracting with the reduced order and sliced set, without
+ * building device programs: out[0] = real FLOPs per slice, out[1] =
+ * algorithmic complex64 bytes per slice, out[2] = peak live bytes per slice,
+ * out[3] = largest |U_b| - 1.  Totals are 2^m times the per-slice counts. */
+int qbe_schedule_cost(const qbe_model* model, const int32_t* reduced_order, int32_t n, const int32_t* mu,
+                      int32_t m, uint64_t* out);
+
+/* Features of every variable for the learned slicing proposal, computed on
+ * the graph without the `removed` variables and its order `order` (a
+ * permutation of the remaining ones): 8 floats per variable (degree,
+ * relative order position, |N+(u)| / width, membership of a maximum bag of
+ * the App. A tree, bags holding u and their total size relative to the
+ * maxima, largest bag / 32, 1).  Rows of removed variables are zero.
+ * feats_out: 8 * n_vars floats. */
+int qbe_vertex_features(const qbe_model* model, const int32_t* order, int32_t n, const int32_t* removed,
+                        int32_t n_removed, float* feats_out);
+
 /* Compiles the bucket schedule (Eq. 2) of the reduced order and the sliced
  * set, the device programs and their memory layout.  ctx may be NULL for a
  * host-only plan (stats and dump work, contraction calls fail with
@@ -225,6 +243,42 @@ int qbe_batch_workspace(const qbe_batch* batch, size_t* ws_bytes_out);
  * or synchronisation inside, so the call may be captured into a HIP graph. */
 int qbe_batch_contract_async(qbe_ctx* ctx, const qbe_batch* batch, void* d_workspace, size_t ws_bytes,
                              double* d_amps_out);
+
+/* ------------------------------------------------------ learned proposal - */
+
+/* A message-passing network that scores variables for slicing: 8 input
+ * features per variable (qbe_vertex_features), three layers
+ * H' = relu(H Ws + mean_{neighbours} H Wn + b) of width 64 and a linear head.
+ * Weights are FP16 in the device passes (FP32 master copy for Adam), sums
+ * are FP32.  Parameters: a flat float vector of qbe_gnn_num_params() entries,
+ * layer by layer (Ws[din][64], Wn[din][64], b[64]), then the head (w[64], c).
+ * Created with Glorot-uniform weights from a SplitMix64 stream of `seed`.
+ * Graphs are passed as symmetric CSR (rowptr[n + 1], col[rowptr[n]]) over n
+ * vertices with feats[n * 8]; the call checks ranges and symmetry. */
+typedef struct qbe_gnn qbe_gnn;
+int qbe_gnn_create(qbe_ctx* ctx, uint64_t seed, qbe_gnn** out);
+int qbe_gnn_destroy(qbe_gnn* gnn);
+int32_t qbe_gnn_num_params(void);
+int qbe_gnn_get_params(const qbe_gnn* gnn, float* params_out);
+/* Replaces the parameters and resets the optimizer state. */
+int qbe_gnn_set_params(qbe_gnn* gnn, const float* params);
+/* Forward pass on the device: scores_out[n] (host). */
+int qbe_gnn_score(qbe_ctx* ctx, qbe_gnn* gnn, int32_t n, const int32_t* rowptr, const int32_t* col,
+                  const float* feats, float* scores_out);
+/* One training step on the device: forward, loss = mean over the n_cand
+ * candidate vertices of (score - target)^2, backward, and (if lr > 0) one
+ * Adam step (betas 0.9, 0.999, eps 1e-8).  loss_out (1 float) and grads_out
+ * (qbe_gnn_num_params() floats, the gradient before the step) are optional. */
+int qbe_gnn_train_step(qbe_ctx* ctx, qbe_gnn* gnn, int32_t n, const int32_t* rowptr, const int32_t* col,
+                       const float* feats, int32_t n_cand, const int32_t* cand, const float* target, float lr,
+                       float* loss_out, float* grads_out);
+
+/* The model's simple graph without `removed`, as CSR over all n_vars ids
+ * (removed vertices have no neighbours): rowptr_out[n_vars + 1], col_out
+ * (capacity cap, neighbours ascending); QBE_ERR_MEM_CAP if cap is short
+ * (*nnz_out still set). */
+int qbe_graph_csr(const qbe_model* model, const int32_t* removed, int32_t n_removed, int32_t* rowptr_out,
+                  int32_t* col_out, int64_t cap, int64_t* nnz_out);
 
 /* ----------------------------------------------------------- diagnostics - */
 

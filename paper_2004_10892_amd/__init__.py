@@ -73,6 +73,8 @@ _SIGS = {
     "qbe_width": (C.c_int, [_vp, _i32p, C.c_int32, _i32p, C.c_int32, _i32p]),
     "qbe_clique_tree": (C.c_int, [_vp, _i32p, C.c_int32, _i32p, _i32p, _i32p, C.c_int64, _i32p]),
     "qbe_slice": (C.c_int, [_vp, _i32p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _i32p, _i32p, _i32p, _i32p]),
+    "qbe_schedule_cost": (C.c_int, [_vp, _i32p, C.c_int32, _i32p, C.c_int32, C.POINTER(C.c_uint64)]),
+    "qbe_vertex_features": (C.c_int, [_vp, _i32p, C.c_int32, _i32p, C.c_int32, C.POINTER(C.c_float)]),
     "qbe_plan_create": (C.c_int, [_vp, _vp, _i32p, C.c_int32, _i32p, C.c_int32, C.POINTER(PlanOpts), C.POINTER(_vp)]),
     "qbe_plan_destroy": (C.c_int, [_vp]),
     "qbe_plan_update_data": (C.c_int, [_vp, _vp]),
@@ -83,6 +85,15 @@ _SIGS = {
     "qbe_contract": (C.c_int, [_vp, _vp, _vp, C.c_size_t, _f64p]),
     "qbe_contract_slices": (C.c_int, [_vp, _vp, C.c_int64, C.c_int64, _vp, C.c_size_t, _f64p, _f64p]),
     "qbe_contract_async": (C.c_int, [_vp, _vp, _vp, C.c_size_t, _vp]),
+    "qbe_gnn_num_params": (C.c_int32, []),
+    "qbe_gnn_create": (C.c_int, [_vp, C.c_uint64, C.POINTER(_vp)]),
+    "qbe_gnn_destroy": (C.c_int, [_vp]),
+    "qbe_gnn_get_params": (C.c_int, [_vp, C.POINTER(C.c_float)]),
+    "qbe_gnn_set_params": (C.c_int, [_vp, C.POINTER(C.c_float)]),
+    "qbe_gnn_score": (C.c_int, [_vp, _vp, C.c_int32, _i32p, _i32p, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
+    "qbe_gnn_train_step": (C.c_int, [_vp, _vp, C.c_int32, _i32p, _i32p, C.POINTER(C.c_float), C.c_int32, _i32p,
+                                     C.POINTER(C.c_float), C.c_float, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
+    "qbe_graph_csr": (C.c_int, [_vp, _i32p, C.c_int32, _i32p, _i32p, C.c_int64, C.POINTER(C.c_int64)]),
     "qbe_batch_create": (C.c_int, [_vp, C.POINTER(_vp), C.c_int32, C.POINTER(_vp)]),
     "qbe_batch_destroy": (C.c_int, [_vp]),
     "qbe_batch_workspace": (C.c_int, [_vp, C.POINTER(C.c_size_t)]),
@@ -230,6 +241,29 @@ def qbe_slice(model: Model, order: Sequence[int], m: int, target_width: int = -1
     return mu[:k].tolist(), red[:n - k].tolist(), tau.value
 
 
+def qbe_schedule_cost(model: Model, reduced_order: Sequence[int], mu: Sequence[int]) -> dict:
+    """Exact per-slice cost of a schedule (no device programs)."""
+    o = _i32(reduced_order)
+    u = _i32(mu)
+    out = (C.c_uint64 * 4)()
+    _check(_lib.qbe_schedule_cost(model.handle, _p32(o), len(o), _p32(u), len(u), out), "qbe_schedule_cost")
+    return {"flops_per_slice": out[0], "bytes_per_slice": out[1], "peak_bytes_per_slice": out[2],
+            "width": int(out[3]), "n_slices": 1 << len(u)}
+
+
+FEATURES = 8
+
+
+def qbe_vertex_features(model: Model, order: Sequence[int], removed: Sequence[int] = ()) -> np.ndarray:
+    """(n_vars, 8) float32 features of the graph without `removed`."""
+    o = _i32(order)
+    r = _i32(removed)
+    out = np.zeros((model.n_vars, FEATURES), dtype=np.float32)
+    _check(_lib.qbe_vertex_features(model.handle, _p32(o), len(o), _p32(r), len(r),
+                                    out.ctypes.data_as(C.POINTER(C.c_float))), "qbe_vertex_features")
+    return out
+
+
 # ------------------------------------------------------------------- plans --
 
 class Plan:
@@ -337,6 +371,78 @@ class Batch:
     def close(self):
         if getattr(self, "handle", None):
             _lib.qbe_batch_destroy(self.handle)
+            self.handle = None
+
+    __del__ = close
+
+
+# -------------------------------------------------------- learned proposal --
+
+def _fp(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def qbe_graph_csr(model: Model, removed: Sequence[int] = ()):
+    """(rowptr int32[n_vars + 1], col int32[nnz]) of the graph without `removed`."""
+    r = _i32(removed)
+    rp = np.zeros(model.n_vars + 1, dtype=np.int32)
+    nnz = C.c_int64()
+    cap = 1 << 16
+    while True:
+        col = np.zeros(cap, dtype=np.int32)
+        rc = _lib.qbe_graph_csr(model.handle, _p32(r), len(r), _p32(rp), _p32(col), cap, C.byref(nnz))
+        if rc == -4:
+            cap = int(nnz.value)
+            continue
+        _check(rc, "qbe_graph_csr")
+        return rp, col[:nnz.value].copy()
+
+
+class Gnn:
+    """The learned slicing proposal's network, resident on the device."""
+
+    n_params = int(_lib.qbe_gnn_num_params())
+
+    def __init__(self, ctx: Context, seed: int = 0):
+        h = _vp()
+        _check(_lib.qbe_gnn_create(ctx.handle, seed, C.byref(h)), "qbe_gnn_create")
+        self.handle = h
+        self.ctx = ctx
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(self.n_params, dtype=np.float32)
+        _check(_lib.qbe_gnn_get_params(self.handle, _fp(out)), "qbe_gnn_get_params")
+        return out
+
+    def set_params(self, p: np.ndarray):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        assert p.shape == (self.n_params,)
+        _check(_lib.qbe_gnn_set_params(self.handle, _fp(p)), "qbe_gnn_set_params")
+
+    def score(self, rowptr, col, feats) -> np.ndarray:
+        rp, cl = _i32(rowptr), _i32(col)
+        f = np.ascontiguousarray(feats, dtype=np.float32)
+        n = len(rp) - 1
+        out = np.zeros(n, dtype=np.float32)
+        _check(_lib.qbe_gnn_score(self.ctx.handle, self.handle, n, _p32(rp), _p32(cl), _fp(f), _fp(out)),
+               "qbe_gnn_score")
+        return out
+
+    def train_step(self, rowptr, col, feats, cand, target, lr: float, want_grads: bool = False):
+        rp, cl, cd = _i32(rowptr), _i32(col), _i32(cand)
+        f = np.ascontiguousarray(feats, dtype=np.float32)
+        y = np.ascontiguousarray(target, dtype=np.float32)
+        n = len(rp) - 1
+        loss = np.zeros(1, dtype=np.float32)
+        grads = np.zeros(self.n_params, dtype=np.float32) if want_grads else None
+        _check(_lib.qbe_gnn_train_step(self.ctx.handle, self.handle, n, _p32(rp), _p32(cl), _fp(f), len(cd),
+                                       _p32(cd), _fp(y), lr, _fp(loss), _fp(grads) if want_grads else None),
+               "qbe_gnn_train_step")
+        return (float(loss[0]), grads) if want_grads else float(loss[0])
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.qbe_gnn_destroy(self.handle)
             self.handle = None
 
     __del__ = close

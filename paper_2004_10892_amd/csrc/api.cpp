@@ -1,6 +1,7 @@
 // C ABI of the library (declared in include/qbe.h).  Every entry point
 // catches all C++ exceptions and turns them into error codes.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -22,6 +23,10 @@ struct qbe_model {
 struct qbe_plan {
   qbe::Plan p;
   qbe_ctx* ctx = nullptr;
+};
+
+struct qbe_gnn {
+  qbe::Gnn g;
 };
 
 struct qbe_batch {
@@ -252,6 +257,35 @@ int qbe_slice(const qbe_model* model, const int32_t* order, int32_t n, int32_t m
   for (size_t i = 0; i < d.reduced_order.size(); ++i) reduced_order_out[i] = d.reduced_order[i];
   *m_out = (int32_t)d.mu.size();
   *tau_out = d.tau;
+  return QBE_OK;
+  QBE_GUARD_END
+}
+
+int qbe_schedule_cost(const qbe_model* model, const int32_t* reduced_order, int32_t n, const int32_t* mu,
+                      int32_t m, uint64_t* out) {
+  QBE_GUARD_BEGIN
+  QBE_REQUIRE(model && out, "NULL argument");
+  qbe::Schedule s = qbe::build_schedule(model->m.n_vars, model->m.tvars, vec(reduced_order, n), vec(mu, m));
+  qbe::ScheduleCost c = qbe::schedule_cost(s);
+  out[0] = c.flops;
+  out[1] = c.bytes;
+  out[2] = c.peak_bytes;
+  out[3] = (uint64_t)c.width;
+  return QBE_OK;
+  QBE_GUARD_END
+}
+
+int qbe_vertex_features(const qbe_model* model, const int32_t* order, int32_t n, const int32_t* removed,
+                        int32_t n_removed, float* feats_out) {
+  QBE_GUARD_BEGIN
+  QBE_REQUIRE(model && feats_out, "NULL argument");
+  qbe::Graph g = graph_of(model->m);
+  for (int v : vec(removed, n_removed)) {
+    QBE_REQUIRE(v >= 0 && v < g.n && g.present[v], "bad removed vertex");
+    g.remove_vertex(v);
+  }
+  auto f = qbe::vertex_features(g, vec(order, n));
+  std::copy(f.begin(), f.end(), feats_out);
   return QBE_OK;
   QBE_GUARD_END
 }
@@ -495,6 +529,155 @@ int qbe_batch_contract_async(qbe_ctx* ctx, const qbe_batch* batch, void* d_works
   int rc = qbe::dev_set(ctx->device);
   if (rc) return rc;
   return qbe::dev_batch_contract(batch->b, ctx->stream, d_workspace, ws_bytes, d_amps_out);
+  QBE_GUARD_END
+}
+
+// ---------------------------------------------------------- learned proposal
+
+int32_t qbe_gnn_num_params(void) { return qbe::gnn_num_params(); }
+
+int qbe_gnn_create(qbe_ctx* ctx, uint64_t seed, qbe_gnn** out) {
+  QBE_GUARD_BEGIN
+  QBE_REQUIRE(ctx && out, "NULL argument");
+  *out = nullptr;
+  int rc = qbe::dev_set(ctx->device);
+  if (rc) return rc;
+  auto* n = new qbe_gnn;
+  std::unique_ptr<qbe_gnn> guard(n);
+  rc = qbe::gnn_alloc(n->g, ctx->device);
+  if (rc) {
+    qbe::gnn_free(n->g);
+    return rc;
+  }
+  // Glorot-uniform weights, zero biases, from SplitMix64 (Steele et al. 2014)
+  std::vector<float> p(qbe::gnn_num_params(), 0.f);
+  uint64_t state = seed;
+  auto next = [&]() {
+    state += 0x9E3779B97F4A7C15ull;
+    uint64_t z = state;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  };
+  auto uniform = [&](float lim) { return (float)((double)(next() >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0) * lim; };
+  size_t o = 0;
+  for (int l = 0; l < qbe::kGnnLayers; ++l) {
+    const int din = l == 0 ? qbe::kGnnFeatures : qbe::kGnnHidden;
+    const float lim = std::sqrt(6.f / (float)(din + qbe::kGnnHidden));
+    for (int i = 0; i < 2 * din * qbe::kGnnHidden; ++i) p[o++] = uniform(lim);
+    o += qbe::kGnnHidden;
+  }
+  const float lim = std::sqrt(6.f / (float)(qbe::kGnnHidden + 1));
+  for (int i = 0; i < qbe::kGnnHidden; ++i) p[o++] = uniform(lim);
+  rc = qbe::gnn_set_params(n->g, p.data(), true);
+  if (rc) {
+    qbe::gnn_free(n->g);
+    return rc;
+  }
+  *out = guard.release();
+  return QBE_OK;
+  QBE_GUARD_END
+}
+
+int qbe_gnn_destroy(qbe_gnn* gnn) {
+  if (gnn) {
+    (void)qbe::dev_set(gnn->g.device);
+    qbe::gnn_free(gnn->g);
+    delete gnn;
+  }
+  return QBE_OK;
+}
+
+int qbe_gnn_get_params(const qbe_gnn* gnn, float* params_out) {
+  QBE_GUARD_BEGIN
+  QBE_REQUIRE(gnn && params_out, "NULL argument");
+  int rc = qbe::dev_set(gnn->g.device);
+  if (rc) return rc;
+  return qbe::gnn_get_params(gnn->g, params_out);
+  QBE_GUARD_END
+}
+
+int qbe_gnn_set_params(qbe_gnn* gnn, const float* params) {
+  QBE_GUARD_BEGIN
+  QBE_REQUIRE(gnn && params, "NULL argument");
+  int rc = qbe::dev_set(gnn->g.device);
+  if (rc) return rc;
+  return qbe::gnn_set_params(gnn->g, params, true);
+  QBE_GUARD_END
+}
+
+// Ranges and symmetry of a CSR graph (the transposed aggregation of the
+// backward pass relies on symmetry).
+static int check_csr(int32_t n, const int32_t* rp, const int32_t* col) {
+  if (n <= 0 || !rp) return QBE_ERR_INVALID_ARG;
+  if (rp[0] != 0) return QBE_ERR_INVALID_ARG;
+  for (int v = 0; v < n; ++v)
+    if (rp[v + 1] < rp[v]) return QBE_ERR_INVALID_ARG;
+  if (rp[n] > 0 && !col) return QBE_ERR_INVALID_ARG;
+  for (int v = 0; v < n; ++v)
+    for (int j = rp[v]; j < rp[v + 1]; ++j) {
+      const int w = col[j];
+      if (w < 0 || w >= n || w == v) return QBE_ERR_INVALID_ARG;
+      bool back = false;
+      for (int k = rp[w]; k < rp[w + 1] && !back; ++k) back = col[k] == v;
+      if (!back) return QBE_ERR_INVALID_ARG;
+    }
+  return QBE_OK;
+}
+
+int qbe_gnn_score(qbe_ctx* ctx, qbe_gnn* gnn, int32_t n, const int32_t* rowptr, const int32_t* col,
+                  const float* feats, float* scores_out) {
+  QBE_GUARD_BEGIN
+  QBE_REQUIRE(ctx && gnn && feats && scores_out, "NULL argument");
+  QBE_REQUIRE(check_csr(n, rowptr, col) == QBE_OK, "graph is not a symmetric CSR over n vertices");
+  int rc = qbe::dev_set(ctx->device);
+  if (rc) return rc;
+  return qbe::gnn_score(gnn->g, ctx->stream, n, rowptr, col, feats, scores_out);
+  QBE_GUARD_END
+}
+
+int qbe_gnn_train_step(qbe_ctx* ctx, qbe_gnn* gnn, int32_t n, const int32_t* rowptr, const int32_t* col,
+                       const float* feats, int32_t n_cand, const int32_t* cand, const float* target, float lr,
+                       float* loss_out, float* grads_out) {
+  QBE_GUARD_BEGIN
+  QBE_REQUIRE(ctx && gnn && feats, "NULL argument");
+  QBE_REQUIRE(check_csr(n, rowptr, col) == QBE_OK, "graph is not a symmetric CSR over n vertices");
+  QBE_REQUIRE(n_cand >= 0 && (n_cand == 0 || (cand && target)), "bad candidates");
+  std::vector<uint8_t> seen(n, 0);
+  for (int i = 0; i < n_cand; ++i) {
+    QBE_REQUIRE(cand[i] >= 0 && cand[i] < n && !seen[cand[i]], "candidates must be distinct vertex ids");
+    seen[cand[i]] = 1;
+  }
+  int rc = qbe::dev_set(ctx->device);
+  if (rc) return rc;
+  return qbe::gnn_train_step(gnn->g, ctx->stream, n, rowptr, col, feats, n_cand, cand, target, lr, loss_out,
+                             grads_out);
+  QBE_GUARD_END
+}
+
+int qbe_graph_csr(const qbe_model* model, const int32_t* removed, int32_t n_removed, int32_t* rowptr_out,
+                  int32_t* col_out, int64_t cap, int64_t* nnz_out) {
+  QBE_GUARD_BEGIN
+  QBE_REQUIRE(model && rowptr_out && nnz_out, "NULL argument");
+  qbe::Graph g = graph_of(model->m);
+  for (int v : vec(removed, n_removed)) {
+    QBE_REQUIRE(v >= 0 && v < g.n && g.present[v], "bad removed vertex");
+    g.remove_vertex(v);
+  }
+  int64_t nnz = 0;
+  for (int v = 0; v < g.n; ++v) nnz += g.degree(v);
+  *nnz_out = nnz;
+  if (nnz > cap || (nnz > 0 && !col_out)) {
+    set_error("col capacity too small");
+    return QBE_ERR_MEM_CAP;
+  }
+  int64_t o = 0;
+  for (int v = 0; v < g.n; ++v) {
+    rowptr_out[v] = (int32_t)o;
+    for (int w : g.neighbours(v)) col_out[o++] = w;
+  }
+  rowptr_out[g.n] = (int32_t)o;
+  return QBE_OK;
   QBE_GUARD_END
 }
 

@@ -1,0 +1,389 @@
+// Learned slicing proposal: a message-passing network over the variables of
+// a (reduced) graphical model, trained on the device.
+//
+// Architecture (fixed): input features F = 8 per variable, three layers of
+//   H_{l+1} = relu(H_l W_s + mean_{w in N(v)} H_l[w] W_n + b)      (width 64)
+// and a linear head s = H_3 w + c.  Weights are FP16 in the forward and
+// backward passes (FP32 master copies for the optimizer); every sum is
+// accumulated in FP32.  Training minimises the mean squared error between s
+// and a target at a set of candidate variables.  All reductions run in a
+// fixed order (no atomics): the same inputs give the same bits.
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "../../include/qbe.h"
+#include "qbe_internal.hpp"
+
+namespace qbe {
+
+#define GNN_HIP(call)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess) {                                                             \
+      set_error(std::string(#call) + ": " + hipGetErrorString(e_));                     \
+      return QBE_ERR_HIP;                                                               \
+    }                                                                                   \
+  } while (0)
+
+// ------------------------------------------------------------- parameters --
+// Flat parameter vector: for layer l = 0..2 (din = 8, 64, 64):
+//   W_s[din][64], W_n[din][64], b[64]; then head w[64], c.
+__host__ __device__ constexpr int gnn_din(int l) { return l == 0 ? kGnnFeatures : kGnnHidden; }
+__host__ __device__ constexpr int gnn_layer_size(int l) { return 2 * gnn_din(l) * kGnnHidden + kGnnHidden; }
+__host__ __device__ constexpr int gnn_layer_off(int l) {
+  return l == 0 ? 0 : gnn_layer_off(l - 1) + gnn_layer_size(l - 1);
+}
+constexpr int kGnnHeadOff = gnn_layer_off(kGnnLayers);
+constexpr int kGnnParams = kGnnHeadOff + kGnnHidden + 1;
+
+int gnn_num_params() { return kGnnParams; }
+static_assert(kGnnFeatures == kFeatures, "feature width");
+
+// ---------------------------------------------------------------- kernels --
+
+// M[v][d] = mean over neighbours w of H[w][d] (0 for an isolated vertex).
+__global__ void gnn_agg(const float* __restrict__ H, const int* __restrict__ rp, const int* __restrict__ col,
+                        int n, int D, float* __restrict__ M) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)n * D) return;
+  const int v = (int)(i / D), d = (int)(i % D);
+  const int b = rp[v], e = rp[v + 1];
+  float s = 0.f;
+  for (int j = b; j < e; ++j) s += H[(int64_t)col[j] * D + d];
+  M[i] = e > b ? s / (float)(e - b) : 0.f;
+}
+
+// dH[w][d] = dHs[w][d] + sum over neighbours v of dM[v][d] / deg(v)
+// (the transpose of gnn_agg on the symmetric adjacency).
+__global__ void gnn_agg_t(const float* __restrict__ dHs, const float* __restrict__ dM, const int* __restrict__ rp,
+                          const int* __restrict__ col, int n, int D, float* __restrict__ dH) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)n * D) return;
+  const int w = (int)(i / D), d = (int)(i % D);
+  float s = dHs[i];
+  for (int j = rp[w]; j < rp[w + 1]; ++j) {
+    const int v = col[j];
+    s += dM[(int64_t)v * D + d] / (float)(rp[v + 1] - rp[v]);
+  }
+  dH[i] = s;
+}
+
+// Z[v][o] = b[o] + sum_k Hin[v][k] Ws[k][o] + Min[v][k] Wn[k][o]; H = relu(Z).
+__global__ void gnn_dense(const float* __restrict__ Hin, const float* __restrict__ Min,
+                          const __half* __restrict__ w, int din, int n, float* __restrict__ Z,
+                          float* __restrict__ Hout) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)n * kGnnHidden) return;
+  const int v = (int)(i / kGnnHidden), o = (int)(i % kGnnHidden);
+  const __half* Ws = w;
+  const __half* Wn = w + din * kGnnHidden;
+  const __half* b = w + 2 * din * kGnnHidden;
+  float z = __half2float(b[o]);
+  const float* hv = Hin + (int64_t)v * din;
+  const float* mv = Min + (int64_t)v * din;
+  for (int k = 0; k < din; ++k)
+    z += hv[k] * __half2float(Ws[k * kGnnHidden + o]) + mv[k] * __half2float(Wn[k * kGnnHidden + o]);
+  Z[i] = z;
+  Hout[i] = z > 0.f ? z : 0.f;
+}
+
+__global__ void gnn_head(const float* __restrict__ H, const __half* __restrict__ w, int n, float* __restrict__ s) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  float a = __half2float(w[kGnnHidden]);
+  for (int o = 0; o < kGnnHidden; ++o) a += H[(int64_t)v * kGnnHidden + o] * __half2float(w[o]);
+  s[v] = a;
+}
+
+// dS = 0 except at the candidates: 2 (s - y) / n_c; loss = mean (s - y)^2.
+// One block, candidates in a fixed order.
+__global__ void gnn_loss(const float* __restrict__ s, const int* __restrict__ cand, const float* __restrict__ y,
+                         int nc, int n, float* __restrict__ dS, float* __restrict__ loss) {
+  __shared__ float part[256];
+  for (int v = threadIdx.x; v < n; v += blockDim.x) dS[v] = 0.f;
+  __syncthreads();
+  float acc = 0.f;
+  for (int i = threadIdx.x; i < nc; i += blockDim.x) {
+    const float d = s[cand[i]] - y[i];
+    dS[cand[i]] = 2.f * d / (float)nc;
+    acc += d * d;
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *loss = part[0] / (float)(nc > 0 ? nc : 1);
+}
+
+// Head backward: dH[v][o] = dS[v] w[o]; g_w[o] = sum_v dS[v] H[v][o]; g_c = sum_v dS[v].
+__global__ void gnn_head_back_x(const float* __restrict__ dS, const __half* __restrict__ w, int n,
+                                float* __restrict__ dH) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)n * kGnnHidden) return;
+  dH[i] = dS[i / kGnnHidden] * __half2float(w[i % kGnnHidden]);
+}
+
+__global__ void gnn_head_back_w(const float* __restrict__ dS, const float* __restrict__ H, int n,
+                                float* __restrict__ g) {
+  const int o = threadIdx.x;  // 0..64: 64 = the bias
+  if (o > kGnnHidden) return;
+  float a = 0.f;
+  for (int v = 0; v < n; ++v) a += dS[v] * (o < kGnnHidden ? H[(int64_t)v * kGnnHidden + o] : 1.f);
+  g[o] = a;
+}
+
+// dZ = dH * (Z > 0), in place into dH.
+__global__ void gnn_relu_back(float* __restrict__ dH, const float* __restrict__ Z, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && !(Z[i] > 0.f)) dH[i] = 0.f;
+}
+
+// g_Ws[k][o] = sum_v Hin[v][k] dZ[v][o]; g_Wn likewise with Min; g_b[o] = sum_v dZ[v][o].
+__global__ void gnn_dense_back_w(const float* __restrict__ Hin, const float* __restrict__ Min,
+                                 const float* __restrict__ dZ, int din, int n, float* __restrict__ g) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int total = 2 * din * kGnnHidden + kGnnHidden;
+  if (i >= total) return;
+  float a = 0.f;
+  if (i < 2 * din * kGnnHidden) {
+    const bool nb = i >= din * kGnnHidden;
+    const int j = nb ? i - din * kGnnHidden : i;
+    const int k = j / kGnnHidden, o = j % kGnnHidden;
+    const float* X = nb ? Min : Hin;
+    for (int v = 0; v < n; ++v) a += X[(int64_t)v * din + k] * dZ[(int64_t)v * kGnnHidden + o];
+  } else {
+    const int o = i - 2 * din * kGnnHidden;
+    for (int v = 0; v < n; ++v) a += dZ[(int64_t)v * kGnnHidden + o];
+  }
+  g[i] = a;
+}
+
+// dHs[v][k] = sum_o dZ[v][o] Ws[k][o];  dM[v][k] = sum_o dZ[v][o] Wn[k][o].
+__global__ void gnn_dense_back_x(const float* __restrict__ dZ, const __half* __restrict__ w, int din, int n,
+                                 float* __restrict__ dHs, float* __restrict__ dM) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)n * din) return;
+  const int v = (int)(i / din), k = (int)(i % din);
+  const __half* Ws = w;
+  const __half* Wn = w + din * kGnnHidden;
+  float a = 0.f, c = 0.f;
+  const float* dz = dZ + (int64_t)v * kGnnHidden;
+  for (int o = 0; o < kGnnHidden; ++o) {
+    a += dz[o] * __half2float(Ws[k * kGnnHidden + o]);
+    c += dz[o] * __half2float(Wn[k * kGnnHidden + o]);
+  }
+  dHs[i] = a;
+  dM[i] = c;
+}
+
+// Adam on the FP32 master weights, refreshing the FP16 copy.
+__global__ void gnn_adam(float* __restrict__ p, __half* __restrict__ p16, const float* __restrict__ g,
+                         float* __restrict__ m, float* __restrict__ v, int n, float lr, float b1, float b2,
+                         float eps, float c1, float c2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  p[i] = pi;
+  p16[i] = __float2half(pi);
+}
+
+__global__ void gnn_to_half(const float* __restrict__ p, __half* __restrict__ p16, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p16[i] = __float2half(p[i]);
+}
+
+// ------------------------------------------------------------------- host --
+
+static unsigned blocks(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+int gnn_alloc(Gnn& g, int device) {
+  g.device = device;
+  GNN_HIP(hipMalloc(&g.d_p, kGnnParams * 4));
+  GNN_HIP(hipMalloc(&g.d_p16, kGnnParams * 2));
+  GNN_HIP(hipMalloc(&g.d_g, kGnnParams * 4));
+  GNN_HIP(hipMalloc(&g.d_m, kGnnParams * 4));
+  GNN_HIP(hipMalloc(&g.d_v, kGnnParams * 4));
+  GNN_HIP(hipMemset(g.d_m, 0, kGnnParams * 4));
+  GNN_HIP(hipMemset(g.d_v, 0, kGnnParams * 4));
+  g.step = 0;
+  return QBE_OK;
+}
+
+void gnn_free(Gnn& g) {
+  void** ptrs[] = {&g.d_p, &g.d_p16, &g.d_g, &g.d_m, &g.d_v, &g.d_ws};
+  for (void** q : ptrs) {
+    if (*q) (void)hipFree(*q);
+    *q = nullptr;
+  }
+  g.ws_bytes = 0;
+}
+
+int gnn_set_params(Gnn& g, const float* host, bool reset_optimizer) {
+  GNN_HIP(hipMemcpy(g.d_p, host, kGnnParams * 4, hipMemcpyHostToDevice));
+  gnn_to_half<<<blocks(kGnnParams), 256>>>((const float*)g.d_p, (__half*)g.d_p16, kGnnParams);
+  GNN_HIP(hipGetLastError());
+  if (reset_optimizer) {
+    GNN_HIP(hipMemset(g.d_m, 0, kGnnParams * 4));
+    GNN_HIP(hipMemset(g.d_v, 0, kGnnParams * 4));
+    g.step = 0;
+  }
+  GNN_HIP(hipDeviceSynchronize());
+  return QBE_OK;
+}
+
+int gnn_get_params(const Gnn& g, float* host) {
+  GNN_HIP(hipMemcpy(host, g.d_p, kGnnParams * 4, hipMemcpyDeviceToHost));
+  return QBE_OK;
+}
+
+// Device workspace for a graph of n vertices and nnz adjacency entries, the
+// candidates, and every activation the backward pass needs.
+struct GnnBufs {
+  int *rp, *col, *cand;
+  float *X, *y, *s, *dS, *loss;
+  float* H[kGnnLayers + 1];
+  float* M[kGnnLayers];
+  float* Z[kGnnLayers];
+  float *dA, *dB, *dC;  // backward scratch (n x 64 each)
+};
+
+static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+static int gnn_layout(Gnn& g, int n, int64_t nnz, int nc, GnnBufs& b) {
+  const size_t sizes[] = {
+      (size_t)(n + 1) * 4, (size_t)nnz * 4, (size_t)nc * 4,                 // rp, col, cand
+      (size_t)n * kGnnFeatures * 4, (size_t)nc * 4, (size_t)n * 4, (size_t)n * 4, 256,  // X, y, s, dS, loss
+  };
+  size_t need = 0;
+  for (size_t z : sizes) need += align256(z);
+  need += kGnnLayers * align256((size_t)n * kGnnHidden * 4);        // H[1..L]
+  need += kGnnLayers * align256((size_t)n * kGnnHidden * 4) * 2;    // M, Z (M[0] sized for 64 too)
+  need += 3 * align256((size_t)n * kGnnHidden * 4);                  // dA, dB, dC
+  if (need > g.ws_bytes) {
+    if (g.d_ws) (void)hipFree(g.d_ws);
+    g.d_ws = nullptr;
+    g.ws_bytes = 0;
+    GNN_HIP(hipMalloc(&g.d_ws, need));
+    g.ws_bytes = need;
+  }
+  char* w = (char*)g.d_ws;
+  auto take = [&](size_t bytes) {
+    char* p = w;
+    w += align256(bytes);
+    return p;
+  };
+  b.rp = (int*)take(sizes[0]);
+  b.col = (int*)take(sizes[1]);
+  b.cand = (int*)take(sizes[2]);
+  b.X = (float*)take(sizes[3]);
+  b.y = (float*)take(sizes[4]);
+  b.s = (float*)take(sizes[5]);
+  b.dS = (float*)take(sizes[6]);
+  b.loss = (float*)take(sizes[7]);
+  b.H[0] = b.X;
+  for (int l = 1; l <= kGnnLayers; ++l) b.H[l] = (float*)take((size_t)n * kGnnHidden * 4);
+  for (int l = 0; l < kGnnLayers; ++l) {
+    b.M[l] = (float*)take((size_t)n * kGnnHidden * 4);
+    b.Z[l] = (float*)take((size_t)n * kGnnHidden * 4);
+  }
+  b.dA = (float*)take((size_t)n * kGnnHidden * 4);
+  b.dB = (float*)take((size_t)n * kGnnHidden * 4);
+  b.dC = (float*)take((size_t)n * kGnnHidden * 4);
+  return QBE_OK;
+}
+
+static int gnn_forward(const Gnn& g, const GnnBufs& b, int n, hipStream_t st) {
+  const __half* w16 = (const __half*)g.d_p16;
+  for (int l = 0; l < kGnnLayers; ++l) {
+    const int din = gnn_din(l);
+    gnn_agg<<<blocks((int64_t)n * din), 256, 0, st>>>(b.H[l], b.rp, b.col, n, din, b.M[l]);
+    gnn_dense<<<blocks((int64_t)n * kGnnHidden), 256, 0, st>>>(b.H[l], b.M[l], w16 + gnn_layer_off(l), din, n,
+                                                                b.Z[l], b.H[l + 1]);
+  }
+  gnn_head<<<blocks(n), 256, 0, st>>>(b.H[kGnnLayers], w16 + kGnnHeadOff, n, b.s);
+  GNN_HIP(hipGetLastError());
+  return QBE_OK;
+}
+
+static int upload_graph(Gnn& g, GnnBufs& b, int n, const int* rp, const int* col, const float* feats, int nc,
+                        const int* cand, const float* y, hipStream_t st) {
+  const int64_t nnz = rp[n];
+  int rc = gnn_layout(g, n, nnz, nc, b);
+  if (rc) return rc;
+  GNN_HIP(hipMemcpyAsync(b.rp, rp, (size_t)(n + 1) * 4, hipMemcpyHostToDevice, st));
+  if (nnz) GNN_HIP(hipMemcpyAsync(b.col, col, (size_t)nnz * 4, hipMemcpyHostToDevice, st));
+  GNN_HIP(hipMemcpyAsync(b.X, feats, (size_t)n * kGnnFeatures * 4, hipMemcpyHostToDevice, st));
+  if (nc) {
+    GNN_HIP(hipMemcpyAsync(b.cand, cand, (size_t)nc * 4, hipMemcpyHostToDevice, st));
+    GNN_HIP(hipMemcpyAsync(b.y, y, (size_t)nc * 4, hipMemcpyHostToDevice, st));
+  }
+  return QBE_OK;
+}
+
+int gnn_score(Gnn& g, void* stream, int n, const int* rp, const int* col, const float* feats, float* scores) {
+  hipStream_t st = (hipStream_t)stream;
+  GnnBufs b{};
+  int rc = upload_graph(g, b, n, rp, col, feats, 0, nullptr, nullptr, st);
+  if (rc) return rc;
+  if ((rc = gnn_forward(g, b, n, st))) return rc;
+  GNN_HIP(hipMemcpyAsync(scores, b.s, (size_t)n * 4, hipMemcpyDeviceToHost, st));
+  GNN_HIP(hipStreamSynchronize(st));
+  return QBE_OK;
+}
+
+int gnn_train_step(Gnn& g, void* stream, int n, const int* rp, const int* col, const float* feats, int nc,
+                   const int* cand, const float* y, float lr, float* loss_out, float* grads_out) {
+  hipStream_t st = (hipStream_t)stream;
+  GnnBufs b{};
+  int rc = upload_graph(g, b, n, rp, col, feats, nc, cand, y, st);
+  if (rc) return rc;
+  if ((rc = gnn_forward(g, b, n, st))) return rc;
+  const __half* w16 = (const __half*)g.d_p16;
+  float* grad = (float*)g.d_g;
+  gnn_loss<<<1, 256, 0, st>>>(b.s, b.cand, b.y, nc, n, b.dS, b.loss);
+  // head
+  gnn_head_back_w<<<1, kGnnHidden + 1, 0, st>>>(b.dS, b.H[kGnnLayers], n, grad + kGnnHeadOff);
+  gnn_head_back_x<<<blocks((int64_t)n * kGnnHidden), 256, 0, st>>>(b.dS, w16 + kGnnHeadOff, n, b.dA);
+  // layers, last to first; dA holds dH_{l+1}
+  float* dH = b.dA;
+  float* dHs = b.dB;
+  float* dM = b.dC;
+  for (int l = kGnnLayers - 1; l >= 0; --l) {
+    const int din = gnn_din(l);
+    gnn_relu_back<<<blocks((int64_t)n * kGnnHidden), 256, 0, st>>>(dH, b.Z[l], (int64_t)n * kGnnHidden);
+    gnn_dense_back_w<<<blocks(2 * din * kGnnHidden + kGnnHidden), 256, 0, st>>>(b.H[l], b.M[l], dH, din, n,
+                                                                                 grad + gnn_layer_off(l));
+    if (l > 0) {
+      gnn_dense_back_x<<<blocks((int64_t)n * din), 256, 0, st>>>(dH, w16 + gnn_layer_off(l), din, n, dHs, dM);
+      // dH_l = dHs + agg^T(dM), written over the dZ buffer (no longer needed)
+      gnn_agg_t<<<blocks((int64_t)n * din), 256, 0, st>>>(dHs, dM, b.rp, b.col, n, din, dH);
+    }
+  }
+  GNN_HIP(hipGetLastError());
+  if (lr > 0.f) {
+    g.step += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.f - powf(b1, (float)g.step), c2 = 1.f - powf(b2, (float)g.step);
+    gnn_adam<<<blocks(kGnnParams), 256, 0, st>>>((float*)g.d_p, (__half*)g.d_p16, grad, (float*)g.d_m,
+                                                 (float*)g.d_v, kGnnParams, lr, b1, b2, 1e-8f, c1, c2);
+    GNN_HIP(hipGetLastError());
+  }
+  if (loss_out) GNN_HIP(hipMemcpyAsync(loss_out, b.loss, 4, hipMemcpyDeviceToHost, st));
+  if (grads_out) GNN_HIP(hipMemcpyAsync(grads_out, grad, kGnnParams * 4, hipMemcpyDeviceToHost, st));
+  GNN_HIP(hipStreamSynchronize(st));
+  return QBE_OK;
+}
+
+}  // namespace qbe

@@ -468,4 +468,41 @@ ScheduleCost schedule_cost(const Schedule& s) {
   return c;
 }
 
+std::vector<float> vertex_features(const Graph& g, const std::vector<int>& order) {
+  const int n = g.n;
+  std::vector<float> f((size_t)n * kFeatures, 0.f);
+  if (order.empty()) return f;
+  auto nplus = eliminate(g, order);
+  CliqueTree ct = clique_tree(g, order);
+  size_t smax = 0;
+  for (const auto& b : ct.bags) smax = std::max(smax, b.size());
+  std::vector<int> len(n, 0), wt(n, 0);
+  std::vector<uint8_t> in_max(n, 0);
+  int lmax = 1, wmax = 1;
+  for (const auto& b : ct.bags)
+    for (int v : b) {
+      len[v] += 1;
+      wt[v] += (int)b.size();
+      if (b.size() == smax) in_max[v] = 1;
+      lmax = std::max(lmax, len[v]);
+      wmax = std::max(wmax, wt[v]);
+    }
+  int tau = 1;
+  for (const auto& nb : nplus) tau = std::max(tau, (int)nb.size());
+  const float nn = (float)order.size();
+  for (size_t i = 0; i < order.size(); ++i) {
+    const int u = order[i];
+    float* r = f.data() + (size_t)u * kFeatures;
+    r[0] = (float)g.degree(u) / 8.f;
+    r[1] = (float)i / nn;
+    r[2] = (float)nplus[i].size() / (float)tau;
+    r[3] = in_max[u] ? 1.f : 0.f;
+    r[4] = (float)len[u] / (float)lmax;
+    r[5] = (float)wt[u] / (float)wmax;
+    r[6] = (float)smax / 32.f;
+    r[7] = 1.f;
+  }
+  return f;
+}
+
 }  // namespace qbe

@@ -107,4 +107,12 @@ struct ScheduleCost {
 };
 ScheduleCost schedule_cost(const Schedule& s);
 
+// Per-vertex features of a reduced graph and its order, for the learned
+// slicing proposal: degree, relative position in the order, |N+(u)| relative
+// to the width, membership of the maximum bags, number of clique-tree bags
+// holding u and their total size (both relative to the maxima), and a
+// constant.  Rows for vertices outside the order are zero.
+constexpr int kFeatures = 8;
+std::vector<float> vertex_features(const Graph& g, const std::vector<int>& order);
+
 }  // namespace qbe

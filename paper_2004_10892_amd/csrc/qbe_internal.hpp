@@ -151,6 +151,33 @@ struct Batch {
   bool prog_in_lds = true;   // every fused plan's records fit in LDS with its data
 };
 
+// -------------------------------------------------- learned proposal (GNN) --
+
+constexpr int kGnnFeatures = 8;   // must equal kFeatures of the planner
+constexpr int kGnnHidden = 64;
+constexpr int kGnnLayers = 3;
+
+struct Gnn {
+  int device = -1;
+  int step = 0;                // optimizer steps taken
+  void* d_p = nullptr;         // FP32 master parameters
+  void* d_p16 = nullptr;       // FP16 copy used by the passes
+  void* d_g = nullptr;         // gradients
+  void* d_m = nullptr;         // Adam moments
+  void* d_v = nullptr;
+  void* d_ws = nullptr;        // graph + activations
+  size_t ws_bytes = 0;
+};
+
+int gnn_num_params();
+int gnn_alloc(Gnn& g, int device);
+void gnn_free(Gnn& g);
+int gnn_set_params(Gnn& g, const float* host, bool reset_optimizer);
+int gnn_get_params(const Gnn& g, float* host);
+int gnn_score(Gnn& g, void* stream, int n, const int* rp, const int* col, const float* feats, float* scores);
+int gnn_train_step(Gnn& g, void* stream, int n, const int* rp, const int* col, const float* feats, int nc,
+                   const int* cand, const float* y, float lr, float* loss_out, float* grads_out);
+
 // Plan compilation (program.cpp).
 void compile_plan(Plan& p);
 
