@@ -175,6 +175,51 @@ def bench_batch(torch, qbe, ctx, steps):
                          "circuits are compared on the scale of a typical amplitude"}
 
 
+def bench_learned(torch, qbe, ctx, labels=20000, epochs=20, hbm_gbs=None):
+    """Learned proposal at the 6x6..8x8 / depth 16..32 scale: ~20k exact-cost
+    labels, device training, evaluation on 10 held-out 8x8 depth-32 circuits
+    against tree-trimming under a 4 GiB per-slice memory cap."""
+    import numpy as np
+    from circuitgen import SplitMix64, circuit_model, random_grid_circuit
+    from paper_2004_10892_amd import learned as L
+    rng = SplitMix64(2020)
+    t0 = time.perf_counter()
+    samples, n_labels, i = [], 0, 0
+    while n_labels < labels and i < 400:
+        r, c, d = 6 + rng.next() % 3, 6 + rng.next() % 3, 16 + rng.next() % 17
+        qm = qbe.Model.from_circuitgen(circuit_model(random_grid_circuit(r, c, d, 2000 + i)))
+        ss, n = L.make_dataset([qm], seed=i)
+        samples += ss
+        n_labels += n
+        i += 1
+    t1 = time.perf_counter()
+    net = qbe.Gnn(ctx, seed=7)
+    hist = L.train(net, samples, epochs=epochs, batch=8, lr=2e-3)
+    t2 = time.perf_counter()
+    rows, gains, best = [], [], []
+    for k in range(10):
+        qm = qbe.Model.from_circuitgen(circuit_model(random_grid_circuit(8, 8, 32, 5000 + k)))
+        res = L.compare(qm, net, mem_cap=L.MEM_CAP)
+        rows.append(res)
+        gains.append(res["log2_gain"])
+        best.append(res["log2_gain_best_of_both"])
+    t3 = time.perf_counter()
+    out = {"workload": "learned_6x6-8x8_d16-32_eval_8x8_d32", "labels": n_labels, "train_circuits": i,
+           "label_s": t1 - t0, "train_s": t2 - t1, "eval_s": t3 - t2, "loss_first_epoch": hist[0],
+           "loss_last_epoch": hist[-1], "mem_cap_bytes": L.MEM_CAP,
+           "mean_log2_gain": float(np.mean(gains)), "mean_log2_gain_best_of_both": float(np.mean(best)),
+           "learned_chosen": sum(r["chosen"] == "learned" for r in rows),
+           "per_circuit": [{"heuristic_m": r["heuristic"]["m"], "learned_m": r["learned"]["m"],
+                            "heuristic_log2_flops": round(r["heuristic"]["log2_total_flops"], 3),
+                            "learned_log2_flops": round(r["learned"]["log2_total_flops"], 3),
+                            "chosen": r["chosen"], "heuristic_plan_ms": round(r["heuristic"]["plan_ms"], 1),
+                            "learned_plan_ms": round(r["learned"]["plan_ms"], 1)} for r in rows]}
+    if hbm_gbs:
+        out["note_time"] = (f"contraction time of these plans is projected from the cost model's bytes at the "
+                            f"measured per-step rate of {hbm_gbs:.0f} GB/s (too long to run here)")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -182,7 +227,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-extra", action="store_true", help="skip the 7x7 and batch lines")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--only", choices=["hbm", "batch"], help="run just one extra workload (profiling)")
+    ap.add_argument("--only", choices=["hbm", "batch", "learned"], help="run just one extra workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: the contraction runs on a single MI355X "
@@ -203,6 +248,9 @@ def main():
         return
     if args.only == "batch":
         print(json.dumps(bench_batch(torch, qbe, ctx, args.steps)), flush=True)
+        return
+    if args.only == "learned":
+        print(json.dumps(bench_learned(torch, qbe, ctx)), flush=True)
         return
 
     # chosen form: fused persistent launch under a HIP graph
@@ -258,6 +306,9 @@ def main():
         line["hbm_workload_bf16x3"] = bench_hbm(torch, qbe, ctx, 5, "bf16x3")
         log("[bench] batch of 512 ...")
         line["batch_workload"] = bench_batch(torch, qbe, ctx, 20)
+        log("[bench] learned proposal ...")
+        line["learned_proposal"] = bench_learned(torch, qbe, ctx,
+                                                 hbm_gbs=line["hbm_workload"]["roofline"]["achieved"])
     print(json.dumps(line), flush=True)
     if err > 1e-5 or err_p > 1e-5:
         sys.exit(1)
