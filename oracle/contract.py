@@ -1,7 +1,7 @@
 """Contraction reference: brute force, the bucket schedule and sliced bucket
 elimination in complex128 -- TEST INFRASTRUCTURE (see package header).
 
-Conventions (readings of the paper, also listed in the design notes):
+Conventions (readings of the paper):
 
 * A tensor over variables (v_0, ..., v_{r-1}) is stored row-major with v_0
   the most significant index; every variable takes the values 0 and 1

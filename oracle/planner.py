@@ -1,8 +1,7 @@
 """Planner reference: graphs, elimination orders, tree decompositions and the
 greedy mu-treewidth deletion -- TEST INFRASTRUCTURE (see package header).
 
-Readings of points the paper leaves open (each one is also listed in the
-design notes):
+Readings of points the paper leaves open:
 
 * Graphs are simple (Sec. 2.2, footnote): a tensor is a clique over its
   variables; self-loops are dropped and parallel edges merged.
@@ -25,7 +24,7 @@ design notes):
   (instead of a random pick).  After each removal the tree is rebuilt from
   the reduced graph and the reduced order.
 * Alg. 2 (Sec. 3): the score is per vertex; the optional recomputation of
-  the order (its line 10) is not performed, so the reduced order is the
+  the order that Alg. 2 allows after each removal is not performed, so the reduced order is the
   original order with mu removed.  It stops after m removals or, when m is
   negative, as soon as the width of the reduced order is at most a target.
 * Alg. 3 (Sec. 3.1): the reduced graph is G minus u (the listing writes
