@@ -146,7 +146,7 @@ def test_min_fill_degree_tie_break():
 
 def test_alg1_star_center_first_drops_by_more_than_one():
     # Sec. 3.1's bound of one per removal holds for optimal treewidth; with a
-    # fixed order the width can drop by more (reading 5 in the design notes).
+    # fixed order the width can drop by more.
     adj = {0: {1, 2, 3, 4}, 1: {0}, 2: {0}, 3: {0}, 4: {0}}
     assert P.treewidth_from_order(adj, [0, 1, 2, 3, 4]) == 4
     assert P.treewidth_from_order(P.remove_vertex(adj, 0), [1, 2, 3, 4]) == 0
