@@ -374,11 +374,18 @@ struct FusedArgs {
   int32_t reduce_here;                // 1: the last workgroup of a plan sums its items
 };
 
-// Loads the first 8 words of a record.
-__device__ __forceinline__ void load_record(const uint32_t* rec, uint32_t S, uint4& r0, uint4& r1) {
+// Threads of a fused workgroup.
+constexpr int kFusedBlock = kBlock;
+// Record rows (16-byte groups of words) held in registers: records of up to
+// 11 operands are read with their level's prefetch, longer ones in a loop.
+constexpr int kRecRows = 3;
+
+// Reads all kRecRows rows at rec (the program ends with enough zero words
+// that this stays inside it for every record).
+__device__ __forceinline__ void load_rows(const uint32_t* rec, uint4 (&r)[kRecRows]) {
   const uint4* q = reinterpret_cast<const uint4*>(rec);
-  r0 = q[0];
-  if (S > 4) r1 = q[1];
+#pragma unroll
+  for (int i = 0; i < kRecRows; ++i) r[i] = q[i];
 }
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
@@ -395,30 +402,112 @@ __device__ __forceinline__ T* uniform_ptr(T* p) {
 
 __device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Product over the operands of one record, for u = 0 (a0) and u = 1 (a1),
-// multiplied as a balanced tree to keep the dependent chain short.
-__device__ __forceinline__ void record_product(const float2* data, const uint4& c0, const uint4& c1, uint32_t S,
-                                               const uint32_t* rec, float2& a0, float2& a1) {
-  const float2 x1 = data[c0.y & 0xFFFFu], y1 = data[c0.y >> 16];
-  const float2 x2 = data[c0.z & 0xFFFFu], y2 = data[c0.z >> 16];
-  const float2 x3 = data[c0.w & 0xFFFFu], y3 = data[c0.w >> 16];
-  a0 = cmul(x1, cmul(x2, x3));
-  a1 = cmul(y1, cmul(y2, y3));
-  if (S > 4) {
-    const float2 x4 = data[c1.x & 0xFFFFu], y4 = data[c1.x >> 16];
-    const float2 x5 = data[c1.y & 0xFFFFu], y5 = data[c1.y >> 16];
-    const float2 x6 = data[c1.z & 0xFFFFu], y6 = data[c1.z >> 16];
-    const float2 x7 = data[c1.w & 0xFFFFu], y7 = data[c1.w >> 16];
-    a0 = cmul(a0, cmul(cmul(x4, x5), cmul(x6, x7)));
-    a1 = cmul(a1, cmul(cmul(y4, y5), cmul(y6, y7)));
-    if (S > 8) {
-      const uint4* q = reinterpret_cast<const uint4*>(rec);
-      for (uint32_t c = 2; c < S / 4; ++c) {
-        const uint4 w = q[c];
-        a0 = cmul(a0, cmul(cmul(data[w.x & 0xFFFFu], data[w.y & 0xFFFFu]),
-                           cmul(data[w.z & 0xFFFFu], data[w.w & 0xFFFFu])));
-        a1 = cmul(a1, cmul(cmul(data[w.x >> 16], data[w.y >> 16]), cmul(data[w.z >> 16], data[w.w >> 16])));
-      }
+// Operand entries of a record of K operands for u = 0 (x) and u = 1 (y): all
+// 2K LDS reads are issued before any is used.
+template <int K>
+__device__ __forceinline__ void gather(const float2* data, const uint4 (&r)[kRecRows], float2 (&x)[K],
+                                       float2 (&y)[K]) {
+  const uint32_t w[4 * kRecRows] = {r[0].x, r[0].y, r[0].z, r[0].w, r[1].x, r[1].y,
+                                    r[1].z, r[1].w, r[2].x, r[2].y, r[2].z, r[2].w};
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    x[i] = data[w[1 + i] & 0xFFFFu];
+    y[i] = data[w[1 + i] >> 16];
+  }
+}
+
+// Product of N complex values as a balanced tree (short dependent chain).
+template <int N>
+__device__ __forceinline__ float2 tree_prod(float2 (&v)[N]) {
+#pragma unroll
+  for (int s = 1; s < N; s <<= 1)
+#pragma unroll
+    for (int i = 0; i + s < N; i += 2 * s) v[i] = cmul(v[i], v[i + s]);
+  return v[0];
+}
+
+// One level whose records have K operands: this thread's first record is
+// in c (read during the previous level) and the next level's is read into p
+// in the same LDS round trip as the operands.  Records beyond the first pass
+// are read here.
+template <int K>
+__device__ __forceinline__ void run_level(float2* data, const uint32_t* rprog, uint32_t base, uint32_t E,
+                                          uint32_t S, const uint4 (&c)[kRecRows], uint4 (&p)[kRecRows],
+                                          uint32_t nb, uint32_t nE, uint32_t nS, uint32_t tid) {
+  // the next level's record first (unconditional: a lane past that level's
+  // end reads its last record), then this record's operands; LDS answers in
+  // order, so one wait covers both
+  load_rows(rprog + nb + (size_t)min(tid, nE > 0 ? nE - 1 : 0u) * nS, p);
+  float2 x[K], y[K];
+  if (tid < E) {
+    gather<K>(data, c, x, y);
+    data[c[0].x] = cadd(tree_prod<K>(x), tree_prod<K>(y));
+  }
+  for (uint32_t f = tid + kFusedBlock; f < E; f += kFusedBlock) {
+    uint4 d[kRecRows];
+    load_rows(rprog + base + (size_t)f * S, d);
+    gather<K>(data, d, x, y);
+    data[d[0].x] = cadd(tree_prod<K>(x), tree_prod<K>(y));
+  }
+}
+
+// A level whose records have more operands than the registers hold: the
+// words are read row by row from the record.
+__device__ __forceinline__ void run_level_long(float2* data, const uint32_t* rprog, uint32_t base, uint32_t E,
+                                               uint32_t S, uint4 (&p)[kRecRows], uint32_t nb, uint32_t nE,
+                                               uint32_t nS, uint32_t tid) {
+  load_rows(rprog + nb + (size_t)min(tid, nE > 0 ? nE - 1 : 0u) * nS, p);
+  for (uint32_t f = tid; f < E; f += kFusedBlock) {
+    const uint4* q = reinterpret_cast<const uint4*>(rprog + base + (size_t)f * S);
+    const uint4 h = q[0];
+    float2 a0 = make_float2(1.f, 0.f), a1 = a0;
+    const uint32_t w0[3] = {h.y, h.z, h.w};
+    for (int i = 0; i < 3; ++i) {
+      a0 = cmul(a0, data[w0[i] & 0xFFFFu]);
+      a1 = cmul(a1, data[w0[i] >> 16]);
+    }
+    for (uint32_t g = 1; g < S / 4; ++g) {
+      const uint4 w = q[g];
+      a0 = cmul(a0, cmul(cmul(data[w.x & 0xFFFFu], data[w.y & 0xFFFFu]),
+                         cmul(data[w.z & 0xFFFFu], data[w.w & 0xFFFFu])));
+      a1 = cmul(a1, cmul(cmul(data[w.x >> 16], data[w.y >> 16]), cmul(data[w.z >> 16], data[w.w >> 16])));
+    }
+    data[h.x] = cadd(a0, a1);
+  }
+}
+
+// Level dispatch on the operand count (uniform per level).
+__device__ __forceinline__ void level_step(float2* data, const uint32_t* rprog, const uint4& t, const uint4& tn,
+                                           const uint4 (&c)[kRecRows], uint4 (&p)[kRecRows], uint32_t tid) {
+  const uint32_t base = uni(t.x), E = uni(t.y), S = uni(t.z), K = uni(t.w);
+  const uint32_t nb = uni(tn.x), nE = uni(tn.y), nS = uni(tn.z);
+  switch (K) {
+#define QBE_LEVEL(KK) \
+  case KK: run_level<KK>(data, rprog, base, E, S, c, p, nb, nE, nS, tid); break;
+    QBE_LEVEL(1) QBE_LEVEL(2) QBE_LEVEL(3) QBE_LEVEL(4) QBE_LEVEL(5) QBE_LEVEL(6)
+    QBE_LEVEL(7) QBE_LEVEL(8) QBE_LEVEL(9) QBE_LEVEL(10) QBE_LEVEL(11)
+#undef QBE_LEVEL
+    default: run_level_long(data, rprog, base, E, S, p, nb, nE, nS, tid); break;
+  }
+}
+
+// Copy of n elements into LDS by a whole workgroup with U loads in flight per
+// thread before the first store (T a native scalar or vector type, so that
+// the staging array stays in registers).
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+template <int U, class T>
+__device__ __forceinline__ void copy_in(T* dst, const T* src, uint32_t n, uint32_t tid) {
+  for (uint32_t i0 = 0; i0 < n; i0 += U * kFusedBlock) {
+    T v[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const uint32_t i = i0 + j * kFusedBlock + tid;
+      v[j] = i < n ? src[i] : T{};
+    }
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const uint32_t i = i0 + j * kFusedBlock + tid;
+      if (i < n) dst[i] = v[j];
     }
   }
 }
@@ -432,7 +521,7 @@ __device__ __forceinline__ void record_product(const float2* data, const uint4& 
 // Work distribution: in one-plan mode workgroup b takes items b, b + grid,
 // ...; in batch mode items are pulled from a counter (uneven sizes).
 template <bool kProgLds>
-__global__ __launch_bounds__(kBlock) void fused_kernel(FusedArgs a) {
+__global__ __launch_bounds__(kFusedBlock) void fused_kernel(FusedArgs a) {
   extern __shared__ uint4 lds4[];
   __shared__ int64_t s_item;
   __shared__ uint32_t s_flag, s_plan;
@@ -473,8 +562,7 @@ __global__ __launch_bounds__(kBlock) void fused_kernel(FusedArgs a) {
     float2* data = reinterpret_cast<float2*>(lds4);
     if (kProgLds) {
       if (plan != __builtin_amdgcn_readfirstlane(s_plan)) {
-        const uint4* src = reinterpret_cast<const uint4*>(gprog);
-        for (uint32_t i = tid; i < words / 4; i += kBlock) lds4[i] = src[i];
+        copy_in<8>(reinterpret_cast<u32x4*>(lds4), reinterpret_cast<const u32x4*>(gprog), words / 4, tid);
       }
       rprog = reinterpret_cast<const uint32_t*>(lds4);
       data = reinterpret_cast<float2*>(lds4 + words / 4);
@@ -483,38 +571,29 @@ __global__ __launch_bounds__(kBlock) void fused_kernel(FusedArgs a) {
     const uint32_t inv = gprog[FH_INV_ELEMS], dep = gprog[FH_DEP_ELEMS];
     const float2* dsrc = prep + gprog[FH_DEP_SRC] + slice * (int64_t)dep;
     if (tid == 0) data[0] = make_float2(1.f, 0.f);
-    for (uint32_t i = tid; i < inv; i += kBlock) data[1 + i] = prep[i];
-    for (uint32_t i = tid; i < dep; i += kBlock) data[1 + inv + i] = dsrc[i];
+    copy_in<8>(reinterpret_cast<uint64_t*>(data + 1), reinterpret_cast<const uint64_t*>(prep), inv, tid);
+    copy_in<8>(reinterpret_cast<uint64_t*>(data + 1 + inv), reinterpret_cast<const uint64_t*>(dsrc), dep, tid);
     __syncthreads();
     if (kProgLds && tid == 0) s_plan = plan;  // read again only after the next barrier
     const uint32_t n_levels = gprog[FH_LEVELS];
-    // level table (LDS copy when the program is there), read two levels
-    // ahead of use so that neither it nor the record prefetch waits
+    // level table (LDS copy when the program is there; two zero entries
+    // after the last level): entries l and l + 1 are in registers while
+    // level l runs, and entry l + 2 is read during it
     const uint4* lv = reinterpret_cast<const uint4*>(rprog + kHdr);
-    uint4 p0 = make_uint4(0, 0, 0, 0), p1 = make_uint4(0, 0, 0, 0);
-    uint4 t1 = make_uint4(0, 0, 0, 0), t2 = make_uint4(0, 0, 0, 0);
-    uint4 t0 = n_levels > 0 ? lv[0] : make_uint4(0, 0, 0, 0);
-    if (n_levels > 1) t1 = lv[1];
-    if (n_levels > 0 && (uint32_t)tid < uni(t0.y))
-      load_record(rprog + uni(t0.x) + (size_t)tid * uni(t0.z), uni(t0.z), p0, p1);
-    for (uint32_t l = 0; l < n_levels; ++l) {
-      const uint32_t base = uni(t0.x), E = uni(t0.y), S = uni(t0.z);
-      uint4 c0 = p0, c1 = p1;
-      if (l + 1 < n_levels) {
-        const uint32_t nb = uni(t1.x), nE = uni(t1.y), nS = uni(t1.z);
-        if ((uint32_t)tid < nE) load_record(rprog + nb + (size_t)tid * nS, nS, p0, p1);
-        if (l + 2 < n_levels) t2 = lv[l + 2];
-      }
-      for (uint32_t f = tid; f < E; f += kBlock) {
-        const uint32_t* rec = rprog + base + (size_t)f * S;
-        if (f != (uint32_t)tid) load_record(rec, S, c0, c1);
-        float2 a0, a1;
-        record_product(data, c0, c1, S, rec, a0, a1);
-        data[c0.x & 0xFFFFu] = (c0.x >> 16) & kRecNoSum ? a0 : cadd(a0, a1);
-      }
-      t0 = t1;
-      t1 = t2;
+    uint4 ca[kRecRows] = {}, cb[kRecRows] = {};
+    uint4 t0 = lv[0], t1 = lv[1];
+    if ((uint32_t)tid < uni(t0.y)) load_rows(rprog + uni(t0.x) + (size_t)tid * uni(t0.z), ca);
+    for (uint32_t l = 0; l < n_levels; l += 2) {
+      // two levels per trip: the record registers swap roles without copies
+      const uint4 t2 = lv[l + 2];
+      level_step(data, rprog, t0, t1, ca, cb, tid);
       __syncthreads();
+      if (l + 1 >= n_levels) break;
+      const uint4 t3 = lv[l + 3];
+      level_step(data, rprog, t1, t2, cb, ca, tid);
+      __syncthreads();
+      t0 = t2;
+      t1 = t3;
     }
     if (tid < 64) {
       // product of the slice's scalar factors: lane j holds factor j (and
@@ -556,17 +635,17 @@ __global__ __launch_bounds__(kBlock) void fused_kernel(FusedArgs a) {
     if (s_flag) {
       // last item of this plan: fixed-order FP64 sum of its items (same order
       // as reduce_kernel), then re-arm the plan's counter for the next launch.
-      // The scratch overwrites LDS; no item of this plan remains.
-      __threadfence();
+      // The scratch overwrites LDS; no item of this plan remains.  The values
+      // are visible: thread 0's acquire on the counter, then the barrier.
       int64_t b = 0, e = a.n_items;
       if (a.ranges) {
         b = a.ranges[2 * plan];
         e = a.ranges[2 * plan + 1];
       }
       double* sre = reinterpret_cast<double*>(lds4);
-      double* sim = sre + kBlock / 64;
+      double* sim = sre + kFusedBlock / 64;
       double re = 0.0, im = 0.0;
-      for (int64_t i = b + tid; i < e; i += kBlock) {
+      for (int64_t i = b + tid; i < e; i += kFusedBlock) {
         const double2 v = a.out[i];
         re += v.x;
         im += v.y;
@@ -581,7 +660,7 @@ __global__ __launch_bounds__(kBlock) void fused_kernel(FusedArgs a) {
       }
       __syncthreads();
       if (tid == 0) {
-        for (int k = 1; k < kBlock / 64; ++k) {
+        for (int k = 1; k < kFusedBlock / 64; ++k) {
           sre[0] += sre[k];
           sim[0] += sim[k];
         }
@@ -885,9 +964,9 @@ static int launch_fused(bool prog_lds, int grid, int lds_bytes, hipStream_t st, 
     attr_set = true;
   }
   if (prog_lds)
-    fused_kernel<true><<<grid, kBlock, lds_bytes, st>>>(a);
+    fused_kernel<true><<<grid, kFusedBlock, lds_bytes, st>>>(a);
   else
-    fused_kernel<false><<<grid, kBlock, lds_bytes, st>>>(a);
+    fused_kernel<false><<<grid, kFusedBlock, lds_bytes, st>>>(a);
   QBE_HIP(hipGetLastError());
   return QBE_OK;
 }

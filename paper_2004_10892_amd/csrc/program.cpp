@@ -322,7 +322,8 @@ void compile_plan(Plan& p) {
     if (data_elems < 65536 && lds_bytes <= kFusedLdsMax && prep_elems < (int64_t(1) << 31)) {
       std::vector<uint32_t> prog(kHdr, 0);
       const size_t lvl_at = prog.size();
-      prog.resize(lvl_at + 4 * (size_t)n_levels, 0);
+      // two zero entries after the last level end the executor's look-ahead
+      prog.resize(lvl_at + 4 * ((size_t)n_levels + 2), 0);
       while (prog.size() % 4) prog.push_back(0);
       for (int l = 0; l < n_levels; ++l) {
         uint32_t K = 1;
@@ -372,6 +373,7 @@ void compile_plan(Plan& p) {
         ++n_scal;
       }
       while (prog.size() % 4) prog.push_back(0);  // whole 16-byte rows for the LDS copy
+      prog.resize(prog.size() + 4 * kFusedTailRows, 0);  // the executor reads whole row groups
       prog[FH_WORDS] = (uint32_t)prog.size();
       prog[FH_LEVELS] = (uint32_t)n_levels;
       prog[FH_SCALARS] = n_scal;

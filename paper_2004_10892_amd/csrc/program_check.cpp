@@ -90,10 +90,12 @@ std::string check_plan(const Plan& p) {
     if (w[FH_DEP_SRC] != inv) return "fused dependent block offset";
     if ((int64_t)inv + (int64_t)dep * p.n_slices != p.fused_elems) return "fused prepared size";
     if (1 + inv + dep > data) return "fused inputs above data size";
-    if ((int64_t)kHdr + 4 * (int64_t)nl > (int64_t)w.size()) return "fused level table truncated";
+    if ((int64_t)kHdr + 4 * ((int64_t)nl + 2) > (int64_t)w.size()) return "fused level table truncated";
     if ((int64_t)so + nsc > (int64_t)w.size()) return "fused scalar list truncated";
     const uint32_t* lv = w.data() + kHdr;
-    int64_t expect_base = (kHdr + 4 * (int64_t)nl + 3) / 4 * 4;
+    for (uint32_t j = 4 * nl; j < 4 * (nl + 2); ++j)
+      if (lv[j] != 0) return "fused level table end";
+    int64_t expect_base = (kHdr + 4 * ((int64_t)nl + 2) + 3) / 4 * 4;
     for (uint32_t l = 0; l < nl; ++l) {
       const uint32_t base = lv[4 * l], E = lv[4 * l + 1], S = lv[4 * l + 2], K = lv[4 * l + 3];
       if (base != expect_base) return fail("fused record base", base, expect_base);
@@ -101,7 +103,7 @@ std::string check_plan(const Plan& p) {
       if ((int64_t)base + (int64_t)E * S > (int64_t)w.size()) return "fused records truncated";
       for (uint32_t f = 0; f < E; ++f) {
         const uint32_t* rec = w.data() + base + (size_t)f * S;
-        const uint32_t out = rec[0] & 0xFFFFu;
+        const uint32_t out = rec[0];
         if (out < 1 + inv + dep || out >= data) return "fused result outside the arena";
         for (uint32_t j = 1; j < S; ++j) {
           if ((rec[j] & 0xFFFFu) >= data || (rec[j] >> 16) >= data) return "fused operand outside LDS data";
@@ -111,7 +113,9 @@ std::string check_plan(const Plan& p) {
       expect_base += (int64_t)E * S;
     }
     if (expect_base != so) return "fused scalar list offset";
-    if ((int64_t)so + nsc + 3 < (int64_t)w.size()) return "fused program tail";
+    if ((int64_t)(so + nsc + 3) / 4 * 4 + 4 * kFusedTailRows != (int64_t)w.size()) return "fused program tail";
+    for (size_t j = so + nsc; j < w.size(); ++j)
+      if (w[j] != 0) return "fused program tail not zero";
     for (uint32_t j = 0; j < nsc; ++j)
       if (w[so + j] >= data) return "fused scalar outside LDS data";
   }

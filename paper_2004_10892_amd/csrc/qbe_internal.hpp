@@ -69,14 +69,19 @@ struct StepProg {
 //   [1 + inv + dep, data)       intermediates (arena, reused level by level)
 // Program words:
 //   header[kHdr]
-//   levels[4 * n_levels]        (record base, elements E, stride S, operands K)
+//   levels[4 * (n_levels + 2)]  (record base, elements E, stride S, operands K),
+//                               then two zero entries
 //   records                     level by level, E records of S words each
 //                               (S a multiple of 4, S >= 1 + K):
-//                                 w0    = result offset | flags << 16
+//                                 w0    = result offset
 //                                 w1..K = i0 | i1 << 16: LDS offsets of the
 //                                         operand entry for u = 0 and u = 1
 //                                 rest  = 0 (the constant 1, both halves)
-//   scalars[n_scalars]          LDS offsets of the slice's scalar factors
+//   scalars[n_scalars]          LDS offsets of the slice's scalar factors,
+//                               zero words to a multiple of 4, then
+//                               4 * kFusedTailRows zero words (the executor
+//                               reads three rows at any record start)
+constexpr int kFusedTailRows = 2;
 enum FusedHdr {
   FH_WORDS = 0,       // total program words
   FH_LEVELS,          // n_levels
@@ -90,8 +95,6 @@ enum FusedHdr {
   FH_N_SLICES,        // 2^m (saturated)
   kHdr = 16
 };
-// Flag of a record's first word: product without the sum over u.
-constexpr uint32_t kRecNoSum = 1u;
 
 struct Plan {
   // host side
