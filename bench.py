@@ -3,9 +3,10 @@ on one MI355X.
 
 Headline workload: a 5x5 grid circuit of depth 16 (seed 1, bitstring from the
 seed), 6 variables sliced by the tree-trimming heuristic (64 slices), one
-amplitude per step.  The chosen form (one persistent fused launch, replayed
-from a HIP graph) is timed next to the plain FP32 form (one launch per bucket,
-slices batched) and next to the CPU oracle.  Extra lines: a 7x7 depth-24
+amplitude per step.  The chosen form (one persistent fused launch per
+amplitude, issued directly or replayed from a HIP graph, the faster of the
+two) is timed next to the plain FP32 form (one launch per bucket, slices
+batched) and next to the CPU oracle.  Extra lines: a 7x7 depth-24
 circuit with 1024 slices (the HBM-bound per-step kernels) and a batch of 512
 uneven instances.
 
@@ -253,17 +254,26 @@ def main():
         print(json.dumps(bench_learned(torch, qbe, ctx)), flush=True)
         return
 
-    # chosen form: fused persistent launch under a HIP graph
+    # chosen form: one fused persistent launch per amplitude, issued directly
+    # or replayed from a HIP graph, whichever is faster on this machine
     plan, plan_ms, cfg = build_plan(qbe, ctx, name, "fused")
     st = plan.stats()
     ws = plan.workspace()
     out = torch.zeros(2, dtype=torch.float64, device="cuda")
-    g = graph_of(torch, qbe, ctx, lambda: qbe.qbe_contract_async(ctx, plan, ws, out))
+    fn = lambda: qbe.qbe_contract_async(ctx, plan, ws, out)  # noqa: E731
+    g = graph_of(torch, qbe, ctx, fn)
     log(f"[bench] {name}: width {st['width']} levels {st['n_levels']} lds {st['lds_bytes']} B")
-    wall, ev = timed(torch, g.replay, args.steps, args.warmup)
-    got = complex(*out.cpu().numpy())
-    err = abs(got - want) / abs(want)
-    log(f"[bench] chosen: {ev * 1e3:.2f} us/amplitude (wall {wall * 1e3:.2f}), rel err {err:.2e}")
+    forms = {}
+    for form, call in (("fused", fn), ("fused+hipgraph", g.replay)):
+        out.zero_()
+        wall_f, ev_f = timed(torch, call, args.steps, args.warmup)
+        got_f = complex(*out.cpu().numpy())
+        forms[form] = {"ms_per_step": ev_f, "wall_ms_per_step": wall_f, "value": 1e3 / ev_f,
+                       "rel_err": abs(got_f - want) / abs(want)}
+        log(f"[bench] {form}: {ev_f * 1e3:.2f} us/amplitude (wall {wall_f * 1e3:.2f}), "
+            f"rel err {forms[form]['rel_err']:.2e}")
+    chosen = min(forms, key=lambda f: forms[f]["ms_per_step"])
+    ev, err = forms[chosen]["ms_per_step"], forms[chosen]["rel_err"]
 
     # plain FP32 form: one launch per bucket
     plan_p, plan_p_ms, _ = build_plan(qbe, ctx, name, "per_step")
@@ -281,8 +291,8 @@ def main():
         "metric": METRIC, "value": 1e3 / ev, "unit": "amplitudes/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ev, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
-        "config": dict({"workload": name, "form": "fused+hipgraph", "slices": plan.n_slices}, **cfg),
-        "rel_err": err, "mfma_util": 0.0,
+        "config": dict({"workload": name, "form": chosen, "slices": plan.n_slices}, **cfg),
+        "rel_err": err, "mfma_util": 0.0, "forms": forms,
         "planning_ms": plan_ms,
         "amplitudes_per_s_with_planning": 1e3 / (ev + plan_ms),
         "note_planning": "host planning per circuit (min-fill, tree-trimming, schedule and program "
@@ -310,7 +320,7 @@ def main():
         line["learned_proposal"] = bench_learned(torch, qbe, ctx,
                                                  hbm_gbs=line["hbm_workload"]["roofline"]["achieved"])
     print(json.dumps(line), flush=True)
-    if err > 1e-5 or err_p > 1e-5:
+    if max(f["rel_err"] for f in forms.values()) > 1e-5 or err_p > 1e-5:
         sys.exit(1)
 
 

@@ -24,6 +24,12 @@ if not os.path.exists(LIB_PATH):
         f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; g.build()'` "
         "from the repository root")
 
+# torch ships its own HIP and HSA runtimes under sonames equal to ROCm's.
+# Loaded first, they satisfy this library's runtime dependency, so that the
+# process holds one HIP runtime; loading libqbe first would bring ROCm's
+# copies beside torch's, and the second runtime to start sees no device.
+import torch  # noqa: E402,F401
+
 _lib = C.CDLL(LIB_PATH)
 
 QBE_OK = 0

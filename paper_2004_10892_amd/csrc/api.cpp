@@ -82,7 +82,11 @@ int qbe_create(qbe_ctx** out, int32_t device, void* hip_stream) {
   QBE_REQUIRE(out, "out is NULL");
   *out = nullptr;
   int n = 0;
-  if (qbe::dev_count(&n) != QBE_OK || n <= 0) {
+  if (qbe::dev_count(&n) != QBE_OK) {
+    set_error("no GPU device available (" + qbe::g_error + ")");
+    return QBE_ERR_NO_DEVICE;
+  }
+  if (n <= 0) {
     set_error("no GPU device available");
     return QBE_ERR_NO_DEVICE;
   }

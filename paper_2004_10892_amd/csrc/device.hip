@@ -302,7 +302,7 @@ __global__ void finalize_kernel(FinalizeArgs a) {
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < a.G;
        g += (int64_t)gridDim.x * blockDim.x) {
     const int64_t s = a.s0 + g;
-    double re = (double)(int64_t(1) << a.n_free), im = 0.0;
+    double re = ldexp(1.0, a.n_free), im = 0.0;
     for (int j = 0; j < a.n_arena; ++j) {
       const float2 v = a.arena[a.arena_off[j] * a.G + g];
       const double vr = v.x, vi = v.y;
@@ -352,18 +352,26 @@ __global__ __launch_bounds__(256) void reduce_kernel(const double2* __restrict__
 
 // -------------------------------------------------------------- fused form --
 
+// The header words a workgroup needs, passed with the launch (one-plan mode)
+// or with every work item (batch mode) so that no device-memory round trip
+// precedes the LDS fill.
+struct FusedMeta {
+  uint32_t lds_tab, levels, scalars, scalar_off, free_vars, inv, dep, dep_src, bytes, pad;
+};
+
 struct FusedItem {
-  uint32_t plan;   // index into the plan tables
-  uint32_t words;  // program words of that plan
+  const uint32_t* prog;  // the item's plan: program
+  const float2* prep;    //   and prepared inputs
+  FusedMeta meta;
   int64_t slice;
+  uint32_t plan;         // index into the batch's plans
+  uint32_t pad;
 };
 
 struct FusedArgs {
   const uint32_t* prog0;              // one-plan mode (items == nullptr)
   const float2* prep0;
-  uint32_t words0;                    // one-plan mode: program words
-  const uint32_t* const* progs;       // batch mode: per plan
-  const float2* const* preps;
+  FusedMeta meta0;
   const FusedItem* items;             // batch mode: the work items
   const int64_t* ranges;              // batch mode: (begin, end) items per plan
   int64_t s_begin;                    // one-plan mode: slice of item 0
@@ -372,26 +380,40 @@ struct FusedArgs {
   double2* out;                       // per item
   double2* amps;                      // per plan: the slice sum (when reduce_here)
   int32_t reduce_here;                // 1: the last workgroup of a plan sums its items
+  uint32_t lds_ctl;                   // LDS byte offset of the workgroup's control words
 };
+
+static FusedMeta fused_meta(const Plan& p) {
+  const std::vector<uint32_t>& w = p.fused_prog;
+  return FusedMeta{(uint32_t)fused_table_lds(w[FH_DATA_ELEMS]), w[FH_LEVELS], w[FH_SCALARS], w[FH_SCALAR_OFF],
+                   w[FH_FREE], w[FH_INV_ELEMS], w[FH_DEP_ELEMS], w[FH_DEP_SRC], w[FH_BYTE_OFFSETS], 0};
+}
 
 // Threads of a fused workgroup.
 constexpr int kFusedBlock = kBlock;
-// Record rows (16-byte groups of words) held in registers: records of up to
-// 11 operands are read with their level's prefetch, longer ones in a loop.
-constexpr int kRecRows = 3;
+// LDS bytes after the data for the workgroup's control words.
+constexpr int kFusedCtlBytes = 16;
+// Record rows (16-byte groups of words) a lane reads per level, two levels
+// ahead: one half-record of up to 15 operands, or a whole record of up to 7.
+constexpr int kRecRows = kFusedTailRows;
+constexpr int kSplitOpsMax = 8 * kRecRows - 1;
+constexpr int kWholeOpsMax = 4 * kRecRows - 1;
 
-// Reads all kRecRows rows at rec (the program ends with enough zero words
-// that this stays inside it for every record).
-__device__ __forceinline__ void load_rows(const uint32_t* rec, uint4 (&r)[kRecRows]) {
-  const uint4* q = reinterpret_cast<const uint4*>(rec);
-#pragma unroll
-  for (int i = 0; i < kRecRows; ++i) r[i] = q[i];
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(1))) uint32_t* gu32p;
+typedef const __attribute__((address_space(1))) u32x4* gu32x4p;
+// Read-only data every lane reads at the same address (the start of the
+// level table): the constant address space, so that the loads are scalar.
+typedef const __attribute__((address_space(4))) u32x4* cu32x4p;
+
+// The same pointer typed as device (global) memory, so that loads through it
+// are global loads (waited on by their own counter) rather than flat ones.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* as_global(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
 }
 
-__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
-
-// A pointer every lane holds the same value of, moved to scalar registers so
-// that loads through it with uniform offsets become scalar loads.
+// A pointer every lane holds the same value of, moved to scalar registers.
 template <class T>
 __device__ __forceinline__ T* uniform_ptr(T* p) {
   const uint64_t v = reinterpret_cast<uint64_t>(p);
@@ -402,18 +424,58 @@ __device__ __forceinline__ T* uniform_ptr(T* p) {
 
 __device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Operand entries of a record of K operands for u = 0 (x) and u = 1 (y): all
-// 2K LDS reads are issued before any is used.
-template <int K>
-__device__ __forceinline__ void gather(const float2* data, const uint4 (&r)[kRecRows], float2 (&x)[K],
-                                       float2 (&y)[K]) {
-  const uint32_t w[4 * kRecRows] = {r[0].x, r[0].y, r[0].z, r[0].w, r[1].x, r[1].y,
-                                    r[1].z, r[1].w, r[2].x, r[2].y, r[2].z, r[2].w};
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+
+// One lane's record words for a level.
+struct Rec {
+  u32x4 r[kRecRows];
+};
+
+__device__ __forceinline__ uint32_t word(const Rec& c, int i) { return c.r[i >> 2][i & 3]; }
+
+// Reads kRecRows rows at word w (16-byte aligned; the program's zero tail
+// keeps every such read inside it).  A 32-bit byte offset from a uniform
+// base, so that the loads take the base from scalar registers.
+__device__ __forceinline__ void load_rec(gu32p prog, uint32_t w, Rec& c) {
+  typedef const __attribute__((address_space(1))) char* gcp;
+  const gu32x4p q = reinterpret_cast<gu32x4p>(reinterpret_cast<gcp>(prog) + (w << 2));
 #pragma unroll
-  for (int i = 0; i < K; ++i) {
-    x[i] = data[w[1 + i] & 0xFFFFu];
-    y[i] = data[w[1 + i] >> 16];
-  }
+  for (int i = 0; i < kRecRows; ++i) c.r[i] = q[i];
+}
+
+// Levels with 2E <= kFusedBlock give each half-record (one value of u) its
+// own lane; larger ones give each lane a whole record.
+__device__ __forceinline__ bool split_level(uint32_t E) { return 2 * E <= (uint32_t)kFusedBlock; }
+
+// First word this lane reads for a level (base, E, R); lanes past the
+// level's end read its last record, so that every lane reads valid words.
+__device__ __forceinline__ uint32_t rec_word(uint32_t base, uint32_t E, uint32_t R, uint32_t tid) {
+  if (E == 0) return base;
+  return split_level(E) ? base + min(tid, 2 * E - 1) * 4 * R : base + min(tid, E - 1) * 8 * R;
+}
+
+// The fused kernel has no static LDS, so its dynamic LDS (the tensor
+// entries) starts at LDS address 0 and a record offset is an address (byte
+// offsets) or an element index (element offsets).
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) f32x2* lds_v2p;
+__device__ __forceinline__ float2 lds_entry(uint32_t byte_off) {
+  const f32x2 v = *(lds_v2p)(size_t)byte_off;
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void lds_store(uint32_t byte_off, float2 v) {
+  *(lds_v2p)(size_t)byte_off = f32x2{v.x, v.y};
+}
+
+// LDS byte address of 16-bit slot j of the words w[w0..].
+template <bool kBytes>
+__device__ __forceinline__ uint32_t slot(uint32_t w, int j) {
+  if (kBytes) return (j & 1) ? w >> 16 : w & 0xFFFFu;
+  return (j & 1) ? (w >> 13) & 0x7FFF8u : (w << 3) & 0x7FFF8u;
+}
+template <bool kBytes>
+__device__ __forceinline__ uint32_t rec_slot(const Rec& c, int w0, int j) {
+  return slot<kBytes>(word(c, w0 + (j >> 1)), j);
 }
 
 // Product of N complex values as a balanced tree (short dependent chain).
@@ -426,107 +488,170 @@ __device__ __forceinline__ float2 tree_prod(float2 (&v)[N]) {
   return v[0];
 }
 
-// One level whose records have K operands: this thread's first record is
-// in c (read during the previous level) and the next level's is read into p
-// in the same LDS round trip as the operands.  Records beyond the first pass
-// are read here.
-template <int K>
-__device__ __forceinline__ void run_level(float2* data, const uint32_t* rprog, uint32_t base, uint32_t E,
-                                          uint32_t S, const uint4 (&c)[kRecRows], uint4 (&p)[kRecRows],
-                                          uint32_t nb, uint32_t nE, uint32_t nS, uint32_t tid) {
-  // the next level's record first (unconditional: a lane past that level's
-  // end reads its last record), then this record's operands; LDS answers in
-  // order, so one wait covers both
-  load_rows(rprog + nb + (size_t)min(tid, nE > 0 ? nE - 1 : 0u) * nS, p);
+// The value of lane tid ^ 1 (a DPP quad permutation [1, 0, 3, 2]).
+__device__ __forceinline__ float swap_pair(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, false));
+}
+
+// Split level: lane tid holds half-record tid (u = tid & 1 of record
+// tid >> 1); the even lane of each pair adds its partner's product and
+// writes the result.  Every lane runs the same code (the DPP partner must
+// be active); only the writes are guarded.
+template <int K, bool kBytes>
+__device__ __forceinline__ void level_split(const Rec& c, uint32_t E, uint32_t tid) {
+  float2 v[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) v[i] = lds_entry(rec_slot<kBytes>(c, 0, 1 + i));
+  __builtin_amdgcn_sched_barrier(0);  // every read in flight before the first product
+  const float2 p = tree_prod<K>(v);
+  const float2 q = make_float2(swap_pair(p.x), swap_pair(p.y));
+  if ((tid & 1u) == 0 && tid < 2 * E) lds_store(rec_slot<kBytes>(c, 0, 0), cadd(p, q));
+}
+
+// Whole-record level (half-records of one row): lane tid holds record tid;
+// records past the first kFusedBlock are read here.
+template <int K, bool kBytes>
+__device__ __forceinline__ float2 record_value(const Rec& c) {
   float2 x[K], y[K];
-  if (tid < E) {
-    gather<K>(data, c, x, y);
-    data[c[0].x] = cadd(tree_prod<K>(x), tree_prod<K>(y));
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    x[i] = lds_entry(rec_slot<kBytes>(c, 0, 1 + i));
+    y[i] = lds_entry(rec_slot<kBytes>(c, 4, 1 + i));
   }
+  __builtin_amdgcn_sched_barrier(0);  // every read in flight before the first product
+  return cadd(tree_prod<K>(x), tree_prod<K>(y));
+}
+
+template <int K, bool kBytes>
+__device__ __forceinline__ void level_whole(gu32p prog, const Rec& c, uint32_t base, uint32_t E, uint32_t tid) {
+  const float2 v = record_value<K, kBytes>(c);
+  if (tid < E) lds_store(rec_slot<kBytes>(c, 0, 0), v);
   for (uint32_t f = tid + kFusedBlock; f < E; f += kFusedBlock) {
-    uint4 d[kRecRows];
-    load_rows(rprog + base + (size_t)f * S, d);
-    gather<K>(data, d, x, y);
-    data[d[0].x] = cadd(tree_prod<K>(x), tree_prod<K>(y));
+    Rec d;
+    load_rec(prog, base + f * 8, d);
+    lds_store(rec_slot<kBytes>(d, 0, 0), record_value<K, kBytes>(d));
   }
 }
 
-// A level whose records have more operands than the registers hold: the
-// words are read row by row from the record.
-__device__ __forceinline__ void run_level_long(float2* data, const uint32_t* rprog, uint32_t base, uint32_t E,
-                                               uint32_t S, uint4 (&p)[kRecRows], uint32_t nb, uint32_t nE,
-                                               uint32_t nS, uint32_t tid) {
-  load_rows(rprog + nb + (size_t)min(tid, nE > 0 ? nE - 1 : 0u) * nS, p);
+// Records larger than a lane's registers hold: slot by slot from memory.
+template <bool kBytes>
+__device__ __forceinline__ void level_long(gu32p prog, uint32_t base, uint32_t E, uint32_t R, uint32_t K,
+                                           uint32_t tid) {
   for (uint32_t f = tid; f < E; f += kFusedBlock) {
-    const uint4* q = reinterpret_cast<const uint4*>(rprog + base + (size_t)f * S);
-    const uint4 h = q[0];
+    const gu32p rec = prog + base + f * 8 * R;
     float2 a0 = make_float2(1.f, 0.f), a1 = a0;
-    const uint32_t w0[3] = {h.y, h.z, h.w};
-    for (int i = 0; i < 3; ++i) {
-      a0 = cmul(a0, data[w0[i] & 0xFFFFu]);
-      a1 = cmul(a1, data[w0[i] >> 16]);
+    for (uint32_t i = 1; i <= K; ++i) {
+      a0 = cmul(a0, lds_entry(slot<kBytes>(rec[i >> 1], i)));
+      a1 = cmul(a1, lds_entry(slot<kBytes>(rec[4 * R + (i >> 1)], i)));
     }
-    for (uint32_t g = 1; g < S / 4; ++g) {
-      const uint4 w = q[g];
-      a0 = cmul(a0, cmul(cmul(data[w.x & 0xFFFFu], data[w.y & 0xFFFFu]),
-                         cmul(data[w.z & 0xFFFFu], data[w.w & 0xFFFFu])));
-      a1 = cmul(a1, cmul(cmul(data[w.x >> 16], data[w.y >> 16]), cmul(data[w.z >> 16], data[w.w >> 16])));
-    }
-    data[h.x] = cadd(a0, a1);
+    lds_store(slot<kBytes>(rec[0], 0), cadd(a0, a1));
   }
 }
 
-// Level dispatch on the operand count (uniform per level).
-__device__ __forceinline__ void level_step(float2* data, const uint32_t* rprog, const uint4& t, const uint4& tn,
-                                           const uint4 (&c)[kRecRows], uint4 (&p)[kRecRows], uint32_t tid) {
-  const uint32_t base = uni(t.x), E = uni(t.y), S = uni(t.z), K = uni(t.w);
-  const uint32_t nb = uni(tn.x), nE = uni(tn.y), nS = uni(tn.z);
-  switch (K) {
-#define QBE_LEVEL(KK) \
-  case KK: run_level<KK>(data, rprog, base, E, S, c, p, nb, nE, nS, tid); break;
-    QBE_LEVEL(1) QBE_LEVEL(2) QBE_LEVEL(3) QBE_LEVEL(4) QBE_LEVEL(5) QBE_LEVEL(6)
-    QBE_LEVEL(7) QBE_LEVEL(8) QBE_LEVEL(9) QBE_LEVEL(10) QBE_LEVEL(11)
-#undef QBE_LEVEL
-    default: run_level_long(data, rprog, base, E, S, p, nb, nE, nS, tid); break;
+// One level: t is its table entry (base, E, R, K) and c this lane's record
+// words, read two levels earlier; the records of the level two ahead (entry
+// tn) are read into pf here, before any of this level's work.
+template <bool kBytes>
+__device__ __forceinline__ void level_step(gu32p prog, const u32x4& t, const u32x4& tn, const Rec& c, Rec& pf,
+                                           uint32_t tid) {
+  load_rec(prog, rec_word(uni(tn.x), uni(tn.y), uni(tn.z), tid), pf);
+  const uint32_t base = uni(t.x), E = uni(t.y), R = uni(t.z), K = uni(t.w);
+  if (split_level(E) && K <= (uint32_t)kSplitOpsMax) {
+    switch (K) {
+#define QBE_SPLIT(KK) \
+  case KK: level_split<KK, kBytes>(c, E, tid); break;
+      QBE_SPLIT(1) QBE_SPLIT(2) QBE_SPLIT(3) QBE_SPLIT(4) QBE_SPLIT(5) QBE_SPLIT(6) QBE_SPLIT(7) QBE_SPLIT(8)
+      QBE_SPLIT(9) QBE_SPLIT(10) QBE_SPLIT(11) QBE_SPLIT(12) QBE_SPLIT(13) QBE_SPLIT(14) QBE_SPLIT(15)
+#undef QBE_SPLIT
+      default: break;
+    }
+  } else if (!split_level(E) && K <= (uint32_t)kWholeOpsMax) {
+    switch (K) {
+#define QBE_WHOLE(KK) \
+  case KK: level_whole<KK, kBytes>(prog, c, base, E, tid); break;
+      QBE_WHOLE(1) QBE_WHOLE(2) QBE_WHOLE(3) QBE_WHOLE(4) QBE_WHOLE(5) QBE_WHOLE(6) QBE_WHOLE(7)
+#undef QBE_WHOLE
+      default: break;
+    }
+  } else {
+    level_long<kBytes>(prog, base, E, R, K, tid);
   }
 }
 
-// Copy of n elements into LDS by a whole workgroup with U loads in flight per
-// thread before the first store (T a native scalar or vector type, so that
-// the staging array stays in registers).
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-template <int U, class T>
-__device__ __forceinline__ void copy_in(T* dst, const T* src, uint32_t n, uint32_t tid) {
-  for (uint32_t i0 = 0; i0 < n; i0 += U * kFusedBlock) {
-    T v[U];
+// All levels of one item: three per trip, so that the record registers
+// rotate without copies (level l uses the records read at level l - 2 and
+// reads those of level l + 2; entries after the last level are zero).
+// lv is the LDS copy of the level table; t0, t1 and the first two levels'
+// records were read before the inputs were copied.
+template <bool kBytes>
+__device__ __forceinline__ void run_levels(gu32p prog, const __attribute__((address_space(3))) u32x4* lv,
+                                           uint32_t n_levels, u32x4 t0, u32x4 t1, Rec& ra, Rec& rb, uint32_t tid) {
+  u32x4 t2 = lv[2];
+  Rec rc;
+  for (uint32_t l = 0; l < n_levels; l += 3) {
+    const u32x4 t3 = lv[l + 3];
+    level_step<kBytes>(prog, t0, t2, ra, rc, tid);
+    __syncthreads();
+    if (l + 1 >= n_levels) break;
+    const u32x4 t4 = lv[l + 4];
+    level_step<kBytes>(prog, t1, t3, rb, ra, tid);
+    __syncthreads();
+    if (l + 2 >= n_levels) break;
+    const u32x4 t5 = lv[l + 5];
+    level_step<kBytes>(prog, t2, t4, rc, rb, tid);
+    __syncthreads();
+    t0 = t3;
+    t1 = t4;
+    t2 = t5;
+  }
+}
+
+// LDS fill of one work item's inputs, in rounds whose loads are all issued
+// before the first store.
+// LDS fill of one work item: its inputs and the level table (n_tab rows of
+// 16 bytes), in rounds whose loads are all issued before the first store.
+template <int U>
+__device__ __forceinline__ void fill_lds(uint64_t* dinv, const uint64_t* sinv_, uint32_t n_inv, uint64_t* ddep,
+                                         const uint64_t* sdep_, uint32_t n_dep, u32x4* dtab, const u32x4* stab_,
+                                         uint32_t n_tab, uint32_t tid) {
+  const auto sinv = as_global(sinv_);
+  const auto sdep = as_global(sdep_);
+  const auto stab = as_global(stab_);
+  for (uint32_t i0 = 0; i0 < n_inv || i0 < n_dep || i0 < n_tab; i0 += U * kFusedBlock) {
+    uint64_t vi[U], vd[U];
+    const uint32_t it = i0 + tid;
+    const u32x4 vt = it < n_tab ? stab[it] : u32x4{};
 #pragma unroll
     for (int j = 0; j < U; ++j) {
       const uint32_t i = i0 + j * kFusedBlock + tid;
-      v[j] = i < n ? src[i] : T{};
+      vi[j] = i < n_inv ? sinv[i] : 0;
+      vd[j] = i < n_dep ? sdep[i] : 0;
     }
+    if (it < n_tab) dtab[it] = vt;
 #pragma unroll
     for (int j = 0; j < U; ++j) {
       const uint32_t i = i0 + j * kFusedBlock + tid;
-      if (i < n) dst[i] = v[j];
+      if (i < n_inv) dinv[i] = vi[j];
+      if (i < n_dep) ddep[i] = vd[j];
     }
   }
 }
 
-// kProgLds: the plan's program is copied into LDS (ahead of the tensor
-// entries) whenever the workgroup switches plans, and records are read from
-// there; otherwise records are read from device memory with a one-level
-// prefetch.  Header and level-table words are always read from device memory
-// with uniform addresses, so they land in scalar registers.
-//
 // Work distribution: in one-plan mode workgroup b takes items b, b + grid,
-// ...; in batch mode items are pulled from a counter (uneven sizes).
-template <bool kProgLds>
-__global__ __launch_bounds__(kFusedBlock) void fused_kernel(FusedArgs a) {
+// ...; in batch mode items are pulled from a counter (uneven sizes).  The
+// program stays in device memory (all workgroups of a plan read the same
+// words, so they come from the caches); LDS holds the tensor entries only.
+// One workgroup of four waves per compute unit is the intended occupancy: the
+// compiler may use the whole register file to keep every read of a level in
+// flight at once.
+__global__ __launch_bounds__(kFusedBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void fused_kernel(FusedArgs a) {
+  // all of the workgroup's LDS is dynamic, so that the tensor entries start
+  // at LDS address 0 and record offsets are addresses; the two shared words
+  // sit after the largest data block of the launch
   extern __shared__ uint4 lds4[];
-  __shared__ int64_t s_item;
-  __shared__ uint32_t s_flag, s_plan;
-  const int tid = threadIdx.x;
-  if (tid == 0) s_plan = 0xFFFFFFFFu;
+  int64_t& s_item = *reinterpret_cast<int64_t*>(reinterpret_cast<char*>(lds4) + a.lds_ctl);
+  uint32_t& s_flag = *reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(lds4) + a.lds_ctl + 8);
+  const uint32_t tid = threadIdx.x;
   int64_t next = blockIdx.x;
   for (;;) {
     int64_t item;
@@ -544,92 +669,84 @@ __global__ __launch_bounds__(kFusedBlock) void fused_kernel(FusedArgs a) {
       next += gridDim.x;
     }
     if (item < 0) break;
-    uint32_t plan = 0, words = a.words0;
+    uint32_t plan = 0;
     int64_t slice = a.s_begin + item;
     const uint32_t* gprog = a.prog0;
     const float2* prep = a.prep0;
+    FusedMeta mt = a.meta0;
     if (a.items) {
       const FusedItem wi = a.items[item];
-      plan = __builtin_amdgcn_readfirstlane(wi.plan);
-      words = __builtin_amdgcn_readfirstlane(wi.words);
-      slice = __builtin_amdgcn_readfirstlane((int)wi.slice);
-      gprog = a.progs[plan];
-      prep = a.preps[plan];
+      plan = uni(wi.plan);
+      slice = uni((uint32_t)wi.slice);
+      gprog = wi.prog;
+      prep = wi.prep;
+      mt = FusedMeta{uni(wi.meta.lds_tab), uni(wi.meta.levels),  uni(wi.meta.scalars), uni(wi.meta.scalar_off),
+                     uni(wi.meta.free_vars), uni(wi.meta.inv), uni(wi.meta.dep),     uni(wi.meta.dep_src),
+                     uni(wi.meta.bytes), 0};
     }
     gprog = uniform_ptr(gprog);
+    const gu32p prog = as_global(gprog);
     prep = uniform_ptr(prep);
-    const uint32_t* rprog = gprog;  // where records are read from
     float2* data = reinterpret_cast<float2*>(lds4);
-    if (kProgLds) {
-      if (plan != __builtin_amdgcn_readfirstlane(s_plan)) {
-        copy_in<8>(reinterpret_cast<u32x4*>(lds4), reinterpret_cast<const u32x4*>(gprog), words / 4, tid);
-      }
-      rprog = reinterpret_cast<const uint32_t*>(lds4);
-      data = reinterpret_cast<float2*>(lds4 + words / 4);
-    }
+    // level table and the records of the first two levels: issued first, so
+    // that they arrive while the inputs are copied
+    const cu32x4p glv = (cu32x4p)(gprog + kHdr);
+    u32x4 t0 = glv[0], t1 = glv[1];
+    typedef __attribute__((address_space(3))) u32x4* lds_u32x4p;
+    const lds_u32x4p lv = (lds_u32x4p)(size_t)mt.lds_tab;  // the LDS copy
+    Rec ra, rb;
+    load_rec(prog, rec_word(uni(t0.x), uni(t0.y), uni(t0.z), tid), ra);
+    load_rec(prog, rec_word(uni(t1.x), uni(t1.y), uni(t1.z), tid), rb);
     // inputs of this slice into LDS, the constant 1 at offset 0
-    const uint32_t inv = gprog[FH_INV_ELEMS], dep = gprog[FH_DEP_ELEMS];
-    const float2* dsrc = prep + gprog[FH_DEP_SRC] + slice * (int64_t)dep;
+    const uint32_t inv = mt.inv, dep = mt.dep;
+    const float2* dsrc = prep + mt.dep_src + slice * (int64_t)dep;
     if (tid == 0) data[0] = make_float2(1.f, 0.f);
-    copy_in<8>(reinterpret_cast<uint64_t*>(data + 1), reinterpret_cast<const uint64_t*>(prep), inv, tid);
-    copy_in<8>(reinterpret_cast<uint64_t*>(data + 1 + inv), reinterpret_cast<const uint64_t*>(dsrc), dep, tid);
+    // the scalar factors' offsets (lane j < 64: factor j), read now for the end
+    const uint32_t n_scal = mt.scalars;
+    const uint32_t scal0 = tid < n_scal && tid < 64 ? prog[mt.scalar_off + tid] : 0u;
+    fill_lds<4>(reinterpret_cast<uint64_t*>(data + 1), reinterpret_cast<const uint64_t*>(prep), inv,
+                reinterpret_cast<uint64_t*>(data + 1 + inv), reinterpret_cast<const uint64_t*>(dsrc), dep,
+                reinterpret_cast<u32x4*>(reinterpret_cast<char*>(lds4) + mt.lds_tab),
+                reinterpret_cast<const u32x4*>(gprog + kHdr), mt.levels + kFusedLevelPad, tid);
     __syncthreads();
-    if (kProgLds && tid == 0) s_plan = plan;  // read again only after the next barrier
-    const uint32_t n_levels = gprog[FH_LEVELS];
-    // level table (LDS copy when the program is there; two zero entries
-    // after the last level): entries l and l + 1 are in registers while
-    // level l runs, and entry l + 2 is read during it
-    const uint4* lv = reinterpret_cast<const uint4*>(rprog + kHdr);
-    uint4 ca[kRecRows] = {}, cb[kRecRows] = {};
-    uint4 t0 = lv[0], t1 = lv[1];
-    if ((uint32_t)tid < uni(t0.y)) load_rows(rprog + uni(t0.x) + (size_t)tid * uni(t0.z), ca);
-    for (uint32_t l = 0; l < n_levels; l += 2) {
-      // two levels per trip: the record registers swap roles without copies
-      const uint4 t2 = lv[l + 2];
-      level_step(data, rprog, t0, t1, ca, cb, tid);
-      __syncthreads();
-      if (l + 1 >= n_levels) break;
-      const uint4 t3 = lv[l + 3];
-      level_step(data, rprog, t1, t2, cb, ca, tid);
-      __syncthreads();
-      t0 = t2;
-      t1 = t3;
-    }
+    if (mt.bytes)
+      run_levels<true>(prog, lv, mt.levels, t0, t1, ra, rb, tid);
+    else
+      run_levels<false>(prog, lv, mt.levels, t0, t1, ra, rb, tid);
     if (tid < 64) {
       // product of the slice's scalar factors: lane j holds factor j (and
-      // j + 64, ...), then a fixed binary tree across the wave, in FP64
-      const uint32_t* scal = rprog + gprog[FH_SCALAR_OFF];
-      const uint32_t n_scal = gprog[FH_SCALARS];
-      double re = tid == 0 ? (double)(1u << gprog[FH_FREE]) : 1.0, im = 0.0;
+      // j + 64, ...), then a binary tree across the wave, in FP64
+      const gu32p scal = prog + mt.scalar_off;
+      double re = tid == 0 ? ldexp(1.0, (int)mt.free_vars) : 1.0, im = 0.0;
       for (uint32_t j = tid; j < n_scal; j += 64) {
-        const float2 v = data[scal[j]];
+        const float2 v = data[j < 64 ? scal0 : scal[j]];
         const double vr = v.x, vi = v.y;
         const double nr = re * vr - im * vi;
         im = re * vi + im * vr;
         re = nr;
       }
-      for (int w = 1; w < 64; w <<= 1) {
+      for (uint32_t w = 1; w < n_scal && w < 64; w <<= 1) {  // lanes >= n_scal hold 1
         const double orr = __shfl_down(re, w, 64), oi = __shfl_down(im, w, 64);
         const double nr = re * orr - im * oi;
         im = re * oi + im * orr;
         re = nr;
       }
-    if (tid == 0) {
-      a.out[item] = make_double2(re, im);
-      s_flag = 0u;
-      if (a.reduce_here) {
-        // publish the value and count it (release); the plan's last item
-        // sums them all (acquire)
-        int64_t b = 0, e = a.n_items;
-        if (a.ranges) {
-          b = a.ranges[2 * plan];
-          e = a.ranges[2 * plan + 1];
+      if (tid == 0) {
+        a.out[item] = make_double2(re, im);
+        s_flag = 0u;
+        if (a.reduce_here) {
+          // publish the value and count it (release); the plan's last item
+          // sums them all (acquire)
+          int64_t b = 0, e = a.n_items;
+          if (a.ranges) {
+            b = a.ranges[2 * plan];
+            e = a.ranges[2 * plan + 1];
+          }
+          const uint32_t done =
+              __hip_atomic_fetch_add(&a.state[2 + plan], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+          if ((int64_t)done == e - b) s_flag = 1u;
         }
-        const uint32_t done =
-            __hip_atomic_fetch_add(&a.state[2 + plan], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
-        if ((int64_t)done == e - b) s_flag = 1u;
       }
-    }
     }
     __syncthreads();
     if (s_flag) {
@@ -668,7 +785,6 @@ __global__ __launch_bounds__(kFusedBlock) void fused_kernel(FusedArgs a) {
       if (tid == 0) {
         a.amps[plan] = make_double2(sre[0], sim[0]);
         a.state[2 + plan] = 0u;
-        s_plan = 0xFFFFFFFFu;
       }
     }
   }
@@ -954,19 +1070,15 @@ int dev_autotune(Plan& p, void* stream, void* ws, size_t ws_bytes, int64_t min_e
   return rc;
 }
 
-static int launch_fused(bool prog_lds, int grid, int lds_bytes, hipStream_t st, const FusedArgs& a) {
+static int launch_fused(int grid, int lds_bytes, hipStream_t st, FusedArgs a) {
   static bool attr_set = false;
   if (!attr_set) {
-    QBE_HIP(hipFuncSetAttribute((const void*)fused_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                kFusedLdsMax));
-    QBE_HIP(hipFuncSetAttribute((const void*)fused_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                kFusedLdsMax));
+    QBE_HIP(hipFuncSetAttribute((const void*)fused_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                kFusedLdsMax + kFusedCtlBytes));
     attr_set = true;
   }
-  if (prog_lds)
-    fused_kernel<true><<<grid, kFusedBlock, lds_bytes, st>>>(a);
-  else
-    fused_kernel<false><<<grid, kFusedBlock, lds_bytes, st>>>(a);
+  a.lds_ctl = (uint32_t)lds_bytes;
+  fused_kernel<<<grid, kFusedBlock, lds_bytes + kFusedCtlBytes, st>>>(a);
   QBE_HIP(hipGetLastError());
   return QBE_OK;
 }
@@ -995,9 +1107,9 @@ int dev_contract(const Plan& p, void* stream, void* ws, size_t ws_bytes, int64_t
     a.state = (uint32_t*)p.d_state;
     a.out = per_slice;
     a.amps = (double2*)d_partial_out;
-    a.words0 = (uint32_t)p.fused_prog.size();
+    a.meta0 = fused_meta(p);
     a.reduce_here = n <= kInKernelReduceMax ? 1 : 0;
-    int rc = launch_fused(p.fused_prog_in_lds, fused_grid(p.fused_lds_bytes, n), p.fused_lds_bytes, st, a);
+    int rc = launch_fused(fused_grid(p.fused_lds_bytes, n), p.fused_lds_bytes, st, a);
     if (rc) return rc;
     if (a.reduce_here) return QBE_OK;
   } else {
@@ -1038,14 +1150,10 @@ int dev_contract(const Plan& p, void* stream, void* ws, size_t ws_bytes, int64_t
 
 int dev_batch_build(Batch& b) {
   const int np = (int)b.plans.size();
-  std::vector<const uint32_t*> progs(np, nullptr);
-  std::vector<const float2*> preps(np, nullptr);
   std::vector<int> idx;
   b.lds_bytes = 0;
   b.wide.clear();
   b.wide_ws = 0;
-  b.prog_in_lds = true;
-  int data_bytes = 0;
   for (int i = 0; i < np; ++i) {
     const Plan& p = *b.plans[i];
     if (p.exec != QBE_EXEC_FUSED) {
@@ -1053,14 +1161,9 @@ int dev_batch_build(Batch& b) {
       b.wide_ws = std::max(b.wide_ws, dev_workspace_all(p));
       continue;
     }
-    progs[i] = (const uint32_t*)p.d_fused_prog;
-    preps[i] = (const float2*)p.d_fused_in;
     b.lds_bytes = std::max(b.lds_bytes, p.fused_lds_bytes);
-    b.prog_in_lds = b.prog_in_lds && p.fused_prog_in_lds;
-    data_bytes = std::max(data_bytes, (int)std::max<int64_t>(8 * (int64_t)p.fused_prog[FH_DATA_ELEMS], 256 * 16));
     idx.push_back(i);
   }
-  if (!b.prog_in_lds) b.lds_bytes = data_bytes;
   // biggest work items first, so the tail of the persistent grid is short
   std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) {
     return b.plans[x]->cost.flops > b.plans[y]->cost.flops;
@@ -1069,15 +1172,15 @@ int dev_batch_build(Batch& b) {
   std::vector<int64_t> ranges(2 * np, 0);
   for (int i : idx) {
     ranges[2 * i] = (int64_t)items.size();
-    const uint32_t words = (uint32_t)b.plans[i]->fused_prog.size();
-    for (int64_t s = 0; s < b.plans[i]->n_slices; ++s) items.push_back(FusedItem{(uint32_t)i, words, s});
+    const Plan& p = *b.plans[i];
+    const FusedMeta mt = fused_meta(p);
+    for (int64_t s = 0; s < p.n_slices; ++s)
+      items.push_back(FusedItem{(const uint32_t*)p.d_fused_prog, (const float2*)p.d_fused_in, mt, s, (uint32_t)i, 0});
     ranges[2 * i + 1] = (int64_t)items.size();
   }
   b.n_items = (int64_t)items.size();
   b.item_begin = ranges;
   int rc;
-  if ((rc = upload(&b.d_progs, progs.data(), np * sizeof(void*)))) return rc;
-  if ((rc = upload(&b.d_preps, preps.data(), np * sizeof(void*)))) return rc;
   if ((rc = upload(&b.d_items, items.data(), items.size() * sizeof(FusedItem)))) return rc;
   if ((rc = upload(&b.d_ranges, ranges.data(), ranges.size() * 8))) return rc;
   if ((rc = dmalloc(&b.d_state, (2 + (size_t)np) * 4))) return rc;
@@ -1089,7 +1192,7 @@ int dev_batch_build(Batch& b) {
 }
 
 void dev_batch_free(Batch& b) {
-  void** ptrs[] = {&b.d_progs, &b.d_preps, &b.d_items, &b.d_ranges, &b.d_state};
+  void** ptrs[] = {&b.d_items, &b.d_ranges, &b.d_state};
   for (void** q : ptrs) {
     if (*q) (void)hipFree(*q);
     *q = nullptr;
@@ -1110,8 +1213,6 @@ int dev_batch_contract(const Batch& b, void* stream, void* ws, size_t ws_bytes, 
   if (b.n_items > 0) {
     double2* per_item = (double2*)(w + 256);
     FusedArgs a{};
-    a.progs = (const uint32_t* const*)b.d_progs;
-    a.preps = (const float2* const*)b.d_preps;
     a.items = (const FusedItem*)b.d_items;
     a.ranges = (const int64_t*)b.d_ranges;
     a.n_items = b.n_items;
@@ -1119,7 +1220,7 @@ int dev_batch_contract(const Batch& b, void* stream, void* ws, size_t ws_bytes, 
     a.out = per_item;
     a.amps = (double2*)d_amps;
     a.reduce_here = b.reduce_here ? 1 : 0;
-    int rc = launch_fused(b.prog_in_lds, fused_grid(b.lds_bytes, b.n_items), b.lds_bytes, st, a);
+    int rc = launch_fused(fused_grid(b.lds_bytes, b.n_items), b.lds_bytes, st, a);
     if (rc) return rc;
     if (!b.reduce_here) {
       // one reduction block per plan; blocks of per-step plans see an empty range

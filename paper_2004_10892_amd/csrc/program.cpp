@@ -317,14 +317,19 @@ void compile_plan(Plan& p) {
     }
     const int64_t arena0 = 1 + inv + dep;
     const int64_t data_elems = arena0 + la.top;
-    const int64_t lds_bytes = std::max<int64_t>(data_elems * 8, 256 * 16);
+    // LDS: the tensor entries, then a copy of the level table
+    const int64_t lds_bytes = std::max<int64_t>(fused_table_lds(data_elems) + 16 * ((int64_t)n_levels + kFusedLevelPad),
+                                                256 * 16);
     const int64_t prep_elems = inv + dep * p.n_slices;
-    if (data_elems < 65536 && lds_bytes <= kFusedLdsMax && prep_elems < (int64_t(1) << 31)) {
+    if (lds_bytes <= kFusedLdsMax && prep_elems < (int64_t(1) << 31)) {
       std::vector<uint32_t> prog(kHdr, 0);
       const size_t lvl_at = prog.size();
-      // two zero entries after the last level end the executor's look-ahead
-      prog.resize(lvl_at + 4 * ((size_t)n_levels + 2), 0);
+      // zero entries after the last level end the executor's look-ahead
+      prog.resize(lvl_at + 4 * ((size_t)n_levels + kFusedLevelPad), 0);
       while (prog.size() % 4) prog.push_back(0);
+      // 16-bit operand offsets: bytes when the data fit 64 KB, else elements
+      const bool bytes = data_elems * 8 <= 65536;
+      const uint32_t unit = bytes ? 8u : 1u;
       for (int l = 0; l < n_levels; ++l) {
         uint32_t K = 1;
         int64_t E = 0;
@@ -332,10 +337,10 @@ void compile_plan(Plan& p) {
           K = std::max<uint32_t>(K, (uint32_t)s.steps[k].ops.size());
           E += int64_t(1) << s.steps[k].out.size();
         }
-        const uint32_t S = (1 + K + 3) / 4 * 4;
+        const uint32_t R = (1 + K + 7) / 8;  // 16-byte rows of a half-record
         prog[lvl_at + 4 * l + 0] = (uint32_t)prog.size();
         prog[lvl_at + 4 * l + 1] = (uint32_t)E;
-        prog[lvl_at + 4 * l + 2] = S;
+        prog[lvl_at + 4 * l + 2] = R;
         prog[lvl_at + 4 * l + 3] = K;
         for (int k : by_level[l]) {
           const Step& st = s.steps[k];
@@ -350,18 +355,24 @@ void compile_plan(Plan& p) {
             up.push_back(((m_ >> r) & 1u) ? (1u << (__builtin_popcount(m_) - 1)) : 0u);
           }
           for (uint32_t x = 0; x < (1u << r); ++x) {
+            // two half-records of 8R halfwords: [result, operand entries for
+            // u = 0] and [0, operand entries for u = 1]
             const size_t at = prog.size();
-            prog.resize(at + S, 0);
-            prog[at] = (uint32_t)(arena0 + lds_out[k] + x);
+            prog.resize(at + 8 * R, 0);
+            auto put = [&](uint32_t half, uint32_t j, uint32_t v) {
+              prog[at + 4 * R * half + j / 2] |= (v * unit) << (16 * (j % 2));
+            };
+            put(0, 0, (uint32_t)(arena0 + lds_out[k] + x));
             for (size_t i = 0; i < st.ops.size(); ++i) {
               uint32_t e = 0, bit = 0;
               for (uint32_t mm = mk[i]; mm; mm &= mm - 1, ++bit) e |= ((x >> __builtin_ctz(mm)) & 1u) << bit;
-              const uint32_t i0 = off[i] + e, i1 = i0 + up[i];
-              prog[at + 1 + i] = i0 | (i1 << 16);
+              put(0, 1 + (uint32_t)i, off[i] + e);
+              put(1, 1 + (uint32_t)i, off[i] + e + up[i]);
             }
           }
         }
       }
+      prog[FH_BYTE_OFFSETS] = bytes ? 1u : 0u;
       const uint32_t scal_at = (uint32_t)prog.size();
       uint32_t n_scal = 0;
       for (int t : s.scalar_inputs) {
@@ -372,7 +383,7 @@ void compile_plan(Plan& p) {
         prog.push_back((uint32_t)(arena0 + lds_out[k]));
         ++n_scal;
       }
-      while (prog.size() % 4) prog.push_back(0);  // whole 16-byte rows for the LDS copy
+      while (prog.size() % 4) prog.push_back(0);
       prog.resize(prog.size() + 4 * kFusedTailRows, 0);  // the executor reads whole row groups
       prog[FH_WORDS] = (uint32_t)prog.size();
       prog[FH_LEVELS] = (uint32_t)n_levels;
@@ -385,10 +396,7 @@ void compile_plan(Plan& p) {
       prog[FH_DEP_SRC] = (uint32_t)inv;
       prog[FH_N_SLICES] = (uint32_t)std::min<int64_t>(p.n_slices, UINT32_MAX);
       p.fused_ok = true;
-      // records travel to LDS with the inputs when both fit
-      const int64_t with_prog = (int64_t)prog.size() * 4 + data_elems * 8;
-      p.fused_prog_in_lds = with_prog <= kFusedLdsMax;
-      p.fused_lds_bytes = (int)(p.fused_prog_in_lds ? std::max<int64_t>(with_prog, lds_bytes) : lds_bytes);
+      p.fused_lds_bytes = (int)lds_bytes;
       p.fused_prog = std::move(prog);
       // gather map: invariant block, then one block per slice
       p.fused_map.reserve(prep_elems);

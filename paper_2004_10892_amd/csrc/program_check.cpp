@@ -80,37 +80,42 @@ std::string check_plan(const Plan& p) {
     if (w.size() < (size_t)kHdr || w[FH_WORDS] != w.size() || w.size() % 4) return "fused header";
     const uint32_t nl = w[FH_LEVELS], nsc = w[FH_SCALARS], so = w[FH_SCALAR_OFF];
     const uint32_t inv = w[FH_INV_ELEMS], dep = w[FH_DEP_ELEMS], data = w[FH_DATA_ELEMS];
-    {
-      const int64_t base = std::max<int64_t>((int64_t)data * 8, 256 * 16);
-      const int64_t want = p.fused_prog_in_lds ? std::max<int64_t>(base, (int64_t)w.size() * 4 + (int64_t)data * 8) : base;
-      if (want != p.fused_lds_bytes) return "fused LDS size";
-    }
+    if (p.fused_lds_bytes != std::max<int64_t>(fused_table_lds(data) + 16 * ((int64_t)nl + kFusedLevelPad), 256 * 16))
+      return "fused LDS size";
     if (p.fused_lds_bytes > kFusedLdsMax) return "fused LDS above budget";
-    if (data >= 65536) return "fused data above 16-bit offsets";
     if (w[FH_DEP_SRC] != inv) return "fused dependent block offset";
     if ((int64_t)inv + (int64_t)dep * p.n_slices != p.fused_elems) return "fused prepared size";
     if (1 + inv + dep > data) return "fused inputs above data size";
-    if ((int64_t)kHdr + 4 * ((int64_t)nl + 2) > (int64_t)w.size()) return "fused level table truncated";
+    if ((int64_t)kHdr + 4 * ((int64_t)nl + kFusedLevelPad) > (int64_t)w.size()) return "fused level table truncated";
     if ((int64_t)so + nsc > (int64_t)w.size()) return "fused scalar list truncated";
     const uint32_t* lv = w.data() + kHdr;
-    for (uint32_t j = 4 * nl; j < 4 * (nl + 2); ++j)
+    for (uint32_t j = 4 * nl; j < 4 * (nl + kFusedLevelPad); ++j)
       if (lv[j] != 0) return "fused level table end";
-    int64_t expect_base = (kHdr + 4 * ((int64_t)nl + 2) + 3) / 4 * 4;
+    int64_t expect_base = (kHdr + 4 * ((int64_t)nl + kFusedLevelPad) + 3) / 4 * 4;
+    const bool bytes = w[FH_BYTE_OFFSETS] != 0;
+    if (w[FH_BYTE_OFFSETS] > 1 || bytes != ((int64_t)data * 8 <= 65536)) return "fused offset unit";
+    const uint32_t unit = bytes ? 8u : 1u;
+    const uint32_t arena_lo = (1 + inv + dep) * unit, data_hi = data * unit;
+    if (data_hi > 65536) return "fused offsets above 16 bits";
     for (uint32_t l = 0; l < nl; ++l) {
-      const uint32_t base = lv[4 * l], E = lv[4 * l + 1], S = lv[4 * l + 2], K = lv[4 * l + 3];
+      const uint32_t base = lv[4 * l], E = lv[4 * l + 1], R = lv[4 * l + 2], K = lv[4 * l + 3];
       if (base != expect_base) return fail("fused record base", base, expect_base);
-      if (base % 4 || S % 4 || S < 1 + K || E == 0) return "fused level shape";
-      if ((int64_t)base + (int64_t)E * S > (int64_t)w.size()) return "fused records truncated";
+      if (base % 4 || R != (1 + K + 7) / 8 || E == 0 || K == 0) return "fused level shape";
+      if ((int64_t)base + (int64_t)E * 8 * R > (int64_t)w.size()) return "fused records truncated";
       for (uint32_t f = 0; f < E; ++f) {
-        const uint32_t* rec = w.data() + base + (size_t)f * S;
-        const uint32_t out = rec[0];
-        if (out < 1 + inv + dep || out >= data) return "fused result outside the arena";
-        for (uint32_t j = 1; j < S; ++j) {
-          if ((rec[j] & 0xFFFFu) >= data || (rec[j] >> 16) >= data) return "fused operand outside LDS data";
-          if (j > K && rec[j] != 0) return "fused padding word not the constant";
-        }
+        const uint32_t* rec = w.data() + base + (size_t)f * 8 * R;
+        auto hw = [&](uint32_t half, uint32_t j) { return (rec[4 * R * half + j / 2] >> (16 * (j % 2))) & 0xFFFFu; };
+        const uint32_t out = hw(0, 0);
+        if (out % unit || out < arena_lo || out >= data_hi) return "fused result outside the arena";
+        if (hw(1, 0) != 0) return "fused second half's first slot not zero";
+        for (uint32_t u = 0; u < 2; ++u)
+          for (uint32_t j = 1; j < 8 * R; ++j) {
+            const uint32_t v = hw(u, j);
+            if (v % unit || v >= data_hi) return "fused operand outside LDS data";
+            if (j > K && v != 0) return "fused padding slot not the constant";
+          }
       }
-      expect_base += (int64_t)E * S;
+      expect_base += (int64_t)E * 8 * R;
     }
     if (expect_base != so) return "fused scalar list offset";
     if ((int64_t)(so + nsc + 3) / 4 * 4 + 4 * kFusedTailRows != (int64_t)w.size()) return "fused program tail";

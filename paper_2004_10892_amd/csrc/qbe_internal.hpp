@@ -61,27 +61,36 @@ struct StepProg {
 
 // --------------------------------------------------------- fused (LDS) form --
 
-// A fused program lives in device memory (uint32 words); the workgroup keeps
-// only tensor entries in LDS.  LDS data layout (complex64 elements):
+// A fused program lives in device memory (uint32 words) and is read from
+// there (through the caches); the workgroup keeps the tensor entries and a
+// copy of the level table in LDS.  LDS data layout (complex64 elements):
 //   [0]                         the constant 1 (padding operand)
 //   [1, 1 + inv)                slice-invariant input tensors
 //   [1 + inv, 1 + inv + dep)    this slice's copies of slice-dependent inputs
 //   [1 + inv + dep, data)       intermediates (arena, reused level by level)
+// then, from byte fused_table_lds(data), the level table (16 bytes a level).
 // Program words:
 //   header[kHdr]
-//   levels[4 * (n_levels + 2)]  (record base, elements E, stride S, operands K),
-//                               then two zero entries
-//   records                     level by level, E records of S words each
-//                               (S a multiple of 4, S >= 1 + K):
-//                                 w0    = result offset
-//                                 w1..K = i0 | i1 << 16: LDS offsets of the
-//                                         operand entry for u = 0 and u = 1
-//                                 rest  = 0 (the constant 1, both halves)
-//   scalars[n_scalars]          LDS offsets of the slice's scalar factors,
-//                               zero words to a multiple of 4, then
+//   levels[4 * (n_levels + kFusedLevelPad)]
+//                               (record base, elements E, rows R of a
+//                               half-record, operands K), then zero entries
+//   records                     level by level, E records of two half-records
+//                               of R 16-byte rows (8R halfwords) each:
+//                                 half u, halfword 0: LDS offset of the
+//                                   result (u = 0), 0 (u = 1)
+//                                 half u, halfwords 1..K: LDS offsets of the
+//                                   operand entries for that value of u
+//                                 rest: 0 (the constant 1)
+//                               offsets in bytes (header FH_BYTE_OFFSETS = 1,
+//                               data within 64 KB) or else in elements
+//   scalars[n_scalars]          LDS element offsets of the slice's scalar
+//                               factors, zero words to a multiple of 4, then
 //                               4 * kFusedTailRows zero words (the executor
-//                               reads three rows at any record start)
+//                               reads kFusedTailRows rows at any half-record)
 constexpr int kFusedTailRows = 2;
+constexpr int kFusedLevelPad = 3;
+// LDS byte offset of the level table's copy: after the tensor entries.
+inline int64_t fused_table_lds(int64_t data_elems) { return (data_elems * 8 + 15) / 16 * 16; }
 enum FusedHdr {
   FH_WORDS = 0,       // total program words
   FH_LEVELS,          // n_levels
@@ -93,6 +102,7 @@ enum FusedHdr {
   FH_DATA_ELEMS,      // total LDS data elements (including the constant)
   FH_DEP_SRC,         // element offset of slice 0's block in the prepared buffer
   FH_N_SLICES,        // 2^m (saturated)
+  FH_BYTE_OFFSETS,    // 1: record offsets are LDS bytes, 0: complex64 elements
   kHdr = 16
 };
 
@@ -123,7 +133,6 @@ struct Plan {
   std::vector<int32_t> fused_map;       // prepared fused buffer gather map
   int64_t fused_elems = 0;
   int fused_lds_bytes = 0;              // LDS of one workgroup
-  bool fused_prog_in_lds = false;       // records copied to LDS per slice
 
   // device side (owned)
   int device = -1;
@@ -145,13 +154,10 @@ struct Batch {
   std::vector<int64_t> item_begin;  // per plan, into the item table (+ end)
   int64_t n_items = 0;
   int lds_bytes = 0;
-  void* d_progs = nullptr;   // const uint32_t* per plan
-  void* d_preps = nullptr;   // const float2* per plan
   void* d_items = nullptr;   // FusedItem per item
   void* d_ranges = nullptr;  // int64 (begin, end) per plan
   void* d_state = nullptr;   // uint32[2 + n_plans]: work, exits, items done per plan
   bool reduce_here = true;   // the fused kernel sums each plan's items itself
-  bool prog_in_lds = true;   // every fused plan's records fit in LDS with its data
 };
 
 // -------------------------------------------------- learned proposal (GNN) --

@@ -158,3 +158,13 @@ def test_no_device_without_gpu():
         pytest.skip("a GPU is present")
     rc = qbe._lib.qbe_create(qbe.C.byref(qbe._vp()), 0, None)
     assert rc == -6
+
+
+def test_one_hip_runtime_in_process():
+    # the package binds to the HIP runtime torch loaded; a second copy of the
+    # runtime in the process would not see the device
+    with open("/proc/self/maps") as f:
+        maps = f.read()
+    for name in ("libamdhip64", "libhsa-runtime64"):
+        paths = {l.split()[-1] for l in maps.splitlines() if name in l}
+        assert len(paths) == 1, paths
