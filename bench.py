@@ -246,6 +246,7 @@ def main():
     if args.only == "hbm":
         print(json.dumps(bench_hbm(torch, qbe, ctx, args.steps)), flush=True)
         print(json.dumps(bench_hbm(torch, qbe, ctx, args.steps, "bf16x3")), flush=True)
+        print(json.dumps(bench_hbm(torch, qbe, ctx, args.steps, "bf16x6")), flush=True)
         return
     if args.only == "batch":
         print(json.dumps(bench_batch(torch, qbe, ctx, args.steps)), flush=True)
@@ -314,6 +315,8 @@ def main():
         line["hbm_workload"] = bench_hbm(torch, qbe, ctx, 5)
         log("[bench] 7x7 d24 per-step, split-BF16 ...")
         line["hbm_workload_bf16x3"] = bench_hbm(torch, qbe, ctx, 5, "bf16x3")
+        log("[bench] 7x7 d24 per-step, three-part split-BF16 ...")
+        line["hbm_workload_bf16x6"] = bench_hbm(torch, qbe, ctx, 5, "bf16x6")
         log("[bench] batch of 512 ...")
         line["batch_workload"] = bench_batch(torch, qbe, ctx, 20)
         log("[bench] learned proposal ...")

@@ -36,7 +36,7 @@ QBE_OK = 0
 ERRORS = {-1: "INVALID_ARG", -2: "OOM", -3: "HIP", -4: "MEM_CAP", -5: "INTERNAL", -6: "NO_DEVICE"}
 SCORE = {"tree_trimming": 0, "degree": 1, "tw_reduction": 2}
 EXEC = {"auto": 0, "per_step": 1, "fused": 2}
-PREC = {"fp32": 0, "bf16x3": 1}
+PREC = {"fp32": 0, "bf16x3": 1, "bf16x6": 2}
 
 _i32p = C.POINTER(C.c_int32)
 _f64p = C.POINTER(C.c_double)

@@ -305,7 +305,7 @@ int qbe_plan_create(qbe_ctx* ctx, const qbe_model* model, const int32_t* reduced
   if (opts) o = *opts;
   for (int r : o.reserved) QBE_REQUIRE(r == 0, "reserved option fields must be zero");
   QBE_REQUIRE(o.exec >= QBE_EXEC_AUTO && o.exec <= QBE_EXEC_FUSED, "bad exec form");
-  QBE_REQUIRE(o.precision == QBE_PREC_FP32 || o.precision == QBE_PREC_BF16X3, "bad precision");
+  QBE_REQUIRE(o.precision >= QBE_PREC_FP32 && o.precision <= QBE_PREC_BF16X6, "bad precision");
   QBE_REQUIRE(o.block == 0 || o.block == qbe::kBlock, "unsupported block size");
   auto* pl = new qbe_plan;
   std::unique_ptr<qbe_plan> guard(pl);
@@ -315,7 +315,7 @@ int qbe_plan_create(qbe_ctx* ctx, const qbe_model* model, const int32_t* reduced
   p.cost = qbe::schedule_cost(p.sched);
   p.precision = o.precision;
   qbe::compile_plan(p);
-  if (o.exec == QBE_EXEC_FUSED && o.precision == QBE_PREC_BF16X3) {
+  if (o.exec == QBE_EXEC_FUSED && o.precision != QBE_PREC_FP32) {
     set_error("the fused form computes in FP32 only");
     return QBE_ERR_INVALID_ARG;
   }
@@ -324,7 +324,7 @@ int qbe_plan_create(qbe_ctx* ctx, const qbe_model* model, const int32_t* reduced
     return QBE_ERR_MEM_CAP;
   }
   p.exec = (o.exec == QBE_EXEC_PER_STEP || !p.fused_ok) ? QBE_EXEC_PER_STEP : QBE_EXEC_FUSED;
-  if (p.precision == QBE_PREC_BF16X3 && p.exec == QBE_EXEC_FUSED && o.exec == QBE_EXEC_AUTO)
+  if (p.precision != QBE_PREC_FP32 && p.exec == QBE_EXEC_FUSED && o.exec == QBE_EXEC_AUTO)
     p.exec = QBE_EXEC_PER_STEP;
   std::string bad = qbe::check_plan(p);
   if (!bad.empty()) {

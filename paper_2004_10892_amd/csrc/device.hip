@@ -171,10 +171,13 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch a) {
 // Real K = 4 stacks (Re, Im) x (u = 0, 1):
 //   Re R = [Re A0, Re A1, -Im A0, -Im A1] . [Re B0; Re B1; Im B0; Im B1]
 //   Im R = [Re A0, Re A1,  Im A0,  Im A1] . [Im B0; Im B1; Re B0; Re B1]
-// FP32 form: v_mfma_f32_16x16x4f32.  Split-BF16 form: each real entry is
-// split into hi + lo bfloat16 parts and one v_mfma_f32_16x16x16bf16 sums
-// hi*hi + hi*lo + lo*hi over K = 16 = [hi | hi | lo | 0] . [hi ; lo ; hi ; 0],
-// accumulating in FP32.
+// FP32 form: v_mfma_f32_16x16x4f32.  Split-BF16 forms (bfloat16 parts,
+// v_mfma_f32_16x16x16bf16 over K = 16 = four groups of the four real-K
+// entries, FP32 accumulation):
+//   bf16x3: x = hi + lo; one MFMA sums hi*hi + hi*lo + lo*hi as
+//           [hi | hi | lo | 0] . [hi ; lo ; hi ; 0]
+//   bf16x6: x = h + m + l; two MFMAs sum h*h + h*m + m*h + h*l + l*h + m*m
+//           as [h | h | m | h] . [h ; m ; h ; l] + [l | m | 0 | 0] . [h ; m ; 0 ; 0]
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef short shortx4 __attribute__((ext_vector_type(4)));
@@ -214,7 +217,15 @@ struct MmLaunch {
   int64_t s0, G, n_tiles;
 };
 
-template <bool kBf16>
+// bfloat16 parts of x: the first two (h, x - h) or all three (h, m, l).
+__device__ __forceinline__ void split_bf16(float x, uint32_t& h, uint32_t& m, uint32_t& l) {
+  h = bf16_bits(x);
+  const float r1 = x - bf16_value(h);  // exact in FP32
+  m = bf16_bits(r1);
+  l = bf16_bits(r1 - bf16_value(m));  // exact in FP32
+}
+
+template <int kPrec>
 __global__ __launch_bounds__(kBlock) void mm_kernel(MmLaunch a) {
   const int lane = threadIdx.x & 63;
   const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
@@ -247,7 +258,7 @@ __global__ __launch_bounds__(kBlock) void mm_kernel(MmLaunch a) {
       A1 = cmul(A1, a.usrc[j][ub + 1]);
     }
     floatx4 cre = {0.f, 0.f, 0.f, 0.f}, cim = {0.f, 0.f, 0.f, 0.f};
-    if (!kBf16) {
+    if (kPrec == QBE_PREC_FP32) {
       // lane holds real-K entry k = grp of its row (A) and of its column (B)
       const float2 Av = (grp & 1) ? A1 : A0;
       const float2 Bv = (grp & 1) ? B1 : B0;
@@ -257,28 +268,39 @@ __global__ __launch_bounds__(kBlock) void mm_kernel(MmLaunch a) {
       cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, b2, cim, 0, 0, 0);
     } else {
       // lane holds the four real-K entries of its row / column, as the part
-      // its group stands for (A: hi, hi, lo, 0; B: hi, lo, hi, 0)
+      // its group stands for in the layouts above
       const float ra1[4] = {A0.x, A1.x, -A0.y, -A1.y}, ra2[4] = {A0.x, A1.x, A0.y, A1.y};
       const float rb1[4] = {B0.x, B1.x, B0.y, B1.y}, rb2[4] = {B0.y, B1.y, B0.x, B1.x};
-      shortx4 pa1, pa2, pb1, pb2;
+      shortx4 pa1, pa2, pb1, pb2, qa1, qa2, qb1, qb2;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        uint32_t h, w;
-        h = bf16_bits(ra1[v]);
-        w = grp == 2 ? bf16_bits(ra1[v] - bf16_value(h)) : h;
-        pa1[v] = (short)(grp == 3 ? 0u : w);
-        h = bf16_bits(ra2[v]);
-        w = grp == 2 ? bf16_bits(ra2[v] - bf16_value(h)) : h;
-        pa2[v] = (short)(grp == 3 ? 0u : w);
-        h = bf16_bits(rb1[v]);
-        w = grp == 1 ? bf16_bits(rb1[v] - bf16_value(h)) : h;
-        pb1[v] = (short)(grp == 3 ? 0u : w);
-        h = bf16_bits(rb2[v]);
-        w = grp == 1 ? bf16_bits(rb2[v] - bf16_value(h)) : h;
-        pb2[v] = (short)(grp == 3 ? 0u : w);
+        uint32_t ha1, ma1, la1, ha2, ma2, la2, hb1, mb1, lb1, hb2, mb2, lb2;
+        split_bf16(ra1[v], ha1, ma1, la1);
+        split_bf16(ra2[v], ha2, ma2, la2);
+        split_bf16(rb1[v], hb1, mb1, lb1);
+        split_bf16(rb2[v], hb2, mb2, lb2);
+        if (kPrec == QBE_PREC_BF16X3) {
+          pa1[v] = (short)(grp == 3 ? 0u : grp == 2 ? ma1 : ha1);
+          pa2[v] = (short)(grp == 3 ? 0u : grp == 2 ? ma2 : ha2);
+          pb1[v] = (short)(grp == 3 ? 0u : grp == 1 ? mb1 : hb1);
+          pb2[v] = (short)(grp == 3 ? 0u : grp == 1 ? mb2 : hb2);
+        } else {
+          pa1[v] = (short)(grp == 2 ? ma1 : ha1);
+          pa2[v] = (short)(grp == 2 ? ma2 : ha2);
+          pb1[v] = (short)(grp == 1 ? mb1 : grp == 3 ? lb1 : hb1);
+          pb2[v] = (short)(grp == 1 ? mb2 : grp == 3 ? lb2 : hb2);
+          qa1[v] = (short)(grp == 0 ? la1 : grp == 1 ? ma1 : 0u);
+          qa2[v] = (short)(grp == 0 ? la2 : grp == 1 ? ma2 : 0u);
+          qb1[v] = (short)(grp == 0 ? hb1 : grp == 1 ? mb1 : 0u);
+          qb2[v] = (short)(grp == 0 ? hb2 : grp == 1 ? mb2 : 0u);
+        }
       }
       cre = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(pa1, pb1, cre, 0, 0, 0);
       cim = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(pa2, pb2, cim, 0, 0, 0);
+      if (kPrec == QBE_PREC_BF16X6) {
+        cre = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(qa1, qb1, cre, 0, 0, 0);
+        cim = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(qa2, qb2, cim, 0, 0, 0);
+      }
     }
     const int64_t ob = (g << r) | xt;
 #pragma unroll
@@ -985,9 +1007,11 @@ static int launch_step(const Plan& p, const StepProg& sp, float2* arena, int64_t
     const int64_t want = (m.n_tiles + 3) / 4;
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)n_cus() * wg_per_cu));
     if (p.precision == QBE_PREC_BF16X3)
-      mm_kernel<true><<<grid, kBlock, 0, st>>>(m);
+      mm_kernel<QBE_PREC_BF16X3><<<grid, kBlock, 0, st>>>(m);
+    else if (p.precision == QBE_PREC_BF16X6)
+      mm_kernel<QBE_PREC_BF16X6><<<grid, kBlock, 0, st>>>(m);
     else
-      mm_kernel<false><<<grid, kBlock, 0, st>>>(m);
+      mm_kernel<QBE_PREC_FP32><<<grid, kBlock, 0, st>>>(m);
     QBE_HIP(hipGetLastError());
     return QBE_OK;
   }
