@@ -26,10 +26,25 @@ METRIC = "amplitudes/sec + MFMA util, chosen vs plain FP32 form at rel err ≤1e
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 SEEDS = {"grid4x4_d10_m0": 0, "grid5x5_d16_m6": 1, "grid7x7_d24_m10": 0}
+# Memory traffic of one headline fused_kernel launch from the FETCH_SIZE and
+# WRITE_SIZE counter runs in profiles/fused_kernel_grid5x5_d16_m6.md (542.46
+# KiB x 2.000 + 4.06 KiB x 1.000, the factors from a 256 MiB device copy),
+# valid while the device source has the digest it was measured on.
+FUSED_TRAFFIC = {"bytes": int(round((542.46 * 2.000 + 4.0625 * 1.000) * 1024)),
+                 "device_sha256": "6f71393115310b5771febedc7bd6b6145e2137c58a4ce0ba1fe31899595356ac"}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def fused_traffic():
+    """Counter-measured bytes per fused_kernel launch, or None once the device
+    source differs from the one the counters were taken on."""
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2004_10892_amd", "csrc", "device.hip"), "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()
+    return FUSED_TRAFFIC["bytes"] if digest == FUSED_TRAFFIC["device_sha256"] else None
 
 
 def golden(name):
@@ -229,6 +244,9 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the 7x7 and batch lines")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only", choices=["hbm", "batch", "learned"], help="run just one extra workload")
+    ap.add_argument("--pmc-workload", action="store_true",
+                    help="for hardware-counter runs: a device-to-device copy of 256 MiB (three times, the "
+                         "calibration of the byte counters) and 20 launches of the headline fused kernel")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: the contraction runs on a single MI355X "
@@ -243,6 +261,20 @@ def main():
     name = "grid5x5_d16_m6"
     ctx = qbe.Context(0)
     want = golden(name)
+    if args.pmc_workload:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        plan, _, _ = build_plan(qbe, ctx, name, "fused")
+        ws = plan.workspace()
+        out = torch.zeros(2, dtype=torch.float64, device="cuda")
+        for _ in range(20):
+            qbe.qbe_contract_async(ctx, plan, ws, out)
+        torch.cuda.synchronize()
+        got = complex(*out.cpu().numpy())
+        log(f"[bench] pmc workload done, rel err {abs(got - want) / abs(want):.2e}")
+        return
     if args.only == "hbm":
         print(json.dumps(bench_hbm(torch, qbe, ctx, args.steps)), flush=True)
         print(json.dumps(bench_hbm(torch, qbe, ctx, args.steps, "bf16x3")), flush=True)
@@ -302,10 +334,11 @@ def main():
                        "launches_per_step": st["n_steps"] + 2},
         "speedup_vs_plain": ev_p / ev,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": fused_traffic(),
                      "kernel": "fused_kernel", "algorithmic_flops_per_launch": flops_launch,
                      "note": "LDS-resident: every operand and intermediate stays on chip; the step is "
-                             "bounded by the chain of dependent bucket levels, not by HBM"},
+                             "bounded by the chain of dependent bucket levels, not by HBM; traffic: bytes "
+                             "per launch from the FETCH_SIZE and WRITE_SIZE counters"},
     }
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle) ...")
