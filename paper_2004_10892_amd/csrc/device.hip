@@ -754,19 +754,26 @@ __global__ __launch_bounds__(kFusedBlock) __attribute__((amdgpu_waves_per_eu(1, 
         re = nr;
       }
       if (tid == 0) {
-        a.out[item] = make_double2(re, im);
         s_flag = 0u;
         if (a.reduce_here) {
-          // publish the value and count it (release); the plan's last item
-          // sums them all (acquire)
+          // publish the value (device-scope atomic stores, which leave the
+          // writeback of the release nothing to flush) and count it with a
+          // release; only the plan's last item acquires, then sums them all
           int64_t b = 0, e = a.n_items;
           if (a.ranges) {
             b = a.ranges[2 * plan];
             e = a.ranges[2 * plan + 1];
           }
+          __hip_atomic_store(&a.out[item].x, re, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&a.out[item].y, im, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           const uint32_t done =
-              __hip_atomic_fetch_add(&a.state[2 + plan], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
-          if ((int64_t)done == e - b) s_flag = 1u;
+              __hip_atomic_fetch_add(&a.state[2 + plan], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+          if ((int64_t)done == e - b) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            s_flag = 1u;
+          }
+        } else {
+          a.out[item] = make_double2(re, im);
         }
       }
     }
@@ -775,7 +782,8 @@ __global__ __launch_bounds__(kFusedBlock) __attribute__((amdgpu_waves_per_eu(1, 
       // last item of this plan: fixed-order FP64 sum of its items (same order
       // as reduce_kernel), then re-arm the plan's counter for the next launch.
       // The scratch overwrites LDS; no item of this plan remains.  The values
-      // are visible: thread 0's acquire on the counter, then the barrier.
+      // are visible: every item's release on the counter, thread 0's acquire
+      // fence after reading its last value, then the barrier.
       int64_t b = 0, e = a.n_items;
       if (a.ranges) {
         b = a.ranges[2 * plan];
