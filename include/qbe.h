@@ -99,6 +99,10 @@ typedef struct qbe_stats {
   int32_t n_mfma_steps;                /* per-step form: outer-product buckets
                                           run as MFMA tiles                   */
   int32_t precision;                   /* QBE_PREC_* of the plan             */
+  int32_t fused_levels;                /* fused form: levels of its program
+                                          (buckets merged along chains; 0 if
+                                          the plan has no fused program)     */
+  int32_t reserved;                    /* 0                                  */
 } qbe_stats;
 
 /* ------------------------------------------------------------------ misc -- */

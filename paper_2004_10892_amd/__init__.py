@@ -60,7 +60,8 @@ class Stats(C.Structure):
                 ("n_steps", C.c_int32), ("n_levels", C.c_int32), ("exec", C.c_int32), ("lds_bytes", C.c_int32),
                 ("flops_per_slice", C.c_uint64), ("bytes_per_slice", C.c_uint64),
                 ("peak_bytes_per_slice", C.c_uint64), ("ws_bytes_min", C.c_uint64),
-                ("ws_bytes_all_slices", C.c_uint64), ("n_mfma_steps", C.c_int32), ("precision", C.c_int32)]
+                ("ws_bytes_all_slices", C.c_uint64), ("n_mfma_steps", C.c_int32), ("precision", C.c_int32),
+                ("fused_levels", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

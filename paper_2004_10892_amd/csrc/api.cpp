@@ -394,6 +394,8 @@ int qbe_plan_stats(const qbe_plan* plan, qbe_stats* out) {
   for (const auto& sp : p.steps)
     if (sp.mm_a >= 0) ++out->n_mfma_steps;
   out->precision = p.precision;
+  out->fused_levels = p.fused_ok ? p.fused_levels : 0;
+  out->reserved = 0;
   return QBE_OK;
   QBE_GUARD_END
 }

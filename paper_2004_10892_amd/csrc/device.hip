@@ -411,8 +411,6 @@ static FusedMeta fused_meta(const Plan& p) {
                    w[FH_FREE], w[FH_INV_ELEMS], w[FH_DEP_ELEMS], w[FH_DEP_SRC], w[FH_BYTE_OFFSETS], 0};
 }
 
-// Threads of a fused workgroup.
-constexpr int kFusedBlock = kBlock;
 // LDS bytes after the data for the workgroup's control words.
 constexpr int kFusedCtlBytes = 16;
 // Record rows (16-byte groups of words) a lane reads per level, two levels
@@ -465,15 +463,15 @@ __device__ __forceinline__ void load_rec(gu32p prog, uint32_t w, Rec& c) {
   for (int i = 0; i < kRecRows; ++i) c.r[i] = q[i];
 }
 
-// Levels with 2E <= kFusedBlock give each half-record (one value of u) its
-// own lane; larger ones give each lane a whole record.
-__device__ __forceinline__ bool split_level(uint32_t E) { return 2 * E <= (uint32_t)kFusedBlock; }
+// Levels whose E entries x 2^lgT terms fit the workgroup give each term
+// record its own lane; larger ones (two terms only) give each lane both.
+__device__ __forceinline__ bool split_level(uint32_t E, uint32_t lgT) { return (E << lgT) <= (uint32_t)kFusedBlock; }
 
-// First word this lane reads for a level (base, E, R); lanes past the
+// First word this lane reads for a level (base, E, R, lgT); lanes past the
 // level's end read its last record, so that every lane reads valid words.
-__device__ __forceinline__ uint32_t rec_word(uint32_t base, uint32_t E, uint32_t R, uint32_t tid) {
+__device__ __forceinline__ uint32_t rec_word(uint32_t base, uint32_t E, uint32_t R, uint32_t lgT, uint32_t tid) {
   if (E == 0) return base;
-  return split_level(E) ? base + min(tid, 2 * E - 1) * 4 * R : base + min(tid, E - 1) * 8 * R;
+  return split_level(E, lgT) ? base + min(tid, (E << lgT) - 1) * 4 * R : base + min(tid, E - 1) * 8 * R;
 }
 
 // The fused kernel has no static LDS, so its dynamic LDS (the tensor
@@ -510,24 +508,29 @@ __device__ __forceinline__ float2 tree_prod(float2 (&v)[N]) {
   return v[0];
 }
 
-// The value of lane tid ^ 1 (a DPP quad permutation [1, 0, 3, 2]).
-__device__ __forceinline__ float swap_pair(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, false));
+// Sum of a value over lane groups by DPP: pairs (quad permutation
+// [1, 0, 3, 2]), quads ([2, 3, 0, 1]) and eights (half-row mirror).
+template <int kCtrl>
+__device__ __forceinline__ float2 dpp_add(float2 v) {
+  const float x = __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v.x), kCtrl, 0xF, 0xF, false));
+  const float y = __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v.y), kCtrl, 0xF, 0xF, false));
+  return make_float2(v.x + x, v.y + y);
 }
 
-// Split level: lane tid holds half-record tid (u = tid & 1 of record
-// tid >> 1); the even lane of each pair adds its partner's product and
-// writes the result.  Every lane runs the same code (the DPP partner must
+// Split level: lane tid holds term record tid (term tid & (T - 1) of entry
+// tid >> lgT); the T lanes of an entry add their products and the first
+// writes the result.  Every lane runs the same code (the DPP partners must
 // be active); only the writes are guarded.
 template <int K, bool kBytes>
-__device__ __forceinline__ void level_split(const Rec& c, uint32_t E, uint32_t tid) {
+__device__ __forceinline__ void level_split(const Rec& c, uint32_t E, uint32_t lgT, uint32_t tid) {
   float2 v[K];
 #pragma unroll
   for (int i = 0; i < K; ++i) v[i] = lds_entry(rec_slot<kBytes>(c, 0, 1 + i));
   __builtin_amdgcn_sched_barrier(0);  // every read in flight before the first product
-  const float2 p = tree_prod<K>(v);
-  const float2 q = make_float2(swap_pair(p.x), swap_pair(p.y));
-  if ((tid & 1u) == 0 && tid < 2 * E) lds_store(rec_slot<kBytes>(c, 0, 0), cadd(p, q));
+  float2 p = dpp_add<0xB1>(tree_prod<K>(v));
+  if (lgT >= 2) p = dpp_add<0x4E>(p);
+  if (lgT >= 3) p = dpp_add<0x141>(p);
+  if ((tid & ((1u << lgT) - 1)) == 0 && tid < (E << lgT)) lds_store(rec_slot<kBytes>(c, 0, 0), p);
 }
 
 // Whole-record level (half-records of one row): lane tid holds record tid;
@@ -555,39 +558,44 @@ __device__ __forceinline__ void level_whole(gu32p prog, const Rec& c, uint32_t b
   }
 }
 
-// Records larger than a lane's registers hold: slot by slot from memory.
+// Records larger than a lane's registers hold: slot by slot from memory,
+// all terms of an entry in one lane.
 template <bool kBytes>
-__device__ __forceinline__ void level_long(gu32p prog, uint32_t base, uint32_t E, uint32_t R, uint32_t K,
-                                           uint32_t tid) {
+__device__ __forceinline__ void level_long(gu32p prog, uint32_t base, uint32_t E, uint32_t R, uint32_t lgT,
+                                           uint32_t K, uint32_t tid) {
   for (uint32_t f = tid; f < E; f += kFusedBlock) {
-    const gu32p rec = prog + base + f * 8 * R;
-    float2 a0 = make_float2(1.f, 0.f), a1 = a0;
-    for (uint32_t i = 1; i <= K; ++i) {
-      a0 = cmul(a0, lds_entry(slot<kBytes>(rec[i >> 1], i)));
-      a1 = cmul(a1, lds_entry(slot<kBytes>(rec[4 * R + (i >> 1)], i)));
+    const gu32p rec0 = prog + base + (f << lgT) * 4 * R;
+    float2 acc = make_float2(0.f, 0.f);
+    for (uint32_t t = 0; t < (1u << lgT); ++t) {
+      const gu32p rec = rec0 + t * 4 * R;
+      float2 a = make_float2(1.f, 0.f);
+      for (uint32_t i = 1; i <= K; ++i) a = cmul(a, lds_entry(slot<kBytes>(rec[i >> 1], i)));
+      acc = cadd(acc, a);
     }
-    lds_store(slot<kBytes>(rec[0], 0), cadd(a0, a1));
+    lds_store(slot<kBytes>(rec0[0], 0), acc);
   }
 }
 
-// One level: t is its table entry (base, E, R, K) and c this lane's record
-// words, read two levels earlier; the records of the level two ahead (entry
-// tn) are read into pf here, before any of this level's work.
+// One level: t is its table entry (base, E, R | lgT << 16, K) and c this
+// lane's record words, read two levels earlier; the records of the level two
+// ahead (entry tn) are read into pf here, before any of this level's work.
 template <bool kBytes>
 __device__ __forceinline__ void level_step(gu32p prog, const u32x4& t, const u32x4& tn, const Rec& c, Rec& pf,
                                            uint32_t tid) {
-  load_rec(prog, rec_word(uni(tn.x), uni(tn.y), uni(tn.z), tid), pf);
-  const uint32_t base = uni(t.x), E = uni(t.y), R = uni(t.z), K = uni(t.w);
-  if (split_level(E) && K <= (uint32_t)kSplitOpsMax) {
+  const uint32_t ntz = uni(tn.z);
+  load_rec(prog, rec_word(uni(tn.x), uni(tn.y), ntz & 0xFFFFu, ntz >> 16, tid), pf);
+  const uint32_t base = uni(t.x), E = uni(t.y), tz = uni(t.z), K = uni(t.w);
+  const uint32_t R = tz & 0xFFFFu, lgT = tz >> 16;
+  if (split_level(E, lgT) && K <= (uint32_t)kSplitOpsMax) {
     switch (K) {
 #define QBE_SPLIT(KK) \
-  case KK: level_split<KK, kBytes>(c, E, tid); break;
+  case KK: level_split<KK, kBytes>(c, E, lgT, tid); break;
       QBE_SPLIT(1) QBE_SPLIT(2) QBE_SPLIT(3) QBE_SPLIT(4) QBE_SPLIT(5) QBE_SPLIT(6) QBE_SPLIT(7) QBE_SPLIT(8)
       QBE_SPLIT(9) QBE_SPLIT(10) QBE_SPLIT(11) QBE_SPLIT(12) QBE_SPLIT(13) QBE_SPLIT(14) QBE_SPLIT(15)
 #undef QBE_SPLIT
       default: break;
     }
-  } else if (!split_level(E) && K <= (uint32_t)kWholeOpsMax) {
+  } else if (lgT == 1 && K <= (uint32_t)kWholeOpsMax) {
     switch (K) {
 #define QBE_WHOLE(KK) \
   case KK: level_whole<KK, kBytes>(prog, c, base, E, tid); break;
@@ -596,7 +604,7 @@ __device__ __forceinline__ void level_step(gu32p prog, const u32x4& t, const u32
       default: break;
     }
   } else {
-    level_long<kBytes>(prog, base, E, R, K, tid);
+    level_long<kBytes>(prog, base, E, R, lgT, K, tid);
   }
 }
 
@@ -717,17 +725,20 @@ __global__ __launch_bounds__(kFusedBlock) __attribute__((amdgpu_waves_per_eu(1, 
     typedef __attribute__((address_space(3))) u32x4* lds_u32x4p;
     const lds_u32x4p lv = (lds_u32x4p)(size_t)mt.lds_tab;  // the LDS copy
     Rec ra, rb;
-    load_rec(prog, rec_word(uni(t0.x), uni(t0.y), uni(t0.z), tid), ra);
-    load_rec(prog, rec_word(uni(t1.x), uni(t1.y), uni(t1.z), tid), rb);
-    // inputs of this slice into LDS, the constant 1 at offset 0
+    load_rec(prog, rec_word(uni(t0.x), uni(t0.y), uni(t0.z) & 0xFFFFu, uni(t0.z) >> 16, tid), ra);
+    load_rec(prog, rec_word(uni(t1.x), uni(t1.y), uni(t1.z) & 0xFFFFu, uni(t1.z) >> 16, tid), rb);
+    // inputs of this slice into LDS after the constants 1 and 0
     const uint32_t inv = mt.inv, dep = mt.dep;
     const float2* dsrc = prep + mt.dep_src + slice * (int64_t)dep;
-    if (tid == 0) data[0] = make_float2(1.f, 0.f);
+    if (tid == 0) {
+      data[0] = make_float2(1.f, 0.f);
+      data[kFusedZero] = make_float2(0.f, 0.f);
+    }
     // the scalar factors' offsets (lane j < 64: factor j), read now for the end
     const uint32_t n_scal = mt.scalars;
     const uint32_t scal0 = tid < n_scal && tid < 64 ? prog[mt.scalar_off + tid] : 0u;
-    fill_lds<4>(reinterpret_cast<uint64_t*>(data + 1), reinterpret_cast<const uint64_t*>(prep), inv,
-                reinterpret_cast<uint64_t*>(data + 1 + inv), reinterpret_cast<const uint64_t*>(dsrc), dep,
+    fill_lds<4>(reinterpret_cast<uint64_t*>(data + kFusedConsts), reinterpret_cast<const uint64_t*>(prep), inv,
+                reinterpret_cast<uint64_t*>(data + kFusedConsts + inv), reinterpret_cast<const uint64_t*>(dsrc), dep,
                 reinterpret_cast<u32x4*>(reinterpret_cast<char*>(lds4) + mt.lds_tab),
                 reinterpret_cast<const u32x4*>(gprog + kHdr), mt.levels + kFusedLevelPad, tid);
     __syncthreads();

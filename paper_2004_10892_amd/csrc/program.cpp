@@ -94,6 +94,120 @@ int64_t raw_index(const Model& md, int t, F&& value_of) {
   return md.data_off[t] + idx;
 }
 
+// A node of the fused program: a root bucket (members[0]) and the buckets it
+// absorbed.  One record per entry of the root's result sums over the
+// eliminated variables of all members (2^|members| terms); a term multiplies
+// the members' operands other than the absorbed members' results.  Every
+// member's variable occurs only in its own bucket's operands, and an
+// absorbed member's other variables are all in the root's union, so each
+// factor is indexed by the root's result variables and the summed ones.
+struct FusedNode {
+  std::vector<int> members;      // root first, then absorbed buckets
+  std::vector<Operand> factors;  // operands of the members except absorbed results
+  std::vector<int> kids;         // buckets (node roots) whose results it reads
+  int level = 0;                 // dependency depth among nodes
+};
+
+// Fused form: merges buckets along the dependency tree to shorten the chain
+// of levels.  A bucket absorbs its producer when that producer is its only
+// deepest input, the merged record stays within kMergeTermsLog2 summed
+// variables and kMergeFactors factors, no level deepens, and every level
+// with more than two terms per entry still gives each term its own lane.
+constexpr int kMergeTermsLog2 = 3;
+constexpr int kMergeFactors = 15;
+
+std::vector<FusedNode> merge_buckets(const Schedule& s) {
+  const int n = (int)s.steps.size();
+  std::vector<std::vector<int>> kids(n), members(n);
+  std::vector<int> F(n), lgT(n, 1), lv(n, 0);
+  std::vector<int64_t> E(n);
+  std::vector<char> alive(n, 1);
+  for (int k = 0; k < n; ++k) {
+    for (const auto& op : s.steps[k].ops)
+      if (op.kind == 'r') kids[k].push_back(op.id);
+    members[k] = {k};
+    F[k] = (int)s.steps[k].ops.size();
+    E[k] = int64_t(1) << s.steps[k].out.size();
+  }
+  auto levels = [&]() {  // steps are in dependency order
+    int depth = 0;
+    for (int k = 0; k < n; ++k)
+      if (alive[k]) {
+        int l = 0;
+        for (int c : kids[k]) l = std::max(l, lv[c] + 1);
+        lv[k] = l;
+        depth = std::max(depth, l + 1);
+      }
+    return depth;
+  };
+  auto fits = [&](int depth) {
+    std::vector<int64_t> el(depth, 0);
+    std::vector<int> tl(depth, 1);
+    for (int k = 0; k < n; ++k)
+      if (alive[k]) {
+        el[lv[k]] += E[k];
+        tl[lv[k]] = std::max(tl[lv[k]], lgT[k]);
+      }
+    for (int l = 0; l < depth; ++l)
+      if (tl[l] > 1 && (el[l] << tl[l]) > kFusedBlock) return false;
+    return true;
+  };
+  int depth = levels();
+  for (bool merged = true; merged;) {
+    merged = false;
+    std::vector<int> order;
+    for (int k = 0; k < n; ++k)
+      if (alive[k]) order.push_back(k);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return lv[a] > lv[b]; });
+    for (int c : order) {
+      int top = -1, k = -1, ntop = 0;
+      for (int x : kids[c]) {
+        if (lv[x] > top) {
+          top = lv[x];
+          k = x;
+          ntop = 1;
+        } else if (lv[x] == top) {
+          ++ntop;
+        }
+      }
+      if (ntop != 1 || lgT[c] + lgT[k] > kMergeTermsLog2 || F[c] + F[k] - 1 > kMergeFactors) continue;
+      const std::vector<int> kids_c = kids[c], lv_c = lv;
+      kids[c].erase(std::find(kids[c].begin(), kids[c].end(), k));
+      kids[c].insert(kids[c].end(), kids[k].begin(), kids[k].end());
+      lgT[c] += lgT[k];
+      F[c] += F[k] - 1;
+      alive[k] = 0;
+      const int d2 = levels();
+      if (d2 <= depth && fits(d2)) {
+        members[c].insert(members[c].end(), members[k].begin(), members[k].end());
+        depth = d2;
+        merged = true;
+        break;
+      }
+      kids[c] = kids_c;
+      lgT[c] -= lgT[k];
+      F[c] -= F[k] - 1;
+      alive[k] = 1;
+      lv = lv_c;
+    }
+  }
+  std::vector<FusedNode> nodes;
+  for (int k = 0; k < n; ++k) {
+    if (!alive[k]) continue;
+    FusedNode nd;
+    nd.members = members[k];
+    for (int m : nd.members)
+      for (const auto& op : s.steps[m].ops)
+        if (!(op.kind == 'r' && std::find(nd.members.begin(), nd.members.end(), op.id) != nd.members.end()))
+          nd.factors.push_back(op);
+    if ((int)nd.factors.size() != F[k]) throw std::logic_error("fused node factor count");
+    nd.kids = kids[k];
+    nd.level = lv[k];
+    nodes.push_back(std::move(nd));
+  }
+  return nodes;
+}
+
 }  // namespace
 
 void compile_plan(Plan& p) {
@@ -284,95 +398,108 @@ void compile_plan(Plan& p) {
   p.fused_map.clear();
   p.fused_elems = 0;
   p.fused_lds_bytes = 0;
+  p.fused_levels = 0;
   bool eligible = p.m <= 24;
   for (const auto& st : s.steps)
     if (st.uni.size() > 15) eligible = false;
   if (eligible) {
-    // LDS element offsets of the inputs (after the constant 1 at 0)
+    // LDS element offsets of the inputs (after the constants 1 and 0)
     std::vector<int64_t> lds_in(nt, -1);
     int64_t inv = 0, dep = 0;
     for (int t = 0; t < nt; ++t)
       if (in[t].smask == 0) {
-        lds_in[t] = 1 + inv;
+        lds_in[t] = kFusedConsts + inv;
         inv += int64_t(1) << in[t].canon.size();
       }
     for (int t = 0; t < nt; ++t)
       if (in[t].smask != 0) {
-        lds_in[t] = 1 + inv + dep;
+        lds_in[t] = kFusedConsts + inv + dep;
         dep += int64_t(1) << in[t].canon.size();
       }
+    // merged nodes (each writes its root bucket's result) and their levels
+    const std::vector<FusedNode> nodes = merge_buckets(s);
+    int f_levels = 0;
+    for (const FusedNode& nd : nodes) f_levels = std::max(f_levels, nd.level + 1);
+    std::vector<std::vector<int>> by_level(f_levels);
+    for (int i = 0; i < (int)nodes.size(); ++i) by_level[nodes[i].level].push_back(i);
     // arena by levels: all results of a level are live while the level runs
-    std::vector<std::vector<int>> by_level(n_levels);
-    for (int k = 0; k < nsteps; ++k) by_level[level[k]].push_back(k);
     Arena la;
     std::vector<int64_t> lds_out(nsteps, -1);
-    for (int l = 0; l < n_levels; ++l) {
-      for (int k : by_level[l]) {
-        int64_t sz = int64_t(1) << s.steps[k].out.size();
-        lds_out[k] = la.alloc(sz, 1);
+    for (int l = 0; l < f_levels; ++l) {
+      for (int i : by_level[l]) {
+        const int c = nodes[i].members[0];
+        lds_out[c] = la.alloc(int64_t(1) << s.steps[c].out.size(), 1);
       }
-      for (int k : by_level[l])
-        for (const auto& op : s.steps[k].ops)
-          if (op.kind == 'r') la.release(lds_out[op.id], int64_t(1) << op.vars.size());
+      for (int i : by_level[l])
+        for (int kid : nodes[i].kids) la.release(lds_out[kid], int64_t(1) << s.steps[kid].out.size());
     }
-    const int64_t arena0 = 1 + inv + dep;
+    const int64_t arena0 = kFusedConsts + inv + dep;
     const int64_t data_elems = arena0 + la.top;
     // LDS: the tensor entries, then a copy of the level table
-    const int64_t lds_bytes = std::max<int64_t>(fused_table_lds(data_elems) + 16 * ((int64_t)n_levels + kFusedLevelPad),
+    const int64_t lds_bytes = std::max<int64_t>(fused_table_lds(data_elems) + 16 * ((int64_t)f_levels + kFusedLevelPad),
                                                 256 * 16);
     const int64_t prep_elems = inv + dep * p.n_slices;
     if (lds_bytes <= kFusedLdsMax && prep_elems < (int64_t(1) << 31)) {
       std::vector<uint32_t> prog(kHdr, 0);
       const size_t lvl_at = prog.size();
       // zero entries after the last level end the executor's look-ahead
-      prog.resize(lvl_at + 4 * ((size_t)n_levels + kFusedLevelPad), 0);
+      prog.resize(lvl_at + 4 * ((size_t)f_levels + kFusedLevelPad), 0);
       while (prog.size() % 4) prog.push_back(0);
       // 16-bit operand offsets: bytes when the data fit 64 KB, else elements
       const bool bytes = data_elems * 8 <= 65536;
       const uint32_t unit = bytes ? 8u : 1u;
-      for (int l = 0; l < n_levels; ++l) {
-        uint32_t K = 1;
+      std::vector<int> val(md.n_vars, -1);  // variable values of the record being written
+      for (int l = 0; l < f_levels; ++l) {
+        uint32_t F = 1, T = 2;
         int64_t E = 0;
-        for (int k : by_level[l]) {
-          K = std::max<uint32_t>(K, (uint32_t)s.steps[k].ops.size());
-          E += int64_t(1) << s.steps[k].out.size();
+        for (int i : by_level[l]) {
+          F = std::max<uint32_t>(F, (uint32_t)nodes[i].factors.size());
+          T = std::max<uint32_t>(T, 2u << (nodes[i].members.size() - 1));
+          E += int64_t(1) << s.steps[nodes[i].members[0]].out.size();
         }
-        const uint32_t R = (1 + K + 7) / 8;  // 16-byte rows of a half-record
+        const uint32_t R = (1 + F + 7) / 8;  // 16-byte rows of a term record
         prog[lvl_at + 4 * l + 0] = (uint32_t)prog.size();
         prog[lvl_at + 4 * l + 1] = (uint32_t)E;
-        prog[lvl_at + 4 * l + 2] = R;
-        prog[lvl_at + 4 * l + 3] = K;
-        for (int k : by_level[l]) {
-          const Step& st = s.steps[k];
-          const int r = (int)st.out.size();
-          // operand LDS offsets, masks and u-strides
-          std::vector<uint32_t> off, mk, up;
-          for (const auto& op : st.ops) {
-            const std::vector<int>& vars = op.kind == 't' ? in[op.id].canon : op.vars;
-            off.push_back((uint32_t)(op.kind == 't' ? lds_in[op.id] : arena0 + lds_out[op.id]));
-            const uint32_t m_ = union_mask(st.uni, vars);
-            mk.push_back(m_);
-            up.push_back(((m_ >> r) & 1u) ? (1u << (__builtin_popcount(m_) - 1)) : 0u);
-          }
+        prog[lvl_at + 4 * l + 2] = R | ((uint32_t)__builtin_ctz(T) << 16);
+        prog[lvl_at + 4 * l + 3] = F;
+        for (int i : by_level[l]) {
+          const FusedNode& nd = nodes[i];
+          const Step& root = s.steps[nd.members[0]];
+          const int r = (int)root.out.size();
+          const uint32_t Tn = 2u << (nd.members.size() - 1);
           for (uint32_t x = 0; x < (1u << r); ++x) {
-            // two half-records of 8R halfwords: [result, operand entries for
-            // u = 0] and [0, operand entries for u = 1]
-            const size_t at = prog.size();
-            prog.resize(at + 8 * R, 0);
-            auto put = [&](uint32_t half, uint32_t j, uint32_t v) {
-              prog[at + 4 * R * half + j / 2] |= (v * unit) << (16 * (j % 2));
-            };
-            put(0, 0, (uint32_t)(arena0 + lds_out[k] + x));
-            for (size_t i = 0; i < st.ops.size(); ++i) {
-              uint32_t e = 0, bit = 0;
-              for (uint32_t mm = mk[i]; mm; mm &= mm - 1, ++bit) e |= ((x >> __builtin_ctz(mm)) & 1u) << bit;
-              put(0, 1 + (uint32_t)i, off[i] + e);
-              put(1, 1 + (uint32_t)i, off[i] + e + up[i]);
+            // T term records of 8R halfwords: [result (term 0) or 0, the
+            // factors' entries for that assignment of the summed variables]
+            for (uint32_t t = 0; t < T; ++t) {
+              const size_t at = prog.size();
+              prog.resize(at + 4 * R, 0);
+              auto put = [&](uint32_t j, uint32_t v) { prog[at + j / 2] |= (v * unit) << (16 * (j % 2)); };
+              if (t == 0) put(0, (uint32_t)(arena0 + lds_out[nd.members[0]] + x));
+              if (t >= Tn) {
+                put(1, kFusedZero);  // padding term: a factor 0
+                continue;
+              }
+              for (int q = 0; q < r; ++q) val[root.out[q]] = (int)((x >> (r - 1 - q)) & 1);
+              for (size_t j = 0; j < nd.members.size(); ++j) val[s.steps[nd.members[j]].var] = (int)((t >> j) & 1);
+              for (size_t f = 0; f < nd.factors.size(); ++f) {
+                const Operand& op = nd.factors[f];
+                const std::vector<int>& vars = op.kind == 't' ? in[op.id].canon : op.vars;
+                uint32_t e = 0;
+                for (int v : vars) {
+                  if (val[v] < 0) throw std::logic_error("fused node factor outside its variables");
+                  e = (e << 1) | (uint32_t)val[v];
+                }
+                const int64_t base = op.kind == 't' ? lds_in[op.id] : arena0 + lds_out[op.id];
+                put(1 + (uint32_t)f, (uint32_t)(base + e));
+              }
+              for (int q = 0; q < r; ++q) val[root.out[q]] = -1;
+              for (size_t j = 0; j < nd.members.size(); ++j) val[s.steps[nd.members[j]].var] = -1;
             }
           }
         }
       }
       prog[FH_BYTE_OFFSETS] = bytes ? 1u : 0u;
+      p.fused_levels = f_levels;
       const uint32_t scal_at = (uint32_t)prog.size();
       uint32_t n_scal = 0;
       for (int t : s.scalar_inputs) {
@@ -386,7 +513,7 @@ void compile_plan(Plan& p) {
       while (prog.size() % 4) prog.push_back(0);
       prog.resize(prog.size() + 4 * kFusedTailRows, 0);  // the executor reads whole row groups
       prog[FH_WORDS] = (uint32_t)prog.size();
-      prog[FH_LEVELS] = (uint32_t)n_levels;
+      prog[FH_LEVELS] = (uint32_t)f_levels;
       prog[FH_SCALARS] = n_scal;
       prog[FH_SCALAR_OFF] = scal_at;
       prog[FH_FREE] = (uint32_t)s.free_vars.size();

@@ -85,7 +85,7 @@ std::string check_plan(const Plan& p) {
     if (p.fused_lds_bytes > kFusedLdsMax) return "fused LDS above budget";
     if (w[FH_DEP_SRC] != inv) return "fused dependent block offset";
     if ((int64_t)inv + (int64_t)dep * p.n_slices != p.fused_elems) return "fused prepared size";
-    if (1 + inv + dep > data) return "fused inputs above data size";
+    if (kFusedConsts + inv + dep > data) return "fused inputs above data size";
     if ((int64_t)kHdr + 4 * ((int64_t)nl + kFusedLevelPad) > (int64_t)w.size()) return "fused level table truncated";
     if ((int64_t)so + nsc > (int64_t)w.size()) return "fused scalar list truncated";
     const uint32_t* lv = w.data() + kHdr;
@@ -95,27 +95,33 @@ std::string check_plan(const Plan& p) {
     const bool bytes = w[FH_BYTE_OFFSETS] != 0;
     if (w[FH_BYTE_OFFSETS] > 1 || bytes != ((int64_t)data * 8 <= 65536)) return "fused offset unit";
     const uint32_t unit = bytes ? 8u : 1u;
-    const uint32_t arena_lo = (1 + inv + dep) * unit, data_hi = data * unit;
+    const uint32_t arena_lo = (kFusedConsts + inv + dep) * unit, data_hi = data * unit;
     if (data_hi > 65536) return "fused offsets above 16 bits";
     for (uint32_t l = 0; l < nl; ++l) {
-      const uint32_t base = lv[4 * l], E = lv[4 * l + 1], R = lv[4 * l + 2], K = lv[4 * l + 3];
+      const uint32_t base = lv[4 * l], E = lv[4 * l + 1], R = lv[4 * l + 2] & 0xFFFFu, lgT = lv[4 * l + 2] >> 16,
+                     K = lv[4 * l + 3];
       if (base != expect_base) return fail("fused record base", base, expect_base);
-      if (base % 4 || R != (1 + K + 7) / 8 || E == 0 || K == 0) return "fused level shape";
-      if ((int64_t)base + (int64_t)E * 8 * R > (int64_t)w.size()) return "fused records truncated";
-      for (uint32_t f = 0; f < E; ++f) {
-        const uint32_t* rec = w.data() + base + (size_t)f * 8 * R;
-        auto hw = [&](uint32_t half, uint32_t j) { return (rec[4 * R * half + j / 2] >> (16 * (j % 2))) & 0xFFFFu; };
-        const uint32_t out = hw(0, 0);
-        if (out % unit || out < arena_lo || out >= data_hi) return "fused result outside the arena";
-        if (hw(1, 0) != 0) return "fused second half's first slot not zero";
-        for (uint32_t u = 0; u < 2; ++u)
+      if (base % 4 || R != (1 + K + 7) / 8 || E == 0 || K == 0 || lgT < 1 || lgT > 3) return "fused level shape";
+      if (lgT > 1 && ((int64_t)E << lgT) > kFusedBlock) return "fused level of many terms above the workgroup";
+      const uint32_t T = 1u << lgT;
+      if ((int64_t)base + (int64_t)E * T * 4 * R > (int64_t)w.size()) return "fused records truncated";
+      for (uint32_t f = 0; f < E; ++f)
+        for (uint32_t t = 0; t < T; ++t) {
+          const uint32_t* rec = w.data() + base + ((size_t)f * T + t) * 4 * R;
+          auto hw = [&](uint32_t j) { return (rec[j / 2] >> (16 * (j % 2))) & 0xFFFFu; };
+          if (t == 0) {
+            const uint32_t out = hw(0);
+            if (out % unit || out < arena_lo || out >= data_hi) return "fused result outside the arena";
+          } else if (hw(0) != 0) {
+            return "fused term's result slot not zero";
+          }
           for (uint32_t j = 1; j < 8 * R; ++j) {
-            const uint32_t v = hw(u, j);
+            const uint32_t v = hw(j);
             if (v % unit || v >= data_hi) return "fused operand outside LDS data";
             if (j > K && v != 0) return "fused padding slot not the constant";
           }
-      }
-      expect_base += (int64_t)E * 8 * R;
+        }
+      expect_base += (int64_t)E * T * 4 * R;
     }
     if (expect_base != so) return "fused scalar list offset";
     if ((int64_t)(so + nsc + 3) / 4 * 4 + 4 * kFusedTailRows != (int64_t)w.size()) return "fused program tail";

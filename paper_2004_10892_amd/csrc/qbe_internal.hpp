@@ -16,6 +16,8 @@ namespace qbe {
 constexpr int kMaxOps = 8;
 // Threads per workgroup of the per-step and fused kernels.
 constexpr int kBlock = 256;
+// Threads of a fused workgroup.
+constexpr int kFusedBlock = 256;
 // Low index bits handled inside one workgroup tile by the per-step kernel.
 constexpr int kLoBits = 8;
 // LDS budget of one fused workgroup (bytes): tensor entries, plus the
@@ -63,32 +65,43 @@ struct StepProg {
 
 // A fused program lives in device memory (uint32 words) and is read from
 // there (through the caches); the workgroup keeps the tensor entries and a
-// copy of the level table in LDS.  LDS data layout (complex64 elements):
-//   [0]                         the constant 1 (padding operand)
-//   [1, 1 + inv)                slice-invariant input tensors
-//   [1 + inv, 1 + inv + dep)    this slice's copies of slice-dependent inputs
-//   [1 + inv + dep, data)       intermediates (arena, reused level by level)
+// copy of the level table in LDS.  A level holds nodes: a root bucket and
+// the buckets it absorbed (the plan compiler merges buckets along chains of
+// the dependency tree); an entry of a node's result sums T = 2^lgT terms,
+// one per assignment of the members' eliminated variables.
+// LDS data layout (complex64 elements):
+//   [0], [1]                    the constants 1 (padding factor) and 0
+//   [2, 2 + inv)                slice-invariant input tensors
+//   [2 + inv, 2 + inv + dep)    this slice's copies of slice-dependent inputs
+//   [2 + inv + dep, data)       intermediates (arena, reused level by level)
 // then, from byte fused_table_lds(data), the level table (16 bytes a level).
 // Program words:
 //   header[kHdr]
 //   levels[4 * (n_levels + kFusedLevelPad)]
-//                               (record base, elements E, rows R of a
-//                               half-record, operands K), then zero entries
-//   records                     level by level, E records of two half-records
+//                               (record base, entries E, R | lgT << 16,
+//                               factors K), then zero entries; R = rows of a
+//                               term record, T = 2^lgT terms per entry
+//   records                     level by level, E entries of T term records
 //                               of R 16-byte rows (8R halfwords) each:
-//                                 half u, halfword 0: LDS offset of the
-//                                   result (u = 0), 0 (u = 1)
-//                                 half u, halfwords 1..K: LDS offsets of the
-//                                   operand entries for that value of u
-//                                 rest: 0 (the constant 1)
+//                                 slot 0: LDS offset of the result (term 0),
+//                                   0 (other terms)
+//                                 slots 1..K: LDS offsets of the factor
+//                                   entries for that term's assignment
+//                                 rest: 0 (the constant 1); a padding term
+//                                   (node with fewer terms than its level)
+//                                   has slot 1 = the constant 0
 //                               offsets in bytes (header FH_BYTE_OFFSETS = 1,
 //                               data within 64 KB) or else in elements
 //   scalars[n_scalars]          LDS element offsets of the slice's scalar
 //                               factors, zero words to a multiple of 4, then
 //                               4 * kFusedTailRows zero words (the executor
-//                               reads kFusedTailRows rows at any half-record)
+//                               reads kFusedTailRows rows at any record)
 constexpr int kFusedTailRows = 2;
 constexpr int kFusedLevelPad = 3;
+// LDS elements 0 and 1 hold the constants 1 (padding factor) and 0 (the
+// factor of a padding term); inputs follow.
+constexpr int kFusedConsts = 2;
+constexpr uint32_t kFusedZero = 1;
 // LDS byte offset of the level table's copy: after the tensor entries.
 inline int64_t fused_table_lds(int64_t data_elems) { return (data_elems * 8 + 15) / 16 * 16; }
 enum FusedHdr {
@@ -116,7 +129,8 @@ struct Plan {
   int exec = 0;
   int precision = 0;
   int block = kBlock;
-  int n_levels = 0;
+  int n_levels = 0;       // dependency depth of the buckets
+  int fused_levels = 0;   // levels of the fused program (merged buckets)
 
   // per-step form
   std::vector<StepProg> steps;          // launch list (chained splits included)

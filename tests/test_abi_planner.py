@@ -125,6 +125,20 @@ def test_fused_form_chosen_for_small_slices_and_per_step_for_large():
         qbe.Plan(q7, pi7, mu7, exec="fused")
 
 
+@pytest.mark.parametrize("rows,cols,depth,seed,m", [(4, 4, 10, 0, 0), (5, 5, 16, 1, 6)])
+def test_fused_program_merges_buckets_into_fewer_levels(rows, cols, depth, seed, m):
+    # the fused program merges chains of buckets (several variables summed
+    # per record); its level count drops below the buckets' dependency depth
+    qm = qbe.Model.from_circuitgen(circuit_model(random_grid_circuit(rows, cols, depth, seed)))
+    _, mu, pi, _ = qbe.plan_circuit(qm, m=m)
+    plan = qbe.Plan(qm, pi, mu, exec="fused")
+    plan.check()
+    st_ = plan.stats()
+    assert 0 < st_["fused_levels"] < st_["n_levels"]
+    per_step = qbe.Plan(qm, pi, mu, exec="per_step").stats()
+    assert per_step["fused_levels"] == st_["fused_levels"]  # the program exists either way
+
+
 def test_batch_instance_plans_are_sound():
     for (r, c, d, m, seed) in batch_instances(24):
         qm = qbe.Model.from_circuitgen(circuit_model(random_grid_circuit(r, c, d, seed)))
