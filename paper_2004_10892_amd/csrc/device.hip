@@ -379,6 +379,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(const double2* __restrict__
 // precedes the LDS fill.
 struct FusedMeta {
   uint32_t lds_tab, levels, scalars, scalar_off, free_vars, inv, dep, dep_src, bytes, pad;
+  uint32_t lv0[4], lv1[4];  // the first two level-table entries
 };
 
 struct FusedItem {
@@ -407,8 +408,13 @@ struct FusedArgs {
 
 static FusedMeta fused_meta(const Plan& p) {
   const std::vector<uint32_t>& w = p.fused_prog;
-  return FusedMeta{(uint32_t)fused_table_lds(w[FH_DATA_ELEMS]), w[FH_LEVELS], w[FH_SCALARS], w[FH_SCALAR_OFF],
-                   w[FH_FREE], w[FH_INV_ELEMS], w[FH_DEP_ELEMS], w[FH_DEP_SRC], w[FH_BYTE_OFFSETS], 0};
+  FusedMeta m{(uint32_t)fused_table_lds(w[FH_DATA_ELEMS]), w[FH_LEVELS], w[FH_SCALARS], w[FH_SCALAR_OFF],
+              w[FH_FREE], w[FH_INV_ELEMS], w[FH_DEP_ELEMS], w[FH_DEP_SRC], w[FH_BYTE_OFFSETS], 0, {}, {}};
+  for (int i = 0; i < 4; ++i) {
+    m.lv0[i] = w[kHdr + i];
+    m.lv1[i] = w[kHdr + 4 + i];
+  }
+  return m;
 }
 
 // LDS bytes after the data for the workgroup's control words.
@@ -422,9 +428,6 @@ constexpr int kWholeOpsMax = 4 * kRecRows - 1;
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef const __attribute__((address_space(1))) uint32_t* gu32p;
 typedef const __attribute__((address_space(1))) u32x4* gu32x4p;
-// Read-only data every lane reads at the same address (the start of the
-// level table): the constant address space, so that the loads are scalar.
-typedef const __attribute__((address_space(4))) u32x4* cu32x4p;
 
 // The same pointer typed as device (global) memory, so that loads through it
 // are global loads (waited on by their own counter) rather than flat ones.
@@ -674,7 +677,7 @@ __device__ __forceinline__ void fill_lds(uint64_t* dinv, const uint64_t* sinv_, 
 // One workgroup of four waves per compute unit is the intended occupancy: the
 // compiler may use the whole register file to keep every read of a level in
 // flight at once.
-__global__ __launch_bounds__(kFusedBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void fused_kernel(FusedArgs a) {
+__global__ __launch_bounds__(kFusedBlock) __attribute__((amdgpu_waves_per_eu(kFusedBlock / 256, kFusedBlock / 256))) void fused_kernel(FusedArgs a) {
   // all of the workgroup's LDS is dynamic, so that the tensor entries start
   // at LDS address 0 and record offsets are addresses; the two shared words
   // sit after the largest data block of the launch
@@ -712,7 +715,11 @@ __global__ __launch_bounds__(kFusedBlock) __attribute__((amdgpu_waves_per_eu(1, 
       prep = wi.prep;
       mt = FusedMeta{uni(wi.meta.lds_tab), uni(wi.meta.levels),  uni(wi.meta.scalars), uni(wi.meta.scalar_off),
                      uni(wi.meta.free_vars), uni(wi.meta.inv), uni(wi.meta.dep),     uni(wi.meta.dep_src),
-                     uni(wi.meta.bytes), 0};
+                     uni(wi.meta.bytes), 0, {}, {}};
+      for (int i = 0; i < 4; ++i) {
+        mt.lv0[i] = uni(wi.meta.lv0[i]);
+        mt.lv1[i] = uni(wi.meta.lv1[i]);
+      }
     }
     gprog = uniform_ptr(gprog);
     const gu32p prog = as_global(gprog);
@@ -720,8 +727,8 @@ __global__ __launch_bounds__(kFusedBlock) __attribute__((amdgpu_waves_per_eu(1, 
     float2* data = reinterpret_cast<float2*>(lds4);
     // level table and the records of the first two levels: issued first, so
     // that they arrive while the inputs are copied
-    const cu32x4p glv = (cu32x4p)(gprog + kHdr);
-    u32x4 t0 = glv[0], t1 = glv[1];
+    const u32x4 t0 = {mt.lv0[0], mt.lv0[1], mt.lv0[2], mt.lv0[3]};
+    const u32x4 t1 = {mt.lv1[0], mt.lv1[1], mt.lv1[2], mt.lv1[3]};
     typedef __attribute__((address_space(3))) u32x4* lds_u32x4p;
     const lds_u32x4p lv = (lds_u32x4p)(size_t)mt.lds_tab;  // the LDS copy
     Rec ra, rb;

@@ -17,7 +17,7 @@ constexpr int kMaxOps = 8;
 // Threads per workgroup of the per-step and fused kernels.
 constexpr int kBlock = 256;
 // Threads of a fused workgroup.
-constexpr int kFusedBlock = 256;
+constexpr int kFusedBlock = 512;
 // Low index bits handled inside one workgroup tile by the per-step kernel.
 constexpr int kLoBits = 8;
 // LDS budget of one fused workgroup (bytes): tensor entries, plus the
