@@ -83,7 +83,10 @@ typedef struct qbe_plan_opts {
   int32_t exec;        /* QBE_EXEC_*                                         */
   int32_t precision;   /* QBE_PREC_*                                         */
   int32_t block;       /* threads per workgroup for per-step kernels; 0 = tuned */
-  int32_t reserved[5]; /* must be zero                                       */
+  int32_t no_merge;    /* 1: one launch per bucket in the per-step form and
+                          one level per bucket depth in the fused form (no
+                          merging of bucket chains); 0: merge (default)      */
+  int32_t reserved[4]; /* must be zero                                       */
 } qbe_plan_opts;
 
 typedef struct qbe_stats {
@@ -102,7 +105,13 @@ typedef struct qbe_stats {
   int32_t fused_levels;                /* fused form: levels of its program
                                           (buckets merged along chains; 0 if
                                           the plan has no fused program)     */
-  int32_t reserved;                    /* 0                                  */
+  int32_t n_merged_steps;              /* per-step form: launches that merge
+                                          a chain of buckets (several summed
+                                          variables)                         */
+  uint64_t step_bytes_per_slice;       /* per-step form: complex64 bytes its
+                                          launches read and write per slice
+                                          (below bytes_per_slice when chains
+                                          are merged)                        */
 } qbe_stats;
 
 /* ------------------------------------------------------------------ misc -- */

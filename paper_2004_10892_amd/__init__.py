@@ -52,7 +52,7 @@ class QbeError(RuntimeError):
 
 class PlanOpts(C.Structure):
     _fields_ = [("exec", C.c_int32), ("precision", C.c_int32), ("block", C.c_int32),
-                ("reserved", C.c_int32 * 5)]
+                ("no_merge", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
 class Stats(C.Structure):
@@ -61,7 +61,7 @@ class Stats(C.Structure):
                 ("flops_per_slice", C.c_uint64), ("bytes_per_slice", C.c_uint64),
                 ("peak_bytes_per_slice", C.c_uint64), ("ws_bytes_min", C.c_uint64),
                 ("ws_bytes_all_slices", C.c_uint64), ("n_mfma_steps", C.c_int32), ("precision", C.c_int32),
-                ("fused_levels", C.c_int32), ("reserved", C.c_int32)]
+                ("fused_levels", C.c_int32), ("n_merged_steps", C.c_int32), ("step_bytes_per_slice", C.c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -277,12 +277,14 @@ class Plan:
     """Compiled schedule (and device programs when a context is given)."""
 
     def __init__(self, model: Model, reduced_order: Sequence[int], mu: Sequence[int],
-                 ctx: Optional[Context] = None, exec: str = "auto", precision: str = "fp32"):
+                 ctx: Optional[Context] = None, exec: str = "auto", precision: str = "fp32",
+                 merge: bool = True):
         o = _i32(reduced_order)
         u = _i32(mu)
         opts = PlanOpts()
         opts.exec = EXEC[exec]
         opts.precision = PREC[precision]
+        opts.no_merge = 0 if merge else 1
         h = _vp()
         _check(_lib.qbe_plan_create(ctx.handle if ctx else None, model.handle, _p32(o), len(o), _p32(u), len(u),
                                     C.byref(opts), C.byref(h)), "qbe_plan_create")

@@ -307,6 +307,7 @@ int qbe_plan_create(qbe_ctx* ctx, const qbe_model* model, const int32_t* reduced
   QBE_REQUIRE(o.exec >= QBE_EXEC_AUTO && o.exec <= QBE_EXEC_FUSED, "bad exec form");
   QBE_REQUIRE(o.precision >= QBE_PREC_FP32 && o.precision <= QBE_PREC_BF16X6, "bad precision");
   QBE_REQUIRE(o.block == 0 || o.block == qbe::kBlock, "unsupported block size");
+  QBE_REQUIRE(o.no_merge == 0 || o.no_merge == 1, "no_merge must be 0 or 1");
   auto* pl = new qbe_plan;
   std::unique_ptr<qbe_plan> guard(pl);
   qbe::Plan& p = pl->p;
@@ -314,6 +315,7 @@ int qbe_plan_create(qbe_ctx* ctx, const qbe_model* model, const int32_t* reduced
   p.sched = qbe::build_schedule(p.model.n_vars, p.model.tvars, vec(reduced_order, n), vec(mu, m));
   p.cost = qbe::schedule_cost(p.sched);
   p.precision = o.precision;
+  p.merge = o.no_merge == 0;
   qbe::compile_plan(p);
   if (o.exec == QBE_EXEC_FUSED && o.precision != QBE_PREC_FP32) {
     set_error("the fused form computes in FP32 only");
@@ -395,7 +397,10 @@ int qbe_plan_stats(const qbe_plan* plan, qbe_stats* out) {
     if (sp.mm_a >= 0) ++out->n_mfma_steps;
   out->precision = p.precision;
   out->fused_levels = p.fused_ok ? p.fused_levels : 0;
-  out->reserved = 0;
+  out->n_merged_steps = 0;
+  for (const auto& sp : p.steps)
+    if (sp.n_sum > 1) ++out->n_merged_steps;
+  out->step_bytes_per_slice = (uint64_t)p.step_bytes_per_slice;
   return QBE_OK;
   QBE_GUARD_END
 }

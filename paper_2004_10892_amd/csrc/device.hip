@@ -79,6 +79,7 @@ struct StepLaunch {
   int32_t n_ops;
   int32_t r;       // bits of x
   int32_t sum_u;   // 1: sum over the top bit u of X
+  int32_t n_sum;   // msum_kernel: summed top bits of X
   int32_t lo;      // min(r, kLoBits)
   int64_t s0;      // first slice of the group
   int64_t G;       // slices in the group
@@ -156,6 +157,89 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch a) {
       }
       a.out[oidx[e]] = acc;
     }
+  }
+}
+
+// A launch that merges a chain of buckets: the top n_sum bits of X are
+// summed (2^n_sum terms per result entry).  The offset of operand i's entry
+// for summed value u is pext(u, the operand's summed-bit mask) above its x
+// bits -- the same for every lane, so that part is scalar work; the tiling
+// over x is that of step_kernel.
+template <int K, int EPT>
+__global__ __launch_bounds__(kBlock) void msum_kernel(StepLaunch a) {
+  const int tid = threadIdx.x;
+  const int r = a.r, lo = a.lo;
+  const uint32_t lomask = (1u << lo) - 1u;
+  const uint32_t x_lo = (uint32_t)tid & lomask;
+  const int64_t g_sub = tid >> lo;
+  const int64_t spt = (int64_t)(kBlock >> lo);
+  const int hib = r - lo;
+  const uint32_t nu = 1u << a.n_sum;
+  uint32_t lo_part[K], hi_mask[K], umask[K];
+  int lo_cnt[K], xcnt[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    const uint32_t m = a.mask[i];
+    lo_part[i] = pext32(x_lo, m & lomask);
+    lo_cnt[i] = __builtin_popcount(m & lomask);
+    hi_mask[i] = (m >> lo) & ((1u << hib) - 1u);
+    umask[i] = m >> r;
+    xcnt[i] = __builtin_popcount(m & ((1u << r) - 1u));
+  }
+  for (int64_t t0 = (int64_t)blockIdx.x * EPT; t0 < a.n_tiles; t0 += (int64_t)gridDim.x * EPT) {
+    const float2* q[EPT][K];
+    int64_t oidx[EPT];
+    bool ok[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int64_t tile = t0 + e;
+      int64_t g;
+      uint32_t x_hi;
+      if (hib > 0) {
+        g = tile >> hib;
+        x_hi = (uint32_t)(tile & ((int64_t(1) << hib) - 1));
+        ok[e] = tile < a.n_tiles;
+      } else {
+        g = tile * spt + g_sub;
+        x_hi = 0;
+        ok[e] = tile < a.n_tiles && g < a.G;
+      }
+      oidx[e] = (g << r) + ((int64_t)x_hi << lo) + x_lo;
+      const int64_t s = a.s0 + g;
+#pragma unroll
+      for (int i = 0; i < K; ++i) {
+        int64_t base;
+        if (a.gstride[i] != 0)
+          base = g * a.gstride[i];
+        else
+          base = (int64_t)pext32((uint32_t)s, a.smask[i]) << a.rank[i];
+        base += (int64_t)(pext32(x_hi, hi_mask[i]) << lo_cnt[i]) + lo_part[i];
+        q[e][i] = a.src[i] + base;
+      }
+    }
+    float2 acc[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) acc[e] = make_float2(0.f, 0.f);
+    for (uint32_t u = 0; u < nu; ++u) {
+      uint32_t off[K];
+#pragma unroll
+      for (int i = 0; i < K; ++i) off[i] = pext32(u, umask[i]) << xcnt[i];
+      float2 v[EPT][K];
+#pragma unroll
+      for (int e = 0; e < EPT; ++e)
+#pragma unroll
+        for (int i = 0; i < K; ++i) v[e][i] = ok[e] ? q[e][i][off[i]] : make_float2(0.f, 0.f);
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        float2 p = v[e][0];
+#pragma unroll
+        for (int i = 1; i < K; ++i) p = cmul(p, v[e][i]);
+        acc[e] = make_float2(acc[e].x + p.x, acc[e].y + p.y);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < EPT; ++e)
+      if (ok[e]) a.out[oidx[e]] = acc[e];
   }
 }
 
@@ -981,6 +1065,7 @@ static int launch_step(const Plan& p, const StepProg& sp, float2* arena, int64_t
   a.n_ops = sp.n_ops;
   a.r = r;
   a.sum_u = sum_u ? 1 : 0;
+  a.n_sum = sp.n_sum;
   a.lo = std::min(r, kLoBits);
   a.s0 = s0;
   a.G = G;
@@ -1047,8 +1132,13 @@ static int launch_step(const Plan& p, const StepProg& sp, float2* arena, int64_t
   if (wg_per_cu <= 0) wg_per_cu = sp.wg_per_cu > 0 ? sp.wg_per_cu : 16;
   const int64_t want = (a.n_tiles + ept - 1) / ept;
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)n_cus() * wg_per_cu));
-#define QBE_CASE(KK, EE) \
-  case KK * 16 + EE: step_kernel<KK, EE><<<grid, kBlock, 0, st>>>(a); break;
+#define QBE_CASE(KK, EE)                                                      \
+  case KK * 16 + EE:                                                          \
+    if (sp.n_sum > 1)                                                         \
+      msum_kernel<KK, EE><<<grid, kBlock, 0, st>>>(a);                        \
+    else                                                                      \
+      step_kernel<KK, EE><<<grid, kBlock, 0, st>>>(a);                        \
+    break;
 #define QBE_KS(KK) QBE_CASE(KK, 1) QBE_CASE(KK, 2) QBE_CASE(KK, 4)
   switch (sp.n_ops * 16 + ept) {
     QBE_KS(1) QBE_KS(2) QBE_KS(3) QBE_KS(4) QBE_KS(5) QBE_KS(6) QBE_KS(7) QBE_KS(8)

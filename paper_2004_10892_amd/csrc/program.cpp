@@ -116,7 +116,7 @@ struct FusedNode {
 constexpr int kMergeTermsLog2 = 3;
 constexpr int kMergeFactors = 15;
 
-std::vector<FusedNode> merge_buckets(const Schedule& s) {
+std::vector<FusedNode> merge_buckets(const Schedule& s, bool merge) {
   const int n = (int)s.steps.size();
   std::vector<std::vector<int>> kids(n), members(n);
   std::vector<int> F(n), lgT(n, 1), lv(n, 0);
@@ -153,7 +153,7 @@ std::vector<FusedNode> merge_buckets(const Schedule& s) {
     return true;
   };
   int depth = levels();
-  for (bool merged = true; merged;) {
+  for (bool merged = merge; merged;) {
     merged = false;
     std::vector<int> order;
     for (int k = 0; k < n; ++k)
@@ -206,6 +206,50 @@ std::vector<FusedNode> merge_buckets(const Schedule& s) {
     nodes.push_back(std::move(nd));
   }
   return nodes;
+}
+
+// Per-step form: a bucket whose result is at least as large as its
+// consumer's (a shrinking chain) and of rank kChainMinRank or more is merged
+// into the consumer, so that one launch sums several variables and the
+// absorbed result never goes to device memory.  Up to kChainSumMax summed
+// variables and kMaxOps operands per launch.
+constexpr int kChainMinRank = 12;
+constexpr int kChainSumMax = 4;
+
+struct StepNode {
+  std::vector<int> members;      // absorbed buckets in elimination order, root last
+  std::vector<Operand> factors;  // operands of the members except absorbed results
+};
+
+std::vector<StepNode> merge_chains(const Schedule& s, bool merge) {
+  const int n = (int)s.steps.size();
+  std::vector<StepNode> nd(n);
+  std::vector<char> alive(n, 1);
+  for (int k = 0; k < n; ++k) {
+    nd[k].members = {k};
+    nd[k].factors = s.steps[k].ops;
+  }
+  for (int k = 0; k < n && merge; ++k) {
+    const int c = s.consumer[k];
+    if (c < 0) continue;
+    const int rk = (int)s.steps[k].out.size(), rc = (int)s.steps[c].out.size();
+    if (rk < kChainMinRank || rk < rc) continue;
+    if ((int)(nd[k].members.size() + nd[c].members.size()) > kChainSumMax) continue;
+    std::vector<Operand> f;
+    for (const Operand& op : nd[c].factors)
+      if (!(op.kind == 'r' && op.id == k)) f.push_back(op);
+    f.insert(f.end(), nd[k].factors.begin(), nd[k].factors.end());
+    if ((int)f.size() > kMaxOps) continue;
+    std::vector<int> m = nd[k].members;
+    m.insert(m.end(), nd[c].members.begin(), nd[c].members.end());
+    nd[c].members = std::move(m);
+    nd[c].factors = std::move(f);
+    alive[k] = 0;
+  }
+  std::vector<StepNode> out;
+  for (int k = 0; k < n; ++k)
+    if (alive[k]) out.push_back(std::move(nd[k]));
+  return out;
 }
 
 }  // namespace
@@ -280,20 +324,28 @@ void compile_plan(Plan& p) {
     o.smask = in[t].smask;
     return o;
   };
-  for (int k = 0; k < nsteps; ++k) {
+  for (const StepNode& node : merge_chains(s, p.merge)) {
+    const int k = node.members.back();  // the root: its result is the launch's
     const Step& st = s.steps[k];
-    if (st.uni.size() > 31) throw std::invalid_argument("bucket union above 31 variables");
+    const int n_sum = (int)node.members.size();
+    // union of the launch: the members' eliminated variables (earliest
+    // first), then the root's result variables -- every factor's variables
+    // lie in it, and the summed ones are its top bits
+    std::vector<int> uni;
+    for (int m : node.members) uni.push_back(s.steps[m].var);
+    uni.insert(uni.end(), st.out.begin(), st.out.end());
+    if (uni.size() > 31) throw std::invalid_argument("bucket union above 31 variables");
     const int rb = (int)st.out.size();
     std::vector<StepOp> ops;
-    for (const auto& op : st.ops) {
+    for (const auto& op : node.factors) {
       if (op.kind == 't') {
-        ops.push_back(input_op(op.id, st.uni));
+        ops.push_back(input_op(op.id, uni));
       } else {
         StepOp o{};
         o.base = out_off[op.id];
         o.is_input = 0;
         o.rank = (int)op.vars.size();
-        o.mask = union_mask(st.uni, op.vars);
+        o.mask = union_mask(uni, op.vars);
         ops.push_back(o);
       }
     }
@@ -310,6 +362,7 @@ void compile_plan(Plan& p) {
       // re-express each member's mask inside the partial product's index
       StepProg sp{};
       sp.out_rank = -pr;  // negative: product without summation, out index = pext(X, gm)
+      sp.n_sum = 0;
       int64_t sz = int64_t(1) << pr;
       int64_t off = arena.alloc(sz, align_for(sz));
       temps.push_back({off, sz});
@@ -339,7 +392,8 @@ void compile_plan(Plan& p) {
     }
     StepProg sp{};
     sp.out_rank = rb;
-    {
+    sp.n_sum = n_sum;
+    if (n_sum == 1) {
       // outer-product shape: two operands hold x bits (and u), the rest only u
       const uint32_t ubit = 1u << rb, xmask = ubit - 1u;
       int big[2] = {-1, -1}, nbig = 0;
@@ -366,11 +420,17 @@ void compile_plan(Plan& p) {
     for (size_t i = 0; i < ops.size(); ++i) sp.ops[i] = ops[i];
     p.steps.push_back(sp);
     for (auto& tb : temps) arena.release(tb.first, tb.second);
-    for (const auto& op : st.ops)
+    for (const auto& op : node.factors)
       if (op.kind == 'r') arena.release(out_off[op.id], int64_t(1) << op.vars.size());
     if (rb == 0) p.scalar_arena.push_back(out_off[k]);
   }
   p.arena_per_slice = std::max<int64_t>(arena.top, 1);
+  p.step_bytes_per_slice = 0;
+  for (const StepProg& sp : p.steps) {
+    int64_t b = int64_t(1) << (sp.out_rank >= 0 ? sp.out_rank : -sp.out_rank);
+    for (int i = 0; i < sp.n_ops; ++i) b += int64_t(1) << sp.ops[i].rank;
+    p.step_bytes_per_slice += 8 * b;
+  }
   // scalar results of steps must stay allocated: they were never released
   // (a rank-0 result has no consumer step).
   p.scalar_inputs_base.clear();
@@ -417,7 +477,7 @@ void compile_plan(Plan& p) {
         dep += int64_t(1) << in[t].canon.size();
       }
     // merged nodes (each writes its root bucket's result) and their levels
-    const std::vector<FusedNode> nodes = merge_buckets(s);
+    const std::vector<FusedNode> nodes = merge_buckets(s, p.merge);
     int f_levels = 0;
     for (const FusedNode& nd : nodes) f_levels = std::max(f_levels, nd.level + 1);
     std::vector<std::vector<int>> by_level(f_levels);

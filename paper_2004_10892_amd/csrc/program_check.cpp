@@ -30,8 +30,10 @@ std::string check_plan(const Plan& p) {
     const StepProg& sp = p.steps[k];
     const bool sum_u = sp.out_rank >= 0;
     const int r = sum_u ? sp.out_rank : -sp.out_rank;
-    const int xbits = r + (sum_u ? 1 : 0);
-    if (r > 30) return "result rank above 30";
+    if (sum_u ? (sp.n_sum < 1 || sp.n_sum > 4) : sp.n_sum != 0) return "summed variable count";
+    const int xbits = r + sp.n_sum;
+    if (r > 30 || xbits > 31) return "result rank above 30";
+    if (sp.n_sum > 1 && sp.mm_a >= 0) return "merged launch with an outer-product tile";
     if (sp.n_ops < 1 || sp.n_ops > kMaxOps) return "operand count";
     if (sp.out_base < 0 || sp.out_base + (int64_t(1) << r) > p.arena_per_slice)
       return fail("result outside the arena", sp.out_base + (int64_t(1) << r), p.arena_per_slice);
@@ -54,6 +56,8 @@ std::string check_plan(const Plan& p) {
       if (__builtin_popcount(o.mask) != o.rank) return "operand mask and rank disagree";
       if (xbits < 32 && (o.mask >> xbits) != 0) return "operand mask outside the union index";
       if (sum_u && o.rank > 0 && !((o.mask >> r) & 1u) && o.rank > r) return "operand rank";
+      if (sp.n_sum > 1 && (o.mask >> r) == 0 && o.rank > 0 && !o.is_input)
+        return "merged launch with an intermediate that holds no summed variable";
       if (o.is_input) {
         const int64_t versions = int64_t(1) << __builtin_popcount(o.smask);
         if (o.base < 0 || o.base + (versions << o.rank) > p.step_elems)

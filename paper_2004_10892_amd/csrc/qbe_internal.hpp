@@ -50,6 +50,9 @@ struct StepOp {
 struct StepProg {
   int32_t out_rank;   // r_b (0 for a scalar result); negative: a partial
                       // product over -out_rank variables without the sum
+  int32_t n_sum = 1;  // summed variables: the top n_sum bits of the union
+                      // index X = (u << r_b) | x (more than one when the
+                      // launch merges a chain of buckets)
   int64_t out_base;   // arena offset (per-slice unit)
   int32_t n_ops;
   int32_t ept = 0;        // tiles per thread per pass (0: default)
@@ -128,6 +131,7 @@ struct Plan {
   int64_t n_slices = 1;
   int exec = 0;
   int precision = 0;
+  bool merge = true;      // merge bucket chains (per-step launches, fused levels)
   int block = kBlock;
   int n_levels = 0;       // dependency depth of the buckets
   int fused_levels = 0;   // levels of the fused program (merged buckets)
@@ -138,6 +142,7 @@ struct Plan {
   std::vector<int64_t> scalar_inputs_base;  // prepared offsets of rank-0 inputs
   std::vector<uint32_t> scalar_inputs_smask;
   int64_t arena_per_slice = 0;          // elements
+  int64_t step_bytes_per_slice = 0;     // complex64 bytes the launches read and write
   std::vector<int32_t> step_map;        // prepared per-step buffer gather map
   int64_t step_elems = 0;
 

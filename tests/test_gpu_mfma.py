@@ -60,7 +60,9 @@ def test_outer_product_bucket_vs_brute_force(env, prec, seed, m):
     mu = order[n - m:] if m else []
     pi = order[:n - m]
     qm = qbe.Model(n, tensors)
-    plan = qbe.Plan(qm, pi, mu, ctx=ctx, exec="per_step", precision=prec)
+    # one launch per bucket, so that the outer-product bucket is not merged
+    # into its consumer
+    plan = qbe.Plan(qm, pi, mu, ctx=ctx, exec="per_step", precision=prec, merge=False)
     assert plan.stats()["n_mfma_steps"] >= 1
     print(f"case outer product seed={seed} m={m} {prec}", flush=True)
     got, per = qbe.qbe_contract_slices(ctx, plan, 0, plan.n_slices, plan.workspace())
@@ -85,7 +87,8 @@ def test_precision_forms_on_7x7_d24_slices(env):
     _, mu, pi, _ = qbe.plan_circuit(qm, m=10)
     errs = {}
     for prec in ("fp32", "bf16x3", "bf16x6"):
-        plan = qbe.Plan(qm, pi, mu, ctx=ctx, exec="per_step", precision=prec)
+        # one launch per bucket: all seven outer-product buckets on MFMA
+        plan = qbe.Plan(qm, pi, mu, ctx=ctx, exec="per_step", precision=prec, merge=False)
         n_mm = plan.stats()["n_mfma_steps"]
         assert n_mm >= 1
         print(f"case 7x7 slices 0-15 {prec}", flush=True)
