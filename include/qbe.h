@@ -99,8 +99,9 @@ typedef struct qbe_stats {
   uint64_t peak_bytes_per_slice;       /* live-tensor peak                   */
   uint64_t ws_bytes_min;               /* smallest workspace contract accepts */
   uint64_t ws_bytes_all_slices;        /* workspace for all slices at once   */
-  int32_t n_mfma_steps;                /* per-step form: outer-product buckets
-                                          run as MFMA tiles                   */
+  int32_t n_mfma_steps;                /* per-step form: launches run as
+                                          MFMA tiles (outer-product buckets
+                                          and merged products)               */
   int32_t precision;                   /* QBE_PREC_* of the plan             */
   int32_t fused_levels;                /* fused form: levels of its program
                                           (buckets merged along chains; 0 if

@@ -394,7 +394,7 @@ int qbe_plan_stats(const qbe_plan* plan, qbe_stats* out) {
   out->ws_bytes_all_slices = qbe::dev_workspace_all(p);
   out->n_mfma_steps = 0;
   for (const auto& sp : p.steps)
-    if (sp.mm_a >= 0) ++out->n_mfma_steps;
+    if (sp.mm_a >= 0 || sp.mmk) ++out->n_mfma_steps;
   out->precision = p.precision;
   out->fused_levels = p.fused_ok ? p.fused_levels : 0;
   out->n_merged_steps = 0;

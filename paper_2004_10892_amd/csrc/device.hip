@@ -161,7 +161,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch a) {
 }
 
 // A launch that merges a chain of buckets: the top n_sum bits of X are
-// summed (2^n_sum terms per result entry).  The offset of operand i's entry
+// summed (2^n_sum >= 4 terms per result entry).  The offset of operand i's entry
 // for summed value u is pext(u, the operand's summed-bit mask) above its x
 // bits -- the same for every lane, so that part is scalar work; the tiling
 // over x is that of step_kernel.
@@ -220,22 +220,28 @@ __global__ __launch_bounds__(kBlock) void msum_kernel(StepLaunch a) {
     float2 acc[EPT];
 #pragma unroll
     for (int e = 0; e < EPT; ++e) acc[e] = make_float2(0.f, 0.f);
-    for (uint32_t u = 0; u < nu; ++u) {
-      uint32_t off[K];
+    // four terms per trip (2^n_sum >= 4), all their loads in flight together
+    for (uint32_t u0 = 0; u0 < nu; u0 += 4) {
+      float2 v[4][EPT][K];
 #pragma unroll
-      for (int i = 0; i < K; ++i) off[i] = pext32(u, umask[i]) << xcnt[i];
-      float2 v[EPT][K];
+      for (int du = 0; du < 4; ++du) {
+        uint32_t off[K];
 #pragma unroll
-      for (int e = 0; e < EPT; ++e)
+        for (int i = 0; i < K; ++i) off[i] = pext32(u0 + du, umask[i]) << xcnt[i];
 #pragma unroll
-        for (int i = 0; i < K; ++i) v[e][i] = ok[e] ? q[e][i][off[i]] : make_float2(0.f, 0.f);
+        for (int e = 0; e < EPT; ++e)
 #pragma unroll
-      for (int e = 0; e < EPT; ++e) {
-        float2 p = v[e][0];
-#pragma unroll
-        for (int i = 1; i < K; ++i) p = cmul(p, v[e][i]);
-        acc[e] = make_float2(acc[e].x + p.x, acc[e].y + p.y);
+          for (int i = 0; i < K; ++i) v[du][e][i] = ok[e] ? q[e][i][off[i]] : make_float2(0.f, 0.f);
       }
+#pragma unroll
+      for (int du = 0; du < 4; ++du)
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+          float2 p = v[du][e][0];
+#pragma unroll
+          for (int i = 1; i < K; ++i) p = cmul(p, v[du][e][i]);
+          acc[e] = make_float2(acc[e].x + p.x, acc[e].y + p.y);
+        }
     }
 #pragma unroll
     for (int e = 0; e < EPT; ++e)
@@ -385,6 +391,90 @@ __global__ __launch_bounds__(kBlock) void mm_kernel(MmLaunch a) {
         cre = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(qa1, qb1, cre, 0, 0, 0);
         cim = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(qa2, qb2, cim, 0, 0, 0);
       }
+    }
+    const int64_t ob = (g << r) | xt;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a.out[ob | oo[i]] = make_float2(cre[i], cim[i]);
+  }
+}
+
+// A merged launch whose result variables all belong to two factor groups A'
+// and B' (each the product of its factors; together all result bits, at
+// least four private bits each), summed over the top J bits of X:
+//   R[c, m, n] = sum_k A'[c, m, k] B'[c, n, k],  k in [0, 2^J)
+// a batched complex product with K = 2^J.  One wavefront computes a 16 x 16
+// (m, n) tile with v_mfma_f32_16x16x4f32 over the real K = 2^(J+1) entries
+// [Re A' | -Im A'] . [Re B' ; Im B'] (real part) and [Re A' | Im A'] .
+// [Im B' ; Re B'] (imaginary part), four entries per MFMA: lane l of a call
+// supplies entry 4c + l/16, i.e. term k = (4c + l/16) mod 2^J.
+struct MmkLaunch {
+  float2* out;
+  const float2* src[kMaxOps];
+  int64_t gs[kMaxOps];      // elements between slices (0: input tensor)
+  uint32_t sm[kMaxOps];     // input slice masks
+  int32_t rk[kMaxOps];
+  uint32_t mk[kMaxOps];     // masks over X
+  int32_t n_ops;
+  uint32_t side_b;          // bit i: factor i belongs to B' (else to A')
+  uint32_t mtile, ntile, rest;
+  int32_t r;
+  int64_t s0, G, n_tiles;
+};
+
+template <int J>
+__global__ __launch_bounds__(kBlock) void mmk_kernel(MmkLaunch a) {
+  constexpr int KQ = (1 << J) / 4;  // terms a lane supplies per side
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int64_t n_waves = (int64_t)gridDim.x * (kBlock / 64);
+  const int r = a.r;
+  const int row = lane & 15, grp = lane >> 4;
+  const uint32_t xm = pdep32((uint32_t)row, a.mtile), xn = pdep32((uint32_t)row, a.ntile);
+  uint32_t oo[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) oo[i] = pdep32((uint32_t)(4 * grp + i), a.mtile) | xn;
+  // bit extraction is linear over disjoint bit sets, so an operand's index
+  // is the OR of the parts from the lane's tile bits and term (fixed per
+  // lane), and from the tile's other bits (fixed per tile)
+  uint32_t plane[kMaxOps], pterm[kMaxOps][KQ];
+  for (int i = 0; i < a.n_ops; ++i) {
+    plane[i] = pext32(((a.side_b >> i) & 1u) ? xn : xm, a.mk[i]);
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) pterm[i][q] = pext32((uint32_t)(4 * q + grp) << r, a.mk[i]);
+  }
+  const int rb = r - 8;
+  for (int64_t t = wave; t < a.n_tiles; t += n_waves) {
+    const int64_t g = t >> rb;
+    const uint32_t xt = pdep32((uint32_t)(t & ((int64_t(1) << rb) - 1)), a.rest);
+    const int64_t s = a.s0 + g;
+    float2 av[KQ], bv[KQ];
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) {
+      av[q] = make_float2(1.f, 0.f);
+      bv[q] = make_float2(1.f, 0.f);
+    }
+    for (int i = 0; i < a.n_ops; ++i) {
+      const int64_t base = a.gs[i] ? g * a.gs[i] : ((int64_t)pext32((uint32_t)s, a.sm[i]) << a.rk[i]);
+      const float2* src = a.src[i] + base + (pext32(xt, a.mk[i]) | plane[i]);
+      const bool is_b = (a.side_b >> i) & 1u;
+#pragma unroll
+      for (int q = 0; q < KQ; ++q) {
+        const float2 v = src[pterm[i][q]];
+        if (is_b)
+          bv[q] = cmul(bv[q], v);
+        else
+          av[q] = cmul(av[q], v);
+      }
+    }
+    floatx4 cre = {0.f, 0.f, 0.f, 0.f}, cim = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < 2 * KQ; ++c) {
+      const int q = c % KQ;
+      const bool im_slot = c >= KQ;
+      const float a1 = im_slot ? -av[q].y : av[q].x, b1 = im_slot ? bv[q].y : bv[q].x;
+      const float a2 = im_slot ? av[q].y : av[q].x, b2 = im_slot ? bv[q].x : bv[q].y;
+      cre = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, cre, 0, 0, 0);
+      cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, b2, cim, 0, 0, 0);
     }
     const int64_t ob = (g << r) | xt;
 #pragma unroll
@@ -1082,6 +1172,56 @@ static int launch_step(const Plan& p, const StepProg& sp, float2* arena, int64_t
     }
     a.mask[i] = o.mask;
     a.rank[i] = o.rank;
+  }
+  if (sp.mmk) {
+    // merged launch on MFMA: operand groups A' and B'
+    MmkLaunch m{};
+    m.out = a.out;
+    m.n_ops = sp.n_ops;
+    m.side_b = sp.mmk_side;
+    const uint32_t xmask = (1u << r) - 1u;
+    uint32_t xa = 0, xb = 0;
+    for (int i = 0; i < sp.n_ops; ++i) {
+      m.src[i] = a.src[i];
+      m.gs[i] = a.gstride[i];
+      m.sm[i] = a.smask[i];
+      m.rk[i] = a.rank[i];
+      m.mk[i] = a.mask[i];
+      ((sp.mmk_side >> i) & 1u ? xb : xa) |= a.mask[i] & xmask;
+    }
+    // the tile's column index is the lane's (16 consecutive lanes): give the
+    // column side the group owning the lowest private result bit, so that
+    // stores cover contiguous entries (the product is symmetric in A', B')
+    const uint32_t priv = (xa ^ xb) & xmask;
+    if (priv & xa & (~priv + 1u)) {
+      m.side_b = ~m.side_b & ((1u << sp.n_ops) - 1u);
+      std::swap(xa, xb);
+    }
+    uint32_t oa = xa & ~xb, ob = xb & ~xa;
+    for (int k = 0; k < 4; ++k) {
+      m.mtile |= oa & (~oa + 1u);
+      oa &= oa - 1u;
+      m.ntile |= ob & (~ob + 1u);
+      ob &= ob - 1u;
+    }
+    m.rest = xmask & ~m.mtile & ~m.ntile;
+    m.r = r;
+    m.s0 = s0;
+    m.G = G;
+    m.n_tiles = G << (r - 8);
+    if (wg_per_cu <= 0) wg_per_cu = sp.wg_per_cu > 0 ? sp.wg_per_cu : 8;
+    const int64_t want = (m.n_tiles + 3) / 4;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)n_cus() * wg_per_cu));
+    switch (sp.n_sum) {
+      case 2: mmk_kernel<2><<<grid, kBlock, 0, st>>>(m); break;
+      case 3: mmk_kernel<3><<<grid, kBlock, 0, st>>>(m); break;
+      case 4: mmk_kernel<4><<<grid, kBlock, 0, st>>>(m); break;
+      default:
+        set_error("merged MFMA launch with an unsupported summed-variable count");
+        return QBE_ERR_INTERNAL;
+    }
+    QBE_HIP(hipGetLastError());
+    return QBE_OK;
   }
   if (sp.mm_a >= 0 && sum_u && r >= 8) {
     MmLaunch m{};

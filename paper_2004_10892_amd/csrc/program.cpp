@@ -18,6 +18,7 @@
 #include <stdexcept>
 
 #include "qbe_internal.hpp"
+#include "../../include/qbe.h"
 
 namespace qbe {
 
@@ -393,6 +394,22 @@ void compile_plan(Plan& p) {
     StepProg sp{};
     sp.out_rank = rb;
     sp.n_sum = n_sum;
+    if (n_sum > 1 && rb >= 8 && p.precision == QBE_PREC_FP32 && ops.size() >= 2) {
+      // merged launch as a batched complex product on MFMA: the operands
+      // split into groups A and B, each with at least four result bits the
+      // other group lacks (the 16 x 16 tile bits); every other result bit is
+      // fixed per tile.  The first such split in operand order is taken.
+      const uint32_t xmask = (1u << rb) - 1u;
+      const uint32_t n = (uint32_t)ops.size();
+      for (uint32_t side = 1; side + 1 < (1u << n) && !sp.mmk; ++side) {
+        uint32_t xa = 0, xb = 0;
+        for (uint32_t i = 0; i < n; ++i) ((side >> i) & 1u ? xb : xa) |= ops[i].mask & xmask;
+        if (__builtin_popcount(xa & ~xb) >= 4 && __builtin_popcount(xb & ~xa) >= 4) {
+          sp.mmk = 1;
+          sp.mmk_side = side;
+        }
+      }
+    }
     if (n_sum == 1) {
       // outer-product shape: two operands hold x bits (and u), the rest only u
       const uint32_t ubit = 1u << rb, xmask = ubit - 1u;

@@ -33,11 +33,18 @@ std::string check_plan(const Plan& p) {
     if (sum_u ? (sp.n_sum < 1 || sp.n_sum > 4) : sp.n_sum != 0) return "summed variable count";
     const int xbits = r + sp.n_sum;
     if (r > 30 || xbits > 31) return "result rank above 30";
-    if (sp.n_sum > 1 && sp.mm_a >= 0) return "merged launch with an outer-product tile";
-    if (sp.n_ops < 1 || sp.n_ops > kMaxOps) return "operand count";
-    if (sp.out_base < 0 || sp.out_base + (int64_t(1) << r) > p.arena_per_slice)
-      return fail("result outside the arena", sp.out_base + (int64_t(1) << r), p.arena_per_slice);
-    if (sp.mm_a >= 0) {
+    if (sp.mmk) {
+      // the merged MFMA kernel's assumptions
+      const uint32_t xm = (1u << r) - 1u;
+      if (sp.n_sum < 2 || sp.n_sum > 4 || r < 8 || sp.mm_a >= 0) return "merged product shape";
+      if (sp.mmk_side == 0 || (sp.mmk_side >> sp.n_ops) != 0 || sp.mmk_side + 1 == (1u << sp.n_ops))
+        return "merged product groups";
+      uint32_t xa = 0, xb = 0;
+      for (int i = 0; i < sp.n_ops; ++i) ((sp.mmk_side >> i) & 1u ? xb : xa) |= sp.ops[i].mask & xm;
+      if (__builtin_popcount(xa & ~xb) < 4 || __builtin_popcount(xb & ~xa) < 4)
+        return "merged product tile needs four private bits per group";
+    }
+    if (sp.mm_a >= 0 && sp.n_sum == 1) {
       // the MFMA tile kernel's assumptions
       if (!sum_u || r < 8 || sp.mm_b < 0 || sp.mm_a == sp.mm_b || sp.mm_a >= sp.n_ops || sp.mm_b >= sp.n_ops)
         return "outer-product bucket shape";

@@ -61,6 +61,11 @@ struct StepProg {
   // run on MFMA in 16 x 16 result tiles: indices of A and B in ops, -1 if
   // the bucket is not of that shape.
   int32_t mm_a = -1, mm_b = -1;
+  // Merged launches (n_sum > 1) that run as a batched complex product on
+  // MFMA: bit i set = operand i belongs to the B group, clear = A group;
+  // mmk = 0 when the launch is not of that shape.
+  int32_t mmk = 0;
+  uint32_t mmk_side = 0;
   StepOp ops[kMaxOps];
 };
 
