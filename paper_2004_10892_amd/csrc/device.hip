@@ -69,6 +69,8 @@ __global__ void prep_kernel(const double2* __restrict__ raw, const int32_t* __re
 
 // --------------------------------------------------------------- per-step --
 
+constexpr int kMaxSumTerms = 16;  // 2^n_sum for a merged launch (n_sum <= 4)
+
 struct StepLaunch {
   float2* out;
   const float2* src[kMaxOps];
@@ -79,173 +81,309 @@ struct StepLaunch {
   int32_t n_ops;
   int32_t r;       // bits of x
   int32_t sum_u;   // 1: sum over the top bit u of X
-  int32_t n_sum;   // msum_kernel: summed top bits of X
+  int32_t n_sum;   // msum kernels: summed top bits of X
   int32_t lo;      // min(r, kLoBits)
   int64_t s0;      // first slice of the group
   int64_t G;       // slices in the group
   int64_t n_tiles;
+  // msum kernels: byte offset of operand i's entry for summed value u above
+  // its entry for u = 0, and the bits of u the operand holds
+  uint32_t uoff[kMaxSumTerms][kMaxOps];
+  uint32_t uhold[kMaxOps];
 };
 
-// EPT: tiles whose operand loads are all issued before any of them is
-// used (more bytes in flight per thread).
+// Global-memory views of addresses carried as integers (a generic pointer
+// would compile to flat accesses).
+typedef const __attribute__((address_space(1))) char* gcbytep;
+typedef __attribute__((address_space(1))) char* gbytep;
+
+typedef float gf32x2 __attribute__((ext_vector_type(2)));
+
+// Load at a wave-uniform base plus a per-lane 32-bit byte offset.
+__device__ __forceinline__ float2 ld_sv(uint64_t base, uint32_t byte_off) {
+  const gf32x2 v = *(const __attribute__((address_space(1))) gf32x2*)((gcbytep)base + byte_off);
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void st_sv(uint64_t base, uint32_t byte_off, float2 v) {
+  *(__attribute__((address_space(1))) gf32x2*)((gbytep)base + byte_off) = gf32x2{v.x, v.y};
+}
+
+// A 64-bit wave-uniform value held by lane k.
+__device__ __forceinline__ uint64_t lane64(uint64_t v, int k) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, k);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), k);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Tiling of step_kernel and msum_kernel (r >= kLoBits).  A tile is 256
+// consecutive result entries of one slice: the lane supplies x_lo (the low 8
+// bits of x), the tile the slice g and x_hi.  A super-tile is EPT tiles that
+// differ only in the lowest bits of x_hi (EPT divides 2^hib); the block takes
+// super-tiles q = blockIdx.x + j * gridDim.x.  An operand's entry offset is
+// linear over disjoint bit sets, so it splits into a per-lane part (x_lo and
+// the sub-tile bits, fixed for the kernel) and a per-super-tile part (slice
+// and the rest of x_hi).  The per-super-tile addresses of 64 super-tiles at a
+// time are worked out in vector code, lane l taking the l-th of them, and the
+// tile loop reads them back with readlane: the per-tile index work is off
+// the scalar unit.
+template <int K, int EPT>
+struct TileSetup {
+  uint32_t lofs[EPT][K];  // per-lane byte offsets
+  uint32_t hi_mask[K];    // x_hi bits of each operand
+  int lo_cnt[K];          // operand bits below x_hi
+  int hib;
+  int64_t n_super;
+
+  __device__ __forceinline__ TileSetup(const StepLaunch& a, uint32_t x_lo) {
+    hib = a.r - kLoBits;
+    n_super = a.n_tiles / EPT;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      const uint32_t m = a.mask[i];
+      const uint32_t lp = pext32(x_lo, m & (kBlock - 1));
+      lo_cnt[i] = __builtin_popcount(m & (kBlock - 1));
+      const uint32_t hm = (m >> kLoBits) & ((1u << hib) - 1u);
+      hi_mask[i] = hm;
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) lofs[e][i] = (lp + (pext32((uint32_t)e, hm) << lo_cnt[i])) * 8u;
+    }
+  }
+
+  // Lane l: operand base addresses and the result address (entry x_lo = 0
+  // of the first tile) of the block's super-tile q0 + l * gridDim.x.  Lanes
+  // past the end compute addresses that are never used.
+  __device__ __forceinline__ void decode(const StepLaunch& a, int64_t q0, int lane, uint64_t (&pl)[K],
+                                         uint64_t& ol) const {
+    const int64_t tl = (q0 + (int64_t)lane * gridDim.x) * EPT;
+    const int64_t g = tl >> hib;
+    const uint32_t xl = (uint32_t)(tl & ((int64_t(1) << hib) - 1));
+    const uint32_t s = (uint32_t)(a.s0 + g);
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      const uint32_t sp = a.gstride[i] != 0 ? 0u : pext32(s, a.smask[i]) << a.rank[i];
+      const uint32_t off = sp + (pext32(xl, hi_mask[i]) << lo_cnt[i]);
+      pl[i] = (uint64_t)(a.src[i] + g * a.gstride[i] + off);
+    }
+    ol = (uint64_t)(a.out + (g << a.r) + ((int64_t)xl << kLoBits));
+  }
+
+  // super-tiles of this block from q0 on that one decode covers
+  __device__ __forceinline__ int count(int64_t q0) const {
+    return (int)std::min<int64_t>(64, (n_super - q0 + gridDim.x - 1) / gridDim.x);
+  }
+};
+
+// One bucket (n_sum <= 1) for r >= kLoBits: result entry
+// sum_u prod_i T_i[pext(X, mask_i)] per lane and tile.
 template <int K, int EPT>
 __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch a) {
-  const int tid = threadIdx.x;
-  const int r = a.r, lo = a.lo;
-  const uint32_t lomask = (1u << lo) - 1u;
-  const uint32_t x_lo = (uint32_t)tid & lomask;
-  const int64_t g_sub = tid >> lo;  // r < kLoBits: several slices per tile
-  const int64_t spt = (int64_t)(kBlock >> lo);
-  const int hib = r - lo;
-  uint32_t lo_part[K], u_part[K], hi_mask[K];
-  int lo_cnt[K];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int r = a.r;
+  const TileSetup<K, EPT> ts(a, (uint32_t)tid);
+  uint32_t ustep[K];  // bytes from an operand's u = 0 entry to its u = 1 entry
 #pragma unroll
-  for (int i = 0; i < K; ++i) {
-    const uint32_t m = a.mask[i];
-    lo_part[i] = pext32(x_lo, m & lomask);
-    lo_cnt[i] = __builtin_popcount(m & lomask);
-    hi_mask[i] = (m >> lo) & ((1u << hib) - 1u);
-    u_part[i] = (a.sum_u && ((m >> r) & 1u)) ? (1u << (a.rank[i] - 1)) : 0u;
-  }
-  for (int64_t t0 = (int64_t)blockIdx.x * EPT; t0 < a.n_tiles; t0 += (int64_t)gridDim.x * EPT) {
-    float2 v0[EPT][K], v1[EPT][K];
-    int64_t oidx[EPT];
-    bool ok[EPT];
+  for (int i = 0; i < K; ++i)
+    ustep[i] = (a.sum_u && ((a.mask[i] >> r) & 1u)) ? (1u << (a.rank[i] - 1)) * 8u : 0u;
+  for (int64_t q0 = blockIdx.x; q0 < ts.n_super; q0 += 64 * (int64_t)gridDim.x) {
+    uint64_t pl[K], ol;
+    ts.decode(a, q0, lane, pl, ol);
+    const int n_here = ts.count(q0);
+    for (int jj = 0; jj < n_here; ++jj) {
+      float2 v0[EPT][K], v1[EPT][K];
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      const int64_t tile = t0 + e;
-      int64_t g;
-      uint32_t x_hi;
-      if (hib > 0) {
-        g = tile >> hib;
-        x_hi = (uint32_t)(tile & ((int64_t(1) << hib) - 1));
-        ok[e] = tile < a.n_tiles;
-      } else {
-        g = tile * spt + g_sub;
-        x_hi = 0;
-        ok[e] = tile < a.n_tiles && g < a.G;
-      }
-      oidx[e] = (g << r) + ((int64_t)x_hi << lo) + x_lo;
-      if (ok[e]) {
-        const int64_t s = a.s0 + g;
+      for (int i = 0; i < K; ++i) {
+        const uint64_t b = lane64(pl[i], jj), b1 = b + ustep[i];
 #pragma unroll
-        for (int i = 0; i < K; ++i) {
-          int64_t base;
-          if (a.gstride[i] != 0)
-            base = g * a.gstride[i];
-          else
-            base = (int64_t)pext32((uint32_t)s, a.smask[i]) << a.rank[i];
-          base += (int64_t)(pext32(x_hi, hi_mask[i]) << lo_cnt[i]) + lo_part[i];
-          const float2* q = a.src[i] + base;
-          v0[e][i] = q[0];
-          v1[e][i] = q[u_part[i]];
+        for (int e = 0; e < EPT; ++e) {
+          v0[e][i] = ld_sv(b, ts.lofs[e][i]);
+          if (a.sum_u) v1[e][i] = ld_sv(b1, ts.lofs[e][i]);
         }
       }
-    }
+      __builtin_amdgcn_sched_barrier(0);
+      const uint64_t o = lane64(ol, jj);
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      if (!ok[e]) continue;
-      float2 acc = v0[e][0];
+      for (int e = 0; e < EPT; ++e) {
+        float2 acc = v0[e][0];
 #pragma unroll
-      for (int i = 1; i < K; ++i) acc = cmul(acc, v0[e][i]);
-      if (a.sum_u) {
-        float2 t = v1[e][0];
+        for (int i = 1; i < K; ++i) acc = cmul(acc, v0[e][i]);
+        if (a.sum_u) {
+          float2 u1 = v1[e][0];
 #pragma unroll
-        for (int i = 1; i < K; ++i) t = cmul(t, v1[e][i]);
-        acc.x += t.x;
-        acc.y += t.y;
+          for (int i = 1; i < K; ++i) u1 = cmul(u1, v1[e][i]);
+          acc.x += u1.x;
+          acc.y += u1.y;
+        }
+        st_sv(o, (uint32_t)((e << kLoBits) + tid) * 8u, acc);
       }
-      a.out[oidx[e]] = acc;
     }
   }
 }
 
-// A launch that merges a chain of buckets: the top n_sum bits of X are
-// summed (2^n_sum >= 4 terms per result entry).  The offset of operand i's entry
-// for summed value u is pext(u, the operand's summed-bit mask) above its x
-// bits -- the same for every lane, so that part is scalar work; the tiling
-// over x is that of step_kernel.
+// A launch that merges a chain of buckets (r >= kLoBits): the top n_sum
+// bits of X are summed, 2^n_sum >= 4 terms per result entry.  Operand i's
+// entry for summed value u sits uoff[u][i] bytes above its u = 0 entry, the
+// same for every lane and tile, so the term loop adds a table entry to a
+// scalar base.
 template <int K, int EPT>
 __global__ __launch_bounds__(kBlock) void msum_kernel(StepLaunch a) {
-  const int tid = threadIdx.x;
-  const int r = a.r, lo = a.lo;
-  const uint32_t lomask = (1u << lo) - 1u;
-  const uint32_t x_lo = (uint32_t)tid & lomask;
-  const int64_t g_sub = tid >> lo;
-  const int64_t spt = (int64_t)(kBlock >> lo);
-  const int hib = r - lo;
-  const uint32_t nu = 1u << a.n_sum;
-  uint32_t lo_part[K], hi_mask[K], umask[K];
-  int lo_cnt[K], xcnt[K];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int r = a.r;
+  const TileSetup<K, EPT> ts(a, (uint32_t)tid);
+  const int nu = 1 << a.n_sum;
+  for (int64_t q0 = blockIdx.x; q0 < ts.n_super; q0 += 64 * (int64_t)gridDim.x) {
+    uint64_t pl[K], ol;
+    ts.decode(a, q0, lane, pl, ol);
+    const int n_here = ts.count(q0);
+    for (int jj = 0; jj < n_here; ++jj) {
+      uint64_t b[K];
 #pragma unroll
-  for (int i = 0; i < K; ++i) {
-    const uint32_t m = a.mask[i];
-    lo_part[i] = pext32(x_lo, m & lomask);
-    lo_cnt[i] = __builtin_popcount(m & lomask);
-    hi_mask[i] = (m >> lo) & ((1u << hib) - 1u);
-    umask[i] = m >> r;
-    xcnt[i] = __builtin_popcount(m & ((1u << r) - 1u));
-  }
-  for (int64_t t0 = (int64_t)blockIdx.x * EPT; t0 < a.n_tiles; t0 += (int64_t)gridDim.x * EPT) {
-    const float2* q[EPT][K];
-    int64_t oidx[EPT];
-    bool ok[EPT];
+      for (int i = 0; i < K; ++i) b[i] = lane64(pl[i], jj);
+      float2 acc[EPT];
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      const int64_t tile = t0 + e;
-      int64_t g;
-      uint32_t x_hi;
-      if (hib > 0) {
-        g = tile >> hib;
-        x_hi = (uint32_t)(tile & ((int64_t(1) << hib) - 1));
-        ok[e] = tile < a.n_tiles;
-      } else {
-        g = tile * spt + g_sub;
-        x_hi = 0;
-        ok[e] = tile < a.n_tiles && g < a.G;
-      }
-      oidx[e] = (g << r) + ((int64_t)x_hi << lo) + x_lo;
-      const int64_t s = a.s0 + g;
+      for (int e = 0; e < EPT; ++e) acc[e] = make_float2(0.f, 0.f);
+      // Four terms per trip, over the two lowest summed bits d: a factor
+      // holding c = its bits of d has 2^popcount(c) distinct entries in the
+      // trip, read once each, all loads in flight together.  Factors with
+      // c = 0 are common to the four terms and multiply their sum.
+      for (int u0 = 0; u0 < nu; u0 += 4) {
+        float2 v[4][EPT][K];
 #pragma unroll
-      for (int i = 0; i < K; ++i) {
-        int64_t base;
-        if (a.gstride[i] != 0)
-          base = g * a.gstride[i];
-        else
-          base = (int64_t)pext32((uint32_t)s, a.smask[i]) << a.rank[i];
-        base += (int64_t)(pext32(x_hi, hi_mask[i]) << lo_cnt[i]) + lo_part[i];
-        q[e][i] = a.src[i] + base;
-      }
-    }
-    float2 acc[EPT];
+        for (int i = 0; i < K; ++i) {
+          const uint32_t c = a.uhold[i] & 3u;
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) acc[e] = make_float2(0.f, 0.f);
-    // four terms per trip (2^n_sum >= 4), all their loads in flight together
-    for (uint32_t u0 = 0; u0 < nu; u0 += 4) {
-      float2 v[4][EPT][K];
+          for (int du = 0; du < 4; ++du)
+            if (((uint32_t)du & ~c) == 0u) {
+              const uint64_t bu = b[i] + a.uoff[u0 + du][i];
 #pragma unroll
-      for (int du = 0; du < 4; ++du) {
-        uint32_t off[K];
-#pragma unroll
-        for (int i = 0; i < K; ++i) off[i] = pext32(u0 + du, umask[i]) << xcnt[i];
-#pragma unroll
-        for (int e = 0; e < EPT; ++e)
-#pragma unroll
-          for (int i = 0; i < K; ++i) v[du][e][i] = ok[e] ? q[e][i][off[i]] : make_float2(0.f, 0.f);
-      }
-#pragma unroll
-      for (int du = 0; du < 4; ++du)
+              for (int e = 0; e < EPT; ++e) v[du][e][i] = ld_sv(bu, ts.lofs[e][i]);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        float2 cm[EPT], pr[4][EPT];
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
-          float2 p = v[du][e][0];
+          cm[e] = make_float2(1.f, 0.f);
 #pragma unroll
-          for (int i = 1; i < K; ++i) p = cmul(p, v[du][e][i]);
-          acc[e] = make_float2(acc[e].x + p.x, acc[e].y + p.y);
+          for (int du = 0; du < 4; ++du) pr[du][e] = make_float2(1.f, 0.f);
         }
-    }
 #pragma unroll
-    for (int e = 0; e < EPT; ++e)
-      if (ok[e]) a.out[oidx[e]] = acc[e];
+        for (int i = 0; i < K; ++i) {
+          const uint32_t c = a.uhold[i] & 3u;
+          if (c == 0u) {
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) cm[e] = cmul(cm[e], v[0][e][i]);
+          } else if (c == 1u) {
+#pragma unroll
+            for (int du = 0; du < 4; ++du)
+#pragma unroll
+              for (int e = 0; e < EPT; ++e) pr[du][e] = cmul(pr[du][e], v[du & 1][e][i]);
+          } else if (c == 2u) {
+#pragma unroll
+            for (int du = 0; du < 4; ++du)
+#pragma unroll
+              for (int e = 0; e < EPT; ++e) pr[du][e] = cmul(pr[du][e], v[du & 2][e][i]);
+          } else {
+#pragma unroll
+            for (int du = 0; du < 4; ++du)
+#pragma unroll
+              for (int e = 0; e < EPT; ++e) pr[du][e] = cmul(pr[du][e], v[du][e][i]);
+          }
+        }
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+          const float2 t = make_float2(pr[0][e].x + pr[1][e].x + pr[2][e].x + pr[3][e].x,
+                                       pr[0][e].y + pr[1][e].y + pr[2][e].y + pr[3][e].y);
+          const float2 q = cmul(cm[e], t);
+          acc[e] = make_float2(acc[e].x + q.x, acc[e].y + q.y);
+        }
+      }
+      const uint64_t o = lane64(ol, jj);
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) st_sv(o, (uint32_t)((e << kLoBits) + tid) * 8u, acc[e]);
+    }
+  }
+}
+
+// Small results (r < kLoBits): a tile holds 256 >> r whole slices, so the
+// slice index comes from the lane.  step_small_kernel is step_kernel's
+// bucket, msum_small_kernel msum_kernel's merged chain.
+template <int K>
+__global__ __launch_bounds__(kBlock) void step_small_kernel(StepLaunch a) {
+  const int tid = threadIdx.x;
+  const int r = a.r;
+  const uint32_t x = (uint32_t)tid & ((1u << r) - 1u);
+  const int64_t g_sub = tid >> r;
+  const int64_t spt = (int64_t)(kBlock >> r);
+  uint32_t xpart[K], u_part[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    xpart[i] = pext32(x, a.mask[i]);
+    u_part[i] = (a.sum_u && ((a.mask[i] >> r) & 1u)) ? (1u << (a.rank[i] - 1)) : 0u;
+  }
+  for (int64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+    const int64_t g = tile * spt + g_sub;
+    if (g >= a.G) continue;
+    const int64_t s = a.s0 + g;
+    float2 v0[K], v1[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      int64_t base;
+      if (a.gstride[i] != 0)
+        base = g * a.gstride[i];
+      else
+        base = (int64_t)pext32((uint32_t)s, a.smask[i]) << a.rank[i];
+      const float2* q = a.src[i] + base + xpart[i];
+      v0[i] = q[0];
+      v1[i] = q[u_part[i]];
+    }
+    float2 acc = v0[0];
+#pragma unroll
+    for (int i = 1; i < K; ++i) acc = cmul(acc, v0[i]);
+    if (a.sum_u) {
+      float2 t = v1[0];
+#pragma unroll
+      for (int i = 1; i < K; ++i) t = cmul(t, v1[i]);
+      acc.x += t.x;
+      acc.y += t.y;
+    }
+    a.out[(g << r) + x] = acc;
+  }
+}
+
+template <int K>
+__global__ __launch_bounds__(kBlock) void msum_small_kernel(StepLaunch a) {
+  const int tid = threadIdx.x;
+  const int r = a.r;
+  const uint32_t x = (uint32_t)tid & ((1u << r) - 1u);
+  const int64_t g_sub = tid >> r;
+  const int64_t spt = (int64_t)(kBlock >> r);
+  const int nu = 1 << a.n_sum;
+  uint32_t xpart[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) xpart[i] = pext32(x, a.mask[i]) * 8u;
+  for (int64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+    const int64_t g = tile * spt + g_sub;
+    if (g >= a.G) continue;
+    const int64_t s = a.s0 + g;
+    const char* q[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      int64_t base;
+      if (a.gstride[i] != 0)
+        base = g * a.gstride[i];
+      else
+        base = (int64_t)pext32((uint32_t)s, a.smask[i]) << a.rank[i];
+      q[i] = (const char*)(a.src[i] + base) + xpart[i];
+    }
+    float2 acc = make_float2(0.f, 0.f);
+    for (int u = 0; u < nu; ++u) {
+      float2 p = *(const float2*)(q[0] + a.uoff[u][0]);
+#pragma unroll
+      for (int i = 1; i < K; ++i) p = cmul(p, *(const float2*)(q[i] + a.uoff[u][i]));
+      acc.x += p.x;
+      acc.y += p.y;
+    }
+    a.out[(g << r) + x] = acc;
   }
 }
 
@@ -421,64 +559,82 @@ struct MmkLaunch {
   int64_t s0, G, n_tiles;
 };
 
-template <int J>
+// Tiles are decoded as in step_kernel: lane l of a wavefront works out the
+// slice, the tile's result bits and the operands' offsets for the wave's
+// l-th next tile, and the tile loop reads them back with readlane.
+template <int J, int K>
 __global__ __launch_bounds__(kBlock) void mmk_kernel(MmkLaunch a) {
   constexpr int KQ = (1 << J) / 4;  // terms a lane supplies per side
   const int lane = threadIdx.x & 63;
   const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
   const int64_t n_waves = (int64_t)gridDim.x * (kBlock / 64);
   const int r = a.r;
+  const int rb = r - 8;
   const int row = lane & 15, grp = lane >> 4;
   const uint32_t xm = pdep32((uint32_t)row, a.mtile), xn = pdep32((uint32_t)row, a.ntile);
-  uint32_t oo[4];
+  uint32_t oo[4];  // bytes
 #pragma unroll
-  for (int i = 0; i < 4; ++i) oo[i] = pdep32((uint32_t)(4 * grp + i), a.mtile) | xn;
+  for (int i = 0; i < 4; ++i) oo[i] = (pdep32((uint32_t)(4 * grp + i), a.mtile) | xn) * 8u;
   // bit extraction is linear over disjoint bit sets, so an operand's index
   // is the OR of the parts from the lane's tile bits and term (fixed per
   // lane), and from the tile's other bits (fixed per tile)
-  uint32_t plane[kMaxOps], pterm[kMaxOps][KQ];
-  for (int i = 0; i < a.n_ops; ++i) {
-    plane[i] = pext32(((a.side_b >> i) & 1u) ? xn : xm, a.mk[i]);
+  uint32_t lofs[K][KQ];  // bytes
 #pragma unroll
-    for (int q = 0; q < KQ; ++q) pterm[i][q] = pext32((uint32_t)(4 * q + grp) << r, a.mk[i]);
+  for (int i = 0; i < K; ++i) {
+    const uint32_t plane = pext32(((a.side_b >> i) & 1u) ? xn : xm, a.mk[i]);
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) lofs[i][q] = (plane | pext32((uint32_t)(4 * q + grp) << r, a.mk[i])) * 8u;
   }
-  const int rb = r - 8;
-  for (int64_t t = wave; t < a.n_tiles; t += n_waves) {
-    const int64_t g = t >> rb;
-    const uint32_t xt = pdep32((uint32_t)(t & ((int64_t(1) << rb) - 1)), a.rest);
-    const int64_t s = a.s0 + g;
-    float2 av[KQ], bv[KQ];
+  for (int64_t t0 = wave; t0 < a.n_tiles; t0 += 64 * n_waves) {
+    // lane l: tile t0 + l * n_waves (lanes past the end compute values that
+    // are never read)
+    const int64_t tl = t0 + (int64_t)lane * n_waves;
+    const int32_t gl = (int32_t)(tl >> rb);
+    const uint32_t xtl = pdep32((uint32_t)(tl & ((int64_t(1) << rb) - 1)), a.rest);
+    const uint32_t sl = (uint32_t)(a.s0 + gl);
+    uint64_t pl[K];
 #pragma unroll
-    for (int q = 0; q < KQ; ++q) {
-      av[q] = make_float2(1.f, 0.f);
-      bv[q] = make_float2(1.f, 0.f);
+    for (int i = 0; i < K; ++i) {
+      const uint32_t off = (a.gs[i] ? 0u : pext32(sl, a.sm[i]) << a.rk[i]) + pext32(xtl, a.mk[i]);
+      pl[i] = (uint64_t)(a.src[i] + (int64_t)gl * a.gs[i] + off);
     }
-    for (int i = 0; i < a.n_ops; ++i) {
-      const int64_t base = a.gs[i] ? g * a.gs[i] : ((int64_t)pext32((uint32_t)s, a.sm[i]) << a.rk[i]);
-      const float2* src = a.src[i] + base + (pext32(xt, a.mk[i]) | plane[i]);
-      const bool is_b = (a.side_b >> i) & 1u;
+    const uint64_t obl = (uint64_t)(a.out + (((int64_t)gl << r) | xtl));
+    const int n_here = (int)std::min<int64_t>(64, (a.n_tiles - t0 + n_waves - 1) / n_waves);
+    for (int k = 0; k < n_here; ++k) {
+      float2 av[KQ], bv[KQ];
 #pragma unroll
       for (int q = 0; q < KQ; ++q) {
-        const float2 v = src[pterm[i][q]];
-        if (is_b)
-          bv[q] = cmul(bv[q], v);
-        else
-          av[q] = cmul(av[q], v);
+        av[q] = make_float2(1.f, 0.f);
+        bv[q] = make_float2(1.f, 0.f);
       }
-    }
-    floatx4 cre = {0.f, 0.f, 0.f, 0.f}, cim = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int c = 0; c < 2 * KQ; ++c) {
-      const int q = c % KQ;
-      const bool im_slot = c >= KQ;
-      const float a1 = im_slot ? -av[q].y : av[q].x, b1 = im_slot ? bv[q].y : bv[q].x;
-      const float a2 = im_slot ? av[q].y : av[q].x, b2 = im_slot ? bv[q].x : bv[q].y;
-      cre = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, cre, 0, 0, 0);
-      cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, b2, cim, 0, 0, 0);
-    }
-    const int64_t ob = (g << r) | xt;
+      for (int i = 0; i < K; ++i) {
+        const uint64_t base = lane64(pl[i], k);
+        float2 v[KQ];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) a.out[ob | oo[i]] = make_float2(cre[i], cim[i]);
+        for (int q = 0; q < KQ; ++q) v[q] = ld_sv(base, lofs[i][q]);
+        if ((a.side_b >> i) & 1u) {
+#pragma unroll
+          for (int q = 0; q < KQ; ++q) bv[q] = cmul(bv[q], v[q]);
+        } else {
+#pragma unroll
+          for (int q = 0; q < KQ; ++q) av[q] = cmul(av[q], v[q]);
+        }
+      }
+      floatx4 cre = {0.f, 0.f, 0.f, 0.f}, cim = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int c = 0; c < 2 * KQ; ++c) {
+        const int q = c % KQ;
+        const bool im_slot = c >= KQ;
+        const float a1 = im_slot ? -av[q].y : av[q].x, b1 = im_slot ? bv[q].y : bv[q].x;
+        const float a2 = im_slot ? av[q].y : av[q].x, b2 = im_slot ? bv[q].x : bv[q].y;
+        cre = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, cre, 0, 0, 0);
+        cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, b2, cim, 0, 0, 0);
+      }
+      const uint64_t ob = lane64(obl, k);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) st_sv(ob, oo[i], make_float2(cre[i], cim[i]));
+    }
   }
 }
 
@@ -1212,14 +1368,20 @@ static int launch_step(const Plan& p, const StepProg& sp, float2* arena, int64_t
     if (wg_per_cu <= 0) wg_per_cu = sp.wg_per_cu > 0 ? sp.wg_per_cu : 8;
     const int64_t want = (m.n_tiles + 3) / 4;
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)n_cus() * wg_per_cu));
-    switch (sp.n_sum) {
-      case 2: mmk_kernel<2><<<grid, kBlock, 0, st>>>(m); break;
-      case 3: mmk_kernel<3><<<grid, kBlock, 0, st>>>(m); break;
-      case 4: mmk_kernel<4><<<grid, kBlock, 0, st>>>(m); break;
+#define QBE_MMK(JJ, KK)                                                       \
+  case JJ * 16 + KK:                                                          \
+    mmk_kernel<JJ, KK><<<grid, kBlock, 0, st>>>(m);                           \
+    break;
+#define QBE_MMKS(JJ) \
+  QBE_MMK(JJ, 2) QBE_MMK(JJ, 3) QBE_MMK(JJ, 4) QBE_MMK(JJ, 5) QBE_MMK(JJ, 6) QBE_MMK(JJ, 7) QBE_MMK(JJ, 8)
+    switch (sp.n_sum * 16 + sp.n_ops) {
+      QBE_MMKS(2) QBE_MMKS(3) QBE_MMKS(4)
       default:
-        set_error("merged MFMA launch with an unsupported summed-variable count");
+        set_error("merged MFMA launch with an unsupported summed-variable or operand count");
         return QBE_ERR_INTERNAL;
     }
+#undef QBE_MMKS
+#undef QBE_MMK
     QBE_HIP(hipGetLastError());
     return QBE_OK;
   }
@@ -1266,11 +1428,63 @@ static int launch_step(const Plan& p, const StepProg& sp, float2* arena, int64_t
     QBE_HIP(hipGetLastError());
     return QBE_OK;
   }
-  const int hib = r - a.lo;
-  a.n_tiles = hib > 0 ? (G << hib) : (G + (kBlock >> a.lo) - 1) / (kBlock >> a.lo);
-  if (ept <= 0) ept = sp.ept > 0 ? sp.ept : 1;
+  if (sp.n_sum > 1) {
+    if (sp.n_sum > 4) {
+      set_error("merged launch with more than four summed variables");
+      return QBE_ERR_INTERNAL;
+    }
+    const uint32_t xmask = (1u << r) - 1u;
+    for (int i = 0; i < sp.n_ops; ++i) {
+      if (a.rank[i] > 28) {
+        set_error("merged launch operand above 2^28 entries");
+        return QBE_ERR_INTERNAL;
+      }
+      // summed variables sit above the operand's x bits, in union order;
+      // the kernel's bit b of u is union bit r + sum_bit[b]
+      const uint32_t um = a.mask[i] >> r;
+      const int xc = __builtin_popcount(a.mask[i] & xmask);
+      a.uhold[i] = 0;
+      for (int b = 0; b < sp.n_sum; ++b) a.uhold[i] |= ((um >> sp.sum_bit[b]) & 1u) << b;
+      for (int u = 0; u < (1 << sp.n_sum); ++u) {
+        uint32_t ux = 0;
+        for (int b = 0; b < sp.n_sum; ++b) ux |= (((uint32_t)u >> b) & 1u) << sp.sum_bit[b];
+        uint32_t e = 0;
+        int k = 0;
+        for (int t = 0; t < sp.n_sum; ++t)
+          if ((um >> t) & 1u) e |= ((ux >> t) & 1u) << k++;
+        a.uoff[u][i] = (e << xc) * 8u;
+      }
+    }
+  }
   if (wg_per_cu <= 0) wg_per_cu = sp.wg_per_cu > 0 ? sp.wg_per_cu : 16;
-  const int64_t want = (a.n_tiles + ept - 1) / ept;
+  if (r < kLoBits) {
+    // several whole slices per tile
+    a.n_tiles = (G + (kBlock >> r) - 1) / (kBlock >> r);
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(a.n_tiles, (int64_t)n_cus() * wg_per_cu));
+#define QBE_SMALL(KK)                                                         \
+  case KK:                                                                    \
+    if (sp.n_sum > 1)                                                         \
+      msum_small_kernel<KK><<<grid, kBlock, 0, st>>>(a);                      \
+    else                                                                      \
+      step_small_kernel<KK><<<grid, kBlock, 0, st>>>(a);                      \
+    break;
+    switch (sp.n_ops) {
+      QBE_SMALL(1) QBE_SMALL(2) QBE_SMALL(3) QBE_SMALL(4) QBE_SMALL(5) QBE_SMALL(6) QBE_SMALL(7)
+      QBE_SMALL(8)
+      default:
+        set_error("per-step launch with an unsupported operand count");
+        return QBE_ERR_INTERNAL;
+    }
+#undef QBE_SMALL
+    QBE_HIP(hipGetLastError());
+    return QBE_OK;
+  }
+  const int hib = r - kLoBits;
+  a.n_tiles = G << hib;
+  if (ept <= 0) ept = sp.ept > 0 ? sp.ept : 1;
+  // a super-tile's EPT tiles share the slice: EPT divides 2^hib
+  while (ept > 1 && (int64_t(1) << hib) % ept != 0) ept >>= 1;
+  const int64_t want = a.n_tiles / ept;
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)n_cus() * wg_per_cu));
 #define QBE_CASE(KK, EE)                                                      \
   case KK * 16 + EE:                                                          \

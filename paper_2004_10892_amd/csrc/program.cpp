@@ -394,6 +394,30 @@ void compile_plan(Plan& p) {
     StepProg sp{};
     sp.out_rank = rb;
     sp.n_sum = n_sum;
+    if (n_sum > 2) {
+      // The multi-term kernel runs four terms at a time over its two lowest
+      // summed-value bits and reads a factor's entries once per distinct
+      // value of the bits of those two it holds: give them to the pair of
+      // summed variables that keeps that count smallest.  Union bit r_b + t
+      // is summed variable uni[n_sum - 1 - t].
+      int best = -1, bp = 0, bq = 1;
+      for (int ti = 0; ti < n_sum; ++ti)
+        for (int tj = ti + 1; tj < n_sum; ++tj) {
+          int cost = 0;
+          for (const StepOp& o : ops)
+            cost += 1 << ((int)((o.mask >> (rb + ti)) & 1u) + (int)((o.mask >> (rb + tj)) & 1u));
+          if (best < 0 || cost < best) {
+            best = cost;
+            bp = ti;
+            bq = tj;
+          }
+        }
+      int nb = 0;
+      sp.sum_bit[nb++] = bp;
+      sp.sum_bit[nb++] = bq;
+      for (int t = 0; t < n_sum; ++t)
+        if (t != bp && t != bq) sp.sum_bit[nb++] = t;
+    }
     if (n_sum > 1 && rb >= 8 && p.precision == QBE_PREC_FP32 && ops.size() >= 2) {
       // merged launch as a batched complex product on MFMA: the operands
       // split into groups A and B, each with at least four result bits the

@@ -33,6 +33,15 @@ std::string check_plan(const Plan& p) {
     if (sum_u ? (sp.n_sum < 1 || sp.n_sum > 4) : sp.n_sum != 0) return "summed variable count";
     const int xbits = r + sp.n_sum;
     if (r > 30 || xbits > 31) return "result rank above 30";
+    if (sp.n_sum > 1) {
+      // the multi-term kernel's summed-value bits: a permutation
+      uint32_t seen = 0;
+      for (int b = 0; b < sp.n_sum; ++b) {
+        if (sp.sum_bit[b] < 0 || sp.sum_bit[b] >= sp.n_sum) return "summed bit order";
+        seen |= 1u << sp.sum_bit[b];
+      }
+      if (seen + 1 != (1u << sp.n_sum)) return "summed bit order";
+    }
     if (sp.mmk) {
       // the merged MFMA kernel's assumptions
       const uint32_t xm = (1u << r) - 1u;

@@ -66,6 +66,10 @@ struct StepProg {
   // mmk = 0 when the launch is not of that shape.
   int32_t mmk = 0;
   uint32_t mmk_side = 0;
+  // Merged launches on the multi-term kernel: the kernel's summed-value bit
+  // b is union index bit r_b + sum_bit[b] (a permutation of 0..n_sum-1; the
+  // kernel handles its two lowest bits four terms at a time).
+  int32_t sum_bit[4] = {0, 1, 2, 3};
   StepOp ops[kMaxOps];
 };
 
