@@ -1,0 +1,77 @@
+// Fused (LDS-resident) form: launch constants and the program format the
+// plan compiler (program.cpp) writes and the fused executor (fused.hip)
+// reads.  Not part of the ABI.
+#pragma once
+
+#include <cstdint>
+
+namespace qbe {
+
+// Threads of a fused workgroup.
+constexpr int kFusedBlock = 512;
+// LDS budget of one fused workgroup (bytes): tensor entries, plus the
+// program's records when they fit too (gfx950: 160 KB per workgroup).
+constexpr int kFusedLdsMax = 160 * 1024 - 256;
+// Largest slice count whose FP64 sum the fused kernel does itself (the
+// last workgroup of a plan); above it a separate reduction kernel runs.
+constexpr int64_t kInKernelReduceMax = 8192;
+
+// --------------------------------------------------------- fused (LDS) form --
+
+// A fused program lives in device memory (uint32 words) and is read from
+// there (through the caches); the workgroup keeps the tensor entries and a
+// copy of the level table in LDS.  A level holds nodes: a root bucket and
+// the buckets it absorbed (the plan compiler merges buckets along chains of
+// the dependency tree); an entry of a node's result sums T = 2^lgT terms,
+// one per assignment of the members' eliminated variables.
+// LDS data layout (complex64 elements):
+//   [0], [1]                    the constants 1 (padding factor) and 0
+//   [2, 2 + inv)                slice-invariant input tensors
+//   [2 + inv, 2 + inv + dep)    this slice's copies of slice-dependent inputs
+//   [2 + inv + dep, data)       intermediates (arena, reused level by level)
+// then, from byte fused_table_lds(data), the level table (16 bytes a level).
+// Program words:
+//   header[kHdr]
+//   levels[4 * (n_levels + kFusedLevelPad)]
+//                               (record base, entries E, R | lgT << 16,
+//                               factors K), then zero entries; R = rows of a
+//                               term record, T = 2^lgT terms per entry
+//   records                     level by level, E entries of T term records
+//                               of R 16-byte rows (8R halfwords) each:
+//                                 slot 0: LDS offset of the result (term 0),
+//                                   0 (other terms)
+//                                 slots 1..K: LDS offsets of the factor
+//                                   entries for that term's assignment
+//                                 rest: 0 (the constant 1); a padding term
+//                                   (node with fewer terms than its level)
+//                                   has slot 1 = the constant 0
+//                               offsets in bytes (header FH_BYTE_OFFSETS = 1,
+//                               data within 64 KB) or else in elements
+//   scalars[n_scalars]          LDS element offsets of the slice's scalar
+//                               factors, zero words to a multiple of 4, then
+//                               4 * kFusedTailRows zero words (the executor
+//                               reads kFusedTailRows rows at any record)
+constexpr int kFusedTailRows = 2;
+constexpr int kFusedLevelPad = 3;
+// LDS elements 0 and 1 hold the constants 1 (padding factor) and 0 (the
+// factor of a padding term); inputs follow.
+constexpr int kFusedConsts = 2;
+constexpr uint32_t kFusedZero = 1;
+// LDS byte offset of the level table's copy: after the tensor entries.
+inline int64_t fused_table_lds(int64_t data_elems) { return (data_elems * 8 + 15) / 16 * 16; }
+enum FusedHdr {
+  FH_WORDS = 0,       // total program words
+  FH_LEVELS,          // n_levels
+  FH_SCALARS,         // n_scalars
+  FH_SCALAR_OFF,      // word offset of the scalar list
+  FH_FREE,            // variables in no tensor (factor 2 each)
+  FH_INV_ELEMS,       // slice-invariant input elements
+  FH_DEP_ELEMS,       // per-slice input elements
+  FH_DATA_ELEMS,      // total LDS data elements (including the constant)
+  FH_DEP_SRC,         // element offset of slice 0's block in the prepared buffer
+  FH_N_SLICES,        // 2^m (saturated)
+  FH_BYTE_OFFSETS,    // 1: record offsets are LDS bytes, 0: complex64 elements
+  kHdr = 16
+};
+
+}  // namespace qbe
