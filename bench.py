@@ -201,6 +201,44 @@ def bench_batch(torch, qbe, ctx, steps):
                          "circuits are compared on the scale of a typical amplitude"}
 
 
+def bench_many(torch, qbe, ctx, steps, n_bits=256):
+    """Many amplitudes of the headline circuit: one plan, cloned for each of
+    n_bits seeded bitstrings (same schedule and programs, other output
+    tensors), contracted in one batched fused launch."""
+    import numpy as np
+    from circuitgen import SplitMix64, WORKLOADS, circuit_model, random_grid_circuit
+    name = "grid5x5_d16_m6"
+    r, c, d, m = WORKLOADS[name]
+    circ = random_grid_circuit(r, c, d, SEEDS[name])
+    rng = SplitMix64(4242)
+    xs = [circ.bitstring] + [rng.next() & ((1 << (r * c)) - 1) for _ in range(n_bits - 1)]
+    t0 = time.perf_counter()
+    qms = [qbe.Model.from_circuitgen(circuit_model(circ, x)) for x in xs]
+    _, mu, pi, _ = qbe.plan_circuit(qms[0], m=m)
+    base = qbe.Plan(qms[0], pi, mu, ctx=ctx, exec="fused")
+    plans = [base] + [base.clone(q) for q in qms[1:]]
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    batch = qbe.Batch(ctx, plans)
+    ws = batch.workspace()
+    amps = torch.zeros(2 * n_bits, dtype=torch.float64, device="cuda")
+    fn = lambda: batch.contract_async(ws, amps)  # noqa: E731
+    wall, ev = timed(torch, fn, steps, 2)
+    got = amps.cpu().numpy().view(np.complex128).copy()
+    # the same amplitudes one launch each, for the first few bitstrings
+    single = []
+    for p in plans[:8]:
+        single.append(qbe.qbe_contract(ctx, p, p.workspace()))
+    scale = 2.0 ** (-(r * c) / 2)
+    diff = max(abs(g - s) / max(abs(s), scale) for g, s in zip(got[:8], single))
+    want = golden(name)
+    return {"workload": f"{name}_x{n_bits}_bitstrings", "bitstrings": n_bits, "slices_each": base.n_slices,
+            "ms_per_batch": ev, "amplitudes_per_s": n_bits / (ev * 1e-3),
+            "rel_err_first_vs_oracle": abs(got[0] - want) / abs(want),
+            "max_diff_batched_vs_single": float(diff), "setup_ms": setup_ms,
+            "note": "one plan (order, slicing, schedule, programs) cloned per bitstring; "
+                    "all bitstrings x slices in one persistent fused launch"}
+
+
 def bench_learned(torch, qbe, ctx, labels=20000, epochs=20, hbm_gbs=None):
     """Learned proposal at the 6x6..8x8 / depth 16..32 scale: ~20k exact-cost
     labels, device training, evaluation on 10 held-out 8x8 depth-32 circuits
@@ -253,7 +291,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-extra", action="store_true", help="skip the 7x7 and batch lines")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--only", choices=["hbm", "batch", "learned"], help="run just one extra workload")
+    ap.add_argument("--only", choices=["hbm", "batch", "many", "learned"], help="run just one extra workload")
     ap.add_argument("--pmc-workload", action="store_true",
                     help="for hardware-counter runs: a device-to-device copy of 256 MiB (three times, the "
                          "calibration of the byte counters) and 20 launches of the headline fused kernel")
@@ -292,6 +330,9 @@ def main():
         return
     if args.only == "batch":
         print(json.dumps(bench_batch(torch, qbe, ctx, args.steps)), flush=True)
+        return
+    if args.only == "many":
+        print(json.dumps(bench_many(torch, qbe, ctx, args.steps)), flush=True)
         return
     if args.only == "learned":
         print(json.dumps(bench_learned(torch, qbe, ctx)), flush=True)
@@ -362,6 +403,8 @@ def main():
         line["hbm_workload_bf16x6"] = bench_hbm(torch, qbe, ctx, 5, "bf16x6")
         log("[bench] batch of 512 ...")
         line["batch_workload"] = bench_batch(torch, qbe, ctx, 20)
+        log("[bench] 256 bitstrings of the headline circuit ...")
+        line["many_amplitudes"] = bench_many(torch, qbe, ctx, 20)
         log("[bench] learned proposal ...")
         line["learned_proposal"] = bench_learned(torch, qbe, ctx,
                                                  hbm_gbs=line["hbm_workload"]["roofline"]["achieved"])

@@ -204,6 +204,18 @@ int qbe_plan_create(qbe_ctx* ctx, const qbe_model* model, const int32_t* reduced
 int qbe_plan_destroy(qbe_plan* plan);
 /* Re-uploads tensor entries from the model (same structure) to the plan. */
 int qbe_plan_update_data(qbe_plan* plan, const qbe_model* model);
+/* A new plan for a model with the same structure as src's (every tensor on
+ * the same variables, in the same order) but other entries -- e.g. another
+ * output bitstring of the same circuit, which changes only the rank-1
+ * tensors on the output variables.  Slicing and schedule depend on the graph
+ * alone (Sec. 2.4, Eq. 3-4), so src's order, sliced set, schedule, programs
+ * and autotuned tile shapes are reused without planning or compiling again.
+ * The clone is bound to src's context (if any) and owns its device memory:
+ * it shares no buffer with src, and either may be destroyed first.
+ * Errors: QBE_ERR_INVALID_ARG for NULL arguments or a model whose
+ * structure differs from src's; device allocation errors as for
+ * qbe_plan_create. */
+int qbe_plan_clone(const qbe_plan* src, const qbe_model* model, qbe_plan** out);
 int qbe_plan_stats(const qbe_plan* plan, qbe_stats* out);
 /* Canonical text of the schedule: order, mu, scalar inputs, free
  * variables, then one line per bucket (eliminated variable, operands,

@@ -85,6 +85,7 @@ _SIGS = {
     "qbe_plan_create": (C.c_int, [_vp, _vp, _i32p, C.c_int32, _i32p, C.c_int32, C.POINTER(PlanOpts), C.POINTER(_vp)]),
     "qbe_plan_destroy": (C.c_int, [_vp]),
     "qbe_plan_update_data": (C.c_int, [_vp, _vp]),
+    "qbe_plan_clone": (C.c_int, [_vp, _vp, C.POINTER(_vp)]),
     "qbe_plan_stats": (C.c_int, [_vp, C.POINTER(Stats)]),
     "qbe_plan_dump": (C.c_int, [_vp, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]),
     "qbe_plan_check": (C.c_int, [_vp]),
@@ -310,6 +311,18 @@ class Plan:
 
     def update_data(self, model: Model):
         _check(_lib.qbe_plan_update_data(self.handle, model.handle), "qbe_plan_update_data")
+
+    def clone(self, model: Model) -> "Plan":
+        """A plan for a model of the same structure (e.g. another bitstring of
+        the same circuit) that reuses this plan's schedule and programs."""
+        h = _vp()
+        _check(_lib.qbe_plan_clone(self.handle, model.handle, C.byref(h)), "qbe_plan_clone")
+        p = Plan.__new__(Plan)
+        p.handle = h
+        p.ctx = self.ctx
+        p.model = model
+        p.n_slices = self.n_slices
+        return p
 
     def autotune(self, ws, min_elems: int = 1 << 20):
         """Times the large per-step launches in each tile shape; keeps the best."""

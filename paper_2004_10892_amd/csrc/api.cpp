@@ -360,6 +360,32 @@ int qbe_plan_destroy(qbe_plan* plan) {
   return QBE_OK;
 }
 
+int qbe_plan_clone(const qbe_plan* src, const qbe_model* model, qbe_plan** out) {
+  QBE_GUARD_BEGIN
+  QBE_REQUIRE(src && model && out, "NULL argument");
+  *out = nullptr;
+  QBE_REQUIRE(model->m.tvars == src->p.model.tvars, "model structure differs from the plan's");
+  auto* pl = new qbe_plan;
+  std::unique_ptr<qbe_plan> guard(pl);
+  qbe::Plan& p = pl->p;
+  p = src->p;  // host side: schedule, programs, layouts, tile shapes
+  p.model = model->m;
+  qbe::dev_forget_plan(p);  // the copied device pointers stay src's
+  if (src->ctx) {
+    int rc = qbe::dev_set(p.device);
+    if (rc) return rc;
+    rc = qbe::dev_upload_plan(p);
+    if (rc) {
+      qbe::dev_free_plan(p);
+      return rc;
+    }
+    pl->ctx = src->ctx;
+  }
+  *out = guard.release();
+  return QBE_OK;
+  QBE_GUARD_END
+}
+
 int qbe_plan_update_data(qbe_plan* plan, const qbe_model* model) {
   QBE_GUARD_BEGIN
   QBE_REQUIRE(plan && model, "NULL argument");

@@ -721,13 +721,25 @@ static int run_prep(Plan& p) {
   return QBE_OK;
 }
 
-void dev_free_plan(Plan& p) {
-  void** ptrs[] = {&p.d_raw,      &p.d_step_map,   &p.d_step_in,    &p.d_fused_map,
+static void plan_buffers(Plan& p, void** (&ptrs)[8]) {
+  void** all[8] = {&p.d_raw,      &p.d_step_map,   &p.d_step_in,    &p.d_fused_map,
                    &p.d_fused_in, &p.d_fused_prog, &p.d_scalar_tab, &p.d_state};
+  for (int i = 0; i < 8; ++i) ptrs[i] = all[i];
+}
+
+void dev_free_plan(Plan& p) {
+  void** ptrs[8];
+  plan_buffers(p, ptrs);
   for (void** q : ptrs) {
     if (*q) (void)hipFree(*q);
     *q = nullptr;
   }
+}
+
+void dev_forget_plan(Plan& p) {
+  void** ptrs[8];
+  plan_buffers(p, ptrs);
+  for (void** q : ptrs) *q = nullptr;
 }
 
 int dmalloc(void** p, size_t bytes) {

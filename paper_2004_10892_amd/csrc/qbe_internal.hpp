@@ -160,6 +160,7 @@ int dev_set(int device);
 int dev_upload_plan(Plan& p);               // allocates + prepares inputs
 int dev_update_data(Plan& p);
 void dev_free_plan(Plan& p);
+void dev_forget_plan(Plan& p);              // clears the device pointers, frees nothing
 int dev_contract(const Plan& p, void* stream, void* ws, size_t ws_bytes, int64_t s_begin,
                  int64_t s_end, double* d_partial_out, double* d_per_slice /*may be null*/);
 size_t dev_workspace_min(const Plan& p, int64_t n_slices_in_call);

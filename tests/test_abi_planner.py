@@ -182,3 +182,23 @@ def test_one_hip_runtime_in_process():
     for name in ("libamdhip64", "libhsa-runtime64"):
         paths = {l.split()[-1] for l in maps.splitlines() if name in l}
         assert len(paths) == 1, paths
+
+
+def test_host_clone_keeps_schedule_and_checks_structure():
+    """A clone for another bitstring has the source plan's schedule and
+    program statistics; a model of another structure is refused."""
+    circ = random_grid_circuit(4, 4, 10, 5)
+    a = qbe.Model.from_circuitgen(circuit_model(circ, 0))
+    b = qbe.Model.from_circuitgen(circuit_model(circ, 0xFFFF))
+    _, mu, pi, _ = qbe.plan_circuit(a, m=3)
+    for form in ("fused", "per_step"):
+        p = qbe.Plan(a, pi, mu, exec=form)
+        c = p.clone(b)
+        assert c.dump() == p.dump()
+        assert c.stats() == p.stats()
+        p.close()  # the clone does not depend on its source
+        assert c.stats()["m"] == 3
+        c.check()
+    other = qbe.Model.from_circuitgen(circuit_model(random_grid_circuit(4, 4, 11, 5)))
+    with pytest.raises(qbe.QbeError):
+        qbe.Plan(a, pi, mu).clone(other)
