@@ -113,6 +113,10 @@ typedef struct qbe_stats {
                                           launches read and write per slice
                                           (below bytes_per_slice when chains
                                           are merged)                        */
+  int32_t n_launches;                  /* per-step form: contraction launches
+                                          per slice group (a merged chain or
+                                          a partial product counts once)     */
+  int32_t reserved0;
 } qbe_stats;
 
 /* ------------------------------------------------------------------ misc -- */

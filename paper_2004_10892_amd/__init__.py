@@ -61,7 +61,8 @@ class Stats(C.Structure):
                 ("flops_per_slice", C.c_uint64), ("bytes_per_slice", C.c_uint64),
                 ("peak_bytes_per_slice", C.c_uint64), ("ws_bytes_min", C.c_uint64),
                 ("ws_bytes_all_slices", C.c_uint64), ("n_mfma_steps", C.c_int32), ("precision", C.c_int32),
-                ("fused_levels", C.c_int32), ("n_merged_steps", C.c_int32), ("step_bytes_per_slice", C.c_uint64)]
+                ("fused_levels", C.c_int32), ("n_merged_steps", C.c_int32), ("step_bytes_per_slice", C.c_uint64),
+                ("n_launches", C.c_int32), ("reserved0", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
