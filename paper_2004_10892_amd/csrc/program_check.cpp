@@ -71,7 +71,9 @@ std::string check_plan(const Plan& p) {
       const StepOp& o = sp.ops[i];
       if (__builtin_popcount(o.mask) != o.rank) return "operand mask and rank disagree";
       if (xbits < 32 && (o.mask >> xbits) != 0) return "operand mask outside the union index";
-      if (sum_u && o.rank > 0 && !((o.mask >> r) & 1u) && o.rank > r) return "operand rank";
+      // one summed bit: an operand without it lies within x (a merged launch's
+      // operands may hold any of its summed bits; the union bound covers them)
+      if (sum_u && sp.n_sum == 1 && o.rank > 0 && !((o.mask >> r) & 1u) && o.rank > r) return "operand rank";
       if (sp.n_sum > 1 && (o.mask >> r) == 0 && o.rank > 0 && !o.is_input)
         return "merged launch with an intermediate that holds no summed variable";
       if (o.is_input) {

@@ -140,11 +140,15 @@ def test_fused_program_merges_buckets_into_fewer_levels(rows, cols, depth, seed,
 
 
 def test_batch_instance_plans_are_sound():
-    for (r, c, d, m, seed) in batch_instances(24):
+    """Every plan of the 512-instance batch workload passes the host check of
+    every index its kernels can form, in both forms and without merging."""
+    for (r, c, d, m, seed) in batch_instances(512):
         qm = qbe.Model.from_circuitgen(circuit_model(random_grid_circuit(r, c, d, seed)))
         _, mu, pi, _ = qbe.plan_circuit(qm, m=m)
-        plan = qbe.Plan(qm, pi, mu)
-        plan.check()
+        for kw in ({}, {"exec": "per_step"}, {"exec": "per_step", "merge": False}):
+            plan = qbe.Plan(qm, pi, mu, **kw)
+            plan.check()
+            plan.close()
 
 
 def test_invalid_arguments_return_errors():

@@ -256,3 +256,21 @@ def test_unit_norm_over_all_bitstrings(qbe, ctx):
     torch.cuda.synchronize()
     a = amps.cpu().numpy().view(np.complex128)
     assert abs(np.sum(np.abs(a) ** 2) - 1.0) <= 1e-5
+
+
+def test_merged_launch_operand_holding_only_higher_summed_bits(qbe, ctx):
+    """Batch instance 167 (5x6 depth 18, no slicing): its per-step plan has a
+    merged launch with an operand that holds summed variables but not the
+    first one and has more variables than the result."""
+    from circuitgen import batch_instances, circuit_model, random_grid_circuit
+    from oracle import contract as C
+    r, c, d, m, seed = batch_instances(512)[167]
+    mod = circuit_model(random_grid_circuit(r, c, d, seed))
+    mu, pi, sched = oracle_schedule(mod, m)
+    want = C.contract(mod.tensors, sched)[0]
+    qm = qbe.Model.from_circuitgen(mod)
+    _say(f"case batch instance 167 ({r}x{c} d{d} m{m}) per-step merged")
+    for merge in (True, False):
+        plan = qbe.Plan(qm, pi, mu, ctx=ctx, exec="per_step", merge=merge)
+        got = qbe.qbe_contract(ctx, plan, plan.workspace())
+        assert abs(got - want) <= TOL * max(abs(want), 2.0 ** (-(r * c) / 2) * 1e-2)
