@@ -427,7 +427,7 @@ int qbe_plan_stats(const qbe_plan* plan, qbe_stats* out) {
   for (const auto& sp : p.steps)
     if (sp.n_sum > 1) ++out->n_merged_steps;
   out->step_bytes_per_slice = (uint64_t)p.step_bytes_per_slice;
-  out->n_launches = (int32_t)p.steps.size();
+  out->n_launches = (int32_t)p.launch_order.size();
   return QBE_OK;
   QBE_GUARD_END
 }

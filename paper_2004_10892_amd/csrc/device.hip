@@ -358,6 +358,62 @@ __global__ __launch_bounds__(kBlock) void msum_small_kernel(StepLaunch a) {
   }
 }
 
+// --------------------------------------------------- grouped small steps --
+//
+// The small launches of one dependency level in one launch.  Work unit w =
+// (tile t of the level's tile range, block yb of sb slices); the step owning
+// tile t is found by binary search in the level's tile prefix.  A tile is
+// 256 consecutive entries of the step's results for the block's sb slices
+// (several slices when r < 8).  Operands are addressed as in step_kernel,
+// with the bit extraction done per lane: these steps are small.
+struct GroupArgs {
+  const GroupStep* steps;   // the level's steps
+  const uint32_t* prefix;   // count + 1 tile offsets
+  int32_t count;
+  int32_t sb;               // slices per block (power of two)
+  float2* arena;
+  const float2* step_in;
+  int64_t G, s0, n_blocks;  // n_blocks = ceil(G / sb)
+};
+
+__global__ __launch_bounds__(kBlock) void group_kernel(GroupArgs a) {
+  const int tid = threadIdx.x;
+  const int64_t total = a.prefix[a.count];
+  for (int64_t w = blockIdx.x; w < total * a.n_blocks; w += gridDim.x) {
+    const int64_t yb = w / total;
+    const uint32_t t = (uint32_t)(w - yb * total);
+    int lo = 0, hi = a.count;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (a.prefix[mid] <= t) lo = mid; else hi = mid;
+    }
+    const GroupStep& d = a.steps[lo];
+    const int r = d.r;
+    const int64_t e = (int64_t)(t - a.prefix[lo]) * kBlock + tid;
+    if (e >= ((int64_t)a.sb << r)) continue;
+    const int64_t g = yb * a.sb + (e >> r);
+    if (g >= a.G) continue;
+    const uint32_t x = (uint32_t)(e & ((int64_t(1) << r) - 1));
+    const uint32_t s = (uint32_t)(a.s0 + g);
+    float2 p0 = make_float2(1.f, 0.f), p1 = make_float2(1.f, 0.f);
+    for (int i = 0; i < d.n_ops; ++i) {
+      const float2* src;
+      if ((d.is_input >> i) & 1u)
+        src = a.step_in + d.base[i] + ((int64_t)pext32(s, d.smask[i]) << d.rank[i]);
+      else
+        src = a.arena + d.base[i] * a.G + (g << d.rank[i]);
+      src += pext32(x, d.mask[i]);
+      p0 = cmul(p0, src[0]);
+      if (d.sum_u) p1 = cmul(p1, src[((d.mask[i] >> r) & 1u) ? (1u << (d.rank[i] - 1)) : 0u]);
+    }
+    if (d.sum_u) {
+      p0.x += p1.x;
+      p0.y += p1.y;
+    }
+    a.arena[d.out * a.G + (g << r) + x] = p0;
+  }
+}
+
 // ------------------------------------------------- outer-product buckets --
 //
 // A bucket whose result variables all belong to two operands A and B (both
@@ -721,14 +777,14 @@ static int run_prep(Plan& p) {
   return QBE_OK;
 }
 
-static void plan_buffers(Plan& p, void** (&ptrs)[8]) {
-  void** all[8] = {&p.d_raw,      &p.d_step_map,   &p.d_step_in,    &p.d_fused_map,
-                   &p.d_fused_in, &p.d_fused_prog, &p.d_scalar_tab, &p.d_state};
-  for (int i = 0; i < 8; ++i) ptrs[i] = all[i];
+static void plan_buffers(Plan& p, void** (&ptrs)[9]) {
+  void** all[9] = {&p.d_raw,      &p.d_step_map,   &p.d_step_in,    &p.d_fused_map, &p.d_fused_in,
+                   &p.d_fused_prog, &p.d_scalar_tab, &p.d_state, &p.d_group};
+  for (int i = 0; i < 9; ++i) ptrs[i] = all[i];
 }
 
 void dev_free_plan(Plan& p) {
-  void** ptrs[8];
+  void** ptrs[9];
   plan_buffers(p, ptrs);
   for (void** q : ptrs) {
     if (*q) (void)hipFree(*q);
@@ -737,7 +793,7 @@ void dev_free_plan(Plan& p) {
 }
 
 void dev_forget_plan(Plan& p) {
-  void** ptrs[8];
+  void** ptrs[9];
   plan_buffers(p, ptrs);
   for (void** q : ptrs) *q = nullptr;
 }
@@ -777,6 +833,13 @@ int dev_upload_plan(Plan& p) {
   }
   if ((rc = dmalloc(&p.d_state, 256))) return rc;
   QBE_HIP(hipMemset(p.d_state, 0, 256));
+  if (!p.group_steps.empty()) {
+    const size_t sb = p.group_steps.size() * sizeof(GroupStep);
+    std::vector<char> buf(sb + p.group_prefix.size() * 4);
+    std::memcpy(buf.data(), p.group_steps.data(), sb);
+    std::memcpy(buf.data() + sb, p.group_prefix.data(), p.group_prefix.size() * 4);
+    if ((rc = upload(&p.d_group, buf.data(), buf.size()))) return rc;
+  }
   if (p.fused_ok) {
     if ((rc = upload(&p.d_fused_map, p.fused_map.data(), p.fused_map.size() * 4))) return rc;
     if ((rc = dmalloc(&p.d_fused_in, p.fused_elems * 8))) return rc;
@@ -1010,6 +1073,25 @@ static int launch_step(const Plan& p, const StepProg& sp, float2* arena, int64_t
   return QBE_OK;
 }
 
+static int launch_group(const Plan& p, int g, float2* arena, int64_t G, int64_t s0, hipStream_t st) {
+  GroupArgs a{};
+  const int32_t first = p.group_first[g];
+  a.steps = (const GroupStep*)p.d_group + first;
+  a.prefix = (const uint32_t*)((const char*)p.d_group + p.group_steps.size() * sizeof(GroupStep)) + first + g;
+  a.count = p.group_first[g + 1] - first;
+  a.sb = p.group_sb;
+  a.arena = arena;
+  a.step_in = (const float2*)p.d_step_in;
+  a.G = G;
+  a.s0 = s0;
+  a.n_blocks = (G + a.sb - 1) / a.sb;
+  const int64_t units = (int64_t)p.group_prefix[first + g + a.count] * a.n_blocks;
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(units, (int64_t)n_cus() * 16));
+  group_kernel<<<grid, kBlock, 0, st>>>(a);
+  QBE_HIP(hipGetLastError());
+  return QBE_OK;
+}
+
 // Autotuner: times every large per-step launch of the plan on the device in
 // each candidate tile shape (tiles per thread x workgroups per CU) and keeps
 // the fastest.  Runs the plan's own schedule on a slice group of G slices, so
@@ -1092,8 +1174,9 @@ int dev_contract(const Plan& p, void* stream, void* ws, size_t ws_bytes, int64_t
     const uint32_t* t_ism = (const uint32_t*)(t_inb + p.scalar_inputs_base.size());
     for (int64_t g0 = 0; g0 < n; g0 += G) {
       const int64_t Gc = std::min<int64_t>(G, n - g0);
-      for (const StepProg& sp : p.steps) {
-        int rc = launch_step(p, sp, arena, Gc, s_begin + g0, st);
+      for (const LaunchItem& li : p.launch_order) {
+        int rc = li.group < 0 ? launch_step(p, p.steps[li.step], arena, Gc, s_begin + g0, st)
+                              : launch_group(p, li.group, arena, Gc, s_begin + g0, st);
         if (rc) return rc;
       }
       FinalizeArgs fa{};

@@ -253,6 +253,93 @@ std::vector<StepNode> merge_chains(const Schedule& s, bool merge) {
   return out;
 }
 
+// Execution order of the per-step launches.  A launch's level is one more
+// than that of every earlier launch it must follow: the producers of its
+// operands, and -- because the arena reuses space -- earlier launches that
+// read or write the space it writes.  Launches of one level are independent;
+// the small ones (no merged or MFMA form, result rank <= kGroupMaxRank) of a
+// level run together in one group launch when there are at least two.
+void build_launch_order(Plan& p) {
+  p.launch_order.clear();
+  p.group_steps.clear();
+  p.group_first.assign(1, 0);
+  p.group_prefix.clear();
+  const int n = (int)p.steps.size();
+  int64_t sb = 1;
+  while (sb < 256 && sb < p.n_slices) sb <<= 1;
+  p.group_sb = (int32_t)sb;
+  if (!p.merge) {
+    // plain form: one launch per bucket, in schedule order
+    for (int k = 0; k < n; ++k) p.launch_order.push_back(LaunchItem{k, -1});
+    return;
+  }
+  struct Span {
+    int64_t b, e;
+  };
+  auto rank_of = [](const StepProg& sp) { return sp.out_rank >= 0 ? sp.out_rank : -sp.out_rank; };
+  std::vector<Span> wr(n);
+  std::vector<std::vector<Span>> rd(n);
+  for (int k = 0; k < n; ++k) {
+    const StepProg& sp = p.steps[k];
+    wr[k] = Span{sp.out_base, sp.out_base + (int64_t(1) << rank_of(sp))};
+    for (int i = 0; i < sp.n_ops; ++i)
+      if (!sp.ops[i].is_input) rd[k].push_back(Span{sp.ops[i].base, sp.ops[i].base + (int64_t(1) << sp.ops[i].rank)});
+  }
+  auto meet = [](const Span& a, const Span& b) { return a.b < b.e && b.b < a.e; };
+  std::vector<int> level(n, 0);
+  int n_lv = 0;
+  for (int k = 0; k < n; ++k) {
+    int l = 0;
+    for (int j = 0; j < k; ++j) {
+      bool dep = meet(wr[j], wr[k]);
+      for (const Span& r : rd[k]) dep = dep || meet(wr[j], r);
+      for (const Span& r : rd[j]) dep = dep || meet(r, wr[k]);
+      if (dep) l = std::max(l, level[j] + 1);
+    }
+    level[k] = l;
+    n_lv = std::max(n_lv, l + 1);
+  }
+  auto small = [&](const StepProg& sp) {
+    return sp.n_sum <= 1 && !sp.mmk && sp.mm_a < 0 && rank_of(sp) <= kGroupMaxRank;
+  };
+  for (int l = 0; l < n_lv; ++l) {
+    std::vector<int> grp;
+    for (int k = 0; k < n; ++k) {
+      if (level[k] != l) continue;
+      if (small(p.steps[k]))
+        grp.push_back(k);
+      else
+        p.launch_order.push_back(LaunchItem{k, -1});
+    }
+    if (grp.size() == 1) p.launch_order.push_back(LaunchItem{grp[0], -1});
+    if (grp.size() < 2) continue;
+    const int g = (int)p.group_first.size() - 1;
+    uint32_t tiles = 0;
+    p.group_prefix.push_back(0);
+    for (int k : grp) {
+      const StepProg& sp = p.steps[k];
+      GroupStep d{};
+      d.out = sp.out_base;
+      d.n_ops = sp.n_ops;
+      d.r = rank_of(sp);
+      d.sum_u = sp.out_rank >= 0 ? 1 : 0;
+      d.step = k;
+      for (int i = 0; i < sp.n_ops; ++i) {
+        d.base[i] = sp.ops[i].base;
+        d.mask[i] = sp.ops[i].mask;
+        d.smask[i] = sp.ops[i].is_input ? sp.ops[i].smask : 0u;
+        d.rank[i] = sp.ops[i].rank;
+        if (sp.ops[i].is_input) d.is_input |= 1u << i;
+      }
+      p.group_steps.push_back(d);
+      tiles += (uint32_t)(((sb << d.r) + 255) / 256);
+      p.group_prefix.push_back(tiles);
+    }
+    p.group_first.push_back((int32_t)p.group_steps.size());
+    p.launch_order.push_back(LaunchItem{-1, g});
+  }
+}
+
 }  // namespace
 
 void compile_plan(Plan& p) {
@@ -480,6 +567,8 @@ void compile_plan(Plan& p) {
     p.scalar_inputs_base.push_back(step_base[t]);
     p.scalar_inputs_smask.push_back(in[t].smask);
   }
+
+  build_launch_order(p);
 
   // ---------------- levels (dependency depth)
   std::vector<int> level(nsteps, 0);

@@ -88,6 +88,48 @@ std::string check_plan(const Plan& p) {
       }
     }
   }
+  // execution order: every step exactly once, alone or in one group whose
+  // descriptor repeats the step's fields and whose tile prefix matches
+  {
+    std::vector<int> seen(p.steps.size(), 0);
+    const int n_groups = (int)p.group_first.size() - 1;
+    if (n_groups < 0 || p.group_first[0] != 0 || p.group_first.back() != (int32_t)p.group_steps.size())
+      return "group table";
+    if (p.group_prefix.size() != p.group_steps.size() + (size_t)n_groups) return "group prefix size";
+    if (p.group_sb < 1 || p.group_sb > 256 || (p.group_sb & (p.group_sb - 1))) return "group slice block";
+    for (const LaunchItem& li : p.launch_order) {
+      if (li.group < 0) {
+        if (li.step < 0 || li.step >= (int)p.steps.size()) return "launch step index";
+        ++seen[li.step];
+        continue;
+      }
+      if (li.group >= n_groups) return "launch group index";
+      const int f = p.group_first[li.group], e = p.group_first[li.group + 1];
+      if (e - f < 2) return "group with fewer than two steps";
+      uint32_t tiles = 0;
+      if (p.group_prefix[f + li.group] != 0) return "group prefix start";
+      for (int j = f; j < e; ++j) {
+        const GroupStep& d = p.group_steps[j];
+        if (d.step < 0 || d.step >= (int)p.steps.size()) return "group step index";
+        ++seen[d.step];
+        const StepProg& sp = p.steps[d.step];
+        const int r = sp.out_rank >= 0 ? sp.out_rank : -sp.out_rank;
+        if (d.r != r || d.r > kGroupMaxRank || d.sum_u != (sp.out_rank >= 0 ? 1 : 0) || d.n_ops != sp.n_ops ||
+            d.out != sp.out_base || sp.n_sum > 1 || sp.mmk || sp.mm_a >= 0)
+          return "group step fields";
+        for (int i = 0; i < sp.n_ops; ++i) {
+          const StepOp& o = sp.ops[i];
+          if (d.base[i] != o.base || d.mask[i] != o.mask || d.rank[i] != o.rank ||
+              (((d.is_input >> i) & 1u) != (uint32_t)o.is_input) || d.smask[i] != (o.is_input ? o.smask : 0u))
+            return "group operand fields";
+        }
+        tiles += (uint32_t)((((int64_t)p.group_sb << d.r) + 255) / 256);
+        if (p.group_prefix[j + 1 + li.group] != tiles) return "group prefix";
+      }
+    }
+    for (int c : seen)
+      if (c != 1) return "execution order misses or repeats a step";
+  }
   for (int64_t off : p.scalar_arena)
     if (off < 0 || off >= p.arena_per_slice) return "scalar result outside the arena";
   for (size_t j = 0; j < p.scalar_inputs_base.size(); ++j) {

@@ -66,6 +66,26 @@ struct StepProg {
   StepOp ops[kMaxOps];
 };
 
+// Small per-step launches of one dependency level run as one launch
+// (group_kernel): each step of a group is described by a GroupStep and owns
+// a run of tiles of 256 result entries for every block of group_sb slices.
+constexpr int kGroupMaxRank = 10;  // largest result rank a grouped step has
+struct GroupStep {
+  int64_t out;              // arena offset of the result (per-slice unit)
+  int64_t base[kMaxOps];    // arena offset (per-slice unit), or prepared-input offset
+  uint32_t mask[kMaxOps];   // bits of X = (u << r) | x each operand reads
+  uint32_t smask[kMaxOps];  // inputs: slice bits selecting the copy
+  int32_t rank[kMaxOps];
+  uint32_t is_input;        // bit i: operand i is a prepared input
+  int32_t n_ops, r, sum_u;  // sum_u 0: product without a summed bit
+  int32_t step;             // index into the plan's steps (host checks)
+};
+// One entry of the per-step execution order: steps[step] alone (group < 0),
+// or group `group` of small steps in one launch.
+struct LaunchItem {
+  int32_t step, group;
+};
+
 struct Plan {
   // host side
   Model model;
@@ -89,6 +109,14 @@ struct Plan {
   int64_t step_bytes_per_slice = 0;     // complex64 bytes the launches read and write
   std::vector<int32_t> step_map;        // prepared per-step buffer gather map
   int64_t step_elems = 0;
+  // execution order: launches level by level (dependency depth, with the
+  // arena's reuse counted as a dependency), small launches of a level grouped
+  std::vector<LaunchItem> launch_order;
+  std::vector<GroupStep> group_steps;   // every group's steps, group by group
+  std::vector<int32_t> group_first;     // group g: steps [first[g], first[g + 1])
+  std::vector<uint32_t> group_prefix;   // group g: first[g + 1] - first[g] + 1 tile
+                                        // offsets from index first[g] + g
+  int32_t group_sb = 1;                 // slices per block of a group launch
 
   // fused form
   bool fused_ok = false;
@@ -107,6 +135,7 @@ struct Plan {
   void* d_fused_prog = nullptr;
   void* d_scalar_tab = nullptr; // int64 arena offsets, int64 input bases, uint32 smasks
   void* d_state = nullptr;      // uint32[4]: work counter, exits, items done (fused)
+  void* d_group = nullptr;      // GroupStep array, then the uint32 tile prefixes
 };
 
 // A set of plans contracted together in one fused launch.
