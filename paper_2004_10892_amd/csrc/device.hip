@@ -376,8 +376,35 @@ struct GroupArgs {
   int64_t G, s0, n_blocks;  // n_blocks = ceil(G / sb)
 };
 
+// Tile t of step d for the block of sb slices starting at slice yb * sb.
+__device__ __forceinline__ void group_tile(const GroupStep& d, float2* arena, const float2* step_in, int64_t G,
+                                           int64_t s0, int sb, int64_t yb, uint32_t t, int tid) {
+  const int r = d.r;
+  const int64_t e = (int64_t)t * kBlock + tid;
+  if (e >= ((int64_t)sb << r)) return;
+  const int64_t g = yb * sb + (e >> r);
+  if (g >= G) return;
+  const uint32_t x = (uint32_t)(e & ((int64_t(1) << r) - 1));
+  const uint32_t s = (uint32_t)(s0 + g);
+  float2 p0 = make_float2(1.f, 0.f), p1 = make_float2(1.f, 0.f);
+  for (int i = 0; i < d.n_ops; ++i) {
+    const float2* src;
+    if ((d.is_input >> i) & 1u)
+      src = step_in + d.base[i] + ((int64_t)pext32(s, d.smask[i]) << d.rank[i]);
+    else
+      src = arena + d.base[i] * G + (g << d.rank[i]);
+    src += pext32(x, d.mask[i]);
+    p0 = cmul(p0, src[0]);
+    if (d.sum_u) p1 = cmul(p1, src[((d.mask[i] >> r) & 1u) ? (1u << (d.rank[i] - 1)) : 0u]);
+  }
+  if (d.sum_u) {
+    p0.x += p1.x;
+    p0.y += p1.y;
+  }
+  arena[d.out * G + (g << r) + x] = p0;
+}
+
 __global__ __launch_bounds__(kBlock) void group_kernel(GroupArgs a) {
-  const int tid = threadIdx.x;
   const int64_t total = a.prefix[a.count];
   for (int64_t w = blockIdx.x; w < total * a.n_blocks; w += gridDim.x) {
     const int64_t yb = w / total;
@@ -387,30 +414,33 @@ __global__ __launch_bounds__(kBlock) void group_kernel(GroupArgs a) {
       const int mid = (lo + hi) >> 1;
       if (a.prefix[mid] <= t) lo = mid; else hi = mid;
     }
-    const GroupStep& d = a.steps[lo];
-    const int r = d.r;
-    const int64_t e = (int64_t)(t - a.prefix[lo]) * kBlock + tid;
-    if (e >= ((int64_t)a.sb << r)) continue;
-    const int64_t g = yb * a.sb + (e >> r);
-    if (g >= a.G) continue;
-    const uint32_t x = (uint32_t)(e & ((int64_t(1) << r) - 1));
-    const uint32_t s = (uint32_t)(a.s0 + g);
-    float2 p0 = make_float2(1.f, 0.f), p1 = make_float2(1.f, 0.f);
-    for (int i = 0; i < d.n_ops; ++i) {
-      const float2* src;
-      if ((d.is_input >> i) & 1u)
-        src = a.step_in + d.base[i] + ((int64_t)pext32(s, d.smask[i]) << d.rank[i]);
-      else
-        src = a.arena + d.base[i] * a.G + (g << d.rank[i]);
-      src += pext32(x, d.mask[i]);
-      p0 = cmul(p0, src[0]);
-      if (d.sum_u) p1 = cmul(p1, src[((d.mask[i] >> r) & 1u) ? (1u << (d.rank[i] - 1)) : 0u]);
+    group_tile(a.steps[lo], a.arena, a.step_in, a.G, a.s0, a.sb, yb, t - a.prefix[lo], threadIdx.x);
+  }
+}
+
+// The grouped steps of one level of a batch's per-step instances, every
+// instance with all its slices: unit w of the level's prefix is (block of
+// slices, tile) of one step.
+struct WideArgs {
+  const WideGroupStep* steps;
+  const uint64_t* prefix;   // count + 1 unit offsets
+  int32_t count;
+  float2* ws;               // the batch's per-step workspace
+};
+
+__global__ __launch_bounds__(kBlock) void wide_group_kernel(WideArgs a) {
+  const uint64_t total = a.prefix[a.count];
+  for (uint64_t w = blockIdx.x; w < total; w += gridDim.x) {
+    int lo = 0, hi = a.count;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (a.prefix[mid] <= w) lo = mid; else hi = mid;
     }
-    if (d.sum_u) {
-      p0.x += p1.x;
-      p0.y += p1.y;
-    }
-    a.arena[d.out * a.G + (g << r) + x] = p0;
+    const WideGroupStep& d = a.steps[lo];
+    const uint64_t local = w - a.prefix[lo];
+    const int64_t yb = (int64_t)(local / (uint32_t)d.tiles);
+    const uint32_t t = (uint32_t)(local - (uint64_t)yb * (uint32_t)d.tiles);
+    group_tile(d.s, a.ws + d.arena, (const float2*)d.step_in, d.G, 0, d.sb, yb, t, threadIdx.x);
   }
 }
 
@@ -1150,6 +1180,29 @@ int dev_autotune(Plan& p, void* stream, void* ws, size_t ws_bytes, int64_t min_e
   return rc;
 }
 
+// Per-slice FP64 product of the rank-0 results of slices s0 .. s0 + G - 1.
+static int finalize_group(const Plan& p, float2* arena, double2* per_slice, int64_t G, int64_t s0,
+                          hipStream_t st) {
+  const int64_t* t_arena = (const int64_t*)p.d_scalar_tab;
+  const int64_t* t_inb = t_arena + p.scalar_arena.size();
+  const uint32_t* t_ism = (const uint32_t*)(t_inb + p.scalar_inputs_base.size());
+  FinalizeArgs fa{};
+  fa.arena = arena;
+  fa.prep = (const float2*)p.d_step_in;
+  fa.arena_off = t_arena;
+  fa.in_base = t_inb;
+  fa.in_smask = t_ism;
+  fa.n_arena = (int)p.scalar_arena.size();
+  fa.n_in = (int)p.scalar_inputs_base.size();
+  fa.n_free = (int)p.sched.free_vars.size();
+  fa.G = G;
+  fa.s0 = s0;
+  fa.per_slice = per_slice;
+  finalize_kernel<<<grid_for(G, 256), 256, 0, st>>>(fa);
+  QBE_HIP(hipGetLastError());
+  return QBE_OK;
+}
+
 int dev_contract(const Plan& p, void* stream, void* ws, size_t ws_bytes, int64_t s_begin,
                  int64_t s_end, double* d_partial_out, double* d_per_slice) {
   hipStream_t st = (hipStream_t)stream;
@@ -1169,9 +1222,6 @@ int dev_contract(const Plan& p, void* stream, void* ws, size_t ws_bytes, int64_t
     const int64_t per_slice_bytes = p.arena_per_slice * 8;
     const int64_t G = std::min<int64_t>(n, (int64_t)((ws_bytes - ws_head(n)) / per_slice_bytes));
     float2* arena = (float2*)(w + ws_head(n));
-    const int64_t* t_arena = (const int64_t*)p.d_scalar_tab;
-    const int64_t* t_inb = t_arena + p.scalar_arena.size();
-    const uint32_t* t_ism = (const uint32_t*)(t_inb + p.scalar_inputs_base.size());
     for (int64_t g0 = 0; g0 < n; g0 += G) {
       const int64_t Gc = std::min<int64_t>(G, n - g0);
       for (const LaunchItem& li : p.launch_order) {
@@ -1179,20 +1229,8 @@ int dev_contract(const Plan& p, void* stream, void* ws, size_t ws_bytes, int64_t
                               : launch_group(p, li.group, arena, Gc, s_begin + g0, st);
         if (rc) return rc;
       }
-      FinalizeArgs fa{};
-      fa.arena = arena;
-      fa.prep = (const float2*)p.d_step_in;
-      fa.arena_off = t_arena;
-      fa.in_base = t_inb;
-      fa.in_smask = t_ism;
-      fa.n_arena = (int)p.scalar_arena.size();
-      fa.n_in = (int)p.scalar_inputs_base.size();
-      fa.n_free = (int)p.sched.free_vars.size();
-      fa.G = Gc;
-      fa.s0 = s_begin + g0;
-      fa.per_slice = per_slice + g0;
-      finalize_kernel<<<grid_for(Gc, 256), 256, 0, st>>>(fa);
-      QBE_HIP(hipGetLastError());
+      int rc = finalize_group(p, arena, per_slice + g0, Gc, s_begin + g0, st);
+      if (rc) return rc;
     }
   }
   return launch_reduce(per_slice, nullptr, n, (double2*)d_partial_out, 1, st);
@@ -1206,9 +1244,90 @@ int launch_reduce(const double2* v, const int64_t* ranges, int64_t n_single, dou
 }
 
 // ------------------------------------------------------------------ batch --
+//
+// The per-step instances of a batch run together, level by level: each has
+// its own region of the workspace (all its slices at once), a level's
+// single launches of every instance go first, then one launch of all their
+// grouped small steps of that level; then each instance's finalize and sum.
 
-// [0, head): counter and per-item values of the fused launch; then the
-// workspace of the widest per-step instance (they run one after another).
+int step_batch_build(Batch& b) {
+  b.wide_off.clear();
+  b.wide_order.clear();
+  b.wide_steps.clear();
+  b.wide_first.assign(1, 0);
+  b.wide_prefix.clear();
+  size_t off = 0;
+  int n_lv = 0;
+  for (int i : b.wide) {
+    const Plan& p = *b.plans[i];
+    b.wide_off.push_back(off);
+    off += (dev_workspace_all(p) + 255) / 256 * 256;
+    for (int lv : p.step_level) n_lv = std::max(n_lv, lv + 1);
+  }
+  b.wide_ws = off;
+  for (int L = 0; L < n_lv; ++L) {
+    std::vector<WideGroupStep> grp;
+    for (size_t q = 0; q < b.wide.size(); ++q) {
+      const Plan& p = *b.plans[b.wide[q]];
+      const int64_t arena = (int64_t)((b.wide_off[q] + ws_head(p.n_slices)) / sizeof(float2));
+      for (const LaunchItem& li : p.launch_order) {
+        if (li.group < 0) {
+          if (p.step_level[li.step] == L) b.wide_order.push_back(WideItem{(int32_t)q, li.step, -1});
+          continue;
+        }
+        const int f = p.group_first[li.group], e = p.group_first[li.group + 1];
+        if (p.step_level[p.group_steps[f].step] != L) continue;
+        for (int j = f; j < e; ++j) {
+          WideGroupStep d{};
+          d.s = p.group_steps[j];
+          d.step_in = p.d_step_in;
+          d.arena = arena;
+          d.G = p.n_slices;
+          d.sb = p.group_sb;
+          d.tiles = (int32_t)((((int64_t)p.group_sb << d.s.r) + kBlock - 1) / kBlock);
+          grp.push_back(d);
+        }
+      }
+    }
+    if (grp.empty()) continue;
+    const int g = (int)b.wide_first.size() - 1;
+    uint64_t units = 0;
+    b.wide_prefix.push_back(0);
+    for (const WideGroupStep& d : grp) {
+      units += (uint64_t)d.tiles * (uint64_t)((d.G + d.sb - 1) / d.sb);
+      b.wide_prefix.push_back(units);
+      b.wide_steps.push_back(d);
+    }
+    b.wide_first.push_back((int32_t)b.wide_steps.size());
+    b.wide_order.push_back(WideItem{-1, -1, g});
+  }
+  if (!b.wide_steps.empty()) {
+    const size_t sb = b.wide_steps.size() * sizeof(WideGroupStep);
+    std::vector<char> buf(sb + b.wide_prefix.size() * 8);
+    std::memcpy(buf.data(), b.wide_steps.data(), sb);
+    std::memcpy(buf.data() + sb, b.wide_prefix.data(), b.wide_prefix.size() * 8);
+    int rc = upload(&b.d_wide, buf.data(), buf.size());
+    if (rc) return rc;
+  }
+  return QBE_OK;
+}
+
+static int launch_wide_group(const Batch& b, int g, char* wide_ws, hipStream_t st) {
+  WideArgs a{};
+  const int32_t first = b.wide_first[g];
+  a.steps = (const WideGroupStep*)b.d_wide + first;
+  a.prefix = (const uint64_t*)((const char*)b.d_wide + b.wide_steps.size() * sizeof(WideGroupStep)) + first + g;
+  a.count = b.wide_first[g + 1] - first;
+  a.ws = (float2*)wide_ws;
+  const uint64_t units = b.wide_prefix[first + g + a.count];
+  const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>(units, (uint64_t)n_cus() * 16));
+  wide_group_kernel<<<grid, kBlock, 0, st>>>(a);
+  QBE_HIP(hipGetLastError());
+  return QBE_OK;
+}
+
+// [0, head): counter and per-item values of the fused launch; then one
+// region per per-step instance (result, per-slice values, arena).
 size_t dev_batch_workspace(const Batch& b) { return ws_head(b.n_items) + b.wide_ws; }
 
 int dev_batch_contract(const Batch& b, void* stream, void* ws, size_t ws_bytes, double* d_amps) {
@@ -1223,9 +1342,23 @@ int dev_batch_contract(const Batch& b, void* stream, void* ws, size_t ws_bytes, 
     if (rc) return rc;
   }
   char* wide_ws = w + ws_head(b.n_items);
-  for (int i : b.wide) {
-    const Plan& p = *b.plans[i];
-    int rc = dev_contract(p, stream, wide_ws, b.wide_ws, 0, p.n_slices, d_amps + 2 * i, nullptr);
+  for (const WideItem& it : b.wide_order) {
+    int rc;
+    if (it.group < 0) {
+      const Plan& p = *b.plans[b.wide[it.plan]];
+      float2* arena = (float2*)(wide_ws + b.wide_off[it.plan] + ws_head(p.n_slices));
+      rc = launch_step(p, p.steps[it.step], arena, p.n_slices, 0, st);
+    } else {
+      rc = launch_wide_group(b, it.group, wide_ws, st);
+    }
+    if (rc) return rc;
+  }
+  for (size_t q = 0; q < b.wide.size(); ++q) {
+    const Plan& p = *b.plans[b.wide[q]];
+    char* pw = wide_ws + b.wide_off[q];
+    double2* per_slice = (double2*)(pw + 256);
+    int rc = finalize_group(p, (float2*)(pw + ws_head(p.n_slices)), per_slice, p.n_slices, 0, st);
+    if (!rc) rc = launch_reduce(per_slice, nullptr, p.n_slices, (double2*)d_amps + b.wide[q], 1, st);
     if (rc) return rc;
   }
   return QBE_OK;

@@ -52,6 +52,9 @@ inline size_t ws_head(int64_t n) { return 256 + ((size_t)n * 16 + 255) / 256 * 2
 int launch_reduce(const double2* v, const int64_t* ranges, int64_t n_single, double2* out, int n_blocks,
                   hipStream_t st);
 
+// Launch order and grouped steps of a batch's per-step instances.
+int step_batch_build(Batch& b);
+
 // -------------------------------------------------- fused form (fused.hip) --
 
 // Slices [s_begin, s_begin + n) of a fused plan: one persistent launch.

@@ -532,7 +532,6 @@ int dev_batch_build(Batch& b) {
     const Plan& p = *b.plans[i];
     if (p.exec != QBE_EXEC_FUSED) {
       b.wide.push_back(i);
-      b.wide_ws = std::max(b.wide_ws, dev_workspace_all(p));
       continue;
     }
     b.lds_bytes = std::max(b.lds_bytes, p.fused_lds_bytes);
@@ -562,11 +561,11 @@ int dev_batch_build(Batch& b) {
   b.reduce_here = true;
   for (int i : idx)
     if (b.plans[i]->n_slices > kInKernelReduceMax) b.reduce_here = false;
-  return QBE_OK;
+  return step_batch_build(b);
 }
 
 void dev_batch_free(Batch& b) {
-  void** ptrs[] = {&b.d_items, &b.d_ranges, &b.d_state};
+  void** ptrs[] = {&b.d_items, &b.d_ranges, &b.d_state, &b.d_wide};
   for (void** q : ptrs) {
     if (*q) (void)hipFree(*q);
     *q = nullptr;

@@ -268,9 +268,13 @@ void build_launch_order(Plan& p) {
   int64_t sb = 1;
   while (sb < 256 && sb < p.n_slices) sb <<= 1;
   p.group_sb = (int32_t)sb;
+  p.step_level.assign(n, 0);
   if (!p.merge) {
     // plain form: one launch per bucket, in schedule order
-    for (int k = 0; k < n; ++k) p.launch_order.push_back(LaunchItem{k, -1});
+    for (int k = 0; k < n; ++k) {
+      p.launch_order.push_back(LaunchItem{k, -1});
+      p.step_level[k] = k;
+    }
     return;
   }
   struct Span {
@@ -299,6 +303,7 @@ void build_launch_order(Plan& p) {
     level[k] = l;
     n_lv = std::max(n_lv, l + 1);
   }
+  p.step_level = level;
   auto small = [&](const StepProg& sp) {
     return sp.n_sum <= 1 && !sp.mmk && sp.mm_a < 0 && rank_of(sp) <= kGroupMaxRank;
   };

@@ -85,6 +85,19 @@ struct GroupStep {
 struct LaunchItem {
   int32_t step, group;
 };
+// A grouped step of a batch's per-step instances, which run level by level
+// together: the step with its plan's context.  Its work units are `tiles`
+// tiles for each of ceil(G / sb) blocks of sb slices.
+struct WideGroupStep {
+  GroupStep s;
+  const void* step_in;   // the plan's prepared inputs (device)
+  int64_t arena;         // the plan's arena: complex64 offset in the batch workspace
+  int64_t G;             // the plan's slices (all run at once)
+  int32_t sb, tiles;
+};
+struct WideItem {
+  int32_t plan, step, group;  // plan's step alone (group < 0), or a group
+};
 
 struct Plan {
   // host side
@@ -117,6 +130,7 @@ struct Plan {
   std::vector<uint32_t> group_prefix;   // group g: first[g + 1] - first[g] + 1 tile
                                         // offsets from index first[g] + g
   int32_t group_sb = 1;                 // slices per block of a group launch
+  std::vector<int32_t> step_level;      // level of each step in that order
 
   // fused form
   bool fused_ok = false;
@@ -142,7 +156,13 @@ struct Plan {
 struct Batch {
   std::vector<const Plan*> plans;
   std::vector<int> wide;            // plans run in the per-step form
-  size_t wide_ws = 0;               // workspace those need (one at a time)
+  size_t wide_ws = 0;               // workspace those need (all at once)
+  std::vector<size_t> wide_off;     // per wide plan: its workspace region
+  std::vector<WideItem> wide_order; // their launches, level by level
+  std::vector<WideGroupStep> wide_steps;
+  std::vector<int32_t> wide_first;  // group g: wide_steps [first[g], first[g + 1])
+  std::vector<uint64_t> wide_prefix;  // group g: count + 1 unit offsets from first[g] + g
+  void* d_wide = nullptr;           // wide_steps, then wide_prefix
   std::vector<int64_t> item_begin;  // per plan, into the item table (+ end)
   int64_t n_items = 0;
   int lds_bytes = 0;
