@@ -298,7 +298,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-extra", action="store_true", help="skip the 7x7 and batch lines")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--only", choices=["hbm", "batch", "many", "learned"], help="run just one extra workload")
+    ap.add_argument("--only", choices=["hbm", "hbm_fp32", "batch", "many", "learned"],
+                    help="run just one extra workload (hbm_fp32: the 7x7 line in FP32 only)")
     ap.add_argument("--pmc-workload", action="store_true",
                     help="for hardware-counter runs: a device-to-device copy of 256 MiB (three times, the "
                          "calibration of the byte counters) and 20 launches of the headline fused kernel")
@@ -329,6 +330,9 @@ def main():
         torch.cuda.synchronize()
         got = complex(*out.cpu().numpy())
         log(f"[bench] pmc workload done, rel err {abs(got - want) / abs(want):.2e}")
+        return
+    if args.only == "hbm_fp32":
+        print(json.dumps(bench_hbm(torch, qbe, ctx, args.steps)), flush=True)
         return
     if args.only == "hbm":
         print(json.dumps(bench_hbm(torch, qbe, ctx, args.steps)), flush=True)
