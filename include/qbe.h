@@ -50,7 +50,10 @@ enum {
 enum {
   QBE_SCORE_TREE_TRIMMING = 0, /* Sec. 3.2                                 */
   QBE_SCORE_DEGREE = 1,        /* Sec. 3.1, number of neighbours            */
-  QBE_SCORE_TW_REDUCTION = 2   /* Sec. 3.1, Alg. 3 (direct width drop)      */
+  QBE_SCORE_TW_REDUCTION = 2,  /* Sec. 3.1, Alg. 3 (direct width drop)      */
+  QBE_SCORE_BETWEENNESS = 3    /* Sec. 3.1, betweenness centrality
+                                  (unnormalised; ties to the earliest vertex
+                                  of the order after rounding to 1e-9)     */
 };
 
 /* Device execution forms of a plan. */

@@ -34,7 +34,7 @@ _lib = C.CDLL(LIB_PATH)
 
 QBE_OK = 0
 ERRORS = {-1: "INVALID_ARG", -2: "OOM", -3: "HIP", -4: "MEM_CAP", -5: "INTERNAL", -6: "NO_DEVICE"}
-SCORE = {"tree_trimming": 0, "degree": 1, "tw_reduction": 2}
+SCORE = {"tree_trimming": 0, "degree": 1, "tw_reduction": 2, "betweenness": 3}
 EXEC = {"auto": 0, "per_step": 1, "fused": 2}
 PREC = {"fp32": 0, "bf16x3": 1, "bf16x6": 2}
 

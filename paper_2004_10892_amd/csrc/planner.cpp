@@ -2,6 +2,7 @@
 #include "planner.hpp"
 
 #include <algorithm>
+#include <cmath>
 #include <stdexcept>
 #include <unordered_map>
 
@@ -263,6 +264,58 @@ int degree_pick(const Graph& g, const std::vector<int>& order) {
   return best;
 }
 
+int betweenness_pick(const Graph& g, const std::vector<int>& order) {
+  const int n = g.n;
+  std::vector<std::vector<int>> nb(n);
+  for (int v : order) nb[v] = g.neighbours(v);
+  std::vector<double> bc(n, 0.0), sigma(n, 0.0), delta(n, 0.0);
+  std::vector<int> dist(n, -1), seq;
+  std::vector<std::vector<int>> pred(n);
+  seq.reserve(order.size());
+  for (int s : order) {
+    // shortest-path counts from s (breadth first), then the dependencies
+    // of s on every vertex, accumulated from the farthest vertices back
+    for (int v : order) {
+      dist[v] = -1;
+      sigma[v] = 0.0;
+      delta[v] = 0.0;
+      pred[v].clear();
+    }
+    seq.clear();
+    dist[s] = 0;
+    sigma[s] = 1.0;
+    seq.push_back(s);
+    for (size_t h = 0; h < seq.size(); ++h) {
+      const int v = seq[h];
+      for (int w : nb[v]) {
+        if (dist[w] < 0) {
+          dist[w] = dist[v] + 1;
+          seq.push_back(w);
+        }
+        if (dist[w] == dist[v] + 1) {
+          sigma[w] += sigma[v];
+          pred[w].push_back(v);
+        }
+      }
+    }
+    for (size_t h = seq.size(); h-- > 0;) {
+      const int w = seq[h];
+      for (int v : pred[w]) delta[v] += sigma[v] / sigma[w] * (1.0 + delta[w]);
+      if (w != s) bc[w] += delta[w];
+    }
+  }
+  int best = -1;
+  long long bk = 0;
+  for (int v : order) {
+    const long long k = std::llround(bc[v] / 2.0 * 1e9);
+    if (best < 0 || k > bk) {
+      best = v;
+      bk = k;
+    }
+  }
+  return best;
+}
+
 static Graph without(const Graph& g, int u) {
   Graph h = g;
   h.remove_vertex(u);
@@ -300,6 +353,7 @@ Deletion greedy_deletion(const Graph& g0, const std::vector<int>& order, int m, 
       case SCORE_TREE_TRIMMING: u = tree_trimming_pick(g, d.reduced_order); break;
       case SCORE_DEGREE: u = degree_pick(g, d.reduced_order); break;
       case SCORE_TW_REDUCTION: u = tw_reduction_pick(g, d.reduced_order); break;
+      case SCORE_BETWEENNESS: u = betweenness_pick(g, d.reduced_order); break;
       default: throw std::invalid_argument("unknown score");
     }
     g.remove_vertex(u);

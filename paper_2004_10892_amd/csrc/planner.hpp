@@ -55,9 +55,13 @@ struct CliqueTree {
 // through the elimination tree.
 CliqueTree clique_tree(const Graph& g, const std::vector<int>& order);
 
-enum Score { SCORE_TREE_TRIMMING = 0, SCORE_DEGREE = 1, SCORE_TW_REDUCTION = 2 };
+enum Score { SCORE_TREE_TRIMMING = 0, SCORE_DEGREE = 1, SCORE_TW_REDUCTION = 2, SCORE_BETWEENNESS = 3 };
 
 int tree_trimming_pick(const Graph& g, const std::vector<int>& order);
+// Sec. 3.1 betweenness centrality (unnormalised, undirected: each pair once)
+// by Brandes' accumulation; the largest value rounded to 1e-9 wins, ties to
+// the earliest vertex in order.
+int betweenness_pick(const Graph& g, const std::vector<int>& order);
 int degree_pick(const Graph& g, const std::vector<int>& order);
 int tw_reduction_pick(const Graph& g, const std::vector<int>& order);
 

@@ -66,7 +66,7 @@ def test_plans_bit_exact_on_circuits(rows, cols, depth, seed, m):
     plan.check()
 
 
-@pytest.mark.parametrize("score", ["degree", "tw_reduction"])
+@pytest.mark.parametrize("score", ["degree", "tw_reduction", "betweenness"])
 def test_other_scores_bit_exact(score):
     for seed in range(4):
         mod = circuit_model(random_grid_circuit(3, 4, 8, seed))
@@ -206,3 +206,32 @@ def test_host_clone_keeps_schedule_and_checks_structure():
     other = qbe.Model.from_circuitgen(circuit_model(random_grid_circuit(4, 4, 11, 5)))
     with pytest.raises(qbe.QbeError):
         qbe.Plan(a, pi, mu).clone(other)
+
+
+def test_betweenness_bit_exact_on_larger_circuits():
+    for (r, c, d, s, m) in [(5, 6, 16, 2, 6), (6, 6, 16, 3, 5)]:
+        mod = circuit_model(random_grid_circuit(r, c, d, s))
+        _, order, mu, pi, tau, _ = oracle_plan(mod, m, score="betweenness")
+        qm = qbe.Model.from_circuitgen(mod)
+        assert qbe.qbe_slice(qm, order, m, score="betweenness") == (mu, pi, tau)
+
+
+def test_score_study_rows_follow_the_planner():
+    """The study's rows are the planner's choices and the cost model's
+    figures for every m; the greedy choices are prefix-consistent."""
+    from paper_2004_10892_amd import study as S
+    qm = qbe.Model.from_circuitgen(circuit_model(random_grid_circuit(4, 4, 10, 2)))
+    res = S.study(qm, S.SCORES, m_max=4)
+    order = qbe.qbe_order_min_fill(qm)
+    widths0 = {rows[0]["width"] for rows in res.values()}
+    assert len(widths0) == 1  # nothing removed: the same order for every score
+    for score, rows in res.items():
+        assert [r["m"] for r in rows] == list(range(5))
+        for r in rows:
+            mu, red, tau = qbe.qbe_slice(qm, order, r["m"], score=score)
+            c = qbe.qbe_schedule_cost(qm, red, mu)
+            assert r["mu"] == mu and r["width"] == tau
+            assert r["flops_per_slice"] == c["flops_per_slice"]
+            assert r["peak_bytes_per_slice"] == c["peak_bytes_per_slice"]
+        assert rows[-1]["mu"][:3] == rows[3]["mu"]
+    assert "| m |" in S.table(res)

@@ -228,3 +228,73 @@ def test_free_variable_contributes_factor_two():
     got, _ = C.contract(t, s)
     assert abs(got - 2 * (3.0 + 1j)) < 1e-14
     assert abs(C.brute_force_sum(2, t) - got) < 1e-14
+
+
+def _brute_betweenness(adj):
+    """Betweenness by enumerating every shortest path of every unordered
+    pair (tiny graphs only): the share of s-t shortest paths through v."""
+    import itertools
+    from collections import deque
+    verts = sorted(adj)
+
+    def dist_from(s):
+        d = {s: 0}
+        q = deque([s])
+        while q:
+            v = q.popleft()
+            for w in adj[v]:
+                if w not in d:
+                    d[w] = d[v] + 1
+                    q.append(w)
+        return d
+
+    dist = {s: dist_from(s) for s in verts}
+
+    def paths(s, t):
+        if s == t:
+            return [[s]]
+        out = []
+        for w in adj[s]:
+            if w in dist[t] and dist[t][w] == dist[t][s] - 1:
+                out += [[s] + p for p in paths(w, t)]
+        return out
+
+    bc = {v: 0.0 for v in verts}
+    for s, t in itertools.combinations(verts, 2):
+        if t not in dist[s]:
+            continue
+        ps = paths(s, t)
+        for v in verts:
+            if v not in (s, t):
+                bc[v] += sum(v in p for p in ps) / len(ps)
+    return bc
+
+
+def test_betweenness_closed_forms_and_brute_force():
+    """Sec. 3.1 betweenness score: on a path of n vertices vertex i lies on
+    i (n - 1 - i) shortest paths, so the middle vertex is picked; a star's
+    centre lies on all C(n - 1, 2) leaf pairs; on small random graphs the
+    pick is the vertex of largest brute-force betweenness (earliest in the
+    order on ties)."""
+    n = 7
+    path = {i: {j for j in (i - 1, i + 1) if 0 <= j < n} for i in range(n)}
+    assert P.betweenness_pick(path, list(range(n))) == 3
+    bc = _brute_betweenness(path)
+    assert all(abs(bc[i] - i * (n - 1 - i)) < 1e-12 for i in range(n))
+    star = {0: set(range(1, 6)), **{i: {0} for i in range(1, 6)}}
+    assert P.betweenness_pick(star, [3, 1, 0, 2, 4, 5]) == 0
+    assert _brute_betweenness(star)[0] == 10
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        k = int(rng.integers(5, 9))
+        adj = {v: set() for v in range(k)}
+        for a in range(k):
+            for b in range(a + 1, k):
+                if rng.random() < 0.35:
+                    adj[a].add(b)
+                    adj[b].add(a)
+        order = [int(v) for v in rng.permutation(k)]
+        bc = _brute_betweenness(adj)
+        pos = {u: i for i, u in enumerate(order)}
+        want = max(adj, key=lambda u: (round(bc[u], 9), -pos[u]))
+        assert P.betweenness_pick(adj, order) == want
