@@ -182,6 +182,40 @@ int qbe_clique_tree(const qbe_model* model, const int32_t* order, int32_t n, int
 int qbe_slice(const qbe_model* model, const int32_t* order, int32_t n, int32_t m,
               int32_t target_width, int32_t score, int32_t* mu_out, int32_t* m_out,
               int32_t* reduced_order_out, int32_t* tau_out);
+/* Alg. 2 with its optional line (Sec. 3): after every recompute_every-th
+ * removal (> 0) the reduced order is recomputed on the reduced graph: the
+ * anytime order of qbe_order_anytime(tries, seed) is turned into its tree
+ * decomposition (App. A) and back into an order by Alg. 5 (App. B), the
+ * route an external tree-decomposition solver's output would take.
+ * recompute_every = 0 is qbe_slice.  Arguments and outputs as qbe_slice;
+ * tries >= 1.  QBE_ERR_INVALID_ARG for a bad order, m, score or tries. */
+int qbe_slice_recompute(const qbe_model* model, const int32_t* order, int32_t n, int32_t m,
+                        int32_t target_width, int32_t score, int32_t recompute_every, int32_t tries,
+                        uint64_t seed, int32_t* mu_out, int32_t* m_out, int32_t* reduced_order_out,
+                        int32_t* tau_out);
+
+/* The project's anytime tree-decomposition heuristic, standing in for the
+ * external solver of Sec. 4: greedy min-fill, then tries - 1 min-fill runs
+ * whose (fill, degree) ties go to SplitMix64(seed) priorities (one draw per
+ * remaining vertex in ascending id order per run); the first order of the
+ * smallest width (Alg. 1) wins.  removed: vertices deleted first (may be
+ * NULL when n_removed == 0).  Outputs: order_out (capacity n_vars; n_vars -
+ * n_removed entries), *width_out.  tries >= 1. */
+int qbe_order_anytime(const qbe_model* model, const int32_t* removed, int32_t n_removed, int32_t tries,
+                      uint64_t seed, int32_t* order_out, int32_t* width_out);
+
+/* App. B, Alg. 5: an elimination order consistent with a tree decomposition
+ * of n_bags bags over vertices [0, n_vars): bag i holds bag_vars[bag_offsets
+ * [i] .. bag_offsets[i + 1]) (ids ascending), parent[i] its parent bag or -1
+ * for a root (a forest is allowed).  Repeatedly the first non-root leaf (in
+ * bag order) gives the vertices it has and its parent lacks (ascending ids)
+ * and is removed; the roots' vertices come last.  Outputs: order_out
+ * (capacity n_vars), *n_out = vertices listed.  QBE_ERR_INVALID_ARG for ids
+ * out of range, unsorted bags, a parent array that is not a forest, or a
+ * vertex listed twice (a decomposition without the running-intersection
+ * property). */
+int qbe_order_from_td(int32_t n_vars, int32_t n_bags, const int32_t* bag_offsets, const int32_t* bag_vars,
+                      const int32_t* parent, int32_t* order_out, int32_t* n_out);
 
 /* Exact cost (the project's cost model for Sec. 4's per-subtask memory and
  * FLOPs) of contracting with the reduced order and sliced set, without

@@ -305,6 +305,120 @@ def greedy_treewidth_deletion(adj: Adj, order: Sequence[int], m: int,
     return mu, g, pi, treewidth_from_order(g, pi)
 
 
+# ------------------------------------------ order recomputation (Alg. 2, 5) --
+
+def recover_order(bags, parent) -> List[int]:
+    """App. B, Alg. 5: an elimination order consistent with a tree
+    decomposition.  Repeatedly the first bag (in index order) that is a leaf
+    and not a root is taken; the vertices it has and its parent lacks go to
+    the order (ascending ids; the algorithm allows any order), and the leaf
+    is removed.  The roots' vertices come last (a forest: root by root)."""
+    nb = len(bags)
+    alive = [True] * nb
+    children = [0] * nb
+    for i, p in enumerate(parent):
+        if p >= 0:
+            children[p] += 1
+    order: List[int] = []
+    while True:
+        leaf = next((i for i in range(nb) if alive[i] and parent[i] >= 0 and children[i] == 0), None)
+        if leaf is None:
+            break
+        order += sorted(set(bags[leaf]) - set(bags[parent[leaf]]))
+        alive[leaf] = False
+        children[parent[leaf]] -= 1
+    for i in range(nb):
+        if alive[i]:
+            order += sorted(bags[i])
+    return order
+
+
+class _SplitMix64:
+    """SplitMix64 (Steele, Lea and Flood, 2014)."""
+
+    def __init__(self, seed: int):
+        self.state = seed & 0xFFFFFFFFFFFFFFFF
+
+    def next(self) -> int:
+        self.state = (self.state + 0x9E3779B97F4A7C15) & 0xFFFFFFFFFFFFFFFF
+        z = self.state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & 0xFFFFFFFFFFFFFFFF
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & 0xFFFFFFFFFFFFFFFF
+        return z ^ (z >> 31)
+
+
+def _min_fill_with(adj: Adj, prio: Dict[int, int]) -> List[int]:
+    """Greedy min-fill; ties in (fill, degree) go to the smaller prio[v]."""
+    verts = sorted(adj)
+    nb = {v: set(adj[v]) for v in verts}
+    alive = set(verts)
+    order = []
+
+    def fill(v):
+        ns = nb[v]
+        d = len(ns)
+        inner = sum(len(nb[w] & ns) for w in ns)
+        return d * (d - 1) // 2 - inner // 2
+
+    while alive:
+        u = min(alive, key=lambda v: (fill(v), len(nb[v]), prio[v]))
+        order.append(u)
+        for w in nb[u]:
+            nb[w] |= nb[u]
+            nb[w].discard(w)
+            nb[w].discard(u)
+        nb[u] = set()
+        alive.discard(u)
+    return order
+
+
+def anytime_order(adj: Adj, tries: int, seed: int) -> List[int]:
+    """The project's anytime tree-decomposition heuristic (it stands in for
+    the external solver of Sec. 4): try 0 is greedy min-fill (ties: degree,
+    id); try t >= 1 breaks (fill, degree) ties by random priorities drawn
+    from one SplitMix64(seed) stream, one draw per vertex in ascending id
+    order per try.  The first order of smallest width wins."""
+    rng = _SplitMix64(seed)
+    best = min_fill_order(adj)
+    bw = treewidth_from_order(adj, best)
+    for _ in range(1, tries):
+        prio = {v: rng.next() for v in sorted(adj)}
+        o = _min_fill_with(adj, prio)
+        w = treewidth_from_order(adj, o)
+        if w < bw:
+            best, bw = o, w
+    return best
+
+
+def greedy_treewidth_deletion_recompute(adj: Adj, order: Sequence[int], m: int, recompute_every: int,
+                                        tries: int, seed: int, target_width: int = -1,
+                                        score: str = "tree_trimming"):
+    """Alg. 2 with its optional line: after every ``recompute_every``-th
+    removal the reduced order is recomputed -- the anytime heuristic's
+    order on the reduced graph, turned into its tree decomposition (App. A)
+    and back into an order by Alg. 5.  Returns ``(mu, reduced_graph,
+    reduced_order, tau)``."""
+    pick = SCORES[score]
+    g = copy_graph(adj)
+    pi = list(order)
+    mu: List[int] = []
+    while pi:
+        if m >= 0 and len(mu) >= m:
+            break
+        if m < 0 and treewidth_from_order(g, pi) <= target_width:
+            break
+        u = pick(g, pi)
+        g = remove_vertex(g, u)
+        pi.remove(u)
+        mu.append(u)
+        if recompute_every > 0 and len(mu) % recompute_every == 0 and pi:
+            bags, parent = clique_tree(g, anytime_order(g, tries, seed))
+            pi = recover_order(bags, parent)
+    if m >= 0 and len(mu) < m:
+        raise ValueError("cannot remove more vertices than the graph has")
+    return mu, g, pi, treewidth_from_order(g, pi)
+
+
 def optimal_treewidth(adj: Adj) -> int:
     """Brute-force treewidth: minimum width over all elimination orders.
 

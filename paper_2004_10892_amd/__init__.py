@@ -86,6 +86,11 @@ _SIGS = {
     "qbe_plan_create": (C.c_int, [_vp, _vp, _i32p, C.c_int32, _i32p, C.c_int32, C.POINTER(PlanOpts), C.POINTER(_vp)]),
     "qbe_plan_destroy": (C.c_int, [_vp]),
     "qbe_plan_update_data": (C.c_int, [_vp, _vp]),
+    "qbe_slice_recompute": (C.c_int, [_vp, _i32p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                      C.c_int32, C.c_uint64, _i32p, C.POINTER(C.c_int32), _i32p,
+                                      C.POINTER(C.c_int32)]),
+    "qbe_order_anytime": (C.c_int, [_vp, _i32p, C.c_int32, C.c_int32, C.c_uint64, _i32p, C.POINTER(C.c_int32)]),
+    "qbe_order_from_td": (C.c_int, [C.c_int32, C.c_int32, _i32p, _i32p, _i32p, _i32p, C.POINTER(C.c_int32)]),
     "qbe_plan_clone": (C.c_int, [_vp, _vp, C.POINTER(_vp)]),
     "qbe_plan_stats": (C.c_int, [_vp, C.POINTER(Stats)]),
     "qbe_plan_dump": (C.c_int, [_vp, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]),
@@ -236,18 +241,49 @@ def qbe_clique_tree(model: Model, order: Sequence[int]):
 
 
 def qbe_slice(model: Model, order: Sequence[int], m: int, target_width: int = -1,
-              score: str = "tree_trimming"):
-    """Alg. 2.  Returns (mu, reduced_order, tau)."""
+              score: str = "tree_trimming", recompute_every: int = 0, tries: int = 8, seed: int = 0):
+    """Alg. 2 (with recompute_every > 0: its optional order recomputation
+    after every recompute_every-th removal).  Returns (mu, reduced_order, tau)."""
     o = _i32(order)
     n = len(o)
     mu = np.zeros(max(n, 1), dtype=np.int32)
     red = np.zeros(max(n, 1), dtype=np.int32)
     mo = C.c_int32()
     tau = C.c_int32()
-    _check(_lib.qbe_slice(model.handle, _p32(o), n, m, target_width, SCORE[score], _p32(mu), C.byref(mo),
-                          _p32(red), C.byref(tau)), "qbe_slice")
+    if recompute_every > 0:
+        _check(_lib.qbe_slice_recompute(model.handle, _p32(o), n, m, target_width, SCORE[score],
+                                        recompute_every, tries, seed, _p32(mu), C.byref(mo), _p32(red),
+                                        C.byref(tau)), "qbe_slice_recompute")
+    else:
+        _check(_lib.qbe_slice(model.handle, _p32(o), n, m, target_width, SCORE[score], _p32(mu), C.byref(mo),
+                              _p32(red), C.byref(tau)), "qbe_slice")
     k = mo.value
     return mu[:k].tolist(), red[:n - k].tolist(), tau.value
+
+
+def qbe_order_anytime(model: Model, removed: Sequence[int] = (), tries: int = 8, seed: int = 0):
+    """The anytime tree-decomposition heuristic.  Returns (order, width)."""
+    r = _i32(removed)
+    out = np.zeros(max(model.n_vars, 1), dtype=np.int32)
+    w = C.c_int32()
+    _check(_lib.qbe_order_anytime(model.handle, _p32(r), len(r), tries, seed, _p32(out), C.byref(w)),
+           "qbe_order_anytime")
+    return out[:model.n_vars - len(r)].tolist(), w.value
+
+
+def qbe_order_from_td(n_vars: int, bags: Sequence[Sequence[int]], parent: Sequence[int]) -> List[int]:
+    """Alg. 5: an elimination order consistent with a tree decomposition."""
+    offs = [0]
+    flat: List[int] = []
+    for b in bags:
+        flat += sorted(b)
+        offs.append(len(flat))
+    bo, bv, pa = _i32(offs), _i32(flat if flat else [0]), _i32(parent if len(parent) else [0])
+    out = np.zeros(max(n_vars, 1), dtype=np.int32)
+    k = C.c_int32()
+    _check(_lib.qbe_order_from_td(n_vars, len(bags), _p32(bo), _p32(bv), _p32(pa), _p32(out), C.byref(k)),
+           "qbe_order_from_td")
+    return out[:k.value].tolist()
 
 
 def qbe_schedule_cost(model: Model, reduced_order: Sequence[int], mu: Sequence[int]) -> dict:

@@ -224,6 +224,84 @@ int qbe_width(const qbe_model* model, const int32_t* order, int32_t n, const int
   QBE_GUARD_END
 }
 
+int qbe_slice_recompute(const qbe_model* model, const int32_t* order, int32_t n, int32_t m,
+                        int32_t target_width, int32_t score, int32_t recompute_every, int32_t tries,
+                        uint64_t seed, int32_t* mu_out, int32_t* m_out, int32_t* reduced_order_out,
+                        int32_t* tau_out) {
+  QBE_GUARD_BEGIN
+  QBE_REQUIRE(model && m_out && tau_out, "NULL argument");
+  QBE_REQUIRE(n == model->m.n_vars, "order must list every variable");
+  QBE_REQUIRE(m <= n, "m larger than the number of variables");
+  QBE_REQUIRE(recompute_every >= 0 && tries >= 1, "recompute_every >= 0 and tries >= 1 required");
+  auto d = qbe::greedy_deletion(graph_of(model->m), vec(order, n), m, target_width, score, recompute_every,
+                                tries, seed);
+  QBE_REQUIRE(d.mu.empty() || mu_out, "mu_out is NULL");
+  QBE_REQUIRE(d.reduced_order.empty() || reduced_order_out, "reduced_order_out is NULL");
+  for (size_t i = 0; i < d.mu.size(); ++i) mu_out[i] = d.mu[i];
+  for (size_t i = 0; i < d.reduced_order.size(); ++i) reduced_order_out[i] = d.reduced_order[i];
+  *m_out = (int32_t)d.mu.size();
+  *tau_out = d.tau;
+  return QBE_OK;
+  QBE_GUARD_END
+}
+
+int qbe_order_anytime(const qbe_model* model, const int32_t* removed, int32_t n_removed, int32_t tries,
+                      uint64_t seed, int32_t* order_out, int32_t* width_out) {
+  QBE_GUARD_BEGIN
+  QBE_REQUIRE(model && order_out && width_out, "NULL argument");
+  QBE_REQUIRE(tries >= 1, "tries must be >= 1");
+  QBE_REQUIRE(n_removed >= 0 && (n_removed == 0 || removed), "bad removed list");
+  qbe::Graph g = graph_of(model->m);
+  for (int i = 0; i < n_removed; ++i) {
+    QBE_REQUIRE(removed[i] >= 0 && removed[i] < g.n && g.present[removed[i]], "bad removed vertex");
+    g.remove_vertex(removed[i]);
+  }
+  std::vector<int> o = qbe::anytime_order(g, tries, seed);
+  for (size_t i = 0; i < o.size(); ++i) order_out[i] = o[i];
+  *width_out = qbe::width_of_order(g, o);
+  return QBE_OK;
+  QBE_GUARD_END
+}
+
+int qbe_order_from_td(int32_t n_vars, int32_t n_bags, const int32_t* bag_offsets, const int32_t* bag_vars,
+                      const int32_t* parent, int32_t* order_out, int32_t* n_out) {
+  QBE_GUARD_BEGIN
+  QBE_REQUIRE(n_vars >= 0 && n_bags >= 0 && n_out && (n_bags == 0 || (bag_offsets && bag_vars && parent)),
+              "bad argument");
+  QBE_REQUIRE(n_bags == 0 || order_out || n_vars == 0, "order_out is NULL");
+  qbe::CliqueTree td;
+  td.bags.resize(n_bags);
+  td.parent.assign(parent, parent + n_bags);
+  for (int i = 0; i < n_bags; ++i) {
+    QBE_REQUIRE(bag_offsets[i] >= 0 && bag_offsets[i] <= bag_offsets[i + 1], "bad bag offsets");
+    for (int k = bag_offsets[i]; k < bag_offsets[i + 1]; ++k) {
+      QBE_REQUIRE(bag_vars[k] >= 0 && bag_vars[k] < n_vars, "bag vertex out of range");
+      QBE_REQUIRE(k == bag_offsets[i] || bag_vars[k - 1] < bag_vars[k], "bag ids must ascend");
+      td.bags[i].push_back(bag_vars[k]);
+    }
+    QBE_REQUIRE(parent[i] >= -1 && parent[i] < n_bags && parent[i] != i, "bad parent");
+  }
+  // a forest: every bag reaches a root within n_bags steps
+  for (int i = 0; i < n_bags; ++i) {
+    int x = i, steps = 0;
+    while (x >= 0 && steps <= n_bags) {
+      x = td.parent[x];
+      ++steps;
+    }
+    QBE_REQUIRE(x < 0, "parent array has a cycle");
+  }
+  std::vector<int> o = qbe::recover_order(td);
+  std::vector<uint8_t> seen(n_vars, 0);
+  for (int v : o) {
+    QBE_REQUIRE(!seen[v], "a vertex is listed twice: not a tree decomposition");
+    seen[v] = 1;
+  }
+  for (size_t i = 0; i < o.size(); ++i) order_out[i] = o[i];
+  *n_out = (int32_t)o.size();
+  return QBE_OK;
+  QBE_GUARD_END
+}
+
 int qbe_clique_tree(const qbe_model* model, const int32_t* order, int32_t n, int32_t* n_bags,
                     int32_t* bag_offsets, int32_t* bag_vars, int64_t cap_vars, int32_t* parent) {
   QBE_GUARD_BEGIN

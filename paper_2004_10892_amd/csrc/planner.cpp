@@ -113,7 +113,13 @@ int width_of_order(const Graph& g, const std::vector<int>& order) {
 
 // --------------------------------------------------------------- min-fill --
 
-std::vector<int> min_fill_order(const Graph& g0) {
+// Greedy min-fill; ties in (fill, degree) go to the smaller prio[v], or to
+// the smaller id without priorities.
+static std::vector<int> min_fill_prio(const Graph& g0, const std::vector<uint64_t>* prio);
+
+std::vector<int> min_fill_order(const Graph& g0) { return min_fill_prio(g0, nullptr); }
+
+static std::vector<int> min_fill_prio(const Graph& g0, const std::vector<uint64_t>* prio) {
   Graph g = g0;
   const int n = g.n;
   std::vector<int64_t> fill(n, 0);
@@ -148,7 +154,8 @@ std::vector<int> min_fill_order(const Graph& g0) {
     size_t bi = 0;
     for (size_t i = 1; i < alive.size(); ++i) {
       int a = alive[i], b = alive[bi];
-      if (fill[a] < fill[b] || (fill[a] == fill[b] && (deg[a] < deg[b] || (deg[a] == deg[b] && a < b))))
+      const bool tie_a = prio ? (*prio)[a] < (*prio)[b] : a < b;
+      if (fill[a] < fill[b] || (fill[a] == fill[b] && (deg[a] < deg[b] || (deg[a] == deg[b] && tie_a))))
         bi = i;
     }
     int u = alive[bi];
@@ -339,8 +346,63 @@ int tw_reduction_pick(const Graph& g, const std::vector<int>& order) {
   return best;
 }
 
+std::vector<int> recover_order(const CliqueTree& td) {
+  const int nb = (int)td.bags.size();
+  std::vector<uint8_t> alive(nb, 1);
+  std::vector<int> children(nb, 0);
+  for (int i = 0; i < nb; ++i)
+    if (td.parent[i] >= 0) ++children[td.parent[i]];
+  std::vector<int> order;
+  for (;;) {
+    int leaf = -1;
+    for (int i = 0; i < nb && leaf < 0; ++i)
+      if (alive[i] && td.parent[i] >= 0 && children[i] == 0) leaf = i;
+    if (leaf < 0) break;
+    const std::vector<int>& b = td.bags[leaf];
+    const std::vector<int>& pb = td.bags[td.parent[leaf]];
+    for (int v : b)  // bags list ids ascending
+      if (!std::binary_search(pb.begin(), pb.end(), v)) order.push_back(v);
+    alive[leaf] = 0;
+    --children[td.parent[leaf]];
+  }
+  for (int i = 0; i < nb; ++i)
+    if (alive[i]) order.insert(order.end(), td.bags[i].begin(), td.bags[i].end());
+  return order;
+}
+
+namespace {
+// SplitMix64 (Steele, Lea and Flood, 2014).
+struct SplitMix64 {
+  uint64_t state;
+  uint64_t next() {
+    uint64_t z = (state += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  }
+};
+}  // namespace
+
+std::vector<int> anytime_order(const Graph& g, int tries, uint64_t seed) {
+  SplitMix64 rng{seed};
+  std::vector<int> best = min_fill_order(g);
+  int bw = width_of_order(g, best);
+  std::vector<uint64_t> prio(g.n, 0);
+  for (int t = 1; t < tries; ++t) {
+    for (int v = 0; v < g.n; ++v)
+      if (g.present[v]) prio[v] = rng.next();
+    std::vector<int> o = min_fill_prio(g, &prio);
+    const int w = width_of_order(g, o);
+    if (w < bw) {
+      best.swap(o);
+      bw = w;
+    }
+  }
+  return best;
+}
+
 Deletion greedy_deletion(const Graph& g0, const std::vector<int>& order, int m, int target_width,
-                         int score) {
+                         int score, int recompute_every, int tries, uint64_t seed) {
   check_order(g0, order);
   Graph g = g0;
   Deletion d;
@@ -359,6 +421,8 @@ Deletion greedy_deletion(const Graph& g0, const std::vector<int>& order, int m, 
     g.remove_vertex(u);
     d.reduced_order.erase(std::find(d.reduced_order.begin(), d.reduced_order.end(), u));
     d.mu.push_back(u);
+    if (recompute_every > 0 && d.mu.size() % (size_t)recompute_every == 0 && !d.reduced_order.empty())
+      d.reduced_order = recover_order(clique_tree(g, anytime_order(g, tries, seed)));
   }
   if (m >= 0 && (int)d.mu.size() < m)
     throw std::invalid_argument("cannot remove more vertices than the graph has");

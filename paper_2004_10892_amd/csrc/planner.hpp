@@ -72,8 +72,20 @@ struct Deletion {
 };
 // Alg. 2 without recomputing the order.  m >= 0: remove m vertices;
 // m < 0: remove until the width is <= target_width.
+// App. B, Alg. 5: an elimination order consistent with a tree decomposition
+// (first leaf in bag order, its vertices missing from its parent in
+// ascending ids; the roots' vertices last).
+std::vector<int> recover_order(const CliqueTree& td);
+// The anytime tree-decomposition heuristic: min-fill, then tries - 1
+// min-fill runs whose (fill, degree) ties go to SplitMix64(seed) priorities
+// (one draw per present vertex in id order per run); the first order of
+// smallest width wins.
+std::vector<int> anytime_order(const Graph& g, int tries, uint64_t seed);
+// Alg. 2; with recompute_every = k > 0 its optional line runs after every
+// k-th removal: the reduced order becomes Alg. 5's order of the clique tree
+// of anytime_order(reduced graph, tries, seed).
 Deletion greedy_deletion(const Graph& g, const std::vector<int>& order, int m, int target_width,
-                         int score);
+                         int score, int recompute_every = 0, int tries = 1, uint64_t seed = 0);
 
 // ---------------------------------------------------------------- schedule --
 

@@ -8,12 +8,13 @@ order (Fig. 7), the FLOPs of one slice (Fig. 10), the total FLOPs 2^m times
 that (Fig. 11), the peak memory of one slice (Fig. 12), and the time the
 heuristic took to choose the first m variables (Fig. 9).  Every figure comes
 from the library's host planner and its exact cost model (no contraction is
-run).  Alg. 2 is greedy without order recomputation, so the first k choices
-for m are the choices for k: one run to m_max gives every m.
+run).  With --recompute k the reduced order is recomputed every k removals
+(Alg. 2's optional line, Fig. 8's variable) by the project's anytime
+tree-decomposition heuristic and Alg. 5.
 
 Usage: python -m paper_2004_10892_amd.study [--rows 7 --cols 7 --depth 24
-       --seed 0 --m-max 20 --scores degree,betweenness,tw_reduction,tree_trimming
-       --json out.json]
+       --seed 0 --m-max 20 --every 1 --scores degree,betweenness,tw_reduction,
+       tree_trimming --recompute 0 --tries 4 --json out.json]
 """
 from __future__ import annotations
 
@@ -27,9 +28,13 @@ from typing import Dict, List, Sequence
 SCORES = ("degree", "betweenness", "tw_reduction", "tree_trimming")
 
 
-def study(model, scores: Sequence[str] = SCORES, m_max: int = 20) -> Dict[str, List[dict]]:
-    """Rows per score: m, width, flops_per_slice, total_flops,
-    peak_bytes_per_slice, pick_ms (time to choose the first m variables)."""
+def study(model, scores: Sequence[str] = SCORES, m_max: int = 20, every: int = 1,
+          recompute_every: int = 0, tries: int = 4, seed: int = 0) -> Dict[str, List[dict]]:
+    """Rows per score for m = 0, every, 2 every, ... m_max: m, width,
+    flops_per_slice, log2_total_flops, peak_bytes_per_slice, pick_ms (time to
+    choose the m variables) and mu.  recompute_every > 0 runs Alg. 2 with its
+    optional order recomputation (Fig. 8's variable) every that many
+    removals, with the anytime heuristic's tries and seed."""
     import paper_2004_10892_amd as qbe
 
     order = qbe.qbe_order_min_fill(model)
@@ -38,13 +43,14 @@ def study(model, scores: Sequence[str] = SCORES, m_max: int = 20) -> Dict[str, L
         rows = []
         mu_all: List[int] = []
         t_prev = 0.0
-        for m in range(m_max + 1):
+        for m in range(0, m_max + 1, every):
             # time the heuristic for exactly m removals (it restarts from
             # scratch, as a user asking for m would)
             t0 = time.perf_counter()
-            mu, red, tau = qbe.qbe_slice(model, order, m, score=score)
+            mu, red, tau = qbe.qbe_slice(model, order, m, score=score, recompute_every=recompute_every,
+                                         tries=tries, seed=seed)
             t_prev = (time.perf_counter() - t0) * 1e3
-            if mu_all and mu[:len(mu_all)] != mu_all:
+            if recompute_every == 0 and mu_all and mu[:len(mu_all)] != mu_all:
                 raise AssertionError("greedy choices are not prefix-consistent")
             mu_all = mu
             c = qbe.qbe_schedule_cost(model, red, mu)
@@ -56,7 +62,7 @@ def study(model, scores: Sequence[str] = SCORES, m_max: int = 20) -> Dict[str, L
     return out
 
 
-def table(res: Dict[str, List[dict]], every: int = 1) -> str:
+def table(res: Dict[str, List[dict]]) -> str:
     """Markdown table: one row per m, per score width / log2 FLOPs per slice /
     log2 total FLOPs / log2 peak bytes."""
     scores = list(res)
@@ -64,7 +70,7 @@ def table(res: Dict[str, List[dict]], every: int = 1) -> str:
     sep = "|---|" + "---|" * len(scores)
     lines = [head, sep]
     n = len(next(iter(res.values())))
-    for i in range(0, n, every):
+    for i in range(n):
         cells = []
         for s in scores:
             r = res[s][i]
@@ -82,7 +88,10 @@ def main(argv=None) -> int:
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--m-max", type=int, default=20)
     ap.add_argument("--scores", default=",".join(SCORES))
-    ap.add_argument("--every", type=int, default=1, help="print every k-th m")
+    ap.add_argument("--every", type=int, default=1, help="every k-th m only")
+    ap.add_argument("--recompute", type=int, default=0,
+                    help="recompute the reduced order every k removals (Alg. 2's optional line)")
+    ap.add_argument("--tries", type=int, default=4, help="runs of the anytime order heuristic")
     ap.add_argument("--json", help="also write the rows to this file")
     a = ap.parse_args(argv)
     import paper_2004_10892_amd as qbe
@@ -90,10 +99,11 @@ def main(argv=None) -> int:
 
     mod = circuit_model(random_grid_circuit(a.rows, a.cols, a.depth, a.seed))
     qm = qbe.Model.from_circuitgen(mod)
-    res = study(qm, [s for s in a.scores.split(",") if s], a.m_max)
+    res = study(qm, [s for s in a.scores.split(",") if s], a.m_max, a.every, a.recompute, a.tries, a.seed)
     print(f"{a.rows}x{a.cols} depth {a.depth} seed {a.seed}: {mod.n_vars} variables, "
-          f"{len(mod.tensors)} tensors")
-    print(table(res, a.every))
+          f"{len(mod.tensors)} tensors" + (f"; order recomputed every {a.recompute} removals "
+                                           f"({a.tries} tries)" if a.recompute else ""))
+    print(table(res))
     for s, rows in res.items():
         print(f"{s}: time to choose {a.m_max} variables {rows[-1]['pick_ms']:.1f} ms")
     if a.json:

@@ -235,3 +235,29 @@ def test_score_study_rows_follow_the_planner():
             assert r["peak_bytes_per_slice"] == c["peak_bytes_per_slice"]
         assert rows[-1]["mu"][:3] == rows[3]["mu"]
     assert "| m |" in S.table(res)
+
+
+def test_order_recomputation_bit_exact():
+    """Alg. 5, the anytime order heuristic and Alg. 2 with recomputation
+    through the C ABI against the oracle."""
+    for (r, c, d, s, m, k) in [(4, 4, 10, 0, 4, 1), (4, 5, 12, 1, 5, 2), (5, 5, 12, 2, 6, 3)]:
+        mod = circuit_model(random_grid_circuit(r, c, d, s))
+        adj = P.simple_graph(mod.n_vars, [v for v, _ in mod.tensors])
+        order = P.min_fill_order(adj)
+        qm = qbe.Model.from_circuitgen(mod)
+        bags, parent = P.clique_tree(adj, order)
+        assert qbe.qbe_order_from_td(mod.n_vars, [sorted(b) for b in bags], parent) == P.recover_order(bags, parent)
+        want = P.anytime_order(adj, 5, 99)
+        assert qbe.qbe_order_anytime(qm, (), 5, 99) == (want, P.treewidth_from_order(adj, want))
+        mu, _, pi, tau = P.greedy_treewidth_deletion_recompute(adj, order, m, k, 3, 7)
+        assert qbe.qbe_slice(qm, order, m, recompute_every=k, tries=3, seed=7) == (mu, pi, tau)
+
+
+def test_order_from_td_rejects_bad_decompositions():
+    with pytest.raises(qbe.QbeError):
+        qbe.qbe_order_from_td(3, [[0, 1], [1, 2]], [1, 0])  # cycle
+    with pytest.raises(qbe.QbeError):
+        qbe.qbe_order_from_td(3, [[0, 1], [1, 2], [0, 2]], [1, -1, 1])  # 0 in two subtrees
+    with pytest.raises(qbe.QbeError):
+        qbe.qbe_order_from_td(3, [[0, 5]], [-1])  # id out of range
+    assert qbe.qbe_order_from_td(3, [[0, 1], [1, 2]], [1, -1]) == [0, 1, 2]

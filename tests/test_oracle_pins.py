@@ -298,3 +298,52 @@ def test_betweenness_closed_forms_and_brute_force():
         pos = {u: i for i, u in enumerate(order)}
         want = max(adj, key=lambda u: (round(bc[u], 9), -pos[u]))
         assert P.betweenness_pick(adj, order) == want
+
+
+def test_alg5_recovers_orders_from_tree_decompositions():
+    """App. B, Alg. 5: on Fig. 6's chain of bags {ijk}-{jkl}-{klm}-{lmn} the
+    leaf-first order has width 2; on random graphs the order recovered from
+    the clique tree of an order lists every vertex once and is no wider than
+    the decomposition (largest bag minus one)."""
+    i, j, k, l, m, n = range(6)
+    bags = [frozenset({i, j, k}), frozenset({j, k, l}), frozenset({k, l, m}), frozenset({l, m, n})]
+    parent = [1, 2, 3, -1]  # rooted at {lmn}
+    order = P.recover_order(bags, parent)
+    assert order == [i, j, k, l, m, n]
+    adj = {v: set() for v in range(6)}
+    for b in bags:
+        for a in b:
+            adj[a] |= set(b) - {a}
+    assert P.treewidth_from_order(adj, order) == 2
+    rng = np.random.default_rng(11)
+    for _ in range(30):
+        nv = int(rng.integers(4, 12))
+        adj = {v: set() for v in range(nv)}
+        for a in range(nv):
+            for b in range(a + 1, nv):
+                if rng.random() < 0.3:
+                    adj[a].add(b)
+                    adj[b].add(a)
+        o = [int(v) for v in rng.permutation(nv)]
+        bags, parent = P.clique_tree(adj, o)
+        rec = P.recover_order(bags, parent)
+        assert sorted(rec) == list(range(nv))
+        assert P.treewidth_from_order(adj, rec) <= P.td_width(bags)
+
+
+def test_anytime_order_and_recomputation_reduce_to_the_plain_forms():
+    """One try of the anytime heuristic is min-fill, more tries are never
+    wider; Alg. 2 without recomputation is the plain greedy deletion, and
+    recomputation never widens the final reduced order on these circuits."""
+    from circuitgen import circuit_model, random_grid_circuit
+    for seed in range(3):
+        mod = circuit_model(random_grid_circuit(4, 4, 10, seed))
+        adj = P.simple_graph(mod.n_vars, [v for v, _ in mod.tensors])
+        o = P.min_fill_order(adj)
+        assert P.anytime_order(adj, 1, 5) == o
+        assert P.treewidth_from_order(adj, P.anytime_order(adj, 6, 5)) <= P.treewidth_from_order(adj, o)
+        plain = P.greedy_treewidth_deletion(adj, o, 3)
+        same = P.greedy_treewidth_deletion_recompute(adj, o, 3, 0, 4, 1)
+        assert plain[0] == same[0] and plain[2] == same[2] and plain[3] == same[3]
+        rec = P.greedy_treewidth_deletion_recompute(adj, o, 3, 1, 4, 1)
+        assert rec[3] <= plain[3]
