@@ -68,10 +68,11 @@ enum {
 enum {
   QBE_PREC_FP32 = 0,    /* complex64 products, FP32 accumulation            */
   QBE_PREC_BF16X3 = 1,  /* split-BF16 products (hi*hi + hi*lo + lo*hi) with
-                           FP32 accumulation in the MFMA outer-product
-                           buckets of the per-step form; other buckets stay
-                           FP32.  Not available in the fused form.  About
-                           2^-16 relative error per product.                 */
+                           FP32 accumulation in the MFMA launches of the
+                           per-step form (outer-product buckets and merged
+                           two-group products); other launches stay FP32.
+                           Not available in the fused form.  About 2^-16
+                           relative error per product.                       */
   QBE_PREC_BF16X6 = 2   /* as BF16X3 with a three-part split x = h + m + l
                            and the six products h*h, h*m, m*h, h*l, l*h,
                            m*m: about FP32 accuracy from bfloat16 MFMAs.     */

@@ -611,10 +611,45 @@ struct MmkLaunch {
   uint32_t mk[kMaxOps];     // masks over X
   int32_t n_ops;
   uint32_t side_b;          // bit i: factor i belongs to B' (else to A')
+  int32_t prec;             // QBE_PREC_*: FP32 or split-BF16 MFMAs
   uint32_t mtile, ntile, rest;
   int32_t r;
   int64_t s0, G, n_tiles;
 };
+
+// acc + a * b over one lane's real-K entry in split bfloat16: slots
+// (h*h, h*m, m*h, 0) for bf16x3 (x = h + m), or (h*h, h*m, m*h, h*l) then
+// (l*h, m*m, 0, 0) in a second call for bf16x6 (x = h + m + l).
+__device__ __forceinline__ floatx4 mfma_split(float a, float b, floatx4 acc, int prec) {
+  uint32_t ha, ma, la, hb, mb, lb;
+  split_bf16(a, ha, ma, la);
+  split_bf16(b, hb, mb, lb);
+  shortx4 pa, pb;
+  pa[0] = (short)ha;
+  pa[1] = (short)ha;
+  pa[2] = (short)ma;
+  pb[0] = (short)hb;
+  pb[1] = (short)mb;
+  pb[2] = (short)hb;
+  if (prec == QBE_PREC_BF16X3) {
+    pa[3] = 0;
+    pb[3] = 0;
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(pa, pb, acc, 0, 0, 0);
+  }
+  pa[3] = (short)ha;
+  pb[3] = (short)lb;
+  acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(pa, pb, acc, 0, 0, 0);
+  shortx4 qa, qb;
+  qa[0] = (short)la;
+  qa[1] = (short)ma;
+  qa[2] = 0;
+  qa[3] = 0;
+  qb[0] = (short)hb;
+  qb[1] = (short)mb;
+  qb[2] = 0;
+  qb[3] = 0;
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(qa, qb, acc, 0, 0, 0);
+}
 
 // Tiles are decoded as in step_kernel: lane l of a wavefront works out the
 // slice, the tile's result bits and the operands' offsets for the wave's
@@ -685,8 +720,15 @@ __global__ __launch_bounds__(kBlock) void mmk_kernel(MmkLaunch a) {
         const bool im_slot = c >= KQ;
         const float a1 = im_slot ? -av[q].y : av[q].x, b1 = im_slot ? bv[q].y : bv[q].x;
         const float a2 = im_slot ? av[q].y : av[q].x, b2 = im_slot ? bv[q].x : bv[q].y;
-        cre = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, cre, 0, 0, 0);
-        cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, b2, cim, 0, 0, 0);
+        if (a.prec == QBE_PREC_FP32) {
+          cre = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, cre, 0, 0, 0);
+          cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, b2, cim, 0, 0, 0);
+        } else {
+          // split-BF16: the lane's entry of the K = 4 call above becomes its
+          // four bfloat16 slots, the part products along the slot index
+          cre = mfma_split(a1, b1, cre, a.prec);
+          cim = mfma_split(a2, b2, cim, a.prec);
+        }
       }
       const uint64_t ob = lane64(obl, k);
 #pragma unroll
@@ -932,6 +974,7 @@ static int launch_step(const Plan& p, const StepProg& sp, float2* arena, int64_t
     m.out = a.out;
     m.n_ops = sp.n_ops;
     m.side_b = sp.mmk_side;
+    m.prec = p.precision;
     const uint32_t xmask = (1u << r) - 1u;
     uint32_t xa = 0, xb = 0;
     for (int i = 0; i < sp.n_ops; ++i) {

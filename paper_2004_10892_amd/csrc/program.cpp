@@ -510,7 +510,7 @@ void compile_plan(Plan& p) {
       for (int t = 0; t < n_sum; ++t)
         if (t != bp && t != bq) sp.sum_bit[nb++] = t;
     }
-    if (n_sum > 1 && rb >= 8 && p.precision == QBE_PREC_FP32 && ops.size() >= 2) {
+    if (n_sum > 1 && rb >= 8 && ops.size() >= 2) {
       // merged launch as a batched complex product on MFMA: the operands
       // split into groups A and B, each with at least four result bits the
       // other group lacks (the 16 x 16 tile bits); every other result bit is

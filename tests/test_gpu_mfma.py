@@ -100,3 +100,28 @@ def test_precision_forms_on_7x7_d24_slices(env):
     assert errs["fp32"][0] <= 1e-5
     assert errs["bf16x3"][0] <= 7 * 4 * SPLIT_EPS
     assert errs["bf16x6"][0] <= 1e-5
+
+
+def test_merged_mfma_precision_forms_on_7x7_d24_slices(env):
+    """With merged chains the two-group products run on MFMA in every
+    precision (K = 2^(j+1) per tile); slices 0..15 of the 7x7 depth-24
+    workload against the complex128 oracle, bounds as above."""
+    qbe, ctx = env
+    from circuitgen import circuit_model, random_grid_circuit
+    gold = json.load(open(os.path.join(GOLD, "amplitudes.json")))["grid7x7_d24_m10"]
+    want = np.array([complex(*v) for v in gold["slices"][:16]])
+    rms = float(np.sqrt(np.mean(np.abs(want) ** 2)))
+    qm = qbe.Model.from_circuitgen(circuit_model(random_grid_circuit(7, 7, 24, gold["seed"])))
+    _, mu, pi, _ = qbe.plan_circuit(qm, m=10)
+    errs = {}
+    for prec in ("fp32", "bf16x3", "bf16x6"):
+        plan = qbe.Plan(qm, pi, mu, ctx=ctx, exec="per_step", precision=prec)
+        st = plan.stats()
+        assert st["n_merged_steps"] >= 1 and st["n_mfma_steps"] >= 6
+        print(f"case merged 7x7 slices 0-15 {prec}", flush=True)
+        _, per = qbe.qbe_contract_slices(ctx, plan, 0, 16, plan.workspace(all_slices=False))
+        errs[prec] = float(np.max(np.abs(per - want) / np.maximum(np.abs(want), rms)))
+        print(f"  {prec}: {st['n_mfma_steps']} MFMA launches, max per-slice rel err {errs[prec]:.3e}", flush=True)
+    assert errs["fp32"] <= 1e-5
+    assert errs["bf16x3"] <= 7 * 4 * SPLIT_EPS
+    assert errs["bf16x6"] <= 1e-5
