@@ -772,6 +772,59 @@ __global__ void finalize_kernel(FinalizeArgs a) {
   }
 }
 
+// FP64 slice product of the rank-0 results and the slice sum of every
+// per-step instance of a batch, one workgroup per instance: lane t takes
+// slices t, t + 256, ... in sequence (computing each as finalize_kernel
+// does and adding it), then a binary tree over the 256 partials -- the
+// order of reduce_kernel.
+struct WideFinal {
+  int64_t arena;            // complex64 offset of the instance's arena in the workspace
+  const float2* prep;       // its prepared inputs
+  const int64_t* arena_off; // its scalar tables (device)
+  const int64_t* in_base;
+  const uint32_t* in_smask;
+  int32_t n_arena, n_in, n_free, plan;  // plan: index of its amplitude
+  int64_t G;                // its slices (all run at once)
+};
+
+__global__ __launch_bounds__(256) void wide_final_kernel(const WideFinal* __restrict__ w, const float2* ws,
+                                                         double2* __restrict__ amps) {
+  __shared__ double sre[256], sim[256];
+  const WideFinal& d = w[blockIdx.x];
+  const float2* arena = ws + d.arena;
+  double sr = 0.0, si = 0.0;
+  for (int64_t g = threadIdx.x; g < d.G; g += 256) {
+    double re = ldexp(1.0, d.n_free), im = 0.0;
+    for (int j = 0; j < d.n_arena; ++j) {
+      const float2 v = arena[d.arena_off[j] * d.G + g];
+      const double vr = v.x, vi = v.y;
+      const double nr = re * vr - im * vi;
+      im = re * vi + im * vr;
+      re = nr;
+    }
+    for (int j = 0; j < d.n_in; ++j) {
+      const float2 v = d.prep[d.in_base[j] + (int64_t)pext32((uint32_t)g, d.in_smask[j])];
+      const double vr = v.x, vi = v.y;
+      const double nr = re * vr - im * vi;
+      im = re * vi + im * vr;
+      re = nr;
+    }
+    sr += re;
+    si += im;
+  }
+  sre[threadIdx.x] = sr;
+  sim[threadIdx.x] = si;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) {
+      sre[threadIdx.x] += sre[threadIdx.x + k];
+      sim[threadIdx.x] += sim[threadIdx.x + k];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) amps[d.plan] = make_double2(sre[0], sim[0]);
+}
+
 // Sum of n FP64 complex values in a fixed order: lane t adds entries
 // t, t + 256, ... in sequence, then a binary tree over the 256 partials.
 __global__ __launch_bounds__(256) void reduce_kernel(const double2* __restrict__ v,
@@ -1293,6 +1346,10 @@ int launch_reduce(const double2* v, const int64_t* ranges, int64_t n_single, dou
 // single launches of every instance go first, then one launch of all their
 // grouped small steps of that level; then each instance's finalize and sum.
 
+// Largest log2(slices x result entries) of a step that the batch runs in
+// its level's group launch although the plan launches it alone.
+constexpr int kWideGroupMaxLog2 = 22;
+
 int step_batch_build(Batch& b) {
   b.wide_off.clear();
   b.wide_order.clear();
@@ -1313,9 +1370,27 @@ int step_batch_build(Batch& b) {
     for (size_t q = 0; q < b.wide.size(); ++q) {
       const Plan& p = *b.plans[b.wide[q]];
       const int64_t arena = (int64_t)((b.wide_off[q] + ws_head(p.n_slices)) / sizeof(float2));
+      auto add = [&](const GroupStep& gs) {
+        WideGroupStep d{};
+        d.s = gs;
+        d.step_in = p.d_step_in;
+        d.arena = arena;
+        d.G = p.n_slices;
+        d.sb = p.group_sb;
+        d.tiles = (int32_t)((((int64_t)p.group_sb << d.s.r) + kBlock - 1) / kBlock);
+        grp.push_back(d);
+      };
       for (const LaunchItem& li : p.launch_order) {
         if (li.group < 0) {
-          if (p.step_level[li.step] == L) b.wide_order.push_back(WideItem{(int32_t)q, li.step, -1});
+          if (p.step_level[li.step] != L) continue;
+          // a step the plan launches alone: grouped here when it is small
+          // enough for the generic kernel across instances
+          const StepProg& sp = p.steps[li.step];
+          const int r = sp.out_rank >= 0 ? sp.out_rank : -sp.out_rank;
+          if (groupable(sp) && (p.n_slices << r) <= (int64_t(1) << kWideGroupMaxLog2))
+            add(group_step_of(sp, li.step));
+          else
+            b.wide_order.push_back(WideItem{(int32_t)q, li.step, -1});
           continue;
         }
         const int f = p.group_first[li.group], e = p.group_first[li.group + 1];
@@ -1343,6 +1418,26 @@ int step_batch_build(Batch& b) {
     }
     b.wide_first.push_back((int32_t)b.wide_steps.size());
     b.wide_order.push_back(WideItem{-1, -1, g});
+  }
+  if (!b.wide.empty()) {
+    std::vector<WideFinal> fin;
+    for (size_t q = 0; q < b.wide.size(); ++q) {
+      const Plan& p = *b.plans[b.wide[q]];
+      WideFinal f{};
+      f.arena = (int64_t)((b.wide_off[q] + ws_head(p.n_slices)) / sizeof(float2));
+      f.prep = (const float2*)p.d_step_in;
+      f.arena_off = (const int64_t*)p.d_scalar_tab;
+      f.in_base = f.arena_off + p.scalar_arena.size();
+      f.in_smask = (const uint32_t*)(f.in_base + p.scalar_inputs_base.size());
+      f.n_arena = (int32_t)p.scalar_arena.size();
+      f.n_in = (int32_t)p.scalar_inputs_base.size();
+      f.n_free = (int32_t)p.sched.free_vars.size();
+      f.plan = b.wide[q];
+      f.G = p.n_slices;
+      fin.push_back(f);
+    }
+    int rc = upload(&b.d_wide_final, fin.data(), fin.size() * sizeof(WideFinal));
+    if (rc) return rc;
   }
   if (!b.wide_steps.empty()) {
     const size_t sb = b.wide_steps.size() * sizeof(WideGroupStep);
@@ -1396,13 +1491,10 @@ int dev_batch_contract(const Batch& b, void* stream, void* ws, size_t ws_bytes, 
     }
     if (rc) return rc;
   }
-  for (size_t q = 0; q < b.wide.size(); ++q) {
-    const Plan& p = *b.plans[b.wide[q]];
-    char* pw = wide_ws + b.wide_off[q];
-    double2* per_slice = (double2*)(pw + 256);
-    int rc = finalize_group(p, (float2*)(pw + ws_head(p.n_slices)), per_slice, p.n_slices, 0, st);
-    if (!rc) rc = launch_reduce(per_slice, nullptr, p.n_slices, (double2*)d_amps + b.wide[q], 1, st);
-    if (rc) return rc;
+  if (!b.wide.empty()) {
+    wide_final_kernel<<<(unsigned)b.wide.size(), 256, 0, st>>>((const WideFinal*)b.d_wide_final,
+                                                              (const float2*)wide_ws, (double2*)d_amps);
+    QBE_HIP(hipGetLastError());
   }
   return QBE_OK;
 }

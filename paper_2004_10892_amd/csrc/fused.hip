@@ -565,7 +565,7 @@ int dev_batch_build(Batch& b) {
 }
 
 void dev_batch_free(Batch& b) {
-  void** ptrs[] = {&b.d_items, &b.d_ranges, &b.d_state, &b.d_wide};
+  void** ptrs[] = {&b.d_items, &b.d_ranges, &b.d_state, &b.d_wide, &b.d_wide_final};
   for (void** q : ptrs) {
     if (*q) (void)hipFree(*q);
     *q = nullptr;

@@ -253,6 +253,29 @@ std::vector<StepNode> merge_chains(const Schedule& s, bool merge) {
   return out;
 }
 
+}  // namespace
+
+bool groupable(const StepProg& sp) { return sp.n_sum <= 1 && !sp.mmk && sp.mm_a < 0; }
+
+GroupStep group_step_of(const StepProg& sp, int k) {
+  GroupStep d{};
+  d.out = sp.out_base;
+  d.n_ops = sp.n_ops;
+  d.r = sp.out_rank >= 0 ? sp.out_rank : -sp.out_rank;
+  d.sum_u = sp.out_rank >= 0 ? 1 : 0;
+  d.step = k;
+  for (int i = 0; i < sp.n_ops; ++i) {
+    d.base[i] = sp.ops[i].base;
+    d.mask[i] = sp.ops[i].mask;
+    d.smask[i] = sp.ops[i].is_input ? sp.ops[i].smask : 0u;
+    d.rank[i] = sp.ops[i].rank;
+    if (sp.ops[i].is_input) d.is_input |= 1u << i;
+  }
+  return d;
+}
+
+namespace {
+
 // Execution order of the per-step launches.  A launch's level is one more
 // than that of every earlier launch it must follow: the producers of its
 // operands, and -- because the arena reuses space -- earlier launches that
@@ -304,9 +327,7 @@ void build_launch_order(Plan& p) {
     n_lv = std::max(n_lv, l + 1);
   }
   p.step_level = level;
-  auto small = [&](const StepProg& sp) {
-    return sp.n_sum <= 1 && !sp.mmk && sp.mm_a < 0 && rank_of(sp) <= kGroupMaxRank;
-  };
+  auto small = [&](const StepProg& sp) { return groupable(sp) && rank_of(sp) <= kGroupMaxRank; };
   for (int l = 0; l < n_lv; ++l) {
     std::vector<int> grp;
     for (int k = 0; k < n; ++k) {
@@ -322,20 +343,7 @@ void build_launch_order(Plan& p) {
     uint32_t tiles = 0;
     p.group_prefix.push_back(0);
     for (int k : grp) {
-      const StepProg& sp = p.steps[k];
-      GroupStep d{};
-      d.out = sp.out_base;
-      d.n_ops = sp.n_ops;
-      d.r = rank_of(sp);
-      d.sum_u = sp.out_rank >= 0 ? 1 : 0;
-      d.step = k;
-      for (int i = 0; i < sp.n_ops; ++i) {
-        d.base[i] = sp.ops[i].base;
-        d.mask[i] = sp.ops[i].mask;
-        d.smask[i] = sp.ops[i].is_input ? sp.ops[i].smask : 0u;
-        d.rank[i] = sp.ops[i].rank;
-        if (sp.ops[i].is_input) d.is_input |= 1u << i;
-      }
+      const GroupStep d = group_step_of(p.steps[k], k);
       p.group_steps.push_back(d);
       tiles += (uint32_t)(((sb << d.r) + 255) / 256);
       p.group_prefix.push_back(tiles);

@@ -80,6 +80,10 @@ struct GroupStep {
   int32_t n_ops, r, sum_u;  // sum_u 0: product without a summed bit
   int32_t step;             // index into the plan's steps (host checks)
 };
+// A step the group kernels can run (one summed variable at most, no MFMA
+// form), and its descriptor.
+bool groupable(const StepProg& sp);
+GroupStep group_step_of(const StepProg& sp, int k);
 // One entry of the per-step execution order: steps[step] alone (group < 0),
 // or group `group` of small steps in one launch.
 struct LaunchItem {
@@ -163,6 +167,7 @@ struct Batch {
   std::vector<int32_t> wide_first;  // group g: wide_steps [first[g], first[g + 1])
   std::vector<uint64_t> wide_prefix;  // group g: count + 1 unit offsets from first[g] + g
   void* d_wide = nullptr;           // wide_steps, then wide_prefix
+  void* d_wide_final = nullptr;     // per wide plan: its slice product and sum
   std::vector<int64_t> item_begin;  // per plan, into the item table (+ end)
   int64_t n_items = 0;
   int lds_bytes = 0;
