@@ -256,3 +256,23 @@ def batch_instances(count: int = 512, first_seed: int = 1000):
         m = rng.next() % 7
         out.append((int(r), int(c), int(d), int(m), seed))
     return out
+
+
+def random_general_network(seed: int, n_vars: int = 7, n_tensors: int = 7, max_rank: int = 3,
+                           max_dim: int = 5):
+    """A random network over variables of dimensions 1..max_dim (numpy
+    default_rng(seed)): returns (dims, tensors), tensors as (vars, data)
+    with data shaped by the variables' dimensions; every variable occurs in
+    some tensor."""
+    rng = np.random.default_rng(seed)
+    dims = [int(rng.integers(1, max_dim + 1)) for _ in range(n_vars)]
+    tensors = []
+    for _ in range(n_tensors):
+        r = int(rng.integers(1, max_rank + 1))
+        vs = tuple(int(v) for v in rng.choice(n_vars, size=r, replace=False))
+        shape = [dims[v] for v in vs]
+        tensors.append((vs, rng.standard_normal(shape) + 1j * rng.standard_normal(shape)))
+    for v in range(n_vars):
+        if not any(v in vs for vs, _ in tensors):
+            tensors.append(((v,), rng.standard_normal(dims[v]) + 1j * rng.standard_normal(dims[v])))
+    return dims, tensors

@@ -149,6 +149,25 @@ int qbe_set_stream(qbe_ctx* ctx, void* hip_stream);
  * Every variable must occur in at least one tensor.  All arrays are copied. */
 int qbe_model_create(int32_t n_vars, int32_t n_tensors, const int32_t* rank, const int32_t* vars,
                      const double* data, qbe_model** out);
+/* A network whose variables have any dimensions L_v = dims[v] >= 1 (Sec.
+ * 2.1 allows any L; the contraction is the same sum over all assignments).
+ * It is stored as the equivalent binary model: variable v becomes b_v =
+ * ceil(log2 L_v) binary variables (its index bits, most significant
+ * first; none for L_v = 1), numbered consecutively in v order, and every
+ * tensor is re-laid out over its variables' bits with entries 0 at index
+ * values >= L_v.  Every later call (orders, slicing, plans, contraction)
+ * works on that binary model: slicing may fix single bits of a variable.
+ * Tensor t over (v_0 .. v_{r-1}) holds prod L_{v_j} complex entries,
+ * row-major with v_0 the most significant; data holds 2 * sum of those
+ * doubles.  Limits: dims[v] in [1, 2^16], sum of b over a tensor's
+ * variables <= 30.  Every variable must occur in a tensor.
+ * QBE_ERR_INVALID_ARG otherwise. */
+int qbe_model_create_dims(int32_t n_vars, const int32_t* dims, int32_t n_tensors, const int32_t* rank,
+                          const int32_t* vars, const double* data, qbe_model** out);
+/* The binary variables of variable v of a qbe_model_create_dims model:
+ * *first_out, *count_out (count 0 for dimension 1).  For a binary model
+ * every variable maps to itself (count 1). */
+int qbe_model_var_bits(const qbe_model* model, int32_t v, int32_t* first_out, int32_t* count_out);
 int qbe_model_destroy(qbe_model* model);
 /* Replaces the tensor entries (same layout as qbe_model_create). */
 int qbe_model_set_data(qbe_model* model, const double* data);

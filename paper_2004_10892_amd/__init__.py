@@ -86,6 +86,8 @@ _SIGS = {
     "qbe_plan_create": (C.c_int, [_vp, _vp, _i32p, C.c_int32, _i32p, C.c_int32, C.POINTER(PlanOpts), C.POINTER(_vp)]),
     "qbe_plan_destroy": (C.c_int, [_vp]),
     "qbe_plan_update_data": (C.c_int, [_vp, _vp]),
+    "qbe_model_create_dims": (C.c_int, [C.c_int32, _i32p, C.c_int32, _i32p, _i32p, _f64p, C.POINTER(_vp)]),
+    "qbe_model_var_bits": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "qbe_slice_recompute": (C.c_int, [_vp, _i32p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                       C.c_int32, C.c_uint64, _i32p, C.POINTER(C.c_int32), _i32p,
                                       C.POINTER(C.c_int32)]),
@@ -192,6 +194,33 @@ class Model:
     @classmethod
     def from_circuitgen(cls, m) -> "Model":
         return cls(m.n_vars, m.tensors)
+
+    @classmethod
+    def from_dims(cls, dims: Sequence[int], tensors: Sequence[Tuple[Sequence[int], np.ndarray]]) -> "Model":
+        """A network over variables of any dimensions (qbe_model_create_dims):
+        tensor data shaped by its variables' dimensions, row-major.  The
+        model's variables are the binary expansion; var_bits(v) maps back."""
+        d = _i32(dims)
+        tv = [tuple(int(v) for v in vs) for vs, _ in tensors]
+        rank = _i32([len(v) for v in tv])
+        flat = _i32([v for vs in tv for v in vs])
+        data = cls._data(tensors)
+        h = _vp()
+        _check(_lib.qbe_model_create_dims(len(d), _p32(d), len(rank), _p32(rank), _p32(flat),
+                                          data.ctypes.data_as(_f64p), C.byref(h)), "qbe_model_create_dims")
+        m = cls.__new__(cls)
+        m.handle = h
+        m.dims = [int(x) for x in dims]
+        m.tensor_vars = None  # binary tensors live in the library
+        first, count = m.var_bits(len(d) - 1) if len(d) else (0, 0)
+        m.n_vars = first + count
+        return m
+
+    def var_bits(self, v: int) -> Tuple[int, int]:
+        """(first binary variable, count) of variable v."""
+        f, c = C.c_int32(), C.c_int32()
+        _check(_lib.qbe_model_var_bits(self.handle, v, C.byref(f), C.byref(c)), "qbe_model_var_bits")
+        return f.value, c.value
 
     def set_data(self, tensors):
         data = self._data(tensors)

@@ -18,6 +18,8 @@ struct qbe_ctx {
 
 struct qbe_model {
   qbe::Model m;
+  // qbe_model_create_dims: the binary variables of each original variable
+  std::vector<int32_t> bit_first, bit_count;
 };
 
 struct qbe_plan {
@@ -174,6 +176,92 @@ int qbe_model_create(int32_t n_vars, int32_t n_tensors, const int32_t* rank, con
     }
   fill_data(m, data);
   *out = md;
+  return QBE_OK;
+  QBE_GUARD_END
+}
+
+int qbe_model_create_dims(int32_t n_vars, const int32_t* dims, int32_t n_tensors, const int32_t* rank,
+                          const int32_t* vars, const double* data, qbe_model** out) {
+  QBE_GUARD_BEGIN
+  QBE_REQUIRE(out, "out is NULL");
+  *out = nullptr;
+  QBE_REQUIRE(n_vars >= 0 && n_tensors >= 0, "negative sizes");
+  QBE_REQUIRE(n_vars == 0 || dims, "dims is NULL");
+  QBE_REQUIRE(n_tensors == 0 || (rank && data), "rank or data is NULL");
+  // binary variables of each variable: its index bits, most significant first
+  std::vector<int32_t> first(n_vars), nb(n_vars);
+  int32_t nbin = 0;
+  for (int v = 0; v < n_vars; ++v) {
+    QBE_REQUIRE(dims[v] >= 1 && dims[v] <= (1 << 16), "dimension outside [1, 2^16]");
+    int b = 0;
+    while ((1 << b) < dims[v]) ++b;
+    first[v] = nbin;
+    nb[v] = b;
+    nbin += b;
+  }
+  std::vector<int32_t> brank(n_tensors), bvars;
+  std::vector<double> bdata;
+  int64_t vp = 0, dp = 0;
+  for (int t = 0; t < n_tensors; ++t) {
+    QBE_REQUIRE(rank[t] >= 0 && rank[t] <= 64 && (rank[t] == 0 || vars), "bad tensor rank or vars");
+    int bits = 0;
+    int64_t size = 1;
+    std::vector<int> tv(vars + vp, vars + vp + rank[t]);
+    for (int v : tv) {
+      QBE_REQUIRE(v >= 0 && v < n_vars, "variable id out of range");
+      bits += nb[v];
+      QBE_REQUIRE(bits <= 30, "a tensor has more than 30 binary variables");
+      size *= dims[v];
+      QBE_REQUIRE(size <= (int64_t(1) << 30), "tensor too large");
+    }
+    brank[t] = bits;
+    for (int v : tv)
+      for (int k = 0; k < nb[v]; ++k) bvars.push_back(first[v] + k);
+    // binary index y (tensor's bits, first variable most significant) ->
+    // the variables' values; a value >= L_v is padding (entry 0)
+    const int64_t bsize = int64_t(1) << bits;
+    const size_t o = bdata.size();
+    bdata.resize(o + 2 * (size_t)bsize, 0.0);
+    for (int64_t y = 0; y < bsize; ++y) {
+      int64_t flat = 0;
+      int shift = bits;
+      bool pad = false;
+      for (int v : tv) {
+        shift -= nb[v];
+        const int64_t val = (y >> shift) & ((int64_t(1) << nb[v]) - 1);
+        if (val >= dims[v]) pad = true;
+        flat = flat * dims[v] + val;
+      }
+      if (pad) continue;
+      bdata[o + 2 * y] = data[2 * (dp + flat)];
+      bdata[o + 2 * y + 1] = data[2 * (dp + flat) + 1];
+    }
+    vp += rank[t];
+    dp += size;
+  }
+  qbe_model* md = nullptr;
+  int rc = qbe_model_create(nbin, n_tensors, brank.data(), bvars.empty() ? nullptr : bvars.data(),
+                            bdata.empty() ? nullptr : bdata.data(), &md);
+  if (rc) return rc;
+  md->bit_first = first;
+  md->bit_count = nb;
+  *out = md;
+  return QBE_OK;
+  QBE_GUARD_END
+}
+
+int qbe_model_var_bits(const qbe_model* model, int32_t v, int32_t* first_out, int32_t* count_out) {
+  QBE_GUARD_BEGIN
+  QBE_REQUIRE(model && first_out && count_out, "NULL argument");
+  if (model->bit_first.empty()) {
+    QBE_REQUIRE(v >= 0 && v < model->m.n_vars, "variable id out of range");
+    *first_out = v;
+    *count_out = 1;
+    return QBE_OK;
+  }
+  QBE_REQUIRE(v >= 0 && v < (int32_t)model->bit_first.size(), "variable id out of range");
+  *first_out = model->bit_first[v];
+  *count_out = model->bit_count[v];
   return QBE_OK;
   QBE_GUARD_END
 }

@@ -261,3 +261,33 @@ def test_order_from_td_rejects_bad_decompositions():
     with pytest.raises(qbe.QbeError):
         qbe.qbe_order_from_td(3, [[0, 5]], [-1])  # id out of range
     assert qbe.qbe_order_from_td(3, [[0, 1], [1, 2]], [1, -1]) == [0, 1, 2]
+
+
+def test_general_dimension_models_expand_to_binary():
+    """qbe_model_create_dims: variable v of dimension L becomes ceil(log2 L)
+    consecutive binary variables; the expanded model has the oracle's
+    expansion's structure (its min-fill order and clique tree are the
+    oracle's on that expansion) and its plans pass the host check."""
+    from circuitgen import random_general_network
+    from oracle import general as Gn
+    for seed in range(6):
+        dims, tensors = random_general_network(seed)
+        qm = qbe.Model.from_dims(dims, tensors)
+        nb, btens, first, count = Gn.binary_expansion(dims, tensors)
+        assert qm.n_vars == nb
+        assert [qm.var_bits(v) for v in range(len(dims))] == list(zip(first, count))
+        adj = P.simple_graph(nb, [vs for vs, _ in btens])
+        order = qbe.qbe_order_min_fill(qm)
+        assert order == P.min_fill_order(adj)
+        m = min(2, nb)
+        mu, pi, tau = qbe.qbe_slice(qm, order, m)
+        for form in ("per_step", "auto"):
+            plan = qbe.Plan(qm, pi, mu, exec=form)
+            plan.check()
+            plan.close()
+    with pytest.raises(qbe.QbeError):
+        qbe.Model.from_dims([3, 0], [((0, 1), np.ones((3, 0)))])  # dimension 0
+    with pytest.raises(qbe.QbeError):
+        qbe.Model.from_dims([2 ** 16, 2 ** 16, 2 ** 16], [((0, 1, 2), np.ones(1))])  # 48 bits
+    b = qbe.Model(3, [((0, 1), np.ones((2, 2))), ((2,), np.ones(2))])
+    assert b.var_bits(2) == (2, 1)

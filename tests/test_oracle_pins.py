@@ -10,7 +10,7 @@ import os
 import numpy as np
 import pytest
 
-from circuitgen import toy_network
+from circuitgen import random_general_network, toy_network
 from oracle import contract as C
 from oracle import cost as K
 from oracle import planner as P
@@ -347,3 +347,24 @@ def test_anytime_order_and_recomputation_reduce_to_the_plain_forms():
         assert plain[0] == same[0] and plain[2] == same[2] and plain[3] == same[3]
         rec = P.greedy_treewidth_deletion_recompute(adj, o, 3, 1, 4, 1)
         assert rec[3] <= plain[3]
+
+
+def test_general_dimension_contraction_pins():
+    """Sec. 2.1 for general L: an all-ones network sums to the product of
+    the dimensions; with L = 2 the definition is the binary brute force; the
+    binary expansion (index bits, padded entries 0) has the same sum."""
+    from oracle import general as Gn
+    dims = [3, 1, 4, 5]
+    tensors = [((0, 1), np.ones((3, 1))), ((2, 3), np.ones((4, 5))), ((0, 3), np.ones((3, 5)))]
+    # each variable is summed over its L values; variables 0 and 3 are shared
+    assert abs(Gn.contract_general(dims, tensors) - 3 * 1 * 4 * 5) < 1e-12
+    n, tens = toy_network(seed=2).n_vars, toy_network(seed=2).tensors
+    assert abs(Gn.contract_general([2] * n, tens) - C.brute_force_sum(n, tens)) < 1e-9 * abs(C.brute_force_sum(n, tens))
+    for seed in range(12):
+        dims, tensors = random_general_network(seed)
+        want = Gn.contract_general(dims, tensors)
+        nb, btens, first, count = Gn.binary_expansion(dims, tensors)
+        assert count == [(L - 1).bit_length() for L in dims]
+        got = C.brute_force_sum(nb, [(vs, d) for vs, d in btens if vs] ) * np.prod(
+            [complex(d) for vs, d in btens if not vs]) if nb else want
+        assert abs(got - want) <= 1e-9 * max(abs(want), 1.0)
