@@ -40,8 +40,6 @@ __global__ void prep_kernel(const double2* __restrict__ raw, const int32_t* __re
 
 // --------------------------------------------------------------- per-step --
 
-constexpr int kMaxSumTerms = 16;  // 2^n_sum for a merged launch (n_sum <= 4)
-
 struct StepLaunch {
   float2* out;
   const float2* src[kMaxOps];
@@ -57,9 +55,11 @@ struct StepLaunch {
   int64_t s0;      // first slice of the group
   int64_t G;       // slices in the group
   int64_t n_tiles;
-  // msum kernels: byte offset of operand i's entry for summed value u above
-  // its entry for u = 0, and the bits of u the operand holds
-  uint32_t uoff[kMaxSumTerms][kMaxOps];
+  // msum kernels: byte offset of operand i's entry for summed value u = 1 <<
+  // b above its entry for u = 0 (0 if it lacks bit b); the offset for any u
+  // is the sum over u's bits (bit extraction is linear over disjoint bits).
+  // And the bits of u the operand holds.
+  uint32_t uw[kMaxOps][4];
   uint32_t uhold[kMaxOps];
 };
 
@@ -192,9 +192,9 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch a) {
 
 // A launch that merges a chain of buckets (r >= kLoBits): the top n_sum
 // bits of X are summed, 2^n_sum >= 4 terms per result entry.  Operand i's
-// entry for summed value u sits uoff[u][i] bytes above its u = 0 entry, the
-// same for every lane and tile, so the term loop adds a table entry to a
-// scalar base.
+// entry for summed value u sits sum_b bit_b(u) uw[i][b] bytes above its
+// u = 0 entry, the same for every lane and tile: the term loop adds scalar
+// offsets, worked out without memory reads, to a scalar base.
 template <int K, int EPT>
 __global__ __launch_bounds__(kBlock) void msum_kernel(StepLaunch a) {
   const int tid = threadIdx.x, lane = tid & 63;
@@ -221,10 +221,12 @@ __global__ __launch_bounds__(kBlock) void msum_kernel(StepLaunch a) {
 #pragma unroll
         for (int i = 0; i < K; ++i) {
           const uint32_t c = a.uhold[i] & 3u;
+          const uint32_t ob = ((u0 & 4) ? a.uw[i][2] : 0u) + ((u0 & 8) ? a.uw[i][3] : 0u);
 #pragma unroll
           for (int du = 0; du < 4; ++du)
             if (((uint32_t)du & ~c) == 0u) {
-              const uint64_t bu = b[i] + a.uoff[u0 + du][i];
+              const uint32_t off = ob + ((du & 1) ? a.uw[i][0] : 0u) + ((du & 2) ? a.uw[i][1] : 0u);
+              const uint64_t bu = b[i] + off;
 #pragma unroll
               for (int e = 0; e < EPT; ++e) v[du][e][i] = ld_sv(bu, ts.lofs[e][i]);
             }
@@ -348,9 +350,13 @@ __global__ __launch_bounds__(kBlock) void msum_small_kernel(StepLaunch a) {
     }
     float2 acc = make_float2(0.f, 0.f);
     for (int u = 0; u < nu; ++u) {
-      float2 p = *(const float2*)(q[0] + a.uoff[u][0]);
+      auto uoff = [&](int i) {
+        return ((u & 1) ? a.uw[i][0] : 0u) + ((u & 2) ? a.uw[i][1] : 0u) + ((u & 4) ? a.uw[i][2] : 0u) +
+               ((u & 8) ? a.uw[i][3] : 0u);
+      };
+      float2 p = *(const float2*)(q[0] + uoff(0));
 #pragma unroll
-      for (int i = 1; i < K; ++i) p = cmul(p, *(const float2*)(q[i] + a.uoff[u][i]));
+      for (int i = 1; i < K; ++i) p = cmul(p, *(const float2*)(q[i] + uoff(i)));
       acc.x += p.x;
       acc.y += p.y;
     }
@@ -1138,14 +1144,13 @@ static int launch_step(const Plan& p, const StepProg& sp, float2* arena, int64_t
       const int xc = __builtin_popcount(a.mask[i] & xmask);
       a.uhold[i] = 0;
       for (int b = 0; b < sp.n_sum; ++b) a.uhold[i] |= ((um >> sp.sum_bit[b]) & 1u) << b;
-      for (int u = 0; u < (1 << sp.n_sum); ++u) {
-        uint32_t ux = 0;
-        for (int b = 0; b < sp.n_sum; ++b) ux |= (((uint32_t)u >> b) & 1u) << sp.sum_bit[b];
-        uint32_t e = 0;
-        int k = 0;
-        for (int t = 0; t < sp.n_sum; ++t)
-          if ((um >> t) & 1u) e |= ((ux >> t) & 1u) << k++;
-        a.uoff[u][i] = (e << xc) * 8u;
+      for (int b = 0; b < 4; ++b) {
+        a.uw[i][b] = 0;
+        if (b >= sp.n_sum || !((um >> sp.sum_bit[b]) & 1u)) continue;
+        // the operand's summed bits sit above its x bits in union order:
+        // union bit r + sum_bit[b] is its bit xc + (held summed bits below it)
+        const int below = __builtin_popcount(um & ((1u << sp.sum_bit[b]) - 1u));
+        a.uw[i][b] = (1u << (xc + below)) * 8u;
       }
     }
   }
