@@ -246,6 +246,36 @@ def bench_many(torch, qbe, ctx, steps, n_bits=256):
                     "all bitstrings x slices in one persistent fused launch"}
 
 
+def bench_permute(torch, qbe, ctx, steps, r=28):
+    """Stand-alone bit permutation of one 2^r-entry complex64 tensor (2 GiB
+    at r = 28, the per-slice size cap of the planner's memory budget) by a
+    seeded random permutation, against a device copy of the same bytes."""
+    import numpy as np
+    rng = np.random.default_rng(2828)
+    perm = [int(p) for p in rng.permutation(r)]
+    n = 1 << r
+    # every entry a distinct bit pattern (compared as 64-bit integers)
+    d_in = torch.arange(2 * n, dtype=torch.int32, device="cuda").view(torch.complex64)
+    d_out = torch.empty_like(d_in)
+    wall, ev = timed(torch, lambda: qbe.qbe_permute(ctx, d_in, d_out, r, perm, 1), steps, 2)
+    # sampled check against the definition: output index o holds the input
+    # entry whose bit perm[j] is o's bit j
+    o = rng.integers(0, n, 4096, dtype=np.int64)
+    i = np.zeros_like(o)
+    for j in range(r):
+        i |= ((o >> j) & 1) << perm[j]
+    got = d_out.view(torch.int64)[torch.from_numpy(o).cuda()].cpu().numpy()
+    want = d_in.view(torch.int64)[torch.from_numpy(i).cuda()].cpu().numpy()
+    copy_wall, copy_ev = timed(torch, lambda: d_out.copy_(d_in), steps, 2)
+    nbytes = 2 * n * 8
+    gbs = nbytes / (ev * 1e-3) / 1e9
+    return {"workload": f"permute_r{r}_complex64", "ms": ev, "GB_per_s": gbs, "copy_ms": copy_ev,
+            "copy_GB_per_s": nbytes / (copy_ev * 1e-3) / 1e9, "sampled_exact": bool(np.array_equal(got, want)),
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                         "note": "algorithmic bytes = read + write of the tensor once"}}
+
+
 def bench_learned(torch, qbe, ctx, labels=20000, epochs=20, hbm_gbs=None):
     """Learned proposal at the 6x6..8x8 / depth 16..32 scale: ~20k exact-cost
     labels, device training, evaluation on 10 held-out 8x8 depth-32 circuits
@@ -298,7 +328,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-extra", action="store_true", help="skip the 7x7 and batch lines")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--only", choices=["hbm", "hbm_fp32", "batch", "many", "learned"],
+    ap.add_argument("--only", choices=["hbm", "hbm_fp32", "batch", "many", "learned", "permute"],
                     help="run just one extra workload (hbm_fp32: the 7x7 line in FP32 only)")
     ap.add_argument("--pmc-workload", action="store_true",
                     help="for hardware-counter runs: a device-to-device copy of 256 MiB (three times, the "
@@ -347,6 +377,9 @@ def main():
         return
     if args.only == "learned":
         print(json.dumps(bench_learned(torch, qbe, ctx)), flush=True)
+        return
+    if args.only == "permute":
+        print(json.dumps(bench_permute(torch, qbe, ctx, args.steps)), flush=True)
         return
 
     # chosen form: one fused persistent launch per amplitude, issued directly
@@ -417,6 +450,8 @@ def main():
         line["batch_workload"] = bench_batch(torch, qbe, ctx, 20)
         log("[bench] 256 bitstrings of the headline circuit ...")
         line["many_amplitudes"] = bench_many(torch, qbe, ctx, 20)
+        log("[bench] stand-alone permute ...")
+        line["permute_workload"] = bench_permute(torch, qbe, ctx, 10)
         log("[bench] learned proposal ...")
         line["learned_proposal"] = bench_learned(torch, qbe, ctx,
                                                  hbm_gbs=line["hbm_workload"]["roofline"]["achieved"])

@@ -335,6 +335,24 @@ int qbe_batch_workspace(const qbe_batch* batch, size_t* ws_bytes_out);
 int qbe_batch_contract_async(qbe_ctx* ctx, const qbe_batch* batch, void* d_workspace, size_t ws_bytes,
                              double* d_amps_out);
 
+/* ------------------------------------------------------------- permute - */
+
+/* Re-orders the variables of complex64 tensors (Sec. 2.1: each intermediate
+ * is a tensor over a clique of variables, so one tensor can be stored in any
+ * order of its variables).  d_in holds `batch` tensors of 2^r complex64
+ * entries each (interleaved re, im floats), one after another; in each, the
+ * linear index's bit p is variable p's value (bit 0 the fastest).  Output
+ * bit j takes input bit perm[j]:
+ *   out[b][sum_j x_{perm[j]} 2^j] = in[b][sum_p x_p 2^p].
+ * perm: host array of r distinct values in [0, r).  d_in, d_out: device
+ * memory of batch * 2^r * 8 bytes each, caller-owned, not overlapping.
+ * 0 <= r <= 31.  Asynchronous on the context's stream; allocates nothing.
+ * QBE_ERR_INVALID_ARG for a NULL pointer, a bad perm, overlapping buffers or
+ * a size beyond 2^62 bytes; batch == 0 is a no-op.  The contraction itself
+ * never calls this: it reads operands in place through bit extraction. */
+int qbe_permute(qbe_ctx* ctx, const void* d_in, void* d_out, int32_t r, const int32_t* perm,
+                int64_t batch);
+
 /* ------------------------------------------------------ learned proposal - */
 
 /* A message-passing network that scores variables for slicing: 8 input

@@ -114,6 +114,7 @@ _SIGS = {
     "qbe_batch_destroy": (C.c_int, [_vp]),
     "qbe_batch_workspace": (C.c_int, [_vp, C.POINTER(C.c_size_t)]),
     "qbe_batch_contract_async": (C.c_int, [_vp, _vp, _vp, C.c_size_t, _vp]),
+    "qbe_permute": (C.c_int, [_vp, _vp, _vp, C.c_int32, _i32p, C.c_int64]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -462,6 +463,21 @@ class Batch:
             self.handle = None
 
     __del__ = close
+
+
+# ----------------------------------------------------------------- permute --
+
+def qbe_permute(ctx: Context, d_in, d_out, r: int, perm: Sequence[int], batch: int = 1):
+    """Enqueues out[b][sum_j x_{perm[j]} 2^j] = in[b][sum_p x_p 2^p] for batch
+    tensors of 2^r complex64 entries (d_in, d_out: contiguous device tensors
+    of at least batch * 2^r * 8 bytes, not overlapping)."""
+    need = int(batch) << int(r) if batch > 0 else 0
+    for name, t in (("d_in", d_in), ("d_out", d_out)):
+        if not t.is_contiguous() or t.numel() * t.element_size() < need * 8:
+            raise ValueError(f"{name} must be contiguous with >= {need * 8} bytes")
+    p = _i32(perm)
+    _check(_lib.qbe_permute(ctx.handle, _vp(d_in.data_ptr()), _vp(d_out.data_ptr()), int(r), _p32(p),
+                            int(batch)), "qbe_permute")
 
 
 # -------------------------------------------------------- learned proposal --

@@ -736,6 +736,31 @@ int qbe_batch_contract_async(qbe_ctx* ctx, const qbe_batch* batch, void* d_works
   QBE_GUARD_END
 }
 
+// ------------------------------------------------------------------ permute
+
+int qbe_permute(qbe_ctx* ctx, const void* d_in, void* d_out, int32_t r, const int32_t* perm, int64_t batch) {
+  QBE_GUARD_BEGIN
+  QBE_REQUIRE(ctx, "NULL argument");
+  QBE_REQUIRE(0 <= r && r <= 31, "r must lie in [0, 31]");
+  QBE_REQUIRE(batch >= 0, "batch must be >= 0");
+  QBE_REQUIRE(batch <= (int64_t(1) << (59 - r)), "tensor bytes beyond 2^62");
+  if (batch == 0) return QBE_OK;
+  QBE_REQUIRE(d_in && d_out, "NULL device pointer");
+  QBE_REQUIRE(r == 0 || perm, "perm is NULL");
+  std::vector<char> seen(r, 0);
+  for (int j = 0; j < r; ++j) {
+    QBE_REQUIRE(0 <= perm[j] && perm[j] < r && !seen[perm[j]], "perm is not a permutation of [0, r)");
+    seen[perm[j]] = 1;
+  }
+  const uintptr_t bytes = (uintptr_t)(batch << r) * 8u;
+  const uintptr_t a = (uintptr_t)d_in, b = (uintptr_t)d_out;
+  QBE_REQUIRE(a + bytes <= b || b + bytes <= a, "d_in and d_out overlap");
+  int rc = qbe::dev_set(ctx->device);
+  if (rc) return rc;
+  return qbe::dev_permute(d_in, d_out, r, perm, batch, ctx->stream);
+  QBE_GUARD_END
+}
+
 // ---------------------------------------------------------- learned proposal
 
 int32_t qbe_gnn_num_params(void) { return qbe::gnn_num_params(); }

@@ -225,6 +225,7 @@ void dev_batch_free(Batch& b);
 size_t dev_batch_workspace(const Batch& b);
 int dev_batch_contract(const Batch& b, void* stream, void* ws, size_t ws_bytes, double* d_amps);
 int dev_memcpy_d2h(void* dst, const void* src, size_t bytes, void* stream);
+int dev_permute(const void* in, void* out, int r, const int32_t* perm, int64_t batch, void* stream);
 
 void set_error(const std::string& s);
 
