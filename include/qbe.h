@@ -334,6 +334,16 @@ int qbe_batch_workspace(const qbe_batch* batch, size_t* ws_bytes_out);
  * or synchronisation inside, so the call may be captured into a HIP graph. */
 int qbe_batch_contract_async(qbe_ctx* ctx, const qbe_batch* batch, void* d_workspace, size_t ws_bytes,
                              double* d_amps_out);
+/* The batch in one synchronous call (Sec. 2.4: the subtasks of all plans
+ * are independent): a transient batch of the plans is built, contracted on
+ * the context's stream and released; amps_out (host, 2 * n_plans doubles)
+ * receives the FP64 amplitudes, plan i at [2 i], [2 i + 1].  With d_workspace
+ * NULL the call only stores the workspace bytes it needs in *ws_needed_out
+ * (which may otherwise be NULL).  QBE_ERR_MEM_CAP if ws_bytes is smaller than
+ * that.  Allocates the batch's device tables each call: for repeated calls
+ * keep a qbe_batch instead. */
+int qbe_contract_batch(qbe_ctx* ctx, const qbe_plan* const* plans, int32_t n_plans, void* d_workspace,
+                       size_t ws_bytes, double* amps_out, size_t* ws_needed_out);
 
 /* ------------------------------------------------------------- permute - */
 
@@ -371,6 +381,15 @@ int32_t qbe_gnn_num_params(void);
 int qbe_gnn_get_params(const qbe_gnn* gnn, float* params_out);
 /* Replaces the parameters and resets the optimizer state. */
 int qbe_gnn_set_params(qbe_gnn* gnn, const float* params);
+/* Training checkpoint at a caller path: the FP32 master parameters, both
+ * Adam moments and the step count, so that training resumes where it
+ * stopped.  File layout (native little-endian): the 8 bytes "QBEGNN01",
+ * int32 parameter count, int32 step, then three float32 arrays of that count
+ * (parameters, first moments, second moments).  QBE_ERR_INVALID_ARG for a
+ * file that cannot be opened, written or read in full, or whose magic or
+ * parameter count differs; the network is unchanged then. */
+int qbe_gnn_save(const qbe_gnn* gnn, const char* path);
+int qbe_gnn_load(qbe_gnn* gnn, const char* path);
 /* Forward pass on the device: scores_out[n] (host). */
 int qbe_gnn_score(qbe_ctx* ctx, qbe_gnn* gnn, int32_t n, const int32_t* rowptr, const int32_t* col,
                   const float* feats, float* scores_out);

@@ -115,6 +115,10 @@ _SIGS = {
     "qbe_batch_workspace": (C.c_int, [_vp, C.POINTER(C.c_size_t)]),
     "qbe_batch_contract_async": (C.c_int, [_vp, _vp, _vp, C.c_size_t, _vp]),
     "qbe_permute": (C.c_int, [_vp, _vp, _vp, C.c_int32, _i32p, C.c_int64]),
+    "qbe_contract_batch": (C.c_int, [_vp, C.POINTER(_vp), C.c_int32, _vp, C.c_size_t, _f64p,
+                                     C.POINTER(C.c_size_t)]),
+    "qbe_gnn_save": (C.c_int, [_vp, C.c_char_p]),
+    "qbe_gnn_load": (C.c_int, [_vp, C.c_char_p]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -434,6 +438,27 @@ def qbe_contract_async(ctx: Context, plan: Plan, ws, d_out):
                                    _vp(d_out.data_ptr())), "qbe_contract_async")
 
 
+def qbe_contract_batch(ctx: Context, plans: Sequence[Plan], ws=None) -> np.ndarray:
+    """All plans in one synchronous call; returns their complex128
+    amplitudes.  ws: a uint8 device tensor of at least
+    qbe_contract_batch_workspace(ctx, plans) bytes (allocated when None)."""
+    arr = (_vp * len(plans))(*[p.handle for p in plans])
+    if ws is None:
+        import torch
+        ws = torch.empty(qbe_contract_batch_workspace(ctx, plans), dtype=torch.uint8, device=f"cuda:{ctx.device}")
+    amps = np.zeros(2 * len(plans), dtype=np.float64)
+    _check(_lib.qbe_contract_batch(ctx.handle, arr, len(plans), _vp(ws.data_ptr()), ws.numel(),
+                                   amps.ctypes.data_as(_f64p), None), "qbe_contract_batch")
+    return amps.view(np.complex128)
+
+
+def qbe_contract_batch_workspace(ctx: Context, plans: Sequence[Plan]) -> int:
+    arr = (_vp * len(plans))(*[p.handle for p in plans])
+    n = C.c_size_t()
+    _check(_lib.qbe_contract_batch(ctx.handle, arr, len(plans), None, 0, None, C.byref(n)), "qbe_contract_batch")
+    return n.value
+
+
 class Batch:
     """Many plans contracted in one persistent fused launch."""
 
@@ -522,6 +547,13 @@ class Gnn:
         p = np.ascontiguousarray(p, dtype=np.float32)
         assert p.shape == (self.n_params,)
         _check(_lib.qbe_gnn_set_params(self.handle, _fp(p)), "qbe_gnn_set_params")
+
+    def save(self, path: str):
+        """Checkpoint: parameters, Adam moments and step count."""
+        _check(_lib.qbe_gnn_save(self.handle, os.fsencode(path)), "qbe_gnn_save")
+
+    def load(self, path: str):
+        _check(_lib.qbe_gnn_load(self.handle, os.fsencode(path)), "qbe_gnn_load")
 
     def score(self, rowptr, col, feats) -> np.ndarray:
         rp, cl = _i32(rowptr), _i32(col)

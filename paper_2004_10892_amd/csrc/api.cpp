@@ -2,11 +2,13 @@
 // catches all C++ exceptions and turns them into error codes.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <memory>
 #include <new>
 #include <stdexcept>
 #include <string>
+#include <vector>
 
 #include "../../include/qbe.h"
 #include "qbe_internal.hpp"
@@ -761,6 +763,32 @@ int qbe_permute(qbe_ctx* ctx, const void* d_in, void* d_out, int32_t r, const in
   QBE_GUARD_END
 }
 
+int qbe_contract_batch(qbe_ctx* ctx, const qbe_plan* const* plans, int32_t n_plans, void* d_workspace,
+                       size_t ws_bytes, double* amps_out, size_t* ws_needed_out) {
+  QBE_GUARD_BEGIN
+  QBE_REQUIRE(ctx && plans && n_plans > 0, "bad argument");
+  QBE_REQUIRE(d_workspace || ws_needed_out, "NULL argument");
+  qbe_batch* b = nullptr;
+  int rc = qbe_batch_create(ctx, plans, n_plans, &b);
+  if (rc) return rc;
+  std::unique_ptr<qbe_batch, int (*)(qbe_batch*)> guard(b, qbe_batch_destroy);
+  // the batch's workspace, then the device copy of the amplitudes
+  const size_t head = (qbe::dev_batch_workspace(b->b) + 255) / 256 * 256;
+  const size_t need = head + 16 * (size_t)n_plans;
+  if (ws_needed_out) *ws_needed_out = need;
+  if (!d_workspace) return QBE_OK;
+  QBE_REQUIRE(amps_out, "amps_out is NULL");
+  if (ws_bytes < need) {
+    set_error("workspace of " + std::to_string(ws_bytes) + " bytes, the batch needs " + std::to_string(need));
+    return QBE_ERR_MEM_CAP;
+  }
+  double* d_amps = reinterpret_cast<double*>(static_cast<char*>(d_workspace) + head);
+  rc = qbe::dev_batch_contract(b->b, ctx->stream, d_workspace, head, d_amps);
+  if (rc) return rc;
+  return qbe::dev_memcpy_d2h(amps_out, d_amps, 16 * (size_t)n_plans, ctx->stream);
+  QBE_GUARD_END
+}
+
 // ---------------------------------------------------------- learned proposal
 
 int32_t qbe_gnn_num_params(void) { return qbe::gnn_num_params(); }
@@ -832,6 +860,50 @@ int qbe_gnn_set_params(qbe_gnn* gnn, const float* params) {
   int rc = qbe::dev_set(gnn->g.device);
   if (rc) return rc;
   return qbe::gnn_set_params(gnn->g, params, true);
+  QBE_GUARD_END
+}
+
+static const char kGnnMagic[8] = {'Q', 'B', 'E', 'G', 'N', 'N', '0', '1'};
+
+int qbe_gnn_save(const qbe_gnn* gnn, const char* path) {
+  QBE_GUARD_BEGIN
+  QBE_REQUIRE(gnn && path, "NULL argument");
+  int rc = qbe::dev_set(gnn->g.device);
+  if (rc) return rc;
+  const int32_t n = qbe::gnn_num_params();
+  std::vector<float> p(n), m(n), v(n);
+  int step = 0;
+  rc = qbe::gnn_get_state(gnn->g, p.data(), m.data(), v.data(), &step);
+  if (rc) return rc;
+  std::unique_ptr<FILE, int (*)(FILE*)> f(std::fopen(path, "wb"), std::fclose);
+  QBE_REQUIRE(f, std::string("cannot open ") + path + " for writing");
+  const int32_t hdr[2] = {n, (int32_t)step};
+  bool ok = std::fwrite(kGnnMagic, 1, 8, f.get()) == 8 && std::fwrite(hdr, 4, 2, f.get()) == 2;
+  for (const std::vector<float>* a : {&p, &m, &v}) ok = ok && std::fwrite(a->data(), 4, n, f.get()) == (size_t)n;
+  ok = std::fclose(f.release()) == 0 && ok;
+  QBE_REQUIRE(ok, std::string("write to ") + path + " failed");
+  return QBE_OK;
+  QBE_GUARD_END
+}
+
+int qbe_gnn_load(qbe_gnn* gnn, const char* path) {
+  QBE_GUARD_BEGIN
+  QBE_REQUIRE(gnn && path, "NULL argument");
+  const int32_t n = qbe::gnn_num_params();
+  std::unique_ptr<FILE, int (*)(FILE*)> f(std::fopen(path, "rb"), std::fclose);
+  QBE_REQUIRE(f, std::string("cannot open ") + path);
+  char magic[8];
+  int32_t hdr[2];
+  QBE_REQUIRE(std::fread(magic, 1, 8, f.get()) == 8 && std::memcmp(magic, kGnnMagic, 8) == 0,
+              std::string(path) + " is not a network checkpoint");
+  QBE_REQUIRE(std::fread(hdr, 4, 2, f.get()) == 2 && hdr[0] == n && hdr[1] >= 0,
+              std::string(path) + ": parameter count or step differs from this network's");
+  std::vector<float> p(n), m(n), v(n);
+  for (std::vector<float>* a : {&p, &m, &v})
+    QBE_REQUIRE(std::fread(a->data(), 4, n, f.get()) == (size_t)n, std::string(path) + " is truncated");
+  int rc = qbe::dev_set(gnn->g.device);
+  if (rc) return rc;
+  return qbe::gnn_set_state(gnn->g, p.data(), m.data(), v.data(), hdr[1]);
   QBE_GUARD_END
 }
 

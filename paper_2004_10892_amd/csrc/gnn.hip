@@ -248,6 +248,23 @@ int gnn_get_params(const Gnn& g, float* host) {
   return QBE_OK;
 }
 
+int gnn_get_state(const Gnn& g, float* p, float* m, float* v, int* step) {
+  GNN_HIP(hipMemcpy(p, g.d_p, kGnnParams * 4, hipMemcpyDeviceToHost));
+  GNN_HIP(hipMemcpy(m, g.d_m, kGnnParams * 4, hipMemcpyDeviceToHost));
+  GNN_HIP(hipMemcpy(v, g.d_v, kGnnParams * 4, hipMemcpyDeviceToHost));
+  *step = g.step;
+  return QBE_OK;
+}
+
+int gnn_set_state(Gnn& g, const float* p, const float* m, const float* v, int step) {
+  int rc = gnn_set_params(g, p, false);
+  if (rc) return rc;
+  GNN_HIP(hipMemcpy(g.d_m, m, kGnnParams * 4, hipMemcpyHostToDevice));
+  GNN_HIP(hipMemcpy(g.d_v, v, kGnnParams * 4, hipMemcpyHostToDevice));
+  g.step = step;
+  return QBE_OK;
+}
+
 // Device workspace for a graph of n vertices and nnz adjacency entries, the
 // candidates, and every activation the backward pass needs.
 struct GnnBufs {

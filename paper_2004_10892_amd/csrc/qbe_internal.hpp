@@ -200,6 +200,9 @@ int gnn_alloc(Gnn& g, int device);
 void gnn_free(Gnn& g);
 int gnn_set_params(Gnn& g, const float* host, bool reset_optimizer);
 int gnn_get_params(const Gnn& g, float* host);
+// FP32 parameters, Adam moments and step count (a training checkpoint).
+int gnn_get_state(const Gnn& g, float* p, float* m, float* v, int* step);
+int gnn_set_state(Gnn& g, const float* p, const float* m, const float* v, int step);
 int gnn_score(Gnn& g, void* stream, int n, const int* rp, const int* col, const float* feats, float* scores);
 int gnn_train_step(Gnn& g, void* stream, int n, const int* rp, const int* col, const float* feats, int nc,
                    const int* cand, const float* y, float lr, float* loss_out, float* grads_out);

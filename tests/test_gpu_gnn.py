@@ -81,3 +81,56 @@ def test_rejects_asymmetric_graphs(env):
     col = np.array([1], dtype=np.int32)
     with pytest.raises(qbe.QbeError, match="INVALID_ARG"):
         net.score(rp, col, np.zeros((2, 8), np.float32))
+
+
+def test_checkpoint_resumes_training_exactly(env, tmp_path):
+    """qbe_gnn_save / qbe_gnn_load: a network restored from a checkpoint
+    taken mid-training continues bit for bit like the original (parameters,
+    Adam moments and step count all restored)."""
+    qbe, ctx = env
+    print("case gnn checkpoint", flush=True)
+    A, X, cand, y = case(7, n=50)
+    rp, col = csr(A)
+    a = qbe.Gnn(ctx, seed=4)
+    for _ in range(5):
+        a.train_step(rp, col, X, cand, y, lr=1e-3)
+    path = str(tmp_path / "net.ckpt")
+    at_ckpt = a.params()
+    a.save(path)
+    b = qbe.Gnn(ctx, seed=99)
+    b.load(path)
+    assert np.array_equal(a.params(), b.params())
+    for _ in range(5):
+        la = a.train_step(rp, col, X, cand, y, lr=1e-3)
+        lb = b.train_step(rp, col, X, cand, y, lr=1e-3)
+        assert la == lb
+    assert np.array_equal(a.params(), b.params())
+    # the same parameters with a fresh optimizer state (set_params) take
+    # other steps: the checkpoint's moments and step count matter
+    c = qbe.Gnn(ctx, seed=99)
+    c.set_params(at_ckpt)
+    for _ in range(5):
+        c.train_step(rp, col, X, cand, y, lr=1e-3)
+    assert not np.array_equal(c.params(), a.params())
+
+
+def test_checkpoint_rejects_bad_files(env, tmp_path):
+    qbe, ctx = env
+    net = qbe.Gnn(ctx, seed=1)
+    before = net.params()
+    with pytest.raises(qbe.QbeError, match="INVALID_ARG"):
+        net.load(str(tmp_path / "missing.ckpt"))
+    bad = tmp_path / "bad.ckpt"
+    bad.write_bytes(b"NOTACKPT" + b"\0" * 64)
+    with pytest.raises(qbe.QbeError, match="INVALID_ARG"):
+        net.load(str(bad))
+    good = tmp_path / "good.ckpt"
+    net.save(str(good))
+    data = good.read_bytes()
+    short = tmp_path / "short.ckpt"
+    short.write_bytes(data[: len(data) // 2])
+    with pytest.raises(qbe.QbeError, match="INVALID_ARG"):
+        net.load(str(short))
+    assert np.array_equal(net.params(), before)
+    with pytest.raises(qbe.QbeError, match="INVALID_ARG"):
+        net.save(str(tmp_path / "no_such_dir" / "x.ckpt"))

@@ -238,6 +238,32 @@ def test_batch_of_uneven_instances(qbe, ctx):
         assert abs(g - w) <= TOL * s
 
 
+def test_contract_batch_one_call(qbe, ctx):
+    """qbe_contract_batch (transient batch, host amplitudes) against the
+    oracle, its size query, and the too-small workspace error."""
+    import torch
+    from circuitgen import batch_instances, circuit_model, random_grid_circuit
+    from oracle import contract as C
+    inst = batch_instances(24)
+    plans, wants = [], []
+    for (r, c, d, m, seed) in inst:
+        mod = circuit_model(random_grid_circuit(r, c, d, seed))
+        mu, pi, sched = oracle_schedule(mod, m)
+        wants.append(C.contract(mod.tensors, sched)[0])
+        plans.append(qbe.Plan(qbe.Model.from_circuitgen(mod), pi, mu, ctx=ctx))
+    _say("case one-call batch of 24 instances")
+    need = qbe.qbe_contract_batch_workspace(ctx, plans)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    got = qbe.qbe_contract_batch(ctx, plans, ws)
+    scale = [max(abs(w), 2.0 ** (-(r * c) / 2) * 1e-2) for w, (r, c, *_ ) in zip(wants, inst)]
+    for g, w, s in zip(got, wants, scale):
+        assert abs(g - w) <= TOL * s
+    again = qbe.qbe_contract_batch(ctx, plans, ws)
+    assert np.array_equal(got, again)
+    with pytest.raises(qbe.QbeError, match="MEM_CAP"):
+        qbe.qbe_contract_batch(ctx, plans, ws[: need - 16])
+
+
 def test_unit_norm_over_all_bitstrings(qbe, ctx):
     """sum_x |<x|C|0>|^2 = 1 over all 2^9 bitstrings of a 3x3 circuit, one
     batch instance per bitstring."""
