@@ -171,8 +171,35 @@ def cpu_baseline(name, budget_s=12.0, max_workers=16):
     return {"value": modes[best]["value"], "unit": "amplitudes/s", "cores": modes[best]["cores"],
             "kind": "oracle", "mode": best, "modes": modes,
             "sample": f"whole amplitudes of {name} (all {1 << m} slices each) for about {budget_s:.0f} s per "
-                      f"mode, numpy complex128 einsum; host has {os.cpu_count()} logical CPUs, "
+                      f"mode, numpy complex128 einsum; host: {cpu_model()}, {os.cpu_count()} logical CPUs, "
                       f"{affinity} usable by this process"}
+
+
+_COPY_GBS = []
+
+
+def copy_peak_gbs(torch):
+    """Measured HBM peak: a 2 GiB device-to-device copy (read + write bytes
+    per second), timed once per process."""
+    if not _COPY_GBS:
+        src = torch.empty(1 << 28, dtype=torch.float64, device="cuda")
+        src.fill_(1.0)
+        dst = torch.empty_like(src)
+        _, ev = timed(torch, lambda: dst.copy_(src), 10, 2)
+        _COPY_GBS.append(2 * src.numel() * 8 / (ev * 1e-3) / 1e9)
+        del src, dst
+    return _COPY_GBS[0]
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def bench_hbm(torch, qbe, ctx, steps, precision="fp32"):
@@ -201,6 +228,7 @@ def bench_hbm(torch, qbe, ctx, steps, precision="fp32"):
             "rel_err": abs(got - want) / abs(want), "planning_ms": plan_ms, "config": cfg,
             "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                         "copy_peak": copy_peak_gbs(torch), "frac_vs_copy": gbs / copy_peak_gbs(torch),
                          "algorithmic_bytes": bytes_amp, "schedule_bytes": sched_bytes,
                          "algorithmic_flops": flops_amp,
                          "note": "all per-step launches of one amplitude; algorithmic bytes = every launch "
@@ -312,6 +340,7 @@ def bench_permute(torch, qbe, ctx, steps, r=28):
             "copy_GB_per_s": nbytes / (copy_ev * 1e-3) / 1e9, "sampled_exact": bool(np.array_equal(got, want)),
             "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                         "copy_peak": copy_peak_gbs(torch), "frac_vs_copy": gbs / copy_peak_gbs(torch),
                          "note": "algorithmic bytes = read + write of the tensor once"}}
 
 
