@@ -743,6 +743,186 @@ __global__ __launch_bounds__(kBlock) void mmk_kernel(MmkLaunch a) {
   }
 }
 
+// Merged two-group products as whole-block GEMMs.  A block is one slice and
+// one value of the result bits outside the block bits: 2^MB (A'-private) x
+// 2^NB (B'-private) result entries of T = 2^J terms each.  Workgroup b takes
+// blocks [b * per_wg, (b + 1) * per_wg) in sequence, so that neighbouring
+// blocks -- neighbouring entries of the factors -- are read by one compute
+// unit.  Per block: the factors that hold no block bit (their value depends
+// on the term and the block only) multiply into one value per term; A'[k][m]
+// and B'[k][n] (the products of each group's other factors, A' times the
+// per-term value) are staged in LDS, every load of a factor in flight at
+// once; the 16 x 16 tiles run on MFMA (waves take tiles round robin; tile
+// bits = the four lowest block bits of each side); each tile is written
+// through a per-wave LDS buffer in result order, so that stores cover runs
+// of consecutive entries.  A factor entry's offset is a sum of parts (bit
+// extraction is linear over disjoint bit sets): the lane's m or n part once
+// per launch, the block part once per block, the term part from per-bit
+// weights.  LDS rows are padded by 16 entries so that the four term groups
+// of an MFMA operand read fall in different banks.
+constexpr int kMmbMaxM = 7, kMmbMaxN = 6, kMmbPad = 16, kMmbBig = 4;
+// entries a thread stages per block: 2^(J + MB) / 256 <= 2^(4 + 7 - 8) of
+// A', 2^(J + NB) / 256 <= 2^(4 + 6 - 8) of B'
+constexpr int kMmbStageA = 8, kMmbStageB = 4;
+
+struct MmbFactor {
+  const float2* src;
+  int64_t gs;        // elements between slices (0: input tensor)
+  uint32_t sm;       // input slice mask
+  int32_t rk;
+  uint32_t mk;       // mask over X
+  uint32_t kw[4];    // index weight of summed bit t (0: not held)
+};
+
+struct MmbLaunch {
+  float2* out;
+  MmbFactor big[kMmbBig];  // factors holding block bits: NA of A', then NB of B'
+  MmbFactor kf[kMaxOps];   // the others
+  int32_t n_kf;
+  int32_t prec;            // QBE_PREC_*: FP32 or split-BF16 MFMAs
+  uint32_t bm, bn;         // block bits of A' and B'
+  uint32_t rest;           // the other result bits (fixed per block)
+  int32_t r, MB, NB, rest_bits;
+  int64_t s0, n_blocks, per_wg;
+};
+
+__device__ __forceinline__ uint32_t lowest_bits(uint32_t m, int n) {
+  uint32_t r = 0;
+  for (int i = 0; i < n && m; ++i) {
+    r |= m & (~m + 1u);
+    m &= m - 1u;
+  }
+  return r;
+}
+
+// First entry of factor f for slice g (slice sl) and block bits xt.
+__device__ __forceinline__ const float2* mmb_base(const MmbFactor& f, int64_t g, uint32_t sl, uint32_t xt) {
+  return f.src + g * f.gs + (f.gs ? 0 : (int64_t)pext32(sl, f.sm) << f.rk) + pext32(xt, f.mk);
+}
+
+template <int J>
+__device__ __forceinline__ uint32_t mmb_term(const MmbFactor& f, int k) {
+  uint32_t o = 0;
+#pragma unroll
+  for (int t = 0; t < J; ++t) o += ((k >> t) & 1) ? f.kw[t] : 0u;
+  return o;
+}
+
+template <int J, int NA, int NBF>
+__global__ __launch_bounds__(kBlock) void mmb_kernel(MmbLaunch a) {
+  constexpr int T = 1 << J;  // terms
+  __shared__ float2 As[T * ((1 << kMmbMaxM) + kMmbPad)];
+  __shared__ float2 Bs[T * ((1 << kMmbMaxN) + kMmbPad)];
+  __shared__ float2 Ts[kBlock / 64][256];
+  __shared__ float2 Ks[T];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int Mn = 1 << a.MB, Nn = 1 << a.NB;
+  const int sa = Mn + kMmbPad, sb = Nn + kMmbPad;
+  const uint32_t mt = lowest_bits(a.bm, 4), nt = lowest_bits(a.bn, 4), tt = mt | nt;
+  const uint32_t mh = a.bm & ~mt, nh = a.bn & ~nt;
+  const int row = lane & 15, grp = lane >> 4;
+  // MFMA result layout: the lane holds tile rows 4 grp + i of column row;
+  // pw: their positions in the tile's result order; qo: the result offset
+  // of tile position lane + 64 j
+  uint32_t pw[4], qo[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    pw[i] = pext32(pdep32((uint32_t)(4 * grp + i), mt) | pdep32((uint32_t)row, nt), tt);
+    qo[i] = pdep32((uint32_t)(lane + 64 * i), tt);
+  }
+  // staging: thread tid takes entries tid + 256 j of A' (m = entry mod Mn,
+  // k = entry / Mn; Mn divides 256, so m is fixed) and likewise of B'
+  const int ma = tid & (Mn - 1), ka0 = tid >> a.MB, kas = kBlock >> a.MB;
+  const int nb = tid & (Nn - 1), kb0 = tid >> a.NB, kbs = kBlock >> a.NB;
+  uint32_t part[NA + NBF];
+#pragma unroll
+  for (int i = 0; i < NA + NBF; ++i)
+    part[i] = pext32(i >= NA ? pdep32((uint32_t)nb, a.bn) : pdep32((uint32_t)ma, a.bm), a.big[i].mk);
+  const int tiles_m = Mn >> 4, n_tiles = tiles_m * (Nn >> 4);
+  const int64_t b_end = std::min<int64_t>((int64_t)(blockIdx.x + 1) * a.per_wg, a.n_blocks);
+  for (int64_t blk = (int64_t)blockIdx.x * a.per_wg; blk < b_end; ++blk) {
+    const int64_t g = blk >> a.rest_bits;
+    const uint32_t xt = pdep32((uint32_t)(blk & ((int64_t(1) << a.rest_bits) - 1)), a.rest);
+    const uint32_t sl = (uint32_t)(a.s0 + g);
+    // the big factors' loads first, every entry's at once
+    float2 wa[NA][kMmbStageA];
+    float2 wb[NBF][kMmbStageB];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const float2* bi = mmb_base(a.big[i], g, sl, xt);
+#pragma unroll
+      for (int j = 0; j < kMmbStageA; ++j) {
+        const int k = ka0 + j * kas;
+        wa[i][j] = k < T ? bi[part[i] + mmb_term<J>(a.big[i], k)] : make_float2(1.f, 0.f);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NBF; ++i) {
+      const float2* bi = mmb_base(a.big[NA + i], g, sl, xt);
+#pragma unroll
+      for (int j = 0; j < kMmbStageB; ++j) {
+        const int k = kb0 + j * kbs;
+        wb[i][j] = k < T ? bi[part[NA + i] + mmb_term<J>(a.big[NA + i], k)] : make_float2(1.f, 0.f);
+      }
+    }
+    __syncthreads();  // the previous block's reads of As, Bs, Ks are done
+    if (tid < T) {
+      float2 v = make_float2(1.f, 0.f);
+      for (int i = 0; i < a.n_kf; ++i) v = cmul(v, mmb_base(a.kf[i], g, sl, xt)[mmb_term<J>(a.kf[i], tid)]);
+      Ks[tid] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kMmbStageA; ++j) {
+      const int k = ka0 + j * kas;
+      if (k < T) {
+        float2 v = Ks[k];
+#pragma unroll
+        for (int i = 0; i < NA; ++i) v = cmul(v, wa[i][j]);
+        As[k * sa + ma] = v;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kMmbStageB; ++j) {
+      const int k = kb0 + j * kbs;
+      if (k < T) {
+        float2 v = make_float2(1.f, 0.f);
+#pragma unroll
+        for (int i = 0; i < NBF; ++i) v = cmul(v, wb[i][j]);
+        Bs[k * sb + nb] = v;
+      }
+    }
+    __syncthreads();
+    float2* const ob = a.out + (g << a.r) + xt;
+    for (int t = wv; t < n_tiles; t += kBlock / 64) {
+      const int tm = t % tiles_m, tn = t / tiles_m;
+      floatx4 cre = {0.f, 0.f, 0.f, 0.f}, cim = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kb = 0; kb < T; kb += 4) {
+        const float2 av = As[(kb + grp) * sa + tm * 16 + row];
+        const float2 bv = Bs[(kb + grp) * sb + tn * 16 + row];
+        if (a.prec == QBE_PREC_FP32) {
+          cre = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv.x, cre, 0, 0, 0);
+          cre = __builtin_amdgcn_mfma_f32_16x16x4f32(-av.y, bv.y, cre, 0, 0, 0);
+          cim = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv.y, cim, 0, 0, 0);
+          cim = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv.x, cim, 0, 0, 0);
+        } else {
+          cre = mfma_split(av.x, bv.x, cre, a.prec);
+          cre = mfma_split(-av.y, bv.y, cre, a.prec);
+          cim = mfma_split(av.x, bv.y, cim, a.prec);
+          cim = mfma_split(av.y, bv.x, cim, a.prec);
+        }
+      }
+      // one wave's LDS accesses complete in order: the buffer needs no barrier
+#pragma unroll
+      for (int i = 0; i < 4; ++i) Ts[wv][pw[i]] = make_float2(cre[i], cim[i]);
+      const uint32_t tb = pdep32((uint32_t)tm, mh) | pdep32((uint32_t)tn, nh);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) ob[tb | qo[j]] = Ts[wv][lane + 64 * j];
+    }
+  }
+}
+
 // Per-slice product of the scalar factors, in FP64.
 struct FinalizeArgs {
   const float2* arena;
@@ -1000,208 +1180,290 @@ size_t dev_workspace_all(const Plan& p) {
   return ws_head(p.n_slices) + (size_t)p.arena_per_slice * 8 * (size_t)p.n_slices;
 }
 
-static int launch_step(const Plan& p, const StepProg& sp, float2* arena, int64_t G, int64_t s0,
-                       hipStream_t st, int ept = 0, int wg_per_cu = 0) {
-  StepLaunch a{};
-  const bool sum_u = sp.out_rank >= 0;
-  const int r = sum_u ? sp.out_rank : -sp.out_rank;
-  a.out = arena + sp.out_base * G;
-  a.n_ops = sp.n_ops;
-  a.r = r;
-  a.sum_u = sum_u ? 1 : 0;
-  a.n_sum = sp.n_sum;
-  a.lo = std::min(r, kLoBits);
-  a.s0 = s0;
-  a.G = G;
+// A merged two-group launch as independent 16 x 16 tiles (mmk_kernel): the
+// form for launches with more factors holding block bits, or term and factor
+// counts, than mmb_kernel takes.
+static int launch_mmk(const Plan& p, const StepProg& sp, const StepLaunch& a, int r, int64_t G, int64_t s0,
+                      hipStream_t st, int wg_per_cu) {
+  MmkLaunch m{};
+  m.out = a.out;
+  m.n_ops = sp.n_ops;
+  m.side_b = sp.mmk_side;
+  m.prec = p.precision;
+  const uint32_t xmask = (1u << r) - 1u;
+  uint32_t xa = 0, xb = 0;
   for (int i = 0; i < sp.n_ops; ++i) {
-    const StepOp& o = sp.ops[i];
-    if (o.is_input) {
-      a.src[i] = (const float2*)p.d_step_in + o.base;
-      a.gstride[i] = 0;
-      a.smask[i] = o.smask;
-    } else {
-      a.src[i] = arena + o.base * G;
-      a.gstride[i] = int64_t(1) << o.rank;
-      a.smask[i] = 0;
-    }
-    a.mask[i] = o.mask;
-    a.rank[i] = o.rank;
+    m.src[i] = a.src[i];
+    m.gs[i] = a.gstride[i];
+    m.sm[i] = a.smask[i];
+    m.rk[i] = a.rank[i];
+    m.mk[i] = a.mask[i];
+    ((sp.mmk_side >> i) & 1u ? xb : xa) |= a.mask[i] & xmask;
   }
-  if (sp.mmk) {
-    // merged launch on MFMA: operand groups A' and B'
-    MmkLaunch m{};
-    m.out = a.out;
-    m.n_ops = sp.n_ops;
-    m.side_b = sp.mmk_side;
-    m.prec = p.precision;
-    const uint32_t xmask = (1u << r) - 1u;
-    uint32_t xa = 0, xb = 0;
-    for (int i = 0; i < sp.n_ops; ++i) {
-      m.src[i] = a.src[i];
-      m.gs[i] = a.gstride[i];
-      m.sm[i] = a.smask[i];
-      m.rk[i] = a.rank[i];
-      m.mk[i] = a.mask[i];
-      ((sp.mmk_side >> i) & 1u ? xb : xa) |= a.mask[i] & xmask;
-    }
-    // the tile's column index is the lane's (16 consecutive lanes): give the
-    // column side the group owning the lowest private result bit, so that
-    // stores cover contiguous entries (the product is symmetric in A', B')
-    const uint32_t priv = (xa ^ xb) & xmask;
-    if (priv & xa & (~priv + 1u)) {
-      m.side_b = ~m.side_b & ((1u << sp.n_ops) - 1u);
-      std::swap(xa, xb);
-    }
-    uint32_t oa = xa & ~xb, ob = xb & ~xa;
-    for (int k = 0; k < 4; ++k) {
-      m.mtile |= oa & (~oa + 1u);
-      oa &= oa - 1u;
-      m.ntile |= ob & (~ob + 1u);
-      ob &= ob - 1u;
-    }
-    m.rest = xmask & ~m.mtile & ~m.ntile;
-    m.r = r;
-    m.s0 = s0;
-    m.G = G;
-    m.n_tiles = G << (r - 8);
-    if (wg_per_cu <= 0) wg_per_cu = sp.wg_per_cu > 0 ? sp.wg_per_cu : 8;
-    const int64_t want = (m.n_tiles + 3) / 4;
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)n_cus() * wg_per_cu));
-#define QBE_MMK(JJ, KK)                                                       \
-  case JJ * 16 + KK:                                                          \
-    mmk_kernel<JJ, KK><<<grid, kBlock, 0, st>>>(m);                           \
+  // the tile's column index is the lane's (16 consecutive lanes): give the
+  // column side the group owning the lowest private result bit, so that
+  // stores cover contiguous entries (the product is symmetric in A', B')
+  const uint32_t priv = (xa ^ xb) & xmask;
+  if (priv & xa & (~priv + 1u)) {
+    m.side_b = ~m.side_b & ((1u << sp.n_ops) - 1u);
+    std::swap(xa, xb);
+  }
+  uint32_t oa = xa & ~xb, ob = xb & ~xa;
+  for (int k = 0; k < 4; ++k) {
+    m.mtile |= oa & (~oa + 1u);
+    oa &= oa - 1u;
+    m.ntile |= ob & (~ob + 1u);
+    ob &= ob - 1u;
+  }
+  m.rest = xmask & ~m.mtile & ~m.ntile;
+  m.r = r;
+  m.s0 = s0;
+  m.G = G;
+  m.n_tiles = G << (r - 8);
+  if (wg_per_cu <= 0) wg_per_cu = sp.wg_per_cu > 0 ? sp.wg_per_cu : 8;
+  const int64_t want = (m.n_tiles + 3) / 4;
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)n_cus() * wg_per_cu));
+#define QBE_MMK(JJ, KK)                                                     \
+  case JJ * 16 + KK:                                                        \
+    mmk_kernel<JJ, KK><<<grid, kBlock, 0, st>>>(m);                         \
     break;
 #define QBE_MMKS(JJ) \
   QBE_MMK(JJ, 2) QBE_MMK(JJ, 3) QBE_MMK(JJ, 4) QBE_MMK(JJ, 5) QBE_MMK(JJ, 6) QBE_MMK(JJ, 7) QBE_MMK(JJ, 8)
-    switch (sp.n_sum * 16 + sp.n_ops) {
-      QBE_MMKS(2) QBE_MMKS(3) QBE_MMKS(4)
-      default:
-        set_error("merged MFMA launch with an unsupported summed-variable or operand count");
-        return QBE_ERR_INTERNAL;
-    }
+  switch (sp.n_sum * 16 + sp.n_ops) {
+    QBE_MMKS(2) QBE_MMKS(3) QBE_MMKS(4)
+    default:
+      set_error("merged MFMA launch with an unsupported summed-variable or operand count");
+      return QBE_ERR_INTERNAL;
+  }
 #undef QBE_MMKS
 #undef QBE_MMK
-    QBE_HIP(hipGetLastError());
-    return QBE_OK;
-  }
-  if (sp.mm_a >= 0 && sum_u && r >= 8) {
-    MmLaunch m{};
-    m.out = a.out;
-    const int idx[2] = {sp.mm_a, sp.mm_b};
-    for (int j = 0; j < 2; ++j) {
-      m.src[j] = a.src[idx[j]];
-      m.gs[j] = a.gstride[idx[j]];
-      m.sm[j] = a.smask[idx[j]];
-      m.rk[j] = a.rank[idx[j]];
-      m.mk[j] = a.mask[idx[j]];
-    }
-    for (int i = 0; i < sp.n_ops; ++i) {
-      if (i == sp.mm_a || i == sp.mm_b) continue;
-      m.usrc[m.n_u] = a.src[i];
-      m.ugs[m.n_u] = a.gstride[i];
-      m.usm[m.n_u] = a.smask[i];
-      ++m.n_u;
-    }
-    const uint32_t xmask = (1u << r) - 1u;
-    uint32_t oa = m.mk[0] & xmask & ~m.mk[1], ob = m.mk[1] & xmask & ~m.mk[0];
-    for (int k = 0; k < 4; ++k) {
-      m.mtile |= oa & (~oa + 1u);
-      oa &= oa - 1u;
-      m.ntile |= ob & (~ob + 1u);
-      ob &= ob - 1u;
-    }
-    m.rest = xmask & ~m.mtile & ~m.ntile;
-    m.r = r;
-    m.s0 = s0;
-    m.G = G;
-    m.n_tiles = G << (r - 8);
-    if (wg_per_cu <= 0) wg_per_cu = sp.wg_per_cu > 0 ? sp.wg_per_cu : 8;
-    const int64_t want = (m.n_tiles + 3) / 4;
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)n_cus() * wg_per_cu));
-    if (p.precision == QBE_PREC_BF16X3)
-      mm_kernel<QBE_PREC_BF16X3><<<grid, kBlock, 0, st>>>(m);
-    else if (p.precision == QBE_PREC_BF16X6)
-      mm_kernel<QBE_PREC_BF16X6><<<grid, kBlock, 0, st>>>(m);
-    else
-      mm_kernel<QBE_PREC_FP32><<<grid, kBlock, 0, st>>>(m);
-    QBE_HIP(hipGetLastError());
-    return QBE_OK;
-  }
-  if (sp.n_sum > 1) {
-    if (sp.n_sum > 4) {
-      set_error("merged launch with more than four summed variables");
-      return QBE_ERR_INTERNAL;
-    }
-    const uint32_t xmask = (1u << r) - 1u;
-    for (int i = 0; i < sp.n_ops; ++i) {
-      if (a.rank[i] > 28) {
-        set_error("merged launch operand above 2^28 entries");
-        return QBE_ERR_INTERNAL;
-      }
-      // summed variables sit above the operand's x bits, in union order;
-      // the kernel's bit b of u is union bit r + sum_bit[b]
-      const uint32_t um = a.mask[i] >> r;
-      const int xc = __builtin_popcount(a.mask[i] & xmask);
-      a.uhold[i] = 0;
-      for (int b = 0; b < sp.n_sum; ++b) a.uhold[i] |= ((um >> sp.sum_bit[b]) & 1u) << b;
-      for (int b = 0; b < 4; ++b) {
-        a.uw[i][b] = 0;
-        if (b >= sp.n_sum || !((um >> sp.sum_bit[b]) & 1u)) continue;
-        // the operand's summed bits sit above its x bits in union order:
-        // union bit r + sum_bit[b] is its bit xc + (held summed bits below it)
-        const int below = __builtin_popcount(um & ((1u << sp.sum_bit[b]) - 1u));
-        a.uw[i][b] = (1u << (xc + below)) * 8u;
-      }
-    }
-  }
-  if (wg_per_cu <= 0) wg_per_cu = sp.wg_per_cu > 0 ? sp.wg_per_cu : 16;
-  if (r < kLoBits) {
-    // several whole slices per tile
-    a.n_tiles = (G + (kBlock >> r) - 1) / (kBlock >> r);
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(a.n_tiles, (int64_t)n_cus() * wg_per_cu));
-#define QBE_SMALL(KK)                                                         \
-  case KK:                                                                    \
-    if (sp.n_sum > 1)                                                         \
-      msum_small_kernel<KK><<<grid, kBlock, 0, st>>>(a);                      \
-    else                                                                      \
-      step_small_kernel<KK><<<grid, kBlock, 0, st>>>(a);                      \
-    break;
-    switch (sp.n_ops) {
-      QBE_SMALL(1) QBE_SMALL(2) QBE_SMALL(3) QBE_SMALL(4) QBE_SMALL(5) QBE_SMALL(6) QBE_SMALL(7)
-      QBE_SMALL(8)
-      default:
-        set_error("per-step launch with an unsupported operand count");
-        return QBE_ERR_INTERNAL;
-    }
-#undef QBE_SMALL
-    QBE_HIP(hipGetLastError());
-    return QBE_OK;
-  }
-  const int hib = r - kLoBits;
-  a.n_tiles = G << hib;
-  if (ept <= 0) ept = sp.ept > 0 ? sp.ept : 1;
-  // a super-tile's EPT tiles share the slice: EPT divides 2^hib
-  while (ept > 1 && (int64_t(1) << hib) % ept != 0) ept >>= 1;
-  const int64_t want = a.n_tiles / ept;
-  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)n_cus() * wg_per_cu));
-#define QBE_CASE(KK, EE)                                                      \
-  case KK * 16 + EE:                                                          \
-    if (sp.n_sum > 1)                                                         \
-      msum_kernel<KK, EE><<<grid, kBlock, 0, st>>>(a);                        \
-    else                                                                      \
-      step_kernel<KK, EE><<<grid, kBlock, 0, st>>>(a);                        \
-    break;
-#define QBE_KS(KK) QBE_CASE(KK, 1) QBE_CASE(KK, 2) QBE_CASE(KK, 4)
-  switch (sp.n_ops * 16 + ept) {
-    QBE_KS(1) QBE_KS(2) QBE_KS(3) QBE_KS(4) QBE_KS(5) QBE_KS(6) QBE_KS(7) QBE_KS(8)
-    default:
-      set_error("per-step launch with an unsupported operand count or tile factor");
-      return QBE_ERR_INTERNAL;
-  }
-#undef QBE_KS
-#undef QBE_CASE
   QBE_HIP(hipGetLastError());
   return QBE_OK;
+}
+
+static int launch_step(const Plan& p, const StepProg& sp, float2* arena, int64_t G, int64_t s0,
+                     hipStream_t st, int ept = 0, int wg_per_cu = 0) {
+StepLaunch a{};
+const bool sum_u = sp.out_rank >= 0;
+const int r = sum_u ? sp.out_rank : -sp.out_rank;
+a.out = arena + sp.out_base * G;
+a.n_ops = sp.n_ops;
+a.r = r;
+a.sum_u = sum_u ? 1 : 0;
+a.n_sum = sp.n_sum;
+a.lo = std::min(r, kLoBits);
+a.s0 = s0;
+a.G = G;
+for (int i = 0; i < sp.n_ops; ++i) {
+  const StepOp& o = sp.ops[i];
+  if (o.is_input) {
+    a.src[i] = (const float2*)p.d_step_in + o.base;
+    a.gstride[i] = 0;
+    a.smask[i] = o.smask;
+  } else {
+    a.src[i] = arena + o.base * G;
+    a.gstride[i] = int64_t(1) << o.rank;
+    a.smask[i] = 0;
+  }
+  a.mask[i] = o.mask;
+  a.rank[i] = o.rank;
+}
+if (sp.mmk) {
+  // merged launch on MFMA: operand groups A' and B', whole blocks per
+  // workgroup; the side with more private result bits is A' (up to 2^7
+  // rows), the other B' (up to 2^6 columns)
+  MmbLaunch m{};
+  m.out = a.out;
+  m.prec = p.precision;
+  const uint32_t xmask = (1u << r) - 1u;
+  uint32_t xa = 0, xb = 0;
+  for (int i = 0; i < sp.n_ops; ++i) ((sp.mmk_side >> i) & 1u ? xb : xa) |= a.mask[i] & xmask;
+  uint32_t pa = xa & ~xb, pb = xb & ~xa;
+  uint32_t side_b = sp.mmk_side;
+  if (__builtin_popcount(pb) > __builtin_popcount(pa)) {
+    side_b = ~side_b & ((1u << sp.n_ops) - 1u);
+    std::swap(pa, pb);
+  }
+  m.MB = std::min(__builtin_popcount(pa), kMmbMaxM);
+  m.NB = std::min(__builtin_popcount(pb), kMmbMaxN);
+  for (int k = 0; k < m.MB; ++k) {
+    m.bm |= pa & (~pa + 1u);
+    pa &= pa - 1u;
+  }
+  for (int k = 0; k < m.NB; ++k) {
+    m.bn |= pb & (~pb + 1u);
+    pb &= pb - 1u;
+  }
+  MmbFactor fa[kMmbBig], fb[kMmbBig];
+  int na = 0, nbf = 0;
+  for (int i = 0; i < sp.n_ops; ++i) {
+    MmbFactor f{};
+    f.src = a.src[i];
+    f.gs = a.gstride[i];
+    f.sm = a.smask[i];
+    f.rk = a.rank[i];
+    f.mk = a.mask[i];
+    for (int t = 0; t < sp.n_sum && t < 4; ++t) {
+      const uint32_t bit = 1u << (r + t);
+      f.kw[t] = (a.mask[i] & bit) ? 1u << __builtin_popcount(a.mask[i] & (bit - 1u)) : 0u;
+    }
+    if (!(a.mask[i] & (m.bm | m.bn))) {
+      m.kf[m.n_kf++] = f;
+    } else if (na + nbf == kMmbBig) {
+      return launch_mmk(p, sp, a, r, G, s0, st, wg_per_cu);
+    } else if ((side_b >> i) & 1u) {
+      fb[nbf++] = f;
+    } else {
+      fa[na++] = f;
+    }
+  }
+  for (int i = 0; i < na; ++i) m.big[i] = fa[i];
+  for (int i = 0; i < nbf; ++i) m.big[na + i] = fb[i];
+  if (m.MB < 4 || m.NB < 4 || sp.n_sum < 2 || sp.n_sum > 4 || na < 1 || nbf < 1)
+    return launch_mmk(p, sp, a, r, G, s0, st, wg_per_cu);
+  m.rest = xmask & ~m.bm & ~m.bn;
+  m.rest_bits = __builtin_popcount(m.rest);
+  m.r = r;
+  m.s0 = s0;
+  m.n_blocks = G << m.rest_bits;
+  if (wg_per_cu <= 0) wg_per_cu = sp.wg_per_cu > 0 ? sp.wg_per_cu : 4;
+  int64_t grid = std::max<int64_t>(1, std::min<int64_t>(m.n_blocks, (int64_t)n_cus() * wg_per_cu));
+  m.per_wg = (m.n_blocks + grid - 1) / grid;
+  grid = (m.n_blocks + m.per_wg - 1) / m.per_wg;
+#define QBE_MMB(JJ, A, B)                                                     \
+case (JJ * 4 + A) * 4 + B:                                                  \
+  mmb_kernel<JJ, A, B><<<(int)grid, kBlock, 0, st>>>(m);                    \
+  break;
+#define QBE_MMBS(JJ) QBE_MMB(JJ, 1, 1) QBE_MMB(JJ, 1, 2) QBE_MMB(JJ, 2, 1) QBE_MMB(JJ, 2, 2) QBE_MMB(JJ, 1, 3) QBE_MMB(JJ, 3, 1)
+  switch ((sp.n_sum * 4 + na) * 4 + nbf) {
+    QBE_MMBS(2) QBE_MMBS(3) QBE_MMBS(4)
+    default:
+      set_error("merged MFMA launch with an unsupported summed-variable or factor count");
+      return QBE_ERR_INTERNAL;
+  }
+#undef QBE_MMBS
+#undef QBE_MMB
+  QBE_HIP(hipGetLastError());
+  return QBE_OK;
+}
+if (sp.mm_a >= 0 && sum_u && r >= 8) {
+  MmLaunch m{};
+  m.out = a.out;
+  const int idx[2] = {sp.mm_a, sp.mm_b};
+  for (int j = 0; j < 2; ++j) {
+    m.src[j] = a.src[idx[j]];
+    m.gs[j] = a.gstride[idx[j]];
+    m.sm[j] = a.smask[idx[j]];
+    m.rk[j] = a.rank[idx[j]];
+    m.mk[j] = a.mask[idx[j]];
+  }
+  for (int i = 0; i < sp.n_ops; ++i) {
+    if (i == sp.mm_a || i == sp.mm_b) continue;
+    m.usrc[m.n_u] = a.src[i];
+    m.ugs[m.n_u] = a.gstride[i];
+    m.usm[m.n_u] = a.smask[i];
+    ++m.n_u;
+  }
+  const uint32_t xmask = (1u << r) - 1u;
+  uint32_t oa = m.mk[0] & xmask & ~m.mk[1], ob = m.mk[1] & xmask & ~m.mk[0];
+  for (int k = 0; k < 4; ++k) {
+    m.mtile |= oa & (~oa + 1u);
+    oa &= oa - 1u;
+    m.ntile |= ob & (~ob + 1u);
+    ob &= ob - 1u;
+  }
+  m.rest = xmask & ~m.mtile & ~m.ntile;
+  m.r = r;
+  m.s0 = s0;
+  m.G = G;
+  m.n_tiles = G << (r - 8);
+  if (wg_per_cu <= 0) wg_per_cu = sp.wg_per_cu > 0 ? sp.wg_per_cu : 8;
+  const int64_t want = (m.n_tiles + 3) / 4;
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)n_cus() * wg_per_cu));
+  if (p.precision == QBE_PREC_BF16X3)
+    mm_kernel<QBE_PREC_BF16X3><<<grid, kBlock, 0, st>>>(m);
+  else if (p.precision == QBE_PREC_BF16X6)
+    mm_kernel<QBE_PREC_BF16X6><<<grid, kBlock, 0, st>>>(m);
+  else
+    mm_kernel<QBE_PREC_FP32><<<grid, kBlock, 0, st>>>(m);
+  QBE_HIP(hipGetLastError());
+  return QBE_OK;
+}
+if (sp.n_sum > 1) {
+  if (sp.n_sum > 4) {
+    set_error("merged launch with more than four summed variables");
+    return QBE_ERR_INTERNAL;
+  }
+  const uint32_t xmask = (1u << r) - 1u;
+  for (int i = 0; i < sp.n_ops; ++i) {
+    if (a.rank[i] > 28) {
+      set_error("merged launch operand above 2^28 entries");
+      return QBE_ERR_INTERNAL;
+    }
+    // summed variables sit above the operand's x bits, in union order;
+    // the kernel's bit b of u is union bit r + sum_bit[b]
+    const uint32_t um = a.mask[i] >> r;
+    const int xc = __builtin_popcount(a.mask[i] & xmask);
+    a.uhold[i] = 0;
+    for (int b = 0; b < sp.n_sum; ++b) a.uhold[i] |= ((um >> sp.sum_bit[b]) & 1u) << b;
+    for (int b = 0; b < 4; ++b) {
+      a.uw[i][b] = 0;
+      if (b >= sp.n_sum || !((um >> sp.sum_bit[b]) & 1u)) continue;
+      // the operand's summed bits sit above its x bits in union order:
+      // union bit r + sum_bit[b] is its bit xc + (held summed bits below it)
+      const int below = __builtin_popcount(um & ((1u << sp.sum_bit[b]) - 1u));
+      a.uw[i][b] = (1u << (xc + below)) * 8u;
+    }
+  }
+}
+if (wg_per_cu <= 0) wg_per_cu = sp.wg_per_cu > 0 ? sp.wg_per_cu : 16;
+if (r < kLoBits) {
+  // several whole slices per tile
+  a.n_tiles = (G + (kBlock >> r) - 1) / (kBlock >> r);
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(a.n_tiles, (int64_t)n_cus() * wg_per_cu));
+#define QBE_SMALL(KK)                                                         \
+case KK:                                                                    \
+  if (sp.n_sum > 1)                                                         \
+    msum_small_kernel<KK><<<grid, kBlock, 0, st>>>(a);                      \
+  else                                                                      \
+    step_small_kernel<KK><<<grid, kBlock, 0, st>>>(a);                      \
+  break;
+  switch (sp.n_ops) {
+    QBE_SMALL(1) QBE_SMALL(2) QBE_SMALL(3) QBE_SMALL(4) QBE_SMALL(5) QBE_SMALL(6) QBE_SMALL(7)
+    QBE_SMALL(8)
+    default:
+      set_error("per-step launch with an unsupported operand count");
+      return QBE_ERR_INTERNAL;
+  }
+#undef QBE_SMALL
+  QBE_HIP(hipGetLastError());
+  return QBE_OK;
+}
+const int hib = r - kLoBits;
+a.n_tiles = G << hib;
+if (ept <= 0) ept = sp.ept > 0 ? sp.ept : 1;
+// a super-tile's EPT tiles share the slice: EPT divides 2^hib
+while (ept > 1 && (int64_t(1) << hib) % ept != 0) ept >>= 1;
+const int64_t want = a.n_tiles / ept;
+const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)n_cus() * wg_per_cu));
+#define QBE_CASE(KK, EE)                                                      \
+case KK * 16 + EE:                                                          \
+  if (sp.n_sum > 1)                                                         \
+    msum_kernel<KK, EE><<<grid, kBlock, 0, st>>>(a);                        \
+  else                                                                      \
+    step_kernel<KK, EE><<<grid, kBlock, 0, st>>>(a);                        \
+  break;
+#define QBE_KS(KK) QBE_CASE(KK, 1) QBE_CASE(KK, 2) QBE_CASE(KK, 4)
+switch (sp.n_ops * 16 + ept) {
+  QBE_KS(1) QBE_KS(2) QBE_KS(3) QBE_KS(4) QBE_KS(5) QBE_KS(6) QBE_KS(7) QBE_KS(8)
+  default:
+    set_error("per-step launch with an unsupported operand count or tile factor");
+    return QBE_ERR_INTERNAL;
+}
+#undef QBE_KS
+#undef QBE_CASE
+QBE_HIP(hipGetLastError());
+return QBE_OK;
 }
 
 static int launch_group(const Plan& p, int g, float2* arena, int64_t G, int64_t s0, hipStream_t st) {
