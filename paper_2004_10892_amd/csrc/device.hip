@@ -917,8 +917,11 @@ __global__ __launch_bounds__(kBlock) void mmb_kernel(MmbLaunch a) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) Ts[wv][pw[i]] = make_float2(cre[i], cim[i]);
       const uint32_t tb = pdep32((uint32_t)tm, mh) | pdep32((uint32_t)tn, nh);
+      // streaming stores: the result is read only by later launches
 #pragma unroll
-      for (int j = 0; j < 4; ++j) ob[tb | qo[j]] = Ts[wv][lane + 64 * j];
+      for (int j = 0; j < 4; ++j)
+        __builtin_nontemporal_store(__builtin_bit_cast(uint64_t, Ts[wv][lane + 64 * j]),
+                                    reinterpret_cast<uint64_t*>(ob + (tb | qo[j])));
     }
   }
 }
