@@ -1226,12 +1226,12 @@ static int launch_mmk(const Plan& p, const StepProg& sp, const StepLaunch& a, in
   if (wg_per_cu <= 0) wg_per_cu = sp.wg_per_cu > 0 ? sp.wg_per_cu : 8;
   const int64_t want = (m.n_tiles + 3) / 4;
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)n_cus() * wg_per_cu));
-#define QBE_MMK(JJ, KK)                                                     \
-  case JJ * 16 + KK:                                                        \
-    mmk_kernel<JJ, KK><<<grid, kBlock, 0, st>>>(m);                         \
-    break;
+#define QBE_MMK(JJ, KK)                                                       \
+case JJ * 16 + KK:                                                          \
+  mmk_kernel<JJ, KK><<<grid, kBlock, 0, st>>>(m);                           \
+  break;
 #define QBE_MMKS(JJ) \
-  QBE_MMK(JJ, 2) QBE_MMK(JJ, 3) QBE_MMK(JJ, 4) QBE_MMK(JJ, 5) QBE_MMK(JJ, 6) QBE_MMK(JJ, 7) QBE_MMK(JJ, 8)
+QBE_MMK(JJ, 2) QBE_MMK(JJ, 3) QBE_MMK(JJ, 4) QBE_MMK(JJ, 5) QBE_MMK(JJ, 6) QBE_MMK(JJ, 7) QBE_MMK(JJ, 8)
   switch (sp.n_sum * 16 + sp.n_ops) {
     QBE_MMKS(2) QBE_MMKS(3) QBE_MMKS(4)
     default:
@@ -1245,228 +1245,228 @@ static int launch_mmk(const Plan& p, const StepProg& sp, const StepLaunch& a, in
 }
 
 static int launch_step(const Plan& p, const StepProg& sp, float2* arena, int64_t G, int64_t s0,
-                     hipStream_t st, int ept = 0, int wg_per_cu = 0) {
-StepLaunch a{};
-const bool sum_u = sp.out_rank >= 0;
-const int r = sum_u ? sp.out_rank : -sp.out_rank;
-a.out = arena + sp.out_base * G;
-a.n_ops = sp.n_ops;
-a.r = r;
-a.sum_u = sum_u ? 1 : 0;
-a.n_sum = sp.n_sum;
-a.lo = std::min(r, kLoBits);
-a.s0 = s0;
-a.G = G;
-for (int i = 0; i < sp.n_ops; ++i) {
-  const StepOp& o = sp.ops[i];
-  if (o.is_input) {
-    a.src[i] = (const float2*)p.d_step_in + o.base;
-    a.gstride[i] = 0;
-    a.smask[i] = o.smask;
-  } else {
-    a.src[i] = arena + o.base * G;
-    a.gstride[i] = int64_t(1) << o.rank;
-    a.smask[i] = 0;
-  }
-  a.mask[i] = o.mask;
-  a.rank[i] = o.rank;
-}
-if (sp.mmk) {
-  // merged launch on MFMA: operand groups A' and B', whole blocks per
-  // workgroup; the side with more private result bits is A' (up to 2^7
-  // rows), the other B' (up to 2^6 columns)
-  MmbLaunch m{};
-  m.out = a.out;
-  m.prec = p.precision;
-  const uint32_t xmask = (1u << r) - 1u;
-  uint32_t xa = 0, xb = 0;
-  for (int i = 0; i < sp.n_ops; ++i) ((sp.mmk_side >> i) & 1u ? xb : xa) |= a.mask[i] & xmask;
-  uint32_t pa = xa & ~xb, pb = xb & ~xa;
-  uint32_t side_b = sp.mmk_side;
-  if (__builtin_popcount(pb) > __builtin_popcount(pa)) {
-    side_b = ~side_b & ((1u << sp.n_ops) - 1u);
-    std::swap(pa, pb);
-  }
-  m.MB = std::min(__builtin_popcount(pa), kMmbMaxM);
-  m.NB = std::min(__builtin_popcount(pb), kMmbMaxN);
-  for (int k = 0; k < m.MB; ++k) {
-    m.bm |= pa & (~pa + 1u);
-    pa &= pa - 1u;
-  }
-  for (int k = 0; k < m.NB; ++k) {
-    m.bn |= pb & (~pb + 1u);
-    pb &= pb - 1u;
-  }
-  MmbFactor fa[kMmbBig], fb[kMmbBig];
-  int na = 0, nbf = 0;
+                       hipStream_t st, int ept = 0, int wg_per_cu = 0) {
+  StepLaunch a{};
+  const bool sum_u = sp.out_rank >= 0;
+  const int r = sum_u ? sp.out_rank : -sp.out_rank;
+  a.out = arena + sp.out_base * G;
+  a.n_ops = sp.n_ops;
+  a.r = r;
+  a.sum_u = sum_u ? 1 : 0;
+  a.n_sum = sp.n_sum;
+  a.lo = std::min(r, kLoBits);
+  a.s0 = s0;
+  a.G = G;
   for (int i = 0; i < sp.n_ops; ++i) {
-    MmbFactor f{};
-    f.src = a.src[i];
-    f.gs = a.gstride[i];
-    f.sm = a.smask[i];
-    f.rk = a.rank[i];
-    f.mk = a.mask[i];
-    for (int t = 0; t < sp.n_sum && t < 4; ++t) {
-      const uint32_t bit = 1u << (r + t);
-      f.kw[t] = (a.mask[i] & bit) ? 1u << __builtin_popcount(a.mask[i] & (bit - 1u)) : 0u;
-    }
-    if (!(a.mask[i] & (m.bm | m.bn))) {
-      m.kf[m.n_kf++] = f;
-    } else if (na + nbf == kMmbBig) {
-      return launch_mmk(p, sp, a, r, G, s0, st, wg_per_cu);
-    } else if ((side_b >> i) & 1u) {
-      fb[nbf++] = f;
+    const StepOp& o = sp.ops[i];
+    if (o.is_input) {
+      a.src[i] = (const float2*)p.d_step_in + o.base;
+      a.gstride[i] = 0;
+      a.smask[i] = o.smask;
     } else {
-      fa[na++] = f;
+      a.src[i] = arena + o.base * G;
+      a.gstride[i] = int64_t(1) << o.rank;
+      a.smask[i] = 0;
     }
+    a.mask[i] = o.mask;
+    a.rank[i] = o.rank;
   }
-  for (int i = 0; i < na; ++i) m.big[i] = fa[i];
-  for (int i = 0; i < nbf; ++i) m.big[na + i] = fb[i];
-  if (m.MB < 4 || m.NB < 4 || sp.n_sum < 2 || sp.n_sum > 4 || na < 1 || nbf < 1)
-    return launch_mmk(p, sp, a, r, G, s0, st, wg_per_cu);
-  m.rest = xmask & ~m.bm & ~m.bn;
-  m.rest_bits = __builtin_popcount(m.rest);
-  m.r = r;
-  m.s0 = s0;
-  m.n_blocks = G << m.rest_bits;
-  if (wg_per_cu <= 0) wg_per_cu = sp.wg_per_cu > 0 ? sp.wg_per_cu : 4;
-  int64_t grid = std::max<int64_t>(1, std::min<int64_t>(m.n_blocks, (int64_t)n_cus() * wg_per_cu));
-  m.per_wg = (m.n_blocks + grid - 1) / grid;
-  grid = (m.n_blocks + m.per_wg - 1) / m.per_wg;
+  if (sp.mmk) {
+    // merged launch on MFMA: operand groups A' and B', whole blocks per
+    // workgroup; the side with more private result bits is A' (up to 2^7
+    // rows), the other B' (up to 2^6 columns)
+    MmbLaunch m{};
+    m.out = a.out;
+    m.prec = p.precision;
+    const uint32_t xmask = (1u << r) - 1u;
+    uint32_t xa = 0, xb = 0;
+    for (int i = 0; i < sp.n_ops; ++i) ((sp.mmk_side >> i) & 1u ? xb : xa) |= a.mask[i] & xmask;
+    uint32_t pa = xa & ~xb, pb = xb & ~xa;
+    uint32_t side_b = sp.mmk_side;
+    if (__builtin_popcount(pb) > __builtin_popcount(pa)) {
+      side_b = ~side_b & ((1u << sp.n_ops) - 1u);
+      std::swap(pa, pb);
+    }
+    m.MB = std::min(__builtin_popcount(pa), kMmbMaxM);
+    m.NB = std::min(__builtin_popcount(pb), kMmbMaxN);
+    for (int k = 0; k < m.MB; ++k) {
+      m.bm |= pa & (~pa + 1u);
+      pa &= pa - 1u;
+    }
+    for (int k = 0; k < m.NB; ++k) {
+      m.bn |= pb & (~pb + 1u);
+      pb &= pb - 1u;
+    }
+    MmbFactor fa[kMmbBig], fb[kMmbBig];
+    int na = 0, nbf = 0;
+    for (int i = 0; i < sp.n_ops; ++i) {
+      MmbFactor f{};
+      f.src = a.src[i];
+      f.gs = a.gstride[i];
+      f.sm = a.smask[i];
+      f.rk = a.rank[i];
+      f.mk = a.mask[i];
+      for (int t = 0; t < sp.n_sum && t < 4; ++t) {
+        const uint32_t bit = 1u << (r + t);
+        f.kw[t] = (a.mask[i] & bit) ? 1u << __builtin_popcount(a.mask[i] & (bit - 1u)) : 0u;
+      }
+      if (!(a.mask[i] & (m.bm | m.bn))) {
+        m.kf[m.n_kf++] = f;
+      } else if (na + nbf == kMmbBig) {
+        return launch_mmk(p, sp, a, r, G, s0, st, wg_per_cu);
+      } else if ((side_b >> i) & 1u) {
+        fb[nbf++] = f;
+      } else {
+        fa[na++] = f;
+      }
+    }
+    for (int i = 0; i < na; ++i) m.big[i] = fa[i];
+    for (int i = 0; i < nbf; ++i) m.big[na + i] = fb[i];
+    if (m.MB < 4 || m.NB < 4 || sp.n_sum < 2 || sp.n_sum > 4 || na < 1 || nbf < 1)
+      return launch_mmk(p, sp, a, r, G, s0, st, wg_per_cu);
+    m.rest = xmask & ~m.bm & ~m.bn;
+    m.rest_bits = __builtin_popcount(m.rest);
+    m.r = r;
+    m.s0 = s0;
+    m.n_blocks = G << m.rest_bits;
+    if (wg_per_cu <= 0) wg_per_cu = sp.wg_per_cu > 0 ? sp.wg_per_cu : 4;
+    int64_t grid = std::max<int64_t>(1, std::min<int64_t>(m.n_blocks, (int64_t)n_cus() * wg_per_cu));
+    m.per_wg = (m.n_blocks + grid - 1) / grid;
+    grid = (m.n_blocks + m.per_wg - 1) / m.per_wg;
 #define QBE_MMB(JJ, A, B)                                                     \
-case (JJ * 4 + A) * 4 + B:                                                  \
-  mmb_kernel<JJ, A, B><<<(int)grid, kBlock, 0, st>>>(m);                    \
-  break;
+  case (JJ * 4 + A) * 4 + B:                                                  \
+    mmb_kernel<JJ, A, B><<<(int)grid, kBlock, 0, st>>>(m);                    \
+    break;
 #define QBE_MMBS(JJ) QBE_MMB(JJ, 1, 1) QBE_MMB(JJ, 1, 2) QBE_MMB(JJ, 2, 1) QBE_MMB(JJ, 2, 2) QBE_MMB(JJ, 1, 3) QBE_MMB(JJ, 3, 1)
-  switch ((sp.n_sum * 4 + na) * 4 + nbf) {
-    QBE_MMBS(2) QBE_MMBS(3) QBE_MMBS(4)
-    default:
-      set_error("merged MFMA launch with an unsupported summed-variable or factor count");
-      return QBE_ERR_INTERNAL;
-  }
+    switch ((sp.n_sum * 4 + na) * 4 + nbf) {
+      QBE_MMBS(2) QBE_MMBS(3) QBE_MMBS(4)
+      default:
+        set_error("merged MFMA launch with an unsupported summed-variable or factor count");
+        return QBE_ERR_INTERNAL;
+    }
 #undef QBE_MMBS
 #undef QBE_MMB
-  QBE_HIP(hipGetLastError());
-  return QBE_OK;
-}
-if (sp.mm_a >= 0 && sum_u && r >= 8) {
-  MmLaunch m{};
-  m.out = a.out;
-  const int idx[2] = {sp.mm_a, sp.mm_b};
-  for (int j = 0; j < 2; ++j) {
-    m.src[j] = a.src[idx[j]];
-    m.gs[j] = a.gstride[idx[j]];
-    m.sm[j] = a.smask[idx[j]];
-    m.rk[j] = a.rank[idx[j]];
-    m.mk[j] = a.mask[idx[j]];
+    QBE_HIP(hipGetLastError());
+    return QBE_OK;
   }
-  for (int i = 0; i < sp.n_ops; ++i) {
-    if (i == sp.mm_a || i == sp.mm_b) continue;
-    m.usrc[m.n_u] = a.src[i];
-    m.ugs[m.n_u] = a.gstride[i];
-    m.usm[m.n_u] = a.smask[i];
-    ++m.n_u;
+  if (sp.mm_a >= 0 && sum_u && r >= 8) {
+    MmLaunch m{};
+    m.out = a.out;
+    const int idx[2] = {sp.mm_a, sp.mm_b};
+    for (int j = 0; j < 2; ++j) {
+      m.src[j] = a.src[idx[j]];
+      m.gs[j] = a.gstride[idx[j]];
+      m.sm[j] = a.smask[idx[j]];
+      m.rk[j] = a.rank[idx[j]];
+      m.mk[j] = a.mask[idx[j]];
+    }
+    for (int i = 0; i < sp.n_ops; ++i) {
+      if (i == sp.mm_a || i == sp.mm_b) continue;
+      m.usrc[m.n_u] = a.src[i];
+      m.ugs[m.n_u] = a.gstride[i];
+      m.usm[m.n_u] = a.smask[i];
+      ++m.n_u;
+    }
+    const uint32_t xmask = (1u << r) - 1u;
+    uint32_t oa = m.mk[0] & xmask & ~m.mk[1], ob = m.mk[1] & xmask & ~m.mk[0];
+    for (int k = 0; k < 4; ++k) {
+      m.mtile |= oa & (~oa + 1u);
+      oa &= oa - 1u;
+      m.ntile |= ob & (~ob + 1u);
+      ob &= ob - 1u;
+    }
+    m.rest = xmask & ~m.mtile & ~m.ntile;
+    m.r = r;
+    m.s0 = s0;
+    m.G = G;
+    m.n_tiles = G << (r - 8);
+    if (wg_per_cu <= 0) wg_per_cu = sp.wg_per_cu > 0 ? sp.wg_per_cu : 8;
+    const int64_t want = (m.n_tiles + 3) / 4;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)n_cus() * wg_per_cu));
+    if (p.precision == QBE_PREC_BF16X3)
+      mm_kernel<QBE_PREC_BF16X3><<<grid, kBlock, 0, st>>>(m);
+    else if (p.precision == QBE_PREC_BF16X6)
+      mm_kernel<QBE_PREC_BF16X6><<<grid, kBlock, 0, st>>>(m);
+    else
+      mm_kernel<QBE_PREC_FP32><<<grid, kBlock, 0, st>>>(m);
+    QBE_HIP(hipGetLastError());
+    return QBE_OK;
   }
-  const uint32_t xmask = (1u << r) - 1u;
-  uint32_t oa = m.mk[0] & xmask & ~m.mk[1], ob = m.mk[1] & xmask & ~m.mk[0];
-  for (int k = 0; k < 4; ++k) {
-    m.mtile |= oa & (~oa + 1u);
-    oa &= oa - 1u;
-    m.ntile |= ob & (~ob + 1u);
-    ob &= ob - 1u;
-  }
-  m.rest = xmask & ~m.mtile & ~m.ntile;
-  m.r = r;
-  m.s0 = s0;
-  m.G = G;
-  m.n_tiles = G << (r - 8);
-  if (wg_per_cu <= 0) wg_per_cu = sp.wg_per_cu > 0 ? sp.wg_per_cu : 8;
-  const int64_t want = (m.n_tiles + 3) / 4;
-  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)n_cus() * wg_per_cu));
-  if (p.precision == QBE_PREC_BF16X3)
-    mm_kernel<QBE_PREC_BF16X3><<<grid, kBlock, 0, st>>>(m);
-  else if (p.precision == QBE_PREC_BF16X6)
-    mm_kernel<QBE_PREC_BF16X6><<<grid, kBlock, 0, st>>>(m);
-  else
-    mm_kernel<QBE_PREC_FP32><<<grid, kBlock, 0, st>>>(m);
-  QBE_HIP(hipGetLastError());
-  return QBE_OK;
-}
-if (sp.n_sum > 1) {
-  if (sp.n_sum > 4) {
-    set_error("merged launch with more than four summed variables");
-    return QBE_ERR_INTERNAL;
-  }
-  const uint32_t xmask = (1u << r) - 1u;
-  for (int i = 0; i < sp.n_ops; ++i) {
-    if (a.rank[i] > 28) {
-      set_error("merged launch operand above 2^28 entries");
+  if (sp.n_sum > 1) {
+    if (sp.n_sum > 4) {
+      set_error("merged launch with more than four summed variables");
       return QBE_ERR_INTERNAL;
     }
-    // summed variables sit above the operand's x bits, in union order;
-    // the kernel's bit b of u is union bit r + sum_bit[b]
-    const uint32_t um = a.mask[i] >> r;
-    const int xc = __builtin_popcount(a.mask[i] & xmask);
-    a.uhold[i] = 0;
-    for (int b = 0; b < sp.n_sum; ++b) a.uhold[i] |= ((um >> sp.sum_bit[b]) & 1u) << b;
-    for (int b = 0; b < 4; ++b) {
-      a.uw[i][b] = 0;
-      if (b >= sp.n_sum || !((um >> sp.sum_bit[b]) & 1u)) continue;
-      // the operand's summed bits sit above its x bits in union order:
-      // union bit r + sum_bit[b] is its bit xc + (held summed bits below it)
-      const int below = __builtin_popcount(um & ((1u << sp.sum_bit[b]) - 1u));
-      a.uw[i][b] = (1u << (xc + below)) * 8u;
+    const uint32_t xmask = (1u << r) - 1u;
+    for (int i = 0; i < sp.n_ops; ++i) {
+      if (a.rank[i] > 28) {
+        set_error("merged launch operand above 2^28 entries");
+        return QBE_ERR_INTERNAL;
+      }
+      // summed variables sit above the operand's x bits, in union order;
+      // the kernel's bit b of u is union bit r + sum_bit[b]
+      const uint32_t um = a.mask[i] >> r;
+      const int xc = __builtin_popcount(a.mask[i] & xmask);
+      a.uhold[i] = 0;
+      for (int b = 0; b < sp.n_sum; ++b) a.uhold[i] |= ((um >> sp.sum_bit[b]) & 1u) << b;
+      for (int b = 0; b < 4; ++b) {
+        a.uw[i][b] = 0;
+        if (b >= sp.n_sum || !((um >> sp.sum_bit[b]) & 1u)) continue;
+        // the operand's summed bits sit above its x bits in union order:
+        // union bit r + sum_bit[b] is its bit xc + (held summed bits below it)
+        const int below = __builtin_popcount(um & ((1u << sp.sum_bit[b]) - 1u));
+        a.uw[i][b] = (1u << (xc + below)) * 8u;
+      }
     }
   }
-}
-if (wg_per_cu <= 0) wg_per_cu = sp.wg_per_cu > 0 ? sp.wg_per_cu : 16;
-if (r < kLoBits) {
-  // several whole slices per tile
-  a.n_tiles = (G + (kBlock >> r) - 1) / (kBlock >> r);
-  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(a.n_tiles, (int64_t)n_cus() * wg_per_cu));
+  if (wg_per_cu <= 0) wg_per_cu = sp.wg_per_cu > 0 ? sp.wg_per_cu : 16;
+  if (r < kLoBits) {
+    // several whole slices per tile
+    a.n_tiles = (G + (kBlock >> r) - 1) / (kBlock >> r);
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(a.n_tiles, (int64_t)n_cus() * wg_per_cu));
 #define QBE_SMALL(KK)                                                         \
-case KK:                                                                    \
-  if (sp.n_sum > 1)                                                         \
-    msum_small_kernel<KK><<<grid, kBlock, 0, st>>>(a);                      \
-  else                                                                      \
-    step_small_kernel<KK><<<grid, kBlock, 0, st>>>(a);                      \
-  break;
-  switch (sp.n_ops) {
-    QBE_SMALL(1) QBE_SMALL(2) QBE_SMALL(3) QBE_SMALL(4) QBE_SMALL(5) QBE_SMALL(6) QBE_SMALL(7)
-    QBE_SMALL(8)
+  case KK:                                                                    \
+    if (sp.n_sum > 1)                                                         \
+      msum_small_kernel<KK><<<grid, kBlock, 0, st>>>(a);                      \
+    else                                                                      \
+      step_small_kernel<KK><<<grid, kBlock, 0, st>>>(a);                      \
+    break;
+    switch (sp.n_ops) {
+      QBE_SMALL(1) QBE_SMALL(2) QBE_SMALL(3) QBE_SMALL(4) QBE_SMALL(5) QBE_SMALL(6) QBE_SMALL(7)
+      QBE_SMALL(8)
+      default:
+        set_error("per-step launch with an unsupported operand count");
+        return QBE_ERR_INTERNAL;
+    }
+#undef QBE_SMALL
+    QBE_HIP(hipGetLastError());
+    return QBE_OK;
+  }
+  const int hib = r - kLoBits;
+  a.n_tiles = G << hib;
+  if (ept <= 0) ept = sp.ept > 0 ? sp.ept : 1;
+  // a super-tile's EPT tiles share the slice: EPT divides 2^hib
+  while (ept > 1 && (int64_t(1) << hib) % ept != 0) ept >>= 1;
+  const int64_t want = a.n_tiles / ept;
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)n_cus() * wg_per_cu));
+#define QBE_CASE(KK, EE)                                                      \
+  case KK * 16 + EE:                                                          \
+    if (sp.n_sum > 1)                                                         \
+      msum_kernel<KK, EE><<<grid, kBlock, 0, st>>>(a);                        \
+    else                                                                      \
+      step_kernel<KK, EE><<<grid, kBlock, 0, st>>>(a);                        \
+    break;
+#define QBE_KS(KK) QBE_CASE(KK, 1) QBE_CASE(KK, 2) QBE_CASE(KK, 4)
+  switch (sp.n_ops * 16 + ept) {
+    QBE_KS(1) QBE_KS(2) QBE_KS(3) QBE_KS(4) QBE_KS(5) QBE_KS(6) QBE_KS(7) QBE_KS(8)
     default:
-      set_error("per-step launch with an unsupported operand count");
+      set_error("per-step launch with an unsupported operand count or tile factor");
       return QBE_ERR_INTERNAL;
   }
-#undef QBE_SMALL
-  QBE_HIP(hipGetLastError());
-  return QBE_OK;
-}
-const int hib = r - kLoBits;
-a.n_tiles = G << hib;
-if (ept <= 0) ept = sp.ept > 0 ? sp.ept : 1;
-// a super-tile's EPT tiles share the slice: EPT divides 2^hib
-while (ept > 1 && (int64_t(1) << hib) % ept != 0) ept >>= 1;
-const int64_t want = a.n_tiles / ept;
-const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)n_cus() * wg_per_cu));
-#define QBE_CASE(KK, EE)                                                      \
-case KK * 16 + EE:                                                          \
-  if (sp.n_sum > 1)                                                         \
-    msum_kernel<KK, EE><<<grid, kBlock, 0, st>>>(a);                        \
-  else                                                                      \
-    step_kernel<KK, EE><<<grid, kBlock, 0, st>>>(a);                        \
-  break;
-#define QBE_KS(KK) QBE_CASE(KK, 1) QBE_CASE(KK, 2) QBE_CASE(KK, 4)
-switch (sp.n_ops * 16 + ept) {
-  QBE_KS(1) QBE_KS(2) QBE_KS(3) QBE_KS(4) QBE_KS(5) QBE_KS(6) QBE_KS(7) QBE_KS(8)
-  default:
-    set_error("per-step launch with an unsupported operand count or tile factor");
-    return QBE_ERR_INTERNAL;
-}
 #undef QBE_KS
 #undef QBE_CASE
-QBE_HIP(hipGetLastError());
-return QBE_OK;
+  QBE_HIP(hipGetLastError());
+  return QBE_OK;
 }
 
 static int launch_group(const Plan& p, int g, float2* arena, int64_t G, int64_t s0, hipStream_t st) {
