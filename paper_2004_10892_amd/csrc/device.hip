@@ -745,10 +745,11 @@ __global__ __launch_bounds__(kBlock) void mmk_kernel(MmkLaunch a) {
 
 // Merged two-group products as whole-block GEMMs.  A block is one slice and
 // one value of the result bits outside the block bits: 2^MB (A'-private) x
-// 2^NB (B'-private) result entries of T = 2^J terms each.  Workgroup b takes
-// blocks [b * per_wg, (b + 1) * per_wg) in sequence, so that neighbouring
-// blocks -- neighbouring entries of the factors -- are read by one compute
-// unit.  Per block: the factors that hold no block bit (their value depends
+// 2^NB (B'-private) result entries of T = 2^J terms each.  Workgroups take
+// blocks in steps of the grid, numbered so that the workgroups of one XCD
+// take consecutive blocks at each step: neighbouring blocks -- neighbouring
+// entries of the factors -- are read at the same time behind one L2.  Per
+// block: the factors that hold no block bit (their value depends
 // on the term and the block only) multiply into one value per term; A'[k][m]
 // and B'[k][n] (the products of each group's other factors, A' times the
 // per-term value) are staged in LDS, every load of a factor in flight at
@@ -761,6 +762,8 @@ __global__ __launch_bounds__(kBlock) void mmk_kernel(MmkLaunch a) {
 // weights.  LDS rows are padded by 16 entries so that the four term groups
 // of an MFMA operand read fall in different banks.
 constexpr int kMmbMaxM = 7, kMmbMaxN = 6, kMmbPad = 16, kMmbBig = 4;
+// XCDs of the chip (workgroups are dealt to them round robin)
+constexpr uint32_t kXcds = 8;
 // entries a thread stages per block: 2^(J + MB) / 256 <= 2^(4 + 7 - 8) of
 // A', 2^(J + NB) / 256 <= 2^(4 + 6 - 8) of B'
 constexpr int kMmbStageA = 8, kMmbStageB = 4;
@@ -783,7 +786,7 @@ struct MmbLaunch {
   uint32_t bm, bn;         // block bits of A' and B'
   uint32_t rest;           // the other result bits (fixed per block)
   int32_t r, MB, NB, rest_bits;
-  int64_t s0, n_blocks, per_wg;
+  int64_t s0, n_blocks;
 };
 
 __device__ __forceinline__ uint32_t lowest_bits(uint32_t m, int n) {
@@ -839,8 +842,14 @@ __global__ __launch_bounds__(kBlock) void mmb_kernel(MmbLaunch a) {
   for (int i = 0; i < NA + NBF; ++i)
     part[i] = pext32(i >= NA ? pdep32((uint32_t)nb, a.bn) : pdep32((uint32_t)ma, a.bm), a.big[i].mk);
   const int tiles_m = Mn >> 4, n_tiles = tiles_m * (Nn >> 4);
-  const int64_t b_end = std::min<int64_t>((int64_t)(blockIdx.x + 1) * a.per_wg, a.n_blocks);
-  for (int64_t blk = (int64_t)blockIdx.x * a.per_wg; blk < b_end; ++blk) {
+  // workgroups are dealt to the XCDs (each with its own L2) round robin:
+  // renumber them so that one XCD's workgroups hold consecutive numbers;
+  // step i takes block number + i * grid, so that neighbouring blocks, whose
+  // factor entries share cache lines, run at the same time behind one L2
+  const uint32_t n_wg = gridDim.x, per_xcd = n_wg / kXcds;
+  const uint32_t wnum = blockIdx.x < per_xcd * kXcds ? (blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds
+                                                     : blockIdx.x;
+  for (int64_t blk = wnum; blk < a.n_blocks; blk += n_wg) {
     const int64_t g = blk >> a.rest_bits;
     const uint32_t xt = pdep32((uint32_t)(blk & ((int64_t(1) << a.rest_bits) - 1)), a.rest);
     const uint32_t sl = (uint32_t)(a.s0 + g);
@@ -1330,9 +1339,7 @@ static int launch_step(const Plan& p, const StepProg& sp, float2* arena, int64_t
     m.s0 = s0;
     m.n_blocks = G << m.rest_bits;
     if (wg_per_cu <= 0) wg_per_cu = sp.wg_per_cu > 0 ? sp.wg_per_cu : 4;
-    int64_t grid = std::max<int64_t>(1, std::min<int64_t>(m.n_blocks, (int64_t)n_cus() * wg_per_cu));
-    m.per_wg = (m.n_blocks + grid - 1) / grid;
-    grid = (m.n_blocks + m.per_wg - 1) / m.per_wg;
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(m.n_blocks, (int64_t)n_cus() * wg_per_cu));
 #define QBE_MMB(JJ, A, B)                                                     \
   case (JJ * 4 + A) * 4 + B:                                                  \
     mmb_kernel<JJ, A, B><<<(int)grid, kBlock, 0, st>>>(m);                    \
