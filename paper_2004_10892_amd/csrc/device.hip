@@ -16,8 +16,13 @@
 //   step_small_kernel  the same two for results of fewer than 8 variables
 //   msum_small_kernel  (several slices per tile).
 //   mm_kernel          outer-product buckets on MFMA (FP32 or split BF16).
-//   mmk_kernel         merged two-group products on MFMA, the contraction
-//                      running over all summed variables.
+//   mmb_kernel         merged two-group products as whole-block GEMMs on
+//                      MFMA, the contraction running over all summed
+//                      variables (A', B' staged in LDS once per block).
+//   mmk_kernel         the same products as independent 16 x 16 tiles (for
+//                      factor counts the block kernel does not take).
+//   group_kernel,      the small launches of one dependency level (of one
+//   wide_group_kernel  plan, or of all per-step instances of a batch).
 //   finalize_kernel    per-slice product of the rank-0 results, in FP64.
 //   reduce_kernel      deterministic FP64 sum of per-slice values (Eq. 4).
 #include "device_common.hpp"
