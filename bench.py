@@ -41,14 +41,26 @@ def log(*a):
 FUSED_SOURCES = ("fused.hip", "fused_format.hpp", "device_common.hpp")
 
 
-def fused_source_digest():
-    """SHA-256 over the sources the fused kernel is compiled from."""
+def source_digest(names):
+    """SHA-256 over the given sources under the package's csrc/."""
     import hashlib
     h = hashlib.sha256()
-    for name in FUSED_SOURCES:
+    for name in names:
         with open(os.path.join(ROOT, "paper_2004_10892_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
+
+
+def fused_source_digest():
+    """SHA-256 over the sources the fused kernel is compiled from."""
+    return source_digest(FUSED_SOURCES)
+
+
+# permute_kernel on the 2^28-entry tensor: FETCH_SIZE and WRITE_SIZE per
+# dispatch (KiB, median of five) scaled by the device copy's calibration
+PERMUTE_SOURCES = ("permute.hip", "device_common.hpp")
+PERMUTE_TRAFFIC = {"bytes": int(round((1048617.125 * 2.000 + 2097234.0 * 1.000) * 1024)),
+                   "sources_sha256": "bc3e876746629b38794d4c483059e78eaf0fba2d97ef9a1f5deedcc9600cd450"}
 
 
 def fused_traffic():
@@ -339,9 +351,13 @@ def bench_permute(torch, qbe, ctx, steps, r=28):
     return {"workload": f"permute_r{r}_complex64", "ms": ev, "GB_per_s": gbs, "copy_ms": copy_ev,
             "copy_GB_per_s": nbytes / (copy_ev * 1e-3) / 1e9, "sampled_exact": bool(np.array_equal(got, want)),
             "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                         "frac": gbs / HBM_PEAK_GBS,
+                         "traffic": PERMUTE_TRAFFIC["bytes"] if r == 28 and source_digest(PERMUTE_SOURCES) ==
+                         PERMUTE_TRAFFIC["sources_sha256"] else None,
+                         "algorithmic_bytes": nbytes,
                          "copy_peak": copy_peak_gbs(torch), "frac_vs_copy": gbs / copy_peak_gbs(torch),
-                         "note": "algorithmic bytes = read + write of the tensor once"}}
+                         "note": "algorithmic bytes = read + write of the tensor once; traffic: FETCH_SIZE and "
+                                 "WRITE_SIZE counters per dispatch with the copy calibration"}}
 
 
 def bench_learned(torch, qbe, ctx, labels=20000, epochs=20, hbm_gbs=None):
