@@ -35,3 +35,10 @@ def test_cpu_baseline_modes():
     best = max(r["modes"].values(), key=lambda m: m["value"])
     assert r["value"] == best["value"] and r["cores"] == best["cores"]
     json.dumps(r)
+
+
+def test_permute_traffic_matches_the_sources():
+    import bench
+    assert bench.source_digest(bench.PERMUTE_SOURCES) == bench.PERMUTE_TRAFFIC["sources_sha256"], \
+        "permute kernel sources changed: re-take its FETCH_SIZE / WRITE_SIZE counters"
+    assert bench.PERMUTE_TRAFFIC["bytes"] > 2 * (1 << 31)
