@@ -66,6 +66,9 @@ struct StepLaunch {
   // And the bits of u the operand holds.
   uint32_t uw[kMaxOps][4];
   uint32_t uhold[kMaxOps];
+  // Tiling (r >= kLoBits): the x bits the lane supplies (eight) and the bits
+  // that tell a super-tile's EPT tiles apart.
+  uint32_t lb, eb;
 };
 
 // Global-memory views of addresses carried as integers (a generic pointer
@@ -83,6 +86,16 @@ __device__ __forceinline__ float2 ld_sv(uint64_t base, uint32_t byte_off) {
 __device__ __forceinline__ void st_sv(uint64_t base, uint32_t byte_off, float2 v) {
   *(__attribute__((address_space(1))) gf32x2*)((gbytep)base + byte_off) = gf32x2{v.x, v.y};
 }
+typedef float gf32x4 __attribute__((ext_vector_type(4)));
+// Two consecutive complex64 entries.
+__device__ __forceinline__ void ld_sv2(uint64_t base, uint32_t byte_off, float2& a, float2& b) {
+  const gf32x4 v = *(const __attribute__((address_space(1))) gf32x4*)((gcbytep)base + byte_off);
+  a = make_float2(v.x, v.y);
+  b = make_float2(v.z, v.w);
+}
+__device__ __forceinline__ void st_sv2(uint64_t base, uint32_t byte_off, float2 a, float2 b) {
+  *(__attribute__((address_space(1))) gf32x4*)((gbytep)base + byte_off) = gf32x4{a.x, a.y, b.x, b.y};
+}
 
 // A 64-bit wave-uniform value held by lane k.
 __device__ __forceinline__ uint64_t lane64(uint64_t v, int k) {
@@ -91,56 +104,69 @@ __device__ __forceinline__ uint64_t lane64(uint64_t v, int k) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+// Scatter the low bits of v to the set bits of m, lowest first.
+__device__ __forceinline__ uint32_t pdep32(uint32_t v, uint32_t m) {
+  uint32_t r = 0;
+  int k = 0;
+  while (m) {
+    const int b = __builtin_ctz(m);
+    r |= ((v >> k) & 1u) << b;
+    ++k;
+    m &= m - 1;
+  }
+  return r;
+}
+
 // Tiling of step_kernel and msum_kernel (r >= kLoBits).  A tile is 256
-// consecutive result entries of one slice: the lane supplies x_lo (the low 8
-// bits of x), the tile the slice g and x_hi.  A super-tile is EPT tiles that
-// differ only in the lowest bits of x_hi (EPT divides 2^hib); the block takes
-// super-tiles q = blockIdx.x + j * gridDim.x.  An operand's entry offset is
-// linear over disjoint bit sets, so it splits into a per-lane part (x_lo and
-// the sub-tile bits, fixed for the kernel) and a per-super-tile part (slice
-// and the rest of x_hi).  The per-super-tile addresses of 64 super-tiles at a
-// time are worked out in vector code, lane l taking the l-th of them, and the
-// tile loop reads them back with readlane: the per-tile index work is off
-// the scalar unit.
+// result entries of one slice: the lane supplies eight bits of x (lb; the
+// low eight by default), and a super-tile is EPT tiles told apart by the
+// bits eb (by default the next lowest; x bit 0 in msum_pair_kernel).  The
+// block takes super-tiles q = blockIdx.x + j * gridDim.x; the super-tile
+// fixes the slice g and the remaining x bits.  An operand's entry offset is
+// linear over disjoint bit sets, so it splits into a per-lane part (lane and
+// tile bits, fixed for the kernel) and a per-super-tile part (slice and the
+// rest of x).  The per-super-tile addresses of 64 super-tiles at a time are
+// worked out in vector code, lane l taking the l-th of them, and the tile
+// loop reads them back with readlane: the per-tile index work is off the
+// scalar unit.
 template <int K, int EPT>
 struct TileSetup {
-  uint32_t lofs[EPT][K];  // per-lane byte offsets
-  uint32_t hi_mask[K];    // x_hi bits of each operand
-  int lo_cnt[K];          // operand bits below x_hi
-  int hib;
+  uint32_t lofs[EPT][K];  // per-lane byte offsets of the operands' entries
+  uint32_t oofs[EPT];     // per-lane byte offsets of the result entries
+  uint32_t rmask;         // x bits fixed by the super-tile
+  int hib;                // their count
   int64_t n_super;
 
-  __device__ __forceinline__ TileSetup(const StepLaunch& a, uint32_t x_lo) {
-    hib = a.r - kLoBits;
+  __device__ __forceinline__ TileSetup(const StepLaunch& a, uint32_t tid) {
+    rmask = ((1u << a.r) - 1u) & ~a.lb & ~a.eb;
+    hib = __builtin_popcount(rmask);
     n_super = a.n_tiles / EPT;
+    const uint32_t xl = pdep32(tid, a.lb);
 #pragma unroll
-    for (int i = 0; i < K; ++i) {
-      const uint32_t m = a.mask[i];
-      const uint32_t lp = pext32(x_lo, m & (kBlock - 1));
-      lo_cnt[i] = __builtin_popcount(m & (kBlock - 1));
-      const uint32_t hm = (m >> kLoBits) & ((1u << hib) - 1u);
-      hi_mask[i] = hm;
+    for (int e = 0; e < EPT; ++e) {
+      const uint32_t xe = xl | pdep32((uint32_t)e, a.eb);
+      oofs[e] = xe * 8u;
 #pragma unroll
-      for (int e = 0; e < EPT; ++e) lofs[e][i] = (lp + (pext32((uint32_t)e, hm) << lo_cnt[i])) * 8u;
+      for (int i = 0; i < K; ++i) lofs[e][i] = pext32(xe, a.mask[i]) * 8u;
     }
   }
 
-  // Lane l: operand base addresses and the result address (entry x_lo = 0
-  // of the first tile) of the block's super-tile q0 + l * gridDim.x.  Lanes
-  // past the end compute addresses that are never used.
+  // Lane l: operand base addresses and the result address (the super-tile's
+  // entry with lane and tile bits 0) of the block's super-tile
+  // q0 + l * gridDim.x.  Lanes past the end compute addresses that are never
+  // used.
   __device__ __forceinline__ void decode(const StepLaunch& a, int64_t q0, int lane, uint64_t (&pl)[K],
                                          uint64_t& ol) const {
-    const int64_t tl = (q0 + (int64_t)lane * gridDim.x) * EPT;
-    const int64_t g = tl >> hib;
-    const uint32_t xl = (uint32_t)(tl & ((int64_t(1) << hib) - 1));
+    const int64_t sq = q0 + (int64_t)lane * gridDim.x;
+    const int64_t g = sq >> hib;
+    const uint32_t xr = pdep32((uint32_t)(sq & ((int64_t(1) << hib) - 1)), rmask);
     const uint32_t s = (uint32_t)(a.s0 + g);
 #pragma unroll
     for (int i = 0; i < K; ++i) {
       const uint32_t sp = a.gstride[i] != 0 ? 0u : pext32(s, a.smask[i]) << a.rank[i];
-      const uint32_t off = sp + (pext32(xl, hi_mask[i]) << lo_cnt[i]);
-      pl[i] = (uint64_t)(a.src[i] + g * a.gstride[i] + off);
+      pl[i] = (uint64_t)(a.src[i] + g * a.gstride[i] + sp + pext32(xr, a.mask[i]));
     }
-    ol = (uint64_t)(a.out + (g << a.r) + ((int64_t)xl << kLoBits));
+    ol = (uint64_t)(a.out + (g << a.r) + xr);
   }
 
   // super-tiles of this block from q0 on that one decode covers
@@ -189,7 +215,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch a) {
           acc.x += u1.x;
           acc.y += u1.y;
         }
-        st_sv(o, (uint32_t)((e << kLoBits) + tid) * 8u, acc);
+        st_sv(o, ts.oofs[e], acc);
       }
     }
   }
@@ -277,7 +303,91 @@ __global__ __launch_bounds__(kBlock) void msum_kernel(StepLaunch a) {
       }
       const uint64_t o = lane64(ol, jj);
 #pragma unroll
-      for (int e = 0; e < EPT; ++e) st_sv(o, (uint32_t)((e << kLoBits) + tid) * 8u, acc[e]);
+      for (int e = 0; e < EPT; ++e) st_sv(o, ts.oofs[e], acc[e]);
+    }
+  }
+}
+
+// msum_kernel with two tiles per thread that differ in x bit 0 (the lane
+// supplies bits 1-8): an operand holding bit 0 -- the first NP operands, as
+// the host orders them -- has its two entries side by side and is read with
+// one 16-byte load; the others have the same entry for both tiles and are
+// read once.  Results are written in 16-byte pairs.  Every load and store
+// instruction thus serves two result entries.
+template <int K, int NP>
+__global__ __launch_bounds__(kBlock) void msum_pair_kernel(StepLaunch a) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const TileSetup<K, 2> ts(a, (uint32_t)tid);
+  const int nu = 1 << a.n_sum;
+  for (int64_t q0 = blockIdx.x; q0 < ts.n_super; q0 += 64 * (int64_t)gridDim.x) {
+    uint64_t pl[K], ol;
+    ts.decode(a, q0, lane, pl, ol);
+    const int n_here = ts.count(q0);
+    for (int jj = 0; jj < n_here; ++jj) {
+      uint64_t b[K];
+#pragma unroll
+      for (int i = 0; i < K; ++i) b[i] = lane64(pl[i], jj);
+      float2 acc[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+      // four terms per trip over the two lowest summed bits, as in msum_kernel
+      for (int u0 = 0; u0 < nu; u0 += 4) {
+        float2 v[4][2][K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+          const uint32_t c = a.uhold[i] & 3u;
+          const uint32_t ob = ((u0 & 4) ? a.uw[i][2] : 0u) + ((u0 & 8) ? a.uw[i][3] : 0u);
+#pragma unroll
+          for (int du = 0; du < 4; ++du)
+            if (((uint32_t)du & ~c) == 0u) {
+              const uint32_t off = ob + ((du & 1) ? a.uw[i][0] : 0u) + ((du & 2) ? a.uw[i][1] : 0u);
+              const uint64_t bu = b[i] + off;
+              if (i < NP) {
+                ld_sv2(bu, ts.lofs[0][i], v[du][0][i], v[du][1][i]);
+              } else {
+                v[du][0][i] = ld_sv(bu, ts.lofs[0][i]);
+                v[du][1][i] = v[du][0][i];
+              }
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        float2 cm[2], pr[4][2];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          cm[e] = make_float2(1.f, 0.f);
+#pragma unroll
+          for (int du = 0; du < 4; ++du) pr[du][e] = make_float2(1.f, 0.f);
+        }
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+          const uint32_t c = a.uhold[i] & 3u;
+          if (c == 0u) {
+#pragma unroll
+            for (int e = 0; e < 2; ++e) cm[e] = cmul(cm[e], v[0][e][i]);
+          } else if (c == 1u) {
+#pragma unroll
+            for (int du = 0; du < 4; ++du)
+#pragma unroll
+              for (int e = 0; e < 2; ++e) pr[du][e] = cmul(pr[du][e], v[du & 1][e][i]);
+          } else if (c == 2u) {
+#pragma unroll
+            for (int du = 0; du < 4; ++du)
+#pragma unroll
+              for (int e = 0; e < 2; ++e) pr[du][e] = cmul(pr[du][e], v[du & 2][e][i]);
+          } else {
+#pragma unroll
+            for (int du = 0; du < 4; ++du)
+#pragma unroll
+              for (int e = 0; e < 2; ++e) pr[du][e] = cmul(pr[du][e], v[du][e][i]);
+          }
+        }
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const float2 t = make_float2(pr[0][e].x + pr[1][e].x + pr[2][e].x + pr[3][e].x,
+                                       pr[0][e].y + pr[1][e].y + pr[2][e].y + pr[3][e].y);
+          const float2 q = cmul(cm[e], t);
+          acc[e] = make_float2(acc[e].x + q.x, acc[e].y + q.y);
+        }
+      }
+      st_sv2(lane64(ol, jj), ts.oofs[0], acc[0], acc[1]);
     }
   }
 }
@@ -478,17 +588,6 @@ __global__ __launch_bounds__(kBlock) void wide_group_kernel(WideArgs a) {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef short shortx4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ uint32_t pdep32(uint32_t v, uint32_t m) {
-  uint32_t r = 0;
-  int k = 0;
-  while (m) {
-    const int b = __builtin_ctz(m);
-    r |= ((v >> k) & 1u) << b;
-    ++k;
-    m &= m - 1;
-  }
-  return r;
-}
 
 // Round-to-nearest-even conversion to bfloat16 (finite inputs).
 __device__ __forceinline__ uint32_t bf16_bits(float f) {
@@ -1459,6 +1558,50 @@ static int launch_step(const Plan& p, const StepProg& sp, float2* arena, int64_t
   if (ept <= 0) ept = sp.ept > 0 ? sp.ept : 1;
   // a super-tile's EPT tiles share the slice: EPT divides 2^hib
   while (ept > 1 && (int64_t(1) << hib) % ept != 0) ept >>= 1;
+  a.lb = (1u << kLoBits) - 1u;
+  a.eb = (uint32_t)(ept - 1) << kLoBits;
+  if (sp.n_sum > 1 && ept == 2) {
+    // paired tiles (msum_pair_kernel): x bit 0 tells them apart, the lane
+    // supplies bits 1-8; the operands holding bit 0 go first
+    a.eb = 1u;
+    a.lb = ((1u << kLoBits) - 1u) << 1;
+    StepLaunch b = a;
+    int np = 0;
+    for (int i = 0; i < sp.n_ops; ++i) np += (a.mask[i] & 1u) ? 1 : 0;
+    int at = 0;
+    for (int pass = 0; pass < 2; ++pass)
+      for (int i = 0; i < sp.n_ops; ++i) {
+        if (((a.mask[i] & 1u) != 0) != (pass == 0)) continue;
+        b.src[at] = a.src[i];
+        b.gstride[at] = a.gstride[i];
+        b.mask[at] = a.mask[i];
+        b.smask[at] = a.smask[i];
+        b.rank[at] = a.rank[i];
+        b.uhold[at] = a.uhold[i];
+        for (int t = 0; t < 4; ++t) b.uw[at][t] = a.uw[i][t];
+        ++at;
+      }
+    const int64_t want = a.n_tiles / 2;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)n_cus() * wg_per_cu));
+#define QBE_PAIR(KK, NN)                                                      \
+  case KK * 16 + NN:                                                          \
+    msum_pair_kernel<KK, NN><<<grid, kBlock, 0, st>>>(b);                     \
+    break;
+    switch (sp.n_ops * 16 + np) {
+      QBE_PAIR(2, 0) QBE_PAIR(2, 1) QBE_PAIR(2, 2) QBE_PAIR(3, 0) QBE_PAIR(3, 1) QBE_PAIR(3, 2) QBE_PAIR(3, 3)
+      QBE_PAIR(4, 0) QBE_PAIR(4, 1) QBE_PAIR(4, 2) QBE_PAIR(4, 3) QBE_PAIR(4, 4) QBE_PAIR(5, 0) QBE_PAIR(5, 1)
+      QBE_PAIR(5, 2) QBE_PAIR(5, 3) QBE_PAIR(5, 4) QBE_PAIR(5, 5) QBE_PAIR(6, 0) QBE_PAIR(6, 1) QBE_PAIR(6, 2)
+      QBE_PAIR(6, 3) QBE_PAIR(6, 4) QBE_PAIR(6, 5) QBE_PAIR(6, 6) QBE_PAIR(7, 0) QBE_PAIR(7, 1) QBE_PAIR(7, 2)
+      QBE_PAIR(7, 3) QBE_PAIR(7, 4) QBE_PAIR(7, 5) QBE_PAIR(7, 6) QBE_PAIR(7, 7) QBE_PAIR(8, 0) QBE_PAIR(8, 1)
+      QBE_PAIR(8, 2) QBE_PAIR(8, 3) QBE_PAIR(8, 4) QBE_PAIR(8, 5) QBE_PAIR(8, 6) QBE_PAIR(8, 7) QBE_PAIR(8, 8)
+      default:
+        set_error("paired merged launch with an unsupported operand count");
+        return QBE_ERR_INTERNAL;
+    }
+#undef QBE_PAIR
+    QBE_HIP(hipGetLastError());
+    return QBE_OK;
+  }
   const int64_t want = a.n_tiles / ept;
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)n_cus() * wg_per_cu));
 #define QBE_CASE(KK, EE)                                                      \
