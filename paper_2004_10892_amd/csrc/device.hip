@@ -308,6 +308,59 @@ __global__ __launch_bounds__(kBlock) void msum_kernel(StepLaunch a) {
   }
 }
 
+// step_kernel with two tiles per thread that differ in x bit 0, paired as
+// in msum_pair_kernel: the first NP operands hold bit 0 (one 16-byte load
+// for both tiles), the others are read once for both.
+template <int K, int NP>
+__global__ __launch_bounds__(kBlock) void step_pair_kernel(StepLaunch a) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int r = a.r;
+  const TileSetup<K, 2> ts(a, (uint32_t)tid);
+  uint32_t ustep[K];  // bytes from an operand's u = 0 entry to its u = 1 entry
+#pragma unroll
+  for (int i = 0; i < K; ++i)
+    ustep[i] = (a.sum_u && ((a.mask[i] >> r) & 1u)) ? (1u << (a.rank[i] - 1)) * 8u : 0u;
+  for (int64_t q0 = blockIdx.x; q0 < ts.n_super; q0 += 64 * (int64_t)gridDim.x) {
+    uint64_t pl[K], ol;
+    ts.decode(a, q0, lane, pl, ol);
+    const int n_here = ts.count(q0);
+    for (int jj = 0; jj < n_here; ++jj) {
+      float2 v0[2][K], v1[2][K];
+#pragma unroll
+      for (int i = 0; i < K; ++i) {
+        const uint64_t b = lane64(pl[i], jj), b1 = b + ustep[i];
+        if (i < NP) {
+          ld_sv2(b, ts.lofs[0][i], v0[0][i], v0[1][i]);
+          if (a.sum_u) ld_sv2(b1, ts.lofs[0][i], v1[0][i], v1[1][i]);
+        } else {
+          v0[0][i] = ld_sv(b, ts.lofs[0][i]);
+          v0[1][i] = v0[0][i];
+          if (a.sum_u) {
+            v1[0][i] = ld_sv(b1, ts.lofs[0][i]);
+            v1[1][i] = v1[0][i];
+          }
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      float2 acc[2];
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        acc[e] = v0[e][0];
+#pragma unroll
+        for (int i = 1; i < K; ++i) acc[e] = cmul(acc[e], v0[e][i]);
+        if (a.sum_u) {
+          float2 u1 = v1[e][0];
+#pragma unroll
+          for (int i = 1; i < K; ++i) u1 = cmul(u1, v1[e][i]);
+          acc[e].x += u1.x;
+          acc[e].y += u1.y;
+        }
+      }
+      st_sv2(lane64(ol, jj), ts.oofs[0], acc[0], acc[1]);
+    }
+  }
+}
+
 // msum_kernel with two tiles per thread that differ in x bit 0 (the lane
 // supplies bits 1-8): an operand holding bit 0 -- the first NP operands, as
 // the host orders them -- has its two entries side by side and is read with
@@ -1503,6 +1556,24 @@ static int launch_step(const Plan& p, const StepProg& sp, float2* arena, int64_t
     QBE_HIP(hipGetLastError());
     return QBE_OK;
   }
+  // VALU kernels: operands holding x bit 0 first (the plan's order for
+  // whole launches; partial products are ordered here), so that every tile
+  // shape, paired or not, multiplies in the same order
+  {
+    StepLaunch b = a;
+    int at = 0;
+    for (int pass = 0; pass < 2; ++pass)
+      for (int i = 0; i < sp.n_ops; ++i) {
+        if (((a.mask[i] & 1u) != 0) != (pass == 0)) continue;
+        b.src[at] = a.src[i];
+        b.gstride[at] = a.gstride[i];
+        b.mask[at] = a.mask[i];
+        b.smask[at] = a.smask[i];
+        b.rank[at] = a.rank[i];
+        ++at;
+      }
+    a = b;
+  }
   if (sp.n_sum > 1) {
     if (sp.n_sum > 4) {
       set_error("merged launch with more than four summed variables");
@@ -1560,34 +1631,25 @@ static int launch_step(const Plan& p, const StepProg& sp, float2* arena, int64_t
   while (ept > 1 && (int64_t(1) << hib) % ept != 0) ept >>= 1;
   a.lb = (1u << kLoBits) - 1u;
   a.eb = (uint32_t)(ept - 1) << kLoBits;
-  if (sp.n_sum > 1 && ept == 2) {
-    // paired tiles (msum_pair_kernel): x bit 0 tells them apart, the lane
-    // supplies bits 1-8; the operands holding bit 0 go first
+  if (ept == 2) {
+    // paired tiles (msum_pair_kernel, step_pair_kernel): x bit 0 tells them
+    // apart, the lane supplies bits 1-8; the operands holding bit 0 go first
     a.eb = 1u;
     a.lb = ((1u << kLoBits) - 1u) << 1;
-    StepLaunch b = a;
+    const StepLaunch& b = a;
     int np = 0;
     for (int i = 0; i < sp.n_ops; ++i) np += (a.mask[i] & 1u) ? 1 : 0;
-    int at = 0;
-    for (int pass = 0; pass < 2; ++pass)
-      for (int i = 0; i < sp.n_ops; ++i) {
-        if (((a.mask[i] & 1u) != 0) != (pass == 0)) continue;
-        b.src[at] = a.src[i];
-        b.gstride[at] = a.gstride[i];
-        b.mask[at] = a.mask[i];
-        b.smask[at] = a.smask[i];
-        b.rank[at] = a.rank[i];
-        b.uhold[at] = a.uhold[i];
-        for (int t = 0; t < 4; ++t) b.uw[at][t] = a.uw[i][t];
-        ++at;
-      }
     const int64_t want = a.n_tiles / 2;
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)n_cus() * wg_per_cu));
 #define QBE_PAIR(KK, NN)                                                      \
   case KK * 16 + NN:                                                          \
-    msum_pair_kernel<KK, NN><<<grid, kBlock, 0, st>>>(b);                     \
+    if (sp.n_sum > 1)                                                         \
+      msum_pair_kernel<KK, NN><<<grid, kBlock, 0, st>>>(b);                   \
+    else                                                                      \
+      step_pair_kernel<KK, NN><<<grid, kBlock, 0, st>>>(b);                   \
     break;
     switch (sp.n_ops * 16 + np) {
+      QBE_PAIR(1, 0) QBE_PAIR(1, 1)
       QBE_PAIR(2, 0) QBE_PAIR(2, 1) QBE_PAIR(2, 2) QBE_PAIR(3, 0) QBE_PAIR(3, 1) QBE_PAIR(3, 2) QBE_PAIR(3, 3)
       QBE_PAIR(4, 0) QBE_PAIR(4, 1) QBE_PAIR(4, 2) QBE_PAIR(4, 3) QBE_PAIR(4, 4) QBE_PAIR(5, 0) QBE_PAIR(5, 1)
       QBE_PAIR(5, 2) QBE_PAIR(5, 3) QBE_PAIR(5, 4) QBE_PAIR(5, 5) QBE_PAIR(6, 0) QBE_PAIR(6, 1) QBE_PAIR(6, 2)
