@@ -135,12 +135,30 @@ struct TileSetup {
   uint32_t oofs[EPT];     // per-lane byte offsets of the result entries
   uint32_t rmask;         // x bits fixed by the super-tile
   int hib;                // their count
+  bool dflt;              // the default layout: the super-tile bits are x's top bits
   int64_t n_super;
 
   __device__ __forceinline__ TileSetup(const StepLaunch& a, uint32_t tid) {
     rmask = ((1u << a.r) - 1u) & ~a.lb & ~a.eb;
     hib = __builtin_popcount(rmask);
+    dflt = a.lb == (1u << kLoBits) - 1u && a.eb == (uint32_t)(EPT - 1) << kLoBits;
     n_super = a.n_tiles / EPT;
+    if (dflt) {
+      // the lane's part from the operand's low eight x bits, the tile's from
+      // its next ones
+#pragma unroll
+      for (int i = 0; i < K; ++i) {
+        const uint32_t m = a.mask[i];
+        const uint32_t lp = pext32(tid, m & ((1u << kLoBits) - 1u));
+        const int lc = __builtin_popcount(m & ((1u << kLoBits) - 1u));
+        const uint32_t em = (m >> kLoBits) & (uint32_t)(EPT - 1);
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) lofs[e][i] = (lp + (pext32((uint32_t)e, em) << lc)) * 8u;
+      }
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) oofs[e] = ((uint32_t)(e << kLoBits) + tid) * 8u;
+      return;
+    }
     const uint32_t xl = pdep32(tid, a.lb);
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
@@ -159,12 +177,18 @@ struct TileSetup {
                                          uint64_t& ol) const {
     const int64_t sq = q0 + (int64_t)lane * gridDim.x;
     const int64_t g = sq >> hib;
-    const uint32_t xr = pdep32((uint32_t)(sq & ((int64_t(1) << hib) - 1)), rmask);
+    // default layout: the super-tile bits are x's top bits, so x's part is a
+    // shift and an operand's part the extraction of its top bits only
+    const uint32_t xr = dflt ? (uint32_t)(sq & ((int64_t(1) << hib) - 1)) << (a.r - hib)
+                             : pdep32((uint32_t)(sq & ((int64_t(1) << hib) - 1)), rmask);
     const uint32_t s = (uint32_t)(a.s0 + g);
 #pragma unroll
     for (int i = 0; i < K; ++i) {
       const uint32_t sp = a.gstride[i] != 0 ? 0u : pext32(s, a.smask[i]) << a.rank[i];
-      pl[i] = (uint64_t)(a.src[i] + g * a.gstride[i] + sp + pext32(xr, a.mask[i]));
+      const uint32_t top = a.mask[i] & rmask;
+      const uint32_t xo = dflt ? pext32(xr, top) << __builtin_popcount(a.mask[i] & ~rmask & ((1u << a.r) - 1u))
+                               : pext32(xr, a.mask[i]);
+      pl[i] = (uint64_t)(a.src[i] + g * a.gstride[i] + sp + xo);
     }
     ol = (uint64_t)(a.out + (g << a.r) + xr);
   }
@@ -1556,9 +1580,9 @@ static int launch_step(const Plan& p, const StepProg& sp, float2* arena, int64_t
     QBE_HIP(hipGetLastError());
     return QBE_OK;
   }
-  // VALU kernels: operands holding x bit 0 first (the plan's order for
-  // whole launches; partial products are ordered here), so that every tile
-  // shape, paired or not, multiplies in the same order
+  // VALU kernels: operands holding x bit 0 first (the paired kernels read
+  // them with 16-byte loads and need that order at compile time), so that
+  // every tile shape, paired or not, multiplies in the same order
   {
     StepLaunch b = a;
     int at = 0;
@@ -1626,7 +1650,10 @@ static int launch_step(const Plan& p, const StepProg& sp, float2* arena, int64_t
   }
   const int hib = r - kLoBits;
   a.n_tiles = G << hib;
-  if (ept <= 0) ept = sp.ept > 0 ? sp.ept : 1;
+  // untuned: large merged launches (32 tiles per compute unit or more) in
+  // the paired form (the faster one on every such launch measured), others
+  // one tile per thread
+  if (ept <= 0) ept = sp.ept > 0 ? sp.ept : (sp.n_sum > 1 && a.n_tiles >= 32 * (int64_t)n_cus() ? 2 : 1);
   // a super-tile's EPT tiles share the slice: EPT divides 2^hib
   while (ept > 1 && (int64_t(1) << hib) % ept != 0) ept >>= 1;
   a.lb = (1u << kLoBits) - 1u;

@@ -554,12 +554,6 @@ void compile_plan(Plan& p) {
         }
       }
     }
-    if ((n_sum > 1 && !sp.mmk) || (n_sum == 1 && sp.mm_a < 0))
-      // launches on the VALU kernels: operands holding x bit 0 first (the
-      // paired form reads them with 16-byte loads and needs that order at
-      // compile time; every form multiplies in this order, so all tile
-      // shapes give the same bits)
-      std::stable_partition(ops.begin(), ops.end(), [](const StepOp& o) { return (o.mask & 1u) != 0; });
     const int64_t osz = int64_t(1) << rb;
     out_off[k] = arena.alloc(osz, align_for(osz));
     sp.out_base = out_off[k];
