@@ -13,6 +13,10 @@
 //                      HBM-bound (about 2 flop/B).
 //   msum_kernel        a merged chain of buckets: the same with 2^n_sum >= 4
 //                      terms per result entry, four at a time.
+//   step_pair_kernel,  the same two with two tiles per thread that differ
+//   msum_pair_kernel   in x bit 0: operands holding it are read with one
+//                      16-byte load for both tiles, the others once for both,
+//                      results stored in 16-byte pairs.
 //   step_small_kernel  the same two for results of fewer than 8 variables
 //   msum_small_kernel  (several slices per tile).
 //   mm_kernel          outer-product buckets on MFMA (FP32 or split BF16).
