@@ -70,9 +70,6 @@ struct StepLaunch {
   // And the bits of u the operand holds.
   uint32_t uw[kMaxOps][4];
   uint32_t uhold[kMaxOps];
-  // Tiling (r >= kLoBits): the x bits the lane supplies (eight) and the bits
-  // that tell a super-tile's EPT tiles apart.
-  uint32_t lb, eb;
 };
 
 // Global-memory views of addresses carried as integers (a generic pointer
@@ -122,79 +119,68 @@ __device__ __forceinline__ uint32_t pdep32(uint32_t v, uint32_t m) {
 }
 
 // Tiling of step_kernel and msum_kernel (r >= kLoBits).  A tile is 256
-// result entries of one slice: the lane supplies eight bits of x (lb; the
-// low eight by default), and a super-tile is EPT tiles told apart by the
-// bits eb (by default the next lowest; x bit 0 in msum_pair_kernel).  The
-// block takes super-tiles q = blockIdx.x + j * gridDim.x; the super-tile
-// fixes the slice g and the remaining x bits.  An operand's entry offset is
-// linear over disjoint bit sets, so it splits into a per-lane part (lane and
-// tile bits, fixed for the kernel) and a per-super-tile part (slice and the
-// rest of x).  The per-super-tile addresses of 64 super-tiles at a time are
-// worked out in vector code, lane l taking the l-th of them, and the tile
-// loop reads them back with readlane: the per-tile index work is off the
-// scalar unit.
-template <int K, int EPT>
+// consecutive result entries of one slice: the lane supplies x_lo (the low 8
+// bits of x), the tile the slice g and x_hi.  A super-tile is EPT tiles that
+// differ only in the lowest bits of x_hi (EPT divides 2^hib); the block takes
+// super-tiles q = blockIdx.x + j * gridDim.x.  An operand's entry offset is
+// linear over disjoint bit sets, so it splits into a per-lane part (x_lo and
+// the sub-tile bits, fixed for the kernel) and a per-super-tile part (slice
+// and the rest of x_hi).  The per-super-tile addresses of 64 super-tiles at a
+// time are worked out in vector code, lane l taking the l-th of them, and the
+// tile loop reads them back with readlane: the per-tile index work is off
+// the scalar unit.
+// PAIR (EPT = 2): the two tiles differ in x bit 0 instead and the lane
+// supplies bits 1-8; the super-tile bits are the same.
+template <int K, int EPT, bool PAIR = false>
 struct TileSetup {
-  uint32_t lofs[EPT][K];  // per-lane byte offsets of the operands' entries
-  uint32_t oofs[EPT];     // per-lane byte offsets of the result entries
-  uint32_t rmask;         // x bits fixed by the super-tile
-  int hib;                // their count
-  bool dflt;              // the default layout: the super-tile bits are x's top bits
+  uint32_t lofs[EPT][K];  // per-lane byte offsets
+  uint32_t hi_mask[K];    // x_hi bits of each operand
+  int lo_cnt[K];          // operand bits below x_hi
+  int hib;
   int64_t n_super;
 
-  __device__ __forceinline__ TileSetup(const StepLaunch& a, uint32_t tid) {
-    rmask = ((1u << a.r) - 1u) & ~a.lb & ~a.eb;
-    hib = __builtin_popcount(rmask);
-    dflt = a.lb == (1u << kLoBits) - 1u && a.eb == (uint32_t)(EPT - 1) << kLoBits;
+  __device__ __forceinline__ TileSetup(const StepLaunch& a, uint32_t x_lo) {
+    hib = a.r - kLoBits;
     n_super = a.n_tiles / EPT;
-    if (dflt) {
-      // the lane's part from the operand's low eight x bits, the tile's from
-      // its next ones
+    if (PAIR) {
+      static_assert(!PAIR || EPT == 2, "paired tiles come two at a time");
 #pragma unroll
       for (int i = 0; i < K; ++i) {
-        const uint32_t m = a.mask[i];
-        const uint32_t lp = pext32(tid, m & ((1u << kLoBits) - 1u));
-        const int lc = __builtin_popcount(m & ((1u << kLoBits) - 1u));
-        const uint32_t em = (m >> kLoBits) & (uint32_t)(EPT - 1);
+        hi_mask[i] = (a.mask[i] >> kLoBits) & ((1u << hib) - 1u);
+        lo_cnt[i] = __builtin_popcount(a.mask[i] & (kBlock - 1));
 #pragma unroll
-        for (int e = 0; e < EPT; ++e) lofs[e][i] = (lp + (pext32((uint32_t)e, em) << lc)) * 8u;
+        for (int e = 0; e < EPT; ++e) lofs[e][i] = pext32((x_lo << 1) | (uint32_t)e, a.mask[i] & (2u * kBlock - 1u)) * 8u;
       }
-#pragma unroll
-      for (int e = 0; e < EPT; ++e) oofs[e] = ((uint32_t)(e << kLoBits) + tid) * 8u;
       return;
     }
-    const uint32_t xl = pdep32(tid, a.lb);
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      const uint32_t xe = xl | pdep32((uint32_t)e, a.eb);
-      oofs[e] = xe * 8u;
+    for (int i = 0; i < K; ++i) {
+      const uint32_t m = a.mask[i];
+      const uint32_t lp = pext32(x_lo, m & (kBlock - 1));
+      lo_cnt[i] = __builtin_popcount(m & (kBlock - 1));
+      const uint32_t hm = (m >> kLoBits) & ((1u << hib) - 1u);
+      hi_mask[i] = hm;
 #pragma unroll
-      for (int i = 0; i < K; ++i) lofs[e][i] = pext32(xe, a.mask[i]) * 8u;
+      for (int e = 0; e < EPT; ++e) lofs[e][i] = (lp + (pext32((uint32_t)e, hm) << lo_cnt[i])) * 8u;
     }
   }
 
-  // Lane l: operand base addresses and the result address (the super-tile's
-  // entry with lane and tile bits 0) of the block's super-tile
-  // q0 + l * gridDim.x.  Lanes past the end compute addresses that are never
-  // used.
+  // Lane l: operand base addresses and the result address (entry x_lo = 0
+  // of the first tile) of the block's super-tile q0 + l * gridDim.x.  Lanes
+  // past the end compute addresses that are never used.
   __device__ __forceinline__ void decode(const StepLaunch& a, int64_t q0, int lane, uint64_t (&pl)[K],
                                          uint64_t& ol) const {
-    const int64_t sq = q0 + (int64_t)lane * gridDim.x;
-    const int64_t g = sq >> hib;
-    // default layout: the super-tile bits are x's top bits, so x's part is a
-    // shift and an operand's part the extraction of its top bits only
-    const uint32_t xr = dflt ? (uint32_t)(sq & ((int64_t(1) << hib) - 1)) << (a.r - hib)
-                             : pdep32((uint32_t)(sq & ((int64_t(1) << hib) - 1)), rmask);
+    const int64_t tl = (q0 + (int64_t)lane * gridDim.x) * EPT;
+    const int64_t g = tl >> hib;
+    const uint32_t xl = (uint32_t)(tl & ((int64_t(1) << hib) - 1));
     const uint32_t s = (uint32_t)(a.s0 + g);
 #pragma unroll
     for (int i = 0; i < K; ++i) {
       const uint32_t sp = a.gstride[i] != 0 ? 0u : pext32(s, a.smask[i]) << a.rank[i];
-      const uint32_t top = a.mask[i] & rmask;
-      const uint32_t xo = dflt ? pext32(xr, top) << __builtin_popcount(a.mask[i] & ~rmask & ((1u << a.r) - 1u))
-                               : pext32(xr, a.mask[i]);
-      pl[i] = (uint64_t)(a.src[i] + g * a.gstride[i] + sp + xo);
+      const uint32_t off = sp + (pext32(xl, hi_mask[i]) << lo_cnt[i]);
+      pl[i] = (uint64_t)(a.src[i] + g * a.gstride[i] + off);
     }
-    ol = (uint64_t)(a.out + (g << a.r) + xr);
+    ol = (uint64_t)(a.out + (g << a.r) + ((int64_t)xl << kLoBits));
   }
 
   // super-tiles of this block from q0 on that one decode covers
@@ -243,7 +229,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch a) {
           acc.x += u1.x;
           acc.y += u1.y;
         }
-        st_sv(o, ts.oofs[e], acc);
+        st_sv(o, (uint32_t)((e << kLoBits) + tid) * 8u, acc);
       }
     }
   }
@@ -331,7 +317,7 @@ __global__ __launch_bounds__(kBlock) void msum_kernel(StepLaunch a) {
       }
       const uint64_t o = lane64(ol, jj);
 #pragma unroll
-      for (int e = 0; e < EPT; ++e) st_sv(o, ts.oofs[e], acc[e]);
+      for (int e = 0; e < EPT; ++e) st_sv(o, (uint32_t)((e << kLoBits) + tid) * 8u, acc[e]);
     }
   }
 }
@@ -343,7 +329,7 @@ template <int K, int NP>
 __global__ __launch_bounds__(kBlock) void step_pair_kernel(StepLaunch a) {
   const int tid = threadIdx.x, lane = tid & 63;
   const int r = a.r;
-  const TileSetup<K, 2> ts(a, (uint32_t)tid);
+  const TileSetup<K, 2, true> ts(a, (uint32_t)tid);
   uint32_t ustep[K];  // bytes from an operand's u = 0 entry to its u = 1 entry
 #pragma unroll
   for (int i = 0; i < K; ++i)
@@ -384,7 +370,7 @@ __global__ __launch_bounds__(kBlock) void step_pair_kernel(StepLaunch a) {
           acc[e].y += u1.y;
         }
       }
-      st_sv2(lane64(ol, jj), ts.oofs[0], acc[0], acc[1]);
+      st_sv2(lane64(ol, jj), (uint32_t)tid * 16u, acc[0], acc[1]);
     }
   }
 }
@@ -398,7 +384,7 @@ __global__ __launch_bounds__(kBlock) void step_pair_kernel(StepLaunch a) {
 template <int K, int NP>
 __global__ __launch_bounds__(kBlock) void msum_pair_kernel(StepLaunch a) {
   const int tid = threadIdx.x, lane = tid & 63;
-  const TileSetup<K, 2> ts(a, (uint32_t)tid);
+  const TileSetup<K, 2, true> ts(a, (uint32_t)tid);
   const int nu = 1 << a.n_sum;
   for (int64_t q0 = blockIdx.x; q0 < ts.n_super; q0 += 64 * (int64_t)gridDim.x) {
     uint64_t pl[K], ol;
@@ -468,7 +454,7 @@ __global__ __launch_bounds__(kBlock) void msum_pair_kernel(StepLaunch a) {
           acc[e] = make_float2(acc[e].x + q.x, acc[e].y + q.y);
         }
       }
-      st_sv2(lane64(ol, jj), ts.oofs[0], acc[0], acc[1]);
+      st_sv2(lane64(ol, jj), (uint32_t)tid * 16u, acc[0], acc[1]);
     }
   }
 }
@@ -1660,13 +1646,9 @@ static int launch_step(const Plan& p, const StepProg& sp, float2* arena, int64_t
   if (ept <= 0) ept = sp.ept > 0 ? sp.ept : (sp.n_sum > 1 && a.n_tiles >= 32 * (int64_t)n_cus() ? 2 : 1);
   // a super-tile's EPT tiles share the slice: EPT divides 2^hib
   while (ept > 1 && (int64_t(1) << hib) % ept != 0) ept >>= 1;
-  a.lb = (1u << kLoBits) - 1u;
-  a.eb = (uint32_t)(ept - 1) << kLoBits;
   if (ept == 2) {
     // paired tiles (msum_pair_kernel, step_pair_kernel): x bit 0 tells them
     // apart, the lane supplies bits 1-8; the operands holding bit 0 go first
-    a.eb = 1u;
-    a.lb = ((1u << kLoBits) - 1u) << 1;
     const StepLaunch& b = a;
     int np = 0;
     for (int i = 0; i < sp.n_ops; ++i) np += (a.mask[i] & 1u) ? 1 : 0;
