@@ -166,7 +166,9 @@ class Context:
         _check(_lib.qbe_set_stream(self.handle, _vp(stream.cuda_stream)), "qbe_set_stream")
 
     def close(self):
-        if self.handle:
+        # at interpreter exit the module's globals may already be cleared;
+        # the process is ending then and its device memory goes with it
+        if getattr(self, "handle", None) and _lib is not None:
             _lib.qbe_destroy(self.handle)
             self.handle = None
 
@@ -232,7 +234,7 @@ class Model:
         _check(_lib.qbe_model_set_data(self.handle, data.ctypes.data_as(_f64p)), "qbe_model_set_data")
 
     def close(self):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and _lib is not None:
             _lib.qbe_model_destroy(self.handle)
             self.handle = None
 
@@ -409,7 +411,7 @@ class Plan:
         return torch.empty(int(n), dtype=torch.uint8, device=f"cuda:{self.ctx.device}")
 
     def close(self):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and _lib is not None:
             _lib.qbe_plan_destroy(self.handle)
             self.handle = None
 
@@ -483,7 +485,7 @@ class Batch:
                                              _vp(d_amps.data_ptr())), "qbe_batch_contract_async")
 
     def close(self):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and _lib is not None:
             _lib.qbe_batch_destroy(self.handle)
             self.handle = None
 
@@ -577,7 +579,7 @@ class Gnn:
         return (float(loss[0]), grads) if want_grads else float(loss[0])
 
     def close(self):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and _lib is not None:
             _lib.qbe_gnn_destroy(self.handle)
             self.handle = None
 
