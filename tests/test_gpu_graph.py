@@ -23,7 +23,7 @@ def _capture(torch, ctx, fn):
     return g
 
 
-@pytest.mark.parametrize("form", ["fused", "per_step"])
+@pytest.mark.parametrize("form", ["fused", "per_step", "per_step_tuned"])
 def test_plan_graph_replays_match_eager(form):
     import torch
     import paper_2004_10892_amd as qbe
@@ -32,8 +32,10 @@ def test_plan_graph_replays_match_eager(form):
     ctx = qbe.Context(0)
     qm = qbe.Model.from_circuitgen(circuit_model(random_grid_circuit(5, 5, 16, 1)))
     _, mu, pi, _ = qbe.plan_circuit(qm, m=6)
-    plan = qbe.Plan(qm, pi, mu, ctx=ctx, exec=form)
+    plan = qbe.Plan(qm, pi, mu, ctx=ctx, exec=form.replace("_tuned", ""))
     ws = plan.workspace()
+    if form.endswith("_tuned"):
+        plan.autotune(ws, min_elems=1 << 10)  # tuned launch shapes, as the benchmark captures them
     eager = qbe.qbe_contract(ctx, plan, ws)
     out = torch.zeros(2, dtype=torch.float64, device="cuda")
     g = _capture(torch, ctx, lambda: qbe.qbe_contract_async(ctx, plan, ws, out))
