@@ -27,6 +27,19 @@ def test_library_exports_every_declared_symbol():
     assert qbe.qbe_version() == 1
 
 
+def test_close_is_safe_once_the_library_handle_is_cleared(monkeypatch):
+    # at interpreter exit module globals may be cleared before finalisers
+    # run; close() must then do nothing rather than raise
+    m = qbe.Model.from_circuitgen(circuit_model(random_grid_circuit(3, 3, 4, 0)))
+    assert m.handle
+    monkeypatch.setattr(qbe, "_lib", None)
+    m.close()
+    assert m.handle  # nothing freed without the library
+    monkeypatch.undo()
+    m.close()
+    assert m.handle is None
+
+
 def oracle_plan(mod, m, score="tree_trimming"):
     tv = [v for v, _ in mod.tensors]
     adj = P.simple_graph(mod.n_vars, tv)
