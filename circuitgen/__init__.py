@@ -276,3 +276,18 @@ def random_general_network(seed: int, n_vars: int = 7, n_tensors: int = 7, max_r
         if not any(v in vs for vs, _ in tensors):
             tensors.append(((v,), rng.standard_normal(dims[v]) + 1j * rng.standard_normal(dims[v])))
     return dims, tensors
+
+
+def star_network(n_leaves: int, seed: int, max_phase: float = 0.3) -> Model:
+    """A hub variable 0 joined to leaves 1..n_leaves by one rank-2 tensor
+    each, T_i over (0, i).  Entries are (0.5 + 0.5 u) e^(i phi) with u,
+    phi / max_phase uniform in [0, 1) (numpy default_rng(seed)): no sum
+    cancels.  Eliminating the hub first makes one intermediate over all
+    leaves (rank n_leaves), the largest a network of this size can hold."""
+    rng = np.random.default_rng(seed)
+    tensors = []
+    for i in range(1, n_leaves + 1):
+        mag = 0.5 + 0.5 * rng.random((2, 2))
+        phase = max_phase * rng.random((2, 2))
+        tensors.append(((0, i), (mag * np.exp(1j * phase)).astype(np.complex128)))
+    return Model(n_leaves + 1, tensors)

@@ -176,8 +176,10 @@ struct TileSetup {
     const uint32_t s = (uint32_t)(a.s0 + g);
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-      const uint32_t sp = a.gstride[i] != 0 ? 0u : pext32(s, a.smask[i]) << a.rank[i];
-      const uint32_t off = sp + (pext32(xl, hi_mask[i]) << lo_cnt[i]);
+      // element offsets in 64 bits: an input's copies of a rank-30 tensor
+      // lie more than 2^32 entries apart
+      const uint64_t sp = a.gstride[i] != 0 ? 0ull : (uint64_t)pext32(s, a.smask[i]) << a.rank[i];
+      const uint64_t off = sp + ((uint64_t)pext32(xl, hi_mask[i]) << lo_cnt[i]);
       pl[i] = (uint64_t)(a.src[i] + g * a.gstride[i] + off);
     }
     ol = (uint64_t)(a.out + (g << a.r) + ((int64_t)xl << kLoBits));
@@ -196,10 +198,12 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch a) {
   const int tid = threadIdx.x, lane = tid & 63;
   const int r = a.r;
   const TileSetup<K, EPT> ts(a, (uint32_t)tid);
-  uint32_t ustep[K];  // bytes from an operand's u = 0 entry to its u = 1 entry
+  // bytes from an operand's u = 0 entry to its u = 1 entry: 2^(rank - 1)
+  // entries, 2^32 bytes for a rank-30 operand, so 64 bits
+  uint64_t ustep[K];
 #pragma unroll
   for (int i = 0; i < K; ++i)
-    ustep[i] = (a.sum_u && ((a.mask[i] >> r) & 1u)) ? (1u << (a.rank[i] - 1)) * 8u : 0u;
+    ustep[i] = (a.sum_u && ((a.mask[i] >> r) & 1u)) ? (uint64_t(1) << (a.rank[i] - 1)) * 8u : 0u;
   for (int64_t q0 = blockIdx.x; q0 < ts.n_super; q0 += 64 * (int64_t)gridDim.x) {
     uint64_t pl[K], ol;
     ts.decode(a, q0, lane, pl, ol);
@@ -330,10 +334,12 @@ __global__ __launch_bounds__(kBlock) void step_pair_kernel(StepLaunch a) {
   const int tid = threadIdx.x, lane = tid & 63;
   const int r = a.r;
   const TileSetup<K, 2, true> ts(a, (uint32_t)tid);
-  uint32_t ustep[K];  // bytes from an operand's u = 0 entry to its u = 1 entry
+  // bytes from an operand's u = 0 entry to its u = 1 entry: 2^(rank - 1)
+  // entries, 2^32 bytes for a rank-30 operand, so 64 bits
+  uint64_t ustep[K];
 #pragma unroll
   for (int i = 0; i < K; ++i)
-    ustep[i] = (a.sum_u && ((a.mask[i] >> r) & 1u)) ? (1u << (a.rank[i] - 1)) * 8u : 0u;
+    ustep[i] = (a.sum_u && ((a.mask[i] >> r) & 1u)) ? (uint64_t(1) << (a.rank[i] - 1)) * 8u : 0u;
   for (int64_t q0 = blockIdx.x; q0 < ts.n_super; q0 += 64 * (int64_t)gridDim.x) {
     uint64_t pl[K], ol;
     ts.decode(a, q0, lane, pl, ol);
@@ -864,7 +870,7 @@ __global__ __launch_bounds__(kBlock) void mmk_kernel(MmkLaunch a) {
     uint64_t pl[K];
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-      const uint32_t off = (a.gs[i] ? 0u : pext32(sl, a.sm[i]) << a.rk[i]) + pext32(xtl, a.mk[i]);
+      const uint64_t off = (a.gs[i] ? 0ull : (uint64_t)pext32(sl, a.sm[i]) << a.rk[i]) + pext32(xtl, a.mk[i]);
       pl[i] = (uint64_t)(a.src[i] + (int64_t)gl * a.gs[i] + off);
     }
     const uint64_t obl = (uint64_t)(a.out + (((int64_t)gl << r) | xtl));
@@ -1595,7 +1601,7 @@ static int launch_step(const Plan& p, const StepProg& sp, float2* arena, int64_t
     }
     const uint32_t xmask = (1u << r) - 1u;
     for (int i = 0; i < sp.n_ops; ++i) {
-      if (a.rank[i] > 28) {
+      if (a.rank[i] > kMergedMaxRank) {
         set_error("merged launch operand above 2^28 entries");
         return QBE_ERR_INTERNAL;
       }

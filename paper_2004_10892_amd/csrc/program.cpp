@@ -213,7 +213,7 @@ std::vector<FusedNode> merge_buckets(const Schedule& s, bool merge) {
 // consumer's (a shrinking chain) and of rank kChainMinRank or more is merged
 // into the consumer, so that one launch sums several variables and the
 // absorbed result never goes to device memory.  Up to kChainSumMax summed
-// variables and kMaxOps operands per launch.
+// variables, kMaxOps operands and operands of rank kMergedMaxRank per launch.
 constexpr int kChainMinRank = 12;
 constexpr int kChainSumMax = 4;
 
@@ -241,6 +241,9 @@ std::vector<StepNode> merge_chains(const Schedule& s, bool merge) {
       if (!(op.kind == 'r' && op.id == k)) f.push_back(op);
     f.insert(f.end(), nd[k].factors.begin(), nd[k].factors.end());
     if ((int)f.size() > kMaxOps) continue;
+    bool narrow = true;
+    for (const Operand& op : f) narrow = narrow && (int)op.vars.size() <= kMergedMaxRank;
+    if (!narrow) continue;
     std::vector<int> m = nd[k].members;
     m.insert(m.end(), nd[c].members.begin(), nd[c].members.end());
     nd[c].members = std::move(m);

@@ -76,6 +76,7 @@ std::string check_plan(const Plan& p) {
       if (sum_u && sp.n_sum == 1 && o.rank > 0 && !((o.mask >> r) & 1u) && o.rank > r) return "operand rank";
       if (sp.n_sum > 1 && (o.mask >> r) == 0 && o.rank > 0 && !o.is_input)
         return "merged launch with an intermediate that holds no summed variable";
+      if (sp.n_sum > 1 && o.rank > kMergedMaxRank) return fail("merged launch operand rank", o.rank, kMergedMaxRank);
       if (o.is_input) {
         const int64_t versions = int64_t(1) << __builtin_popcount(o.smask);
         if (o.base < 0 || o.base + (versions << o.rank) > p.step_elems)

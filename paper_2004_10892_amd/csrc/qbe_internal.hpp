@@ -19,6 +19,9 @@ constexpr int kMaxOps = 8;
 constexpr int kBlock = 256;
 // Low index bits handled inside one workgroup tile by the per-step kernel.
 constexpr int kLoBits = 8;
+// Largest operand rank of a launch that sums several variables: the merged
+// kernels carry an operand's per-summed-bit byte offsets in 32 bits.
+constexpr int kMergedMaxRank = 28;
 
 struct Model {
   int n_vars = 0;
