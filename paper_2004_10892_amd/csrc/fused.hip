@@ -55,6 +55,9 @@ static FusedMeta fused_meta(const Plan& p) {
 
 // LDS bytes after the data for the workgroup's control words.
 constexpr int kFusedCtlBytes = 16;
+// Lanes of the in-kernel slice sum: the width of reduce_kernel's tree, so
+// that both sum in one order.
+constexpr int kFusedReduceLanes = 256;
 // Record rows (16-byte groups of words) a lane reads per level, two levels
 // ahead: one half-record of up to 15 operands, or a whole record of up to 7.
 constexpr int kRecRows = kFusedTailRows;
@@ -433,38 +436,39 @@ __global__ __launch_bounds__(kFusedBlock) __attribute__((amdgpu_waves_per_eu(kFu
     }
     __syncthreads();
     if (s_flag) {
-      // last item of this plan: fixed-order FP64 sum of its items (same order
-      // as reduce_kernel), then re-arm the plan's counter for the next launch.
-      // The scratch overwrites LDS; no item of this plan remains.  The values
-      // are visible: every item's release on the counter, thread 0's acquire
-      // fence after reading its last value, then the barrier.
+      // last item of this plan: FP64 sum of its items in reduce_kernel's
+      // order (lane t < 256 adds items t, t + 256, ... in sequence, then a
+      // binary tree over the 256 partials), so that a plan's amplitude has
+      // the same bits whether it is summed here or by reduce_kernel; then
+      // re-arm the plan's counter for the next launch.  The 4 KB of partials
+      // overwrite LDS data (launch_fused sizes LDS for them); no item of this
+      // plan remains.  The values are visible: every item's release on the
+      // counter, thread 0's acquire fence after reading its last value, then
+      // the barrier.
       int64_t b = 0, e = a.n_items;
       if (a.ranges) {
         b = a.ranges[2 * plan];
         e = a.ranges[2 * plan + 1];
       }
       double* sre = reinterpret_cast<double*>(lds4);
-      double* sim = sre + kFusedBlock / 64;
-      double re = 0.0, im = 0.0;
-      for (int64_t i = b + tid; i < e; i += kFusedBlock) {
-        const double2 v = a.out[i];
-        re += v.x;
-        im += v.y;
-      }
-      for (int w = 32; w > 0; w >>= 1) {
-        re += __shfl_down(re, w, 64);
-        im += __shfl_down(im, w, 64);
-      }
-      if ((tid & 63) == 0) {
-        sre[tid >> 6] = re;
-        sim[tid >> 6] = im;
+      double* sim = sre + kFusedReduceLanes;
+      if (tid < kFusedReduceLanes) {
+        double re = 0.0, im = 0.0;
+        for (int64_t i = b + tid; i < e; i += kFusedReduceLanes) {
+          const double2 v = a.out[i];
+          re += v.x;
+          im += v.y;
+        }
+        sre[tid] = re;
+        sim[tid] = im;
       }
       __syncthreads();
-      if (tid == 0) {
-        for (int k = 1; k < kFusedBlock / 64; ++k) {
-          sre[0] += sre[k];
-          sim[0] += sim[k];
+      for (int w = kFusedReduceLanes / 2; w > 0; w >>= 1) {
+        if (tid < w) {
+          sre[tid] += sre[tid + w];
+          sim[tid] += sim[tid + w];
         }
+        __syncthreads();
       }
       if (tid == 0) {
         a.amps[plan] = make_double2(sre[0], sim[0]);
@@ -493,6 +497,8 @@ static int launch_fused(int grid, int lds_bytes, hipStream_t st, FusedArgs a) {
                                 kFusedLdsMax + kFusedCtlBytes));
     attr_set = true;
   }
+  // at least the in-kernel slice sum's partials below the control words
+  lds_bytes = std::max(lds_bytes, kFusedReduceLanes * 16);
   a.lds_ctl = (uint32_t)lds_bytes;
   fused_kernel<<<grid, kFusedBlock, lds_bytes + kFusedCtlBytes, st>>>(a);
   QBE_HIP(hipGetLastError());
