@@ -141,6 +141,37 @@ def _p32(a: np.ndarray):
     return a.ctypes.data_as(_i32p)
 
 
+def _dev_buffer(ctx, t, name: str, dtype=None, min_numel: int = 0):
+    """Device address of a torch tensor handed to the library, after checking
+    that it is a contiguous tensor on the context's device (of `dtype` and
+    at least `min_numel` elements when given): the library writes through
+    the raw address, so a CPU, short or mistyped tensor must not reach it."""
+    import torch
+
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda" or (t.device.index if t.device.index is not None else 0) != ctx.device:
+        raise ValueError(f"{name} must live on cuda:{ctx.device}, not {t.device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, not {t.dtype}")
+    if t.numel() < min_numel:
+        raise ValueError(f"{name} must hold at least {min_numel} elements, not {t.numel()}")
+    return _vp(t.data_ptr())
+
+
+def _workspace(ctx, ws):
+    """(address, bytes) of a device workspace tensor (any dtype)."""
+    return _dev_buffer(ctx, ws, "workspace"), ws.numel() * ws.element_size()
+
+
+def _f64():
+    import torch
+
+    return torch.float64
+
+
 def qbe_version() -> int:
     return int(_lib.qbe_version())
 
@@ -399,8 +430,8 @@ class Plan:
 
     def autotune(self, ws, min_elems: int = 1 << 20):
         """Times the large per-step launches in each tile shape; keeps the best."""
-        _check(_lib.qbe_plan_autotune(self.ctx.handle, self.handle, _vp(ws.data_ptr()), ws.numel(), min_elems),
-               "qbe_plan_autotune")
+        w, nb = _workspace(self.ctx, ws)
+        _check(_lib.qbe_plan_autotune(self.ctx.handle, self.handle, w, nb, min_elems), "qbe_plan_autotune")
 
     def workspace(self, all_slices: bool = True):
         """A device workspace (torch uint8 tensor) of the plan's size."""
@@ -420,8 +451,8 @@ class Plan:
 
 def qbe_contract(ctx: Context, plan: Plan, ws) -> complex:
     out = np.zeros(2)
-    _check(_lib.qbe_contract(ctx.handle, plan.handle, _vp(ws.data_ptr()), ws.numel(),
-                             out.ctypes.data_as(_f64p)), "qbe_contract")
+    w, nb = _workspace(ctx, ws)
+    _check(_lib.qbe_contract(ctx.handle, plan.handle, w, nb, out.ctypes.data_as(_f64p)), "qbe_contract")
     return complex(out[0], out[1])
 
 
@@ -429,15 +460,17 @@ def qbe_contract_slices(ctx: Context, plan: Plan, s_begin: int, s_end: int, ws):
     """Returns (sum over the range, per-slice values as complex128 array)."""
     part = np.zeros(2)
     per = np.zeros(2 * (s_end - s_begin))
-    _check(_lib.qbe_contract_slices(ctx.handle, plan.handle, s_begin, s_end, _vp(ws.data_ptr()), ws.numel(),
+    w, nb = _workspace(ctx, ws)
+    _check(_lib.qbe_contract_slices(ctx.handle, plan.handle, s_begin, s_end, w, nb,
                                     part.ctypes.data_as(_f64p), per.ctypes.data_as(_f64p)), "qbe_contract_slices")
     return complex(part[0], part[1]), per.view(np.complex128).copy()
 
 
 def qbe_contract_async(ctx: Context, plan: Plan, ws, d_out):
     """Enqueues the contraction; d_out is a float64 device tensor of >= 2 entries."""
-    _check(_lib.qbe_contract_async(ctx.handle, plan.handle, _vp(ws.data_ptr()), ws.numel(),
-                                   _vp(d_out.data_ptr())), "qbe_contract_async")
+    w, nb = _workspace(ctx, ws)
+    out = _dev_buffer(ctx, d_out, "d_out", _f64(), 2)
+    _check(_lib.qbe_contract_async(ctx.handle, plan.handle, w, nb, out), "qbe_contract_async")
 
 
 def qbe_contract_batch(ctx: Context, plans: Sequence[Plan], ws=None) -> np.ndarray:
@@ -449,8 +482,9 @@ def qbe_contract_batch(ctx: Context, plans: Sequence[Plan], ws=None) -> np.ndarr
         import torch
         ws = torch.empty(qbe_contract_batch_workspace(ctx, plans), dtype=torch.uint8, device=f"cuda:{ctx.device}")
     amps = np.zeros(2 * len(plans), dtype=np.float64)
-    _check(_lib.qbe_contract_batch(ctx.handle, arr, len(plans), _vp(ws.data_ptr()), ws.numel(),
-                                   amps.ctypes.data_as(_f64p), None), "qbe_contract_batch")
+    w, nb = _workspace(ctx, ws)
+    _check(_lib.qbe_contract_batch(ctx.handle, arr, len(plans), w, nb, amps.ctypes.data_as(_f64p), None),
+           "qbe_contract_batch")
     return amps.view(np.complex128)
 
 
@@ -481,8 +515,10 @@ class Batch:
         return torch.empty(int(self.ws_bytes), dtype=torch.uint8, device=f"cuda:{self.ctx.device}")
 
     def contract_async(self, ws, d_amps):
-        _check(_lib.qbe_batch_contract_async(self.ctx.handle, self.handle, _vp(ws.data_ptr()), ws.numel(),
-                                             _vp(d_amps.data_ptr())), "qbe_batch_contract_async")
+        """Enqueues the batch; d_amps: float64 device tensor of >= 2 * n_plans entries."""
+        w, nb = _workspace(self.ctx, ws)
+        out = _dev_buffer(self.ctx, d_amps, "d_amps", _f64(), 2 * len(self.plans))
+        _check(_lib.qbe_batch_contract_async(self.ctx.handle, self.handle, w, nb, out), "qbe_batch_contract_async")
 
     def close(self):
         if getattr(self, "handle", None) and _lib is not None:
@@ -499,12 +535,13 @@ def qbe_permute(ctx: Context, d_in, d_out, r: int, perm: Sequence[int], batch: i
     tensors of 2^r complex64 entries (d_in, d_out: contiguous device tensors
     of at least batch * 2^r * 8 bytes, not overlapping)."""
     need = int(batch) << int(r) if batch > 0 else 0
+    ptrs = []
     for name, t in (("d_in", d_in), ("d_out", d_out)):
-        if not t.is_contiguous() or t.numel() * t.element_size() < need * 8:
-            raise ValueError(f"{name} must be contiguous with >= {need * 8} bytes")
+        ptrs.append(_dev_buffer(ctx, t, name))
+        if t.numel() * t.element_size() < need * 8:
+            raise ValueError(f"{name} must hold >= {need * 8} bytes")
     p = _i32(perm)
-    _check(_lib.qbe_permute(ctx.handle, _vp(d_in.data_ptr()), _vp(d_out.data_ptr()), int(r), _p32(p),
-                            int(batch)), "qbe_permute")
+    _check(_lib.qbe_permute(ctx.handle, ptrs[0], ptrs[1], int(r), _p32(p), int(batch)), "qbe_permute")
 
 
 # -------------------------------------------------------- learned proposal --
