@@ -1,7 +1,11 @@
 """Writes tests/golden/amplitudes.json from the CPU oracle only.
 
-Run from the repository root:  python tests/golden/make_golden.py
+Run from the repository root:  python tests/golden/make_golden.py [--only batch]
 (takes a few minutes: a 2^25 statevector and 1024 slices of the 7x7 circuit).
+It also writes tests/golden/batch512.json: the oracle's amplitude of every
+instance of the 512-instance batch workload (circuitgen.batch_instances),
+planned by the oracle's own min-fill order and Alg. 2 with the instance's m
+(about a minute; --only batch writes just that file).
 
 Contents per workload: the circuit seed and bitstring, the statevector
 amplitude where the qubit count allows (<= 25), the oracle's per-slice values
@@ -17,7 +21,7 @@ import time
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 
-from circuitgen import WORKLOADS, circuit_model, random_grid_circuit  # noqa: E402
+from circuitgen import WORKLOADS, batch_instances, circuit_model, random_grid_circuit  # noqa: E402
 from oracle import contract as C  # noqa: E402
 from oracle import planner as P  # noqa: E402
 from oracle import statevector as SV  # noqa: E402
@@ -34,7 +38,25 @@ def plan(circ, m):
     return mod, C.bucket_schedule(mod.n_vars, tv, pi, mu), tau
 
 
+def batch_golden():
+    rows_out = []
+    t0 = time.time()
+    for (rows, cols, depth, m, seed) in batch_instances(512):
+        circ = random_grid_circuit(rows, cols, depth, seed)
+        mod, sched, tau = plan(circ, m)
+        total, _ = C.contract(mod.tensors, sched)
+        rows_out.append({"rows": rows, "cols": cols, "depth": depth, "m": m, "seed": seed, "tau": tau,
+                         "bitstring": circ.bitstring, "oracle": [total.real, total.imag]})
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "batch512.json"), "w") as f:
+        f.write('{"instances": [\n' + ",\n".join(json.dumps(r) for r in rows_out) + "\n]}\n")
+    print("batch512", len(rows_out), "%.1fs" % (time.time() - t0), flush=True)
+
+
 def main():
+    if "--only" in sys.argv and sys.argv[sys.argv.index("--only") + 1] == "batch":
+        batch_golden()
+        return
+    batch_golden()
     out = {}
     for name, (rows, cols, depth, m) in WORKLOADS.items():
         t0 = time.time()
