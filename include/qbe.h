@@ -317,6 +317,24 @@ int qbe_contract_slices(qbe_ctx* ctx, const qbe_plan* plan, int64_t s_begin, int
 int qbe_contract_async(qbe_ctx* ctx, const qbe_plan* plan, void* d_workspace, size_t ws_bytes,
                        double* d_amp_out);
 
+/* ------------------------------------------------ allocation-free entry - */
+
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the
+ * contraction of qbe_contract_async with the library's own fixed device
+ * workspace instead of a caller's.  Enqueues all slices on the context's
+ * stream and writes the FP64 amplitude (2 doubles) to device memory
+ * d_amp_out; no allocation, free, copy or synchronisation happens inside.
+ * The workspace is one array of qbe_static_scratch_bytes() bytes per device,
+ * held from the library's first use on that device (qbe_create) until the
+ * process ends, and shared by every call on that device: calls that overlap
+ * on one device (other streams or threads) race on it and must be ordered
+ * by the caller.  QBE_ERR_MEM_CAP (nothing enqueued) when the plan's
+ * stats.ws_bytes_min exceeds that size; other errors as qbe_contract_async. */
+int qbe_contract_static(qbe_ctx* ctx, const qbe_plan* plan, double* d_amp_out);
+/* Bytes of the per-device workspace of qbe_contract_static (64 MiB). */
+size_t qbe_static_scratch_bytes(void);
+
 /* ---------------------------------------------------------------- batch - */
 
 /* A set of independent plans (instances, e.g. circuits of uneven size)

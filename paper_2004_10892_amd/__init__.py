@@ -101,6 +101,8 @@ _SIGS = {
     "qbe_contract": (C.c_int, [_vp, _vp, _vp, C.c_size_t, _f64p]),
     "qbe_contract_slices": (C.c_int, [_vp, _vp, C.c_int64, C.c_int64, _vp, C.c_size_t, _f64p, _f64p]),
     "qbe_contract_async": (C.c_int, [_vp, _vp, _vp, C.c_size_t, _vp]),
+    "qbe_contract_static": (C.c_int, [_vp, _vp, _vp]),
+    "qbe_static_scratch_bytes": (C.c_size_t, []),
     "qbe_gnn_num_params": (C.c_int32, []),
     "qbe_gnn_create": (C.c_int, [_vp, C.c_uint64, C.POINTER(_vp)]),
     "qbe_gnn_destroy": (C.c_int, [_vp]),
@@ -471,6 +473,18 @@ def qbe_contract_async(ctx: Context, plan: Plan, ws, d_out):
     w, nb = _workspace(ctx, ws)
     out = _dev_buffer(ctx, d_out, "d_out", _f64(), 2)
     _check(_lib.qbe_contract_async(ctx.handle, plan.handle, w, nb, out), "qbe_contract_async")
+
+
+def qbe_contract_static(ctx: Context, plan: Plan, d_out):
+    """Enqueues the contraction on the library's fixed per-device workspace
+    (no allocation anywhere); d_out is a float64 device tensor of >= 2
+    entries.  Calls overlapping on one device share that workspace."""
+    out = _dev_buffer(ctx, d_out, "d_out", _f64(), 2)
+    _check(_lib.qbe_contract_static(ctx.handle, plan.handle, out), "qbe_contract_static")
+
+
+def qbe_static_scratch_bytes() -> int:
+    return int(_lib.qbe_static_scratch_bytes())
 
 
 def qbe_contract_batch(ctx: Context, plans: Sequence[Plan], ws=None) -> np.ndarray:

@@ -97,6 +97,8 @@ int qbe_create(qbe_ctx** out, int32_t device, void* hip_stream) {
   QBE_REQUIRE(device >= 0 && device < n, "device index out of range");
   int rc = qbe::dev_set(device);
   if (rc) return rc;
+  rc = qbe::dev_static_scratch_init(device);
+  if (rc) return rc;
   qbe_ctx* c = new qbe_ctx;
   c->device = device;
   c->stream = hip_stream;
@@ -662,6 +664,21 @@ int qbe_contract_async(qbe_ctx* ctx, const qbe_plan* plan, void* d_workspace, si
                            nullptr);
   QBE_GUARD_END
 }
+
+int qbe_contract_static(qbe_ctx* ctx, const qbe_plan* plan, double* d_amp_out) {
+  QBE_GUARD_BEGIN
+  QBE_REQUIRE(ctx && plan && d_amp_out, "NULL argument");
+  QBE_REQUIRE(plan->ctx, "plan was created without a device context");
+  QBE_REQUIRE(plan->p.device == ctx->device, "plan belongs to another device");
+  int rc = qbe::dev_set(ctx->device);
+  if (rc) return rc;
+  rc = qbe::dev_static_scratch_init(ctx->device);  // no-op once qbe_create did it
+  if (rc) return rc;
+  return qbe::dev_contract_static(plan->p, ctx->stream, d_amp_out);
+  QBE_GUARD_END
+}
+
+size_t qbe_static_scratch_bytes(void) { return qbe::kStaticScratchBytes; }
 
 int qbe_contract_slices(qbe_ctx* ctx, const qbe_plan* plan, int64_t s_begin, int64_t s_end,
                         void* d_workspace, size_t ws_bytes, double* partial_out, double* per_slice_out) {

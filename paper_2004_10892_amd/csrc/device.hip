@@ -33,6 +33,8 @@
 
 #include <cstdio>
 #include <cstring>
+#include <mutex>
+#include <string>
 
 namespace qbe {
 
@@ -1836,6 +1838,64 @@ int dev_contract(const Plan& p, void* stream, void* ws, size_t ws_bytes, int64_t
     }
   }
   return launch_reduce(per_slice, nullptr, n, (double2*)d_partial_out, 1, st);
+}
+
+// ------------------------------------------------- allocation-free entry --
+//
+// qbe_contract_static runs dev_contract on this fixed array instead of a
+// caller's workspace.  Each device holds its own copy from the library's
+// first use on it until the process ends; host code reaches it only through
+// the address hipGetSymbolAddress reports on that device (the array's name
+// is a host-side stand-in).  Nothing in it needs clearing: every kernel of
+// the contraction writes a region before any kernel reads it.
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};
+}  // namespace
+
+int dev_static_scratch_init(int device) {
+  if (device < 0 || device >= kScratchDevices) {
+    set_error("device index beyond the static scratch table");
+    return QBE_ERR_INVALID_ARG;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return QBE_OK;
+  int cur = -1;
+  QBE_HIP(hipGetDevice(&cur));
+  if (cur != device) {
+    set_error("static scratch set-up needs its device current");
+    return QBE_ERR_INTERNAL;
+  }
+  void* ptr = nullptr;
+  QBE_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  if (!ptr) {
+    set_error("hipGetSymbolAddress returned no address for the static scratch");
+    return QBE_ERR_HIP;
+  }
+  g_scratch_ptr[device] = ptr;
+  return QBE_OK;
+}
+
+int dev_contract_static(const Plan& p, void* stream, double* d_amp_out) {
+  void* ptr = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (p.device >= 0 && p.device < kScratchDevices) ptr = g_scratch_ptr[p.device];
+  }
+  if (!ptr) {
+    set_error("static scratch is not set up on the plan's device");
+    return QBE_ERR_INTERNAL;
+  }
+  const size_t need = dev_workspace_min(p, p.n_slices);
+  if (need > kStaticScratchBytes) {
+    set_error("plan needs a workspace of " + std::to_string(need) + " bytes, above the static scratch's " +
+              std::to_string(kStaticScratchBytes));
+    return QBE_ERR_MEM_CAP;
+  }
+  return dev_contract(p, stream, ptr, kStaticScratchBytes, 0, p.n_slices, d_amp_out, nullptr);
 }
 
 int launch_reduce(const double2* v, const int64_t* ranges, int64_t n_single, double2* out, int n_blocks,

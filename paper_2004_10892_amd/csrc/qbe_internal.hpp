@@ -224,6 +224,12 @@ void dev_forget_plan(Plan& p);              // clears the device pointers, frees
 int dev_contract(const Plan& p, void* stream, void* ws, size_t ws_bytes, int64_t s_begin,
                  int64_t s_end, double* d_partial_out, double* d_per_slice /*may be null*/);
 size_t dev_workspace_min(const Plan& p, int64_t n_slices_in_call);
+// Allocation-free contraction (qbe_contract_static): a fixed device array of
+// kStaticScratchBytes per device serves as the workspace.  The set-up call
+// looks its address up once per device (with that device current).
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+int dev_static_scratch_init(int device);
+int dev_contract_static(const Plan& p, void* stream, double* d_amp_out);
 size_t dev_workspace_all(const Plan& p);
 int dev_autotune(Plan& p, void* stream, void* ws, size_t ws_bytes, int64_t min_elems);
 int dev_batch_build(Batch& b);

@@ -19,7 +19,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def test_library_exports_every_declared_symbol():
     header = open(os.path.join(ROOT, "include", "qbe.h")).read()
-    declared = set(re.findall(r"^\s*(?:int|int32_t|const char\*)\s+(qbe_\w+)\s*\(", header, re.M))
+    declared = set(re.findall(r"^\s*(?:int|int32_t|size_t|const char\*)\s+(qbe_\w+)\s*\(", header, re.M))
     assert len(declared) >= 20
     for name in declared:
         assert hasattr(qbe._lib, name), name
