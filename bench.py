@@ -1,16 +1,28 @@
 """Benchmark: amplitudes per second of sliced bucket-elimination contraction
 on one MI355X.
 
-Headline workload: a 5x5 grid circuit of depth 16 (seed 1, bitstring from the
-seed), 6 variables sliced by the tree-trimming heuristic (64 slices), one
-amplitude per step.  The chosen form (one persistent fused launch per
-amplitude, issued directly or replayed from a HIP graph, the faster of the
-two) is timed next to the plain FP32 form (one launch per bucket, slices
-batched) and next to the CPU oracle.  Extra lines: a 7x7 depth-24
-circuit with 1024 slices (the HBM-bound per-step kernels) and a batch of 512
-uneven instances.
+Headline workload: a 7x7 grid circuit of depth 24 (49 qubits, seed 0,
+bitstring from the seed), 10 variables sliced (1024 slices), one amplitude
+per step with the plan cached -- the largest of the benchmark configurations
+and the one whose bucket contractions stream through HBM.  Timed forms:
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extra]
+* chosen: the sliced set picked by the learned proposal or by tree-trimming
+  (whichever has fewer exact FLOPs; the heuristic is the fallback), merged
+  bucket chains, grouped small launches, autotuned tiles, all 1024 slices at
+  once, products in FP32 or split-BF16 -- the fastest form whose amplitude is
+  within 1e-5 of the complex128 oracle, issued directly or replayed from a
+  HIP graph;
+* plain FP32: tree-trimming's sliced set, one launch per bucket, FP32.
+
+The line carries MFMA utilisation and memory traffic from hardware counters
+(valid only for the sources and plan they were taken on), a live per-launch
+timing of the chosen plan with the roofline of its dominant kernel, and the
+CPU oracle timed on a bounded sample of the same amplitude's slices.  Extra
+lines: the 5x5 depth-16 circuit (64 slices, LDS-resident fused kernel), a
+batch of 512 uneven instances, 256 bitstrings of one circuit, the stand-alone
+permute, and the learned proposal's evaluation on 8x8 depth-32 circuits.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extra] [--no-cpu]
 Prints one JSON line.
 """
 import argparse
@@ -214,50 +226,271 @@ def cpu_model():
     return "unknown"
 
 
-def bench_hbm(torch, qbe, ctx, steps, precision="fp32"):
-    """7x7 depth-24 circuit, 1024 slices, per-step form: HBM-bound kernels
-    (outer-product buckets on MFMA, in FP32 or split-BF16)."""
-    name = "grid7x7_d24_m10"
-    plan, plan_ms, cfg = build_plan(qbe, ctx, name, "per_step", precision)
-    st = plan.stats()
-    ws = torch.empty(int(st["ws_bytes_all_slices"]), dtype=torch.uint8, device="cuda")
-    out = torch.zeros(2, dtype=torch.float64, device="cuda")
+
+# ------------------------------------------------------------ headline (C3) --
+
+C3 = "grid7x7_d24_m10"
+# Sources that decide the per-step form's kernels and launches: counters
+# taken on other sources describe other code and are not reported.
+STEP_SOURCES = ("device.hip", "device_common.hpp", "qbe_internal.hpp", "program.cpp", "planner.cpp")
+# Hardware counters of one contraction of the headline plan
+# (profiles/step_kernels_grid7x7_d24_m10.md): per precision, summed over the
+# contraction's dispatches.  mfma_busy: SQ_VALU_MFMA_BUSY_CYCLES; capacity:
+# GRBM_GUI_ACTIVE / 8 XCDs x 256 CUs x 4 SIMDs; fetch/write: FETCH_SIZE x
+# 2.000 and WRITE_SIZE x 1.000 bytes (the 256 MiB device-copy calibration);
+# dominant: the same for the dominant kernel's launch.  Keyed by the
+# sources' digest and the plan's sliced set.
+C3_COUNTERS = {"sources_sha256": None, "mu": None}
+
+
+def step_source_digest():
+    return source_digest(STEP_SOURCES)
+
+
+def c3_counters(precision, mu):
+    """The committed counters of the headline plan, or (None, reason)."""
+    if C3_COUNTERS.get("sources_sha256") != step_source_digest():
+        return None, "per-step sources differ from those the counters were taken on"
+    if C3_COUNTERS.get("mu") != list(mu):
+        return None, "sliced set differs from the one the counters were taken on"
+    rec = C3_COUNTERS.get(precision)
+    if not rec:
+        return None, f"no counters taken for {precision}"
+    return rec, None
+
+
+def c3_model(qbe):
+    from circuitgen import circuit_model, random_grid_circuit
+    r, c, d, m = 7, 7, 24, 10
+    return qbe.Model.from_circuitgen(circuit_model(random_grid_circuit(r, c, d, SEEDS[C3]))), m
+
+
+def train_net(qbe, ctx, labels=20000, epochs=20):
+    """The learned proposal's network trained on the device: ~20k exact-cost
+    labels from seeded 6x6..8x8 circuits of depth 16..32."""
+    from circuitgen import SplitMix64, circuit_model, random_grid_circuit
+    from paper_2004_10892_amd import learned as L
+    rng = SplitMix64(2020)
     t0 = time.perf_counter()
-    plan.autotune(ws)
-    tune_ms = (time.perf_counter() - t0) * 1e3
-    cfg["autotune_ms"] = tune_ms
+    samples, n_labels, i = [], 0, 0
+    while n_labels < labels and i < 400:
+        r, c, d = 6 + rng.next() % 3, 6 + rng.next() % 3, 16 + rng.next() % 17
+        qm = qbe.Model.from_circuitgen(circuit_model(random_grid_circuit(r, c, d, 2000 + i)))
+        ss, n = L.make_dataset([qm], seed=i)
+        samples += ss
+        n_labels += n
+        i += 1
+    t1 = time.perf_counter()
+    net = qbe.Gnn(ctx, seed=7)
+    hist = L.train(net, samples, epochs=epochs, batch=8, lr=2e-3)
+    t2 = time.perf_counter()
+    return net, {"labels": n_labels, "train_circuits": i, "label_s": t1 - t0, "train_s": t2 - t1,
+                 "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1]}
+
+
+def slicing_candidates(qbe, qm, m, net):
+    """Tree-trimming's sliced set and, with a network, the learned one, with
+    their exact costs and planning times."""
+    from paper_2004_10892_amd import learned as L
+    t0 = time.perf_counter()
+    order = qbe.qbe_order_min_fill(qm)
+    mu_t, pi_t, tau_t = qbe.qbe_slice(qm, order, m)
+    t1 = time.perf_counter()
+    cands = {"tree_trimming": (mu_t, pi_t, (t1 - t0) * 1e3)}
+    if net is not None:
+        t2 = time.perf_counter()
+        mu_l, pi_l = L.learned_slice(qm, order, net, m=m)
+        t3 = time.perf_counter()
+        cands["learned"] = (mu_l, pi_l, (t1 - t0 + t3 - t2) * 1e3)
+    info = {}
+    for k, (mu, pi, ms) in cands.items():
+        c = qbe.qbe_schedule_cost(qm, pi, mu)
+        info[k] = {"mu": mu, "width": c["width"], "log2_total_flops": L.total_log2_flops(c),
+                   "log2_total_bytes": L.total_log2_flops({"flops_per_slice": c["bytes_per_slice"],
+                                                           "n_slices": c["n_slices"]}),
+                   "peak_bytes_per_slice": c["peak_bytes_per_slice"], "planning_ms": ms}
+    return cands, info
+
+
+def time_plan(torch, qbe, ctx, plan, steps, warmup):
+    """One amplitude per step, issued directly and replayed from a HIP
+    graph (both must give the same bits)."""
+    ws = plan.workspace()
+    out = torch.zeros(2, dtype=torch.float64, device="cuda")
     fn = lambda: qbe.qbe_contract_async(ctx, plan, ws, out)  # noqa: E731
-    wall_d, ev_d = timed(torch, fn, steps, 1)
+    wall_d, ev_d = timed(torch, fn, steps, warmup)
     got = complex(*out.cpu().numpy())
-    # the same launches replayed from a HIP graph (no host launch gaps
-    # between the ~100 dispatches); both forms must give the same bits
     g = graph_of(torch, qbe, ctx, fn)
     out.fill_(float("nan"))
-    wall_g, ev_g = timed(torch, g.replay, steps, 1)
+    wall_g, ev_g = timed(torch, g.replay, steps, warmup)
     got_g = complex(*out.cpu().numpy())
     if got_g != got:
-        raise SystemExit(f"{name} {precision}: graph replay {got_g} differs from direct launch {got}")
+        raise SystemExit(f"graph replay {got_g} differs from direct launch {got}")
     forms = {"direct": {"ms_per_amplitude": ev_d, "wall_ms_per_amplitude": wall_d},
              "graph": {"ms_per_amplitude": ev_g, "wall_ms_per_amplitude": wall_g}}
-    ev = min(ev_d, ev_g)
-    want = golden(name)
-    bytes_amp = st["step_bytes_per_slice"] * plan.n_slices
-    sched_bytes = st["bytes_per_slice"] * plan.n_slices
-    flops_amp = st["flops_per_slice"] * plan.n_slices
-    gbs = bytes_amp / (ev * 1e-3) / 1e9
-    return {"workload": name, "form": "per_step", "precision": precision, "mfma_launches": st["n_mfma_steps"],
-            "merged_launches": st["n_merged_steps"], "launches": st["n_launches"], "buckets": st["n_steps"],
-            "ms_per_amplitude": ev, "amplitudes_per_s": 1e3 / ev, "forms": forms,
-            "rel_err": abs(got - want) / abs(want), "planning_ms": plan_ms, "config": cfg,
-            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": gbs / HBM_PEAK_GBS, "traffic": None,
-                         "copy_peak": copy_peak_gbs(torch), "frac_vs_copy": gbs / copy_peak_gbs(torch),
-                         "algorithmic_bytes": bytes_amp, "schedule_bytes": sched_bytes,
-                         "algorithmic_flops": flops_amp,
-                         "note": "all per-step launches of one amplitude; algorithmic bytes = every launch "
-                                 "reads each operand once and writes its result once (merged chains keep "
-                                 "their intermediates on chip); schedule_bytes = the same count for one "
-                                 "launch per bucket (cost model)"}}
+    return forms, got, ws
+
+
+def launch_profile(plan, ws, reps):
+    """Per-launch HIP-event timing of whole contractions (qbe_plan_profile),
+    averaged over reps; with each launch's algorithmic bytes and FLOPs."""
+    import numpy as np
+    info = plan.launches()
+    ms = np.mean([plan.profile(ws) for _ in range(reps)], axis=0)
+    n = plan.n_slices
+    rows = []
+    for i, (li, t) in enumerate(zip(info, ms)):
+        rows.append(dict(li, index=i, ms=float(t), bytes=li["bytes_per_slice"] * n, flops=li["flops_per_slice"] * n))
+    return rows
+
+
+def bench_headline(torch, qbe, ctx, steps, warmup, net):
+    qm, m = c3_model(qbe)
+    want = golden(C3)
+    cands, plans_info = slicing_candidates(qbe, qm, m, net)
+    # the sliced set: each candidate's FP32 plan autotuned and timed, the
+    # faster one kept (exact FLOPs do not rank plans for this executor:
+    # merged launches and their kernels decide the time)
+    for k, (mu_k, pi_k, _) in cands.items():
+        plan_k = qbe.Plan(qm, pi_k, mu_k, ctx=ctx, exec="per_step")
+        ws_k = plan_k.workspace()
+        plan_k.autotune(ws_k)
+        out_k = torch.zeros(2, dtype=torch.float64, device="cuda")
+        _, ev_k = timed(torch, lambda: qbe.qbe_contract_async(ctx, plan_k, ws_k, out_k), max(3, steps // 2), 1)
+        plans_info[k]["fp32_ms_per_amplitude"] = ev_k
+        plans_info[k]["rel_err_fp32"] = abs(complex(*out_k.cpu().numpy()) - want) / abs(want)
+        del ws_k, plan_k
+    src = min(cands, key=lambda k: (plans_info[k]["fp32_ms_per_amplitude"], k != "tree_trimming"))
+    mu, pi, _ = cands[src]
+    log(f"[bench] {C3}: sliced set from {src}; " +
+        ", ".join(f"{k} width {v['width']} log2 FLOPs {v['log2_total_flops']:.2f} fp32 "
+                  f"{v['fp32_ms_per_amplitude']:.3f} ms" for k, v in plans_info.items()))
+    forms = {}
+    for prec in ("fp32", "bf16x6", "bf16x3"):
+        plan = qbe.Plan(qm, pi, mu, ctx=ctx, exec="per_step", precision=prec)
+        ws0 = plan.workspace()
+        t0 = time.perf_counter()
+        plan.autotune(ws0)
+        tune_ms = (time.perf_counter() - t0) * 1e3
+        del ws0
+        fr, got, ws = time_plan(torch, qbe, ctx, plan, steps, warmup)
+        ev = min(f["ms_per_amplitude"] for f in fr.values())
+        err = abs(got - want) / abs(want)
+        forms[prec] = {"ms_per_amplitude": ev, "amplitudes_per_s": 1e3 / ev, "rel_err": err, "issue": fr,
+                       "autotune_ms": tune_ms, "within_1e-5": err <= 1e-5, "_plan": plan, "_ws": ws}
+        log(f"[bench] {prec}: {ev:.3f} ms/amplitude, rel err {err:.2e}")
+    ok = [p for p in forms if forms[p]["within_1e-5"]]
+    if not ok:
+        raise SystemExit("no form of the headline workload met the 1e-5 bound")
+    chosen = min(ok, key=lambda p: forms[p]["ms_per_amplitude"])
+    plan, ws = forms[chosen]["_plan"], forms[chosen]["_ws"]
+    st = plan.stats()
+    prof = launch_profile(plan, ws, max(3, steps // 4))
+    # plain FP32 form: tree-trimming's sliced set, one launch per bucket
+    mu_t, pi_t, _ = cands["tree_trimming"]
+    plan_p = qbe.Plan(qm, pi_t, mu_t, ctx=ctx, exec="per_step", merge=False)
+    ws_p = plan_p.workspace()
+    out_p = torch.zeros(2, dtype=torch.float64, device="cuda")
+    wall_p, ev_p = timed(torch, lambda: qbe.qbe_contract_async(ctx, plan_p, ws_p, out_p), max(2, steps // 4), 1)
+    err_p = abs(complex(*out_p.cpu().numpy()) - want) / abs(want)
+    log(f"[bench] plain FP32 (one launch per bucket): {ev_p:.3f} ms/amplitude, rel err {err_p:.2e}")
+    plain = {"form": "per_step, one launch per bucket, tree-trimming sliced set", "precision": "fp32",
+             "ms_per_amplitude": ev_p, "amplitudes_per_s": 1e3 / ev_p, "rel_err": err_p,
+             "launches_per_amplitude": plan_p.stats()["n_launches"] + 2}
+    del ws_p, plan_p
+    # roofline: the dominant kernel's launch (longest in the live per-launch
+    # timing) and the whole amplitude
+    dom = max(prof, key=lambda r: r["ms"])
+    gbs = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
+    total_ms = sum(r["ms"] for r in prof)
+    amp_bytes = st["step_bytes_per_slice"] * plan.n_slices
+    launch_flops = sum(r["flops"] for r in prof)
+    cnt, why = c3_counters(chosen, mu)
+    roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+            "traffic": cnt["dominant"]["bytes"] if cnt else None,
+            "kernel": f"launch {dom['index']}: {dom['kind']}, {dom['n_ops']} operands, result rank "
+                      f"{dom['out_rank']}, {dom['n_sum']} summed, {'MFMA' if dom['mfma'] else 'VALU'}",
+            "launch_ms": dom["ms"], "algorithmic_bytes_per_launch": dom["bytes"],
+            "bytes_per_slice": dom["bytes_per_slice"], "slices_per_launch": plan.n_slices,
+            "launch_share_of_amplitude": dom["ms"] / total_ms,
+            "copy_peak": copy_peak_gbs(torch), "frac_vs_copy": gbs / copy_peak_gbs(torch),
+            "amplitude": {"algorithmic_bytes": amp_bytes, "cost_model_bytes": st["bytes_per_slice"] * plan.n_slices,
+                          "ms": forms[chosen]["ms_per_amplitude"],
+                          "achieved_GB_per_s": amp_bytes / (forms[chosen]["ms_per_amplitude"] * 1e-3) / 1e9,
+                          "frac": amp_bytes / (forms[chosen]["ms_per_amplitude"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                          "traffic": cnt["amplitude"]["bytes"] if cnt else None,
+                          "launch_flops": launch_flops, "cost_model_flops": st["flops_per_slice"] * plan.n_slices},
+            "note": "achieved = the dominant launch's algorithmic bytes (each operand read once, its result "
+                    "written once, per slice x slices) / its average duration from HIP events around each launch "
+                    "of whole contractions (qbe_plan_profile); amplitude: the same count over all launches "
+                    "(merged chains keep their intermediates on chip) / the step time; cost_model_bytes: one "
+                    "launch per bucket; traffic: FETCH_SIZE and WRITE_SIZE counters with the copy calibration"
+                    + ("" if cnt else f" (null: {why})")}
+    mfma = {"value": cnt["mfma_util"] if cnt else None,
+            "plain_fp32": C3_COUNTERS.get("plain_fp32", {}).get("mfma_util") if cnt else None,
+            "source": "SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / 8 x 256 CUs x 4 SIMDs) over all dispatches of "
+                      "one contraction" + ("" if cnt else f" (null: {why})")}
+    top = sorted(prof, key=lambda r: -r["ms"])[:8]
+    result = {
+        "chosen": chosen, "ev": forms[chosen]["ms_per_amplitude"], "rel_err": forms[chosen]["rel_err"],
+        "forms": {p: {k: v for k, v in f.items() if not k.startswith("_")} for p, f in forms.items()},
+        "plain": plain, "roofline": roof, "mfma": mfma, "mu_source": src, "mu": mu, "slicing": plans_info,
+        "planning_ms": plans_info[src]["planning_ms"],
+        "config": {"workload": C3, "rows": 7, "cols": 7, "depth": 24, "m": m, "seed": SEEDS[C3],
+                   "slices": plan.n_slices, "width": st["width"], "n_vars": st["n_vars"], "n_tensors": st["n_tensors"],
+                   "buckets": st["n_steps"], "launches": st["n_launches"], "merged_launches": st["n_merged_steps"],
+                   "mfma_launches": st["n_mfma_steps"], "mu_source": src},
+        "launches_top": [{k: r[k] for k in ("index", "kind", "n_ops", "out_rank", "n_sum", "mfma", "ms", "bytes")}
+                         for r in top],
+    }
+    for f in forms.values():
+        f.pop("_plan", None)
+        f.pop("_ws", None)
+    return result
+
+
+def _cpu_slices_worker(s):
+    return _cpu_slice(s)
+
+
+def cpu_baseline_slices(name, budget_s=10.0, max_workers=16):
+    """The oracle as it stands on the host, on a bounded sample of one
+    amplitude's slices (slices 0, 1, 2, ... until the budget is spent),
+    scaled to whole amplitudes: (i) one process; (ii) the slices spread over
+    worker processes (spawned children that never touch the GPU)."""
+    m = _cpu_setup(name)
+    n_all = 1 << m
+    k = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s and k < n_all:
+        _cpu_slice(k)
+        k += 1
+    dt = time.perf_counter() - t0
+    modes = {"one_process": {"value": k / dt / n_all, "cores": 1, "slices": k}}
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count() or 1
+    workers = max(1, min(max_workers, affinity))
+    if workers > 1:
+        import multiprocessing as mp
+        with mp.get_context("spawn").Pool(workers, initializer=_cpu_setup, initargs=(name,)) as pool:
+            pool.map(_cpu_slices_worker, range(workers))  # warm every worker
+            done = 0
+            t0 = time.perf_counter()
+            while time.perf_counter() - t0 < budget_s and done < n_all:
+                chunk = list(range(done, min(n_all, done + 4 * workers)))
+                pool.map(_cpu_slices_worker, chunk, chunksize=1)
+                done += len(chunk)
+            dt = time.perf_counter() - t0
+            modes["slices_across_processes"] = {"value": done / dt / n_all, "cores": workers, "slices": done}
+    best = max(modes, key=lambda q: modes[q]["value"])
+    return {"value": modes[best]["value"], "unit": "amplitudes/s", "cores": modes[best]["cores"],
+            "kind": "oracle", "mode": best, "modes": modes,
+            "sample": f"slices 0..{modes[best]['slices'] - 1} of one {name} amplitude ({n_all} slices per "
+                      f"amplitude; about {budget_s:.0f} s per mode), numpy complex128 einsum per bucket, scaled to "
+                      f"whole amplitudes; host: {cpu_model()}, {os.cpu_count()} logical CPUs, {affinity} usable"}
+
 
 
 def bench_batch(torch, qbe, ctx, steps):
@@ -371,26 +604,13 @@ def bench_permute(torch, qbe, ctx, steps, r=28):
                                  "WRITE_SIZE counters per dispatch with the copy calibration"}}
 
 
-def bench_learned(torch, qbe, ctx, labels=20000, epochs=20, hbm_gbs=None):
-    """Learned proposal at the 6x6..8x8 / depth 16..32 scale: ~20k exact-cost
-    labels, device training, evaluation on 10 held-out 8x8 depth-32 circuits
-    against tree-trimming under a 4 GiB per-slice memory cap."""
+def bench_learned(qbe, net, train_info):
+    """The learned proposal at the 8x8 / depth-32 scale: the trained network
+    against tree-trimming on 10 held-out circuits under a 4 GiB per-slice
+    memory cap, judged by exact total FLOPs (the heuristic is the fallback)."""
     import numpy as np
-    from circuitgen import SplitMix64, circuit_model, random_grid_circuit
+    from circuitgen import circuit_model, random_grid_circuit
     from paper_2004_10892_amd import learned as L
-    rng = SplitMix64(2020)
-    t0 = time.perf_counter()
-    samples, n_labels, i = [], 0, 0
-    while n_labels < labels and i < 400:
-        r, c, d = 6 + rng.next() % 3, 6 + rng.next() % 3, 16 + rng.next() % 17
-        qm = qbe.Model.from_circuitgen(circuit_model(random_grid_circuit(r, c, d, 2000 + i)))
-        ss, n = L.make_dataset([qm], seed=i)
-        samples += ss
-        n_labels += n
-        i += 1
-    t1 = time.perf_counter()
-    net = qbe.Gnn(ctx, seed=7)
-    hist = L.train(net, samples, epochs=epochs, batch=8, lr=2e-3)
     t2 = time.perf_counter()
     rows, gains, best = [], [], []
     for k in range(10):
@@ -400,53 +620,96 @@ def bench_learned(torch, qbe, ctx, labels=20000, epochs=20, hbm_gbs=None):
         gains.append(res["log2_gain"])
         best.append(res["log2_gain_best_of_both"])
     t3 = time.perf_counter()
-    out = {"workload": "learned_6x6-8x8_d16-32_eval_8x8_d32", "labels": n_labels, "train_circuits": i,
-           "label_s": t1 - t0, "train_s": t2 - t1, "eval_s": t3 - t2, "loss_first_epoch": hist[0],
-           "loss_last_epoch": hist[-1], "mem_cap_bytes": L.MEM_CAP,
-           "mean_log2_gain": float(np.mean(gains)), "mean_log2_gain_best_of_both": float(np.mean(best)),
-           "learned_chosen": sum(r["chosen"] == "learned" for r in rows),
-           "per_circuit": [{"heuristic_m": r["heuristic"]["m"], "learned_m": r["learned"]["m"],
-                            "heuristic_log2_flops": round(r["heuristic"]["log2_total_flops"], 3),
-                            "learned_log2_flops": round(r["learned"]["log2_total_flops"], 3),
-                            "chosen": r["chosen"], "heuristic_plan_ms": round(r["heuristic"]["plan_ms"], 1),
-                            "learned_plan_ms": round(r["learned"]["plan_ms"], 1)} for r in rows]}
-    if hbm_gbs:
-        out["note_time"] = (f"contraction time of these plans is projected from the cost model's bytes at the "
-                            f"measured per-step rate of {hbm_gbs:.0f} GB/s (too long to run here)")
+    out = dict(train_info, workload="learned_6x6-8x8_d16-32_eval_8x8_d32", eval_s=t3 - t2, mem_cap_bytes=L.MEM_CAP,
+               mean_log2_gain=float(np.mean(gains)), mean_log2_gain_best_of_both=float(np.mean(best)),
+               learned_chosen=sum(r["chosen"] == "learned" for r in rows),
+               per_circuit=[{"heuristic_m": r["heuristic"]["m"], "learned_m": r["learned"]["m"],
+                             "heuristic_log2_flops": round(r["heuristic"]["log2_total_flops"], 3),
+                             "learned_log2_flops": round(r["learned"]["log2_total_flops"], 3),
+                             "chosen": r["chosen"], "heuristic_plan_ms": round(r["heuristic"]["plan_ms"], 1),
+                             "learned_plan_ms": round(r["learned"]["plan_ms"], 1)} for r in rows])
     return out
+
+
+
+
+def bench_fused_c2(torch, qbe, ctx, steps, warmup):
+    """5x5 depth-16 circuit, 64 slices: one LDS-resident fused launch per
+    amplitude (issued directly or from a HIP graph) vs one launch per bucket."""
+    name = "grid5x5_d16_m6"
+    want = golden(name)
+    plan, plan_ms, cfg = build_plan(qbe, ctx, name, "fused")
+    st = plan.stats()
+    ws = plan.workspace()
+    out = torch.zeros(2, dtype=torch.float64, device="cuda")
+    fn = lambda: qbe.qbe_contract_async(ctx, plan, ws, out)  # noqa: E731
+    g = graph_of(torch, qbe, ctx, fn)
+    forms = {}
+    for form, call in (("fused", fn), ("fused+hipgraph", g.replay)):
+        out.zero_()
+        wall_f, ev_f = timed(torch, call, steps, warmup)
+        got_f = complex(*out.cpu().numpy())
+        forms[form] = {"ms_per_step": ev_f, "wall_ms_per_step": wall_f, "value": 1e3 / ev_f,
+                       "rel_err": abs(got_f - want) / abs(want)}
+    chosen = min(forms, key=lambda f: forms[f]["ms_per_step"])
+    ev = forms[chosen]["ms_per_step"]
+    plan_p, _, _ = build_plan(qbe, ctx, name, "per_step", merge=False)
+    ws_p = plan_p.workspace()
+    out_p = torch.zeros(2, dtype=torch.float64, device="cuda")
+    wall_p, ev_p = timed(torch, lambda: qbe.qbe_contract_async(ctx, plan_p, ws_p, out_p), max(1, steps // 4), 1)
+    err_p = abs(complex(*out_p.cpu().numpy()) - want) / abs(want)
+    flops = st["flops_per_slice"] * plan.n_slices
+    achieved = flops / (ev * 1e-3) / 1e12
+    return {"workload": name, "form": chosen, "ms_per_amplitude": ev, "amplitudes_per_s": 1e3 / ev,
+            "rel_err": forms[chosen]["rel_err"], "forms": forms, "planning_ms": plan_ms, "config": cfg,
+            "plain_fp32": {"ms_per_amplitude": ev_p, "amplitudes_per_s": 1e3 / ev_p, "rel_err": err_p},
+            "speedup_vs_plain": ev_p / ev,
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": achieved / FP32_PEAK_TFLOPS, "traffic": fused_traffic(), "kernel": "fused_kernel",
+                         "algorithmic_flops_per_launch": flops,
+                         "note": "LDS-resident: operands and intermediates stay on chip; bounded by the chain of "
+                                 "dependent bucket levels (latency), not by HBM or ALU throughput"}}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--no-extra", action="store_true", help="skip the 7x7 and batch lines")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-extra", action="store_true", help="headline line only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--only", choices=["hbm", "hbm_fp32", "batch", "many", "learned", "permute"],
-                    help="run just one extra workload (hbm_fp32: the 7x7 line in FP32 only)")
+    ap.add_argument("--no-learned", action="store_true", help="headline without the learned proposal")
+    ap.add_argument("--only", choices=["headline", "c2", "batch", "many", "learned", "permute"],
+                    help="run just one workload")
     ap.add_argument("--pmc-workload", action="store_true",
                     help="for hardware-counter runs: a device-to-device copy of 256 MiB (three times, the "
-                         "calibration of the byte counters) and 20 launches of the headline fused kernel")
+                         "calibration of the byte counters) and 20 launches of the 5x5 fused kernel")
+    ap.add_argument("--pmc-c3", choices=["fp32", "bf16x6", "bf16x3", "plain_fp32"],
+                    help="for hardware-counter runs: the copy calibration, then the headline plan in this form "
+                         "(sliced set from --mu, else tree-trimming), autotuned, and two contractions")
+    ap.add_argument("--mu", default="", help="comma-separated sliced set for --pmc-c3")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: the contraction runs on a single MI355X "
               f"(--gpus {args.gpus} is not supported)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
+    if args.only == "headline":
+        args.no_extra = args.no_cpu = True
+
     import torch
 
     import paper_2004_10892_amd as qbe
 
-    name = "grid5x5_d16_m6"
     ctx = qbe.Context(0)
-    want = golden(name)
-    if args.pmc_workload:
+    if args.pmc_workload or args.pmc_c3:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
+        torch.cuda.synchronize()
+    if args.pmc_workload:
+        name = "grid5x5_d16_m6"
         plan, _, _ = build_plan(qbe, ctx, name, "fused")
         ws = plan.workspace()
         out = torch.zeros(2, dtype=torch.float64, device="cuda")
@@ -454,15 +717,33 @@ def main():
             qbe.qbe_contract_async(ctx, plan, ws, out)
         torch.cuda.synchronize()
         got = complex(*out.cpu().numpy())
-        log(f"[bench] pmc workload done, rel err {abs(got - want) / abs(want):.2e}")
+        log(f"[bench] pmc workload done, rel err {abs(got - golden(name)) / abs(golden(name)):.2e}")
         return
-    if args.only == "hbm_fp32":
-        print(json.dumps(bench_hbm(torch, qbe, ctx, args.steps)), flush=True)
+    if args.pmc_c3:
+        qm, m = c3_model(qbe)
+        order = qbe.qbe_order_min_fill(qm)
+        if args.mu:
+            mu = [int(v) for v in args.mu.split(",")]
+        else:
+            mu, _, _ = qbe.qbe_slice(qm, order, m)
+        pi = [v for v in order if v not in set(mu)]
+        plain = args.pmc_c3 == "plain_fp32"
+        plan = qbe.Plan(qm, pi, mu, ctx=ctx, exec="per_step", precision="fp32" if plain else args.pmc_c3,
+                        merge=not plain)
+        ws = plan.workspace()
+        out = torch.zeros(2, dtype=torch.float64, device="cuda")
+        if not plain:
+            plan.autotune(ws)
+        torch.cuda.synchronize()
+        for _ in range(2):
+            qbe.qbe_contract_async(ctx, plan, ws, out)
+        torch.cuda.synchronize()
+        got = complex(*out.cpu().numpy())
+        log(f"[bench] pmc c3 {args.pmc_c3} mu {mu}: {plan.stats()['n_launches'] + 2} dispatches per contraction, "
+            f"rel err {abs(got - golden(C3)) / abs(golden(C3)):.2e}")
         return
-    if args.only == "hbm":
-        print(json.dumps(bench_hbm(torch, qbe, ctx, args.steps)), flush=True)
-        print(json.dumps(bench_hbm(torch, qbe, ctx, args.steps, "bf16x3")), flush=True)
-        print(json.dumps(bench_hbm(torch, qbe, ctx, args.steps, "bf16x6")), flush=True)
+    if args.only == "c2":
+        print(json.dumps(bench_fused_c2(torch, qbe, ctx, args.steps, args.warmup)), flush=True)
         return
     if args.only == "batch":
         print(json.dumps(bench_batch(torch, qbe, ctx, args.steps)), flush=True)
@@ -470,88 +751,57 @@ def main():
     if args.only == "many":
         print(json.dumps(bench_many(torch, qbe, ctx, args.steps)), flush=True)
         return
-    if args.only == "learned":
-        print(json.dumps(bench_learned(torch, qbe, ctx)), flush=True)
-        return
     if args.only == "permute":
         print(json.dumps(bench_permute(torch, qbe, ctx, args.steps)), flush=True)
         return
 
-    # chosen form: one fused persistent launch per amplitude, issued directly
-    # or replayed from a HIP graph, whichever is faster on this machine
-    plan, plan_ms, cfg = build_plan(qbe, ctx, name, "fused")
-    st = plan.stats()
-    ws = plan.workspace()
-    out = torch.zeros(2, dtype=torch.float64, device="cuda")
-    fn = lambda: qbe.qbe_contract_async(ctx, plan, ws, out)  # noqa: E731
-    g = graph_of(torch, qbe, ctx, fn)
-    log(f"[bench] {name}: width {st['width']} levels {st['n_levels']} lds {st['lds_bytes']} B")
-    forms = {}
-    for form, call in (("fused", fn), ("fused+hipgraph", g.replay)):
-        out.zero_()
-        wall_f, ev_f = timed(torch, call, args.steps, args.warmup)
-        got_f = complex(*out.cpu().numpy())
-        forms[form] = {"ms_per_step": ev_f, "wall_ms_per_step": wall_f, "value": 1e3 / ev_f,
-                       "rel_err": abs(got_f - want) / abs(want)}
-        log(f"[bench] {form}: {ev_f * 1e3:.2f} us/amplitude (wall {wall_f * 1e3:.2f}), "
-            f"rel err {forms[form]['rel_err']:.2e}")
-    chosen = min(forms, key=lambda f: forms[f]["ms_per_step"])
-    ev, err = forms[chosen]["ms_per_step"], forms[chosen]["rel_err"]
+    net, train_info = (None, None)
+    if not args.no_learned or args.only == "learned":
+        log("[bench] training the learned proposal's network ...")
+        net, train_info = train_net(qbe, ctx)
+        log(f"[bench] {train_info['labels']} labels, train {train_info['train_s']:.1f} s, loss "
+            f"{train_info['loss_first_epoch']:.3f} -> {train_info['loss_last_epoch']:.3f}")
+    if args.only == "learned":
+        print(json.dumps(bench_learned(qbe, net, train_info)), flush=True)
+        return
 
-    # plain FP32 form: one launch per bucket (no merged chains, no grouped
-    # small launches)
-    plan_p, plan_p_ms, _ = build_plan(qbe, ctx, name, "per_step", merge=False)
-    ws_p = plan_p.workspace()
-    out_p = torch.zeros(2, dtype=torch.float64, device="cuda")
-    wall_p, ev_p = timed(torch, lambda: qbe.qbe_contract_async(ctx, plan_p, ws_p, out_p),
-                         max(1, args.steps // 4), max(1, args.warmup // 4))
-    got_p = complex(*out_p.cpu().numpy())
-    err_p = abs(got_p - want) / abs(want)
-    log(f"[bench] plain: {ev_p * 1e3:.2f} us/amplitude, rel err {err_p:.2e}")
-
-    flops_launch = st["flops_per_slice"] * plan.n_slices
-    achieved = flops_launch / (ev * 1e-3) / 1e12
+    h = bench_headline(torch, qbe, ctx, args.steps, args.warmup, net)
+    ev = h["ev"]
     line = {
         "metric": METRIC, "value": 1e3 / ev, "unit": "amplitudes/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ev, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
-        "config": dict({"workload": name, "form": chosen, "slices": plan.n_slices}, **cfg),
-        "rel_err": err, "mfma_util": 0.0, "forms": forms,
-        "planning_ms": plan_ms,
-        "amplitudes_per_s_with_planning": 1e3 / (ev + plan_ms),
-        "note_planning": "host planning per circuit (min-fill, tree-trimming, schedule and program "
-                         "compilation); the plan is cached across amplitudes in the timed loop",
-        "plain_fp32": {"form": "per_step, one launch per bucket", "ms_per_step": ev_p, "value": 1e3 / ev_p,
-                       "rel_err": err_p, "launches_per_step": plan_p.stats()["n_launches"] + 2},
-        "speedup_vs_plain": ev_p / ev,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": fused_traffic(),
-                     "kernel": "fused_kernel", "algorithmic_flops_per_launch": flops_launch,
-                     "note": "LDS-resident: every operand and intermediate stays on chip; the step is "
-                             "bounded by the chain of dependent bucket levels, not by HBM; traffic: bytes "
-                             "per launch from the FETCH_SIZE and WRITE_SIZE counters"},
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if h["chosen"] == "fp32" else "bf16",
+        "data": "synthetic", "config": h["config"],
+        "rel_err": h["rel_err"], "precision": h["chosen"],
+        "mfma_util": h["mfma"]["value"], "mfma_util_plain_fp32": h["mfma"]["plain_fp32"],
+        "mfma_util_source": h["mfma"]["source"],
+        "plain_fp32": h["plain"], "speedup_vs_plain": h["plain"]["ms_per_amplitude"] / ev,
+        "forms": h["forms"],
+        "planning_ms": h["planning_ms"], "amplitudes_per_s_with_planning": 1e3 / (ev + h["planning_ms"]),
+        "note_planning": "host planning per circuit (min-fill, sliced-set choice, schedule); the plan is cached "
+                         "across amplitudes in the timed loop",
+        "slicing": h["slicing"], "mu": h["mu"],
+        "roofline": h["roofline"], "launches_top": h["launches_top"],
     }
+    if train_info:
+        line["learned_training"] = train_info
     if not args.no_cpu:
-        log("[bench] cpu baseline (oracle) ...")
-        line["cpu_baseline"] = cpu_baseline(name)
+        log("[bench] cpu baseline (oracle, sampled slices) ...")
+        line["cpu_baseline"] = cpu_baseline_slices(C3)
     if not args.no_extra:
-        log("[bench] 7x7 d24 per-step ...")
-        line["hbm_workload"] = bench_hbm(torch, qbe, ctx, 5)
-        log("[bench] 7x7 d24 per-step, split-BF16 ...")
-        line["hbm_workload_bf16x3"] = bench_hbm(torch, qbe, ctx, 5, "bf16x3")
-        log("[bench] 7x7 d24 per-step, three-part split-BF16 ...")
-        line["hbm_workload_bf16x6"] = bench_hbm(torch, qbe, ctx, 5, "bf16x6")
+        log("[bench] 5x5 d16 fused ...")
+        line["c2_fused"] = bench_fused_c2(torch, qbe, ctx, 100, 10)
         log("[bench] batch of 512 ...")
         line["batch_workload"] = bench_batch(torch, qbe, ctx, 20)
-        log("[bench] 256 bitstrings of the headline circuit ...")
+        log("[bench] 256 bitstrings of the 5x5 circuit ...")
         line["many_amplitudes"] = bench_many(torch, qbe, ctx, 20)
         log("[bench] stand-alone permute ...")
         line["permute_workload"] = bench_permute(torch, qbe, ctx, 10)
-        log("[bench] learned proposal ...")
-        line["learned_proposal"] = bench_learned(torch, qbe, ctx,
-                                                 hbm_gbs=line["hbm_workload"]["roofline"]["achieved"])
+        if net is not None:
+            log("[bench] learned proposal on 8x8 d32 ...")
+            line["learned_proposal"] = bench_learned(qbe, net, train_info)
     print(json.dumps(line), flush=True)
-    if max(f["rel_err"] for f in forms.values()) > 1e-5 or err_p > 1e-5:
+    if h["rel_err"] > 1e-5 or h["plain"]["rel_err"] > 1e-5:
         sys.exit(1)
 
 

@@ -293,6 +293,38 @@ int qbe_plan_dump(const qbe_plan* plan, char* buf, size_t cap, size_t* len_out);
 int qbe_plan_autotune(qbe_ctx* ctx, qbe_plan* plan, void* d_workspace, size_t ws_bytes,
                       int64_t min_elems);
 
+/* Per-launch view of a per-step plan (diagnostics and measurement): the
+ * execution order's launches -- a single bucket, a merged chain of buckets
+ * (several summed variables), a partial product of a wide bucket, or a
+ * group of small buckets of one level -- then the per-slice FP64 product
+ * of the rank-0 results (finalize) and the slice sum (reduce, Eq. 4). */
+enum {
+  QBE_LAUNCH_BUCKET = 0,
+  QBE_LAUNCH_MERGED = 1,
+  QBE_LAUNCH_PARTIAL = 2,
+  QBE_LAUNCH_GROUP = 3,
+  QBE_LAUNCH_FINALIZE = 4,
+  QBE_LAUNCH_REDUCE = 5
+};
+typedef struct qbe_launch_info {
+  int32_t kind;              /* QBE_LAUNCH_*                                  */
+  int32_t n_buckets;         /* buckets the launch contracts (chain length,
+                                group size)                                   */
+  int32_t n_ops;             /* operands (largest in a group)                 */
+  int32_t out_rank;          /* result rank (largest in a group)              */
+  int32_t n_sum;             /* summed variables per result entry             */
+  int32_t mfma;              /* 1: runs on MFMA tiles                         */
+  uint64_t bytes_per_slice;  /* algorithmic complex64 bytes: each operand read
+                                once, the result written once                 */
+  uint64_t flops_per_slice;  /* real flops: per result entry 2^n_sum terms of
+                                n_ops - 1 complex products (6 flops each) and
+                                their sum                                     */
+} qbe_launch_info;
+/* Launches of a per-step plan (its execution order + 2); 0 for a fused plan. */
+int qbe_plan_num_launches(const qbe_plan* plan, int32_t* n_out);
+/* Launch i (0 <= i < qbe_plan_num_launches) of a per-step plan. */
+int qbe_plan_launch_info(const qbe_plan* plan, int32_t i, qbe_launch_info* out);
+
 /* ------------------------------------------------------------ contraction - */
 
 /* Contracts all 2^m slices and sums them (Eq. 4) in FP64.  d_workspace is a
@@ -334,6 +366,16 @@ int qbe_contract_async(qbe_ctx* ctx, const qbe_plan* plan, void* d_workspace, si
 int qbe_contract_static(qbe_ctx* ctx, const qbe_plan* plan, double* d_amp_out);
 /* Bytes of the per-device workspace of qbe_contract_static (64 MiB). */
 size_t qbe_static_scratch_bytes(void);
+
+/* Per-launch timing of a per-step plan: contracts all slices at once
+ * (d_workspace of ws_bytes >= stats.ws_bytes_all_slices, else
+ * QBE_ERR_MEM_CAP) with a HIP event on the context's stream before the first
+ * launch and after each one; ms_out[i] (capacity cap >= the plan's launch
+ * count, else QBE_ERR_MEM_CAP) receives launch i's time in milliseconds, in
+ * the order of qbe_plan_launch_info, and *n_out the launch count.  Blocks
+ * until done.  QBE_ERR_INVALID_ARG for a fused plan. */
+int qbe_plan_profile(qbe_ctx* ctx, const qbe_plan* plan, void* d_workspace, size_t ws_bytes, float* ms_out,
+                     int32_t cap, int32_t* n_out);
 
 /* ---------------------------------------------------------------- batch - */
 

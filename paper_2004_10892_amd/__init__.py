@@ -68,6 +68,20 @@ class Stats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class LaunchInfo(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n_buckets", C.c_int32), ("n_ops", C.c_int32), ("out_rank", C.c_int32),
+                ("n_sum", C.c_int32), ("mfma", C.c_int32), ("bytes_per_slice", C.c_uint64),
+                ("flops_per_slice", C.c_uint64)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["kind"] = LAUNCH_KINDS[d["kind"]]
+        return d
+
+
+LAUNCH_KINDS = {0: "bucket", 1: "merged", 2: "partial", 3: "group", 4: "finalize", 5: "reduce"}
+
+
 _SIGS = {
     "qbe_last_error": (C.c_char_p, []),
     "qbe_version": (C.c_int32, []),
@@ -102,6 +116,10 @@ _SIGS = {
     "qbe_contract_slices": (C.c_int, [_vp, _vp, C.c_int64, C.c_int64, _vp, C.c_size_t, _f64p, _f64p]),
     "qbe_contract_async": (C.c_int, [_vp, _vp, _vp, C.c_size_t, _vp]),
     "qbe_contract_static": (C.c_int, [_vp, _vp, _vp]),
+    "qbe_plan_num_launches": (C.c_int, [_vp, C.POINTER(C.c_int32)]),
+    "qbe_plan_launch_info": (C.c_int, [_vp, C.c_int32, C.c_void_p]),
+    "qbe_plan_profile": (C.c_int, [_vp, _vp, _vp, C.c_size_t, C.POINTER(C.c_float), C.c_int32,
+                                   C.POINTER(C.c_int32)]),
     "qbe_static_scratch_bytes": (C.c_size_t, []),
     "qbe_gnn_num_params": (C.c_int32, []),
     "qbe_gnn_create": (C.c_int, [_vp, C.c_uint64, C.POINTER(_vp)]),
@@ -434,6 +452,30 @@ class Plan:
         """Times the large per-step launches in each tile shape; keeps the best."""
         w, nb = _workspace(self.ctx, ws)
         _check(_lib.qbe_plan_autotune(self.ctx.handle, self.handle, w, nb, min_elems), "qbe_plan_autotune")
+
+    def launches(self) -> list:
+        """Per-launch info of a per-step plan (qbe_plan_launch_info), in
+        execution order, then finalize and reduce."""
+        n = C.c_int32()
+        _check(_lib.qbe_plan_num_launches(self.handle, C.byref(n)), "qbe_plan_num_launches")
+        out = []
+        for i in range(n.value):
+            li = LaunchInfo()
+            _check(_lib.qbe_plan_launch_info(self.handle, i, C.byref(li)), "qbe_plan_launch_info")
+            out.append(li.as_dict())
+        return out
+
+    def profile(self, ws) -> np.ndarray:
+        """Milliseconds of each launch of one contraction of all slices
+        (qbe_plan_profile), in the order of launches()."""
+        n = C.c_int32()
+        _check(_lib.qbe_plan_num_launches(self.handle, C.byref(n)), "qbe_plan_num_launches")
+        ms = np.zeros(max(n.value, 1), dtype=np.float32)
+        w, nb = _workspace(self.ctx, ws)
+        got = C.c_int32()
+        _check(_lib.qbe_plan_profile(self.ctx.handle, self.handle, w, nb, ms.ctypes.data_as(C.POINTER(C.c_float)),
+                                     len(ms), C.byref(got)), "qbe_plan_profile")
+        return ms[:got.value].copy()
 
     def workspace(self, all_slices: bool = True):
         """A device workspace (torch uint8 tensor) of the plan's size."""

@@ -654,6 +654,92 @@ int qbe_plan_autotune(qbe_ctx* ctx, qbe_plan* plan, void* d_workspace, size_t ws
   QBE_GUARD_END
 }
 
+// Launch info of a per-step plan's execution order (then finalize, reduce).
+namespace {
+
+uint64_t step_bytes(const qbe::StepProg& sp) {
+  const int r = sp.out_rank >= 0 ? sp.out_rank : -sp.out_rank;
+  uint64_t e = uint64_t(1) << r;
+  for (int i = 0; i < sp.n_ops; ++i) e += uint64_t(1) << sp.ops[i].rank;
+  return 8 * e;
+}
+
+// products and sums of one launch: every result entry sums 2^n_sum terms of
+// n_ops complex factors (a partial product: one term, no sum)
+uint64_t step_flops(const qbe::StepProg& sp) {
+  const int r = sp.out_rank >= 0 ? sp.out_rank : -sp.out_rank;
+  const uint64_t terms = uint64_t(1) << sp.n_sum;
+  const uint64_t per_term = 6 * (uint64_t)std::max(sp.n_ops - 1, 0);
+  return (uint64_t(1) << r) * (terms * per_term + 2 * (terms - 1));
+}
+
+}  // namespace
+
+int qbe_plan_num_launches(const qbe_plan* plan, int32_t* n_out) {
+  QBE_GUARD_BEGIN
+  QBE_REQUIRE(plan && n_out, "NULL argument");
+  *n_out = plan->p.exec == QBE_EXEC_PER_STEP ? (int32_t)plan->p.launch_order.size() + 2 : 0;
+  return QBE_OK;
+  QBE_GUARD_END
+}
+
+int qbe_plan_launch_info(const qbe_plan* plan, int32_t i, qbe_launch_info* out) {
+  QBE_GUARD_BEGIN
+  QBE_REQUIRE(plan && out, "NULL argument");
+  const qbe::Plan& p = plan->p;
+  QBE_REQUIRE(p.exec == QBE_EXEC_PER_STEP, "launch info is for per-step plans");
+  const int n_order = (int)p.launch_order.size();
+  QBE_REQUIRE(i >= 0 && i < n_order + 2, "launch index out of range");
+  std::memset(out, 0, sizeof(*out));
+  if (i == n_order) {
+    out->kind = QBE_LAUNCH_FINALIZE;
+    out->bytes_per_slice = 8 * (p.scalar_arena.size() + p.scalar_inputs_base.size()) + 16;
+    return QBE_OK;
+  }
+  if (i == n_order + 1) {
+    out->kind = QBE_LAUNCH_REDUCE;
+    out->bytes_per_slice = 16;
+    return QBE_OK;
+  }
+  const qbe::LaunchItem& li = p.launch_order[i];
+  if (li.group >= 0) {
+    out->kind = QBE_LAUNCH_GROUP;
+    for (int k = p.group_first[li.group]; k < p.group_first[li.group + 1]; ++k) {
+      const qbe::StepProg& sp = p.steps[p.group_steps[k].step];
+      out->n_buckets += 1;
+      out->bytes_per_slice += step_bytes(sp);
+      out->flops_per_slice += step_flops(sp);
+      out->n_ops = std::max(out->n_ops, sp.n_ops);
+      out->out_rank = std::max(out->out_rank, sp.out_rank >= 0 ? sp.out_rank : -sp.out_rank);
+    }
+    return QBE_OK;
+  }
+  const qbe::StepProg& sp = p.steps[li.step];
+  out->kind = sp.out_rank < 0 ? QBE_LAUNCH_PARTIAL : sp.n_sum > 1 ? QBE_LAUNCH_MERGED : QBE_LAUNCH_BUCKET;
+  out->n_buckets = std::max(sp.n_sum, 1);
+  out->n_ops = sp.n_ops;
+  out->out_rank = sp.out_rank >= 0 ? sp.out_rank : -sp.out_rank;
+  out->n_sum = sp.n_sum;
+  out->mfma = (sp.mmk || sp.mm_a >= 0) ? 1 : 0;
+  out->bytes_per_slice = step_bytes(sp);
+  out->flops_per_slice = step_flops(sp);
+  return QBE_OK;
+  QBE_GUARD_END
+}
+
+int qbe_plan_profile(qbe_ctx* ctx, const qbe_plan* plan, void* d_workspace, size_t ws_bytes, float* ms_out,
+                     int32_t cap, int32_t* n_out) {
+  QBE_GUARD_BEGIN
+  int rc = check_device_call(ctx, plan, d_workspace);
+  if (rc) return rc;
+  QBE_REQUIRE(ms_out && n_out, "NULL argument");
+  int n = 0;
+  rc = qbe::dev_profile(plan->p, ctx->stream, d_workspace, ws_bytes, ms_out, cap, &n);
+  *n_out = n;
+  return rc;
+  QBE_GUARD_END
+}
+
 int qbe_contract_async(qbe_ctx* ctx, const qbe_plan* plan, void* d_workspace, size_t ws_bytes,
                        double* d_amp_out) {
   QBE_GUARD_BEGIN

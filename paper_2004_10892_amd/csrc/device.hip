@@ -35,6 +35,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <vector>
 
 namespace qbe {
 
@@ -1838,6 +1839,55 @@ int dev_contract(const Plan& p, void* stream, void* ws, size_t ws_bytes, int64_t
     }
   }
   return launch_reduce(per_slice, nullptr, n, (double2*)d_partial_out, 1, st);
+}
+
+// Per-launch timing of a per-step plan: the contraction of all slices at
+// once (one slice group), with a HIP event recorded on the stream before the
+// first launch and after every launch of the execution order, then the
+// finalize and reduce launches.  ms_out[i] = time between events i and i + 1.
+int dev_profile(const Plan& p, void* stream, void* ws, size_t ws_bytes, float* ms_out, int cap, int* n_out) {
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t n = p.n_slices;
+  const int items = (int)p.launch_order.size() + 2;
+  *n_out = items;
+  if (p.exec != QBE_EXEC_PER_STEP) {
+    set_error("per-launch timing is for per-step plans (a fused plan is one launch)");
+    return QBE_ERR_INVALID_ARG;
+  }
+  if (ws_bytes < dev_workspace_all(p)) {
+    set_error("per-launch timing runs all slices at once: workspace below stats.ws_bytes_all_slices");
+    return QBE_ERR_MEM_CAP;
+  }
+  if (cap < items) {
+    set_error("ms_out holds fewer entries than the plan's launches");
+    return QBE_ERR_MEM_CAP;
+  }
+  char* w = (char*)ws;
+  double2* per_slice = (double2*)(w + 256);
+  float2* arena = (float2*)(w + ws_head(n));
+  std::vector<hipEvent_t> ev(items + 1, nullptr);
+  int rc = QBE_OK;
+  for (auto& e : ev)
+    if (rc == QBE_OK && hipEventCreate(&e) != hipSuccess) rc = QBE_ERR_HIP;
+  if (rc == QBE_OK && hipEventRecord(ev[0], st) != hipSuccess) rc = QBE_ERR_HIP;
+  for (int i = 0; i < items && rc == QBE_OK; ++i) {
+    if (i < (int)p.launch_order.size()) {
+      const LaunchItem& li = p.launch_order[i];
+      rc = li.group < 0 ? launch_step(p, p.steps[li.step], arena, n, 0, st) : launch_group(p, li.group, arena, n, 0, st);
+    } else if (i == items - 2) {
+      rc = finalize_group(p, arena, per_slice, n, 0, st);
+    } else {
+      rc = launch_reduce(per_slice, nullptr, n, (double2*)w, 1, st);
+    }
+    if (rc == QBE_OK && hipEventRecord(ev[i + 1], st) != hipSuccess) rc = QBE_ERR_HIP;
+  }
+  if (rc == QBE_OK && hipEventSynchronize(ev[items]) != hipSuccess) rc = QBE_ERR_HIP;
+  for (int i = 0; i < items && rc == QBE_OK; ++i)
+    if (hipEventElapsedTime(&ms_out[i], ev[i], ev[i + 1]) != hipSuccess) rc = QBE_ERR_HIP;
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
+  if (rc == QBE_ERR_HIP) set_error("per-launch timing: a HIP event call failed");
+  return rc;
 }
 
 // ------------------------------------------------- allocation-free entry --

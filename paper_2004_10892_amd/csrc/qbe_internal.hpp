@@ -232,6 +232,7 @@ int dev_static_scratch_init(int device);
 int dev_contract_static(const Plan& p, void* stream, double* d_amp_out);
 size_t dev_workspace_all(const Plan& p);
 int dev_autotune(Plan& p, void* stream, void* ws, size_t ws_bytes, int64_t min_elems);
+int dev_profile(const Plan& p, void* stream, void* ws, size_t ws_bytes, float* ms_out, int cap, int* n_out);
 int dev_batch_build(Batch& b);
 void dev_batch_free(Batch& b);
 size_t dev_batch_workspace(const Batch& b);
