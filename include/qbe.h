@@ -51,9 +51,17 @@ enum {
   QBE_SCORE_TREE_TRIMMING = 0, /* Sec. 3.2                                 */
   QBE_SCORE_DEGREE = 1,        /* Sec. 3.1, number of neighbours            */
   QBE_SCORE_TW_REDUCTION = 2,  /* Sec. 3.1, Alg. 3 (direct width drop)      */
-  QBE_SCORE_BETWEENNESS = 3    /* Sec. 3.1, betweenness centrality
+  QBE_SCORE_BETWEENNESS = 3,   /* Sec. 3.1, betweenness centrality
                                   (unnormalised; ties to the earliest vertex
                                   of the order after rounding to 1e-9)     */
+  QBE_SCORE_LEARNED = 4        /* the network's slicing head (qbe_slice_ex
+                                  only: it needs a network and a device)   */
+};
+
+/* Heads of the learned proposal's network. */
+enum {
+  QBE_HEAD_SLICING = 0,     /* predicted total cost after slicing a variable */
+  QBE_HEAD_ELIMINATION = 1  /* predicted total cost after eliminating it next */
 };
 
 /* Device execution forms of a plan. */
@@ -82,6 +90,7 @@ typedef struct qbe_ctx qbe_ctx;
 typedef struct qbe_model qbe_model;
 typedef struct qbe_plan qbe_plan;
 typedef struct qbe_batch qbe_batch;
+typedef struct qbe_gnn qbe_gnn;
 
 typedef struct qbe_plan_opts {
   int32_t exec;        /* QBE_EXEC_*                                         */
@@ -202,6 +211,76 @@ int qbe_clique_tree(const qbe_model* model, const int32_t* order, int32_t n, int
 int qbe_slice(const qbe_model* model, const int32_t* order, int32_t n, int32_t m,
               int32_t target_width, int32_t score, int32_t* mu_out, int32_t* m_out,
               int32_t* reduced_order_out, int32_t* tau_out);
+/* Options of qbe_slice_ex: Alg. 2 with its score f, its stopping rule and
+ * its optional order recomputation. */
+typedef struct qbe_slice_opts {
+  int32_t score;           /* QBE_SCORE_*                                     */
+  int32_t m;               /* >= 0: remove exactly m variables; < 0: remove
+                              until the stop rules below hold               */
+  int32_t target_width;    /* m < 0: stop once the reduced order's width is
+                              <= target_width (< 0: no width rule)          */
+  int32_t recompute_every; /* > 0: recompute the order after every k-th
+                              removal as qbe_slice_recompute does; 0: never */
+  int32_t tries;           /* anytime heuristic tries of the recomputation  */
+  int32_t reserved0;       /* must be zero                                  */
+  uint64_t seed;           /* anytime heuristic seed                        */
+  uint64_t mem_cap;        /* m < 0: also stop only once the peak live bytes
+                              per slice (cost model) are <= mem_cap (0: no
+                              memory rule).  QBE_SCORE_LEARNED: if the
+                              network's sliced set misses the cap, the
+                              result is tree-trimming's under the same rules
+                              (the heuristic remains the fallback)          */
+  uint64_t reserved[2];    /* must be zero                                  */
+} qbe_slice_opts;
+
+/* Alg. 2 (Sec. 3) whose score f may be the learned proposal's network
+ * (QBE_SCORE_LEARNED: among the vertices of the maximum bags of App. A's
+ * tree -- tree-trimming's candidates -- the one the slicing head predicts
+ * cheapest, ties to the earliest in the order; the network is re-run on the
+ * reduced graph after every removal).  ctx and gnn are needed only for the
+ * learned score (else may be NULL).  Outputs as qbe_slice; *fell_back_out
+ * (optional) = 1 when the memory-cap fallback replaced the learned result.
+ * QBE_ERR_INVALID_ARG for bad options (m < 0 needs a width or memory rule). */
+int qbe_slice_ex(qbe_ctx* ctx, qbe_gnn* gnn, const qbe_model* model, const int32_t* order, int32_t n,
+                 const qbe_slice_opts* opts, int32_t* mu_out, int32_t* m_out, int32_t* reduced_order_out,
+                 int32_t* tau_out, int32_t* fell_back_out);
+
+/* An elimination order (Sec. 2.2's order problem) from greedy min-fill
+ * whose ties in fill go to the network's elimination head (lower predicted
+ * cost first; then smaller degree, then smaller id).  The head is evaluated
+ * on the current elimination graph, with the features of that graph's
+ * greedy min-fill order, before the first elimination and after every
+ * `refresh` eliminations.  The min-fill order remains the fallback: the
+ * result is whichever of the two orders has fewer exact total FLOPs
+ * (cost model, no slicing); *fell_back_out (optional) = 1 when that is
+ * min-fill's.  flops_out (optional, 2 entries): the learned and the
+ * min-fill order's total FLOPs.  order_out: n_vars entries; *width_out its
+ * width (Alg. 1). */
+int qbe_order_learned(qbe_ctx* ctx, qbe_gnn* gnn, const qbe_model* model, int32_t refresh,
+                      int32_t* order_out, int32_t* width_out, int32_t* fell_back_out, uint64_t* flops_out);
+
+/* One training sample of the learned proposal, labelled with the method's
+ * own exact costs (the cost model of qbe_schedule_cost):
+ *  - head QBE_HEAD_SLICING: the state is the graph without mu (m entries)
+ *    and its order (n = n_vars - m entries); the candidates are the
+ *    vertices of the maximum bags; the label of candidate c is log2 of the
+ *    total FLOPs (2^(m + 1) slices) of removing c as well;
+ *  - head QBE_HEAD_ELIMINATION: the state is the elimination graph after
+ *    eliminating order[0 .. k_elim) (n = n_vars, m = 0); the candidates are
+ *    its vertices of minimum fill; the label of c is log2 of the total FLOPs
+ *    (no slicing) of the order prefix, c, then greedy min-fill of the rest.
+ * At most max_cand (>= 2) candidates are kept (a SplitMix64(seed) sample),
+ * ascending ids; labels are standardised within the sample: (y - mean) /
+ * max(std, 0.05).  Outputs: the state graph as CSR over all n_vars ids
+ * (rowptr_out[n_vars + 1], col_out of capacity col_cap, *nnz_out; MEM_CAP if
+ * short), features (feats_out[8 n_vars], qbe_vertex_features of the state
+ * and -- for elimination -- its min-fill order), cand_out / target_out
+ * (max_cand entries) and *n_cand_out (fewer than 2: no labels written). */
+int qbe_learned_sample(const qbe_model* model, int32_t head, const int32_t* order, int32_t n, const int32_t* mu,
+                       int32_t m, int32_t k_elim, int32_t max_cand, uint64_t seed, int32_t* rowptr_out,
+                       int32_t* col_out, int64_t col_cap, int64_t* nnz_out, float* feats_out, int32_t* cand_out,
+                       float* target_out, int32_t* n_cand_out);
+
 /* Alg. 2 with its optional line (Sec. 3): after every recompute_every-th
  * removal (> 0) the reduced order is recomputed on the reduced graph: the
  * anytime order of qbe_order_anytime(tries, seed) is turned into its tree
@@ -425,16 +504,16 @@ int qbe_permute(qbe_ctx* ctx, const void* d_in, void* d_out, int32_t r, const in
 
 /* ------------------------------------------------------ learned proposal - */
 
-/* A message-passing network that scores variables for slicing: 8 input
- * features per variable (qbe_vertex_features), three layers
- * H' = relu(H Ws + mean_{neighbours} H Wn + b) of width 64 and a linear head.
- * Weights are FP16 in the device passes (FP32 master copy for Adam), sums
- * are FP32.  Parameters: a flat float vector of qbe_gnn_num_params() entries,
- * layer by layer (Ws[din][64], Wn[din][64], b[64]), then the head (w[64], c).
+/* A message-passing network that scores variables for slicing and for
+ * elimination: 8 input features per variable (qbe_vertex_features), three
+ * layers H' = relu(H Ws + mean_{neighbours} H Wn + b) of width 64 shared by
+ * two linear heads (QBE_HEAD_*).  Weights are FP16 in the device passes
+ * (FP32 master copy for Adam), sums are FP32.  Parameters: a flat float
+ * vector of qbe_gnn_num_params() entries, layer by layer (Ws[din][64],
+ * Wn[din][64], b[64]), then head 0 (w[64], c), then head 1 (w[64], c).
  * Created with Glorot-uniform weights from a SplitMix64 stream of `seed`.
  * Graphs are passed as symmetric CSR (rowptr[n + 1], col[rowptr[n]]) over n
  * vertices with feats[n * 8]; the call checks ranges and symmetry. */
-typedef struct qbe_gnn qbe_gnn;
 int qbe_gnn_create(qbe_ctx* ctx, uint64_t seed, qbe_gnn** out);
 int qbe_gnn_destroy(qbe_gnn* gnn);
 int32_t qbe_gnn_num_params(void);
@@ -443,20 +522,29 @@ int qbe_gnn_get_params(const qbe_gnn* gnn, float* params_out);
 int qbe_gnn_set_params(qbe_gnn* gnn, const float* params);
 /* Training checkpoint at a caller path: the FP32 master parameters, both
  * Adam moments and the step count, so that training resumes where it
- * stopped.  File layout (native little-endian): the 8 bytes "QBEGNN01",
+ * stopped.  File layout (native little-endian): the 8 bytes "QBEGNN02",
  * int32 parameter count, int32 step, then three float32 arrays of that count
  * (parameters, first moments, second moments).  QBE_ERR_INVALID_ARG for a
  * file that cannot be opened, written or read in full, or whose magic or
  * parameter count differs; the network is unchanged then. */
 int qbe_gnn_save(const qbe_gnn* gnn, const char* path);
 int qbe_gnn_load(qbe_gnn* gnn, const char* path);
-/* Forward pass on the device: scores_out[n] (host). */
+/* Forward pass on the device through head `head`: scores_out[n] (host). */
+int qbe_gnn_score_head(qbe_ctx* ctx, qbe_gnn* gnn, int32_t head, int32_t n, const int32_t* rowptr,
+                       const int32_t* col, const float* feats, float* scores_out);
+/* qbe_gnn_score_head with the slicing head. */
 int qbe_gnn_score(qbe_ctx* ctx, qbe_gnn* gnn, int32_t n, const int32_t* rowptr, const int32_t* col,
                   const float* feats, float* scores_out);
-/* One training step on the device: forward, loss = mean over the n_cand
- * candidate vertices of (score - target)^2, backward, and (if lr > 0) one
- * Adam step (betas 0.9, 0.999, eps 1e-8).  loss_out (1 float) and grads_out
- * (qbe_gnn_num_params() floats, the gradient before the step) are optional. */
+/* One training step on the device through head `head`: forward, loss =
+ * mean over the n_cand candidate vertices of (score - target)^2, backward
+ * (the other head's gradient is zero), and (if lr > 0) one Adam step (betas
+ * 0.9, 0.999, eps 1e-8) of every parameter.  loss_out (1 float) and
+ * grads_out (qbe_gnn_num_params() floats, the gradient before the step) are
+ * optional. */
+int qbe_gnn_train_step_head(qbe_ctx* ctx, qbe_gnn* gnn, int32_t head, int32_t n, const int32_t* rowptr,
+                            const int32_t* col, const float* feats, int32_t n_cand, const int32_t* cand,
+                            const float* target, float lr, float* loss_out, float* grads_out);
+/* qbe_gnn_train_step_head with the slicing head. */
 int qbe_gnn_train_step(qbe_ctx* ctx, qbe_gnn* gnn, int32_t n, const int32_t* rowptr, const int32_t* col,
                        const float* feats, int32_t n_cand, const int32_t* cand, const float* target, float lr,
                        float* loss_out, float* grads_out);

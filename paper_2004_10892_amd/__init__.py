@@ -34,7 +34,8 @@ _lib = C.CDLL(LIB_PATH)
 
 QBE_OK = 0
 ERRORS = {-1: "INVALID_ARG", -2: "OOM", -3: "HIP", -4: "MEM_CAP", -5: "INTERNAL", -6: "NO_DEVICE"}
-SCORE = {"tree_trimming": 0, "degree": 1, "tw_reduction": 2, "betweenness": 3}
+SCORE = {"tree_trimming": 0, "degree": 1, "tw_reduction": 2, "betweenness": 3, "learned": 4}
+HEAD = {"slicing": 0, "elimination": 1}
 EXEC = {"auto": 0, "per_step": 1, "fused": 2}
 PREC = {"fp32": 0, "bf16x3": 1, "bf16x6": 2}
 
@@ -66,6 +67,12 @@ class Stats(C.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class SliceOpts(C.Structure):
+    _fields_ = [("score", C.c_int32), ("m", C.c_int32), ("target_width", C.c_int32),
+                ("recompute_every", C.c_int32), ("tries", C.c_int32), ("reserved0", C.c_int32),
+                ("seed", C.c_uint64), ("mem_cap", C.c_uint64), ("reserved", C.c_uint64 * 2)]
 
 
 class LaunchInfo(C.Structure):
@@ -138,6 +145,17 @@ _SIGS = {
     "qbe_contract_batch": (C.c_int, [_vp, C.POINTER(_vp), C.c_int32, _vp, C.c_size_t, _f64p,
                                      C.POINTER(C.c_size_t)]),
     "qbe_gnn_save": (C.c_int, [_vp, C.c_char_p]),
+    "qbe_slice_ex": (C.c_int, [_vp, _vp, _vp, _i32p, C.c_int32, C.POINTER(SliceOpts), _i32p, _i32p, _i32p, _i32p,
+                               _i32p]),
+    "qbe_order_learned": (C.c_int, [_vp, _vp, _vp, C.c_int32, _i32p, _i32p, _i32p, C.POINTER(C.c_uint64)]),
+    "qbe_learned_sample": (C.c_int, [_vp, C.c_int32, _i32p, C.c_int32, _i32p, C.c_int32, C.c_int32, C.c_int32,
+                                     C.c_uint64, _i32p, _i32p, C.c_int64, C.POINTER(C.c_int64),
+                                     C.POINTER(C.c_float), _i32p, C.POINTER(C.c_float), _i32p]),
+    "qbe_gnn_score_head": (C.c_int, [_vp, _vp, C.c_int32, C.c_int32, _i32p, _i32p, C.POINTER(C.c_float),
+                                     C.POINTER(C.c_float)]),
+    "qbe_gnn_train_step_head": (C.c_int, [_vp, _vp, C.c_int32, C.c_int32, _i32p, _i32p, C.POINTER(C.c_float),
+                                          C.c_int32, _i32p, C.POINTER(C.c_float), C.c_float,
+                                          C.POINTER(C.c_float), C.POINTER(C.c_float)]),
     "qbe_gnn_load": (C.c_int, [_vp, C.c_char_p]),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -328,16 +346,34 @@ def qbe_clique_tree(model: Model, order: Sequence[int]):
 
 
 def qbe_slice(model: Model, order: Sequence[int], m: int, target_width: int = -1,
-              score: str = "tree_trimming", recompute_every: int = 0, tries: int = 8, seed: int = 0):
+              score: str = "tree_trimming", recompute_every: int = 0, tries: int = 8, seed: int = 0,
+              net: Optional["Gnn"] = None, mem_cap: int = 0, with_fallback: bool = False):
     """Alg. 2 (with recompute_every > 0: its optional order recomputation
-    after every recompute_every-th removal).  Returns (mu, reduced_order, tau)."""
+    after every recompute_every-th removal).  score "learned" uses the
+    network `net` (qbe_slice_ex); mem_cap > 0 with m < 0 stops once the
+    per-slice peak fits.  Returns (mu, reduced_order, tau), plus whether the
+    learned result fell back to tree-trimming when with_fallback."""
     o = _i32(order)
     n = len(o)
     mu = np.zeros(max(n, 1), dtype=np.int32)
     red = np.zeros(max(n, 1), dtype=np.int32)
     mo = C.c_int32()
     tau = C.c_int32()
-    if recompute_every > 0:
+    fb = C.c_int32(0)
+    if score == "learned" or mem_cap or with_fallback:
+        opts = SliceOpts()
+        opts.score = SCORE[score]
+        opts.m = m
+        opts.target_width = target_width
+        opts.recompute_every = recompute_every
+        opts.tries = tries
+        opts.seed = seed
+        opts.mem_cap = mem_cap
+        ctx = net.ctx.handle if net is not None else None
+        _check(_lib.qbe_slice_ex(ctx, net.handle if net is not None else None, model.handle, _p32(o), n,
+                                 C.byref(opts), _p32(mu), C.byref(mo), _p32(red), C.byref(tau), C.byref(fb)),
+               "qbe_slice_ex")
+    elif recompute_every > 0:
         _check(_lib.qbe_slice_recompute(model.handle, _p32(o), n, m, target_width, SCORE[score],
                                         recompute_every, tries, seed, _p32(mu), C.byref(mo), _p32(red),
                                         C.byref(tau)), "qbe_slice_recompute")
@@ -345,7 +381,51 @@ def qbe_slice(model: Model, order: Sequence[int], m: int, target_width: int = -1
         _check(_lib.qbe_slice(model.handle, _p32(o), n, m, target_width, SCORE[score], _p32(mu), C.byref(mo),
                               _p32(red), C.byref(tau)), "qbe_slice")
     k = mo.value
-    return mu[:k].tolist(), red[:n - k].tolist(), tau.value
+    out = (mu[:k].tolist(), red[:n - k].tolist(), tau.value)
+    return out + (bool(fb.value),) if with_fallback else out
+
+
+def qbe_order_learned(model: Model, net: "Gnn", refresh: int = 16):
+    """Greedy min-fill with the elimination head breaking fill ties, min-fill
+    as fallback.  Returns (order, width, fell_back, (learned FLOPs, min-fill
+    FLOPs))."""
+    out = np.zeros(max(model.n_vars, 1), dtype=np.int32)
+    w = C.c_int32()
+    fb = C.c_int32()
+    fl = (C.c_uint64 * 2)()
+    _check(_lib.qbe_order_learned(net.ctx.handle, net.handle, model.handle, refresh, _p32(out), C.byref(w),
+                                  C.byref(fb), fl), "qbe_order_learned")
+    return out[:model.n_vars].tolist(), w.value, bool(fb.value), (int(fl[0]), int(fl[1]))
+
+
+def qbe_learned_sample(model: Model, head: str, order: Sequence[int], mu: Sequence[int] = (), k_elim: int = 0,
+                       max_cand: int = 24, seed: int = 0):
+    """One labelled state (qbe_learned_sample): (rowptr, col, feats, cand,
+    target) or None when the state has fewer than two candidates."""
+    o = _i32(order)
+    u = _i32(mu)
+    nv = model.n_vars
+    rp = np.zeros(nv + 1, dtype=np.int32)
+    feats = np.zeros((nv, FEATURES), dtype=np.float32)
+    cand = np.zeros(max_cand, dtype=np.int32)
+    tgt = np.zeros(max_cand, dtype=np.float32)
+    nnz = C.c_int64()
+    nc = C.c_int32()
+    cap = 1 << 16
+    while True:
+        col = np.zeros(cap, dtype=np.int32)
+        rc = _lib.qbe_learned_sample(model.handle, HEAD[head], _p32(o), len(o), _p32(u), len(u), k_elim, max_cand,
+                                     seed, _p32(rp), _p32(col), cap, C.byref(nnz),
+                                     feats.ctypes.data_as(C.POINTER(C.c_float)), _p32(cand),
+                                     tgt.ctypes.data_as(C.POINTER(C.c_float)), C.byref(nc))
+        if rc == -4 and nnz.value > cap:
+            cap = int(nnz.value)
+            continue
+        _check(rc, "qbe_learned_sample")
+        break
+    if nc.value < 2:
+        return None
+    return rp, col[:nnz.value].copy(), feats, cand[:nc.value].copy(), tgt[:nc.value].copy()
 
 
 def qbe_order_anytime(model: Model, removed: Sequence[int] = (), tries: int = 8, seed: int = 0):
@@ -650,25 +730,26 @@ class Gnn:
     def load(self, path: str):
         _check(_lib.qbe_gnn_load(self.handle, os.fsencode(path)), "qbe_gnn_load")
 
-    def score(self, rowptr, col, feats) -> np.ndarray:
+    def score(self, rowptr, col, feats, head: str = "slicing") -> np.ndarray:
         rp, cl = _i32(rowptr), _i32(col)
         f = np.ascontiguousarray(feats, dtype=np.float32)
         n = len(rp) - 1
         out = np.zeros(n, dtype=np.float32)
-        _check(_lib.qbe_gnn_score(self.ctx.handle, self.handle, n, _p32(rp), _p32(cl), _fp(f), _fp(out)),
-               "qbe_gnn_score")
+        _check(_lib.qbe_gnn_score_head(self.ctx.handle, self.handle, HEAD[head], n, _p32(rp), _p32(cl), _fp(f),
+                                       _fp(out)), "qbe_gnn_score_head")
         return out
 
-    def train_step(self, rowptr, col, feats, cand, target, lr: float, want_grads: bool = False):
+    def train_step(self, rowptr, col, feats, cand, target, lr: float, want_grads: bool = False,
+                   head: str = "slicing"):
         rp, cl, cd = _i32(rowptr), _i32(col), _i32(cand)
         f = np.ascontiguousarray(feats, dtype=np.float32)
         y = np.ascontiguousarray(target, dtype=np.float32)
         n = len(rp) - 1
         loss = np.zeros(1, dtype=np.float32)
         grads = np.zeros(self.n_params, dtype=np.float32) if want_grads else None
-        _check(_lib.qbe_gnn_train_step(self.ctx.handle, self.handle, n, _p32(rp), _p32(cl), _fp(f), len(cd),
-                                       _p32(cd), _fp(y), lr, _fp(loss), _fp(grads) if want_grads else None),
-               "qbe_gnn_train_step")
+        _check(_lib.qbe_gnn_train_step_head(self.ctx.handle, self.handle, HEAD[head], n, _p32(rp), _p32(cl),
+                                            _fp(f), len(cd), _p32(cd), _fp(y), lr, _fp(loss),
+                                            _fp(grads) if want_grads else None), "qbe_gnn_train_step_head")
         return (float(loss[0]), grads) if want_grads else float(loss[0])
 
     def close(self):

@@ -74,6 +74,37 @@ using qbe::set_error;
     }                                 \
   } while (0)
 
+namespace {
+
+// A device call failed inside a host loop (a score callback): unwinds to the
+// entry point, which returns its code.
+struct DeviceError {
+  int rc;
+};
+
+void csr_of(const qbe::Graph& g, std::vector<int32_t>& rp, std::vector<int32_t>& col) {
+  rp.assign(g.n + 1, 0);
+  col.clear();
+  for (int v = 0; v < g.n; ++v) {
+    rp[v] = (int32_t)col.size();
+    for (int w : g.neighbours(v)) col.push_back(w);
+  }
+  rp[g.n] = (int32_t)col.size();
+}
+
+// The network's head scores on graph g with the features of (g, order).
+void net_scores(qbe_ctx* ctx, qbe_gnn* gnn, int head, const qbe::Graph& g, const std::vector<int>& order,
+                std::vector<float>& feats, std::vector<float>& scores) {
+  feats = qbe::vertex_features(g, order);
+  std::vector<int32_t> rp, col;
+  csr_of(g, rp, col);
+  scores.assign(g.n, 0.f);
+  const int rc = qbe::gnn_score(gnn->g, ctx->stream, head, g.n, rp.data(), col.data(), feats.data(), scores.data());
+  if (rc) throw DeviceError{rc};
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* qbe_last_error(void) { return qbe::g_error.c_str(); }
@@ -424,6 +455,7 @@ int qbe_slice(const qbe_model* model, const int32_t* order, int32_t n, int32_t m
   QBE_REQUIRE(model && m_out && tau_out, "NULL argument");
   QBE_REQUIRE(n == model->m.n_vars, "order must list every variable");
   QBE_REQUIRE(m <= n, "m larger than the number of variables");
+  QBE_REQUIRE(score != QBE_SCORE_LEARNED, "the learned score needs a network: use qbe_slice_ex");
   auto d = qbe::greedy_deletion(graph_of(model->m), vec(order, n), m, target_width, score);
   QBE_REQUIRE(d.mu.empty() || mu_out, "mu_out is NULL");
   QBE_REQUIRE(d.reduced_order.empty() || reduced_order_out, "reduced_order_out is NULL");
@@ -431,6 +463,179 @@ int qbe_slice(const qbe_model* model, const int32_t* order, int32_t n, int32_t m
   for (size_t i = 0; i < d.reduced_order.size(); ++i) reduced_order_out[i] = d.reduced_order[i];
   *m_out = (int32_t)d.mu.size();
   *tau_out = d.tau;
+  return QBE_OK;
+  QBE_GUARD_END
+}
+
+int qbe_slice_ex(qbe_ctx* ctx, qbe_gnn* gnn, const qbe_model* model, const int32_t* order, int32_t n,
+                 const qbe_slice_opts* opts, int32_t* mu_out, int32_t* m_out, int32_t* reduced_order_out,
+                 int32_t* tau_out, int32_t* fell_back_out) {
+  QBE_GUARD_BEGIN
+  QBE_REQUIRE(model && opts && m_out && tau_out, "NULL argument");
+  QBE_REQUIRE(n == model->m.n_vars, "order must list every variable");
+  const qbe_slice_opts& o = *opts;
+  QBE_REQUIRE(o.reserved0 == 0 && o.reserved[0] == 0 && o.reserved[1] == 0, "reserved fields must be zero");
+  QBE_REQUIRE(o.m <= n, "m larger than the number of variables");
+  QBE_REQUIRE(o.m >= 0 || o.target_width >= 0 || o.mem_cap > 0, "m < 0 needs a target width or a memory cap");
+  QBE_REQUIRE(o.recompute_every >= 0 && (o.recompute_every == 0 || o.tries >= 1), "bad recomputation options");
+  const bool learned = o.score == QBE_SCORE_LEARNED;
+  QBE_REQUIRE(learned || (o.score >= QBE_SCORE_TREE_TRIMMING && o.score <= QBE_SCORE_BETWEENNESS), "bad score");
+  QBE_REQUIRE(!learned || (ctx && gnn), "the learned score needs a context and a network");
+  if (learned) {
+    int rc = qbe::dev_set(ctx->device);
+    if (rc) return rc;
+  }
+  const qbe::Graph g = graph_of(model->m);
+  qbe::DeletionStop stop;
+  stop.m = o.m;
+  stop.width_rule = o.m < 0 && o.target_width >= 0;
+  stop.target_width = o.target_width;
+  stop.mem_cap = o.m < 0 ? o.mem_cap : 0;
+  stop.tensor_vars = &model->m.tvars;
+  std::vector<float> feats, scores;
+  qbe::PickFn pick;
+  if (learned) {
+    // Alg. 2's argmax with f = the network's slicing head: among the
+    // vertices of the maximum bags (tree-trimming's candidates), the lowest
+    // predicted cost wins; ties go to the earliest in the order
+    pick = [&](const qbe::Graph& gr, const std::vector<int>& ord) {
+      net_scores(ctx, gnn, QBE_HEAD_SLICING, gr, ord, feats, scores);
+      int best = -1;
+      for (int v : ord)
+        if (feats[(size_t)v * qbe::kFeatures + 3] > 0.5f && (best < 0 || scores[v] < scores[best])) best = v;
+      return best;
+    };
+  } else {
+    pick = qbe::score_pick(o.score);
+  }
+  qbe::Deletion d;
+  int fell_back = 0;
+  try {
+    d = qbe::greedy_deletion_with(g, vec(order, n), stop, pick, o.recompute_every, o.tries, o.seed);
+    if (learned && o.mem_cap > 0) {
+      const auto c = qbe::schedule_cost(qbe::build_schedule(n, model->m.tvars, d.reduced_order, d.mu));
+      if (c.peak_bytes > o.mem_cap) {
+        // the heuristic remains the fallback: tree-trimming, same rule
+        d = qbe::greedy_deletion_with(g, vec(order, n), stop, qbe::score_pick(QBE_SCORE_TREE_TRIMMING),
+                                      o.recompute_every, o.tries, o.seed);
+        fell_back = 1;
+      }
+    }
+  } catch (const DeviceError& e) {
+    return e.rc;
+  }
+  QBE_REQUIRE(d.mu.empty() || mu_out, "mu_out is NULL");
+  QBE_REQUIRE(d.reduced_order.empty() || reduced_order_out, "reduced_order_out is NULL");
+  for (size_t i = 0; i < d.mu.size(); ++i) mu_out[i] = d.mu[i];
+  for (size_t i = 0; i < d.reduced_order.size(); ++i) reduced_order_out[i] = d.reduced_order[i];
+  *m_out = (int32_t)d.mu.size();
+  *tau_out = d.tau;
+  if (fell_back_out) *fell_back_out = fell_back;
+  return QBE_OK;
+  QBE_GUARD_END
+}
+
+int qbe_order_learned(qbe_ctx* ctx, qbe_gnn* gnn, const qbe_model* model, int32_t refresh, int32_t* order_out,
+                      int32_t* width_out, int32_t* fell_back_out, uint64_t* flops_out) {
+  QBE_GUARD_BEGIN
+  QBE_REQUIRE(ctx && gnn && model && order_out && width_out, "NULL argument");
+  QBE_REQUIRE(refresh >= 1, "refresh must be >= 1");
+  int rc = qbe::dev_set(ctx->device);
+  if (rc) return rc;
+  const qbe::Graph g = graph_of(model->m);
+  std::vector<float> feats, scores;
+  // priorities: the elimination head on the current elimination graph with
+  // the features of its greedy min-fill order
+  auto rescore = [&](const qbe::Graph& cur, std::vector<float>& prio) {
+    net_scores(ctx, gnn, QBE_HEAD_ELIMINATION, cur, qbe::min_fill_order(cur), feats, scores);
+    prio = scores;
+  };
+  std::vector<int> learned;
+  try {
+    learned = qbe::min_fill_order_learned(g, rescore, refresh);
+  } catch (const DeviceError& e) {
+    return e.rc;
+  }
+  const std::vector<int> mf = qbe::min_fill_order(g);
+  const uint64_t fl = qbe::schedule_cost(qbe::build_schedule(g.n, model->m.tvars, learned, {})).flops;
+  const uint64_t fm = qbe::schedule_cost(qbe::build_schedule(g.n, model->m.tvars, mf, {})).flops;
+  // the heuristic remains the fallback: min-fill's order when it is cheaper
+  const bool use_learned = fl <= fm;
+  const std::vector<int>& best = use_learned ? learned : mf;
+  std::copy(best.begin(), best.end(), order_out);
+  *width_out = qbe::width_of_order(g, best);
+  if (fell_back_out) *fell_back_out = use_learned ? 0 : 1;
+  if (flops_out) {
+    flops_out[0] = fl;
+    flops_out[1] = fm;
+  }
+  return QBE_OK;
+  QBE_GUARD_END
+}
+
+int qbe_learned_sample(const qbe_model* model, int32_t head, const int32_t* order, int32_t n, const int32_t* mu,
+                       int32_t m, int32_t k_elim, int32_t max_cand, uint64_t seed, int32_t* rowptr_out,
+                       int32_t* col_out, int64_t col_cap, int64_t* nnz_out, float* feats_out, int32_t* cand_out,
+                       float* target_out, int32_t* n_cand_out) {
+  QBE_GUARD_BEGIN
+  QBE_REQUIRE(model && rowptr_out && nnz_out && feats_out && n_cand_out, "NULL argument");
+  QBE_REQUIRE(head == QBE_HEAD_SLICING || head == QBE_HEAD_ELIMINATION, "bad head");
+  QBE_REQUIRE(max_cand >= 2 && cand_out && target_out, "max_cand must be >= 2 with output arrays");
+  const int nv = model->m.n_vars;
+  qbe::Graph g = graph_of(model->m);
+  std::vector<int> mus = vec(mu, m);
+  for (int v : mus) {
+    QBE_REQUIRE(v >= 0 && v < nv && g.present[v], "bad sliced variable");
+    g.remove_vertex(v);
+  }
+  const std::vector<int> ord = vec(order, n);
+  qbe::Graph state;
+  std::vector<int> cand, feat_order;
+  std::vector<double> y;
+  if (head == QBE_HEAD_SLICING) {
+    QBE_REQUIRE(n == nv - m, "order must list every variable not in mu");
+    state = g;
+    const std::vector<float> f = qbe::vertex_features(g, ord);
+    for (int v : ord)
+      if (f[(size_t)v * qbe::kFeatures + 3] > 0.5f) cand.push_back(v);
+    std::sort(cand.begin(), cand.end());
+    cand = qbe::sample_ids(cand, max_cand, seed);
+    feat_order = ord;
+    if (cand.size() >= 2) y = qbe::slice_labels(g, ord, mus, model->m.tvars, cand);
+  } else {
+    QBE_REQUIRE(m == 0, "elimination samples take the whole graph (m = 0)");
+    QBE_REQUIRE(n == nv, "order must list every variable");
+    QBE_REQUIRE(k_elim >= 0 && k_elim < n, "bad elimination state");
+    state = qbe::eliminated_prefix(g, ord, k_elim);
+    cand = qbe::sample_ids(qbe::min_fill_ties(state), max_cand, seed);
+    feat_order = qbe::min_fill_order(state);
+    if (cand.size() >= 2)
+      y = qbe::elim_labels(state, std::vector<int>(ord.begin(), ord.begin() + k_elim), model->m.tvars, cand);
+  }
+  int64_t nnz = 0;
+  for (int v = 0; v < state.n; ++v) nnz += state.degree(v);
+  *nnz_out = nnz;
+  if (nnz > col_cap || (nnz > 0 && !col_out)) {
+    set_error("col capacity too small");
+    return QBE_ERR_MEM_CAP;
+  }
+  std::vector<int32_t> rp, col;
+  csr_of(state, rp, col);
+  std::copy(rp.begin(), rp.end(), rowptr_out);
+  std::copy(col.begin(), col.end(), col_out);
+  const std::vector<float> f = qbe::vertex_features(state, feat_order);
+  std::copy(f.begin(), f.end(), feats_out);
+  *n_cand_out = (int32_t)cand.size();
+  for (size_t i = 0; i < cand.size(); ++i) cand_out[i] = cand[i];
+  if (cand.size() >= 2) {
+    // standardised within the state: (y - mean) / max(std, 0.05)
+    double mean = 0.0, var = 0.0;
+    for (double v : y) mean += v;
+    mean /= (double)y.size();
+    for (double v : y) var += (v - mean) * (v - mean);
+    const double sd = std::max(std::sqrt(var / (double)y.size()), 0.05);
+    for (size_t i = 0; i < y.size(); ++i) target_out[i] = (float)((y[i] - mean) / sd);
+  }
   return QBE_OK;
   QBE_GUARD_END
 }
@@ -928,7 +1133,10 @@ int qbe_gnn_create(qbe_ctx* ctx, uint64_t seed, qbe_gnn** out) {
     o += qbe::kGnnHidden;
   }
   const float lim = std::sqrt(6.f / (float)(qbe::kGnnHidden + 1));
-  for (int i = 0; i < qbe::kGnnHidden; ++i) p[o++] = uniform(lim);
+  for (int h = 0; h < qbe::kGnnHeads; ++h) {
+    for (int i = 0; i < qbe::kGnnHidden; ++i) p[o++] = uniform(lim);
+    o += 1;  // the head's bias
+  }
   rc = qbe::gnn_set_params(n->g, p.data(), true);
   if (rc) {
     qbe::gnn_free(n->g);
@@ -966,7 +1174,7 @@ int qbe_gnn_set_params(qbe_gnn* gnn, const float* params) {
   QBE_GUARD_END
 }
 
-static const char kGnnMagic[8] = {'Q', 'B', 'E', 'G', 'N', 'N', '0', '1'};
+static const char kGnnMagic[8] = {'Q', 'B', 'E', 'G', 'N', 'N', '0', '2'};
 
 int qbe_gnn_save(const qbe_gnn* gnn, const char* path) {
   QBE_GUARD_BEGIN
@@ -1029,22 +1237,29 @@ static int check_csr(int32_t n, const int32_t* rp, const int32_t* col) {
   return QBE_OK;
 }
 
-int qbe_gnn_score(qbe_ctx* ctx, qbe_gnn* gnn, int32_t n, const int32_t* rowptr, const int32_t* col,
-                  const float* feats, float* scores_out) {
+int qbe_gnn_score_head(qbe_ctx* ctx, qbe_gnn* gnn, int32_t head, int32_t n, const int32_t* rowptr,
+                       const int32_t* col, const float* feats, float* scores_out) {
   QBE_GUARD_BEGIN
   QBE_REQUIRE(ctx && gnn && feats && scores_out, "NULL argument");
+  QBE_REQUIRE(head >= 0 && head < qbe::kGnnHeads, "bad head");
   QBE_REQUIRE(check_csr(n, rowptr, col) == QBE_OK, "graph is not a symmetric CSR over n vertices");
   int rc = qbe::dev_set(ctx->device);
   if (rc) return rc;
-  return qbe::gnn_score(gnn->g, ctx->stream, n, rowptr, col, feats, scores_out);
+  return qbe::gnn_score(gnn->g, ctx->stream, head, n, rowptr, col, feats, scores_out);
   QBE_GUARD_END
 }
 
-int qbe_gnn_train_step(qbe_ctx* ctx, qbe_gnn* gnn, int32_t n, const int32_t* rowptr, const int32_t* col,
-                       const float* feats, int32_t n_cand, const int32_t* cand, const float* target, float lr,
-                       float* loss_out, float* grads_out) {
+int qbe_gnn_score(qbe_ctx* ctx, qbe_gnn* gnn, int32_t n, const int32_t* rowptr, const int32_t* col,
+                  const float* feats, float* scores_out) {
+  return qbe_gnn_score_head(ctx, gnn, QBE_HEAD_SLICING, n, rowptr, col, feats, scores_out);
+}
+
+int qbe_gnn_train_step_head(qbe_ctx* ctx, qbe_gnn* gnn, int32_t head, int32_t n, const int32_t* rowptr,
+                            const int32_t* col, const float* feats, int32_t n_cand, const int32_t* cand,
+                            const float* target, float lr, float* loss_out, float* grads_out) {
   QBE_GUARD_BEGIN
   QBE_REQUIRE(ctx && gnn && feats, "NULL argument");
+  QBE_REQUIRE(head >= 0 && head < qbe::kGnnHeads, "bad head");
   QBE_REQUIRE(check_csr(n, rowptr, col) == QBE_OK, "graph is not a symmetric CSR over n vertices");
   QBE_REQUIRE(n_cand >= 0 && (n_cand == 0 || (cand && target)), "bad candidates");
   std::vector<uint8_t> seen(n, 0);
@@ -1054,9 +1269,16 @@ int qbe_gnn_train_step(qbe_ctx* ctx, qbe_gnn* gnn, int32_t n, const int32_t* row
   }
   int rc = qbe::dev_set(ctx->device);
   if (rc) return rc;
-  return qbe::gnn_train_step(gnn->g, ctx->stream, n, rowptr, col, feats, n_cand, cand, target, lr, loss_out,
-                             grads_out);
+  return qbe::gnn_train_step(gnn->g, ctx->stream, head, n, rowptr, col, feats, n_cand, cand, target, lr,
+                             loss_out, grads_out);
   QBE_GUARD_END
+}
+
+int qbe_gnn_train_step(qbe_ctx* ctx, qbe_gnn* gnn, int32_t n, const int32_t* rowptr, const int32_t* col,
+                       const float* feats, int32_t n_cand, const int32_t* cand, const float* target, float lr,
+                       float* loss_out, float* grads_out) {
+  return qbe_gnn_train_step_head(ctx, gnn, QBE_HEAD_SLICING, n, rowptr, col, feats, n_cand, cand, target, lr,
+                                 loss_out, grads_out);
 }
 
 int qbe_graph_csr(const qbe_model* model, const int32_t* removed, int32_t n_removed, int32_t* rowptr_out,

@@ -1,9 +1,11 @@
-// Learned slicing proposal: a message-passing network over the variables of
-// a (reduced) graphical model, trained on the device.
+// Learned proposal: a message-passing network over the variables of a
+// (reduced) graphical model, trained on the device.
 //
 // Architecture (fixed): input features F = 8 per variable, three layers of
 //   H_{l+1} = relu(H_l W_s + mean_{w in N(v)} H_l[w] W_n + b)      (width 64)
-// and a linear head s = H_3 w + c.  Weights are FP16 in the forward and
+// shared by two linear heads s_h = H_3 w_h + c_h: head 0 scores variables
+// for slicing (Alg. 2), head 1 for elimination (ties of greedy min-fill).
+// Weights are FP16 in the forward and
 // backward passes (FP32 master copies for the optimizer); every sum is
 // accumulated in FP32.  Training minimises the mean squared error between s
 // and a target at a set of candidate variables.  All reductions run in a
@@ -32,14 +34,15 @@ namespace qbe {
 
 // ------------------------------------------------------------- parameters --
 // Flat parameter vector: for layer l = 0..2 (din = 8, 64, 64):
-//   W_s[din][64], W_n[din][64], b[64]; then head w[64], c.
+//   W_s[din][64], W_n[din][64], b[64]; then head 0 (w[64], c), head 1 (w[64], c).
 __host__ __device__ constexpr int gnn_din(int l) { return l == 0 ? kGnnFeatures : kGnnHidden; }
 __host__ __device__ constexpr int gnn_layer_size(int l) { return 2 * gnn_din(l) * kGnnHidden + kGnnHidden; }
 __host__ __device__ constexpr int gnn_layer_off(int l) {
   return l == 0 ? 0 : gnn_layer_off(l - 1) + gnn_layer_size(l - 1);
 }
 constexpr int kGnnHeadOff = gnn_layer_off(kGnnLayers);
-constexpr int kGnnParams = kGnnHeadOff + kGnnHidden + 1;
+constexpr int kGnnHeadSize = kGnnHidden + 1;
+constexpr int kGnnParams = kGnnHeadOff + kGnnHeads * kGnnHeadSize;
 
 int gnn_num_params() { return kGnnParams; }
 static_assert(kGnnFeatures == kFeatures, "feature width");
@@ -199,6 +202,10 @@ __global__ void gnn_adam(float* __restrict__ p, __half* __restrict__ p16, const 
   p16[i] = __float2half(pi);
 }
 
+__global__ void gnn_zero(float* __restrict__ x, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = 0.f;
+}
+
 __global__ void gnn_to_half(const float* __restrict__ p, __half* __restrict__ p16, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p16[i] = __float2half(p[i]);
@@ -321,7 +328,7 @@ static int gnn_layout(Gnn& g, int n, int64_t nnz, int nc, GnnBufs& b) {
   return QBE_OK;
 }
 
-static int gnn_forward(const Gnn& g, const GnnBufs& b, int n, hipStream_t st) {
+static int gnn_forward(const Gnn& g, const GnnBufs& b, int n, int head, hipStream_t st) {
   const __half* w16 = (const __half*)g.d_p16;
   for (int l = 0; l < kGnnLayers; ++l) {
     const int din = gnn_din(l);
@@ -329,7 +336,7 @@ static int gnn_forward(const Gnn& g, const GnnBufs& b, int n, hipStream_t st) {
     gnn_dense<<<blocks((int64_t)n * kGnnHidden), 256, 0, st>>>(b.H[l], b.M[l], w16 + gnn_layer_off(l), din, n,
                                                                 b.Z[l], b.H[l + 1]);
   }
-  gnn_head<<<blocks(n), 256, 0, st>>>(b.H[kGnnLayers], w16 + kGnnHeadOff, n, b.s);
+  gnn_head<<<blocks(n), 256, 0, st>>>(b.H[kGnnLayers], w16 + kGnnHeadOff + head * kGnnHeadSize, n, b.s);
   GNN_HIP(hipGetLastError());
   return QBE_OK;
 }
@@ -349,30 +356,33 @@ static int upload_graph(Gnn& g, GnnBufs& b, int n, const int* rp, const int* col
   return QBE_OK;
 }
 
-int gnn_score(Gnn& g, void* stream, int n, const int* rp, const int* col, const float* feats, float* scores) {
+int gnn_score(Gnn& g, void* stream, int head, int n, const int* rp, const int* col, const float* feats,
+              float* scores) {
   hipStream_t st = (hipStream_t)stream;
   GnnBufs b{};
   int rc = upload_graph(g, b, n, rp, col, feats, 0, nullptr, nullptr, st);
   if (rc) return rc;
-  if ((rc = gnn_forward(g, b, n, st))) return rc;
+  if ((rc = gnn_forward(g, b, n, head, st))) return rc;
   GNN_HIP(hipMemcpyAsync(scores, b.s, (size_t)n * 4, hipMemcpyDeviceToHost, st));
   GNN_HIP(hipStreamSynchronize(st));
   return QBE_OK;
 }
 
-int gnn_train_step(Gnn& g, void* stream, int n, const int* rp, const int* col, const float* feats, int nc,
-                   const int* cand, const float* y, float lr, float* loss_out, float* grads_out) {
+int gnn_train_step(Gnn& g, void* stream, int head, int n, const int* rp, const int* col, const float* feats,
+                   int nc, const int* cand, const float* y, float lr, float* loss_out, float* grads_out) {
   hipStream_t st = (hipStream_t)stream;
   GnnBufs b{};
   int rc = upload_graph(g, b, n, rp, col, feats, nc, cand, y, st);
   if (rc) return rc;
-  if ((rc = gnn_forward(g, b, n, st))) return rc;
+  if ((rc = gnn_forward(g, b, n, head, st))) return rc;
   const __half* w16 = (const __half*)g.d_p16;
   float* grad = (float*)g.d_g;
   gnn_loss<<<1, 256, 0, st>>>(b.s, b.cand, b.y, nc, n, b.dS, b.loss);
-  // head
-  gnn_head_back_w<<<1, kGnnHidden + 1, 0, st>>>(b.dS, b.H[kGnnLayers], n, grad + kGnnHeadOff);
-  gnn_head_back_x<<<blocks((int64_t)n * kGnnHidden), 256, 0, st>>>(b.dS, w16 + kGnnHeadOff, n, b.dA);
+  // heads: the loss reaches only the scored head; the other's gradient is 0
+  const int hoff = kGnnHeadOff + head * kGnnHeadSize;
+  gnn_zero<<<1, 256, 0, st>>>(grad + kGnnHeadOff, kGnnHeads * kGnnHeadSize);
+  gnn_head_back_w<<<1, kGnnHidden + 1, 0, st>>>(b.dS, b.H[kGnnLayers], n, grad + hoff);
+  gnn_head_back_x<<<blocks((int64_t)n * kGnnHidden), 256, 0, st>>>(b.dS, w16 + hoff, n, b.dA);
   // layers, last to first; dA holds dH_{l+1}
   float* dH = b.dA;
   float* dHs = b.dB;

@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <functional>
 #include <stdexcept>
 #include <unordered_map>
 
@@ -401,33 +402,56 @@ std::vector<int> anytime_order(const Graph& g, int tries, uint64_t seed) {
   return best;
 }
 
-Deletion greedy_deletion(const Graph& g0, const std::vector<int>& order, int m, int target_width,
-                         int score, int recompute_every, int tries, uint64_t seed) {
+Deletion greedy_deletion_with(const Graph& g0, const std::vector<int>& order, const DeletionStop& stop,
+                              const PickFn& pick, int recompute_every, int tries, uint64_t seed) {
   check_order(g0, order);
+  if (stop.m < 0 && !stop.width_rule && stop.mem_cap == 0)
+    throw std::invalid_argument("m < 0 needs a target width or a memory cap");
+  if (stop.mem_cap && !stop.tensor_vars) throw std::invalid_argument("a memory cap needs the tensors");
   Graph g = g0;
   Deletion d;
   d.reduced_order = order;
+  auto peak = [&]() {
+    return schedule_cost(build_schedule(g0.n, *stop.tensor_vars, d.reduced_order, d.mu)).peak_bytes;
+  };
   while (!d.reduced_order.empty()) {
-    if (m >= 0 && (int)d.mu.size() >= m) break;
-    if (m < 0 && width_of_order(g, d.reduced_order) <= target_width) break;
-    int u;
-    switch (score) {
-      case SCORE_TREE_TRIMMING: u = tree_trimming_pick(g, d.reduced_order); break;
-      case SCORE_DEGREE: u = degree_pick(g, d.reduced_order); break;
-      case SCORE_TW_REDUCTION: u = tw_reduction_pick(g, d.reduced_order); break;
-      case SCORE_BETWEENNESS: u = betweenness_pick(g, d.reduced_order); break;
-      default: throw std::invalid_argument("unknown score");
+    if (stop.m >= 0) {
+      if ((int)d.mu.size() >= stop.m) break;
+    } else {
+      const bool w_ok = !stop.width_rule || width_of_order(g, d.reduced_order) <= stop.target_width;
+      if (w_ok && (stop.mem_cap == 0 || peak() <= stop.mem_cap)) break;
     }
+    const int u = pick(g, d.reduced_order);
+    if (u < 0 || u >= g.n || !g.present[u]) throw std::logic_error("score picked an absent vertex");
     g.remove_vertex(u);
     d.reduced_order.erase(std::find(d.reduced_order.begin(), d.reduced_order.end(), u));
     d.mu.push_back(u);
     if (recompute_every > 0 && d.mu.size() % (size_t)recompute_every == 0 && !d.reduced_order.empty())
       d.reduced_order = recover_order(clique_tree(g, anytime_order(g, tries, seed)));
   }
-  if (m >= 0 && (int)d.mu.size() < m)
+  if (stop.m >= 0 && (int)d.mu.size() < stop.m)
     throw std::invalid_argument("cannot remove more vertices than the graph has");
   d.tau = width_of_order(g, d.reduced_order);
   return d;
+}
+
+PickFn score_pick(int score) {
+  switch (score) {
+    case SCORE_TREE_TRIMMING: return tree_trimming_pick;
+    case SCORE_DEGREE: return degree_pick;
+    case SCORE_TW_REDUCTION: return tw_reduction_pick;
+    case SCORE_BETWEENNESS: return betweenness_pick;
+    default: throw std::invalid_argument("unknown score");
+  }
+}
+
+Deletion greedy_deletion(const Graph& g0, const std::vector<int>& order, int m, int target_width,
+                         int score, int recompute_every, int tries, uint64_t seed) {
+  DeletionStop stop;
+  stop.m = m;
+  stop.width_rule = m < 0;
+  stop.target_width = target_width;
+  return greedy_deletion_with(g0, order, stop, score_pick(score), recompute_every, tries, seed);
 }
 
 // --------------------------------------------------------------- schedule --
@@ -621,6 +645,127 @@ std::vector<float> vertex_features(const Graph& g, const std::vector<int>& order
     r[7] = 1.f;
   }
   return f;
+}
+
+// ------------------------------------------------------ learned proposal --
+
+// Fill and degree of every present vertex of g (fill: missing edges among
+// the vertex's neighbours).
+static void fill_and_degree(const Graph& g, std::vector<int64_t>& fill, std::vector<int>& deg) {
+  fill.assign(g.n, 0);
+  deg.assign(g.n, 0);
+  for (int v = 0; v < g.n; ++v) {
+    if (!g.present[v]) continue;
+    const uint64_t* rv = g.row(v);
+    int d = 0;
+    int64_t inner = 0;
+    for (int i = 0; i < g.words; ++i) {
+      uint64_t x = rv[i];
+      d += __builtin_popcountll(x);
+      while (x) {
+        const int w = i * 64 + __builtin_ctzll(x);
+        x &= x - 1;
+        const uint64_t* rw = g.row(w);
+        for (int j = 0; j < g.words; ++j) inner += __builtin_popcountll(rw[j] & rv[j]);
+      }
+    }
+    deg[v] = d;
+    fill[v] = (int64_t)d * (d - 1) / 2 - inner / 2;
+  }
+}
+
+std::vector<int> min_fill_order_learned(const Graph& g0, const PrioRescore& rescore, int refresh) {
+  if (refresh < 1) throw std::invalid_argument("refresh must be >= 1");
+  Graph g = g0;
+  std::vector<int64_t> fill;
+  std::vector<int> deg;
+  std::vector<float> prio(g.n, 0.f);
+  std::vector<int> order;
+  int left = g.count();
+  for (int step = 0; left > 0; ++step, --left) {
+    if (step % refresh == 0) rescore(g, prio);
+    fill_and_degree(g, fill, deg);
+    int u = -1;
+    for (int v = 0; v < g.n; ++v) {
+      if (!g.present[v]) continue;
+      if (u < 0 || fill[v] < fill[u] ||
+          (fill[v] == fill[u] && (prio[v] < prio[u] || (prio[v] == prio[u] && deg[v] < deg[u]))))
+        u = v;  // ascending ids: a full tie keeps the smaller id
+    }
+    order.push_back(u);
+    eliminate_vertex(g, u, g.neighbours(u));
+  }
+  return order;
+}
+
+Graph eliminated_prefix(const Graph& g0, const std::vector<int>& order, int k) {
+  if (k < 0 || k > (int)order.size()) throw std::invalid_argument("bad elimination state");
+  Graph g = g0;
+  for (int i = 0; i < k; ++i) {
+    const int u = order[i];
+    if (u < 0 || u >= g.n || !g.present[u]) throw std::invalid_argument("bad order");
+    eliminate_vertex(g, u, g.neighbours(u));
+  }
+  return g;
+}
+
+std::vector<int> min_fill_ties(const Graph& g) {
+  std::vector<int64_t> fill;
+  std::vector<int> deg;
+  fill_and_degree(g, fill, deg);
+  int64_t best = -1;
+  std::vector<int> out;
+  for (int v = 0; v < g.n; ++v) {
+    if (!g.present[v]) continue;
+    if (best < 0 || fill[v] < best) {
+      best = fill[v];
+      out.clear();
+    }
+    if (fill[v] == best) out.push_back(v);
+  }
+  return out;
+}
+
+std::vector<int> sample_ids(std::vector<int> ids, int max_count, uint64_t seed) {
+  if ((int)ids.size() <= max_count) return ids;
+  SplitMix64 rng{seed};
+  for (int i = 0; i < max_count; ++i) {
+    const int j = i + (int)(rng.next() % (uint64_t)(ids.size() - i));
+    std::swap(ids[i], ids[j]);
+  }
+  ids.resize(max_count);
+  std::sort(ids.begin(), ids.end());
+  return ids;
+}
+
+std::vector<double> elim_labels(const Graph& state, const std::vector<int>& prefix,
+                                const std::vector<std::vector<int>>& tensor_vars, const std::vector<int>& cand) {
+  std::vector<double> y;
+  for (int c : cand) {
+    Graph g = state;
+    eliminate_vertex(g, c, g.neighbours(c));
+    std::vector<int> full = prefix;
+    full.push_back(c);
+    for (int v : min_fill_order(g)) full.push_back(v);
+    const ScheduleCost cost = schedule_cost(build_schedule(state.n, tensor_vars, full, {}));
+    y.push_back(std::log2((double)std::max<uint64_t>(cost.flops, 1)));
+  }
+  return y;
+}
+
+std::vector<double> slice_labels(const Graph& g, const std::vector<int>& order, const std::vector<int>& mu,
+                                 const std::vector<std::vector<int>>& tensor_vars, const std::vector<int>& cand) {
+  std::vector<double> y;
+  for (int c : cand) {
+    std::vector<int> red;
+    for (int v : order)
+      if (v != c) red.push_back(v);
+    std::vector<int> m2 = mu;
+    m2.push_back(c);
+    const ScheduleCost cost = schedule_cost(build_schedule(g.n, tensor_vars, red, m2));
+    y.push_back(std::log2((double)std::max<uint64_t>(cost.flops, 1)) + (double)m2.size());
+  }
+  return y;
 }
 
 }  // namespace qbe

@@ -10,6 +10,7 @@
 #pragma once
 
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -86,6 +87,22 @@ std::vector<int> anytime_order(const Graph& g, int tries, uint64_t seed);
 // of anytime_order(reduced graph, tries, seed).
 Deletion greedy_deletion(const Graph& g, const std::vector<int>& order, int m, int target_width,
                          int score, int recompute_every = 0, int tries = 1, uint64_t seed = 0);
+// Alg. 2 with the score f as a function (the argmax of Alg. 2's loop: it
+// returns the vertex to remove from the graph and its order) and stopping
+// rules: m >= 0 removes exactly m vertices; m < 0 removes until the width of
+// the reduced order is <= target_width (when width_rule) and the peak live
+// bytes per slice of its schedule are <= mem_cap (when mem_cap > 0).
+using PickFn = std::function<int(const Graph&, const std::vector<int>&)>;
+struct DeletionStop {
+  int m = 0;
+  bool width_rule = false;
+  int target_width = 0;
+  uint64_t mem_cap = 0;
+  const std::vector<std::vector<int>>* tensor_vars = nullptr;  // for the memory cap
+};
+PickFn score_pick(int score);
+Deletion greedy_deletion_with(const Graph& g, const std::vector<int>& order, const DeletionStop& stop,
+                              const PickFn& pick, int recompute_every = 0, int tries = 1, uint64_t seed = 0);
 
 // ---------------------------------------------------------------- schedule --
 
@@ -130,5 +147,30 @@ ScheduleCost schedule_cost(const Schedule& s);
 // constant.  Rows for vertices outside the order are zero.
 constexpr int kFeatures = 8;
 std::vector<float> vertex_features(const Graph& g, const std::vector<int>& order);
+
+// ------------------------------------------------------ learned proposal --
+
+// Greedy min-fill whose ties in fill go to the smaller priority, then the
+// smaller degree, then the smaller id; rescore(g, prio) sets the priorities
+// of the current elimination graph g (eliminated vertices absent, fill edges
+// in) before the first elimination and after every `refresh` eliminations.
+// With equal priorities this is min_fill_order.
+using PrioRescore = std::function<void(const Graph&, std::vector<float>&)>;
+std::vector<int> min_fill_order_learned(const Graph& g, const PrioRescore& rescore, int refresh);
+// The elimination graph after eliminating order[0 .. k).
+Graph eliminated_prefix(const Graph& g, const std::vector<int>& order, int k);
+// The present vertices of minimum fill (ascending ids).
+std::vector<int> min_fill_ties(const Graph& g);
+// At most max_count of ids (a SplitMix64(seed) partial shuffle), ascending.
+std::vector<int> sample_ids(std::vector<int> ids, int max_count, uint64_t seed);
+// Labels of the learned proposal, the method's own exact costs (cost model):
+// elimination -- for each candidate c of the state (prefix eliminated),
+// log2 of the total FLOPs of the order prefix + c + greedy min-fill of the
+// rest (no slicing); slicing -- log2 of the total FLOPs (2^(|mu| + 1)
+// slices) of the reduced order without c and the sliced set mu + c.
+std::vector<double> elim_labels(const Graph& state, const std::vector<int>& prefix,
+                                const std::vector<std::vector<int>>& tensor_vars, const std::vector<int>& cand);
+std::vector<double> slice_labels(const Graph& g, const std::vector<int>& order, const std::vector<int>& mu,
+                                 const std::vector<std::vector<int>>& tensor_vars, const std::vector<int>& cand);
 
 }  // namespace qbe

@@ -185,6 +185,7 @@ struct Batch {
 constexpr int kGnnFeatures = 8;   // must equal kFeatures of the planner
 constexpr int kGnnHidden = 64;
 constexpr int kGnnLayers = 3;
+constexpr int kGnnHeads = 2;      // 0: slicing score, 1: elimination priority
 
 struct Gnn {
   int device = -1;
@@ -206,9 +207,10 @@ int gnn_get_params(const Gnn& g, float* host);
 // FP32 parameters, Adam moments and step count (a training checkpoint).
 int gnn_get_state(const Gnn& g, float* p, float* m, float* v, int* step);
 int gnn_set_state(Gnn& g, const float* p, const float* m, const float* v, int step);
-int gnn_score(Gnn& g, void* stream, int n, const int* rp, const int* col, const float* feats, float* scores);
-int gnn_train_step(Gnn& g, void* stream, int n, const int* rp, const int* col, const float* feats, int nc,
-                   const int* cand, const float* y, float lr, float* loss_out, float* grads_out);
+int gnn_score(Gnn& g, void* stream, int head, int n, const int* rp, const int* col, const float* feats,
+              float* scores);
+int gnn_train_step(Gnn& g, void* stream, int head, int n, const int* rp, const int* col, const float* feats,
+                   int nc, const int* cand, const float* y, float lr, float* loss_out, float* grads_out);
 
 // Plan compilation (program.cpp).
 void compile_plan(Plan& p);

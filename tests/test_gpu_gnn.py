@@ -41,21 +41,22 @@ def case(seed, n=40, p=0.15):
     return A, X, cand, y
 
 
-@pytest.mark.parametrize("seed", [0, 1])
-def test_forward_and_gradients_match_oracle(env, seed):
+@pytest.mark.parametrize("seed,head", [(0, "slicing"), (1, "slicing"), (2, "elimination"), (3, "elimination")])
+def test_forward_and_gradients_match_oracle(env, seed, head):
     qbe, ctx = env
     from oracle import gnn as G
-    print(f"case gnn parity seed={seed}", flush=True)
+    h = qbe.HEAD[head]
+    print(f"case gnn parity seed={seed} head={head}", flush=True)
     net = qbe.Gnn(ctx, seed=seed)
     p = net.params()
     p16 = p.astype(np.float16).astype(np.float64)  # the weights the device uses
     A, X, cand, y = case(seed)
     rp, col = csr(A)
-    s_dev = net.score(rp, col, X)
-    s_ref, _ = G.forward(p16, A, X.astype(np.float64))
+    s_dev = net.score(rp, col, X, head=head)
+    s_ref, _ = G.forward(p16, A, X.astype(np.float64), h)
     assert np.max(np.abs(s_dev - s_ref)) <= 1e-4 * max(1.0, np.max(np.abs(s_ref)))
-    loss_dev, g_dev = net.train_step(rp, col, X, cand, y, lr=0.0, want_grads=True)
-    loss_ref, g_ref = G.loss_and_grad(p16, A, X.astype(np.float64), cand, y.astype(np.float64))
+    loss_dev, g_dev = net.train_step(rp, col, X, cand, y, lr=0.0, want_grads=True, head=head)
+    loss_ref, g_ref = G.loss_and_grad(p16, A, X.astype(np.float64), cand, y.astype(np.float64), h)
     assert abs(loss_dev - loss_ref) <= 1e-4 * max(1.0, loss_ref)
     assert np.max(np.abs(g_dev - g_ref)) <= 1e-4 * max(1.0, np.max(np.abs(g_ref)))
     assert np.array_equal(net.params(), p)  # lr = 0 leaves the weights alone
