@@ -1,11 +1,12 @@
 """Float64 reference of the learned proposal's network -- TEST INFRASTRUCTURE.
 
 Forward and hand-written backward of the message-passing network used to
-score variables for slicing (see the library header for the architecture):
-three layers H' = relu(H Ws + mean_{w in N(v)} H[w] Wn + b) of width 64 over
-8 input features, a linear head s = H w + c, and the loss
-mean_i (s[cand_i] - y_i)^2.  Parameters are the flat vector of the library
-(layer by layer Ws[din][64], Wn[din][64], b[64]; then w[64], c).  The
+score variables for slicing and for elimination (see the library header for
+the architecture): three layers H' = relu(H Ws + mean_{w in N(v)} H[w] Wn + b)
+of width 64 over 8 input features shared by two linear heads s_h = H w_h +
+c_h (0: slicing, 1: elimination), and the loss mean_i (s_h[cand_i] - y_i)^2.
+Parameters are the flat vector of the library (layer by layer Ws[din][64],
+Wn[din][64], b[64]; then head 0 (w[64], c), then head 1 (w[64], c)).  The
 backward pass is pinned by central finite differences in the tests.
 """
 from __future__ import annotations
@@ -13,9 +14,10 @@ from __future__ import annotations
 import numpy as np
 
 F, H, L = 8, 64, 3
+HEADS = 2
 
 
-def unpack(p):
+def unpack(p, head=0):
     p = np.asarray(p, dtype=np.float64)
     layers = []
     o = 0
@@ -25,13 +27,14 @@ def unpack(p):
         wn = p[o:o + din * H].reshape(din, H); o += din * H
         b = p[o:o + H]; o += H
         layers.append((ws, wn, b))
+    o += head * (H + 1)
     w = p[o:o + H]; o += H
     c = p[o]
     return layers, w, c
 
 
 def n_params():
-    return sum(2 * (F if l == 0 else H) * H + H for l in range(L)) + H + 1
+    return sum(2 * (F if l == 0 else H) * H + H for l in range(L)) + HEADS * (H + 1)
 
 
 def mean_agg(A, X):
@@ -44,8 +47,8 @@ def mean_agg(A, X):
     return M
 
 
-def forward(p, A, X):
-    layers, w, c = unpack(p)
+def forward(p, A, X, head=0):
+    layers, w, c = unpack(p, head)
     Hs, Ms, Zs = [np.asarray(X, dtype=np.float64)], [], []
     for ws, wn, b in layers:
         M = mean_agg(A, Hs[-1])
@@ -57,9 +60,9 @@ def forward(p, A, X):
     return s, (Hs, Ms, Zs)
 
 
-def loss_and_grad(p, A, X, cand, y):
-    layers, w, c = unpack(p)
-    s, (Hs, Ms, Zs) = forward(p, A, X)
+def loss_and_grad(p, A, X, cand, y, head=0):
+    layers, w, c = unpack(p, head)
+    s, (Hs, Ms, Zs) = forward(p, A, X, head)
     cand = np.asarray(cand)
     d = s[cand] - np.asarray(y, dtype=np.float64)
     loss = float(np.mean(d ** 2))
@@ -85,5 +88,6 @@ def loss_and_grad(p, A, X, cand, y):
     flat = []
     for gws, gwn, gb in grads:
         flat += [gws.ravel(), gwn.ravel(), gb]
-    flat += [gw, np.array([gc])]
+    for h in range(HEADS):  # the loss reaches only the scored head
+        flat += [gw, np.array([gc])] if h == head else [np.zeros(H), np.zeros(1)]
     return loss, np.concatenate(flat)
