@@ -215,6 +215,9 @@ std::vector<FusedNode> merge_buckets(const Schedule& s, bool merge) {
 // absorbed result never goes to device memory.  Up to kChainSumMax summed
 // variables, kMaxOps operands and operands of rank kMergedMaxRank per launch.
 constexpr int kChainMinRank = 12;
+// Results of this rank or less are not placed in reused arena space (their
+// total is small; see compile_plan).
+constexpr int kOwnSpaceRank = 8;
 constexpr int kChainSumMax = 4;
 
 struct StepNode {
@@ -417,6 +420,7 @@ void compile_plan(Plan& p) {
   const int nsteps = (int)s.steps.size();
   std::vector<int64_t> out_off(nsteps, -1);
   Arena arena;
+  int64_t own = 0;  // elements of the small results' own space
   p.steps.clear();
   p.scalar_arena.clear();
   auto input_op = [&](int t, const std::vector<int>& uni) {
@@ -558,17 +562,37 @@ void compile_plan(Plan& p) {
       }
     }
     const int64_t osz = int64_t(1) << rb;
-    out_off[k] = arena.alloc(osz, align_for(osz));
+    if (rb <= kOwnSpaceRank) {
+      // small results get space of their own after the arena (encoded as
+      // -(offset + 1) until the arena's size is known): reusing freed space
+      // would order otherwise independent launches behind one another
+      own = (own + align_for(osz) - 1) / align_for(osz) * align_for(osz);
+      out_off[k] = -(own + 1);
+      own += osz;
+    } else {
+      out_off[k] = arena.alloc(osz, align_for(osz));
+    }
     sp.out_base = out_off[k];
     sp.n_ops = (int)ops.size();
     for (size_t i = 0; i < ops.size(); ++i) sp.ops[i] = ops[i];
     p.steps.push_back(sp);
     for (auto& tb : temps) arena.release(tb.first, tb.second);
     for (const auto& op : node.factors)
-      if (op.kind == 'r') arena.release(out_off[op.id], int64_t(1) << op.vars.size());
+      if (op.kind == 'r' && out_off[op.id] >= 0) arena.release(out_off[op.id], int64_t(1) << op.vars.size());
     if (rb == 0) p.scalar_arena.push_back(out_off[k]);
   }
-  p.arena_per_slice = std::max<int64_t>(arena.top, 1);
+  // place the small results' own space after the arena
+  const int64_t own_base = (arena.top + 63) / 64 * 64;
+  auto place = [&](int64_t& off) {
+    if (off < 0) off = own_base + (-off - 1);
+  };
+  for (StepProg& sp : p.steps) {
+    place(sp.out_base);
+    for (int i = 0; i < sp.n_ops; ++i)
+      if (!sp.ops[i].is_input) place(sp.ops[i].base);
+  }
+  for (int64_t& off : p.scalar_arena) place(off);
+  p.arena_per_slice = std::max<int64_t>(own > 0 ? own_base + own : arena.top, 1);
   p.step_bytes_per_slice = 0;
   for (const StepProg& sp : p.steps) {
     int64_t b = int64_t(1) << (sp.out_rank >= 0 ? sp.out_rank : -sp.out_rank);
