@@ -760,7 +760,10 @@ def main():
     ap.add_argument("--pmc-c3", choices=["fp32", "bf16x6", "bf16x3", "plain_fp32"],
                     help="for hardware-counter runs: the copy calibration, then the headline plan in this form "
                          "(sliced set from --mu, else tree-trimming), autotuned, and two contractions")
-    ap.add_argument("--mu", default="", help="comma-separated sliced set for --pmc-c3")
+    ap.add_argument("--plan", default="min_fill+tt_rec2",
+                    help="for --pmc-c3: a candidate plan of the headline search without the network "
+                         "(min_fill or anytime8, + tt or tt_rec2)")
+    ap.add_argument("--reps", type=int, default=2, help="contractions in a --pmc-c3 run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: the contraction runs on a single MI355X "
@@ -794,12 +797,10 @@ def main():
         return
     if args.pmc_c3:
         qm, m = c3_model(qbe)
-        order = qbe.qbe_order_min_fill(qm)
-        if args.mu:
-            mu = [int(v) for v in args.mu.split(",")]
-        else:
-            mu, _, _ = qbe.qbe_slice(qm, order, m)
-        pi = [v for v in order if v not in set(mu)]
+        cands = plan_candidates(qbe, qm, m, None)
+        if args.plan not in cands:
+            raise SystemExit(f"--plan must be one of {sorted(cands)}")
+        mu, pi, _ = cands[args.plan]
         plain = args.pmc_c3 == "plain_fp32"
         plan = qbe.Plan(qm, pi, mu, ctx=ctx, exec="per_step", precision="fp32" if plain else args.pmc_c3,
                         merge=not plain)
@@ -808,12 +809,12 @@ def main():
         if not plain:
             plan.autotune(ws)
         torch.cuda.synchronize()
-        for _ in range(2):
+        for _ in range(args.reps):
             qbe.qbe_contract_async(ctx, plan, ws, out)
         torch.cuda.synchronize()
         got = complex(*out.cpu().numpy())
-        log(f"[bench] pmc c3 {args.pmc_c3} mu {mu}: {plan.stats()['n_launches'] + 2} dispatches per contraction, "
-            f"rel err {abs(got - golden(C3)) / abs(golden(C3)):.2e}")
+        log(f"[bench] pmc c3 {args.pmc_c3} plan {args.plan} mu {mu}: {plan.stats()['n_launches'] + 2} dispatches "
+            f"per contraction, rel err {abs(got - golden(C3)) / abs(golden(C3)):.2e}")
         return
     if args.only == "c2":
         print(json.dumps(bench_fused_c2(torch, qbe, ctx, args.steps, args.warmup)), flush=True)

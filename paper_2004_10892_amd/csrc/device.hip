@@ -250,7 +250,6 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch a) {
 template <int K, int EPT>
 __global__ __launch_bounds__(kBlock) void msum_kernel(StepLaunch a) {
   const int tid = threadIdx.x, lane = tid & 63;
-  const int r = a.r;
   const TileSetup<K, EPT> ts(a, (uint32_t)tid);
   const int nu = 1 << a.n_sum;
   for (int64_t q0 = blockIdx.x; q0 < ts.n_super; q0 += 64 * (int64_t)gridDim.x) {
