@@ -240,19 +240,59 @@ STEP_SOURCES = ("device.hip", "device_common.hpp", "qbe_internal.hpp", "program.
 # 2.000 and WRITE_SIZE x 1.000 bytes (the 256 MiB device-copy calibration);
 # dominant: the same for the dominant kernel's launch.  Keyed by the
 # sources' digest and the plan's sliced set.
-C3_COUNTERS = {"sources_sha256": None, "mu": None}
+C3_COUNTERS = {
+    "sources_sha256": "fe9d5ab366c9af0446edfc2c61a1193f00f057fecc52c0ef2769edf1340b5f3e",
+    "plan": "min_fill+tt_rec2",
+    "mu": [
+        119,
+        353,
+        220,
+        183,
+        66,
+        335,
+        486,
+        169,
+        453,
+        398
+    ],
+    "fp32": {
+        "mfma_util": 0.0011540529700733721,
+        "mfma_busy_cycles": 4194304.0,
+        "gui_active": 28393844.0,
+        "amplitude": {
+            "bytes": 1204353824,
+            "fetch_kib": 307667.4375,
+            "write_kib": 560791.90625
+        },
+        "dominant": {
+            "launch": 65,
+            "kernel": "qbe::msum_pair_kernel<8, 2>",
+            "bytes": 102640640,
+            "fetch_kib": 33733.5,
+            "write_kib": 32768.0
+        }
+    },
+    "bf16x6": {
+        "mfma_util": 0.001139092084373741,
+        "mfma_busy_cycles": 4194304.0,
+        "gui_active": 28766770.0
+    },
+    "plain_fp32_same_plan": {
+        "mfma_util": 0.00012238179777516406
+    }
+}
 
 
 def step_source_digest():
     return source_digest(STEP_SOURCES)
 
 
-def c3_counters(precision, mu):
+def c3_counters(precision, mu, plan=None):
     """The committed counters of the headline plan, or (None, reason)."""
     if C3_COUNTERS.get("sources_sha256") != step_source_digest():
         return None, "per-step sources differ from those the counters were taken on"
-    if C3_COUNTERS.get("mu") != list(mu):
-        return None, "sliced set differs from the one the counters were taken on"
+    if C3_COUNTERS.get("mu") != list(mu) or (plan is not None and C3_COUNTERS.get("plan") != plan):
+        return None, "the plan differs from the one the counters were taken on"
     rec = C3_COUNTERS.get(precision)
     if not rec:
         return None, f"no counters taken for {precision}"
@@ -466,9 +506,13 @@ def bench_headline(torch, qbe, ctx, steps, warmup, net, n_timed=6):
     total_ms = sum(r["ms"] for r in prof)
     amp_bytes = st["step_bytes_per_slice"] * plan.n_slices
     launch_flops = sum(r["flops"] for r in prof)
-    cnt, why = c3_counters(chosen, mu)
+    cnt, why = c3_counters(chosen, mu, src)
+    dom_cnt = cnt.get("dominant") if cnt else None
+    if dom_cnt and dom_cnt["launch"] != dom["index"]:
+        dom_cnt, why = None, f"the counters' dominant launch ({dom_cnt['launch']}) is not this run's"
     roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
-            "traffic": cnt["dominant"]["bytes"] if cnt else None,
+            "traffic": dom_cnt["bytes"] if dom_cnt else None,
+            "traffic_kernel": dom_cnt["kernel"] if dom_cnt else None,
             "kernel": f"launch {dom['index']}: {dom['kind']}, {dom['n_ops']} operands, result rank "
                       f"{dom['out_rank']}, {dom['n_sum']} summed, {'MFMA' if dom['mfma'] else 'VALU'}",
             "launch_ms": dom["ms"], "algorithmic_bytes_per_launch": dom["bytes"],
@@ -479,16 +523,18 @@ def bench_headline(torch, qbe, ctx, steps, warmup, net, n_timed=6):
                           "ms": forms[chosen]["ms_per_amplitude"],
                           "achieved_GB_per_s": amp_bytes / (forms[chosen]["ms_per_amplitude"] * 1e-3) / 1e9,
                           "frac": amp_bytes / (forms[chosen]["ms_per_amplitude"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                          "traffic": cnt["amplitude"]["bytes"] if cnt else None,
+                          "traffic": cnt["amplitude"]["bytes"] if cnt and "amplitude" in cnt else None,
                           "launch_flops": launch_flops, "cost_model_flops": st["flops_per_slice"] * plan.n_slices},
             "note": "achieved = the dominant launch's algorithmic bytes (each operand read once, its result "
                     "written once, per slice x slices) / its average duration from HIP events around each launch "
                     "of whole contractions (qbe_plan_profile); amplitude: the same count over all launches "
                     "(merged chains keep their intermediates on chip) / the step time; cost_model_bytes: one "
                     "launch per bucket; traffic: FETCH_SIZE and WRITE_SIZE counters with the copy calibration"
-                    + ("" if cnt else f" (null: {why})")}
+                    + ("" if dom_cnt else f" (null: {why})")}
     mfma = {"value": cnt["mfma_util"] if cnt else None,
             "plain_fp32": C3_COUNTERS.get("plain_fp32", {}).get("mfma_util") if cnt else None,
+            "ceiling": "bucket contractions of complex64 operands carry 1.6-4 flop/B (cost model); at 8 TB/s "
+                       "that is at most ~30 TFLOP/s, 19% of the FP32 MFMA peak even if every flop ran on MFMA",
             "source": "SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / 8 x 256 CUs x 4 SIMDs) over all dispatches of "
                       "one contraction" + ("" if cnt else f" (null: {why})")}
     top = sorted(prof, key=lambda r: -r["ms"])[:8]
