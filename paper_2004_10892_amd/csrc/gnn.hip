@@ -5,7 +5,9 @@
 //   H_{l+1} = relu(H_l W_s + mean_{w in N(v)} H_l[w] W_n + b)      (width 64)
 // shared by two linear heads s_h = H_3 w_h + c_h: head 0 scores variables
 // for slicing (Alg. 2), head 1 for elimination (ties of greedy min-fill).
-// Weights are FP16 in the forward and
+// The dense layers and their gradients run on MFMA (v_mfma_f32_16x16x4f32:
+// FP32 activations times the FP16 weights widened exactly to FP32, staged
+// in LDS).  Weights are FP16 in the forward and
 // backward passes (FP32 master copies for the optimizer); every sum is
 // accumulated in FP32.  Training minimises the mean squared error between s
 // and a target at a set of candidate variables.  All reductions run in a
@@ -76,23 +78,89 @@ __global__ void gnn_agg_t(const float* __restrict__ dHs, const float* __restrict
   dH[i] = s;
 }
 
-// Z[v][o] = b[o] + sum_k Hin[v][k] Ws[k][o] + Min[v][k] Wn[k][o]; H = relu(Z).
-__global__ void gnn_dense(const float* __restrict__ Hin, const float* __restrict__ Min,
-                          const __half* __restrict__ w, int din, int n, float* __restrict__ Z,
-                          float* __restrict__ Hout) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)n * kGnnHidden) return;
-  const int v = (int)(i / kGnnHidden), o = (int)(i % kGnnHidden);
-  const __half* Ws = w;
-  const __half* Wn = w + din * kGnnHidden;
-  const __half* b = w + 2 * din * kGnnHidden;
-  float z = __half2float(b[o]);
-  const float* hv = Hin + (int64_t)v * din;
-  const float* mv = Min + (int64_t)v * din;
-  for (int k = 0; k < din; ++k)
-    z += hv[k] * __half2float(Ws[k * kGnnHidden + o]) + mv[k] * __half2float(Wn[k * kGnnHidden + o]);
-  Z[i] = z;
-  Hout[i] = z > 0.f ? z : 0.f;
+// The dense layer as matrix products on MFMA: [H | M] (n x 2 din, FP32)
+// times [Ws ; Wn] (2 din x 64, the FP16 weights widened to FP32 -- exact),
+// v_mfma_f32_16x16x4f32 with FP32 accumulation.  A workgroup stages the
+// layer's weights in LDS once and its four waves take 16 vertices each; a
+// wave accumulates its 16 x 64 block in four 16 x 16 tiles over K in steps
+// of 4.  Lane l supplies A[row l % 16][k = l / 16] and B[k][col l % 16] and
+// receives C[4 (l / 16) + j][l % 16], j = 0..3 (the layout mm_kernel uses).
+typedef float gnn_f4 __attribute__((ext_vector_type(4)));
+constexpr int kGnnRows = 64;  // vertices per workgroup (4 waves x 16)
+
+__global__ __launch_bounds__(256) void gnn_dense_mfma(const float* __restrict__ Hin, const float* __restrict__ Min,
+                                                      const __half* __restrict__ w, int din, int n,
+                                                      float* __restrict__ Z, float* __restrict__ Hout) {
+  __shared__ float wl[2 * kGnnHidden * kGnnHidden];  // [k][o], k < din: Ws, else Wn
+  __shared__ float bl[kGnnHidden];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < 2 * din * kGnnHidden; i += 256) wl[i] = __half2float(w[i]);
+  if (tid < kGnnHidden) bl[tid] = __half2float(w[2 * din * kGnnHidden + tid]);
+  __syncthreads();
+  const int lane = tid & 63, row = lane & 15, grp = lane >> 4;
+  const int v0 = blockIdx.x * kGnnRows + (tid >> 6) * 16;
+  if (v0 >= n) return;
+  const int vr = v0 + row;
+  const bool ok = vr < n;
+  gnn_f4 acc[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) acc[c] = gnn_f4{0.f, 0.f, 0.f, 0.f};
+  for (int kb = 0; kb < 2 * din; kb += 4) {
+    const int k = kb + grp;
+    const float a = ok ? (k < din ? Hin[(int64_t)vr * din + k] : Min[(int64_t)vr * din + (k - din)]) : 0.f;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, wl[k * kGnnHidden + c * 16 + row], acc[c], 0, 0, 0);
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int v = v0 + 4 * grp + j;
+      if (v >= n) continue;
+      const int o = c * 16 + row;
+      const float z = acc[c][j] + bl[o];
+      Z[(int64_t)v * kGnnHidden + o] = z;
+      Hout[(int64_t)v * kGnnHidden + o] = z > 0.f ? z : 0.f;
+    }
+}
+
+// dHs = dZ Ws^T and dM = dZ Wn^T (din = 64) on MFMA: A = dZ (n x 64), B[o][k]
+// = the weight of input k to output o; a wave computes 16 vertices x 128
+// columns (64 of dHs, 64 of dM) in eight 16 x 16 tiles.
+__global__ __launch_bounds__(256) void gnn_dense_back_x_mfma(const float* __restrict__ dZ,
+                                                             const __half* __restrict__ w, int n,
+                                                             float* __restrict__ dHs, float* __restrict__ dM) {
+  __shared__ float wl[2 * kGnnHidden * kGnnHidden];  // [k][o] as in the forward
+  const int tid = threadIdx.x;
+  for (int i = tid; i < 2 * kGnnHidden * kGnnHidden; i += 256) wl[i] = __half2float(w[i]);
+  __syncthreads();
+  const int lane = tid & 63, row = lane & 15, grp = lane >> 4;
+  const int v0 = blockIdx.x * kGnnRows + (tid >> 6) * 16;
+  if (v0 >= n) return;
+  const int vr = v0 + row;
+  const bool ok = vr < n;
+  gnn_f4 acc[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) acc[c] = gnn_f4{0.f, 0.f, 0.f, 0.f};
+  for (int ob = 0; ob < kGnnHidden; ob += 4) {
+    const int o = ob + grp;
+    const float a = ok ? dZ[(int64_t)vr * kGnnHidden + o] : 0.f;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      // column c * 16 + row: input k of Ws (c < 4) or of Wn (c >= 4)
+      const int k = (c & 3) * 16 + row;
+      acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, wl[((c >> 2) * kGnnHidden + k) * kGnnHidden + o], acc[c], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 8; ++c)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int v = v0 + 4 * grp + j;
+      if (v >= n) continue;
+      const int k = (c & 3) * 16 + row;
+      (c < 4 ? dHs : dM)[(int64_t)v * kGnnHidden + k] = acc[c][j];
+    }
 }
 
 __global__ void gnn_head(const float* __restrict__ H, const __half* __restrict__ w, int n, float* __restrict__ s) {
@@ -125,21 +193,12 @@ __global__ void gnn_loss(const float* __restrict__ s, const int* __restrict__ ca
   if (threadIdx.x == 0) *loss = part[0] / (float)(nc > 0 ? nc : 1);
 }
 
-// Head backward: dH[v][o] = dS[v] w[o]; g_w[o] = sum_v dS[v] H[v][o]; g_c = sum_v dS[v].
+// Head backward: dH[v][o] = dS[v] w[o] (its weight gradient: gnn_head_back_w_part).
 __global__ void gnn_head_back_x(const float* __restrict__ dS, const __half* __restrict__ w, int n,
                                 float* __restrict__ dH) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)n * kGnnHidden) return;
   dH[i] = dS[i / kGnnHidden] * __half2float(w[i % kGnnHidden]);
-}
-
-__global__ void gnn_head_back_w(const float* __restrict__ dS, const float* __restrict__ H, int n,
-                                float* __restrict__ g) {
-  const int o = threadIdx.x;  // 0..64: 64 = the bias
-  if (o > kGnnHidden) return;
-  float a = 0.f;
-  for (int v = 0; v < n; ++v) a += dS[v] * (o < kGnnHidden ? H[(int64_t)v * kGnnHidden + o] : 1.f);
-  g[o] = a;
 }
 
 // dZ = dH * (Z > 0), in place into dH.
@@ -148,42 +207,64 @@ __global__ void gnn_relu_back(float* __restrict__ dH, const float* __restrict__ 
   if (i < n && !(Z[i] > 0.f)) dH[i] = 0.f;
 }
 
-// g_Ws[k][o] = sum_v Hin[v][k] dZ[v][o]; g_Wn likewise with Min; g_b[o] = sum_v dZ[v][o].
-__global__ void gnn_dense_back_w(const float* __restrict__ Hin, const float* __restrict__ Min,
-                                 const float* __restrict__ dZ, int din, int n, float* __restrict__ g) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int total = 2 * din * kGnnHidden + kGnnHidden;
-  if (i >= total) return;
-  float a = 0.f;
-  if (i < 2 * din * kGnnHidden) {
-    const bool nb = i >= din * kGnnHidden;
-    const int j = nb ? i - din * kGnnHidden : i;
-    const int k = j / kGnnHidden, o = j % kGnnHidden;
-    const float* X = nb ? Min : Hin;
-    for (int v = 0; v < n; ++v) a += X[(int64_t)v * din + k] * dZ[(int64_t)v * kGnnHidden + o];
-  } else {
-    const int o = i - 2 * din * kGnnHidden;
-    for (int v = 0; v < n; ++v) a += dZ[(int64_t)v * kGnnHidden + o];
+// Weight gradients are sums over all vertices.  They run in two passes
+// with a fixed order: every workgroup sums one chunk of kGnnChunk vertices
+// into a partial, then gnn_sum_parts adds the partials in chunk order.
+constexpr int kGnnChunk = 64;
+
+// Partial of layer l's gradient over chunk blockIdx.x: row k of [Ws ; Wn]
+// (input k of H for k < din, of M after), P[k][o] = sum_v X[v][k] dZ[v][o]
+// on MFMA (A = a 16 x 4 tile of X^T, B = a 4 x 16 tile of dZ, vertices as
+// the contraction), and the bias row P[2 din][o] = sum_v dZ[v][o].
+__global__ __launch_bounds__(256) void gnn_dense_back_w_part(const float* __restrict__ Hin,
+                                                             const float* __restrict__ Min,
+                                                             const float* __restrict__ dZ, int din, int n,
+                                                             float* __restrict__ part) {
+  const int tid = threadIdx.x, lane = tid & 63, row = lane & 15, grp = lane >> 4;
+  const int vb0 = blockIdx.x * kGnnChunk, ve = min(n, vb0 + kGnnChunk);
+  const int rows = 2 * din, len = (rows + 1) * kGnnHidden;
+  float* P = part + (int64_t)blockIdx.x * len;
+  for (int tile = tid >> 6; tile < (rows / 16) * 4; tile += 4) {
+    const int rt = tile >> 2, ct = tile & 3;
+    const int k = rt * 16 + row;
+    gnn_f4 acc = gnn_f4{0.f, 0.f, 0.f, 0.f};
+    for (int vb = vb0; vb < ve; vb += 4) {
+      const int v = vb + grp;
+      const bool ok = v < ve;
+      const float a = ok ? (k < din ? Hin[(int64_t)v * din + k] : Min[(int64_t)v * din + (k - din)]) : 0.f;
+      const float b = ok ? dZ[(int64_t)v * kGnnHidden + ct * 16 + row] : 0.f;
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) P[(rt * 16 + 4 * grp + j) * kGnnHidden + ct * 16 + row] = acc[j];
   }
-  g[i] = a;
+  if (tid < kGnnHidden) {
+    float sb = 0.f;
+    for (int v = vb0; v < ve; ++v) sb += dZ[(int64_t)v * kGnnHidden + tid];
+    P[rows * kGnnHidden + tid] = sb;
+  }
 }
 
-// dHs[v][k] = sum_o dZ[v][o] Ws[k][o];  dM[v][k] = sum_o dZ[v][o] Wn[k][o].
-__global__ void gnn_dense_back_x(const float* __restrict__ dZ, const __half* __restrict__ w, int din, int n,
-                                 float* __restrict__ dHs, float* __restrict__ dM) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)n * din) return;
-  const int v = (int)(i / din), k = (int)(i % din);
-  const __half* Ws = w;
-  const __half* Wn = w + din * kGnnHidden;
-  float a = 0.f, c = 0.f;
-  const float* dz = dZ + (int64_t)v * kGnnHidden;
-  for (int o = 0; o < kGnnHidden; ++o) {
-    a += dz[o] * __half2float(Ws[k * kGnnHidden + o]);
-    c += dz[o] * __half2float(Wn[k * kGnnHidden + o]);
-  }
-  dHs[i] = a;
-  dM[i] = c;
+// Partial of a head's gradient over one chunk: g_w[o] = sum_v dS[v] H[v][o]
+// (o < 64), g_c = sum_v dS[v] (o = 64).
+__global__ __launch_bounds__(128) void gnn_head_back_w_part(const float* __restrict__ dS,
+                                                            const float* __restrict__ H, int n,
+                                                            float* __restrict__ part) {
+  const int o = threadIdx.x;
+  if (o > kGnnHidden) return;
+  const int vb0 = blockIdx.x * kGnnChunk, ve = min(n, vb0 + kGnnChunk);
+  float a = 0.f;
+  for (int v = vb0; v < ve; ++v) a += dS[v] * (o < kGnnHidden ? H[(int64_t)v * kGnnHidden + o] : 1.f);
+  part[(int64_t)blockIdx.x * (kGnnHidden + 1) + o] = a;
+}
+
+// g[i] = sum over the n_parts partials (chunk order) of entry i.
+__global__ void gnn_sum_parts(const float* __restrict__ part, int n_parts, int len, float* __restrict__ g) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= len) return;
+  float a = 0.f;
+  for (int c = 0; c < n_parts; ++c) a += part[(int64_t)c * len + i];
+  g[i] = a;
 }
 
 // Adam on the FP32 master weights, refreshing the FP16 copy.
@@ -281,6 +362,7 @@ struct GnnBufs {
   float* M[kGnnLayers];
   float* Z[kGnnLayers];
   float *dA, *dB, *dC;  // backward scratch (n x 64 each)
+  float* part;          // weight-gradient partials, one per chunk of vertices
 };
 
 static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
@@ -295,6 +377,8 @@ static int gnn_layout(Gnn& g, int n, int64_t nnz, int nc, GnnBufs& b) {
   need += kGnnLayers * align256((size_t)n * kGnnHidden * 4);        // H[1..L]
   need += kGnnLayers * align256((size_t)n * kGnnHidden * 4) * 2;    // M, Z (M[0] sized for 64 too)
   need += 3 * align256((size_t)n * kGnnHidden * 4);                  // dA, dB, dC
+  const size_t n_parts = ((size_t)n + kGnnChunk - 1) / kGnnChunk;
+  need += align256(n_parts * (2 * kGnnHidden + 1) * kGnnHidden * 4);  // partials
   if (need > g.ws_bytes) {
     if (g.d_ws) (void)hipFree(g.d_ws);
     g.d_ws = nullptr;
@@ -325,6 +409,7 @@ static int gnn_layout(Gnn& g, int n, int64_t nnz, int nc, GnnBufs& b) {
   b.dA = (float*)take((size_t)n * kGnnHidden * 4);
   b.dB = (float*)take((size_t)n * kGnnHidden * 4);
   b.dC = (float*)take((size_t)n * kGnnHidden * 4);
+  b.part = (float*)take(n_parts * (2 * kGnnHidden + 1) * kGnnHidden * 4);
   return QBE_OK;
 }
 
@@ -333,8 +418,8 @@ static int gnn_forward(const Gnn& g, const GnnBufs& b, int n, int head, hipStrea
   for (int l = 0; l < kGnnLayers; ++l) {
     const int din = gnn_din(l);
     gnn_agg<<<blocks((int64_t)n * din), 256, 0, st>>>(b.H[l], b.rp, b.col, n, din, b.M[l]);
-    gnn_dense<<<blocks((int64_t)n * kGnnHidden), 256, 0, st>>>(b.H[l], b.M[l], w16 + gnn_layer_off(l), din, n,
-                                                                b.Z[l], b.H[l + 1]);
+    gnn_dense_mfma<<<blocks(n, kGnnRows), 256, 0, st>>>(b.H[l], b.M[l], w16 + gnn_layer_off(l), din, n, b.Z[l],
+                                                         b.H[l + 1]);
   }
   gnn_head<<<blocks(n), 256, 0, st>>>(b.H[kGnnLayers], w16 + kGnnHeadOff + head * kGnnHeadSize, n, b.s);
   GNN_HIP(hipGetLastError());
@@ -381,7 +466,9 @@ int gnn_train_step(Gnn& g, void* stream, int head, int n, const int* rp, const i
   // heads: the loss reaches only the scored head; the other's gradient is 0
   const int hoff = kGnnHeadOff + head * kGnnHeadSize;
   gnn_zero<<<1, 256, 0, st>>>(grad + kGnnHeadOff, kGnnHeads * kGnnHeadSize);
-  gnn_head_back_w<<<1, kGnnHidden + 1, 0, st>>>(b.dS, b.H[kGnnLayers], n, grad + hoff);
+  const int n_parts = (n + kGnnChunk - 1) / kGnnChunk;
+  gnn_head_back_w_part<<<n_parts, 128, 0, st>>>(b.dS, b.H[kGnnLayers], n, b.part);
+  gnn_sum_parts<<<1, 128, 0, st>>>(b.part, n_parts, kGnnHidden + 1, grad + hoff);
   gnn_head_back_x<<<blocks((int64_t)n * kGnnHidden), 256, 0, st>>>(b.dS, w16 + hoff, n, b.dA);
   // layers, last to first; dA holds dH_{l+1}
   float* dH = b.dA;
@@ -390,10 +477,11 @@ int gnn_train_step(Gnn& g, void* stream, int head, int n, const int* rp, const i
   for (int l = kGnnLayers - 1; l >= 0; --l) {
     const int din = gnn_din(l);
     gnn_relu_back<<<blocks((int64_t)n * kGnnHidden), 256, 0, st>>>(dH, b.Z[l], (int64_t)n * kGnnHidden);
-    gnn_dense_back_w<<<blocks(2 * din * kGnnHidden + kGnnHidden), 256, 0, st>>>(b.H[l], b.M[l], dH, din, n,
-                                                                                 grad + gnn_layer_off(l));
+    gnn_dense_back_w_part<<<n_parts, 256, 0, st>>>(b.H[l], b.M[l], dH, din, n, b.part);
+    gnn_sum_parts<<<blocks(gnn_layer_size(l)), 256, 0, st>>>(b.part, n_parts, gnn_layer_size(l),
+                                                           grad + gnn_layer_off(l));
     if (l > 0) {
-      gnn_dense_back_x<<<blocks((int64_t)n * din), 256, 0, st>>>(dH, w16 + gnn_layer_off(l), din, n, dHs, dM);
+      gnn_dense_back_x_mfma<<<blocks(n, kGnnRows), 256, 0, st>>>(dH, w16 + gnn_layer_off(l), n, dHs, dM);
       // dH_l = dHs + agg^T(dM), written over the dZ buffer (no longer needed)
       gnn_agg_t<<<blocks((int64_t)n * din), 256, 0, st>>>(dHs, dM, b.rp, b.col, n, din, dH);
     }
