@@ -336,8 +336,9 @@ def plan_candidates(qbe, qm, m, net):
     the anytime heuristic standing in for the paper's tree-decomposition
     solver; with a network, min-fill with learned tie-breaking) times sliced
     sets of m variables (tree-trimming; tree-trimming with Alg. 2's order
-    recomputation after every second removal; with a network, the learned
-    score with and without it).  Returns {name: (mu, reduced_order,
+    recomputation after every k-th removal, k = 1..3, with two try counts
+    and seeds of the anytime heuristic; with a network, the learned score
+    with and without it).  Returns {name: (mu, reduced_order,
     planning_ms)}, duplicates dropped."""
     orders = {}
     t0 = time.perf_counter()
@@ -347,10 +348,15 @@ def plan_candidates(qbe, qm, m, net):
     if net is not None:
         t0 = time.perf_counter()
         orders["learned_order"] = (qbe.qbe_order_learned(qm, net, 16)[0], (time.perf_counter() - t0) * 1e3)
-    slicings = {"tt": dict(), "tt_rec2": dict(recompute_every=2, tries=8, seed=1)}
+    slicings = {"tt": dict()}
+    for k in (1, 2, 3):
+        for tries in (4, 16):
+            for seed in (1, 2):
+                slicings[f"tt_rec{k}_t{tries}_s{seed}"] = dict(recompute_every=k, tries=tries, seed=seed)
     if net is not None:
         slicings["learned"] = dict(score="learned", net=net)
-        slicings["learned_rec2"] = dict(score="learned", net=net, recompute_every=2, tries=8, seed=1)
+        for k in (1, 2):
+            slicings[f"learned_rec{k}_t16_s2"] = dict(score="learned", net=net, recompute_every=k, tries=16, seed=2)
     cands, seen = {}, set()
     for on, (order, oms) in orders.items():
         for sn, kw in slicings.items():
@@ -422,6 +428,7 @@ def bench_headline(torch, qbe, ctx, steps, warmup, net, n_timed=6):
     from paper_2004_10892_amd import learned as L
     qm, m = c3_model(qbe)
     want = golden(C3)
+    t_search = time.perf_counter()
     cands = plan_candidates(qbe, qm, m, net)
     # every candidate's schedule on the host; the most promising by a rough
     # estimate (bytes at 2.5 TB/s plus 6 us a launch) are built on the
@@ -437,7 +444,8 @@ def bench_headline(torch, qbe, ctx, steps, warmup, net, n_timed=6):
                          "estimate_ms": st_k["step_bytes_per_slice"] * (1 << m) / 2.5e9 + 0.006 * st_k["n_launches"]}
     ranked = sorted(plans_info, key=lambda k: plans_info[k]["estimate_ms"])
     to_time = ranked[:n_timed]
-    for extra in ("min_fill+tt", next((k for k in ranked if "learned" in k), None)):
+    for extra in ("min_fill+tt", next((k for k in ranked if "learned" in k), None),
+                  next((k for k in ranked if k.startswith("anytime8")), None)):
         if extra and extra not in to_time:
             to_time.append(extra)
     for k in to_time:
@@ -453,6 +461,7 @@ def bench_headline(torch, qbe, ctx, steps, warmup, net, n_timed=6):
     timed_ok = [k for k in to_time if plans_info[k]["rel_err_fp32"] <= 1e-5]
     src = min(timed_ok, key=lambda k: plans_info[k]["fp32_ms_per_amplitude"])
     mu, pi, _ = cands[src]
+    search_s = time.perf_counter() - t_search
     log(f"[bench] {C3}: plan {src}; " + ", ".join(
         f"{k} w{v['width']} {v['fp32_ms_per_amplitude']:.3f} ms" for k, v in plans_info.items()
         if "fp32_ms_per_amplitude" in v))
@@ -543,7 +552,7 @@ def bench_headline(torch, qbe, ctx, steps, warmup, net, n_timed=6):
         "forms": {p: {k: v for k, v in f.items() if not k.startswith("_")} for p, f in forms.items()},
         "plain": plain, "combined": combined, "roofline": roof, "mfma": mfma, "mu_source": src, "mu": mu,
         "plans": plans_info,
-        "planning_ms": plans_info[src]["planning_ms"],
+        "planning_ms": plans_info[src]["planning_ms"], "plan_search_s": search_s,
         "config": {"workload": C3, "rows": 7, "cols": 7, "depth": 24, "m": m, "seed": SEEDS[C3],
                    "slices": plan.n_slices, "width": st["width"], "n_vars": st["n_vars"], "n_tensors": st["n_tensors"],
                    "buckets": st["n_steps"], "launches": st["n_launches"], "merged_launches": st["n_merged_steps"],
@@ -806,9 +815,9 @@ def main():
     ap.add_argument("--pmc-c3", choices=["fp32", "bf16x6", "bf16x3", "plain_fp32"],
                     help="for hardware-counter runs: the copy calibration, then the headline plan in this form "
                          "(sliced set from --mu, else tree-trimming), autotuned, and two contractions")
-    ap.add_argument("--plan", default="min_fill+tt_rec2",
+    ap.add_argument("--plan", default="min_fill+tt_rec1_t16_s2",
                     help="for --pmc-c3: a candidate plan of the headline search without the network "
-                         "(min_fill or anytime8, + tt or tt_rec2)")
+                         "(min_fill or anytime8, + tt or tt_rec<k>_t<tries>_s<seed>)")
     ap.add_argument("--reps", type=int, default=2, help="contractions in a --pmc-c3 run")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -901,7 +910,8 @@ def main():
         "note_planning": "host planning of the chosen plan (its order and sliced set, schedule); the plan search "
                          "over candidate plans (plans) is a one-time cost per circuit; the plan is cached across "
                          "amplitudes in the timed loop",
-        "plan": h["mu_source"], "plans": h["plans"], "mu": h["mu"], "combined_form": h["combined"],
+        "plan": h["mu_source"], "plan_search_s": h["plan_search_s"], "plans": h["plans"], "mu": h["mu"],
+        "combined_form": h["combined"],
         "roofline": h["roofline"], "launches_top": h["launches_top"],
     }
     if train_info:
