@@ -402,12 +402,21 @@ def launch_profile(plan, ws, reps):
     return rows
 
 
-def time_precisions(torch, qbe, ctx, qm, mu, pi, precisions, steps, warmup, want, keep=True):
+PREFIX = "+prefix"
+
+
+def split_plan_name(name):
+    """A timed plan's name: a candidate's, with PREFIX appended when the plan
+    runs its small buckets in a fused prefix.  Returns (candidate, prefix)."""
+    return (name[:-len(PREFIX)], True) if name.endswith(PREFIX) else (name, False)
+
+
+def time_precisions(torch, qbe, ctx, qm, mu, pi, precisions, steps, warmup, want, keep=True, prefix=False):
     """The plan (mu, pi) in each precision: autotuned, then timed issued
     directly and from a HIP graph; error against the oracle amplitude."""
     forms = {}
     for prec in precisions:
-        plan = qbe.Plan(qm, pi, mu, ctx=ctx, exec="per_step", precision=prec)
+        plan = qbe.Plan(qm, pi, mu, ctx=ctx, exec="per_step", precision=prec, fused_prefix=prefix)
         ws0 = plan.workspace()
         t0 = time.perf_counter()
         plan.autotune(ws0)
@@ -448,24 +457,36 @@ def bench_headline(torch, qbe, ctx, steps, warmup, net, n_timed=6):
                   next((k for k in ranked if k.startswith("anytime8")), None)):
         if extra and extra not in to_time:
             to_time.append(extra)
+    # each without and with the fused prefix (small buckets in one
+    # LDS-resident launch)
+    timed_ms = {}
     for k in to_time:
         mu_k, pi_k, _ = cands[k]
-        plan_k = qbe.Plan(qm, pi_k, mu_k, ctx=ctx, exec="per_step")
-        ws_k = plan_k.workspace()
-        plan_k.autotune(ws_k)
-        out_k = torch.zeros(2, dtype=torch.float64, device="cuda")
-        _, ev_k = timed(torch, lambda: qbe.qbe_contract_async(ctx, plan_k, ws_k, out_k), max(3, steps // 2), 1)
-        plans_info[k]["fp32_ms_per_amplitude"] = ev_k
-        plans_info[k]["rel_err_fp32"] = abs(complex(*out_k.cpu().numpy()) - want) / abs(want)
-        del ws_k, plan_k
-    timed_ok = [k for k in to_time if plans_info[k]["rel_err_fp32"] <= 1e-5]
-    src = min(timed_ok, key=lambda k: plans_info[k]["fp32_ms_per_amplitude"])
-    mu, pi, _ = cands[src]
+        for pre in (False, True):
+            plan_k = qbe.Plan(qm, pi_k, mu_k, ctx=ctx, exec="per_step", fused_prefix=pre)
+            if pre and plan_k.stats()["prefix_buckets"] == 0:
+                continue
+            ws_k = plan_k.workspace()
+            plan_k.autotune(ws_k)
+            out_k = torch.zeros(2, dtype=torch.float64, device="cuda")
+            _, ev_k = timed(torch, lambda: qbe.qbe_contract_async(ctx, plan_k, ws_k, out_k), max(3, steps // 2), 1)
+            err_k = abs(complex(*out_k.cpu().numpy()) - want) / abs(want)
+            tag = "prefix_" if pre else ""
+            plans_info[k][f"fp32_{tag}ms_per_amplitude"] = ev_k
+            plans_info[k][f"rel_err_fp32_{tag}".rstrip("_")] = err_k
+            if pre:
+                plans_info[k]["prefix_buckets"] = plan_k.stats()["prefix_buckets"]
+                plans_info[k]["prefix_launches"] = plan_k.stats()["n_launches"]
+            if err_k <= 1e-5:
+                timed_ms[k + (PREFIX if pre else "")] = ev_k
+            del ws_k, plan_k
+    src = min(timed_ms, key=timed_ms.get)
+    base, use_prefix = split_plan_name(src)
+    mu, pi, _ = cands[base]
     search_s = time.perf_counter() - t_search
-    log(f"[bench] {C3}: plan {src}; " + ", ".join(
-        f"{k} w{v['width']} {v['fp32_ms_per_amplitude']:.3f} ms" for k, v in plans_info.items()
-        if "fp32_ms_per_amplitude" in v))
-    forms = time_precisions(torch, qbe, ctx, qm, mu, pi, ("fp32", "bf16x6", "bf16x3"), steps, warmup, want)
+    log(f"[bench] {C3}: plan {src}; " + ", ".join(f"{k} {v:.3f} ms" for k, v in sorted(timed_ms.items())))
+    forms = time_precisions(torch, qbe, ctx, qm, mu, pi, ("fp32", "bf16x6", "bf16x3"), steps, warmup, want,
+                            prefix=use_prefix)
     ok = [p for p in forms if forms[p]["within_1e-5"]]
     if not ok:
         raise SystemExit("no form of the headline workload met the 1e-5 bound")
@@ -490,19 +511,20 @@ def bench_headline(torch, qbe, ctx, steps, warmup, net, n_timed=6):
     ws_q = plan_q.workspace()
     out_q = torch.zeros(2, dtype=torch.float64, device="cuda")
     _, ev_q = timed(torch, lambda: qbe.qbe_contract_async(ctx, plan_q, ws_q, out_q), max(2, steps // 4), 1)
-    plain["same_plan"] = {"plan": src, "ms_per_amplitude": ev_q, "amplitudes_per_s": 1e3 / ev_q,
+    plain["same_plan"] = {"plan": base, "ms_per_amplitude": ev_q, "amplitudes_per_s": 1e3 / ev_q,
                           "rel_err": abs(complex(*out_q.cpu().numpy()) - want) / abs(want),
                           "launches_per_amplitude": plan_q.stats()["n_launches"] + 2}
     del ws_q, plan_q
     # the combined form with the learned proposal in the plan: the fastest
     # timed candidate that uses the network, in split-BF16 and FP32
     combined = None
-    lk = [k for k in plans_info if "learned" in k and "fp32_ms_per_amplitude" in plans_info[k]]
+    lk = [k for k in timed_ms if "learned" in k]
     if lk:
-        kb = min(lk, key=lambda k: plans_info[k]["fp32_ms_per_amplitude"])
-        mu_c, pi_c, _ = cands[kb]
+        kb = min(lk, key=timed_ms.get)
+        kb_base, kb_prefix = split_plan_name(kb)
+        mu_c, pi_c, _ = cands[kb_base]
         fc = forms if kb == src else time_precisions(torch, qbe, ctx, qm, mu_c, pi_c, ("bf16x3", "bf16x6", "fp32"),
-                                                     max(3, steps // 2), 1, want, keep=False)
+                                                     max(3, steps // 2), 1, want, keep=False, prefix=kb_prefix)
         combined = {"plan": kb, "forms": {p: {k: v for k, v in f.items() if not k.startswith("_")}
                                           for p, f in fc.items()},
                     "speedup_vs_plain": {p: ev_p / f["ms_per_amplitude"] for p, f in fc.items()},
@@ -552,7 +574,7 @@ def bench_headline(torch, qbe, ctx, steps, warmup, net, n_timed=6):
         "forms": {p: {k: v for k, v in f.items() if not k.startswith("_")} for p, f in forms.items()},
         "plain": plain, "combined": combined, "roofline": roof, "mfma": mfma, "mu_source": src, "mu": mu,
         "plans": plans_info,
-        "planning_ms": plans_info[src]["planning_ms"], "plan_search_s": search_s,
+        "planning_ms": plans_info[base]["planning_ms"], "plan_search_s": search_s,
         "config": {"workload": C3, "rows": 7, "cols": 7, "depth": 24, "m": m, "seed": SEEDS[C3],
                    "slices": plan.n_slices, "width": st["width"], "n_vars": st["n_vars"], "n_tensors": st["n_tensors"],
                    "buckets": st["n_steps"], "launches": st["n_launches"], "merged_launches": st["n_merged_steps"],
@@ -853,12 +875,13 @@ def main():
     if args.pmc_c3:
         qm, m = c3_model(qbe)
         cands = plan_candidates(qbe, qm, m, None)
-        if args.plan not in cands:
-            raise SystemExit(f"--plan must be one of {sorted(cands)}")
-        mu, pi, _ = cands[args.plan]
+        base, use_prefix = split_plan_name(args.plan)
+        if base not in cands:
+            raise SystemExit(f"--plan must be one of {sorted(cands)}, optionally followed by {PREFIX}")
+        mu, pi, _ = cands[base]
         plain = args.pmc_c3 == "plain_fp32"
         plan = qbe.Plan(qm, pi, mu, ctx=ctx, exec="per_step", precision="fp32" if plain else args.pmc_c3,
-                        merge=not plain)
+                        merge=not plain, fused_prefix=use_prefix and not plain)
         ws = plan.workspace()
         out = torch.zeros(2, dtype=torch.float64, device="cuda")
         if not plain:

@@ -99,7 +99,22 @@ typedef struct qbe_plan_opts {
   int32_t no_merge;    /* 1: one launch per bucket in the per-step form and
                           one level per bucket depth in the fused form (no
                           merging of bucket chains); 0: merge (default)      */
-  int32_t reserved[4]; /* must be zero                                       */
+  int32_t fused_prefix; /* > 0: a per-step plan contracts its small buckets
+                          -- every bucket of at most R + 1 variables whose
+                          producers all are such -- in one LDS-resident
+                          launch of the fused form's executor (FP32,
+                          whatever the plan's precision) before its
+                          per-step launches, which read the results it
+                          writes to the workspace.  1: R is the largest of
+                          10, 8, 6, 4 whose prefix fits LDS; 2..14: R =
+                          fused_prefix.  Needs merging (no_merge 0) and at
+                          most 24 sliced variables; a plan with no such
+                          prefix (fewer than two small buckets, or it does
+                          not fit LDS) runs without one
+                          (stats.prefix_buckets 0).  Ignored by plans that
+                          run in the fused form.  0: no prefix (default);
+                          other values: QBE_ERR_INVALID_ARG                 */
+  int32_t reserved[3]; /* must be zero                                       */
 } qbe_plan_opts;
 
 typedef struct qbe_stats {
@@ -128,8 +143,10 @@ typedef struct qbe_stats {
                                           are merged)                        */
   int32_t n_launches;                  /* per-step form: contraction launches
                                           per slice group (a merged chain or
-                                          a partial product counts once)     */
-  int32_t reserved0;
+                                          a partial product counts once; the
+                                          fused prefix counts once)          */
+  int32_t prefix_buckets;              /* per-step form: buckets contracted
+                                          by the fused prefix (0: none)      */
 } qbe_stats;
 
 /* ------------------------------------------------------------------ misc -- */
@@ -373,17 +390,21 @@ int qbe_plan_autotune(qbe_ctx* ctx, qbe_plan* plan, void* d_workspace, size_t ws
                       int64_t min_elems);
 
 /* Per-launch view of a per-step plan (diagnostics and measurement): the
- * execution order's launches -- a single bucket, a merged chain of buckets
- * (several summed variables), a partial product of a wide bucket, or a
- * group of small buckets of one level -- then the per-slice FP64 product
- * of the rank-0 results (finalize) and the slice sum (reduce, Eq. 4). */
+ * fused prefix, if the plan has one, then the execution order's launches
+ * -- a single bucket, a merged chain of buckets (several summed
+ * variables), a partial product of a wide bucket, or a group of small
+ * buckets of one level -- then the per-slice FP64 product of the rank-0
+ * results (finalize) and the slice sum (reduce, Eq. 4). */
 enum {
   QBE_LAUNCH_BUCKET = 0,
   QBE_LAUNCH_MERGED = 1,
   QBE_LAUNCH_PARTIAL = 2,
   QBE_LAUNCH_GROUP = 3,
   QBE_LAUNCH_FINALIZE = 4,
-  QBE_LAUNCH_REDUCE = 5
+  QBE_LAUNCH_REDUCE = 5,
+  QBE_LAUNCH_PREFIX = 6  /* the fused prefix: bytes_per_slice counts its
+                            inputs and exported results once (its other
+                            intermediates stay in LDS)                    */
 };
 typedef struct qbe_launch_info {
   int32_t kind;              /* QBE_LAUNCH_*                                  */
@@ -398,8 +419,12 @@ typedef struct qbe_launch_info {
   uint64_t flops_per_slice;  /* real flops: per result entry 2^n_sum terms of
                                 n_ops - 1 complex products (6 flops each) and
                                 their sum                                     */
+  int32_t levels;            /* fused prefix: levels of its program (barriers
+                                per slice); 0 for other launches              */
+  int32_t lds_bytes;         /* fused prefix: LDS per workgroup; 0 otherwise  */
 } qbe_launch_info;
-/* Launches of a per-step plan (its execution order + 2); 0 for a fused plan. */
+/* Launches of a per-step plan (its prefix, its execution order, + 2); 0 for
+ * a fused plan. */
 int qbe_plan_num_launches(const qbe_plan* plan, int32_t* n_out);
 /* Launch i (0 <= i < qbe_plan_num_launches) of a per-step plan. */
 int qbe_plan_launch_info(const qbe_plan* plan, int32_t i, qbe_launch_info* out);

@@ -1275,18 +1275,26 @@ static int run_prep(Plan& p) {
         (const double2*)p.d_raw, (const int32_t*)p.d_fused_map, (float2*)p.d_fused_in, p.fused_elems);
     QBE_HIP(hipGetLastError());
   }
+  if (p.prefix_ok && p.prefix_elems > 0) {
+    prep_kernel<<<grid_for(p.prefix_elems, 256), 256, 0, 0>>>(
+        (const double2*)p.d_raw, (const int32_t*)p.d_prefix_map, (float2*)p.d_prefix_in, p.prefix_elems);
+    QBE_HIP(hipGetLastError());
+  }
   QBE_HIP(hipDeviceSynchronize());
   return QBE_OK;
 }
 
-static void plan_buffers(Plan& p, void** (&ptrs)[9]) {
-  void** all[9] = {&p.d_raw,      &p.d_step_map,   &p.d_step_in,    &p.d_fused_map, &p.d_fused_in,
-                   &p.d_fused_prog, &p.d_scalar_tab, &p.d_state, &p.d_group};
-  for (int i = 0; i < 9; ++i) ptrs[i] = all[i];
+constexpr int kPlanBuffers = 12;
+
+static void plan_buffers(Plan& p, void** (&ptrs)[kPlanBuffers]) {
+  void** all[kPlanBuffers] = {&p.d_raw,        &p.d_step_map,  &p.d_step_in,     &p.d_fused_map, &p.d_fused_in,
+                              &p.d_fused_prog, &p.d_scalar_tab, &p.d_state,      &p.d_group,     &p.d_prefix_map,
+                              &p.d_prefix_in,  &p.d_prefix_prog};
+  for (int i = 0; i < kPlanBuffers; ++i) ptrs[i] = all[i];
 }
 
 void dev_free_plan(Plan& p) {
-  void** ptrs[9];
+  void** ptrs[kPlanBuffers];
   plan_buffers(p, ptrs);
   for (void** q : ptrs) {
     if (*q) (void)hipFree(*q);
@@ -1295,7 +1303,7 @@ void dev_free_plan(Plan& p) {
 }
 
 void dev_forget_plan(Plan& p) {
-  void** ptrs[9];
+  void** ptrs[kPlanBuffers];
   plan_buffers(p, ptrs);
   for (void** q : ptrs) *q = nullptr;
 }
@@ -1346,6 +1354,11 @@ int dev_upload_plan(Plan& p) {
     if ((rc = upload(&p.d_fused_map, p.fused_map.data(), p.fused_map.size() * 4))) return rc;
     if ((rc = dmalloc(&p.d_fused_in, p.fused_elems * 8))) return rc;
     if ((rc = upload(&p.d_fused_prog, p.fused_prog.data(), p.fused_prog.size() * 4))) return rc;
+  }
+  if (p.prefix_ok) {
+    if ((rc = upload(&p.d_prefix_map, p.prefix_map.data(), p.prefix_map.size() * 4))) return rc;
+    if ((rc = dmalloc(&p.d_prefix_in, p.prefix_elems * 8))) return rc;
+    if ((rc = upload(&p.d_prefix_prog, p.prefix_prog.data(), p.prefix_prog.size() * 4))) return rc;
   }
   return run_prep(p);
 }
@@ -1828,6 +1841,10 @@ int dev_contract(const Plan& p, void* stream, void* ws, size_t ws_bytes, int64_t
     float2* arena = (float2*)(w + ws_head(n));
     for (int64_t g0 = 0; g0 < n; g0 += G) {
       const int64_t Gc = std::min<int64_t>(G, n - g0);
+      if (p.prefix_ok) {
+        int rc = prefix_launch(p, arena, Gc, s_begin + g0, st);
+        if (rc) return rc;
+      }
       for (const LaunchItem& li : p.launch_order) {
         int rc = li.group < 0 ? launch_step(p, p.steps[li.step], arena, Gc, s_begin + g0, st)
                               : launch_group(p, li.group, arena, Gc, s_begin + g0, st);
@@ -1842,12 +1859,15 @@ int dev_contract(const Plan& p, void* stream, void* ws, size_t ws_bytes, int64_t
 
 // Per-launch timing of a per-step plan: the contraction of all slices at
 // once (one slice group), with a HIP event recorded on the stream before the
-// first launch and after every launch of the execution order, then the
-// finalize and reduce launches.  ms_out[i] = time between events i and i + 1.
+// first launch and after every launch of the execution order (the fused
+// prefix first, if the plan has one), then the finalize and reduce launches.
+// ms_out[i] = time between events i and i + 1.
 int dev_profile(const Plan& p, void* stream, void* ws, size_t ws_bytes, float* ms_out, int cap, int* n_out) {
   hipStream_t st = (hipStream_t)stream;
   const int64_t n = p.n_slices;
-  const int items = (int)p.launch_order.size() + 2;
+  const int pre = p.prefix_ok ? 1 : 0;
+  const int n_order = (int)p.launch_order.size();
+  const int items = pre + n_order + 2;
   *n_out = items;
   if (p.exec != QBE_EXEC_PER_STEP) {
     set_error("per-launch timing is for per-step plans (a fused plan is one launch)");
@@ -1870,8 +1890,10 @@ int dev_profile(const Plan& p, void* stream, void* ws, size_t ws_bytes, float* m
     if (rc == QBE_OK && hipEventCreate(&e) != hipSuccess) rc = QBE_ERR_HIP;
   if (rc == QBE_OK && hipEventRecord(ev[0], st) != hipSuccess) rc = QBE_ERR_HIP;
   for (int i = 0; i < items && rc == QBE_OK; ++i) {
-    if (i < (int)p.launch_order.size()) {
-      const LaunchItem& li = p.launch_order[i];
+    if (i < pre) {
+      rc = prefix_launch(p, arena, n, 0, st);
+    } else if (i < pre + n_order) {
+      const LaunchItem& li = p.launch_order[i - pre];
       rc = li.group < 0 ? launch_step(p, p.steps[li.step], arena, n, 0, st) : launch_group(p, li.group, arena, n, 0, st);
     } else if (i == items - 2) {
       rc = finalize_group(p, arena, per_slice, n, 0, st);

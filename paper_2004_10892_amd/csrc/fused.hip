@@ -14,7 +14,7 @@ namespace qbe {
 // or with every work item (batch mode) so that no device-memory round trip
 // precedes the LDS fill.
 struct FusedMeta {
-  uint32_t lds_tab, levels, scalars, scalar_off, free_vars, inv, dep, dep_src, bytes, pad;
+  uint32_t lds_tab, levels, scalars, scalar_off, free_vars, inv, dep, dep_src, bytes, exports;
   uint32_t lv0[4], lv1[4];  // the first two level-table entries
 };
 
@@ -40,12 +40,17 @@ struct FusedArgs {
   double2* amps;                      // per plan: the slice sum (when reduce_here)
   int32_t reduce_here;                // 1: the last workgroup of a plan sums its items
   uint32_t lds_ctl;                   // LDS byte offset of the workgroup's control words
+  // export mode (one-plan mode with a prefix program): instead of the scalar
+  // product, item g copies each export row's result (LDS element, rank,
+  // arena offset) to arena[offset * G + (g << rank) + i]
+  float2* arena;
+  int64_t G;
 };
 
 static FusedMeta fused_meta(const Plan& p) {
   const std::vector<uint32_t>& w = p.fused_prog;
   FusedMeta m{(uint32_t)fused_table_lds(w[FH_DATA_ELEMS]), w[FH_LEVELS], w[FH_SCALARS], w[FH_SCALAR_OFF],
-              w[FH_FREE], w[FH_INV_ELEMS], w[FH_DEP_ELEMS], w[FH_DEP_SRC], w[FH_BYTE_OFFSETS], 0, {}, {}};
+              w[FH_FREE], w[FH_INV_ELEMS], w[FH_DEP_ELEMS], w[FH_DEP_SRC], w[FH_BYTE_OFFSETS], w[FH_EXPORTS], {}, {}};
   for (int i = 0; i < 4; ++i) {
     m.lv0[i] = w[kHdr + i];
     m.lv1[i] = w[kHdr + 4 + i];
@@ -59,10 +64,9 @@ constexpr int kFusedCtlBytes = 16;
 // that both sum in one order.
 constexpr int kFusedReduceLanes = 256;
 // Record rows (16-byte groups of words) a lane reads per level, two levels
-// ahead: one half-record of up to 15 operands, or a whole record of up to 7.
+// ahead: one half-record of up to kSplitOpsMax operands, or a whole record
+// of up to kWholeOpsMax.
 constexpr int kRecRows = kFusedTailRows;
-constexpr int kSplitOpsMax = 8 * kRecRows - 1;
-constexpr int kWholeOpsMax = 4 * kRecRows - 1;
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef const __attribute__((address_space(1))) uint32_t* gu32p;
@@ -226,7 +230,7 @@ __device__ __forceinline__ void level_step(gu32p prog, const u32x4& t, const u32
                                            uint32_t tid) {
   const uint32_t ntz = uni(tn.z);
   load_rec(prog, rec_word(uni(tn.x), uni(tn.y), ntz & 0xFFFFu, ntz >> 16, tid), pf);
-  const uint32_t base = uni(t.x), E = uni(t.y), tz = uni(t.z), K = uni(t.w);
+  const uint32_t base = uni(t.x), E = uni(t.y), tz = uni(t.z), K = uni(t.w) & 0xFFFFu;
   const uint32_t R = tz & 0xFFFFu, lgT = tz >> 16;
   if (split_level(E, lgT) && K <= (uint32_t)kSplitOpsMax) {
     switch (K) {
@@ -255,27 +259,61 @@ __device__ __forceinline__ void level_step(gu32p prog, const u32x4& t, const u32
 // reads those of level l + 2; entries after the last level are zero).
 // lv is the LDS copy of the level table; t0, t1 and the first two levels'
 // records were read before the inputs were copied.
+// Export rows of a prefix program and where they go (one-plan mode: the
+// arena of the launch's slice group, item = the slice's place in it).
+struct ExportCtx {
+  const __attribute__((address_space(3))) u32x4* rows;  // LDS copy of the rows
+  float2* arena;
+  int64_t G, item;
+};
+
+// Copies export rows [first, first + count): every lane moves entries of
+// each result from LDS to the arena.
+__device__ __forceinline__ void copy_exports(const ExportCtx& x, uint32_t first, uint32_t count, uint32_t tid) {
+  for (uint32_t e = first; e < first + count; ++e) {
+    const u32x4 r = x.rows[e];
+    const uint32_t src = uni(r.x), rank = uni(r.y);
+    const uint64_t off = ((uint64_t)uni(r.w) << 32) | uni(r.z);
+    float2* dst = x.arena + (int64_t)off * x.G + (x.item << rank);
+    for (uint32_t i = tid; i < (1u << rank); i += kFusedBlock) dst[i] = lds_entry(8u * (src + i));
+  }
+}
+
+// The export rows a level copies as it starts (results of earlier levels,
+// read by no later level); returns the next row.
+__device__ __forceinline__ uint32_t level_exports(const ExportCtx& x, u32x4 t, uint32_t next, uint32_t tid) {
+  const uint32_t n = uni(t.w) >> 16;
+  if (n) copy_exports(x, next, n, tid);
+  return next + n;
+}
+
 template <bool kBytes>
-__device__ __forceinline__ void run_levels(gu32p prog, const __attribute__((address_space(3))) u32x4* lv,
-                                           uint32_t n_levels, u32x4 t0, u32x4 t1, Rec& ra, Rec& rb, uint32_t tid) {
+__device__ __forceinline__ uint32_t run_levels(gu32p prog, const __attribute__((address_space(3))) u32x4* lv,
+                                               uint32_t n_levels, u32x4 t0, u32x4 t1, Rec& ra, Rec& rb,
+                                               const ExportCtx& xc, uint32_t tid) {
   u32x4 t2 = lv[2];
   Rec rc;
+  uint32_t xn = 0;  // next export row
   for (uint32_t l = 0; l < n_levels; l += 3) {
     const u32x4 t3 = lv[l + 3];
+    xn = level_exports(xc, t0, xn, tid);
     level_step<kBytes>(prog, t0, t2, ra, rc, tid);
     __syncthreads();
     if (l + 1 >= n_levels) break;
     const u32x4 t4 = lv[l + 4];
+    xn = level_exports(xc, t1, xn, tid);
     level_step<kBytes>(prog, t1, t3, rb, ra, tid);
     __syncthreads();
     if (l + 2 >= n_levels) break;
     const u32x4 t5 = lv[l + 5];
+    xn = level_exports(xc, t2, xn, tid);
     level_step<kBytes>(prog, t2, t4, rc, rb, tid);
     __syncthreads();
     t0 = t3;
     t1 = t4;
     t2 = t5;
   }
+  return xn;
 }
 
 // LDS fill of one work item's inputs, in rounds whose loads are all issued
@@ -313,10 +351,13 @@ __device__ __forceinline__ void fill_lds(uint64_t* dinv, const uint64_t* sinv_, 
 // ...; in batch mode items are pulled from a counter (uneven sizes).  The
 // program stays in device memory (all workgroups of a plan read the same
 // words, so they come from the caches); LDS holds the tensor entries only.
-// One workgroup of four waves per compute unit is the intended occupancy: the
-// compiler may use the whole register file to keep every read of a level in
-// flight at once.
-__global__ __launch_bounds__(kFusedBlock) __attribute__((amdgpu_waves_per_eu(kFusedBlock / 256, kFusedBlock / 256))) void fused_kernel(FusedArgs a) {
+// Registers are budgeted for two workgroups per compute unit (4 waves per
+// SIMD): where LDS allows, a second workgroup's slice runs while the first
+// waits on its record reads.  (A bound of one workgroup -- the register file
+// for one -- keeps the hardware to one workgroup per compute unit whatever
+// the LDS size, and slices then run in rounds of 256.)
+constexpr int kFusedWgPerCu = 2;
+__global__ __launch_bounds__(kFusedBlock) __attribute__((amdgpu_waves_per_eu(kFusedBlock / 256, kFusedWgPerCu * kFusedBlock / 256))) void fused_kernel(FusedArgs a) {
   // all of the workgroup's LDS is dynamic, so that the tensor entries start
   // at LDS address 0 and record offsets are addresses; the two shared words
   // sit after the largest data block of the launch
@@ -354,7 +395,7 @@ __global__ __launch_bounds__(kFusedBlock) __attribute__((amdgpu_waves_per_eu(kFu
       prep = wi.prep;
       mt = FusedMeta{uni(wi.meta.lds_tab), uni(wi.meta.levels),  uni(wi.meta.scalars), uni(wi.meta.scalar_off),
                      uni(wi.meta.free_vars), uni(wi.meta.inv), uni(wi.meta.dep),     uni(wi.meta.dep_src),
-                     uni(wi.meta.bytes), 0, {}, {}};
+                     uni(wi.meta.bytes), 0, {}, {}};  // batch programs export nothing
       for (int i = 0; i < 4; ++i) {
         mt.lv0[i] = uni(wi.meta.lv0[i]);
         mt.lv1[i] = uni(wi.meta.lv1[i]);
@@ -386,12 +427,17 @@ __global__ __launch_bounds__(kFusedBlock) __attribute__((amdgpu_waves_per_eu(kFu
     fill_lds<4>(reinterpret_cast<uint64_t*>(data + kFusedConsts), reinterpret_cast<const uint64_t*>(prep), inv,
                 reinterpret_cast<uint64_t*>(data + kFusedConsts + inv), reinterpret_cast<const uint64_t*>(dsrc), dep,
                 reinterpret_cast<u32x4*>(reinterpret_cast<char*>(lds4) + mt.lds_tab),
-                reinterpret_cast<const u32x4*>(gprog + kHdr), mt.levels + kFusedLevelPad, tid);
+                reinterpret_cast<const u32x4*>(gprog + kHdr), mt.levels + kFusedLevelPad + mt.exports, tid);
     __syncthreads();
-    if (mt.bytes)
-      run_levels<true>(prog, lv, mt.levels, t0, t1, ra, rb, tid);
-    else
-      run_levels<false>(prog, lv, mt.levels, t0, t1, ra, rb, tid);
+    const ExportCtx xc{lv + mt.levels + kFusedLevelPad, a.arena, a.G, item};
+    const uint32_t xn = mt.bytes ? run_levels<true>(prog, lv, mt.levels, t0, t1, ra, rb, xc, tid)
+                                 : run_levels<false>(prog, lv, mt.levels, t0, t1, ra, rb, xc, tid);
+    if (mt.exports) {
+      // the last levels' results; the next item's LDS fill waits at the
+      // loop head's barrier
+      copy_exports(xc, xn, mt.exports - xn, tid);
+      continue;
+    }
     if (tid < 64) {
       // product of the slice's scalar factors: lane j holds factor j (and
       // j + 64, ...), then a binary tree across the wave, in FP64
@@ -506,7 +552,9 @@ static int launch_fused(int grid, int lds_bytes, hipStream_t st, FusedArgs a) {
 }
 
 static int fused_grid(int lds_bytes, int64_t n_items) {
-  const int per_cu = std::max(1, std::min(8, (160 * 1024) / std::max(lds_bytes, 1)));
+  // resident workgroups per compute unit: the register bound, or fewer when
+  // LDS (160 KB per compute unit) holds fewer
+  const int per_cu = std::max(1, std::min(kFusedWgPerCu, (160 * 1024) / (lds_bytes + kFusedCtlBytes)));
   return (int)std::max<int64_t>(1, std::min<int64_t>(n_items, (int64_t)n_cus() * per_cu));
 }
 
@@ -524,6 +572,25 @@ int fused_contract(const Plan& p, hipStream_t st, int64_t s_begin, int64_t n, do
   a.reduce_here = n <= kInKernelReduceMax ? 1 : 0;
   *reduced = a.reduce_here != 0;
   return launch_fused(fused_grid(p.fused_lds_bytes, n), p.fused_lds_bytes, st, a);
+}
+
+int prefix_launch(const Plan& p, float2* arena, int64_t G, int64_t s0, hipStream_t st) {
+  const std::vector<uint32_t>& w = p.prefix_prog;
+  FusedArgs a{};
+  a.prog0 = (const uint32_t*)p.d_prefix_prog;
+  a.prep0 = (const float2*)p.d_prefix_in;
+  a.meta0 = FusedMeta{(uint32_t)fused_table_lds(w[FH_DATA_ELEMS]), w[FH_LEVELS], 0, w[FH_SCALAR_OFF], 0,
+                      w[FH_INV_ELEMS], w[FH_DEP_ELEMS], w[FH_DEP_SRC], w[FH_BYTE_OFFSETS], w[FH_EXPORTS], {}, {}};
+  for (int i = 0; i < 4; ++i) {
+    a.meta0.lv0[i] = w[kHdr + i];
+    a.meta0.lv1[i] = w[kHdr + 4 + i];
+  }
+  a.s_begin = s0;
+  a.n_items = G;
+  a.state = (uint32_t*)p.d_state;
+  a.arena = arena;
+  a.G = G;
+  return launch_fused(fused_grid(p.prefix_lds_bytes, G), p.prefix_lds_bytes, st, a);
 }
 
 // ------------------------------------------------------------------ batch --

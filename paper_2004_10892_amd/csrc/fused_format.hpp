@@ -29,13 +29,20 @@ constexpr int64_t kInKernelReduceMax = 8192;
 //   [2, 2 + inv)                slice-invariant input tensors
 //   [2 + inv, 2 + inv + dep)    this slice's copies of slice-dependent inputs
 //   [2 + inv + dep, data)       intermediates (arena, reused level by level)
-// then, from byte fused_table_lds(data), the level table (16 bytes a level).
+// then, from byte fused_table_lds(data), the level table (16 bytes a level)
+// and the export rows after it.
 // Program words:
 //   header[kHdr]
 //   levels[4 * (n_levels + kFusedLevelPad)]
 //                               (record base, entries E, R | lgT << 16,
-//                               factors K), then zero entries; R = rows of a
-//                               term record, T = 2^lgT terms per entry
+//                               factors K | X << 16), then zero entries; R =
+//                               rows of a term record, T = 2^lgT terms per
+//                               entry, X = export rows copied as the level
+//                               starts (the results of earlier levels)
+//   exports[4 * n_exports]      a prefix program's results for the per-step
+//                               launches: (LDS element, rank, arena offset
+//                               lo, hi) in the order levels copy them; rows
+//                               left after the last level are copied then
 //   records                     level by level, E entries of T term records
 //                               of R 16-byte rows (8R halfwords) each:
 //                                 slot 0: LDS offset of the result (term 0),
@@ -53,6 +60,20 @@ constexpr int64_t kInKernelReduceMax = 8192;
 //                               reads kFusedTailRows rows at any record)
 constexpr int kFusedTailRows = 2;
 constexpr int kFusedLevelPad = 3;
+// A level runs in one pass when every lane holds what it computes in the
+// kFusedTailRows rows it read ahead: E x T <= kFusedBlock term records of
+// at most kSplitOpsMax factors (a term record a lane), or, with T = 2,
+// E <= kFusedBlock entries of at most kWholeOpsMax factors (both terms a
+// lane).  Larger levels read further records while they run.
+constexpr int kSplitOpsMax = 8 * kFusedTailRows - 1;
+constexpr int kWholeOpsMax = 4 * kFusedTailRows - 1;
+// Entries of a one-pass level of 2^lgT terms of K factors (kFusedBlock
+// when no level of that shape runs in one pass).
+inline int64_t fused_pass_entries(uint32_t lgT, uint32_t K) {
+  if (lgT == 1 && K <= (uint32_t)kWholeOpsMax) return kFusedBlock;
+  if (K <= (uint32_t)kSplitOpsMax) return kFusedBlock >> lgT;
+  return kFusedBlock;
+}
 // LDS elements 0 and 1 hold the constants 1 (padding factor) and 0 (the
 // factor of a padding term); inputs follow.
 constexpr int kFusedConsts = 2;
@@ -71,6 +92,7 @@ enum FusedHdr {
   FH_DEP_SRC,         // element offset of slice 0's block in the prepared buffer
   FH_N_SLICES,        // 2^m (saturated)
   FH_BYTE_OFFSETS,    // 1: record offsets are LDS bytes, 0: complex64 elements
+  FH_EXPORTS,         // export rows (prefix programs; 0 otherwise)
   kHdr = 16
 };
 

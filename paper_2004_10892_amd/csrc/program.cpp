@@ -117,12 +117,12 @@ struct FusedNode {
 constexpr int kMergeTermsLog2 = 3;
 constexpr int kMergeFactors = 15;
 
-std::vector<FusedNode> merge_buckets(const Schedule& s, bool merge) {
+std::vector<FusedNode> merge_buckets(const Schedule& s, bool merge, const std::vector<char>& incl) {
   const int n = (int)s.steps.size();
   std::vector<std::vector<int>> kids(n), members(n);
   std::vector<int> F(n), lgT(n, 1), lv(n, 0);
   std::vector<int64_t> E(n);
-  std::vector<char> alive(n, 1);
+  std::vector<char> alive(incl);
   for (int k = 0; k < n; ++k) {
     for (const auto& op : s.steps[k].ops)
       if (op.kind == 'r') kids[k].push_back(op.id);
@@ -225,17 +225,18 @@ struct StepNode {
   std::vector<Operand> factors;  // operands of the members except absorbed results
 };
 
-std::vector<StepNode> merge_chains(const Schedule& s, bool merge) {
+std::vector<StepNode> merge_chains(const Schedule& s, bool merge, const std::vector<char>& skip) {
   const int n = (int)s.steps.size();
   std::vector<StepNode> nd(n);
   std::vector<char> alive(n, 1);
   for (int k = 0; k < n; ++k) {
     nd[k].members = {k};
     nd[k].factors = s.steps[k].ops;
+    if (skip[k]) alive[k] = 0;  // runs in the fused prefix
   }
   for (int k = 0; k < n && merge; ++k) {
     const int c = s.consumer[k];
-    if (c < 0) continue;
+    if (c < 0 || !alive[k]) continue;
     const int rk = (int)s.steps[k].out.size(), rc = (int)s.steps[c].out.size();
     if (rk < kChainMinRank || rk < rc) continue;
     if ((int)(nd[k].members.size() + nd[c].members.size()) > kChainSumMax) continue;
@@ -361,6 +362,241 @@ void build_launch_order(Plan& p) {
 
 }  // namespace
 
+// A fused program (the executor of fused.hip) for the buckets in `incl`
+// (every producer of an included bucket included).  Without exports it is
+// the whole schedule: the program ends with the slice's scalar factors.
+// With exports (per-step arena offsets per bucket, -1 if none) it is a
+// prefix of a per-step plan: the listed buckets' results are copied from LDS
+// to the per-step arena after the last level, and no scalar list follows.
+struct FusedCode {
+  bool ok = false;
+  std::vector<uint32_t> prog;
+  std::vector<int32_t> map;
+  int lds_bytes = 0, levels = 0;
+  size_t export_at = 0;           // word of the first export row in prog
+  std::vector<int> export_steps;  // the bucket of each export row
+};
+
+static FusedCode build_fused(const Plan& p, const std::vector<InputInfo>& in, const std::vector<int>& muj,
+                             const std::vector<char>& incl, const std::vector<int64_t>* export_off) {
+  const Model& md = p.model;
+  const Schedule& s = p.sched;
+  const int nt = (int)md.tvars.size();
+  const int nsteps = (int)s.steps.size();
+  FusedCode out;
+  // the inputs the included buckets read
+  std::vector<char> used(nt, export_off ? 0 : 1);
+  if (export_off)
+    for (int k = 0; k < nsteps; ++k)
+      if (incl[k])
+        for (const auto& op : s.steps[k].ops)
+          if (op.kind == 't') used[op.id] = 1;
+  // LDS element offsets of the inputs (after the constants 1 and 0)
+  std::vector<int64_t> lds_in(nt, -1);
+  int64_t inv = 0, dep = 0;
+  for (int t = 0; t < nt; ++t)
+    if (used[t] && in[t].smask == 0) {
+      lds_in[t] = kFusedConsts + inv;
+      inv += int64_t(1) << in[t].canon.size();
+    }
+  for (int t = 0; t < nt; ++t)
+    if (used[t] && in[t].smask != 0) {
+      lds_in[t] = kFusedConsts + inv + dep;
+      dep += int64_t(1) << in[t].canon.size();
+    }
+  // merged nodes (each writes its root bucket's result) and their levels
+  const std::vector<FusedNode> nodes = merge_buckets(s, p.merge, incl);
+  int f_levels = 0;
+  for (const FusedNode& nd : nodes) f_levels = std::max(f_levels, nd.level + 1);
+  std::vector<std::vector<int>> by_level(f_levels);
+  for (int i = 0; i < (int)nodes.size(); ++i) by_level[nodes[i].level].push_back(i);
+  // exports (prefix programs): results no included bucket reads, in the
+  // order of their nodes' levels; those of level l are copied out as level
+  // l + 1 starts (the last level's after it)
+  std::vector<int> exp_steps;
+  std::vector<int> exp_level;
+  if (export_off)
+    for (int l = 0; l < f_levels; ++l)
+      for (int i : by_level[l]) {
+        const int c = nodes[i].members[0];
+        if ((*export_off)[c] >= 0) {
+          exp_steps.push_back(c);
+          exp_level.push_back(l);
+        }
+      }
+  // arena by levels: all results of a level are live while the level runs;
+  // an exported result stays live through the next level, during which it is
+  // copied out
+  Arena la;
+  std::vector<int64_t> lds_out(nsteps, -1);
+  std::vector<int> copying;  // exported results of the previous level
+  for (int l = 0; l < f_levels; ++l) {
+    for (int i : by_level[l]) {
+      const int c = nodes[i].members[0];
+      lds_out[c] = la.alloc(int64_t(1) << s.steps[c].out.size(), 1);
+    }
+    for (int i : by_level[l])
+      for (int kid : nodes[i].kids) la.release(lds_out[kid], int64_t(1) << s.steps[kid].out.size());
+    for (int c : copying) la.release(lds_out[c], int64_t(1) << s.steps[c].out.size());
+    copying.clear();
+    for (size_t e = 0; e < exp_steps.size(); ++e)
+      if (exp_level[e] == l) copying.push_back(exp_steps[e]);
+  }
+  const int64_t arena0 = kFusedConsts + inv + dep;
+  const int64_t data_elems = arena0 + la.top;
+  // each level's factors F, terms T and entries E; a prefix program splits
+  // its levels into one-pass parts (their records all read ahead), as many
+  // slices run it at once and a level's extra record reads would stall them
+  std::vector<uint32_t> lvF(f_levels, 1), lvT(f_levels, 2);
+  std::vector<int64_t> lvE(f_levels, 0), lvCap(f_levels);
+  int64_t n_table = 0;
+  for (int l = 0; l < f_levels; ++l) {
+    for (int i : by_level[l]) {
+      lvF[l] = std::max<uint32_t>(lvF[l], (uint32_t)nodes[i].factors.size());
+      lvT[l] = std::max<uint32_t>(lvT[l], 2u << (nodes[i].members.size() - 1));
+      lvE[l] += int64_t(1) << s.steps[nodes[i].members[0]].out.size();
+    }
+    lvCap[l] = export_off ? fused_pass_entries((uint32_t)__builtin_ctz(lvT[l]), lvF[l]) : lvE[l];
+    n_table += (lvE[l] + lvCap[l] - 1) / lvCap[l];
+  }
+  // LDS: the tensor entries, then a copy of the level table and export rows
+  const int64_t n_exp = (int64_t)exp_steps.size();
+  const int64_t lds_bytes =
+      std::max<int64_t>(fused_table_lds(data_elems) + 16 * (n_table + kFusedLevelPad + n_exp), 256 * 16);
+  const int64_t prep_elems = inv + dep * p.n_slices;
+  if (f_levels == 0 || lds_bytes > kFusedLdsMax || prep_elems >= (int64_t(1) << 31)) return out;
+  std::vector<uint32_t> prog(kHdr, 0);
+  const size_t lvl_at = prog.size();
+  // zero entries after the last level end the executor's look-ahead
+  prog.resize(lvl_at + 4 * ((size_t)n_table + kFusedLevelPad), 0);
+  while (prog.size() % 4) prog.push_back(0);
+  // export rows (arena offsets are set once the per-step arena is placed)
+  out.export_at = prog.size();
+  for (int64_t e = 0; e < n_exp; ++e) {
+    const int c = exp_steps[e];
+    prog.insert(prog.end(), {0u, (uint32_t)s.steps[c].out.size(), 0u, 0u});
+  }
+  out.export_steps = exp_steps;
+  // 16-bit operand offsets: bytes when the data fit 64 KB, else elements
+  const bool bytes = data_elems * 8 <= 65536;
+  const uint32_t unit = bytes ? 8u : 1u;
+  std::vector<int> val(md.n_vars, -1);  // variable values of the record being written
+  size_t tab = 0;                       // next level-table entry
+  for (int l = 0; l < f_levels; ++l) {
+    const uint32_t F = lvF[l], T = lvT[l];
+    const int64_t E = lvE[l], cap = lvCap[l];
+    const uint32_t R = (1 + F + 7) / 8;  // 16-byte rows of a term record
+    int64_t done = 0;                    // entries of the level written
+    uint32_t X = 0;                      // exports of the previous level
+    for (int64_t e = 0; e < n_exp; ++e) X += exp_level[e] == l - 1;
+    for (int i : by_level[l]) {
+      const FusedNode& nd = nodes[i];
+      const Step& root = s.steps[nd.members[0]];
+      const int r = (int)root.out.size();
+      const uint32_t Tn = 2u << (nd.members.size() - 1);
+      for (uint32_t x = 0; x < (1u << r); ++x, ++done) {
+        if (done % cap == 0) {
+          prog[lvl_at + 4 * tab + 0] = (uint32_t)prog.size();
+          prog[lvl_at + 4 * tab + 1] = (uint32_t)std::min(cap, E - done);
+          prog[lvl_at + 4 * tab + 2] = R | ((uint32_t)__builtin_ctz(T) << 16);
+          prog[lvl_at + 4 * tab + 3] = F | (done == 0 ? X << 16 : 0u);
+          ++tab;
+        }
+        // T term records of 8R halfwords: [result (term 0) or 0, the
+        // factors' entries for that assignment of the summed variables]
+        for (uint32_t t = 0; t < T; ++t) {
+          const size_t at = prog.size();
+          prog.resize(at + 4 * R, 0);
+          auto put = [&](uint32_t j, uint32_t v) { prog[at + j / 2] |= (v * unit) << (16 * (j % 2)); };
+          if (t == 0) put(0, (uint32_t)(arena0 + lds_out[nd.members[0]] + x));
+          if (t >= Tn) {
+            put(1, kFusedZero);  // padding term: a factor 0
+            continue;
+          }
+          for (int q = 0; q < r; ++q) val[root.out[q]] = (int)((x >> (r - 1 - q)) & 1);
+          for (size_t j = 0; j < nd.members.size(); ++j) val[s.steps[nd.members[j]].var] = (int)((t >> j) & 1);
+          for (size_t f = 0; f < nd.factors.size(); ++f) {
+            const Operand& op = nd.factors[f];
+            const std::vector<int>& vars = op.kind == 't' ? in[op.id].canon : op.vars;
+            uint32_t e = 0;
+            for (int v : vars) {
+              if (val[v] < 0) throw std::logic_error("fused node factor outside its variables");
+              e = (e << 1) | (uint32_t)val[v];
+            }
+            const int64_t base = op.kind == 't' ? lds_in[op.id] : arena0 + lds_out[op.id];
+            put(1 + (uint32_t)f, (uint32_t)(base + e));
+          }
+          for (int q = 0; q < r; ++q) val[root.out[q]] = -1;
+          for (size_t j = 0; j < nd.members.size(); ++j) val[s.steps[nd.members[j]].var] = -1;
+        }
+      }
+    }
+  }
+  prog[FH_BYTE_OFFSETS] = bytes ? 1u : 0u;
+  const uint32_t scal_at = (uint32_t)prog.size();
+  uint32_t n_scal = 0;
+  if (!export_off) {
+    for (int t : s.scalar_inputs) {
+      prog.push_back((uint32_t)lds_in[t]);
+      ++n_scal;
+    }
+    for (int k : s.scalar_steps) {
+      prog.push_back((uint32_t)(arena0 + lds_out[k]));
+      ++n_scal;
+    }
+  } else {
+    for (int64_t e = 0; e < n_exp; ++e) {
+      if (lds_out[exp_steps[e]] < 0) throw std::logic_error("exported bucket without a result");
+      prog[out.export_at + 4 * e] = (uint32_t)(arena0 + lds_out[exp_steps[e]]);
+    }
+  }
+  while (prog.size() % 4) prog.push_back(0);
+  prog.resize(prog.size() + 4 * kFusedTailRows, 0);  // the executor reads whole row groups
+  if ((int64_t)tab != n_table) throw std::logic_error("fused level table count");
+  prog[FH_WORDS] = (uint32_t)prog.size();
+  prog[FH_LEVELS] = (uint32_t)n_table;
+  prog[FH_SCALARS] = n_scal;
+  prog[FH_SCALAR_OFF] = scal_at;
+  prog[FH_FREE] = (uint32_t)s.free_vars.size();
+  prog[FH_INV_ELEMS] = (uint32_t)inv;
+  prog[FH_DEP_ELEMS] = (uint32_t)dep;
+  prog[FH_DATA_ELEMS] = (uint32_t)data_elems;
+  prog[FH_DEP_SRC] = (uint32_t)inv;
+  prog[FH_N_SLICES] = (uint32_t)std::min<int64_t>(p.n_slices, UINT32_MAX);
+  prog[FH_EXPORTS] = (uint32_t)n_exp;
+  out.ok = true;
+  out.lds_bytes = (int)lds_bytes;
+  out.levels = (int)n_table;
+  out.prog = std::move(prog);
+  // gather map: invariant block, then one block per slice
+  out.map.reserve(prep_elems);
+  for (int t = 0; t < nt; ++t)
+    if (used[t] && in[t].smask == 0) {
+      const int r = (int)in[t].canon.size();
+      for (int64_t y = 0; y < (int64_t(1) << r); ++y) {
+        auto val = [&](int v) -> int {
+          int c = (int)(std::find(in[t].canon.begin(), in[t].canon.end(), v) - in[t].canon.begin());
+          return (int)((y >> (r - 1 - c)) & 1);
+        };
+        out.map.push_back((int32_t)raw_index(md, t, val));
+      }
+    }
+  for (int64_t sl = 0; sl < p.n_slices; ++sl)
+    for (int t = 0; t < nt; ++t)
+      if (used[t] && in[t].smask != 0) {
+        const int r = (int)in[t].canon.size();
+        for (int64_t y = 0; y < (int64_t(1) << r); ++y) {
+          auto val = [&](int v) -> int {
+            if (muj[v] >= 0) return (int)((sl >> muj[v]) & 1);
+            int c = (int)(std::find(in[t].canon.begin(), in[t].canon.end(), v) - in[t].canon.begin());
+            return (int)((y >> (r - 1 - c)) & 1);
+          };
+          out.map.push_back((int32_t)raw_index(md, t, val));
+        }
+      }
+  return out;
+}
+
 void compile_plan(Plan& p) {
   const Model& md = p.model;
   const Schedule& s = p.sched;
@@ -416,13 +652,65 @@ void compile_plan(Plan& p) {
   }
   p.step_elems = (int64_t)p.step_map.size();
 
-  // ---------------- per-step launches and arena
+  // ---------------- fused prefix (per-step plans that ask for it): the
+  // subtrees of small buckets -- every bucket whose union has at most
+  // R + 1 variables and whose producers all do -- run as one LDS-resident
+  // launch (fused.hip) before the per-step launches; the results that larger
+  // buckets read (and rank-0 results) are exported to the arena.  R is the
+  // largest of 10, 8, 6, 4 whose prefix fits the LDS budget.
   const int nsteps = (int)s.steps.size();
+  std::vector<char> in_prefix(nsteps, 0);
+  std::vector<int64_t> export_mark(nsteps, -1);
+  FusedCode prefix;
+  p.prefix_ok = false;
+  p.prefix_prog.clear();
+  p.prefix_map.clear();
+  p.prefix_exports.clear();
+  p.prefix_elems = 0;
+  p.prefix_lds_bytes = p.prefix_levels = p.prefix_buckets = 0;
+  p.prefix_max_rank = -1;
+  p.prefix_bytes_per_slice = 0;
+  p.prefix_flops_per_slice = 0;
+  if (p.want_prefix > 0 && p.merge && p.m <= 24) {
+    const std::vector<int> bounds = p.want_prefix == 1 ? std::vector<int>{10, 8, 6, 4} : std::vector<int>{p.want_prefix};
+    for (int R : bounds) {
+      std::vector<char> f(nsteps, 0);
+      int cnt = 0;
+      for (int k = 0; k < nsteps; ++k) {  // producers precede their consumers
+        bool ok = (int)s.steps[k].uni.size() <= R + 1;
+        for (const auto& op : s.steps[k].ops)
+          if (op.kind == 'r' && !f[op.id]) ok = false;
+        f[k] = ok;
+        cnt += ok;
+      }
+      if (cnt < 2) break;
+      std::vector<int64_t> mark(nsteps, -1);
+      for (int k = 0; k < nsteps; ++k)
+        if (f[k] && (s.consumer[k] < 0 || !f[s.consumer[k]])) mark[k] = 0;
+      FusedCode fc = build_fused(p, in, muj, f, &mark);
+      if (!fc.ok) continue;
+      in_prefix = f;
+      export_mark = mark;
+      prefix = std::move(fc);
+      p.prefix_max_rank = R;
+      p.prefix_buckets = cnt;
+      break;
+    }
+  }
+
+  // ---------------- per-step launches and arena
   std::vector<int64_t> out_off(nsteps, -1);
   Arena arena;
   int64_t own = 0;  // elements of the small results' own space
   p.steps.clear();
   p.scalar_arena.clear();
+  // results the prefix exports: placed first, freed by their consumers
+  for (int k = 0; k < nsteps; ++k)
+    if (export_mark[k] >= 0) {
+      const int64_t osz = int64_t(1) << s.steps[k].out.size();
+      out_off[k] = arena.alloc(osz, align_for(osz));
+      if (s.steps[k].out.empty()) p.scalar_arena.push_back(out_off[k]);
+    }
   auto input_op = [&](int t, const std::vector<int>& uni) {
     StepOp o{};
     o.base = step_base[t];
@@ -432,7 +720,7 @@ void compile_plan(Plan& p) {
     o.smask = in[t].smask;
     return o;
   };
-  for (const StepNode& node : merge_chains(s, p.merge)) {
+  for (const StepNode& node : merge_chains(s, p.merge, in_prefix)) {
     const int k = node.members.back();  // the root: its result is the launch's
     const Step& st = s.steps[k];
     const int n_sum = (int)node.members.size();
@@ -593,7 +881,33 @@ void compile_plan(Plan& p) {
   }
   for (int64_t& off : p.scalar_arena) place(off);
   p.arena_per_slice = std::max<int64_t>(own > 0 ? own_base + own : arena.top, 1);
-  p.step_bytes_per_slice = 0;
+  if (!prefix.prog.empty()) {
+    for (size_t i = 0; i < prefix.export_steps.size(); ++i) {
+      const uint64_t a = (uint64_t)out_off[prefix.export_steps[i]];
+      prefix.prog[prefix.export_at + 4 * i + 2] = (uint32_t)a;
+      prefix.prog[prefix.export_at + 4 * i + 3] = (uint32_t)(a >> 32);
+    }
+    p.prefix_ok = true;
+    p.prefix_exports.assign(prefix.prog.begin() + prefix.export_at,
+                            prefix.prog.begin() + prefix.export_at + 4 * prefix.export_steps.size());
+    p.prefix_prog = std::move(prefix.prog);
+    p.prefix_map = std::move(prefix.map);
+    p.prefix_elems = (int64_t)p.prefix_map.size();
+    p.prefix_lds_bytes = prefix.lds_bytes;
+    p.prefix_levels = prefix.levels;
+    // algorithmic traffic of the launch per slice: its inputs read once,
+    // its exported results written once; products and sums of its buckets
+    int64_t e = (int64_t)p.prefix_prog[FH_INV_ELEMS] + (int64_t)p.prefix_prog[FH_DEP_ELEMS];
+    for (size_t i = 0; i < p.prefix_exports.size(); i += 4) e += int64_t(1) << p.prefix_exports[i + 1];
+    p.prefix_bytes_per_slice = 8 * e;
+    for (int k = 0; k < nsteps; ++k)
+      if (in_prefix[k]) {
+        const int64_t kk = (int64_t)s.steps[k].ops.size();
+        p.prefix_flops_per_slice += 6 * std::max<int64_t>(kk - 1, 0) * (int64_t(1) << s.steps[k].uni.size()) +
+                                    2 * (int64_t(1) << s.steps[k].out.size());
+      }
+  }
+  p.step_bytes_per_slice = p.prefix_bytes_per_slice;
   for (const StepProg& sp : p.steps) {
     int64_t b = int64_t(1) << (sp.out_rank >= 0 ? sp.out_rank : -sp.out_rank);
     for (int i = 0; i < sp.n_ops; ++i) b += int64_t(1) << sp.ops[i].rank;
@@ -622,7 +936,7 @@ void compile_plan(Plan& p) {
   }
   p.n_levels = n_levels;
 
-  // ---------------- fused form
+  // ---------------- fused form: the whole schedule in LDS
   p.fused_ok = false;
   p.fused_prog.clear();
   p.fused_map.clear();
@@ -633,155 +947,14 @@ void compile_plan(Plan& p) {
   for (const auto& st : s.steps)
     if (st.uni.size() > 15) eligible = false;
   if (eligible) {
-    // LDS element offsets of the inputs (after the constants 1 and 0)
-    std::vector<int64_t> lds_in(nt, -1);
-    int64_t inv = 0, dep = 0;
-    for (int t = 0; t < nt; ++t)
-      if (in[t].smask == 0) {
-        lds_in[t] = kFusedConsts + inv;
-        inv += int64_t(1) << in[t].canon.size();
-      }
-    for (int t = 0; t < nt; ++t)
-      if (in[t].smask != 0) {
-        lds_in[t] = kFusedConsts + inv + dep;
-        dep += int64_t(1) << in[t].canon.size();
-      }
-    // merged nodes (each writes its root bucket's result) and their levels
-    const std::vector<FusedNode> nodes = merge_buckets(s, p.merge);
-    int f_levels = 0;
-    for (const FusedNode& nd : nodes) f_levels = std::max(f_levels, nd.level + 1);
-    std::vector<std::vector<int>> by_level(f_levels);
-    for (int i = 0; i < (int)nodes.size(); ++i) by_level[nodes[i].level].push_back(i);
-    // arena by levels: all results of a level are live while the level runs
-    Arena la;
-    std::vector<int64_t> lds_out(nsteps, -1);
-    for (int l = 0; l < f_levels; ++l) {
-      for (int i : by_level[l]) {
-        const int c = nodes[i].members[0];
-        lds_out[c] = la.alloc(int64_t(1) << s.steps[c].out.size(), 1);
-      }
-      for (int i : by_level[l])
-        for (int kid : nodes[i].kids) la.release(lds_out[kid], int64_t(1) << s.steps[kid].out.size());
-    }
-    const int64_t arena0 = kFusedConsts + inv + dep;
-    const int64_t data_elems = arena0 + la.top;
-    // LDS: the tensor entries, then a copy of the level table
-    const int64_t lds_bytes = std::max<int64_t>(fused_table_lds(data_elems) + 16 * ((int64_t)f_levels + kFusedLevelPad),
-                                                256 * 16);
-    const int64_t prep_elems = inv + dep * p.n_slices;
-    if (lds_bytes <= kFusedLdsMax && prep_elems < (int64_t(1) << 31)) {
-      std::vector<uint32_t> prog(kHdr, 0);
-      const size_t lvl_at = prog.size();
-      // zero entries after the last level end the executor's look-ahead
-      prog.resize(lvl_at + 4 * ((size_t)f_levels + kFusedLevelPad), 0);
-      while (prog.size() % 4) prog.push_back(0);
-      // 16-bit operand offsets: bytes when the data fit 64 KB, else elements
-      const bool bytes = data_elems * 8 <= 65536;
-      const uint32_t unit = bytes ? 8u : 1u;
-      std::vector<int> val(md.n_vars, -1);  // variable values of the record being written
-      for (int l = 0; l < f_levels; ++l) {
-        uint32_t F = 1, T = 2;
-        int64_t E = 0;
-        for (int i : by_level[l]) {
-          F = std::max<uint32_t>(F, (uint32_t)nodes[i].factors.size());
-          T = std::max<uint32_t>(T, 2u << (nodes[i].members.size() - 1));
-          E += int64_t(1) << s.steps[nodes[i].members[0]].out.size();
-        }
-        const uint32_t R = (1 + F + 7) / 8;  // 16-byte rows of a term record
-        prog[lvl_at + 4 * l + 0] = (uint32_t)prog.size();
-        prog[lvl_at + 4 * l + 1] = (uint32_t)E;
-        prog[lvl_at + 4 * l + 2] = R | ((uint32_t)__builtin_ctz(T) << 16);
-        prog[lvl_at + 4 * l + 3] = F;
-        for (int i : by_level[l]) {
-          const FusedNode& nd = nodes[i];
-          const Step& root = s.steps[nd.members[0]];
-          const int r = (int)root.out.size();
-          const uint32_t Tn = 2u << (nd.members.size() - 1);
-          for (uint32_t x = 0; x < (1u << r); ++x) {
-            // T term records of 8R halfwords: [result (term 0) or 0, the
-            // factors' entries for that assignment of the summed variables]
-            for (uint32_t t = 0; t < T; ++t) {
-              const size_t at = prog.size();
-              prog.resize(at + 4 * R, 0);
-              auto put = [&](uint32_t j, uint32_t v) { prog[at + j / 2] |= (v * unit) << (16 * (j % 2)); };
-              if (t == 0) put(0, (uint32_t)(arena0 + lds_out[nd.members[0]] + x));
-              if (t >= Tn) {
-                put(1, kFusedZero);  // padding term: a factor 0
-                continue;
-              }
-              for (int q = 0; q < r; ++q) val[root.out[q]] = (int)((x >> (r - 1 - q)) & 1);
-              for (size_t j = 0; j < nd.members.size(); ++j) val[s.steps[nd.members[j]].var] = (int)((t >> j) & 1);
-              for (size_t f = 0; f < nd.factors.size(); ++f) {
-                const Operand& op = nd.factors[f];
-                const std::vector<int>& vars = op.kind == 't' ? in[op.id].canon : op.vars;
-                uint32_t e = 0;
-                for (int v : vars) {
-                  if (val[v] < 0) throw std::logic_error("fused node factor outside its variables");
-                  e = (e << 1) | (uint32_t)val[v];
-                }
-                const int64_t base = op.kind == 't' ? lds_in[op.id] : arena0 + lds_out[op.id];
-                put(1 + (uint32_t)f, (uint32_t)(base + e));
-              }
-              for (int q = 0; q < r; ++q) val[root.out[q]] = -1;
-              for (size_t j = 0; j < nd.members.size(); ++j) val[s.steps[nd.members[j]].var] = -1;
-            }
-          }
-        }
-      }
-      prog[FH_BYTE_OFFSETS] = bytes ? 1u : 0u;
-      p.fused_levels = f_levels;
-      const uint32_t scal_at = (uint32_t)prog.size();
-      uint32_t n_scal = 0;
-      for (int t : s.scalar_inputs) {
-        prog.push_back((uint32_t)lds_in[t]);
-        ++n_scal;
-      }
-      for (int k : s.scalar_steps) {
-        prog.push_back((uint32_t)(arena0 + lds_out[k]));
-        ++n_scal;
-      }
-      while (prog.size() % 4) prog.push_back(0);
-      prog.resize(prog.size() + 4 * kFusedTailRows, 0);  // the executor reads whole row groups
-      prog[FH_WORDS] = (uint32_t)prog.size();
-      prog[FH_LEVELS] = (uint32_t)f_levels;
-      prog[FH_SCALARS] = n_scal;
-      prog[FH_SCALAR_OFF] = scal_at;
-      prog[FH_FREE] = (uint32_t)s.free_vars.size();
-      prog[FH_INV_ELEMS] = (uint32_t)inv;
-      prog[FH_DEP_ELEMS] = (uint32_t)dep;
-      prog[FH_DATA_ELEMS] = (uint32_t)data_elems;
-      prog[FH_DEP_SRC] = (uint32_t)inv;
-      prog[FH_N_SLICES] = (uint32_t)std::min<int64_t>(p.n_slices, UINT32_MAX);
+    FusedCode fc = build_fused(p, in, muj, std::vector<char>(nsteps, 1), nullptr);
+    if (fc.ok) {
       p.fused_ok = true;
-      p.fused_lds_bytes = (int)lds_bytes;
-      p.fused_prog = std::move(prog);
-      // gather map: invariant block, then one block per slice
-      p.fused_map.reserve(prep_elems);
-      for (int t = 0; t < nt; ++t)
-        if (in[t].smask == 0) {
-          const int r = (int)in[t].canon.size();
-          for (int64_t y = 0; y < (int64_t(1) << r); ++y) {
-            auto val = [&](int v) -> int {
-              int c = (int)(std::find(in[t].canon.begin(), in[t].canon.end(), v) - in[t].canon.begin());
-              return (int)((y >> (r - 1 - c)) & 1);
-            };
-            p.fused_map.push_back((int32_t)raw_index(md, t, val));
-          }
-        }
-      for (int64_t sl = 0; sl < p.n_slices; ++sl)
-        for (int t = 0; t < nt; ++t)
-          if (in[t].smask != 0) {
-            const int r = (int)in[t].canon.size();
-            for (int64_t y = 0; y < (int64_t(1) << r); ++y) {
-              auto val = [&](int v) -> int {
-                if (muj[v] >= 0) return (int)((sl >> muj[v]) & 1);
-                int c = (int)(std::find(in[t].canon.begin(), in[t].canon.end(), v) - in[t].canon.begin());
-                return (int)((y >> (r - 1 - c)) & 1);
-              };
-              p.fused_map.push_back((int32_t)raw_index(md, t, val));
-            }
-          }
+      p.fused_prog = std::move(fc.prog);
+      p.fused_map = std::move(fc.map);
       p.fused_elems = (int64_t)p.fused_map.size();
+      p.fused_lds_bytes = fc.lds_bytes;
+      p.fused_levels = fc.levels;
     }
   }
 }

@@ -17,6 +17,80 @@ std::string fail(const std::string& what, int64_t a, int64_t b) {
 
 }  // namespace
 
+// A fused program (fused.hip's executor) against the LDS size and prepared
+// input count of its plan; "" if it holds.
+static std::string check_fused_program(const std::vector<uint32_t>& w, int64_t lds_bytes, int64_t elems,
+                                       int64_t n_slices) {
+  if (w.size() < (size_t)kHdr || w[FH_WORDS] != w.size() || w.size() % 4) return "fused header";
+  const uint32_t nl = w[FH_LEVELS], nsc = w[FH_SCALARS], so = w[FH_SCALAR_OFF];
+  const uint32_t inv = w[FH_INV_ELEMS], dep = w[FH_DEP_ELEMS], data = w[FH_DATA_ELEMS], nx = w[FH_EXPORTS];
+  if (lds_bytes != std::max<int64_t>(fused_table_lds(data) + 16 * ((int64_t)nl + kFusedLevelPad + nx), 256 * 16))
+    return "fused LDS size";
+  if (nx > 0 && nsc > 0) return "fused program with both exports and scalars";
+  if (lds_bytes > kFusedLdsMax) return "fused LDS above budget";
+  if (w[FH_DEP_SRC] != inv) return "fused dependent block offset";
+  if ((int64_t)inv + (int64_t)dep * n_slices != elems) return "fused prepared size";
+  if (kFusedConsts + inv + dep > data) return "fused inputs above data size";
+  if ((int64_t)kHdr + 4 * ((int64_t)nl + kFusedLevelPad + nx) > (int64_t)w.size()) return "fused level table truncated";
+  if ((int64_t)so + nsc > (int64_t)w.size()) return "fused scalar list truncated";
+  const uint32_t* lv = w.data() + kHdr;
+  for (uint32_t j = 4 * nl; j < 4 * (nl + kFusedLevelPad); ++j)
+    if (lv[j] != 0) return "fused level table end";
+  // export rows after the table: LDS results of the program, copied
+  // exactly once (counts of the levels' X fields plus the rows left for the
+  // end); the arena side is checked by the plan
+  const uint32_t* xr = lv + 4 * ((int64_t)nl + kFusedLevelPad);
+  if ((kHdr + 4 * ((int64_t)nl + kFusedLevelPad)) % 4) return "fused export rows unaligned";
+  for (uint32_t e = 0; e < nx; ++e) {
+    const uint32_t src = xr[4 * e], rank = xr[4 * e + 1];
+    if (rank > 15 || src < kFusedConsts + inv + dep || (int64_t)src + (int64_t(1) << rank) > data)
+      return "fused export row outside its LDS results";
+  }
+  int64_t x_copied = 0;
+  int64_t expect_base = kHdr + 4 * ((int64_t)nl + kFusedLevelPad + nx);
+  const bool bytes = w[FH_BYTE_OFFSETS] != 0;
+  if (w[FH_BYTE_OFFSETS] > 1 || bytes != ((int64_t)data * 8 <= 65536)) return "fused offset unit";
+  const uint32_t unit = bytes ? 8u : 1u;
+  const uint32_t arena_lo = (kFusedConsts + inv + dep) * unit, data_hi = data * unit;
+  if (data_hi > 65536) return "fused offsets above 16 bits";
+  for (uint32_t l = 0; l < nl; ++l) {
+    const uint32_t base = lv[4 * l], E = lv[4 * l + 1], R = lv[4 * l + 2] & 0xFFFFu, lgT = lv[4 * l + 2] >> 16,
+                   K = lv[4 * l + 3] & 0xFFFFu, X = lv[4 * l + 3] >> 16;
+    if (base != expect_base) return fail("fused record base", base, expect_base);
+    x_copied += X;
+    if (x_copied > nx) return "fused level copies more export rows than the program holds";
+    if (base % 4 || R != (1 + K + 7) / 8 || E == 0 || K == 0 || lgT < 1 || lgT > 3) return "fused level shape";
+    if (lgT > 1 && ((int64_t)E << lgT) > kFusedBlock) return "fused level of many terms above the workgroup";
+    const uint32_t T = 1u << lgT;
+    if ((int64_t)base + (int64_t)E * T * 4 * R > (int64_t)w.size()) return "fused records truncated";
+    for (uint32_t f = 0; f < E; ++f)
+      for (uint32_t t = 0; t < T; ++t) {
+        const uint32_t* rec = w.data() + base + ((size_t)f * T + t) * 4 * R;
+        auto hw = [&](uint32_t j) { return (rec[j / 2] >> (16 * (j % 2))) & 0xFFFFu; };
+        if (t == 0) {
+          const uint32_t out = hw(0);
+          if (out % unit || out < arena_lo || out >= data_hi) return "fused result outside the arena";
+        } else if (hw(0) != 0) {
+          return "fused term's result slot not zero";
+        }
+        for (uint32_t j = 1; j < 8 * R; ++j) {
+          const uint32_t v = hw(j);
+          if (v % unit || v >= data_hi) return "fused operand outside LDS data";
+          if (j > K && v != 0) return "fused padding slot not the constant";
+        }
+      }
+    expect_base += (int64_t)E * T * 4 * R;
+  }
+  if (expect_base != so) return "fused scalar list offset";
+  (void)x_copied;  // the rest of the rows are copied after the last level
+  if ((int64_t)(so + nsc + 3) / 4 * 4 + 4 * kFusedTailRows != (int64_t)w.size()) return "fused program tail";
+  for (size_t j = so + nsc; j < w.size(); ++j)
+    if (w[j] != 0) return "fused program tail not zero";
+  for (uint32_t j = 0; j < nsc; ++j)
+    if (w[so + j] >= data) return "fused scalar outside LDS data";
+  return "";
+}
+
 std::string check_plan(const Plan& p) {
   const int64_t raw_elems = (int64_t)p.model.data.size() / 2;
   for (size_t i = 0; i < p.step_map.size(); ++i)
@@ -141,59 +215,33 @@ std::string check_plan(const Plan& p) {
 
   // fused program
   if (p.fused_ok) {
-    const auto& w = p.fused_prog;
-    if (w.size() < (size_t)kHdr || w[FH_WORDS] != w.size() || w.size() % 4) return "fused header";
-    const uint32_t nl = w[FH_LEVELS], nsc = w[FH_SCALARS], so = w[FH_SCALAR_OFF];
-    const uint32_t inv = w[FH_INV_ELEMS], dep = w[FH_DEP_ELEMS], data = w[FH_DATA_ELEMS];
-    if (p.fused_lds_bytes != std::max<int64_t>(fused_table_lds(data) + 16 * ((int64_t)nl + kFusedLevelPad), 256 * 16))
-      return "fused LDS size";
-    if (p.fused_lds_bytes > kFusedLdsMax) return "fused LDS above budget";
-    if (w[FH_DEP_SRC] != inv) return "fused dependent block offset";
-    if ((int64_t)inv + (int64_t)dep * p.n_slices != p.fused_elems) return "fused prepared size";
-    if (kFusedConsts + inv + dep > data) return "fused inputs above data size";
-    if ((int64_t)kHdr + 4 * ((int64_t)nl + kFusedLevelPad) > (int64_t)w.size()) return "fused level table truncated";
-    if ((int64_t)so + nsc > (int64_t)w.size()) return "fused scalar list truncated";
-    const uint32_t* lv = w.data() + kHdr;
-    for (uint32_t j = 4 * nl; j < 4 * (nl + kFusedLevelPad); ++j)
-      if (lv[j] != 0) return "fused level table end";
-    int64_t expect_base = (kHdr + 4 * ((int64_t)nl + kFusedLevelPad) + 3) / 4 * 4;
-    const bool bytes = w[FH_BYTE_OFFSETS] != 0;
-    if (w[FH_BYTE_OFFSETS] > 1 || bytes != ((int64_t)data * 8 <= 65536)) return "fused offset unit";
-    const uint32_t unit = bytes ? 8u : 1u;
-    const uint32_t arena_lo = (kFusedConsts + inv + dep) * unit, data_hi = data * unit;
-    if (data_hi > 65536) return "fused offsets above 16 bits";
-    for (uint32_t l = 0; l < nl; ++l) {
-      const uint32_t base = lv[4 * l], E = lv[4 * l + 1], R = lv[4 * l + 2] & 0xFFFFu, lgT = lv[4 * l + 2] >> 16,
-                     K = lv[4 * l + 3];
-      if (base != expect_base) return fail("fused record base", base, expect_base);
-      if (base % 4 || R != (1 + K + 7) / 8 || E == 0 || K == 0 || lgT < 1 || lgT > 3) return "fused level shape";
-      if (lgT > 1 && ((int64_t)E << lgT) > kFusedBlock) return "fused level of many terms above the workgroup";
-      const uint32_t T = 1u << lgT;
-      if ((int64_t)base + (int64_t)E * T * 4 * R > (int64_t)w.size()) return "fused records truncated";
-      for (uint32_t f = 0; f < E; ++f)
-        for (uint32_t t = 0; t < T; ++t) {
-          const uint32_t* rec = w.data() + base + ((size_t)f * T + t) * 4 * R;
-          auto hw = [&](uint32_t j) { return (rec[j / 2] >> (16 * (j % 2))) & 0xFFFFu; };
-          if (t == 0) {
-            const uint32_t out = hw(0);
-            if (out % unit || out < arena_lo || out >= data_hi) return "fused result outside the arena";
-          } else if (hw(0) != 0) {
-            return "fused term's result slot not zero";
-          }
-          for (uint32_t j = 1; j < 8 * R; ++j) {
-            const uint32_t v = hw(j);
-            if (v % unit || v >= data_hi) return "fused operand outside LDS data";
-            if (j > K && v != 0) return "fused padding slot not the constant";
-          }
-        }
-      expect_base += (int64_t)E * T * 4 * R;
+    const std::string bad = check_fused_program(p.fused_prog, p.fused_lds_bytes, p.fused_elems, p.n_slices);
+    if (!bad.empty()) return bad;
+  }
+  // fused prefix: a program with no scalar list whose exports land in the
+  // arena; no per-step launch contracts its buckets (the execution order
+  // check above covers the per-step steps only)
+  if (p.prefix_ok) {
+    for (size_t i = 0; i < p.prefix_map.size(); ++i)
+      if (p.prefix_map[i] < 0 || p.prefix_map[i] >= raw_elems)
+        return fail("prefix map entry out of range", p.prefix_map[i], raw_elems);
+    const auto& w = p.prefix_prog;
+    const std::string bad = check_fused_program(w, p.prefix_lds_bytes, p.prefix_elems, p.n_slices);
+    if (!bad.empty()) return "prefix: " + bad;
+    if (w[FH_SCALARS] != 0) return "prefix with a scalar list";
+    if (p.prefix_exports.empty() || p.prefix_exports.size() != 4 * (size_t)w[FH_EXPORTS]) return "prefix export list";
+    if (!std::equal(p.prefix_exports.begin(), p.prefix_exports.end(),
+                    w.begin() + kHdr + 4 * ((int64_t)w[FH_LEVELS] + kFusedLevelPad)))
+      return "prefix export list differs from the program's rows";
+    const int64_t lo = kFusedConsts + (int64_t)w[FH_INV_ELEMS] + w[FH_DEP_ELEMS], hi = w[FH_DATA_ELEMS];
+    for (size_t i = 0; i < p.prefix_exports.size(); i += 4) {
+      const int64_t src = p.prefix_exports[i], rank = p.prefix_exports[i + 1];
+      const int64_t off = (int64_t)(((uint64_t)p.prefix_exports[i + 3] << 32) | p.prefix_exports[i + 2]);
+      if (rank > p.prefix_max_rank) return "prefix export above its rank bound";
+      if (src < lo || src + (int64_t(1) << rank) > hi) return "prefix export outside its LDS results";
+      if (off < 0 || off + (int64_t(1) << rank) > p.arena_per_slice)
+        return fail("prefix export outside the arena", off + (int64_t(1) << rank), p.arena_per_slice);
     }
-    if (expect_base != so) return "fused scalar list offset";
-    if ((int64_t)(so + nsc + 3) / 4 * 4 + 4 * kFusedTailRows != (int64_t)w.size()) return "fused program tail";
-    for (size_t j = so + nsc; j < w.size(); ++j)
-      if (w[j] != 0) return "fused program tail not zero";
-    for (uint32_t j = 0; j < nsc; ++j)
-      if (w[so + j] >= data) return "fused scalar outside LDS data";
   }
   return "";
 }

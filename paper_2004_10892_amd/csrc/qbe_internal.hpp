@@ -139,6 +139,22 @@ struct Plan {
   int32_t group_sb = 1;                 // slices per block of a group launch
   std::vector<int32_t> step_level;      // level of each step in that order
 
+  // fused prefix of a per-step plan (qbe_plan_opts.fused_prefix): the
+  // subtrees of small buckets in one LDS-resident launch before the per-step
+  // launches; its export rows (4 words each: LDS element offset, rank, arena
+  // offset lo, hi; prefix_exports is a copy of those in the program) copy
+  // the results larger buckets read to the arena
+  int want_prefix = 0;                  // 0 none, 1 the largest bound that fits, else R
+  bool prefix_ok = false;
+  int prefix_max_rank = -1;             // result rank bound R of its buckets
+  int prefix_buckets = 0;
+  std::vector<uint32_t> prefix_prog;    // a fused program (fused_format.hpp), no scalar list
+  std::vector<int32_t> prefix_map;      // its prepared-input gather map
+  int64_t prefix_elems = 0;
+  int prefix_lds_bytes = 0, prefix_levels = 0;
+  std::vector<uint32_t> prefix_exports;
+  int64_t prefix_bytes_per_slice = 0, prefix_flops_per_slice = 0;
+
   // fused form
   bool fused_ok = false;
   std::vector<uint32_t> fused_prog;
@@ -157,6 +173,9 @@ struct Plan {
   void* d_scalar_tab = nullptr; // int64 arena offsets, int64 input bases, uint32 smasks
   void* d_state = nullptr;      // uint32[4]: work counter, exits, items done (fused)
   void* d_group = nullptr;      // GroupStep array, then the uint32 tile prefixes
+  void* d_prefix_map = nullptr; // fused prefix: gather map, prepared inputs
+  void* d_prefix_in = nullptr;  //   and program
+  void* d_prefix_prog = nullptr;
 };
 
 // A set of plans contracted together in one fused launch.
