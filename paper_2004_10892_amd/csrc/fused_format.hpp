@@ -12,6 +12,9 @@ constexpr int kFusedBlock = 512;
 // LDS budget of one fused workgroup (bytes): tensor entries, plus the
 // program's records when they fit too (gfx950: 160 KB per workgroup).
 constexpr int kFusedLdsMax = 160 * 1024 - 256;
+// The largest LDS size (bytes) of which two workgroups fit one compute unit
+// (with the 16 bytes of control words each).
+constexpr int kFusedLdsPair = 160 * 1024 / 2 - 16;
 // Largest slice count whose FP64 sum the fused kernel does itself (the
 // last workgroup of a plan); above it a separate reduction kernel runs.
 constexpr int64_t kInKernelReduceMax = 8192;

@@ -378,7 +378,8 @@ struct FusedCode {
 };
 
 static FusedCode build_fused(const Plan& p, const std::vector<InputInfo>& in, const std::vector<int>& muj,
-                             const std::vector<char>& incl, const std::vector<int64_t>* export_off) {
+                             const std::vector<char>& incl, const std::vector<int64_t>* export_off,
+                             int64_t lds_cap = kFusedLdsMax) {
   const Model& md = p.model;
   const Schedule& s = p.sched;
   const int nt = (int)md.tvars.size();
@@ -391,19 +392,24 @@ static FusedCode build_fused(const Plan& p, const std::vector<InputInfo>& in, co
       if (incl[k])
         for (const auto& op : s.steps[k].ops)
           if (op.kind == 't') used[op.id] = 1;
-  // LDS element offsets of the inputs (after the constants 1 and 0)
+  // LDS element offsets (after the constants 1 and 0): one arena holds the
+  // inputs -- its first allocations, contiguous, slice-invariant ones first,
+  // as the executor copies them in -- and the results.  A node reads each of
+  // its inputs only, so an input's space is reused once its node has run.
+  Arena la;
   std::vector<int64_t> lds_in(nt, -1);
   int64_t inv = 0, dep = 0;
   for (int t = 0; t < nt; ++t)
     if (used[t] && in[t].smask == 0) {
-      lds_in[t] = kFusedConsts + inv;
+      lds_in[t] = kFusedConsts + la.alloc(int64_t(1) << in[t].canon.size(), 1);
       inv += int64_t(1) << in[t].canon.size();
     }
   for (int t = 0; t < nt; ++t)
     if (used[t] && in[t].smask != 0) {
-      lds_in[t] = kFusedConsts + inv + dep;
+      lds_in[t] = kFusedConsts + la.alloc(int64_t(1) << in[t].canon.size(), 1);
       dep += int64_t(1) << in[t].canon.size();
     }
+  if (la.top != inv + dep) throw std::logic_error("fused input block not contiguous");
   // merged nodes (each writes its root bucket's result) and their levels
   const std::vector<FusedNode> nodes = merge_buckets(s, p.merge, incl);
   int f_levels = 0;
@@ -424,26 +430,28 @@ static FusedCode build_fused(const Plan& p, const std::vector<InputInfo>& in, co
           exp_level.push_back(l);
         }
       }
-  // arena by levels: all results of a level are live while the level runs;
-  // an exported result stays live through the next level, during which it is
+  // results by levels: all results of a level are live while the level
+  // runs; then its nodes' operands (results and inputs) are free; an
+  // exported result stays live through the next level, during which it is
   // copied out
-  Arena la;
   std::vector<int64_t> lds_out(nsteps, -1);
   std::vector<int> copying;  // exported results of the previous level
   for (int l = 0; l < f_levels; ++l) {
     for (int i : by_level[l]) {
       const int c = nodes[i].members[0];
-      lds_out[c] = la.alloc(int64_t(1) << s.steps[c].out.size(), 1);
+      lds_out[c] = kFusedConsts + la.alloc(int64_t(1) << s.steps[c].out.size(), 1);
     }
-    for (int i : by_level[l])
-      for (int kid : nodes[i].kids) la.release(lds_out[kid], int64_t(1) << s.steps[kid].out.size());
-    for (int c : copying) la.release(lds_out[c], int64_t(1) << s.steps[c].out.size());
+    for (int i : by_level[l]) {
+      for (int kid : nodes[i].kids) la.release(lds_out[kid] - kFusedConsts, int64_t(1) << s.steps[kid].out.size());
+      for (const Operand& op : nodes[i].factors)
+        if (op.kind == 't') la.release(lds_in[op.id] - kFusedConsts, int64_t(1) << in[op.id].canon.size());
+    }
+    for (int c : copying) la.release(lds_out[c] - kFusedConsts, int64_t(1) << s.steps[c].out.size());
     copying.clear();
     for (size_t e = 0; e < exp_steps.size(); ++e)
       if (exp_level[e] == l) copying.push_back(exp_steps[e]);
   }
-  const int64_t arena0 = kFusedConsts + inv + dep;
-  const int64_t data_elems = arena0 + la.top;
+  const int64_t data_elems = kFusedConsts + la.top;
   // each level's factors F, terms T and entries E; a prefix program splits
   // its levels into one-pass parts (their records all read ahead), as many
   // slices run it at once and a level's extra record reads would stall them
@@ -464,7 +472,8 @@ static FusedCode build_fused(const Plan& p, const std::vector<InputInfo>& in, co
   const int64_t lds_bytes =
       std::max<int64_t>(fused_table_lds(data_elems) + 16 * (n_table + kFusedLevelPad + n_exp), 256 * 16);
   const int64_t prep_elems = inv + dep * p.n_slices;
-  if (f_levels == 0 || lds_bytes > kFusedLdsMax || prep_elems >= (int64_t(1) << 31)) return out;
+  // (a whole-schedule program may have no levels: every variable sliced)
+  if ((export_off && f_levels == 0) || lds_bytes > lds_cap || prep_elems >= (int64_t(1) << 31)) return out;
   std::vector<uint32_t> prog(kHdr, 0);
   const size_t lvl_at = prog.size();
   // zero entries after the last level end the executor's look-ahead
@@ -508,7 +517,7 @@ static FusedCode build_fused(const Plan& p, const std::vector<InputInfo>& in, co
           const size_t at = prog.size();
           prog.resize(at + 4 * R, 0);
           auto put = [&](uint32_t j, uint32_t v) { prog[at + j / 2] |= (v * unit) << (16 * (j % 2)); };
-          if (t == 0) put(0, (uint32_t)(arena0 + lds_out[nd.members[0]] + x));
+          if (t == 0) put(0, (uint32_t)(lds_out[nd.members[0]] + x));
           if (t >= Tn) {
             put(1, kFusedZero);  // padding term: a factor 0
             continue;
@@ -523,7 +532,7 @@ static FusedCode build_fused(const Plan& p, const std::vector<InputInfo>& in, co
               if (val[v] < 0) throw std::logic_error("fused node factor outside its variables");
               e = (e << 1) | (uint32_t)val[v];
             }
-            const int64_t base = op.kind == 't' ? lds_in[op.id] : arena0 + lds_out[op.id];
+            const int64_t base = op.kind == 't' ? lds_in[op.id] : lds_out[op.id];
             put(1 + (uint32_t)f, (uint32_t)(base + e));
           }
           for (int q = 0; q < r; ++q) val[root.out[q]] = -1;
@@ -541,13 +550,13 @@ static FusedCode build_fused(const Plan& p, const std::vector<InputInfo>& in, co
       ++n_scal;
     }
     for (int k : s.scalar_steps) {
-      prog.push_back((uint32_t)(arena0 + lds_out[k]));
+      prog.push_back((uint32_t)lds_out[k]);
       ++n_scal;
     }
   } else {
     for (int64_t e = 0; e < n_exp; ++e) {
       if (lds_out[exp_steps[e]] < 0) throw std::logic_error("exported bucket without a result");
-      prog[out.export_at + 4 * e] = (uint32_t)(arena0 + lds_out[exp_steps[e]]);
+      prog[out.export_at + 4 * e] = (uint32_t)lds_out[exp_steps[e]];
     }
   }
   while (prog.size() % 4) prog.push_back(0);
@@ -657,7 +666,10 @@ void compile_plan(Plan& p) {
   // R + 1 variables and whose producers all do -- run as one LDS-resident
   // launch (fused.hip) before the per-step launches; the results that larger
   // buckets read (and rank-0 results) are exported to the arena.  R is the
-  // largest of 10, 8, 6, 4 whose prefix fits the LDS budget.
+  // one asked for, or else the largest of 14 .. 4 whose prefix lets two
+  // workgroups share a compute unit (a slice's levels are latency-bound:
+  // two slices per compute unit halve the rounds), else the largest of 10,
+  // 8, 6, 4 that fits LDS at all.
   const int nsteps = (int)s.steps.size();
   std::vector<char> in_prefix(nsteps, 0);
   std::vector<int64_t> export_mark(nsteps, -1);
@@ -672,8 +684,14 @@ void compile_plan(Plan& p) {
   p.prefix_bytes_per_slice = 0;
   p.prefix_flops_per_slice = 0;
   if (p.want_prefix > 0 && p.merge && p.m <= 24) {
-    const std::vector<int> bounds = p.want_prefix == 1 ? std::vector<int>{10, 8, 6, 4} : std::vector<int>{p.want_prefix};
-    for (int R : bounds) {
+    std::vector<std::pair<int, int64_t>> tries;  // (R, LDS cap)
+    if (p.want_prefix == 1) {
+      for (int R = 14; R >= 4; --R) tries.push_back({R, kFusedLdsPair});
+      for (int R : {10, 8, 6, 4}) tries.push_back({R, kFusedLdsMax});
+    } else {
+      tries.push_back({p.want_prefix, kFusedLdsMax});
+    }
+    for (const auto& [R, cap] : tries) {
       std::vector<char> f(nsteps, 0);
       int cnt = 0;
       for (int k = 0; k < nsteps; ++k) {  // producers precede their consumers
@@ -687,7 +705,7 @@ void compile_plan(Plan& p) {
       std::vector<int64_t> mark(nsteps, -1);
       for (int k = 0; k < nsteps; ++k)
         if (f[k] && (s.consumer[k] < 0 || !f[s.consumer[k]])) mark[k] = 0;
-      FusedCode fc = build_fused(p, in, muj, f, &mark);
+      FusedCode fc = build_fused(p, in, muj, f, &mark, cap);
       if (!fc.ok) continue;
       in_prefix = f;
       export_mark = mark;

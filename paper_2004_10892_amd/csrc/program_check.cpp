@@ -43,7 +43,7 @@ static std::string check_fused_program(const std::vector<uint32_t>& w, int64_t l
   if ((kHdr + 4 * ((int64_t)nl + kFusedLevelPad)) % 4) return "fused export rows unaligned";
   for (uint32_t e = 0; e < nx; ++e) {
     const uint32_t src = xr[4 * e], rank = xr[4 * e + 1];
-    if (rank > 15 || src < kFusedConsts + inv + dep || (int64_t)src + (int64_t(1) << rank) > data)
+    if (rank > 15 || src < kFusedConsts || (int64_t)src + (int64_t(1) << rank) > data)
       return "fused export row outside its LDS results";
   }
   int64_t x_copied = 0;
@@ -51,7 +51,8 @@ static std::string check_fused_program(const std::vector<uint32_t>& w, int64_t l
   const bool bytes = w[FH_BYTE_OFFSETS] != 0;
   if (w[FH_BYTE_OFFSETS] > 1 || bytes != ((int64_t)data * 8 <= 65536)) return "fused offset unit";
   const uint32_t unit = bytes ? 8u : 1u;
-  const uint32_t arena_lo = (kFusedConsts + inv + dep) * unit, data_hi = data * unit;
+  // results may take the space of inputs their level no longer needs
+  const uint32_t arena_lo = kFusedConsts * unit, data_hi = data * unit;
   if (data_hi > 65536) return "fused offsets above 16 bits";
   for (uint32_t l = 0; l < nl; ++l) {
     const uint32_t base = lv[4 * l], E = lv[4 * l + 1], R = lv[4 * l + 2] & 0xFFFFu, lgT = lv[4 * l + 2] >> 16,
@@ -233,7 +234,7 @@ std::string check_plan(const Plan& p) {
     if (!std::equal(p.prefix_exports.begin(), p.prefix_exports.end(),
                     w.begin() + kHdr + 4 * ((int64_t)w[FH_LEVELS] + kFusedLevelPad)))
       return "prefix export list differs from the program's rows";
-    const int64_t lo = kFusedConsts + (int64_t)w[FH_INV_ELEMS] + w[FH_DEP_ELEMS], hi = w[FH_DATA_ELEMS];
+    const int64_t lo = kFusedConsts, hi = w[FH_DATA_ELEMS];
     for (size_t i = 0; i < p.prefix_exports.size(); i += 4) {
       const int64_t src = p.prefix_exports[i], rank = p.prefix_exports[i + 1];
       const int64_t off = (int64_t)(((uint64_t)p.prefix_exports[i + 3] << 32) | p.prefix_exports[i + 2]);

@@ -304,3 +304,20 @@ def test_general_dimension_models_expand_to_binary():
         qbe.Model.from_dims([2 ** 16, 2 ** 16, 2 ** 16], [((0, 1, 2), np.ones(1))])  # 48 bits
     b = qbe.Model(3, [((0, 1), np.ones((2, 2))), ((2,), np.ones(2))])
     assert b.var_bits(2) == (2, 1)
+
+
+def test_fused_programs_of_degenerate_schedules():
+    """Schedules with no buckets (every variable sliced) or a single one
+    still compile to sound fused programs (only scalar factors, or one
+    level), as the per-step form does."""
+    rng = np.random.default_rng(3)
+    t = [((0, 1), rng.standard_normal((2, 2)) + 1j * rng.standard_normal((2, 2))),
+         ((1,), rng.standard_normal(2) + 0j)]
+    qm = qbe.Model(2, t)
+    for mu, order in (([0, 1], []), ([1], [0]), ([], [0, 1])):
+        for form in ("fused", "per_step"):
+            plan = qbe.Plan(qm, order, mu, exec=form)
+            plan.check()
+            assert plan.stats()["exec"] == qbe.EXEC[form]
+        if not order:
+            assert qbe.Plan(qm, order, mu, exec="fused").stats()["fused_levels"] == 0

@@ -27,7 +27,7 @@ def test_prefix_takes_small_buckets_and_keeps_the_byte_count(c3):
     assert sq["step_bytes_per_slice"] <= sp["step_bytes_per_slice"]
     la = pre.launches()
     assert la[0]["kind"] == "prefix" and la[0]["n_buckets"] == sq["prefix_buckets"]
-    assert 4 <= la[0]["out_rank"] <= 10
+    assert 4 <= la[0]["out_rank"] <= 14
     assert [l["kind"] for l in la[-2:]] == ["finalize", "reduce"]
     assert "prefix" not in [l["kind"] for l in la[1:]]
     assert len(la) == sq["n_launches"] + 2
@@ -84,5 +84,12 @@ def test_explicit_rank_bounds(c3):
         n = p.stats()["prefix_buckets"]
         assert n >= prev
         prev = n
+    # the automatic bound: the largest whose prefix lets two workgroups
+    # share a compute unit's 160 KB of LDS
+    pair = 160 * 1024 // 2 - 16
     auto = qbe.Plan(qm, pi, mu, exec="per_step", fused_prefix=True).launches()[0]
-    assert auto["out_rank"] == 10
+    R = auto["out_rank"]
+    assert auto["kind"] == "prefix" and auto["lds_bytes"] <= pair
+    for bigger in range(R + 1, 15):
+        la = qbe.Plan(qm, pi, mu, exec="per_step", fused_prefix=bigger).launches()[0]
+        assert la["kind"] != "prefix" or la["lds_bytes"] > pair
