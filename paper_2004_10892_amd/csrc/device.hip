@@ -1114,46 +1114,82 @@ __global__ __launch_bounds__(kBlock) void mmb_kernel(MmbLaunch a) {
   }
 }
 
-// Per-slice product of the scalar factors, in FP64.
-struct FinalizeArgs {
+// Where one slice group's scalar factors are: its rank-0 results in the
+// arena and the scalar inputs in the prepared buffer.
+struct ScalarSrc {
   const float2* arena;
   const float2* prep;
-  const int64_t* arena_off;   // device arrays
+  const int64_t* arena_off;  // device arrays
   const int64_t* in_base;
   const uint32_t* in_smask;
   int32_t n_arena, n_in, n_free;
-  int64_t G, s0;
+  int64_t G;
+};
+
+// FP64 product of one slice's scalar factors -- 2^n_free, the rank-0
+// results, then the scalar inputs -- by a group of L lanes (L a power of two
+// of at most 64, q the lane in the group): lane q multiplies factors q,
+// q + L, ... in sequence (lane 0 starting from 2^n_free), then a binary tree
+// over the group; its lane 0 returns the product.  ok = false: a lane past
+// the last slice (factors of 1, nothing read).  Every lane of the group
+// calls it (the tree shuffles within the group).
+__device__ __forceinline__ double2 slice_product(const ScalarSrc& a, int64_t g, int64_t s, bool ok, uint32_t q,
+                                                 uint32_t L) {
+  double re = q == 0 ? ldexp(1.0, a.n_free) : 1.0, im = 0.0;
+  const int n = ok ? a.n_arena + a.n_in : 0;
+  for (int j = (int)q; j < n; j += (int)L) {
+    const float2 v = j < a.n_arena
+                         ? a.arena[a.arena_off[j] * a.G + g]
+                         : a.prep[a.in_base[j - a.n_arena] + (int64_t)pext32((uint32_t)s, a.in_smask[j - a.n_arena])];
+    const double vr = v.x, vi = v.y;
+    const double nr = re * vr - im * vi;
+    im = re * vi + im * vr;
+    re = nr;
+  }
+  for (uint32_t w = 1; w < L; w <<= 1) {
+    const double orr = __shfl_down(re, w, (int)L), oi = __shfl_down(im, w, (int)L);
+    const double nr = re * orr - im * oi;
+    im = re * oi + im * orr;
+    re = nr;
+  }
+  return make_double2(re, im);
+}
+
+// Lanes per slice of slice_product: the factor count rounded up to a power
+// of two, at most a wave.
+static uint32_t scalar_lanes(int n_factors) {
+  uint32_t L = 1;
+  while ((int)L < n_factors && L < 64) L <<= 1;
+  return L;
+}
+
+// Per-slice product of the scalar factors, in FP64: L lanes a slice, so
+// that the factors of a slice are read at once.
+struct FinalizeArgs {
+  ScalarSrc src;
+  uint32_t lanes;
+  int64_t s0;
   double2* per_slice;  // indexed by g
 };
 
-__global__ void finalize_kernel(FinalizeArgs a) {
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < a.G;
-       g += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t s = a.s0 + g;
-    double re = ldexp(1.0, a.n_free), im = 0.0;
-    for (int j = 0; j < a.n_arena; ++j) {
-      const float2 v = a.arena[a.arena_off[j] * a.G + g];
-      const double vr = v.x, vi = v.y;
-      const double nr = re * vr - im * vi;
-      im = re * vi + im * vr;
-      re = nr;
-    }
-    for (int j = 0; j < a.n_in; ++j) {
-      const float2 v = a.prep[a.in_base[j] + (int64_t)pext32((uint32_t)s, a.in_smask[j])];
-      const double vr = v.x, vi = v.y;
-      const double nr = re * vr - im * vi;
-      im = re * vi + im * vr;
-      re = nr;
-    }
-    a.per_slice[g] = make_double2(re, im);
+__global__ __launch_bounds__(256) void finalize_kernel(FinalizeArgs a) {
+  const uint32_t L = a.lanes, q = threadIdx.x % L;
+  const int64_t per_block = 256 / L;
+  // the bound is the same for every lane of a workgroup, so every group's
+  // lanes reach its tree together
+  for (int64_t base = (int64_t)blockIdx.x * per_block; base < a.src.G; base += (int64_t)gridDim.x * per_block) {
+    const int64_t g = base + threadIdx.x / L;
+    const bool ok = g < a.src.G;
+    const double2 v = slice_product(a.src, g, a.s0 + g, ok, q, L);
+    if (ok && q == 0) a.per_slice[g] = v;
   }
 }
 
 // FP64 slice product of the rank-0 results and the slice sum of every
-// per-step instance of a batch, one workgroup per instance: lane t takes
-// slices t, t + 256, ... in sequence (computing each as finalize_kernel
-// does and adding it), then a binary tree over the 256 partials -- the
-// order of reduce_kernel.
+// per-step instance of a batch, one workgroup per instance: the products as
+// finalize_kernel computes them (L lanes a slice), 256 slices at a time into
+// LDS; lane t adds slices t, t + 256, ... in sequence, then a binary tree
+// over the 256 partials -- the order of reduce_kernel.
 struct WideFinal {
   int64_t arena;            // complex64 offset of the instance's arena in the workspace
   const float2* prep;       // its prepared inputs
@@ -1162,32 +1198,33 @@ struct WideFinal {
   const uint32_t* in_smask;
   int32_t n_arena, n_in, n_free, plan;  // plan: index of its amplitude
   int64_t G;                // its slices (all run at once)
+  uint32_t lanes;           // lanes per slice product
+  uint32_t pad;
 };
 
 __global__ __launch_bounds__(256) void wide_final_kernel(const WideFinal* __restrict__ w, const float2* ws,
                                                          double2* __restrict__ amps) {
   __shared__ double sre[256], sim[256];
   const WideFinal& d = w[blockIdx.x];
-  const float2* arena = ws + d.arena;
+  const ScalarSrc src{ws + d.arena, d.prep, d.arena_off, d.in_base, d.in_smask, d.n_arena, d.n_in, d.n_free, d.G};
+  const uint32_t L = d.lanes, q = threadIdx.x % L, per = 256 / L;
   double sr = 0.0, si = 0.0;
-  for (int64_t g = threadIdx.x; g < d.G; g += 256) {
-    double re = ldexp(1.0, d.n_free), im = 0.0;
-    for (int j = 0; j < d.n_arena; ++j) {
-      const float2 v = arena[d.arena_off[j] * d.G + g];
-      const double vr = v.x, vi = v.y;
-      const double nr = re * vr - im * vi;
-      im = re * vi + im * vr;
-      re = nr;
+  for (int64_t base = 0; base < d.G; base += 256) {
+    for (uint32_t k = 0; k < L; ++k) {
+      const uint32_t i = k * per + threadIdx.x / L;  // slice base + i of this chunk
+      const bool ok = base + i < d.G;
+      const double2 v = slice_product(src, base + i, base + i, ok, q, L);
+      if (q == 0) {
+        sre[i] = v.x;
+        sim[i] = v.y;
+      }
     }
-    for (int j = 0; j < d.n_in; ++j) {
-      const float2 v = d.prep[d.in_base[j] + (int64_t)pext32((uint32_t)g, d.in_smask[j])];
-      const double vr = v.x, vi = v.y;
-      const double nr = re * vr - im * vi;
-      im = re * vi + im * vr;
-      re = nr;
+    __syncthreads();
+    if (base + threadIdx.x < d.G) {
+      sr += sre[threadIdx.x];
+      si += sim[threadIdx.x];
     }
-    sr += re;
-    si += im;
+    __syncthreads();
   }
   sre[threadIdx.x] = sr;
   sim[threadIdx.x] = si;
@@ -1804,18 +1841,19 @@ static int finalize_group(const Plan& p, float2* arena, double2* per_slice, int6
   const int64_t* t_inb = t_arena + p.scalar_arena.size();
   const uint32_t* t_ism = (const uint32_t*)(t_inb + p.scalar_inputs_base.size());
   FinalizeArgs fa{};
-  fa.arena = arena;
-  fa.prep = (const float2*)p.d_step_in;
-  fa.arena_off = t_arena;
-  fa.in_base = t_inb;
-  fa.in_smask = t_ism;
-  fa.n_arena = (int)p.scalar_arena.size();
-  fa.n_in = (int)p.scalar_inputs_base.size();
-  fa.n_free = (int)p.sched.free_vars.size();
-  fa.G = G;
+  fa.src = ScalarSrc{arena,
+                     (const float2*)p.d_step_in,
+                     t_arena,
+                     t_inb,
+                     t_ism,
+                     (int32_t)p.scalar_arena.size(),
+                     (int32_t)p.scalar_inputs_base.size(),
+                     (int32_t)p.sched.free_vars.size(),
+                     G};
+  fa.lanes = scalar_lanes(fa.src.n_arena + fa.src.n_in);
   fa.s0 = s0;
   fa.per_slice = per_slice;
-  finalize_kernel<<<grid_for(G, 256), 256, 0, st>>>(fa);
+  finalize_kernel<<<grid_for(G * fa.lanes, 256), 256, 0, st>>>(fa);
   QBE_HIP(hipGetLastError());
   return QBE_OK;
 }
@@ -2071,6 +2109,7 @@ int step_batch_build(Batch& b) {
       f.n_free = (int32_t)p.sched.free_vars.size();
       f.plan = b.wide[q];
       f.G = p.n_slices;
+      f.lanes = scalar_lanes(f.n_arena + f.n_in);
       fin.push_back(f);
     }
     int rc = upload(&b.d_wide_final, fin.data(), fin.size() * sizeof(WideFinal));
