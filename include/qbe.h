@@ -106,15 +106,26 @@ typedef struct qbe_plan_opts {
                           whatever the plan's precision) before its
                           per-step launches, which read the results it
                           writes to the workspace.  1: R is the largest of
-                          10, 8, 6, 4 whose prefix fits LDS; 2..14: R =
-                          fused_prefix.  Needs merging (no_merge 0) and at
-                          most 24 sliced variables; a plan with no such
-                          prefix (fewer than two small buckets, or it does
-                          not fit LDS) runs without one
-                          (stats.prefix_buckets 0).  Ignored by plans that
-                          run in the fused form.  0: no prefix (default);
-                          other values: QBE_ERR_INVALID_ARG                 */
-  int32_t reserved[3]; /* must be zero                                       */
+                          14 .. 4 whose prefix lets two workgroups share a
+                          compute unit's LDS, else the largest of 10, 8,
+                          6, 4 that fits at all; 2..14: R = fused_prefix.
+                          Needs merging (no_merge 0) and at most 24 sliced
+                          variables; a plan with no such prefix (fewer
+                          than two small buckets, or it does not fit LDS)
+                          runs without one (stats.prefix_buckets 0).
+                          Ignored by plans that run in the fused form.
+                          0: no prefix (default); other values:
+                          QBE_ERR_INVALID_ARG                               */
+  int32_t fused_segments; /* 1 (with fused_prefix > 0 and a prefix): every
+                          later connected run of at least three buckets of
+                          at most R + 1 variables (connected through the
+                          buckets that read their results) is contracted
+                          by one more such launch, which reads the larger
+                          results it needs from the workspace and writes
+                          its top bucket's result there; a run that does
+                          not fit LDS stays per-step launches.  0: none
+                          (default)                                         */
+  int32_t reserved[2]; /* must be zero                                       */
 } qbe_plan_opts;
 
 typedef struct qbe_stats {
@@ -142,11 +153,14 @@ typedef struct qbe_stats {
                                           (below bytes_per_slice when chains
                                           are merged)                        */
   int32_t n_launches;                  /* per-step form: contraction launches
-                                          per slice group (a merged chain or
-                                          a partial product counts once; the
-                                          fused prefix counts once)          */
+                                          per slice group (a merged chain, a
+                                          partial product or a fused segment
+                                          counts once)                       */
   int32_t prefix_buckets;              /* per-step form: buckets contracted
                                           by the fused prefix (0: none)      */
+  int32_t n_fused_segments;            /* per-step form: fused launches (the
+                                          prefix and later segments)         */
+  int32_t fused_buckets;               /* buckets they contract              */
 } qbe_stats;
 
 /* ------------------------------------------------------------------ misc -- */
@@ -390,11 +404,11 @@ int qbe_plan_autotune(qbe_ctx* ctx, qbe_plan* plan, void* d_workspace, size_t ws
                       int64_t min_elems);
 
 /* Per-launch view of a per-step plan (diagnostics and measurement): the
- * fused prefix, if the plan has one, then the execution order's launches
- * -- a single bucket, a merged chain of buckets (several summed
- * variables), a partial product of a wide bucket, or a group of small
- * buckets of one level -- then the per-slice FP64 product of the rank-0
- * results (finalize) and the slice sum (reduce, Eq. 4). */
+ * execution order's launches -- a single bucket, a merged chain of buckets
+ * (several summed variables), a partial product of a wide bucket, a group
+ * of small buckets of one level, or a fused segment -- then the per-slice
+ * FP64 product of the rank-0 results (finalize) and the slice sum (reduce,
+ * Eq. 4). */
 enum {
   QBE_LAUNCH_BUCKET = 0,
   QBE_LAUNCH_MERGED = 1,
@@ -402,16 +416,20 @@ enum {
   QBE_LAUNCH_GROUP = 3,
   QBE_LAUNCH_FINALIZE = 4,
   QBE_LAUNCH_REDUCE = 5,
-  QBE_LAUNCH_PREFIX = 6  /* the fused prefix: bytes_per_slice counts its
-                            inputs and exported results once (its other
-                            intermediates stay in LDS)                    */
+  QBE_LAUNCH_PREFIX = 6,  /* the fused prefix: bytes_per_slice counts its
+                             inputs and exported results once (its other
+                             intermediates stay in LDS)                   */
+  QBE_LAUNCH_SEGMENT = 7  /* a later fused segment: n_ops = its imported
+                             results; bytes_per_slice also counts them    */
 };
 typedef struct qbe_launch_info {
   int32_t kind;              /* QBE_LAUNCH_*                                  */
   int32_t n_buckets;         /* buckets the launch contracts (chain length,
                                 group size)                                   */
-  int32_t n_ops;             /* operands (largest in a group)                 */
-  int32_t out_rank;          /* result rank (largest in a group)              */
+  int32_t n_ops;             /* operands (largest in a group; imported
+                                results of a fused segment)                   */
+  int32_t out_rank;          /* result rank (largest in a group; the bound R
+                                of a fused segment's buckets)                 */
   int32_t n_sum;             /* summed variables per result entry             */
   int32_t mfma;              /* 1: runs on MFMA tiles                         */
   uint64_t bytes_per_slice;  /* algorithmic complex64 bytes: each operand read
@@ -419,12 +437,12 @@ typedef struct qbe_launch_info {
   uint64_t flops_per_slice;  /* real flops: per result entry 2^n_sum terms of
                                 n_ops - 1 complex products (6 flops each) and
                                 their sum                                     */
-  int32_t levels;            /* fused prefix: levels of its program (barriers
-                                per slice); 0 for other launches              */
-  int32_t lds_bytes;         /* fused prefix: LDS per workgroup; 0 otherwise  */
+  int32_t levels;            /* fused segments: levels of its program
+                                (barriers per slice); 0 for other launches    */
+  int32_t lds_bytes;         /* fused segments: LDS per workgroup; 0 otherwise */
 } qbe_launch_info;
-/* Launches of a per-step plan (its prefix, its execution order, + 2); 0 for
- * a fused plan. */
+/* Launches of a per-step plan (its execution order + 2); 0 for a fused
+ * plan. */
 int qbe_plan_num_launches(const qbe_plan* plan, int32_t* n_out);
 /* Launch i (0 <= i < qbe_plan_num_launches) of a per-step plan. */
 int qbe_plan_launch_info(const qbe_plan* plan, int32_t i, qbe_launch_info* out);

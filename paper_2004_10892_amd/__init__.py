@@ -53,7 +53,8 @@ class QbeError(RuntimeError):
 
 class PlanOpts(C.Structure):
     _fields_ = [("exec", C.c_int32), ("precision", C.c_int32), ("block", C.c_int32),
-                ("no_merge", C.c_int32), ("fused_prefix", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("no_merge", C.c_int32), ("fused_prefix", C.c_int32), ("fused_segments", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
 
 
 class Stats(C.Structure):
@@ -63,7 +64,8 @@ class Stats(C.Structure):
                 ("peak_bytes_per_slice", C.c_uint64), ("ws_bytes_min", C.c_uint64),
                 ("ws_bytes_all_slices", C.c_uint64), ("n_mfma_steps", C.c_int32), ("precision", C.c_int32),
                 ("fused_levels", C.c_int32), ("n_merged_steps", C.c_int32), ("step_bytes_per_slice", C.c_uint64),
-                ("n_launches", C.c_int32), ("prefix_buckets", C.c_int32)]
+                ("n_launches", C.c_int32), ("prefix_buckets", C.c_int32), ("n_fused_segments", C.c_int32),
+                ("fused_buckets", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -86,7 +88,8 @@ class LaunchInfo(C.Structure):
         return d
 
 
-LAUNCH_KINDS = {0: "bucket", 1: "merged", 2: "partial", 3: "group", 4: "finalize", 5: "reduce", 6: "prefix"}
+LAUNCH_KINDS = {0: "bucket", 1: "merged", 2: "partial", 3: "group", 4: "finalize", 5: "reduce", 6: "prefix",
+                7: "segment"}
 
 
 _SIGS = {
@@ -483,7 +486,7 @@ class Plan:
 
     def __init__(self, model: Model, reduced_order: Sequence[int], mu: Sequence[int],
                  ctx: Optional[Context] = None, exec: str = "auto", precision: str = "fp32",
-                 merge: bool = True, fused_prefix=False):
+                 merge: bool = True, fused_prefix=False, fused_segments: bool = False):
         o = _i32(reduced_order)
         u = _i32(mu)
         opts = PlanOpts()
@@ -493,6 +496,7 @@ class Plan:
         # False/True: no prefix / the largest rank bound that fits; an int
         # R >= 2: buckets of at most R + 1 variables
         opts.fused_prefix = int(fused_prefix)
+        opts.fused_segments = 1 if fused_segments else 0
         h = _vp()
         _check(_lib.qbe_plan_create(ctx.handle if ctx else None, model.handle, _p32(o), len(o), _p32(u), len(u),
                                     C.byref(opts), C.byref(h)), "qbe_plan_create")

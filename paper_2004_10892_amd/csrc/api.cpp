@@ -684,6 +684,8 @@ int qbe_plan_create(qbe_ctx* ctx, const qbe_model* model, const int32_t* reduced
   QBE_REQUIRE(o.block == 0 || o.block == qbe::kBlock, "unsupported block size");
   QBE_REQUIRE(o.no_merge == 0 || o.no_merge == 1, "no_merge must be 0 or 1");
   QBE_REQUIRE(o.fused_prefix >= 0 && o.fused_prefix <= 14, "fused_prefix must be in [0, 14]");
+  QBE_REQUIRE(o.fused_segments == 0 || o.fused_segments == 1, "fused_segments must be 0 or 1");
+  QBE_REQUIRE(o.fused_segments == 0 || o.fused_prefix > 0, "fused_segments needs fused_prefix > 0");
   auto* pl = new qbe_plan;
   std::unique_ptr<qbe_plan> guard(pl);
   qbe::Plan& p = pl->p;
@@ -693,6 +695,7 @@ int qbe_plan_create(qbe_ctx* ctx, const qbe_model* model, const int32_t* reduced
   p.precision = o.precision;
   p.merge = o.no_merge == 0;
   p.want_prefix = o.exec != QBE_EXEC_FUSED ? o.fused_prefix : 0;
+  p.want_segments = o.fused_segments == 1;
   qbe::compile_plan(p);
   if (o.exec == QBE_EXEC_FUSED && o.precision != QBE_PREC_FP32) {
     set_error("the fused form computes in FP32 only");
@@ -705,9 +708,10 @@ int qbe_plan_create(qbe_ctx* ctx, const qbe_model* model, const int32_t* reduced
   p.exec = (o.exec == QBE_EXEC_PER_STEP || !p.fused_ok) ? QBE_EXEC_PER_STEP : QBE_EXEC_FUSED;
   if (p.precision != QBE_PREC_FP32 && p.exec == QBE_EXEC_FUSED && o.exec == QBE_EXEC_AUTO)
     p.exec = QBE_EXEC_PER_STEP;
-  if (p.exec == QBE_EXEC_FUSED && p.prefix_ok) {
-    // nothing runs before the fused launch: the per-step part without it
+  if (p.exec == QBE_EXEC_FUSED && !p.segs.empty()) {
+    // the fused form is one launch: the per-step part without segments
     p.want_prefix = 0;
+    p.want_segments = false;
     qbe::compile_plan(p);
   }
   std::string bad = qbe::check_plan(p);
@@ -809,8 +813,11 @@ int qbe_plan_stats(const qbe_plan* plan, qbe_stats* out) {
   for (const auto& sp : p.steps)
     if (sp.n_sum > 1) ++out->n_merged_steps;
   out->step_bytes_per_slice = (uint64_t)p.step_bytes_per_slice;
-  out->n_launches = (int32_t)p.launch_order.size() + (p.prefix_ok ? 1 : 0);
-  out->prefix_buckets = p.prefix_ok ? p.prefix_buckets : 0;
+  out->n_launches = (int32_t)p.launch_order.size();
+  out->prefix_buckets = p.has_prefix ? p.segs[0].buckets : 0;
+  out->n_fused_segments = (int32_t)p.segs.size();
+  out->fused_buckets = 0;
+  for (const qbe::FusedSeg& sg : p.segs) out->fused_buckets += sg.buckets;
   return QBE_OK;
   QBE_GUARD_END
 }
@@ -892,7 +899,7 @@ int qbe_plan_num_launches(const qbe_plan* plan, int32_t* n_out) {
   QBE_GUARD_BEGIN
   QBE_REQUIRE(plan && n_out, "NULL argument");
   const qbe::Plan& p = plan->p;
-  *n_out = p.exec == QBE_EXEC_PER_STEP ? (int32_t)p.launch_order.size() + 2 + (p.prefix_ok ? 1 : 0) : 0;
+  *n_out = p.exec == QBE_EXEC_PER_STEP ? (int32_t)p.launch_order.size() + 2 : 0;
   return QBE_OK;
   QBE_GUARD_END
 }
@@ -902,21 +909,9 @@ int qbe_plan_launch_info(const qbe_plan* plan, int32_t i, qbe_launch_info* out) 
   QBE_REQUIRE(plan && out, "NULL argument");
   const qbe::Plan& p = plan->p;
   QBE_REQUIRE(p.exec == QBE_EXEC_PER_STEP, "launch info is for per-step plans");
-  const int pre = p.prefix_ok ? 1 : 0;
   const int n_order = (int)p.launch_order.size();
-  QBE_REQUIRE(i >= 0 && i < pre + n_order + 2, "launch index out of range");
+  QBE_REQUIRE(i >= 0 && i < n_order + 2, "launch index out of range");
   std::memset(out, 0, sizeof(*out));
-  if (i < pre) {
-    out->kind = QBE_LAUNCH_PREFIX;
-    out->n_buckets = p.prefix_buckets;
-    out->out_rank = p.prefix_max_rank;
-    out->bytes_per_slice = (uint64_t)p.prefix_bytes_per_slice;
-    out->flops_per_slice = (uint64_t)p.prefix_flops_per_slice;
-    out->levels = p.prefix_levels;
-    out->lds_bytes = p.prefix_lds_bytes;
-    return QBE_OK;
-  }
-  i -= pre;
   if (i == n_order) {
     out->kind = QBE_LAUNCH_FINALIZE;
     out->bytes_per_slice = 8 * (p.scalar_arena.size() + p.scalar_inputs_base.size()) + 16;
@@ -928,6 +923,18 @@ int qbe_plan_launch_info(const qbe_plan* plan, int32_t i, qbe_launch_info* out) 
     return QBE_OK;
   }
   const qbe::LaunchItem& li = p.launch_order[i];
+  if (li.seg >= 0) {
+    const qbe::FusedSeg& sg = p.segs[li.seg];
+    out->kind = sg.imports.empty() ? QBE_LAUNCH_PREFIX : QBE_LAUNCH_SEGMENT;
+    out->n_buckets = sg.buckets;
+    out->n_ops = (int32_t)(sg.imports.size() / 4);
+    out->out_rank = p.seg_max_rank;
+    out->bytes_per_slice = (uint64_t)sg.bytes_per_slice;
+    out->flops_per_slice = (uint64_t)sg.flops_per_slice;
+    out->levels = sg.levels;
+    out->lds_bytes = sg.lds_bytes;
+    return QBE_OK;
+  }
   if (li.group >= 0) {
     out->kind = QBE_LAUNCH_GROUP;
     for (int k = p.group_first[li.group]; k < p.group_first[li.group + 1]; ++k) {
@@ -1026,7 +1033,7 @@ int qbe_batch_create(qbe_ctx* ctx, const qbe_plan* const* plans, int32_t n_plans
   std::unique_ptr<qbe_batch> guard(b);
   for (int i = 0; i < n_plans; ++i) {
     QBE_REQUIRE(plans[i] && plans[i]->ctx && plans[i]->p.device == ctx->device, "bad plan in batch");
-    QBE_REQUIRE(!plans[i]->p.prefix_ok, "plans with a fused prefix are contracted alone, not in a batch");
+    QBE_REQUIRE(plans[i]->p.segs.empty(), "plans with fused segments are contracted alone, not in a batch");
     b->b.plans.push_back(&plans[i]->p);
   }
   int rc = qbe::dev_set(ctx->device);

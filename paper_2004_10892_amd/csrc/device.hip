@@ -1312,37 +1312,33 @@ static int run_prep(Plan& p) {
         (const double2*)p.d_raw, (const int32_t*)p.d_fused_map, (float2*)p.d_fused_in, p.fused_elems);
     QBE_HIP(hipGetLastError());
   }
-  if (p.prefix_ok && p.prefix_elems > 0) {
-    prep_kernel<<<grid_for(p.prefix_elems, 256), 256, 0, 0>>>(
-        (const double2*)p.d_raw, (const int32_t*)p.d_prefix_map, (float2*)p.d_prefix_in, p.prefix_elems);
-    QBE_HIP(hipGetLastError());
-  }
+  for (const FusedSeg& sg : p.segs)
+    if (sg.elems > 0) {
+      prep_kernel<<<grid_for(sg.elems, 256), 256, 0, 0>>>((const double2*)p.d_raw, (const int32_t*)sg.d_map,
+                                                            (float2*)sg.d_in, sg.elems);
+      QBE_HIP(hipGetLastError());
+    }
   QBE_HIP(hipDeviceSynchronize());
   return QBE_OK;
 }
 
-constexpr int kPlanBuffers = 12;
-
-static void plan_buffers(Plan& p, void** (&ptrs)[kPlanBuffers]) {
-  void** all[kPlanBuffers] = {&p.d_raw,        &p.d_step_map,  &p.d_step_in,     &p.d_fused_map, &p.d_fused_in,
-                              &p.d_fused_prog, &p.d_scalar_tab, &p.d_state,      &p.d_group,     &p.d_prefix_map,
-                              &p.d_prefix_in,  &p.d_prefix_prog};
-  for (int i = 0; i < kPlanBuffers; ++i) ptrs[i] = all[i];
+// Every device buffer a plan owns.
+static std::vector<void**> plan_buffers(Plan& p) {
+  std::vector<void**> all = {&p.d_raw,        &p.d_step_map,   &p.d_step_in, &p.d_fused_map, &p.d_fused_in,
+                             &p.d_fused_prog, &p.d_scalar_tab, &p.d_state,   &p.d_group};
+  for (FusedSeg& sg : p.segs) all.insert(all.end(), {&sg.d_map, &sg.d_in, &sg.d_prog});
+  return all;
 }
 
 void dev_free_plan(Plan& p) {
-  void** ptrs[kPlanBuffers];
-  plan_buffers(p, ptrs);
-  for (void** q : ptrs) {
+  for (void** q : plan_buffers(p)) {
     if (*q) (void)hipFree(*q);
     *q = nullptr;
   }
 }
 
 void dev_forget_plan(Plan& p) {
-  void** ptrs[kPlanBuffers];
-  plan_buffers(p, ptrs);
-  for (void** q : ptrs) *q = nullptr;
+  for (void** q : plan_buffers(p)) *q = nullptr;
 }
 
 int dmalloc(void** p, size_t bytes) {
@@ -1392,10 +1388,10 @@ int dev_upload_plan(Plan& p) {
     if ((rc = dmalloc(&p.d_fused_in, p.fused_elems * 8))) return rc;
     if ((rc = upload(&p.d_fused_prog, p.fused_prog.data(), p.fused_prog.size() * 4))) return rc;
   }
-  if (p.prefix_ok) {
-    if ((rc = upload(&p.d_prefix_map, p.prefix_map.data(), p.prefix_map.size() * 4))) return rc;
-    if ((rc = dmalloc(&p.d_prefix_in, p.prefix_elems * 8))) return rc;
-    if ((rc = upload(&p.d_prefix_prog, p.prefix_prog.data(), p.prefix_prog.size() * 4))) return rc;
+  for (FusedSeg& sg : p.segs) {
+    if ((rc = upload(&sg.d_map, sg.map.data(), sg.map.size() * 4))) return rc;
+    if ((rc = dmalloc(&sg.d_in, sg.elems * 8))) return rc;
+    if ((rc = upload(&sg.d_prog, sg.prog.data(), sg.prog.size() * 4))) return rc;
   }
   return run_prep(p);
 }
@@ -1834,6 +1830,13 @@ int dev_autotune(Plan& p, void* stream, void* ws, size_t ws_bytes, int64_t min_e
   return rc;
 }
 
+// One launch of the execution order for slices s0 .. s0 + G - 1.
+static int launch_item(const Plan& p, const LaunchItem& li, float2* arena, int64_t G, int64_t s0, hipStream_t st) {
+  if (li.seg >= 0) return seg_launch(p.segs[li.seg], arena, G, s0, st);
+  if (li.group >= 0) return launch_group(p, li.group, arena, G, s0, st);
+  return launch_step(p, p.steps[li.step], arena, G, s0, st);
+}
+
 // Per-slice FP64 product of the rank-0 results of slices s0 .. s0 + G - 1.
 static int finalize_group(const Plan& p, float2* arena, double2* per_slice, int64_t G, int64_t s0,
                           hipStream_t st) {
@@ -1879,13 +1882,8 @@ int dev_contract(const Plan& p, void* stream, void* ws, size_t ws_bytes, int64_t
     float2* arena = (float2*)(w + ws_head(n));
     for (int64_t g0 = 0; g0 < n; g0 += G) {
       const int64_t Gc = std::min<int64_t>(G, n - g0);
-      if (p.prefix_ok) {
-        int rc = prefix_launch(p, arena, Gc, s_begin + g0, st);
-        if (rc) return rc;
-      }
       for (const LaunchItem& li : p.launch_order) {
-        int rc = li.group < 0 ? launch_step(p, p.steps[li.step], arena, Gc, s_begin + g0, st)
-                              : launch_group(p, li.group, arena, Gc, s_begin + g0, st);
+        int rc = launch_item(p, li, arena, Gc, s_begin + g0, st);
         if (rc) return rc;
       }
       int rc = finalize_group(p, arena, per_slice + g0, Gc, s_begin + g0, st);
@@ -1897,15 +1895,14 @@ int dev_contract(const Plan& p, void* stream, void* ws, size_t ws_bytes, int64_t
 
 // Per-launch timing of a per-step plan: the contraction of all slices at
 // once (one slice group), with a HIP event recorded on the stream before the
-// first launch and after every launch of the execution order (the fused
-// prefix first, if the plan has one), then the finalize and reduce launches.
-// ms_out[i] = time between events i and i + 1.
+// first launch and after every launch of the execution order, then the
+// finalize and reduce launches.  ms_out[i] = time between events i and
+// i + 1.
 int dev_profile(const Plan& p, void* stream, void* ws, size_t ws_bytes, float* ms_out, int cap, int* n_out) {
   hipStream_t st = (hipStream_t)stream;
   const int64_t n = p.n_slices;
-  const int pre = p.prefix_ok ? 1 : 0;
   const int n_order = (int)p.launch_order.size();
-  const int items = pre + n_order + 2;
+  const int items = n_order + 2;
   *n_out = items;
   if (p.exec != QBE_EXEC_PER_STEP) {
     set_error("per-launch timing is for per-step plans (a fused plan is one launch)");
@@ -1928,11 +1925,8 @@ int dev_profile(const Plan& p, void* stream, void* ws, size_t ws_bytes, float* m
     if (rc == QBE_OK && hipEventCreate(&e) != hipSuccess) rc = QBE_ERR_HIP;
   if (rc == QBE_OK && hipEventRecord(ev[0], st) != hipSuccess) rc = QBE_ERR_HIP;
   for (int i = 0; i < items && rc == QBE_OK; ++i) {
-    if (i < pre) {
-      rc = prefix_launch(p, arena, n, 0, st);
-    } else if (i < pre + n_order) {
-      const LaunchItem& li = p.launch_order[i - pre];
-      rc = li.group < 0 ? launch_step(p, p.steps[li.step], arena, n, 0, st) : launch_group(p, li.group, arena, n, 0, st);
+    if (i < n_order) {
+      rc = launch_item(p, p.launch_order[i], arena, n, 0, st);
     } else if (i == items - 2) {
       rc = finalize_group(p, arena, per_slice, n, 0, st);
     } else {

@@ -62,9 +62,9 @@ int step_batch_build(Batch& b);
 // reduces per_slice).
 int fused_contract(const Plan& p, hipStream_t st, int64_t s_begin, int64_t n, double2* per_slice,
                    double2* amps, bool* reduced);
-// The fused prefix of a per-step plan for slices s0 .. s0 + G - 1: its
-// exported results go to the slice group's arena.
-int prefix_launch(const Plan& p, float2* arena, int64_t G, int64_t s0, hipStream_t st);
+// A fused segment of a per-step plan for slices s0 .. s0 + G - 1: its
+// imports come from and its exports go to the slice group's arena.
+int seg_launch(const FusedSeg& sg, float2* arena, int64_t G, int64_t s0, hipStream_t st);
 // The fused instances of a batch in one launch (per_item: one value per work
 // item), with their per-plan sums in amps.
 int fused_batch_launch(const Batch& b, hipStream_t st, double2* per_item, double2* amps);

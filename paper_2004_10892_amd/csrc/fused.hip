@@ -14,7 +14,7 @@ namespace qbe {
 // or with every work item (batch mode) so that no device-memory round trip
 // precedes the LDS fill.
 struct FusedMeta {
-  uint32_t lds_tab, levels, scalars, scalar_off, free_vars, inv, dep, dep_src, bytes, exports;
+  uint32_t lds_tab, levels, scalars, scalar_off, free_vars, inv, dep, dep_src, bytes, exports, imports, pad;
   uint32_t lv0[4], lv1[4];  // the first two level-table entries
 };
 
@@ -40,9 +40,10 @@ struct FusedArgs {
   double2* amps;                      // per plan: the slice sum (when reduce_here)
   int32_t reduce_here;                // 1: the last workgroup of a plan sums its items
   uint32_t lds_ctl;                   // LDS byte offset of the workgroup's control words
-  // export mode (one-plan mode with a prefix program): instead of the scalar
-  // product, item g copies each export row's result (LDS element, rank,
-  // arena offset) to arena[offset * G + (g << rank) + i]
+  // segment mode (one-plan mode with a segment program): item g first
+  // copies each import row's result (LDS element, rank, arena offset) from
+  // arena[offset * G + (g << rank) + i] into LDS, and instead of the scalar
+  // product copies each export row's result to its arena place
   float2* arena;
   int64_t G;
 };
@@ -50,7 +51,8 @@ struct FusedArgs {
 static FusedMeta fused_meta(const Plan& p) {
   const std::vector<uint32_t>& w = p.fused_prog;
   FusedMeta m{(uint32_t)fused_table_lds(w[FH_DATA_ELEMS]), w[FH_LEVELS], w[FH_SCALARS], w[FH_SCALAR_OFF],
-              w[FH_FREE], w[FH_INV_ELEMS], w[FH_DEP_ELEMS], w[FH_DEP_SRC], w[FH_BYTE_OFFSETS], w[FH_EXPORTS], {}, {}};
+              w[FH_FREE], w[FH_INV_ELEMS], w[FH_DEP_ELEMS], w[FH_DEP_SRC], w[FH_BYTE_OFFSETS], w[FH_EXPORTS],
+              w[FH_IMPORTS], 0, {}, {}};
   for (int i = 0; i < 4; ++i) {
     m.lv0[i] = w[kHdr + i];
     m.lv1[i] = w[kHdr + 4 + i];
@@ -259,7 +261,7 @@ __device__ __forceinline__ void level_step(gu32p prog, const u32x4& t, const u32
 // reads those of level l + 2; entries after the last level are zero).
 // lv is the LDS copy of the level table; t0, t1 and the first two levels'
 // records were read before the inputs were copied.
-// Export rows of a prefix program and where they go (one-plan mode: the
+// Export rows of a segment program and where they go (one-plan mode: the
 // arena of the launch's slice group, item = the slice's place in it).
 struct ExportCtx {
   const __attribute__((address_space(3))) u32x4* rows;  // LDS copy of the rows
@@ -395,7 +397,7 @@ __global__ __launch_bounds__(kFusedBlock) __attribute__((amdgpu_waves_per_eu(kFu
       prep = wi.prep;
       mt = FusedMeta{uni(wi.meta.lds_tab), uni(wi.meta.levels),  uni(wi.meta.scalars), uni(wi.meta.scalar_off),
                      uni(wi.meta.free_vars), uni(wi.meta.inv), uni(wi.meta.dep),     uni(wi.meta.dep_src),
-                     uni(wi.meta.bytes), 0, {}, {}};  // batch programs export nothing
+                     uni(wi.meta.bytes), 0, 0, 0, {}, {}};  // batch programs export and import nothing
       for (int i = 0; i < 4; ++i) {
         mt.lv0[i] = uni(wi.meta.lv0[i]);
         mt.lv1[i] = uni(wi.meta.lv1[i]);
@@ -428,6 +430,16 @@ __global__ __launch_bounds__(kFusedBlock) __attribute__((amdgpu_waves_per_eu(kFu
                 reinterpret_cast<uint64_t*>(data + kFusedConsts + inv), reinterpret_cast<const uint64_t*>(dsrc), dep,
                 reinterpret_cast<u32x4*>(reinterpret_cast<char*>(lds4) + mt.lds_tab),
                 reinterpret_cast<const u32x4*>(gprog + kHdr), mt.levels + kFusedLevelPad + mt.exports, tid);
+    if (mt.imports) {
+      // results of other launches this segment reads, into their LDS slots
+      const gu32p rows = prog + kHdr + 4 * (mt.levels + kFusedLevelPad + mt.exports);
+      for (uint32_t e = 0; e < mt.imports; ++e) {
+        const uint32_t dst = uni(rows[4 * e]), rank = uni(rows[4 * e + 1]);
+        const uint64_t off = ((uint64_t)uni(rows[4 * e + 3]) << 32) | uni(rows[4 * e + 2]);
+        const float2* src = a.arena + (int64_t)off * a.G + (item << rank);
+        for (uint32_t i = tid; i < (1u << rank); i += kFusedBlock) lds_store(8u * (dst + i), src[i]);
+      }
+    }
     __syncthreads();
     const ExportCtx xc{lv + mt.levels + kFusedLevelPad, a.arena, a.G, item};
     const uint32_t xn = mt.bytes ? run_levels<true>(prog, lv, mt.levels, t0, t1, ra, rb, xc, tid)
@@ -574,23 +586,24 @@ int fused_contract(const Plan& p, hipStream_t st, int64_t s_begin, int64_t n, do
   return launch_fused(fused_grid(p.fused_lds_bytes, n), p.fused_lds_bytes, st, a);
 }
 
-int prefix_launch(const Plan& p, float2* arena, int64_t G, int64_t s0, hipStream_t st) {
-  const std::vector<uint32_t>& w = p.prefix_prog;
+int seg_launch(const FusedSeg& sg, float2* arena, int64_t G, int64_t s0, hipStream_t st) {
+  const std::vector<uint32_t>& w = sg.prog;
   FusedArgs a{};
-  a.prog0 = (const uint32_t*)p.d_prefix_prog;
-  a.prep0 = (const float2*)p.d_prefix_in;
+  a.prog0 = (const uint32_t*)sg.d_prog;
+  a.prep0 = (const float2*)sg.d_in;
   a.meta0 = FusedMeta{(uint32_t)fused_table_lds(w[FH_DATA_ELEMS]), w[FH_LEVELS], 0, w[FH_SCALAR_OFF], 0,
-                      w[FH_INV_ELEMS], w[FH_DEP_ELEMS], w[FH_DEP_SRC], w[FH_BYTE_OFFSETS], w[FH_EXPORTS], {}, {}};
+                      w[FH_INV_ELEMS], w[FH_DEP_ELEMS], w[FH_DEP_SRC], w[FH_BYTE_OFFSETS], w[FH_EXPORTS],
+                      w[FH_IMPORTS], 0, {}, {}};
   for (int i = 0; i < 4; ++i) {
     a.meta0.lv0[i] = w[kHdr + i];
     a.meta0.lv1[i] = w[kHdr + 4 + i];
   }
   a.s_begin = s0;
   a.n_items = G;
-  a.state = (uint32_t*)p.d_state;
+  a.state = nullptr;  // one-plan mode without the in-kernel sum uses no state
   a.arena = arena;
   a.G = G;
-  return launch_fused(fused_grid(p.prefix_lds_bytes, G), p.prefix_lds_bytes, st, a);
+  return launch_fused(fused_grid(sg.lds_bytes, G), sg.lds_bytes, st, a);
 }
 
 // ------------------------------------------------------------------ batch --

@@ -42,10 +42,13 @@ constexpr int64_t kInKernelReduceMax = 8192;
 //                               rows of a term record, T = 2^lgT terms per
 //                               entry, X = export rows copied as the level
 //                               starts (the results of earlier levels)
-//   exports[4 * n_exports]      a prefix program's results for the per-step
+//   exports[4 * n_exports]      a segment program's results for other
 //                               launches: (LDS element, rank, arena offset
 //                               lo, hi) in the order levels copy them; rows
 //                               left after the last level are copied then
+//   imports[4 * n_imports]      results of other launches a segment program
+//                               reads: (LDS element, rank, arena offset lo,
+//                               hi), copied in with the inputs
 //   records                     level by level, E entries of T term records
 //                               of R 16-byte rows (8R halfwords) each:
 //                                 slot 0: LDS offset of the result (term 0),
@@ -95,7 +98,8 @@ enum FusedHdr {
   FH_DEP_SRC,         // element offset of slice 0's block in the prepared buffer
   FH_N_SLICES,        // 2^m (saturated)
   FH_BYTE_OFFSETS,    // 1: record offsets are LDS bytes, 0: complex64 elements
-  FH_EXPORTS,         // export rows (prefix programs; 0 otherwise)
+  FH_EXPORTS,         // export rows (segment programs; 0 otherwise)
+  FH_IMPORTS,         // import rows (segment programs; 0 otherwise)
   kHdr = 16
 };
 

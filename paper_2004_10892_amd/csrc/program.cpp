@@ -125,7 +125,7 @@ std::vector<FusedNode> merge_buckets(const Schedule& s, bool merge, const std::v
   std::vector<char> alive(incl);
   for (int k = 0; k < n; ++k) {
     for (const auto& op : s.steps[k].ops)
-      if (op.kind == 'r') kids[k].push_back(op.id);
+      if (op.kind == 'r' && incl[op.id]) kids[k].push_back(op.id);  // others: imported results
     members[k] = {k};
     F[k] = (int)s.steps[k].ops.size();
     E[k] = int64_t(1) << s.steps[k].out.size();
@@ -219,6 +219,9 @@ constexpr int kChainMinRank = 12;
 // total is small; see compile_plan).
 constexpr int kOwnSpaceRank = 8;
 constexpr int kChainSumMax = 4;
+// A later fused segment takes a run of at least this many buckets: a
+// shorter run saves fewer launches than its levels cost.
+constexpr int kSegMinBuckets = 3;
 
 struct StepNode {
   std::vector<int> members;      // absorbed buckets in elimination order, root last
@@ -232,11 +235,12 @@ std::vector<StepNode> merge_chains(const Schedule& s, bool merge, const std::vec
   for (int k = 0; k < n; ++k) {
     nd[k].members = {k};
     nd[k].factors = s.steps[k].ops;
-    if (skip[k]) alive[k] = 0;  // runs in the fused prefix
+    if (skip[k]) alive[k] = 0;  // runs in a fused segment
   }
   for (int k = 0; k < n && merge; ++k) {
     const int c = s.consumer[k];
-    if (c < 0 || !alive[k]) continue;
+    // a consumer in a fused segment reads k's result from the arena
+    if (c < 0 || !alive[k] || skip[c]) continue;
     const int rk = (int)s.steps[k].out.size(), rc = (int)s.steps[c].out.size();
     if (rk < kChainMinRank || rk < rc) continue;
     if ((int)(nd[k].members.size() + nd[c].members.size()) > kChainSumMax) continue;
@@ -307,38 +311,74 @@ void build_launch_order(Plan& p) {
     }
     return;
   }
+  // units in schedule order: each fused segment before the step at its
+  // position, then that step; unit u >= 0 is step u, u < 0 segment -1 - u
+  std::vector<int> units;
+  for (int k = 0; k <= n; ++k) {
+    for (size_t j = 0; j < p.segs.size(); ++j)
+      if (p.segs[j].pos == k) units.push_back(-1 - (int)j);
+    if (k < n) units.push_back(k);
+  }
   struct Span {
     int64_t b, e;
   };
   auto rank_of = [](const StepProg& sp) { return sp.out_rank >= 0 ? sp.out_rank : -sp.out_rank; };
-  std::vector<Span> wr(n);
-  std::vector<std::vector<Span>> rd(n);
-  for (int k = 0; k < n; ++k) {
-    const StepProg& sp = p.steps[k];
-    wr[k] = Span{sp.out_base, sp.out_base + (int64_t(1) << rank_of(sp))};
+  auto row_spans = [](const std::vector<uint32_t>& rows) {
+    std::vector<Span> v;
+    for (size_t i = 0; i < rows.size(); i += 4) {
+      const int64_t off = (int64_t)(((uint64_t)rows[i + 3] << 32) | rows[i + 2]);
+      v.push_back(Span{off, off + (int64_t(1) << rows[i + 1])});
+    }
+    return v;
+  };
+  const int nu = (int)units.size();
+  std::vector<std::vector<Span>> wr(nu), rd(nu);
+  for (int u = 0; u < nu; ++u) {
+    if (units[u] < 0) {
+      const FusedSeg& sg = p.segs[-1 - units[u]];
+      wr[u] = row_spans(sg.exports);
+      rd[u] = row_spans(sg.imports);
+      continue;
+    }
+    const StepProg& sp = p.steps[units[u]];
+    wr[u].push_back(Span{sp.out_base, sp.out_base + (int64_t(1) << rank_of(sp))});
     for (int i = 0; i < sp.n_ops; ++i)
-      if (!sp.ops[i].is_input) rd[k].push_back(Span{sp.ops[i].base, sp.ops[i].base + (int64_t(1) << sp.ops[i].rank)});
+      if (!sp.ops[i].is_input) rd[u].push_back(Span{sp.ops[i].base, sp.ops[i].base + (int64_t(1) << sp.ops[i].rank)});
   }
   auto meet = [](const Span& a, const Span& b) { return a.b < b.e && b.b < a.e; };
-  std::vector<int> level(n, 0);
+  auto meets = [&](const std::vector<Span>& x, const std::vector<Span>& y) {
+    for (const Span& a : x)
+      for (const Span& b : y)
+        if (meet(a, b)) return true;
+    return false;
+  };
+  // level of a unit: one above every earlier unit it has a memory hazard
+  // with (it reads what that one writes, writes what it reads or writes)
+  std::vector<int> level(nu, 0);
   int n_lv = 0;
-  for (int k = 0; k < n; ++k) {
+  for (int u = 0; u < nu; ++u) {
     int l = 0;
-    for (int j = 0; j < k; ++j) {
-      bool dep = meet(wr[j], wr[k]);
-      for (const Span& r : rd[k]) dep = dep || meet(wr[j], r);
-      for (const Span& r : rd[j]) dep = dep || meet(r, wr[k]);
-      if (dep) l = std::max(l, level[j] + 1);
-    }
-    level[k] = l;
+    for (int v = 0; v < u; ++v)
+      if (meets(wr[v], wr[u]) || meets(wr[v], rd[u]) || meets(rd[v], wr[u])) l = std::max(l, level[v] + 1);
+    level[u] = l;
     n_lv = std::max(n_lv, l + 1);
   }
-  p.step_level = level;
+  for (int u = 0; u < nu; ++u) {
+    if (units[u] >= 0)
+      p.step_level[units[u]] = level[u];
+    else
+      p.segs[-1 - units[u]].level = level[u];
+  }
   auto small = [&](const StepProg& sp) { return groupable(sp) && rank_of(sp) <= kGroupMaxRank; };
   for (int l = 0; l < n_lv; ++l) {
     std::vector<int> grp;
-    for (int k = 0; k < n; ++k) {
-      if (level[k] != l) continue;
+    for (int u = 0; u < nu; ++u) {
+      if (level[u] != l) continue;
+      if (units[u] < 0) {
+        p.launch_order.push_back(LaunchItem{-1, -1, -1 - units[u]});
+        continue;
+      }
+      const int k = units[u];
       if (small(p.steps[k]))
         grp.push_back(k);
       else
@@ -362,19 +402,21 @@ void build_launch_order(Plan& p) {
 
 }  // namespace
 
-// A fused program (the executor of fused.hip) for the buckets in `incl`
-// (every producer of an included bucket included).  Without exports it is
-// the whole schedule: the program ends with the slice's scalar factors.
-// With exports (per-step arena offsets per bucket, -1 if none) it is a
-// prefix of a per-step plan: the listed buckets' results are copied from LDS
-// to the per-step arena after the last level, and no scalar list follows.
+// A fused program (the executor of fused.hip) for the buckets in `incl`.
+// Without exports it is the whole schedule: the program ends with the
+// slice's scalar factors.  With exports (marks per bucket, >= 0 for the
+// results other launches read) it is a segment of a per-step plan: the
+// marked results are copied from LDS to the per-step arena, the results of
+// excluded buckets that included ones read are imported from it, and no
+// scalar list follows (arena offsets of both rows are set by the caller).
 struct FusedCode {
   bool ok = false;
   std::vector<uint32_t> prog;
   std::vector<int32_t> map;
   int lds_bytes = 0, levels = 0;
-  size_t export_at = 0;           // word of the first export row in prog
-  std::vector<int> export_steps;  // the bucket of each export row
+  size_t export_at = 0, import_at = 0;  // words of the first export and import rows
+  std::vector<int> export_steps;        // the bucket of each export row
+  std::vector<int> import_steps;        // the (excluded) bucket of each import row
 };
 
 static FusedCode build_fused(const Plan& p, const std::vector<InputInfo>& in, const std::vector<int>& muj,
@@ -416,7 +458,7 @@ static FusedCode build_fused(const Plan& p, const std::vector<InputInfo>& in, co
   for (const FusedNode& nd : nodes) f_levels = std::max(f_levels, nd.level + 1);
   std::vector<std::vector<int>> by_level(f_levels);
   for (int i = 0; i < (int)nodes.size(); ++i) by_level[nodes[i].level].push_back(i);
-  // exports (prefix programs): results no included bucket reads, in the
+  // exports (segment programs): results no included bucket reads, in the
   // order of their nodes' levels; those of level l are copied out as level
   // l + 1 starts (the last level's after it)
   std::vector<int> exp_steps;
@@ -430,11 +472,22 @@ static FusedCode build_fused(const Plan& p, const std::vector<InputInfo>& in, co
           exp_level.push_back(l);
         }
       }
-  // results by levels: all results of a level are live while the level
-  // runs; then its nodes' operands (results and inputs) are free; an
-  // exported result stays live through the next level, during which it is
-  // copied out
+  // imports (segment programs): results of excluded buckets that included
+  // ones read, copied in with the inputs, after them
   std::vector<int64_t> lds_out(nsteps, -1);
+  std::vector<int> imp_steps;
+  if (export_off)
+    for (int k = 0; k < nsteps; ++k)
+      if (incl[k])
+        for (const auto& op : s.steps[k].ops)
+          if (op.kind == 'r' && !incl[op.id]) {
+            imp_steps.push_back(op.id);
+            lds_out[op.id] = kFusedConsts + la.alloc(int64_t(1) << op.vars.size(), 1);
+          }
+  // results by levels: all results of a level are live while the level
+  // runs; then its nodes' operands (results, inputs and imports) are free;
+  // an exported result stays live through the next level, during which it
+  // is copied out
   std::vector<int> copying;  // exported results of the previous level
   for (int l = 0; l < f_levels; ++l) {
     for (int i : by_level[l]) {
@@ -443,8 +496,10 @@ static FusedCode build_fused(const Plan& p, const std::vector<InputInfo>& in, co
     }
     for (int i : by_level[l]) {
       for (int kid : nodes[i].kids) la.release(lds_out[kid] - kFusedConsts, int64_t(1) << s.steps[kid].out.size());
-      for (const Operand& op : nodes[i].factors)
+      for (const Operand& op : nodes[i].factors) {
         if (op.kind == 't') la.release(lds_in[op.id] - kFusedConsts, int64_t(1) << in[op.id].canon.size());
+        if (op.kind == 'r' && !incl[op.id]) la.release(lds_out[op.id] - kFusedConsts, int64_t(1) << op.vars.size());
+      }
     }
     for (int c : copying) la.release(lds_out[c] - kFusedConsts, int64_t(1) << s.steps[c].out.size());
     copying.clear();
@@ -486,6 +541,11 @@ static FusedCode build_fused(const Plan& p, const std::vector<InputInfo>& in, co
     prog.insert(prog.end(), {0u, (uint32_t)s.steps[c].out.size(), 0u, 0u});
   }
   out.export_steps = exp_steps;
+  // import rows (read from device memory before the first level)
+  out.import_at = prog.size();
+  for (int c : imp_steps)
+    prog.insert(prog.end(), {(uint32_t)lds_out[c], (uint32_t)s.steps[c].out.size(), 0u, 0u});
+  out.import_steps = imp_steps;
   // 16-bit operand offsets: bytes when the data fit 64 KB, else elements
   const bool bytes = data_elems * 8 <= 65536;
   const uint32_t unit = bytes ? 8u : 1u;
@@ -573,6 +633,7 @@ static FusedCode build_fused(const Plan& p, const std::vector<InputInfo>& in, co
   prog[FH_DEP_SRC] = (uint32_t)inv;
   prog[FH_N_SLICES] = (uint32_t)std::min<int64_t>(p.n_slices, UINT32_MAX);
   prog[FH_EXPORTS] = (uint32_t)n_exp;
+  prog[FH_IMPORTS] = (uint32_t)imp_steps.size();
   out.ok = true;
   out.lds_bytes = (int)lds_bytes;
   out.levels = (int)n_table;
@@ -661,28 +722,26 @@ void compile_plan(Plan& p) {
   }
   p.step_elems = (int64_t)p.step_map.size();
 
-  // ---------------- fused prefix (per-step plans that ask for it): the
-  // subtrees of small buckets -- every bucket whose union has at most
-  // R + 1 variables and whose producers all do -- run as one LDS-resident
-  // launch (fused.hip) before the per-step launches; the results that larger
-  // buckets read (and rank-0 results) are exported to the arena.  R is the
-  // one asked for, or else the largest of 14 .. 4 whose prefix lets two
-  // workgroups share a compute unit (a slice's levels are latency-bound:
-  // two slices per compute unit halve the rounds), else the largest of 10,
-  // 8, 6, 4 that fits LDS at all.
+  // ---------------- fused segments (per-step plans that ask for them).
+  // The prefix: the subtrees of small buckets -- every bucket whose union
+  // has at most R + 1 variables and whose producers all do -- in one
+  // LDS-resident launch (fused.hip) before the others; the results that
+  // larger buckets read (and rank-0 results) are exported to the arena.  R
+  // is the one asked for, or else the largest of 14 .. 4 whose prefix lets
+  // two workgroups share a compute unit (a slice's levels are
+  // latency-bound: two slices per compute unit halve the rounds), else the
+  // largest of 10, 8, 6, 4 that fits LDS at all.  Later segments (if asked
+  // for): each connected run of at least kSegMinBuckets other small buckets
+  // (connected along the consumer edges, so a run has one top bucket, whose
+  // result is its export) in one launch that imports the results of other
+  // launches it reads.
   const int nsteps = (int)s.steps.size();
-  std::vector<char> in_prefix(nsteps, 0);
-  std::vector<int64_t> export_mark(nsteps, -1);
-  FusedCode prefix;
-  p.prefix_ok = false;
-  p.prefix_prog.clear();
-  p.prefix_map.clear();
-  p.prefix_exports.clear();
-  p.prefix_elems = 0;
-  p.prefix_lds_bytes = p.prefix_levels = p.prefix_buckets = 0;
-  p.prefix_max_rank = -1;
-  p.prefix_bytes_per_slice = 0;
-  p.prefix_flops_per_slice = 0;
+  std::vector<char> fused_any(nsteps, 0);  // bucket runs in a segment
+  std::vector<FusedCode> seg_code;
+  std::vector<std::vector<char>> seg_incl;
+  p.segs.clear();
+  p.has_prefix = false;
+  p.seg_max_rank = -1;
   if (p.want_prefix > 0 && p.merge && p.m <= 24) {
     std::vector<std::pair<int, int64_t>> tries;  // (R, LDS cap)
     if (p.want_prefix == 1) {
@@ -707,28 +766,84 @@ void compile_plan(Plan& p) {
         if (f[k] && (s.consumer[k] < 0 || !f[s.consumer[k]])) mark[k] = 0;
       FusedCode fc = build_fused(p, in, muj, f, &mark, cap);
       if (!fc.ok) continue;
-      in_prefix = f;
-      export_mark = mark;
-      prefix = std::move(fc);
-      p.prefix_max_rank = R;
-      p.prefix_buckets = cnt;
+      seg_code.push_back(std::move(fc));
+      seg_incl.push_back(f);
+      for (int k = 0; k < nsteps; ++k) fused_any[k] |= f[k];
+      p.has_prefix = true;
+      p.seg_max_rank = R;
       break;
     }
   }
+  if (p.want_segments && p.has_prefix) {
+    const int R = p.seg_max_rank;
+    std::vector<char> small(nsteps, 0);
+    for (int k = 0; k < nsteps; ++k) small[k] = !fused_any[k] && (int)s.steps[k].uni.size() <= R + 1;
+    // the top of each bucket's run (consumers come after their producers)
+    std::vector<int> top(nsteps, -1);
+    for (int k = nsteps - 1; k >= 0; --k)
+      if (small[k]) {
+        const int c = s.consumer[k];
+        top[k] = (c >= 0 && small[c]) ? top[c] : k;
+      }
+    std::vector<int> size(nsteps, 0);
+    for (int k = 0; k < nsteps; ++k)
+      if (small[k]) ++size[top[k]];
+    for (int t = 0; t < nsteps; ++t) {
+      if (!small[t] || top[t] != t || size[t] < kSegMinBuckets) continue;
+      std::vector<char> f(nsteps, 0);
+      for (int k = 0; k < nsteps; ++k) f[k] = small[k] && top[k] == t;
+      std::vector<int64_t> mark(nsteps, -1);
+      mark[t] = 0;
+      FusedCode fc = build_fused(p, in, muj, f, &mark, kFusedLdsMax);
+      if (!fc.ok) continue;  // its buckets stay per-step launches
+      seg_code.push_back(std::move(fc));
+      seg_incl.push_back(f);
+      for (int k = 0; k < nsteps; ++k) fused_any[k] |= f[k];
+    }
+  }
+  // each segment's position in schedule order: its last bucket
+  std::vector<int> seg_last(seg_code.size(), -1);
+  for (size_t j = 0; j < seg_code.size(); ++j)
+    for (int k = 0; k < nsteps; ++k)
+      if (seg_incl[j][k]) seg_last[j] = k;
 
   // ---------------- per-step launches and arena
   std::vector<int64_t> out_off(nsteps, -1);
+  std::vector<char> placed(nsteps, 0);  // out_off is set (-1 also encodes own-space offset 0)
   Arena arena;
   int64_t own = 0;  // elements of the small results' own space
   p.steps.clear();
   p.scalar_arena.clear();
+  // small results get space of their own after the arena (encoded as
+  // -(offset + 1) until the arena's size is known): reusing freed space
+  // would order otherwise independent launches behind one another
+  auto place_result = [&](int k) {
+    const int64_t osz = int64_t(1) << s.steps[k].out.size();
+    if ((int)s.steps[k].out.size() <= kOwnSpaceRank) {
+      own = (own + align_for(osz) - 1) / align_for(osz) * align_for(osz);
+      out_off[k] = -(own + 1);
+      own += osz;
+    } else {
+      out_off[k] = arena.alloc(osz, align_for(osz));
+    }
+    placed[k] = 1;
+  };
+  std::vector<int32_t> seg_pos(seg_code.size(), 0);
   // results the prefix exports: placed first, freed by their consumers
-  for (int k = 0; k < nsteps; ++k)
-    if (export_mark[k] >= 0) {
+  if (p.has_prefix)
+    for (int k : seg_code[0].export_steps) {
       const int64_t osz = int64_t(1) << s.steps[k].out.size();
       out_off[k] = arena.alloc(osz, align_for(osz));
+      placed[k] = 1;
       if (s.steps[k].out.empty()) p.scalar_arena.push_back(out_off[k]);
     }
+  // later segments: at their top bucket's place in schedule order, their
+  // export placed like a launch's result, their imports then freed
+  const std::vector<StepNode> step_nodes = merge_chains(s, p.merge, fused_any);
+  std::vector<std::pair<int, int>> items;  // (schedule position, node index or -1 - segment)
+  for (size_t i = 0; i < step_nodes.size(); ++i) items.push_back({step_nodes[i].members.back(), (int)i});
+  for (size_t j = p.has_prefix ? 1 : 0; j < seg_code.size(); ++j) items.push_back({seg_last[j], -1 - (int)j});
+  std::sort(items.begin(), items.end());
   auto input_op = [&](int t, const std::vector<int>& uni) {
     StepOp o{};
     o.base = step_base[t];
@@ -738,7 +853,19 @@ void compile_plan(Plan& p) {
     o.smask = in[t].smask;
     return o;
   };
-  for (const StepNode& node : merge_chains(s, p.merge, in_prefix)) {
+  for (const auto& item : items) {
+    if (item.second < 0) {
+      const int j = -1 - item.second;
+      seg_pos[j] = (int32_t)p.steps.size();
+      for (int k : seg_code[j].export_steps) {
+        place_result(k);
+        if (s.steps[k].out.empty()) p.scalar_arena.push_back(out_off[k]);
+      }
+      for (int k : seg_code[j].import_steps)
+        if (out_off[k] >= 0) arena.release(out_off[k], int64_t(1) << s.steps[k].out.size());
+      continue;
+    }
+    const StepNode& node = step_nodes[item.second];
     const int k = node.members.back();  // the root: its result is the launch's
     const Step& st = s.steps[k];
     const int n_sum = (int)node.members.size();
@@ -867,17 +994,7 @@ void compile_plan(Plan& p) {
         }
       }
     }
-    const int64_t osz = int64_t(1) << rb;
-    if (rb <= kOwnSpaceRank) {
-      // small results get space of their own after the arena (encoded as
-      // -(offset + 1) until the arena's size is known): reusing freed space
-      // would order otherwise independent launches behind one another
-      own = (own + align_for(osz) - 1) / align_for(osz) * align_for(osz);
-      out_off[k] = -(own + 1);
-      own += osz;
-    } else {
-      out_off[k] = arena.alloc(osz, align_for(osz));
-    }
+    place_result(k);
     sp.out_base = out_off[k];
     sp.n_ops = (int)ops.size();
     for (size_t i = 0; i < ops.size(); ++i) sp.ops[i] = ops[i];
@@ -899,33 +1016,46 @@ void compile_plan(Plan& p) {
   }
   for (int64_t& off : p.scalar_arena) place(off);
   p.arena_per_slice = std::max<int64_t>(own > 0 ? own_base + own : arena.top, 1);
-  if (!prefix.prog.empty()) {
-    for (size_t i = 0; i < prefix.export_steps.size(); ++i) {
-      const uint64_t a = (uint64_t)out_off[prefix.export_steps[i]];
-      prefix.prog[prefix.export_at + 4 * i + 2] = (uint32_t)a;
-      prefix.prog[prefix.export_at + 4 * i + 3] = (uint32_t)(a >> 32);
-    }
-    p.prefix_ok = true;
-    p.prefix_exports.assign(prefix.prog.begin() + prefix.export_at,
-                            prefix.prog.begin() + prefix.export_at + 4 * prefix.export_steps.size());
-    p.prefix_prog = std::move(prefix.prog);
-    p.prefix_map = std::move(prefix.map);
-    p.prefix_elems = (int64_t)p.prefix_map.size();
-    p.prefix_lds_bytes = prefix.lds_bytes;
-    p.prefix_levels = prefix.levels;
-    // algorithmic traffic of the launch per slice: its inputs read once,
-    // its exported results written once; products and sums of its buckets
-    int64_t e = (int64_t)p.prefix_prog[FH_INV_ELEMS] + (int64_t)p.prefix_prog[FH_DEP_ELEMS];
-    for (size_t i = 0; i < p.prefix_exports.size(); i += 4) e += int64_t(1) << p.prefix_exports[i + 1];
-    p.prefix_bytes_per_slice = 8 * e;
-    for (int k = 0; k < nsteps; ++k)
-      if (in_prefix[k]) {
-        const int64_t kk = (int64_t)s.steps[k].ops.size();
-        p.prefix_flops_per_slice += 6 * std::max<int64_t>(kk - 1, 0) * (int64_t(1) << s.steps[k].uni.size()) +
-                                    2 * (int64_t(1) << s.steps[k].out.size());
+  // the segments, with the arena offsets of their rows
+  for (size_t j = 0; j < seg_code.size(); ++j) {
+    FusedCode& fc = seg_code[j];
+    auto set_rows = [&](size_t at, const std::vector<int>& ks) {
+      for (size_t i = 0; i < ks.size(); ++i) {
+        if (!placed[ks[i]]) throw std::logic_error("fused segment row for a result with no arena place");
+        int64_t off = out_off[ks[i]];
+        place(off);
+        fc.prog[at + 4 * i + 2] = (uint32_t)(uint64_t)off;
+        fc.prog[at + 4 * i + 3] = (uint32_t)((uint64_t)off >> 32);
       }
+    };
+    set_rows(fc.export_at, fc.export_steps);
+    set_rows(fc.import_at, fc.import_steps);
+    FusedSeg sg;
+    sg.exports.assign(fc.prog.begin() + fc.export_at, fc.prog.begin() + fc.export_at + 4 * fc.export_steps.size());
+    sg.imports.assign(fc.prog.begin() + fc.import_at, fc.prog.begin() + fc.import_at + 4 * fc.import_steps.size());
+    sg.prog = std::move(fc.prog);
+    sg.map = std::move(fc.map);
+    sg.elems = (int64_t)sg.map.size();
+    sg.lds_bytes = fc.lds_bytes;
+    sg.levels = fc.levels;
+    sg.pos = seg_pos[j];
+    // algorithmic traffic of the launch per slice: its inputs and imports
+    // read once, its exports written once; products and sums of its buckets
+    int64_t e = (int64_t)sg.prog[FH_INV_ELEMS] + (int64_t)sg.prog[FH_DEP_ELEMS];
+    for (size_t i = 0; i < sg.exports.size(); i += 4) e += int64_t(1) << sg.exports[i + 1];
+    for (size_t i = 0; i < sg.imports.size(); i += 4) e += int64_t(1) << sg.imports[i + 1];
+    sg.bytes_per_slice = 8 * e;
+    for (int k = 0; k < nsteps; ++k)
+      if (seg_incl[j][k]) {
+        const int64_t kk = (int64_t)s.steps[k].ops.size();
+        sg.flops_per_slice += 6 * std::max<int64_t>(kk - 1, 0) * (int64_t(1) << s.steps[k].uni.size()) +
+                              2 * (int64_t(1) << s.steps[k].out.size());
+        ++sg.buckets;
+      }
+    p.segs.push_back(std::move(sg));
   }
-  p.step_bytes_per_slice = p.prefix_bytes_per_slice;
+  p.step_bytes_per_slice = 0;
+  for (const FusedSeg& sg : p.segs) p.step_bytes_per_slice += sg.bytes_per_slice;
   for (const StepProg& sp : p.steps) {
     int64_t b = int64_t(1) << (sp.out_rank >= 0 ? sp.out_rank : -sp.out_rank);
     for (int i = 0; i < sp.n_ops; ++i) b += int64_t(1) << sp.ops[i].rank;

@@ -23,15 +23,18 @@ static std::string check_fused_program(const std::vector<uint32_t>& w, int64_t l
                                        int64_t n_slices) {
   if (w.size() < (size_t)kHdr || w[FH_WORDS] != w.size() || w.size() % 4) return "fused header";
   const uint32_t nl = w[FH_LEVELS], nsc = w[FH_SCALARS], so = w[FH_SCALAR_OFF];
-  const uint32_t inv = w[FH_INV_ELEMS], dep = w[FH_DEP_ELEMS], data = w[FH_DATA_ELEMS], nx = w[FH_EXPORTS];
+  const uint32_t inv = w[FH_INV_ELEMS], dep = w[FH_DEP_ELEMS], data = w[FH_DATA_ELEMS], nx = w[FH_EXPORTS],
+                 ni = w[FH_IMPORTS];
   if (lds_bytes != std::max<int64_t>(fused_table_lds(data) + 16 * ((int64_t)nl + kFusedLevelPad + nx), 256 * 16))
     return "fused LDS size";
   if (nx > 0 && nsc > 0) return "fused program with both exports and scalars";
+  if (ni > 0 && nx == 0) return "fused program with imports but no exports";
   if (lds_bytes > kFusedLdsMax) return "fused LDS above budget";
   if (w[FH_DEP_SRC] != inv) return "fused dependent block offset";
   if ((int64_t)inv + (int64_t)dep * n_slices != elems) return "fused prepared size";
   if (kFusedConsts + inv + dep > data) return "fused inputs above data size";
-  if ((int64_t)kHdr + 4 * ((int64_t)nl + kFusedLevelPad + nx) > (int64_t)w.size()) return "fused level table truncated";
+  if ((int64_t)kHdr + 4 * ((int64_t)nl + kFusedLevelPad + nx + ni) > (int64_t)w.size())
+    return "fused level table truncated";
   if ((int64_t)so + nsc > (int64_t)w.size()) return "fused scalar list truncated";
   const uint32_t* lv = w.data() + kHdr;
   for (uint32_t j = 4 * nl; j < 4 * (nl + kFusedLevelPad); ++j)
@@ -41,13 +44,16 @@ static std::string check_fused_program(const std::vector<uint32_t>& w, int64_t l
   // end); the arena side is checked by the plan
   const uint32_t* xr = lv + 4 * ((int64_t)nl + kFusedLevelPad);
   if ((kHdr + 4 * ((int64_t)nl + kFusedLevelPad)) % 4) return "fused export rows unaligned";
-  for (uint32_t e = 0; e < nx; ++e) {
+  // import rows after them: LDS slots the executor fills before the first
+  // level, outside the input block it copies
+  for (uint32_t e = 0; e < nx + ni; ++e) {
     const uint32_t src = xr[4 * e], rank = xr[4 * e + 1];
     if (rank > 15 || src < kFusedConsts || (int64_t)src + (int64_t(1) << rank) > data)
-      return "fused export row outside its LDS results";
+      return "fused export or import row outside its LDS data";
+    if (e >= nx && src < kFusedConsts + inv + dep) return "fused import slot inside the input block";
   }
   int64_t x_copied = 0;
-  int64_t expect_base = kHdr + 4 * ((int64_t)nl + kFusedLevelPad + nx);
+  int64_t expect_base = kHdr + 4 * ((int64_t)nl + kFusedLevelPad + nx + ni);
   const bool bytes = w[FH_BYTE_OFFSETS] != 0;
   if (w[FH_BYTE_OFFSETS] > 1 || bytes != ((int64_t)data * 8 <= 65536)) return "fused offset unit";
   const uint32_t unit = bytes ? 8u : 1u;
@@ -174,6 +180,7 @@ std::string check_plan(const Plan& p) {
     if (p.group_prefix.size() != p.group_steps.size() + (size_t)n_groups) return "group prefix size";
     if (p.group_sb < 1 || p.group_sb > 256 || (p.group_sb & (p.group_sb - 1))) return "group slice block";
     for (const LaunchItem& li : p.launch_order) {
+      if (li.seg >= 0) continue;  // checked with the segments below
       if (li.group < 0) {
         if (li.step < 0 || li.step >= (int)p.steps.size()) return "launch step index";
         ++seen[li.step];
@@ -219,30 +226,43 @@ std::string check_plan(const Plan& p) {
     const std::string bad = check_fused_program(p.fused_prog, p.fused_lds_bytes, p.fused_elems, p.n_slices);
     if (!bad.empty()) return bad;
   }
-  // fused prefix: a program with no scalar list whose exports land in the
-  // arena; no per-step launch contracts its buckets (the execution order
-  // check above covers the per-step steps only)
-  if (p.prefix_ok) {
-    for (size_t i = 0; i < p.prefix_map.size(); ++i)
-      if (p.prefix_map[i] < 0 || p.prefix_map[i] >= raw_elems)
-        return fail("prefix map entry out of range", p.prefix_map[i], raw_elems);
-    const auto& w = p.prefix_prog;
-    const std::string bad = check_fused_program(w, p.prefix_lds_bytes, p.prefix_elems, p.n_slices);
-    if (!bad.empty()) return "prefix: " + bad;
-    if (w[FH_SCALARS] != 0) return "prefix with a scalar list";
-    if (p.prefix_exports.empty() || p.prefix_exports.size() != 4 * (size_t)w[FH_EXPORTS]) return "prefix export list";
-    if (!std::equal(p.prefix_exports.begin(), p.prefix_exports.end(),
-                    w.begin() + kHdr + 4 * ((int64_t)w[FH_LEVELS] + kFusedLevelPad)))
-      return "prefix export list differs from the program's rows";
-    const int64_t lo = kFusedConsts, hi = w[FH_DATA_ELEMS];
-    for (size_t i = 0; i < p.prefix_exports.size(); i += 4) {
-      const int64_t src = p.prefix_exports[i], rank = p.prefix_exports[i + 1];
-      const int64_t off = (int64_t)(((uint64_t)p.prefix_exports[i + 3] << 32) | p.prefix_exports[i + 2]);
-      if (rank > p.prefix_max_rank) return "prefix export above its rank bound";
-      if (src < lo || src + (int64_t(1) << rank) > hi) return "prefix export outside its LDS results";
-      if (off < 0 || off + (int64_t(1) << rank) > p.arena_per_slice)
-        return fail("prefix export outside the arena", off + (int64_t(1) << rank), p.arena_per_slice);
+  // fused segments: programs with no scalar list whose import and export
+  // rows (copies kept in the segment) lie in the arena; the prefix imports
+  // nothing; every segment is launched exactly once
+  std::vector<int> seg_seen(p.segs.size(), 0);
+  for (const LaunchItem& li : p.launch_order)
+    if (li.seg >= 0) {
+      if (li.seg >= (int)p.segs.size() || li.step != -1 || li.group != -1) return "launch segment index";
+      ++seg_seen[li.seg];
     }
+  for (size_t j = 0; j < p.segs.size(); ++j) {
+    const FusedSeg& sg = p.segs[j];
+    if (seg_seen[j] != 1) return "execution order misses or repeats a fused segment";
+    for (size_t i = 0; i < sg.map.size(); ++i)
+      if (sg.map[i] < 0 || sg.map[i] >= raw_elems) return fail("segment map entry out of range", sg.map[i], raw_elems);
+    if ((int64_t)sg.map.size() != sg.elems) return "segment map size";
+    const auto& w = sg.prog;
+    const std::string bad = check_fused_program(w, sg.lds_bytes, sg.elems, p.n_slices);
+    if (!bad.empty()) return "segment: " + bad;
+    if (w[FH_SCALARS] != 0) return "segment with a scalar list";
+    if (sg.exports.empty() || sg.exports.size() != 4 * (size_t)w[FH_EXPORTS]) return "segment export list";
+    if (sg.imports.size() != 4 * (size_t)w[FH_IMPORTS]) return "segment import list";
+    if (j == 0 && p.has_prefix && !sg.imports.empty()) return "prefix with imports";
+    const size_t x_at = kHdr + 4 * ((size_t)w[FH_LEVELS] + kFusedLevelPad);
+    const size_t i_at = x_at + sg.exports.size();
+    if (i_at + sg.imports.size() > w.size() || !std::equal(sg.exports.begin(), sg.exports.end(), w.begin() + x_at) ||
+        !std::equal(sg.imports.begin(), sg.imports.end(), w.begin() + i_at))
+      return "segment rows differ from the program's";
+    const int64_t lo = kFusedConsts, hi = w[FH_DATA_ELEMS];
+    for (const std::vector<uint32_t>* rows : {&sg.exports, &sg.imports})
+      for (size_t i = 0; i < rows->size(); i += 4) {
+        const int64_t src = (*rows)[i], rank = (*rows)[i + 1];
+        const int64_t off = (int64_t)(((uint64_t)(*rows)[i + 3] << 32) | (*rows)[i + 2]);
+        if (rank > p.seg_max_rank + 1 || rank > 15) return "segment row above its rank bound";
+        if (src < lo || src + (int64_t(1) << rank) > hi) return "segment row outside its LDS data";
+        if (off < 0 || off + (int64_t(1) << rank) > p.arena_per_slice)
+          return fail("segment row outside the arena", off + (int64_t(1) << rank), p.arena_per_slice);
+      }
   }
   return "";
 }

@@ -91,6 +91,28 @@ GroupStep group_step_of(const StepProg& sp, int k);
 // or group `group` of small steps in one launch.
 struct LaunchItem {
   int32_t step, group;
+  int32_t seg = -1;  // >= 0: fused segment seg (step and group -1)
+};
+
+// A fused segment of a per-step plan: a connected run of small buckets
+// (unions of at most R + 1 variables) contracted by one LDS-resident launch
+// of the fused executor (fused.hip).  Its import rows copy the results of
+// other launches that it reads from the arena into LDS; its export rows copy
+// its results that other launches read (and its rank-0 results) from LDS to
+// the arena.  The prefix -- the subtrees of small buckets above the inputs
+// -- imports nothing; a later segment exports only its top bucket's result.
+struct FusedSeg {
+  std::vector<uint32_t> prog;   // fused program (fused_format.hpp), no scalar list
+  std::vector<int32_t> map;     // its prepared-input gather map
+  int64_t elems = 0;            // map entries
+  int lds_bytes = 0, levels = 0, buckets = 0;
+  std::vector<uint32_t> exports, imports;  // copies of the program's rows
+  int64_t bytes_per_slice = 0, flops_per_slice = 0;
+  int32_t level = 0;            // launch level (depth by memory hazards)
+  int32_t pos = 0;              // launched before per-step step pos (in step order)
+  void* d_map = nullptr;        // device copies: map, prepared inputs, program
+  void* d_in = nullptr;
+  void* d_prog = nullptr;
 };
 // A grouped step of a batch's per-step instances, which run level by level
 // together: the step with its plan's context.  Its work units are `tiles`
@@ -139,21 +161,14 @@ struct Plan {
   int32_t group_sb = 1;                 // slices per block of a group launch
   std::vector<int32_t> step_level;      // level of each step in that order
 
-  // fused prefix of a per-step plan (qbe_plan_opts.fused_prefix): the
-  // subtrees of small buckets in one LDS-resident launch before the per-step
-  // launches; its export rows (4 words each: LDS element offset, rank, arena
-  // offset lo, hi; prefix_exports is a copy of those in the program) copy
-  // the results larger buckets read to the arena
+  // fused segments of a per-step plan (qbe_plan_opts.fused_prefix and
+  // fused_segments): the prefix (segs[0] when has_prefix) and later runs
+  // of small buckets, launched in launch_order
   int want_prefix = 0;                  // 0 none, 1 the largest bound that fits, else R
-  bool prefix_ok = false;
-  int prefix_max_rank = -1;             // result rank bound R of its buckets
-  int prefix_buckets = 0;
-  std::vector<uint32_t> prefix_prog;    // a fused program (fused_format.hpp), no scalar list
-  std::vector<int32_t> prefix_map;      // its prepared-input gather map
-  int64_t prefix_elems = 0;
-  int prefix_lds_bytes = 0, prefix_levels = 0;
-  std::vector<uint32_t> prefix_exports;
-  int64_t prefix_bytes_per_slice = 0, prefix_flops_per_slice = 0;
+  bool want_segments = false;
+  bool has_prefix = false;
+  int seg_max_rank = -1;                // result rank bound R of their buckets (-1: none)
+  std::vector<FusedSeg> segs;
 
   // fused form
   bool fused_ok = false;
@@ -173,9 +188,6 @@ struct Plan {
   void* d_scalar_tab = nullptr; // int64 arena offsets, int64 input bases, uint32 smasks
   void* d_state = nullptr;      // uint32[4]: work counter, exits, items done (fused)
   void* d_group = nullptr;      // GroupStep array, then the uint32 tile prefixes
-  void* d_prefix_map = nullptr; // fused prefix: gather map, prepared inputs
-  void* d_prefix_in = nullptr;  //   and program
-  void* d_prefix_prog = nullptr;
 };
 
 // A set of plans contracted together in one fused launch.

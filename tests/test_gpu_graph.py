@@ -23,7 +23,7 @@ def _capture(torch, ctx, fn):
     return g
 
 
-@pytest.mark.parametrize("form", ["fused", "per_step", "per_step_tuned", "per_step_prefix"])
+@pytest.mark.parametrize("form", ["fused", "per_step", "per_step_tuned", "per_step_prefix", "per_step_segments"])
 def test_plan_graph_replays_match_eager(form):
     import torch
     import paper_2004_10892_amd as qbe
@@ -32,8 +32,8 @@ def test_plan_graph_replays_match_eager(form):
     ctx = qbe.Context(0)
     qm = qbe.Model.from_circuitgen(circuit_model(random_grid_circuit(5, 5, 16, 1)))
     _, mu, pi, _ = qbe.plan_circuit(qm, m=6)
-    plan = qbe.Plan(qm, pi, mu, ctx=ctx, exec=form.split("_t")[0].replace("_prefix", ""),
-                    fused_prefix=form.endswith("_prefix"))
+    plan = qbe.Plan(qm, pi, mu, ctx=ctx, exec="fused" if form == "fused" else "per_step",
+                    fused_prefix=form.endswith(("_prefix", "_segments")), fused_segments=form.endswith("_segments"))
     ws = plan.workspace()
     if form.endswith("_tuned"):
         plan.autotune(ws, min_elems=1 << 10)  # tuned launch shapes, as the benchmark captures them

@@ -1,7 +1,9 @@
 """Per-step plans with a fused prefix: the subtrees of small buckets run in one
 LDS-resident launch of the fused executor, which writes the results larger
-buckets read to the workspace; the per-step launches do the rest.  The
-prefix changes where the buckets run, never what they compute (Eqs. 2-4):
+buckets read to the workspace; the per-step launches do the rest.  With
+fused segments, later runs of small buckets also run as such launches,
+reading the larger results they need from the workspace.  Neither changes
+what the buckets compute, only where they run (Eqs. 2-4):
 amplitudes and per-slice values must match the oracle at the parity
 tolerance (relative 1e-5, per-slice values floored at 1e-5 of their RMS),
 for whole and ragged slice ranges, small workspaces (several slice groups
@@ -44,22 +46,25 @@ def golden_case(qbe, name, r, c, d):
     return g, qm
 
 
-def prefix_plan(qbe, ctx, qm, pi, mu, **kw):
-    plan = qbe.Plan(qm, pi, mu, ctx=ctx, exec="per_step", fused_prefix=True, **kw)
+def prefix_plan(qbe, ctx, qm, pi, mu, segments=False, **kw):
+    plan = qbe.Plan(qm, pi, mu, ctx=ctx, exec="per_step", fused_prefix=True, fused_segments=segments, **kw)
     st = plan.stats()
     assert st["prefix_buckets"] >= 2, st
     assert plan.launches()[0]["kind"] == "prefix"
     return plan
 
 
+@pytest.mark.parametrize("segments", [False, True])
 @pytest.mark.parametrize("name,shape,m", [("grid5x5_d16_m6", (5, 5, 16), 6), ("grid7x7_d24_m10", (7, 7, 24), 10)])
-def test_prefix_plan_matches_oracle_slices_and_amplitude(env, name, shape, m):
+def test_prefix_plan_matches_oracle_slices_and_amplitude(env, name, shape, m, segments):
     qbe, ctx = env
     g, qm = golden_case(qbe, name, *shape)
     _, mu, pi, tau = qbe.plan_circuit(qm, m=m)
     assert tau == g["tau"]
-    plan = prefix_plan(qbe, ctx, qm, pi, mu)
-    print(f"case prefix {name}: {plan.stats()['prefix_buckets']} buckets in the prefix", flush=True)
+    plan = prefix_plan(qbe, ctx, qm, pi, mu, segments)
+    st = plan.stats()
+    print(f"case prefix {name} segments={segments}: {st['fused_buckets']} buckets in "
+          f"{st['n_fused_segments']} fused launches", flush=True)
     ws = plan.workspace()
     n = min(plan.n_slices, 64)
     _, per = qbe.qbe_contract_slices(ctx, plan, 0, n, ws)
@@ -68,16 +73,19 @@ def test_prefix_plan_matches_oracle_slices_and_amplitude(env, name, shape, m):
     assert rel(qbe.qbe_contract(ctx, plan, ws), complex(*g["oracle"])) <= TOL
 
 
+@pytest.mark.parametrize("segments", [False, True])
 @pytest.mark.parametrize("every", [1, 2])
-def test_prefix_on_recomputed_plans(env, every):
+def test_prefix_on_recomputed_plans(env, every, segments):
     """The headline's plan family: Alg. 2 with order recomputation on the
     7x7 depth-24 circuit (1024 slices), whose amplitude is fixed by the
     oracle whatever the schedule."""
     qbe, ctx = env
     g, qm = golden_case(qbe, "grid7x7_d24_m10", 7, 7, 24)
     mu, pi, _ = qbe.qbe_slice(qm, qbe.qbe_order_min_fill(qm), 10, recompute_every=every, tries=16, seed=2)
-    plan = prefix_plan(qbe, ctx, qm, pi, mu)
-    print(f"case prefix 7x7 recompute every {every}", flush=True)
+    plan = prefix_plan(qbe, ctx, qm, pi, mu, segments)
+    if segments:
+        assert plan.stats()["n_fused_segments"] >= 2
+    print(f"case prefix 7x7 recompute every {every} segments={segments}", flush=True)
     ws = plan.workspace()
     got = qbe.qbe_contract(ctx, plan, ws)
     assert rel(got, complex(*g["oracle"])) <= TOL
@@ -85,9 +93,10 @@ def test_prefix_on_recomputed_plans(env, every):
     assert rel(got, qbe.qbe_contract(ctx, plain, plain.workspace())) <= TOL
 
 
-def test_prefix_ragged_ranges_and_small_workspace(env):
-    """Slice groups that start anywhere: the prefix reads each slice's own
-    inputs and writes the group's arena rows."""
+@pytest.mark.parametrize("segments", [False, True])
+def test_prefix_ragged_ranges_and_small_workspace(env, segments):
+    """Slice groups that start anywhere: the fused launches read each
+    slice's own inputs and the group's arena rows, and write its rows."""
     import torch
     qbe, ctx = env
     from circuitgen import circuit_model, random_grid_circuit
@@ -99,12 +108,12 @@ def test_prefix_ragged_ranges_and_small_workspace(env):
     mu, _, pi, _ = P.greedy_treewidth_deletion(adj, P.min_fill_order(adj), 5)
     _, vals = C.contract(mod.tensors, C.bucket_schedule(mod.n_vars, tv, pi, mu))
     qm = qbe.Model.from_circuitgen(mod)
-    plan = prefix_plan(qbe, ctx, qm, pi, mu)
+    plan = prefix_plan(qbe, ctx, qm, pi, mu, segments)
     st = plan.stats()
     ws = torch.empty(st["ws_bytes_min"] + 3 * (st["ws_bytes_all_slices"] - st["ws_bytes_min"]) // 32,
                      dtype=torch.uint8, device="cuda")
     for (b, e) in [(0, 32), (3, 17), (31, 32), (5, 6)]:
-        print(f"case prefix ragged range {b}-{e}", flush=True)
+        print(f"case prefix ragged range {b}-{e} segments={segments}", flush=True)
         _, per = qbe.qbe_contract_slices(ctx, plan, b, e, ws)
         check_slices(per, vals[b:e])
 
@@ -118,8 +127,8 @@ def test_prefix_with_reduced_precision_mfma(env, prec):
     qbe, ctx = env
     g, qm = golden_case(qbe, "grid5x5_d16_m6", 5, 5, 16)
     _, mu, pi, _ = qbe.plan_circuit(qm, m=6)
-    plan = prefix_plan(qbe, ctx, qm, pi, mu, precision=prec)
-    print(f"case prefix {prec}", flush=True)
+    plan = prefix_plan(qbe, ctx, qm, pi, mu, True, precision=prec)
+    print(f"case prefix and segments {prec}", flush=True)
     got = qbe.qbe_contract(ctx, plan, plan.workspace())
     assert rel(got, complex(*g["oracle"])) <= (TOL if prec == "bf16x6" else 7 * 4 * 2.5 * 2.0 ** -17)
 
@@ -129,9 +138,9 @@ def test_prefix_static_entry_and_profile(env):
     (same bits); per-launch timing lists the prefix first."""
     import torch
     qbe, ctx = env
-    g, qm = golden_case(qbe, "grid5x5_d16_m6", 5, 5, 16)
-    _, mu, pi, _ = qbe.plan_circuit(qm, m=6)
-    plan = prefix_plan(qbe, ctx, qm, pi, mu)
+    g, qm = golden_case(qbe, "grid7x7_d24_m10", 7, 7, 24)
+    _, mu, pi, _ = qbe.plan_circuit(qm, m=10)
+    plan = prefix_plan(qbe, ctx, qm, pi, mu, True)
     print("case prefix static entry", flush=True)
     ws = plan.workspace()
     want = qbe.qbe_contract(ctx, plan, ws)
@@ -148,6 +157,6 @@ def test_prefix_plans_are_not_batched(env):
     qbe, ctx = env
     g, qm = golden_case(qbe, "grid5x5_d16_m6", 5, 5, 16)
     _, mu, pi, _ = qbe.plan_circuit(qm, m=6)
-    plan = prefix_plan(qbe, ctx, qm, pi, mu)
+    plan = prefix_plan(qbe, ctx, qm, pi, mu, True)
     with pytest.raises(qbe.QbeError, match="INVALID_ARG"):
         qbe.Batch(ctx, [plan])

@@ -1,6 +1,6 @@
-"""Fused-prefix plans on the host (no device): which buckets the prefix
-takes, the plan check over its program and exports, the per-launch view,
-and the option's validation."""
+"""Fused-prefix and fused-segment plans on the host (no device): which
+buckets they take, the plan check over their programs and rows, the
+per-launch view, and the options' validation."""
 import pytest
 
 
@@ -93,3 +93,64 @@ def test_explicit_rank_bounds(c3):
     for bigger in range(R + 1, 15):
         la = qbe.Plan(qm, pi, mu, exec="per_step", fused_prefix=bigger).launches()[0]
         assert la["kind"] != "prefix" or la["lds_bytes"] > pair
+
+
+def test_later_segments_take_runs_of_small_buckets(c3):
+    """fused_segments: runs of at least three small buckets after the prefix
+    become one launch each, importing what they read; the byte count of
+    the plan is still the sum over its launches, and no bucket is lost."""
+    qbe, qm, mu, pi = c3
+    pre = qbe.Plan(qm, pi, mu, exec="per_step", fused_prefix=True)
+    seg = qbe.Plan(qm, pi, mu, exec="per_step", fused_prefix=True, fused_segments=True)
+    seg.check()
+    sp, sq = pre.stats(), seg.stats()
+    assert sp["n_fused_segments"] == 1 and sq["n_fused_segments"] >= 2
+    assert sq["prefix_buckets"] == sp["prefix_buckets"]
+    assert sq["fused_buckets"] > sp["fused_buckets"]
+    assert sq["n_launches"] < sp["n_launches"]
+    la = seg.launches()
+    kinds = [l["kind"] for l in la]
+    assert kinds[0] == "prefix" and kinds.count("prefix") == 1
+    segs = [l for l in la if l["kind"] == "segment"]
+    assert len(segs) == sq["n_fused_segments"] - 1
+    assert sum(l["n_buckets"] for l in la if l["kind"] in ("prefix", "segment")) == sq["fused_buckets"]
+    for l in segs:
+        assert l["n_buckets"] >= 3 and l["n_ops"] >= 1 and l["levels"] > 0 and 0 < l["lds_bytes"] <= 160 * 1024
+    assert sum(l["bytes_per_slice"] for l in la[:-2]) == sq["step_bytes_per_slice"]
+    assert [l["kind"] for l in la[-2:]] == ["finalize", "reduce"]
+
+
+def test_segment_option_validation(c3):
+    import ctypes as C
+    import numpy as np
+    import paper_2004_10892_amd as qbe
+    _, qm, mu, pi = c3
+    po = np.asarray(pi, dtype=np.int32)
+    pm = np.asarray(mu, dtype=np.int32)
+    for prefix, segments, what in ((0, 1, "fused_segments needs"), (1, 2, "fused_segments must")):
+        o = qbe.PlanOpts()
+        o.exec = qbe.EXEC["per_step"]
+        o.fused_prefix = prefix
+        o.fused_segments = segments
+        h = C.c_void_p()
+        rc = qbe._lib.qbe_plan_create(None, qm.handle, po.ctypes.data_as(C.POINTER(C.c_int32)), len(po),
+                                      pm.ctypes.data_as(C.POINTER(C.c_int32)), len(pm), C.byref(o), C.byref(h))
+        assert qbe.ERRORS[rc] == "INVALID_ARG"
+        assert what in qbe._lib.qbe_last_error().decode()
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_segment_plans_of_random_circuits_pass_the_plan_check(seed):
+    """Segments over other schedules (orders from the anytime heuristic,
+    several slicing sizes): every plan passes the host check of every
+    index its kernels and rows can form."""
+    import paper_2004_10892_amd as qbe
+    from circuitgen import circuit_model, random_grid_circuit
+    qm = qbe.Model.from_circuitgen(circuit_model(random_grid_circuit(5 + seed % 2, 6, 12 + 4 * seed, 50 + seed)))
+    for m in (0, 2, 5):
+        _, mu, pi, _ = qbe.plan_circuit(qm, m=m)
+        for R in (True, 4, 7):
+            p = qbe.Plan(qm, pi, mu, exec="per_step", fused_prefix=R, fused_segments=True)
+            p.check()
+            st = p.stats()
+            assert st["fused_buckets"] <= st["n_steps"]
