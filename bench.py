@@ -38,12 +38,12 @@ METRIC = "amplitudes/sec + MFMA util, chosen vs plain FP32 form at rel err ≤1e
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 SEEDS = {"grid4x4_d10_m0": 0, "grid5x5_d16_m6": 1, "grid7x7_d24_m10": 0}
-# Memory traffic of one headline fused_kernel launch from the FETCH_SIZE and
-# WRITE_SIZE counter runs in profiles/fused_kernel_grid5x5_d16_m6.md (702.44
-# KiB x 2.000 + 6.06 KiB x 1.000, the factors from a 256 MiB device copy),
+# Memory traffic of one 5x5 depth-16 fused_kernel launch from the FETCH_SIZE
+# and WRITE_SIZE counter runs in profiles/fused_kernel_grid5x5_d16_m6.md
+# (722.06 KiB x 2.000 + 6.06 KiB x 1.000, the factors from a 256 MiB device copy),
 # valid while the fused kernel's sources have the digest they were measured on.
-FUSED_TRAFFIC = {"bytes": int(round((702.4375 * 2.000 + 6.0625 * 1.000) * 1024)),
-                 "sources_sha256": "45387944cb35a83c5dd47a6f7a4c8da07409b00ffe9f0240679ad7ad0e327f8c"}
+FUSED_TRAFFIC = {"bytes": int(round((722.0625 * 2.000 + 6.0625 * 1.000) * 1024)),
+                 "sources_sha256": "6d2ebd8c1828c4f5c14865302cd4e39fbc3a8934798ee7c8f13482e0d335d840"}
 
 
 def log(*a):
@@ -232,53 +232,54 @@ def cpu_model():
 C3 = "grid7x7_d24_m10"
 # Sources that decide the per-step form's kernels and launches: counters
 # taken on other sources describe other code and are not reported.
-STEP_SOURCES = ("device.hip", "device_common.hpp", "qbe_internal.hpp", "program.cpp", "planner.cpp")
+STEP_SOURCES = ("device.hip", "device_common.hpp", "qbe_internal.hpp", "program.cpp", "planner.cpp", "fused.hip",
+                "fused_format.hpp")
 # Hardware counters of one contraction of the headline plan
-# (profiles/step_kernels_grid7x7_d24_m10.md): per precision, summed over the
+# (profiles/fused_and_step_kernels_grid7x7_d24_m10.md): per precision, summed over the
 # contraction's dispatches.  mfma_busy: SQ_VALU_MFMA_BUSY_CYCLES; capacity:
 # GRBM_GUI_ACTIVE / 8 XCDs x 256 CUs x 4 SIMDs; fetch/write: FETCH_SIZE x
 # 2.000 and WRITE_SIZE x 1.000 bytes (the 256 MiB device-copy calibration);
 # dominant: the same for the dominant kernel's launch.  Keyed by the
 # sources' digest and the plan's sliced set.
 C3_COUNTERS = {
-    "sources_sha256": "fe9d5ab366c9af0446edfc2c61a1193f00f057fecc52c0ef2769edf1340b5f3e",
-    "plan": "min_fill+tt_rec2",
+    "sources_sha256": "6b6ec7ca833d57a992a01d52fbeab77f32e26719d9255b1d9434e4b3d016f758",
+    "plan": "min_fill+tt_rec1_t16_s2+segments",
     "mu": [
         119,
-        353,
-        220,
-        183,
+        154,
+        406,
+        113,
         66,
-        335,
-        486,
+        308,
+        385,
+        150,
         169,
-        453,
-        398
+        289
     ],
     "fp32": {
-        "mfma_util": 0.0011540529700733721,
-        "mfma_busy_cycles": 4194304.0,
-        "gui_active": 28393844.0,
+        "mfma_util": 0.0017440396189937666,
+        "mfma_busy_cycles": 2097152.0,
+        "gui_active": 9394282.0,
         "amplitude": {
-            "bytes": 1204353824,
-            "fetch_kib": 307667.4375,
-            "write_kib": 560791.90625
+            "bytes": 578582816,
+            "fetch_kib": 166887.125,
+            "write_kib": 231248.03125
         },
         "dominant": {
-            "launch": 65,
-            "kernel": "qbe::msum_pair_kernel<8, 2>",
-            "bytes": 102640640,
-            "fetch_kib": 33733.5,
-            "write_kib": 32768.0
+            "launch": 0,
+            "kernel": "qbe::fused_kernel",
+            "bytes": 64882816,
+            "fetch_kib": 6193.0625,
+            "write_kib": 50976.0
         }
     },
     "bf16x6": {
-        "mfma_util": 0.001139092084373741,
-        "mfma_busy_cycles": 4194304.0,
-        "gui_active": 28766770.0
+        "mfma_util": 0.0017001317851176208,
+        "mfma_busy_cycles": 2097152.0,
+        "gui_active": 9636900.0
     },
-    "plain_fp32_same_plan": {
-        "mfma_util": 0.00012238179777516406
+    "plain_fp32": {
+        "mfma_util": 0.0003731293005150303
     }
 }
 
@@ -402,21 +403,28 @@ def launch_profile(plan, ws, reps):
     return rows
 
 
-PREFIX = "+prefix"
+FUSED_FORMS = {"": (False, False), "+prefix": (True, False), "+segments": (True, True)}
 
 
 def split_plan_name(name):
-    """A timed plan's name: a candidate's, with PREFIX appended when the plan
-    runs its small buckets in a fused prefix.  Returns (candidate, prefix)."""
-    return (name[:-len(PREFIX)], True) if name.endswith(PREFIX) else (name, False)
+    """A timed plan's name: a candidate's, with "+prefix" appended when the
+    plan runs its first small buckets in a fused prefix, "+segments" when
+    later runs of small buckets are fused launches too.  Returns
+    (candidate, fused_prefix, fused_segments)."""
+    for suffix, (pre, seg) in FUSED_FORMS.items():
+        if suffix and name.endswith(suffix):
+            return name[:-len(suffix)], pre, seg
+    return name, False, False
 
 
-def time_precisions(torch, qbe, ctx, qm, mu, pi, precisions, steps, warmup, want, keep=True, prefix=False):
+def time_precisions(torch, qbe, ctx, qm, mu, pi, precisions, steps, warmup, want, keep=True, prefix=False,
+                    segments=False):
     """The plan (mu, pi) in each precision: autotuned, then timed issued
     directly and from a HIP graph; error against the oracle amplitude."""
     forms = {}
     for prec in precisions:
-        plan = qbe.Plan(qm, pi, mu, ctx=ctx, exec="per_step", precision=prec, fused_prefix=prefix)
+        plan = qbe.Plan(qm, pi, mu, ctx=ctx, exec="per_step", precision=prec, fused_prefix=prefix,
+                        fused_segments=segments)
         ws0 = plan.workspace()
         t0 = time.perf_counter()
         plan.autotune(ws0)
@@ -457,36 +465,36 @@ def bench_headline(torch, qbe, ctx, steps, warmup, net, n_timed=6):
                   next((k for k in ranked if k.startswith("anytime8")), None)):
         if extra and extra not in to_time:
             to_time.append(extra)
-    # each without and with the fused prefix (small buckets in one
-    # LDS-resident launch)
+    # each in the plain per-step form, with the fused prefix (first small
+    # buckets in one LDS-resident launch) and with fused segments (later
+    # runs of small buckets too)
     timed_ms = {}
     for k in to_time:
         mu_k, pi_k, _ = cands[k]
-        for pre in (False, True):
-            plan_k = qbe.Plan(qm, pi_k, mu_k, ctx=ctx, exec="per_step", fused_prefix=pre)
-            if pre and plan_k.stats()["prefix_buckets"] == 0:
+        for suffix, (pre, seg) in FUSED_FORMS.items():
+            plan_k = qbe.Plan(qm, pi_k, mu_k, ctx=ctx, exec="per_step", fused_prefix=pre, fused_segments=seg)
+            st_k = plan_k.stats()
+            if (pre and st_k["prefix_buckets"] == 0) or (seg and st_k["n_fused_segments"] < 2):
                 continue
             ws_k = plan_k.workspace()
             plan_k.autotune(ws_k)
             out_k = torch.zeros(2, dtype=torch.float64, device="cuda")
             _, ev_k = timed(torch, lambda: qbe.qbe_contract_async(ctx, plan_k, ws_k, out_k), max(3, steps // 2), 1)
             err_k = abs(complex(*out_k.cpu().numpy()) - want) / abs(want)
-            tag = "prefix_" if pre else ""
+            tag = suffix.lstrip("+") + "_" if suffix else ""
             plans_info[k][f"fp32_{tag}ms_per_amplitude"] = ev_k
             plans_info[k][f"rel_err_fp32_{tag}".rstrip("_")] = err_k
-            if pre:
-                plans_info[k]["prefix_buckets"] = plan_k.stats()["prefix_buckets"]
-                plans_info[k]["prefix_launches"] = plan_k.stats()["n_launches"]
+            plans_info[k][f"{tag}launches"] = st_k["n_launches"]
             if err_k <= 1e-5:
-                timed_ms[k + (PREFIX if pre else "")] = ev_k
+                timed_ms[k + suffix] = ev_k
             del ws_k, plan_k
     src = min(timed_ms, key=timed_ms.get)
-    base, use_prefix = split_plan_name(src)
+    base, use_prefix, use_segments = split_plan_name(src)
     mu, pi, _ = cands[base]
     search_s = time.perf_counter() - t_search
     log(f"[bench] {C3}: plan {src}; " + ", ".join(f"{k} {v:.3f} ms" for k, v in sorted(timed_ms.items())))
     forms = time_precisions(torch, qbe, ctx, qm, mu, pi, ("fp32", "bf16x6", "bf16x3"), steps, warmup, want,
-                            prefix=use_prefix)
+                            prefix=use_prefix, segments=use_segments)
     ok = [p for p in forms if forms[p]["within_1e-5"]]
     if not ok:
         raise SystemExit("no form of the headline workload met the 1e-5 bound")
@@ -521,10 +529,11 @@ def bench_headline(torch, qbe, ctx, steps, warmup, net, n_timed=6):
     lk = [k for k in timed_ms if "learned" in k]
     if lk:
         kb = min(lk, key=timed_ms.get)
-        kb_base, kb_prefix = split_plan_name(kb)
+        kb_base, kb_prefix, kb_segments = split_plan_name(kb)
         mu_c, pi_c, _ = cands[kb_base]
         fc = forms if kb == src else time_precisions(torch, qbe, ctx, qm, mu_c, pi_c, ("bf16x3", "bf16x6", "fp32"),
-                                                     max(3, steps // 2), 1, want, keep=False, prefix=kb_prefix)
+                                                     max(3, steps // 2), 1, want, keep=False, prefix=kb_prefix,
+                                                     segments=kb_segments)
         combined = {"plan": kb, "forms": {p: {k: v for k, v in f.items() if not k.startswith("_")}
                                           for p, f in fc.items()},
                     "speedup_vs_plain": {p: ev_p / f["ms_per_amplitude"] for p, f in fc.items()},
@@ -544,8 +553,12 @@ def bench_headline(torch, qbe, ctx, steps, warmup, net, n_timed=6):
     roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
             "traffic": dom_cnt["bytes"] if dom_cnt else None,
             "traffic_kernel": dom_cnt["kernel"] if dom_cnt else None,
-            "kernel": f"launch {dom['index']}: {dom['kind']}, {dom['n_ops']} operands, result rank "
-                      f"{dom['out_rank']}, {dom['n_sum']} summed, {'MFMA' if dom['mfma'] else 'VALU'}",
+            "kernel": (f"launch {dom['index']}: fused {dom['kind']} (fused_kernel), {dom['n_buckets']} buckets "
+                       f"of at most {dom['out_rank'] + 1} variables, {dom['levels']} levels, {dom['lds_bytes']} B LDS "
+                       f"a workgroup, {dom['n_ops']} imported results"
+                       if dom["kind"] in ("prefix", "segment") else
+                       f"launch {dom['index']}: {dom['kind']}, {dom['n_ops']} operands, result rank "
+                       f"{dom['out_rank']}, {dom['n_sum']} summed, {'MFMA' if dom['mfma'] else 'VALU'}"),
             "launch_ms": dom["ms"], "algorithmic_bytes_per_launch": dom["bytes"],
             "bytes_per_slice": dom["bytes_per_slice"], "slices_per_launch": plan.n_slices,
             "launch_share_of_amplitude": dom["ms"] / total_ms,
@@ -837,9 +850,10 @@ def main():
     ap.add_argument("--pmc-c3", choices=["fp32", "bf16x6", "bf16x3", "plain_fp32"],
                     help="for hardware-counter runs: the copy calibration, then the headline plan in this form "
                          "(sliced set from --mu, else tree-trimming), autotuned, and two contractions")
-    ap.add_argument("--plan", default="min_fill+tt_rec1_t16_s2",
+    ap.add_argument("--plan", default="min_fill+tt_rec1_t16_s2+segments",
                     help="for --pmc-c3: a candidate plan of the headline search without the network "
-                         "(min_fill or anytime8, + tt or tt_rec<k>_t<tries>_s<seed>)")
+                         "(min_fill or anytime8, + tt or tt_rec<k>_t<tries>_s<seed>), optionally followed by "
+                         "+prefix or +segments")
     ap.add_argument("--reps", type=int, default=2, help="contractions in a --pmc-c3 run")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -875,13 +889,14 @@ def main():
     if args.pmc_c3:
         qm, m = c3_model(qbe)
         cands = plan_candidates(qbe, qm, m, None)
-        base, use_prefix = split_plan_name(args.plan)
+        base, use_prefix, use_segments = split_plan_name(args.plan)
         if base not in cands:
-            raise SystemExit(f"--plan must be one of {sorted(cands)}, optionally followed by {PREFIX}")
+            raise SystemExit(f"--plan must be one of {sorted(cands)}, optionally followed by +prefix or +segments")
         mu, pi, _ = cands[base]
         plain = args.pmc_c3 == "plain_fp32"
         plan = qbe.Plan(qm, pi, mu, ctx=ctx, exec="per_step", precision="fp32" if plain else args.pmc_c3,
-                        merge=not plain, fused_prefix=use_prefix and not plain)
+                        merge=not plain, fused_prefix=use_prefix and not plain,
+                        fused_segments=use_segments and not plain)
         ws = plan.workspace()
         out = torch.zeros(2, dtype=torch.float64, device="cuda")
         if not plain:
