@@ -1,8 +1,9 @@
 // Host driver for the sanitizer build of the planner and plan compiler
 // (planner.cpp, program.cpp, program_check.cpp): reads a network and a plan
 // (sliced set and reduced order), builds the schedule, compiles the device
-// programs in the merged and the one-launch-per-bucket form and runs the
-// host bounds check of every program.  Prints "ok" and exits 0, or prints
+// programs in the one-launch-per-bucket form, the merged form, and the
+// merged form with a fused prefix (automatic and fixed rank bounds) and
+// fused segments, and runs the host bounds check of every program.  Prints "ok" and exits 0, or prints
 // the failure and exits 1.  Input: n_vars n_tensors, then per tensor its
 // rank and variables, then the order (count, ids) and mu (count, ids).
 #include <cstdio>
@@ -43,12 +44,16 @@ int main(int argc, char** argv) {
   for (int& v : mu) f >> v;
   if (!f) return 2;
   try {
-    for (int merge = 0; merge < 2; ++merge) {
+    // (merge, fused prefix, fused segments)
+    const int forms[][3] = {{0, 0, 0}, {1, 0, 0}, {1, 1, 0}, {1, 1, 1}, {1, 6, 1}, {1, 4, 0}};
+    for (const auto& form : forms) {
       qbe::Plan p;
       p.model = md;
       p.sched = qbe::build_schedule(nv, md.tvars, order, mu);
       p.cost = qbe::schedule_cost(p.sched);
-      p.merge = merge != 0;
+      p.merge = form[0] != 0;
+      p.want_prefix = form[1];
+      p.want_segments = form[2] != 0;
       qbe::compile_plan(p);
       const std::string bad = qbe::check_plan(p);
       if (!bad.empty()) {
