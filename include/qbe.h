@@ -398,8 +398,12 @@ int qbe_plan_dump(const qbe_plan* plan, char* buf, size_t cap, size_t* len_out);
  * covers at least min_elems result entries in every candidate tile shape
  * (tiles per thread in {1, 2, 4} x workgroups per compute unit in {4, 8, 16,
  * 32}) on the device, with the workspace the contraction will use, and keeps
- * the fastest shape in the plan.  Blocks until done.  Plans in the fused form
- * have nothing to tune (QBE_OK).  The workspace contents are overwritten. */
+ * the fastest shape in the plan.  In an FP32 plan a merged launch that runs
+ * as an MFMA product is also timed on the VALU kernels, and the faster form
+ * is kept (both are FP32 products; the sums' rounding order differs, so a
+ * tuned plan's bits may differ from the untuned plan's within FP32
+ * rounding).  Blocks until done.  Plans in the fused form have nothing to
+ * tune (QBE_OK).  The workspace contents are overwritten. */
 int qbe_plan_autotune(qbe_ctx* ctx, qbe_plan* plan, void* d_workspace, size_t ws_bytes,
                       int64_t min_elems);
 

@@ -1774,8 +1774,10 @@ static int launch_group(const Plan& p, int g, float2* arena, int64_t G, int64_t 
 
 // Autotuner: times every large per-step launch of the plan on the device in
 // each candidate tile shape (tiles per thread x workgroups per CU) and keeps
-// the fastest.  Runs the plan's own schedule on a slice group of G slices, so
-// the data it reads are the intermediates of the group's slices.
+// the fastest; an FP32 merged launch on MFMA is also timed on the VALU
+// kernels, and the faster form kept.  Runs the plan's own schedule on a
+// slice group of G slices, so the data it reads are the intermediates of
+// the group's slices.
 int dev_autotune(Plan& p, void* stream, void* ws, size_t ws_bytes, int64_t min_elems) {
   hipStream_t st = (hipStream_t)stream;
   const int64_t n = p.n_slices;
@@ -1792,23 +1794,46 @@ int dev_autotune(Plan& p, void* stream, void* ws, size_t ws_bytes, int64_t min_e
   const int epts[] = {1, 2, 4};
   const int wgs[] = {4, 8, 16, 32};
   int rc = QBE_OK;
+  // time of one configuration: the mean of two runs after a warm-up run
+  auto time_config = [&](StepProg& sp, int e, int w, float& total) {
+    total = 0.f;
+    for (int rep = 0; rep < 3 && rc == QBE_OK; ++rep) {
+      if (hipEventRecord(e0, st) != hipSuccess) rc = QBE_ERR_HIP;
+      if (rc == QBE_OK) rc = launch_step(p, sp, arena, G, 0, st, e, w);
+      if (rc == QBE_OK && hipEventRecord(e1, st) != hipSuccess) rc = QBE_ERR_HIP;
+      if (rc == QBE_OK && hipEventSynchronize(e1) != hipSuccess) rc = QBE_ERR_HIP;
+      float ms = 0.f;
+      if (rc == QBE_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = QBE_ERR_HIP;
+      if (rep > 0) total += ms;  // first run warms caches and code
+    }
+  };
   for (StepProg& sp : p.steps) {
     const int r = sp.out_rank >= 0 ? sp.out_rank : -sp.out_rank;
     if ((G << r) >= min_elems) {
+      // a merged launch on MFMA in FP32 against the same launch on the
+      // VALU kernels (both FP32 products: the same sum, other tiles); the
+      // split-BF16 plans keep their MFMA form
+      float mfma_ms = 1e30f;
+      int mfma_w = 0;
+      const bool both = sp.mmk && p.precision == QBE_PREC_FP32;
+      if (both) {
+        for (int w : wgs) {
+          float total = 0.f;
+          time_config(sp, 1, w, total);
+          if (rc != QBE_OK) break;
+          if (total < mfma_ms) {
+            mfma_ms = total;
+            mfma_w = w;
+          }
+        }
+        sp.mmk = 0;
+      }
       float best = 1e30f;
       int be = 1, bw = 16;
       for (int e : epts)
         for (int w : wgs) {
           float total = 0.f;
-          for (int rep = 0; rep < 3 && rc == QBE_OK; ++rep) {
-            if (hipEventRecord(e0, st) != hipSuccess) rc = QBE_ERR_HIP;
-            if (rc == QBE_OK) rc = launch_step(p, sp, arena, G, 0, st, e, w);
-            if (rc == QBE_OK && hipEventRecord(e1, st) != hipSuccess) rc = QBE_ERR_HIP;
-            if (rc == QBE_OK && hipEventSynchronize(e1) != hipSuccess) rc = QBE_ERR_HIP;
-            float ms = 0.f;
-            if (rc == QBE_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = QBE_ERR_HIP;
-            if (rep > 0) total += ms;  // first run warms caches and code
-          }
+          time_config(sp, e, w, total);
           if (rc != QBE_OK) break;
           if (total < best) {
             best = total;
@@ -1818,6 +1843,11 @@ int dev_autotune(Plan& p, void* stream, void* ws, size_t ws_bytes, int64_t min_e
         }
       sp.ept = be;
       sp.wg_per_cu = bw;
+      if (both && mfma_ms <= best) {
+        sp.mmk = 1;
+        sp.ept = 1;
+        sp.wg_per_cu = mfma_w;
+      }
     } else {
       // launch-bound: the first configuration is as good as any
       rc = launch_step(p, sp, arena, G, 0, st);

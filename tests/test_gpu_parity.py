@@ -105,8 +105,17 @@ def test_7x7_d24_sampled_slices_and_full_amplitude(qbe, ctx):
     total = qbe.qbe_contract(ctx, plan, ws_all)
     assert rel(total, complex(*gold["oracle"])) <= TOL
     _say("case 7x7 autotuned")
-    plan.autotune(ws_all)  # tile shapes change, the arithmetic per entry does not
-    assert qbe.qbe_contract(ctx, plan, ws_all) == total
+    n_mfma = st["n_mfma_steps"]
+    plan.autotune(ws_all)
+    tuned = qbe.qbe_contract(ctx, plan, ws_all)
+    assert rel(tuned, complex(*gold["oracle"])) <= TOL
+    if plan.stats()["n_mfma_steps"] == n_mfma:
+        # tile shapes changed, the arithmetic per entry did not
+        assert tuned == total
+    else:
+        # merged launches moved between the MFMA and the VALU kernels (both
+        # FP32 products, other rounding order of the sums)
+        _say(f"  {n_mfma - plan.stats()['n_mfma_steps']} merged launches moved to the VALU kernels")
 
 
 @pytest.mark.parametrize("seed", range(6))
