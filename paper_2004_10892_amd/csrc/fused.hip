@@ -231,9 +231,9 @@ template <bool kBytes>
 __device__ __forceinline__ void level_step(gu32p prog, const u32x4& t, const u32x4& tn, const Rec& c, Rec& pf,
                                            uint32_t tid) {
   const uint32_t ntz = uni(tn.z);
-  load_rec(prog, rec_word(uni(tn.x), uni(tn.y), ntz & 0xFFFFu, ntz >> 16, tid), pf);
+  load_rec(prog, rec_word(uni(tn.x), uni(tn.y), ntz & 0xFFFFu, (ntz >> 16) & 0xFFu, tid), pf);
   const uint32_t base = uni(t.x), E = uni(t.y), tz = uni(t.z), K = uni(t.w) & 0xFFFFu;
-  const uint32_t R = tz & 0xFFFFu, lgT = tz >> 16;
+  const uint32_t R = tz & 0xFFFFu, lgT = (tz >> 16) & 0xFFu;
   if (split_level(E, lgT) && K <= (uint32_t)kSplitOpsMax) {
     switch (K) {
 #define QBE_SPLIT(KK) \
@@ -289,6 +289,13 @@ __device__ __forceinline__ uint32_t level_exports(const ExportCtx& x, u32x4 t, u
   return next + n;
 }
 
+// The barrier after a level, unless the next level is another part of the
+// same dependency level (flag C of its entry): such parts read only earlier
+// levels' results and write fresh space, so waves run on into the next part.
+__device__ __forceinline__ void level_sync(const u32x4& t) {
+  if (!((uni(t.z) >> 24) & kLevelCont)) __syncthreads();
+}
+
 template <bool kBytes>
 __device__ __forceinline__ uint32_t run_levels(gu32p prog, const __attribute__((address_space(3))) u32x4* lv,
                                                uint32_t n_levels, u32x4 t0, u32x4 t1, Rec& ra, Rec& rb,
@@ -300,17 +307,17 @@ __device__ __forceinline__ uint32_t run_levels(gu32p prog, const __attribute__((
     const u32x4 t3 = lv[l + 3];
     xn = level_exports(xc, t0, xn, tid);
     level_step<kBytes>(prog, t0, t2, ra, rc, tid);
-    __syncthreads();
+    level_sync(t0);
     if (l + 1 >= n_levels) break;
     const u32x4 t4 = lv[l + 4];
     xn = level_exports(xc, t1, xn, tid);
     level_step<kBytes>(prog, t1, t3, rb, ra, tid);
-    __syncthreads();
+    level_sync(t1);
     if (l + 2 >= n_levels) break;
     const u32x4 t5 = lv[l + 5];
     xn = level_exports(xc, t2, xn, tid);
     level_step<kBytes>(prog, t2, t4, rc, rb, tid);
-    __syncthreads();
+    level_sync(t2);
     t0 = t3;
     t1 = t4;
     t2 = t5;
@@ -414,8 +421,8 @@ __global__ __launch_bounds__(kFusedBlock) __attribute__((amdgpu_waves_per_eu(kFu
     typedef __attribute__((address_space(3))) u32x4* lds_u32x4p;
     const lds_u32x4p lv = (lds_u32x4p)(size_t)mt.lds_tab;  // the LDS copy
     Rec ra, rb;
-    load_rec(prog, rec_word(uni(t0.x), uni(t0.y), uni(t0.z) & 0xFFFFu, uni(t0.z) >> 16, tid), ra);
-    load_rec(prog, rec_word(uni(t1.x), uni(t1.y), uni(t1.z) & 0xFFFFu, uni(t1.z) >> 16, tid), rb);
+    load_rec(prog, rec_word(uni(t0.x), uni(t0.y), uni(t0.z) & 0xFFFFu, (uni(t0.z) >> 16) & 0xFFu, tid), ra);
+    load_rec(prog, rec_word(uni(t1.x), uni(t1.y), uni(t1.z) & 0xFFFFu, (uni(t1.z) >> 16) & 0xFFu, tid), rb);
     // inputs of this slice into LDS after the constants 1 and 0
     const uint32_t inv = mt.inv, dep = mt.dep;
     const float2* dsrc = prep + mt.dep_src + slice * (int64_t)dep;

@@ -37,10 +37,13 @@ constexpr int64_t kInKernelReduceMax = 8192;
 // Program words:
 //   header[kHdr]
 //   levels[4 * (n_levels + kFusedLevelPad)]
-//                               (record base, entries E, R | lgT << 16,
-//                               factors K | X << 16), then zero entries; R =
-//                               rows of a term record, T = 2^lgT terms per
-//                               entry, X = export rows copied as the level
+//                               (record base, entries E, R | lgT << 16 |
+//                               C << 24, factors K | X << 16), then zero
+//                               entries; R = rows of a term record, T =
+//                               2^lgT terms per entry, C = kLevelCont when
+//                               the next level is another part of the same
+//                               dependency level (no barrier between the
+//                               two), X = export rows copied as the level
 //                               starts (the results of earlier levels)
 //   exports[4 * n_exports]      a segment program's results for other
 //                               launches: (LDS element, rank, arena offset
@@ -65,6 +68,11 @@ constexpr int64_t kInKernelReduceMax = 8192;
 //                               4 * kFusedTailRows zero words (the executor
 //                               reads kFusedTailRows rows at any record)
 constexpr int kFusedTailRows = 2;
+// C of a level entry: the next level reads nothing this one writes and
+// writes nothing this one reads (both parts of one dependency level, whose
+// results take fresh arena space), so the workgroup needs no barrier
+// between them.
+constexpr uint32_t kLevelCont = 1u;
 constexpr int kFusedLevelPad = 3;
 // A level runs in one pass when every lane holds what it computes in the
 // kFusedTailRows rows it read ahead: E x T <= kFusedBlock term records of

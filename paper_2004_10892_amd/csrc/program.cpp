@@ -565,6 +565,9 @@ static FusedCode build_fused(const Plan& p, const std::vector<InputInfo>& in, co
       const uint32_t Tn = 2u << (nd.members.size() - 1);
       for (uint32_t x = 0; x < (1u << r); ++x, ++done) {
         if (done % cap == 0) {
+          // a later part of the level: the part before it runs on without
+          // a barrier (both read earlier levels only and write fresh space)
+          if (done > 0) prog[lvl_at + 4 * (tab - 1) + 2] |= kLevelCont << 24;
           prog[lvl_at + 4 * tab + 0] = (uint32_t)prog.size();
           prog[lvl_at + 4 * tab + 1] = (uint32_t)std::min(cap, E - done);
           prog[lvl_at + 4 * tab + 2] = R | ((uint32_t)__builtin_ctz(T) << 16);

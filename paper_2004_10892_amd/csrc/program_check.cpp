@@ -60,10 +60,21 @@ static std::string check_fused_program(const std::vector<uint32_t>& w, int64_t l
   // results may take the space of inputs their level no longer needs
   const uint32_t arena_lo = kFusedConsts * unit, data_hi = data * unit;
   if (data_hi > 65536) return "fused offsets above 16 bits";
+  // levels the executor runs without a barrier between them (flag C): the
+  // group's reads (its operands and the export rows it copies) and writes
+  // (its results) must be disjoint, and each result written once
+  std::vector<char> wrote(data, 0);
+  std::vector<uint32_t> g_reads, g_writes;
+  bool cont_prev = false;
   for (uint32_t l = 0; l < nl; ++l) {
-    const uint32_t base = lv[4 * l], E = lv[4 * l + 1], R = lv[4 * l + 2] & 0xFFFFu, lgT = lv[4 * l + 2] >> 16,
-                   K = lv[4 * l + 3] & 0xFFFFu, X = lv[4 * l + 3] >> 16;
+    const uint32_t base = lv[4 * l], E = lv[4 * l + 1], R = lv[4 * l + 2] & 0xFFFFu,
+                   lgT = (lv[4 * l + 2] >> 16) & 0xFFu, C = lv[4 * l + 2] >> 24, K = lv[4 * l + 3] & 0xFFFFu,
+                   X = lv[4 * l + 3] >> 16;
     if (base != expect_base) return fail("fused record base", base, expect_base);
+    if (C > kLevelCont || (C && l + 1 == nl)) return "fused level continuation flag";
+    if (cont_prev && X) return "fused level copies export rows without a barrier before it";
+    for (int64_t e = x_copied; e < x_copied + X && e < nx; ++e)
+      for (uint32_t i = 0; i < (1u << xr[4 * e + 1]); ++i) g_reads.push_back(xr[4 * e] + i);
     x_copied += X;
     if (x_copied > nx) return "fused level copies more export rows than the program holds";
     if (base % 4 || R != (1 + K + 7) / 8 || E == 0 || K == 0 || lgT < 1 || lgT > 3) return "fused level shape";
@@ -77,6 +88,7 @@ static std::string check_fused_program(const std::vector<uint32_t>& w, int64_t l
         if (t == 0) {
           const uint32_t out = hw(0);
           if (out % unit || out < arena_lo || out >= data_hi) return "fused result outside the arena";
+          g_writes.push_back(out / unit);
         } else if (hw(0) != 0) {
           return "fused term's result slot not zero";
         }
@@ -84,9 +96,22 @@ static std::string check_fused_program(const std::vector<uint32_t>& w, int64_t l
           const uint32_t v = hw(j);
           if (v % unit || v >= data_hi) return "fused operand outside LDS data";
           if (j > K && v != 0) return "fused padding slot not the constant";
+          if (j <= K) g_reads.push_back(v / unit);
         }
       }
     expect_base += (int64_t)E * T * 4 * R;
+    cont_prev = C != 0;
+    if (!cont_prev) {
+      for (uint32_t v : g_writes) {
+        if (wrote[v]) return "fused result written twice between barriers";
+        wrote[v] = 1;
+      }
+      for (uint32_t v : g_reads)
+        if (v < data && wrote[v]) return "fused level reads a result written without a barrier between";
+      for (uint32_t v : g_writes) wrote[v] = 0;
+      g_reads.clear();
+      g_writes.clear();
+    }
   }
   if (expect_base != so) return "fused scalar list offset";
   (void)x_copied;  // the rest of the rows are copied after the last level
