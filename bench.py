@@ -502,9 +502,10 @@ def bench_headline(torch, qbe, ctx, steps, warmup, net, n_timed=6):
     plan, ws = forms[chosen]["_plan"], forms[chosen]["_ws"]
     st = plan.stats()
     prof = launch_profile(plan, ws, max(3, steps // 4))
-    # plain FP32 form: tree-trimming's sliced set, one launch per bucket
+    # plain FP32 form: tree-trimming's sliced set, one launch per bucket,
+    # every input tensor a factor of its own
     mu_t, pi_t, _ = cands["min_fill+tt"]
-    plan_p = qbe.Plan(qm, pi_t, mu_t, ctx=ctx, exec="per_step", merge=False)
+    plan_p = qbe.Plan(qm, pi_t, mu_t, ctx=ctx, exec="per_step", merge=False, fold_inputs=False)
     ws_p = plan_p.workspace()
     out_p = torch.zeros(2, dtype=torch.float64, device="cuda")
     wall_p, ev_p = timed(torch, lambda: qbe.qbe_contract_async(ctx, plan_p, ws_p, out_p), max(2, steps // 4), 1)
@@ -515,7 +516,7 @@ def bench_headline(torch, qbe, ctx, steps, warmup, net, n_timed=6):
              "launches_per_amplitude": plan_p.stats()["n_launches"] + 2}
     del ws_p, plan_p
     # the same for the chosen plan's schedule: what the executor alone gains
-    plan_q = qbe.Plan(qm, pi, mu, ctx=ctx, exec="per_step", merge=False)
+    plan_q = qbe.Plan(qm, pi, mu, ctx=ctx, exec="per_step", merge=False, fold_inputs=False)
     ws_q = plan_q.workspace()
     out_q = torch.zeros(2, dtype=torch.float64, device="cuda")
     _, ev_q = timed(torch, lambda: qbe.qbe_contract_async(ctx, plan_q, ws_q, out_q), max(2, steps // 4), 1)
@@ -655,7 +656,7 @@ def bench_batch(torch, qbe, ctx, steps):
         qm = qbe.Model.from_circuitgen(circuit_model(random_grid_circuit(r, c, d, seed)))
         _, mu, pi, _ = qbe.plan_circuit(qm, m=m)
         plans_b.append(qbe.Plan(qm, pi, mu, ctx=ctx))
-        plans_p.append(qbe.Plan(qm, pi, mu, ctx=ctx, exec="per_step", merge=False))
+        plans_p.append(qbe.Plan(qm, pi, mu, ctx=ctx, exec="per_step", merge=False, fold_inputs=False))
     plan_ms = (time.perf_counter() - t0) * 1e3
     batch = qbe.Batch(ctx, plans_b)
     ws = batch.workspace()
@@ -896,7 +897,7 @@ def main():
         plain = args.pmc_c3 == "plain_fp32"
         plan = qbe.Plan(qm, pi, mu, ctx=ctx, exec="per_step", precision="fp32" if plain else args.pmc_c3,
                         merge=not plain, fused_prefix=use_prefix and not plain,
-                        fused_segments=use_segments and not plain)
+                        fused_segments=use_segments and not plain, fold_inputs=not plain)
         ws = plan.workspace()
         out = torch.zeros(2, dtype=torch.float64, device="cuda")
         if not plain:

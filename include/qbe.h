@@ -125,7 +125,15 @@ typedef struct qbe_plan_opts {
                           its top bucket's result there; a run that does
                           not fit LDS stays per-step launches.  0: none
                           (default)                                         */
-  int32_t reserved[2]; /* must be zero                                       */
+  int32_t no_fold;     /* 0 (default): the input tensors of a bucket (two or
+                          more, over at most 6 variables together) are
+                          multiplied into one tensor once per plan, in
+                          complex128, so that each entry of the bucket
+                          multiplies fewer factors (Eq. 2's product,
+                          regrouped); 1: every input tensor stays a factor
+                          of its own.  The plan's schedule dump and cost
+                          model are the caller's model's either way.       */
+  int32_t reserved[1]; /* must be zero                                       */
 } qbe_plan_opts;
 
 typedef struct qbe_stats {

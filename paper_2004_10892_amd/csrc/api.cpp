@@ -686,12 +686,28 @@ int qbe_plan_create(qbe_ctx* ctx, const qbe_model* model, const int32_t* reduced
   QBE_REQUIRE(o.fused_prefix >= 0 && o.fused_prefix <= 14, "fused_prefix must be in [0, 14]");
   QBE_REQUIRE(o.fused_segments == 0 || o.fused_segments == 1, "fused_segments must be 0 or 1");
   QBE_REQUIRE(o.fused_segments == 0 || o.fused_prefix > 0, "fused_segments needs fused_prefix > 0");
+  QBE_REQUIRE(o.no_fold == 0 || o.no_fold == 1, "no_fold must be 0 or 1");
   auto* pl = new qbe_plan;
   std::unique_ptr<qbe_plan> guard(pl);
   qbe::Plan& p = pl->p;
-  p.model = model->m;
-  p.sched = qbe::build_schedule(p.model.n_vars, p.model.tvars, vec(reduced_order, n), vec(mu, m));
-  p.cost = qbe::schedule_cost(p.sched);
+  const std::vector<int> order = vec(reduced_order, n), mus = vec(mu, m);
+  p.src_tvars = model->m.tvars;
+  p.src_sched = qbe::build_schedule(model->m.n_vars, model->m.tvars, order, mus);
+  p.cost = qbe::schedule_cost(p.src_sched);
+  if (o.no_fold == 0) p.fold = qbe::fold_groups(model->m, p.src_sched);
+  if (!p.fold.empty() && p.fold.size() < model->m.tvars.size()) {
+    p.model = qbe::fold_model(model->m, p.fold);
+    p.sched = qbe::build_schedule(p.model.n_vars, p.model.tvars, order, mus);
+    // the same buckets: a folded tensor lies in its members' bucket
+    QBE_REQUIRE(p.sched.steps.size() == p.src_sched.steps.size(), "internal: folding changed the buckets");
+    for (size_t k = 0; k < p.sched.steps.size(); ++k)
+      QBE_REQUIRE(p.sched.steps[k].var == p.src_sched.steps[k].var && p.sched.steps[k].uni == p.src_sched.steps[k].uni,
+                  "internal: folding changed the buckets");
+  } else {
+    p.fold.clear();
+    p.model = model->m;
+    p.sched = p.src_sched;
+  }
   p.precision = o.precision;
   p.merge = o.no_merge == 0;
   p.want_prefix = o.exec != QBE_EXEC_FUSED ? o.fused_prefix : 0;
@@ -750,12 +766,12 @@ int qbe_plan_clone(const qbe_plan* src, const qbe_model* model, qbe_plan** out) 
   QBE_GUARD_BEGIN
   QBE_REQUIRE(src && model && out, "NULL argument");
   *out = nullptr;
-  QBE_REQUIRE(model->m.tvars == src->p.model.tvars, "model structure differs from the plan's");
+  QBE_REQUIRE(model->m.tvars == src->p.src_tvars, "model structure differs from the plan's");
   auto* pl = new qbe_plan;
   std::unique_ptr<qbe_plan> guard(pl);
   qbe::Plan& p = pl->p;
   p = src->p;  // host side: schedule, programs, layouts, tile shapes
-  p.model = model->m;
+  p.model = p.fold.empty() ? model->m : qbe::fold_model(model->m, p.fold);
   qbe::dev_forget_plan(p);  // the copied device pointers stay src's
   if (src->ctx) {
     int rc = qbe::dev_set(p.device);
@@ -775,8 +791,8 @@ int qbe_plan_clone(const qbe_plan* src, const qbe_model* model, qbe_plan** out) 
 int qbe_plan_update_data(qbe_plan* plan, const qbe_model* model) {
   QBE_GUARD_BEGIN
   QBE_REQUIRE(plan && model, "NULL argument");
-  QBE_REQUIRE(model->m.tvars == plan->p.model.tvars, "model structure differs from the plan's");
-  plan->p.model.data = model->m.data;
+  QBE_REQUIRE(model->m.tvars == plan->p.src_tvars, "model structure differs from the plan's");
+  plan->p.model.data = plan->p.fold.empty() ? model->m.data : qbe::fold_model(model->m, plan->p.fold).data;
   if (plan->ctx) {
     int rc = qbe::dev_set(plan->p.device);
     if (rc) return rc;
@@ -792,7 +808,7 @@ int qbe_plan_stats(const qbe_plan* plan, qbe_stats* out) {
   const qbe::Plan& p = plan->p;
   std::memset(out, 0, sizeof(*out));
   out->n_vars = p.model.n_vars;
-  out->n_tensors = (int32_t)p.model.tvars.size();
+  out->n_tensors = (int32_t)p.src_tvars.size();
   out->m = p.m;
   out->width = p.cost.width;
   out->n_steps = (int32_t)p.sched.steps.size();
@@ -825,7 +841,7 @@ int qbe_plan_stats(const qbe_plan* plan, qbe_stats* out) {
 int qbe_plan_dump(const qbe_plan* plan, char* buf, size_t cap, size_t* len_out) {
   QBE_GUARD_BEGIN
   QBE_REQUIRE(plan && len_out, "NULL argument");
-  std::string s = qbe::dump_schedule(plan->p.sched);
+  std::string s = qbe::dump_schedule(plan->p.src_sched);
   *len_out = s.size();
   if (buf && cap) {
     size_t n = std::min(cap, s.size() + 1);

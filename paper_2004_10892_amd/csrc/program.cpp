@@ -670,6 +670,64 @@ static FusedCode build_fused(const Plan& p, const std::vector<InputInfo>& in, co
   return out;
 }
 
+std::vector<std::vector<int>> fold_groups(const Model& m, const Schedule& s) {
+  const int nt = (int)m.tvars.size();
+  std::vector<int> group_of(nt, -1);
+  std::vector<std::vector<int>> groups;
+  for (const Step& st : s.steps) {
+    std::vector<int> ids, vars;
+    for (const Operand& op : st.ops)
+      if (op.kind == 't') {
+        ids.push_back(op.id);
+        for (int v : m.tvars[op.id])
+          if (std::find(vars.begin(), vars.end(), v) == vars.end()) vars.push_back(v);
+      }
+    if (ids.size() < 2 || (int)vars.size() > kFoldMaxVars) continue;
+    std::sort(ids.begin(), ids.end());
+    for (int t : ids) group_of[t] = (int)groups.size();
+    groups.push_back(ids);
+  }
+  // the compiled tensors in the caller's order, a group where its first
+  // member was
+  std::vector<std::vector<int>> out;
+  for (int t = 0; t < nt; ++t) {
+    if (group_of[t] < 0)
+      out.push_back({t});
+    else if (groups[group_of[t]][0] == t)
+      out.push_back(groups[group_of[t]]);
+  }
+  return out;
+}
+
+Model fold_model(const Model& m, const std::vector<std::vector<int>>& groups) {
+  Model f;
+  f.n_vars = m.n_vars;
+  for (const std::vector<int>& g : groups) {
+    std::vector<int> vars;
+    for (int t : g)
+      for (int v : m.tvars[t])
+        if (std::find(vars.begin(), vars.end(), v) == vars.end()) vars.push_back(v);
+    const int r = (int)vars.size();
+    f.data_off.push_back((int64_t)f.data.size() / 2);
+    f.tvars.push_back(vars);
+    std::vector<int> val(m.n_vars, 0);
+    for (int64_t y = 0; y < (int64_t(1) << r); ++y) {
+      for (int j = 0; j < r; ++j) val[vars[j]] = (int)((y >> (r - 1 - j)) & 1);
+      double re = 1.0, im = 0.0;
+      for (int t : g) {
+        const int64_t e = raw_index(m, t, [&](int v) { return val[v]; });
+        const double a = m.data[2 * e], b = m.data[2 * e + 1];
+        const double nr = re * a - im * b;
+        im = re * b + im * a;
+        re = nr;
+      }
+      f.data.push_back(re);
+      f.data.push_back(im);
+    }
+  }
+  return f;
+}
+
 void compile_plan(Plan& p) {
   const Model& md = p.model;
   const Schedule& s = p.sched;

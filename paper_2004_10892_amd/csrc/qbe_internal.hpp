@@ -129,9 +129,14 @@ struct WideItem {
 };
 
 struct Plan {
-  // host side
+  // host side: the model and schedule the programs are compiled from --
+  // the caller's, or (input folding) one whose tensors are products of the
+  // caller's -- and the caller's schedule, whose cost model the plan reports
   Model model;
   Schedule sched;
+  Schedule src_sched;
+  std::vector<std::vector<int>> src_tvars;  // the caller's model structure
+  std::vector<std::vector<int>> fold;       // compiled tensor -> caller's tensors
   ScheduleCost cost;
   int m = 0;
   int64_t n_slices = 1;
@@ -244,6 +249,17 @@ int gnn_train_step(Gnn& g, void* stream, int head, int n, const int* rp, const i
                    int nc, const int* cand, const float* y, float lr, float* loss_out, float* grads_out);
 
 // Plan compilation (program.cpp).
+// Input folding: the input tensors of a bucket multiplied into one tensor
+// over the union of their variables (at most kFoldMaxVars of them), so that
+// an entry of the bucket multiplies fewer factors.  The product is the same
+// (Eq. 2 multiplies all of a bucket's tensors), formed once per plan in
+// complex128.  fold_groups lists the compiled model's tensors as groups of
+// the caller's (singletons for tensors left as they are); fold_model builds
+// that model's structure and data.
+constexpr int kFoldMaxVars = 6;
+std::vector<std::vector<int>> fold_groups(const Model& m, const Schedule& s);
+Model fold_model(const Model& m, const std::vector<std::vector<int>>& groups);
+
 void compile_plan(Plan& p);
 
 // Device entry points (device.hip).  All return 0 or a QBE_ERR_* code and

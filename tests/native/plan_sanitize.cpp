@@ -3,9 +3,16 @@
 // (sliced set and reduced order), builds the schedule, compiles the device
 // programs in the one-launch-per-bucket form, the merged form, and the
 // merged form with a fused prefix (automatic and fixed rank bounds) and
-// fused segments, and runs the host bounds check of every program.  Prints "ok" and exits 0, or prints
+// fused segments, each with and without input folding, and runs the host
+// bounds check of every program.  The folded model is checked against its
+// definition: its tensors partition the caller's, each group is the input
+// tensors of one bucket, and every entry is the product of the members'
+// entries (worked out here from the variable lists, on seeded data).
+// Prints "ok" and exits 0, or prints
 // the failure and exits 1.  Input: n_vars n_tensors, then per tensor its
 // rank and variables, then the order (count, ids) and mu (count, ids).
+#include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <fstream>
 #include <string>
@@ -34,7 +41,12 @@ int main(int argc, char** argv) {
     md.data_off.push_back(off);
     off += int64_t(1) << r;
   }
-  md.data.assign(2 * off, 0.0);
+  md.data.resize(2 * off);
+  uint64_t lcg = 12345;
+  for (double& d : md.data) {
+    lcg = lcg * 6364136223846793005ull + 1442695040888963407ull;
+    d = (double)(lcg >> 11) / 9007199254740992.0 - 0.5;
+  }
   int n = 0, m = 0;
   f >> n;
   std::vector<int> order(n);
@@ -46,10 +58,62 @@ int main(int argc, char** argv) {
   try {
     // (merge, fused prefix, fused segments)
     const int forms[][3] = {{0, 0, 0}, {1, 0, 0}, {1, 1, 0}, {1, 1, 1}, {1, 6, 1}, {1, 4, 0}};
+    const qbe::Schedule s0 = qbe::build_schedule(nv, md.tvars, order, mu);
+    const std::vector<std::vector<int>> groups = qbe::fold_groups(md, s0);
+    const qbe::Model fm = qbe::fold_model(md, groups);
+    {
+      std::vector<int> seen(nt, 0);
+      for (const auto& g : groups)
+        for (int t : g) ++seen[t];
+      for (int t = 0; t < nt; ++t)
+        if (seen[t] != 1) {
+          std::printf("fold: tensor %d in %d groups\n", t, seen[t]);
+          return 1;
+        }
+      for (size_t j = 0; j < groups.size(); ++j) {
+        const auto& g = groups[j];
+        if (g.size() < 2) continue;
+        bool one_bucket = false;
+        for (const auto& st : s0.steps) {
+          std::vector<int> ids;
+          for (const auto& op : st.ops)
+            if (op.kind == 't') ids.push_back(op.id);
+          std::sort(ids.begin(), ids.end());
+          if (ids == g) one_bucket = true;
+        }
+        if (!one_bucket) {
+          std::printf("fold: group %zu is not one bucket's inputs\n", j);
+          return 1;
+        }
+        const auto& vars = fm.tvars[j];
+        if ((int)vars.size() > qbe::kFoldMaxVars) return 1;
+        for (int64_t y = 0; y < (int64_t(1) << vars.size()); ++y) {
+          double re = 1.0, im = 0.0;
+          for (int t : g) {
+            int64_t e = 0;
+            for (int v : md.tvars[t]) {
+              const size_t q = std::find(vars.begin(), vars.end(), v) - vars.begin();
+              e = 2 * e + ((y >> (vars.size() - 1 - q)) & 1);
+            }
+            const double a = md.data[2 * (md.data_off[t] + e)], b = md.data[2 * (md.data_off[t] + e) + 1];
+            const double nr = re * a - im * b;
+            im = re * b + im * a;
+            re = nr;
+          }
+          const int64_t at = 2 * (fm.data_off[j] + y);
+          if (std::abs(fm.data[at] - re) > 1e-14 || std::abs(fm.data[at + 1] - im) > 1e-14) {
+            std::printf("fold: group %zu entry %lld\n", j, (long long)y);
+            return 1;
+          }
+        }
+      }
+    }
+    for (int folded = 0; folded < 2; ++folded)
     for (const auto& form : forms) {
       qbe::Plan p;
-      p.model = md;
-      p.sched = qbe::build_schedule(nv, md.tvars, order, mu);
+      p.model = folded ? fm : md;
+      p.sched = qbe::build_schedule(nv, p.model.tvars, order, mu);
+      if (p.sched.steps.size() != s0.steps.size()) return 1;
       p.cost = qbe::schedule_cost(p.sched);
       p.merge = form[0] != 0;
       p.want_prefix = form[1];
