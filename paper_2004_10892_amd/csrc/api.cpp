@@ -708,6 +708,7 @@ int qbe_plan_create(qbe_ctx* ctx, const qbe_model* model, const int32_t* reduced
     p.model = model->m;
     p.sched = p.src_sched;
   }
+  if (o.no_fold == 0) (void)qbe::push_inputs(p.sched);
   p.precision = o.precision;
   p.merge = o.no_merge == 0;
   p.want_prefix = o.exec != QBE_EXEC_FUSED ? o.fused_prefix : 0;

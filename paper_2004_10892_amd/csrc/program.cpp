@@ -14,6 +14,7 @@
 //  * Intermediates live in an arena laid out by simulating the schedule
 //    (first fit; per-slice units scaled by the slice-group size).
 #include <algorithm>
+#include <cstdint>
 #include <map>
 #include <stdexcept>
 
@@ -726,6 +727,43 @@ Model fold_model(const Model& m, const std::vector<std::vector<int>>& groups) {
     }
   }
   return f;
+}
+
+int push_inputs(Schedule& s) {
+  int moves = 0;
+  for (int k = (int)s.steps.size() - 1; k >= 0; --k) {
+    Step& st = s.steps[k];
+    for (size_t i = 0; i < st.ops.size();) {
+      const Operand op = st.ops[i];
+      if (op.kind != 't') {
+        ++i;
+        continue;
+      }
+      int to = -1;
+      size_t best = SIZE_MAX;
+      for (const Operand& r : st.ops) {
+        if (r.kind != 'r' || r.vars.size() >= best) continue;
+        bool inside = true;
+        for (int v : op.vars) inside = inside && std::find(r.vars.begin(), r.vars.end(), v) != r.vars.end();
+        if (inside) {
+          best = r.vars.size();
+          to = r.id;
+        }
+      }
+      if (to < 0 || best + 2 > st.uni.size()) {
+        ++i;
+        continue;
+      }
+      st.ops.erase(st.ops.begin() + (long)i);
+      // inputs by tensor id, then intermediates
+      std::vector<Operand>& dst = s.steps[to].ops;
+      size_t at = 0;
+      while (at < dst.size() && dst[at].kind == 't' && dst[at].id < op.id) ++at;
+      dst.insert(dst.begin() + (long)at, op);
+      ++moves;
+    }
+  }
+  return moves;
 }
 
 void compile_plan(Plan& p) {

@@ -259,6 +259,14 @@ int gnn_train_step(Gnn& g, void* stream, int head, int n, const int* rp, const i
 constexpr int kFoldMaxVars = 6;
 std::vector<std::vector<int>> fold_groups(const Model& m, const Schedule& s);
 Model fold_model(const Model& m, const std::vector<std::vector<int>>& groups);
+// Then an input factor of bucket k whose variables all lie in a result
+// operand R of k (R's producer j has them all in its result) moves into
+// bucket j when R has at least two variables fewer than U_k: j multiplies
+// it into each of its 2^(|R| + 1) terms (it is constant in j's summed
+// variable, so it passes the sum unchanged) instead of k into each of its
+// 2^|U_k|.  Steps are visited from the last, so a factor moves on down
+// while that holds.  Returns the number of moves.
+int push_inputs(Schedule& s);
 
 void compile_plan(Plan& p);
 

@@ -3,7 +3,8 @@
 // (sliced set and reduced order), builds the schedule, compiles the device
 // programs in the one-launch-per-bucket form, the merged form, and the
 // merged form with a fused prefix (automatic and fixed rank bounds) and
-// fused segments, each with and without input folding, and runs the host
+// fused segments, each with and without input folding (and the moves of
+// input factors into producer buckets), and runs the host
 // bounds check of every program.  The folded model is checked against its
 // definition: its tensors partition the caller's, each group is the input
 // tensors of one bucket, and every entry is the product of the members'
@@ -114,6 +115,35 @@ int main(int argc, char** argv) {
       p.model = folded ? fm : md;
       p.sched = qbe::build_schedule(nv, p.model.tvars, order, mu);
       if (p.sched.steps.size() != s0.steps.size()) return 1;
+      if (folded) {
+        (void)qbe::push_inputs(p.sched);
+        // every input is a factor of one bucket, and a moved one is
+        // constant in that bucket's summed variable
+        std::vector<int> uses(p.model.tvars.size(), 0);
+        for (int t : p.sched.scalar_inputs) ++uses[t];
+        for (const auto& st : p.sched.steps)
+          for (const auto& op : st.ops) {
+            for (int v : op.vars)
+              if (std::find(st.uni.begin(), st.uni.end(), v) == st.uni.end()) {
+                std::printf("push: operand variable outside its bucket\n");
+                return 1;
+              }
+            if (op.kind != 't') continue;
+            ++uses[op.id];
+            const bool holds_u = std::find(op.vars.begin(), op.vars.end(), st.var) != op.vars.end();
+            if (!holds_u)
+              for (int v : op.vars)
+                if (std::find(st.out.begin(), st.out.end(), v) == st.out.end()) {
+                  std::printf("push: moved factor outside the result\n");
+                  return 1;
+                }
+          }
+        for (size_t t = 0; t < uses.size(); ++t)
+          if (uses[t] > 1) {
+            std::printf("push: tensor %zu used %d times\n", t, uses[t]);
+            return 1;
+          }
+      }
       p.cost = qbe::schedule_cost(p.sched);
       p.merge = form[0] != 0;
       p.want_prefix = form[1];
