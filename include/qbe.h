@@ -106,8 +106,10 @@ typedef struct qbe_plan_opts {
                           whatever the plan's precision) before its
                           per-step launches, which read the results it
                           writes to the workspace.  1: R is the largest of
-                          14 .. 4 whose prefix lets two workgroups share a
-                          compute unit's LDS, else the largest of 10, 8,
+                          14 .. 4 whose prefix -- and with fused_segments
+                          its later segments too -- lets two workgroups
+                          share a compute unit's LDS, else the largest
+                          whose prefix does, else the largest of 10, 8,
                           6, 4 that fits at all; 2..14: R = fused_prefix.
                           Needs merging (no_merge 0) and at most 24 sliced
                           variables; a plan with no such prefix (fewer

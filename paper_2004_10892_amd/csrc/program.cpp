@@ -435,24 +435,21 @@ static FusedCode build_fused(const Plan& p, const std::vector<InputInfo>& in, co
       if (incl[k])
         for (const auto& op : s.steps[k].ops)
           if (op.kind == 't') used[op.id] = 1;
-  // LDS element offsets (after the constants 1 and 0): one arena holds the
-  // inputs -- its first allocations, contiguous, slice-invariant ones first,
-  // as the executor copies them in -- and the results.  A node reads each of
-  // its inputs only, so an input's space is reused once its node has run.
-  Arena la;
+  // LDS element offsets (after the constants 1 and 0): the inputs first,
+  // one contiguous block, slice-invariant ones first, as the executor copies
+  // them in
   std::vector<int64_t> lds_in(nt, -1);
   int64_t inv = 0, dep = 0;
   for (int t = 0; t < nt; ++t)
     if (used[t] && in[t].smask == 0) {
-      lds_in[t] = kFusedConsts + la.alloc(int64_t(1) << in[t].canon.size(), 1);
+      lds_in[t] = kFusedConsts + inv;
       inv += int64_t(1) << in[t].canon.size();
     }
   for (int t = 0; t < nt; ++t)
     if (used[t] && in[t].smask != 0) {
-      lds_in[t] = kFusedConsts + la.alloc(int64_t(1) << in[t].canon.size(), 1);
+      lds_in[t] = kFusedConsts + inv + dep;
       dep += int64_t(1) << in[t].canon.size();
     }
-  if (la.top != inv + dep) throw std::logic_error("fused input block not contiguous");
   // merged nodes (each writes its root bucket's result) and their levels
   const std::vector<FusedNode> nodes = merge_buckets(s, p.merge, incl);
   int f_levels = 0;
@@ -474,40 +471,69 @@ static FusedCode build_fused(const Plan& p, const std::vector<InputInfo>& in, co
         }
       }
   // imports (segment programs): results of excluded buckets that included
-  // ones read, copied in with the inputs, after them
+  // ones read, copied in with the inputs
   std::vector<int64_t> lds_out(nsteps, -1);
   std::vector<int> imp_steps;
   if (export_off)
     for (int k = 0; k < nsteps; ++k)
       if (incl[k])
         for (const auto& op : s.steps[k].ops)
-          if (op.kind == 'r' && !incl[op.id]) {
-            imp_steps.push_back(op.id);
-            lds_out[op.id] = kFusedConsts + la.alloc(int64_t(1) << op.vars.size(), 1);
-          }
-  // results by levels: all results of a level are live while the level
-  // runs; then its nodes' operands (results, inputs and imports) are free;
-  // an exported result stays live through the next level, during which it
-  // is copied out
-  std::vector<int> copying;  // exported results of the previous level
-  for (int l = 0; l < f_levels; ++l) {
-    for (int i : by_level[l]) {
-      const int c = nodes[i].members[0];
-      lds_out[c] = kFusedConsts + la.alloc(int64_t(1) << s.steps[c].out.size(), 1);
+          if (op.kind == 'r' && !incl[op.id]) imp_steps.push_back(op.id);
+  // Lifetimes in levels (-1: before the first, f_levels: after the last):
+  // an input or import lives from the start through the level of the node
+  // that reads it, a result from its node's level through its reader's (an
+  // exported one through the next level, which copies it out; one read at
+  // the end, through f_levels).  A level's results are written while its
+  // operands are still read, so the two lifetimes overlap at that level.
+  std::vector<int> in_to(nt, f_levels), res_to(nsteps, f_levels);
+  for (const FusedNode& nd : nodes) {
+    for (int kid : nd.kids) res_to[kid] = nd.level;
+    for (const Operand& op : nd.factors) {
+      if (op.kind == 't') in_to[op.id] = nd.level;
+      if (op.kind == 'r' && !incl[op.id]) res_to[op.id] = nd.level;
     }
-    for (int i : by_level[l]) {
-      for (int kid : nodes[i].kids) la.release(lds_out[kid] - kFusedConsts, int64_t(1) << s.steps[kid].out.size());
-      for (const Operand& op : nodes[i].factors) {
-        if (op.kind == 't') la.release(lds_in[op.id] - kFusedConsts, int64_t(1) << in[op.id].canon.size());
-        if (op.kind == 'r' && !incl[op.id]) la.release(lds_out[op.id] - kFusedConsts, int64_t(1) << op.vars.size());
-      }
-    }
-    for (int c : copying) la.release(lds_out[c] - kFusedConsts, int64_t(1) << s.steps[c].out.size());
-    copying.clear();
-    for (size_t e = 0; e < exp_steps.size(); ++e)
-      if (exp_level[e] == l) copying.push_back(exp_steps[e]);
   }
-  const int64_t data_elems = kFusedConsts + la.top;
+  for (size_t e = 0; e < exp_steps.size(); ++e) res_to[exp_steps[e]] = std::min(exp_level[e] + 1, f_levels);
+  // Offline placement of imports and results around the fixed input block:
+  // largest first (earlier first on ties), each at the lowest offset that
+  // no item living at the same time uses.
+  struct Span {
+    int64_t off, size;
+    int from, to;
+  };
+  std::vector<Span> placed;
+  for (int t = 0; t < nt; ++t)
+    if (used[t]) placed.push_back({lds_in[t] - kFusedConsts, int64_t(1) << in[t].canon.size(), -1, in_to[t]});
+  struct Want {
+    int64_t size;
+    int from, to, step;
+  };
+  std::vector<Want> want;
+  for (int c : imp_steps) want.push_back({int64_t(1) << s.steps[c].out.size(), -1, res_to[c], c});
+  for (const FusedNode& nd : nodes) {
+    const int c = nd.members[0];
+    want.push_back({int64_t(1) << s.steps[c].out.size(), nd.level, res_to[c], c});
+  }
+  std::stable_sort(want.begin(), want.end(), [](const Want& x, const Want& y) {
+    return x.size != y.size ? x.size > y.size : x.from < y.from;
+  });
+  std::vector<std::pair<int64_t, int64_t>> busy;
+  for (const Want& w : want) {
+    busy.clear();
+    for (const Span& q : placed)
+      if (q.from <= w.to && w.from <= q.to) busy.push_back({q.off, q.off + q.size});
+    std::sort(busy.begin(), busy.end());
+    int64_t at = 0;
+    for (const auto& iv : busy) {
+      if (at + w.size <= iv.first) break;
+      at = std::max(at, iv.second);
+    }
+    placed.push_back({at, w.size, w.from, w.to});
+    lds_out[w.step] = kFusedConsts + at;
+  }
+  int64_t top = inv + dep;
+  for (const Span& q : placed) top = std::max(top, q.off + q.size);
+  const int64_t data_elems = kFusedConsts + top;
   // each level's factors F, terms T and entries E; a prefix program splits
   // its levels into one-pass parts (their records all read ahead), as many
   // slices run it at once and a level's extra record reads would stall them
@@ -841,63 +867,91 @@ void compile_plan(Plan& p) {
   p.segs.clear();
   p.has_prefix = false;
   p.seg_max_rank = -1;
-  if (p.want_prefix > 0 && p.merge && p.m <= 24) {
-    std::vector<std::pair<int, int64_t>> tries;  // (R, LDS cap)
-    if (p.want_prefix == 1) {
-      for (int R = 14; R >= 4; --R) tries.push_back({R, kFusedLdsPair});
-      for (int R : {10, 8, 6, 4}) tries.push_back({R, kFusedLdsMax});
-    } else {
-      tries.push_back({p.want_prefix, kFusedLdsMax});
+  // The prefix for rank bound R (buckets of at most R + 1 variables whose
+  // producers all are such), then with segments wanted every later run of
+  // at least kSegMinBuckets such buckets (connected through their
+  // consumers).  Programs above seg_cap leave their buckets to per-step
+  // launches, or with strict set reject R.  Returns 0 when fewer than two
+  // buckets qualify (no smaller R has more), 1 when built, -1 when R is
+  // rejected.
+  auto try_fused = [&](int R, int64_t cap, int64_t seg_cap, bool strict) -> int {
+    std::vector<FusedCode> codes;
+    std::vector<std::vector<char>> incls;
+    std::vector<char> any(nsteps, 0);
+    std::vector<char> f(nsteps, 0);
+    int cnt = 0;
+    for (int k = 0; k < nsteps; ++k) {  // producers precede their consumers
+      bool ok = (int)s.steps[k].uni.size() <= R + 1;
+      for (const auto& op : s.steps[k].ops)
+        if (op.kind == 'r' && !f[op.id]) ok = false;
+      f[k] = ok;
+      cnt += ok;
     }
-    for (const auto& [R, cap] : tries) {
-      std::vector<char> f(nsteps, 0);
-      int cnt = 0;
-      for (int k = 0; k < nsteps; ++k) {  // producers precede their consumers
-        bool ok = (int)s.steps[k].uni.size() <= R + 1;
-        for (const auto& op : s.steps[k].ops)
-          if (op.kind == 'r' && !f[op.id]) ok = false;
-        f[k] = ok;
-        cnt += ok;
-      }
-      if (cnt < 2) break;
-      std::vector<int64_t> mark(nsteps, -1);
-      for (int k = 0; k < nsteps; ++k)
-        if (f[k] && (s.consumer[k] < 0 || !f[s.consumer[k]])) mark[k] = 0;
-      FusedCode fc = build_fused(p, in, muj, f, &mark, cap);
-      if (!fc.ok) continue;
-      seg_code.push_back(std::move(fc));
-      seg_incl.push_back(f);
-      for (int k = 0; k < nsteps; ++k) fused_any[k] |= f[k];
-      p.has_prefix = true;
-      p.seg_max_rank = R;
-      break;
-    }
-  }
-  if (p.want_segments && p.has_prefix) {
-    const int R = p.seg_max_rank;
-    std::vector<char> small(nsteps, 0);
-    for (int k = 0; k < nsteps; ++k) small[k] = !fused_any[k] && (int)s.steps[k].uni.size() <= R + 1;
-    // the top of each bucket's run (consumers come after their producers)
-    std::vector<int> top(nsteps, -1);
-    for (int k = nsteps - 1; k >= 0; --k)
-      if (small[k]) {
-        const int c = s.consumer[k];
-        top[k] = (c >= 0 && small[c]) ? top[c] : k;
-      }
-    std::vector<int> size(nsteps, 0);
+    if (cnt < 2) return 0;
+    std::vector<int64_t> mark(nsteps, -1);
     for (int k = 0; k < nsteps; ++k)
-      if (small[k]) ++size[top[k]];
-    for (int t = 0; t < nsteps; ++t) {
-      if (!small[t] || top[t] != t || size[t] < kSegMinBuckets) continue;
-      std::vector<char> f(nsteps, 0);
-      for (int k = 0; k < nsteps; ++k) f[k] = small[k] && top[k] == t;
-      std::vector<int64_t> mark(nsteps, -1);
-      mark[t] = 0;
-      FusedCode fc = build_fused(p, in, muj, f, &mark, kFusedLdsMax);
-      if (!fc.ok) continue;  // its buckets stay per-step launches
-      seg_code.push_back(std::move(fc));
-      seg_incl.push_back(f);
-      for (int k = 0; k < nsteps; ++k) fused_any[k] |= f[k];
+      if (f[k] && (s.consumer[k] < 0 || !f[s.consumer[k]])) mark[k] = 0;
+    FusedCode fc = build_fused(p, in, muj, f, &mark, cap);
+    if (!fc.ok) return -1;
+    codes.push_back(std::move(fc));
+    incls.push_back(f);
+    for (int k = 0; k < nsteps; ++k) any[k] |= f[k];
+    if (p.want_segments) {
+      std::vector<char> small(nsteps, 0);
+      for (int k = 0; k < nsteps; ++k) small[k] = !any[k] && (int)s.steps[k].uni.size() <= R + 1;
+      // the top of each bucket's run (consumers come after their producers)
+      std::vector<int> top(nsteps, -1);
+      for (int k = nsteps - 1; k >= 0; --k)
+        if (small[k]) {
+          const int c = s.consumer[k];
+          top[k] = (c >= 0 && small[c]) ? top[c] : k;
+        }
+      std::vector<int> size(nsteps, 0);
+      for (int k = 0; k < nsteps; ++k)
+        if (small[k]) ++size[top[k]];
+      for (int t = 0; t < nsteps; ++t) {
+        if (!small[t] || top[t] != t || size[t] < kSegMinBuckets) continue;
+        std::vector<char> g(nsteps, 0);
+        for (int k = 0; k < nsteps; ++k) g[k] = small[k] && top[k] == t;
+        std::vector<int64_t> mk(nsteps, -1);
+        mk[t] = 0;
+        FusedCode sc = build_fused(p, in, muj, g, &mk, seg_cap);
+        if (!sc.ok) {
+          if (strict) return -1;
+          continue;  // its buckets stay per-step launches
+        }
+        codes.push_back(std::move(sc));
+        incls.push_back(g);
+        for (int k = 0; k < nsteps; ++k) any[k] |= g[k];
+      }
+    }
+    for (size_t j = 0; j < codes.size(); ++j) {
+      seg_code.push_back(std::move(codes[j]));
+      seg_incl.push_back(incls[j]);
+    }
+    fused_any = any;
+    p.has_prefix = true;
+    p.seg_max_rank = R;
+    return 1;
+  };
+  if (p.want_prefix > 0 && p.merge && p.m <= 24) {
+    if (p.want_prefix == 1) {
+      // the largest R whose launches all let two workgroups share a compute
+      // unit's LDS; else the largest whose prefix does (segments up to the
+      // whole LDS); else the largest that fits at all
+      bool done = false;
+      for (int pass = 0; pass < 3 && !done; ++pass)
+        for (int R : pass < 2 ? std::vector<int>{14, 13, 12, 11, 10, 9, 8, 7, 6, 5, 4} : std::vector<int>{10, 8, 6, 4}) {
+          const int64_t cap = pass < 2 ? kFusedLdsPair : kFusedLdsMax;
+          const int rc = try_fused(R, cap, pass == 0 ? kFusedLdsPair : kFusedLdsMax, pass == 0 && p.want_segments);
+          if (rc == 0) break;
+          if (rc == 1) {
+            done = true;
+            break;
+          }
+        }
+    } else {
+      (void)try_fused(p.want_prefix, kFusedLdsMax, kFusedLdsMax, false);
     }
   }
   // each segment's position in schedule order: its last bucket

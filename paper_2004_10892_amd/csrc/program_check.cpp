@@ -17,6 +17,76 @@ std::string fail(const std::string& what, int64_t a, int64_t b) {
 
 }  // namespace
 
+// The data flow of a fused program through LDS, from its records alone.
+// Time steps are the barrier groups (levels joined by continuation flags),
+// 0..G-1, with the input block and the import rows filled at -1 and the
+// export rows left over and the scalar list read at G.  An element is read
+// only after a write (or the fill) at an earlier step; a write never lands
+// at the step of a read of the same element, twice in one step, or over a
+// value not yet read: every value of a contraction (input entry, result
+// entry) is read by its one consumer -- a node or an export row -- at one
+// step, so an overwrite before any read means a value lost.  So no result
+// overwrites an operand that is still to be read, and a barrier group never
+// reads what it writes.
+static std::string check_fused_liveness(const std::vector<uint32_t>& w, uint32_t nl, uint32_t nx, uint32_t ni,
+                                        const uint32_t* xr, uint32_t unit, uint32_t data) {
+  const uint32_t* lv = w.data() + kHdr;
+  const uint32_t inv = w[FH_INV_ELEMS], dep = w[FH_DEP_ELEMS];
+  // per element: the step of its last write (-2: never written), and
+  // whether a read since then forbids a write until a later step
+  std::vector<int> last_w(data, -2), last_r(data, -2);
+  std::vector<char> unread(data, 0);
+  for (uint32_t e = kFusedConsts; e < kFusedConsts + inv + dep; ++e) last_w[e] = -1, unread[e] = 1;
+  for (uint32_t e = nx; e < nx + ni; ++e)
+    for (uint32_t i = 0; i < (1u << xr[4 * e + 1]); ++i) last_w[xr[4 * e] + i] = -1, unread[xr[4 * e] + i] = 1;
+  auto read = [&](uint32_t e, int g) -> bool {
+    if (e < kFusedConsts) return true;  // the constants
+    if (last_w[e] == -2 || last_w[e] >= g) return false;
+    last_r[e] = std::max(last_r[e], g);
+    unread[e] = 0;
+    return true;
+  };
+  auto write = [&](uint32_t e, int g) -> bool {
+    // not over a value read at this step or later, nor twice in one step
+    if (last_r[e] >= g || last_w[e] == g || unread[e]) return false;
+    last_w[e] = g;
+    unread[e] = 1;
+    return true;
+  };
+  int g = 0;
+  int64_t xn = 0;
+  std::vector<uint32_t> writes;
+  for (uint32_t l = 0; l < nl; ++l) {
+    const uint32_t base = lv[4 * l], E = lv[4 * l + 1], R = lv[4 * l + 2] & 0xFFFFu,
+                   lgT = (lv[4 * l + 2] >> 16) & 0xFFu, C = lv[4 * l + 2] >> 24, K = lv[4 * l + 3] & 0xFFFFu,
+                   X = lv[4 * l + 3] >> 16;
+    for (uint32_t e = 0; e < X; ++e, ++xn)
+      for (uint32_t i = 0; i < (1u << xr[4 * xn + 1]); ++i)
+        if (!read(xr[4 * xn] + i, g)) return "fused export row reads an element not written before it";
+    for (uint32_t f = 0; f < E; ++f)
+      for (uint32_t t = 0; t < (1u << lgT); ++t) {
+        const uint32_t* rec = w.data() + base + ((size_t)f * (1u << lgT) + t) * 4 * R;
+        auto hw = [&](uint32_t j) { return (rec[j / 2] >> (16 * (j % 2))) & 0xFFFFu; };
+        for (uint32_t j = 1; j <= K; ++j)
+          if (!read(hw(j) / unit, g)) return "fused operand read before it is written, or after it is overwritten";
+        if (t == 0) writes.push_back(hw(0) / unit);
+      }
+    if (!C) {
+      for (uint32_t e : writes)
+        if (!write(e, g)) return "fused result overwrites a value still to be read";
+      writes.clear();
+      ++g;
+    }
+  }
+  for (; xn < nx; ++xn)
+    for (uint32_t i = 0; i < (1u << xr[4 * xn + 1]); ++i)
+      if (!read(xr[4 * xn] + i, g)) return "fused export row reads an element not written before it";
+  const uint32_t so = w[FH_SCALAR_OFF], nsc = w[FH_SCALARS];
+  for (uint32_t j = 0; j < nsc; ++j)
+    if (!read(w[so + j], g)) return "fused scalar read before it is written";
+  return "";
+}
+
 // A fused program (fused.hip's executor) against the LDS size and prepared
 // input count of its plan; "" if it holds.
 static std::string check_fused_program(const std::vector<uint32_t>& w, int64_t lds_bytes, int64_t elems,
@@ -120,7 +190,7 @@ static std::string check_fused_program(const std::vector<uint32_t>& w, int64_t l
     if (w[j] != 0) return "fused program tail not zero";
   for (uint32_t j = 0; j < nsc; ++j)
     if (w[so + j] >= data) return "fused scalar outside LDS data";
-  return "";
+  return check_fused_liveness(w, nl, nx, ni, xr, unit, data);
 }
 
 std::string check_plan(const Plan& p) {

@@ -100,8 +100,8 @@ def test_later_segments_take_runs_of_small_buckets(c3):
     become one launch each, importing what they read; the byte count of
     the plan is still the sum over its launches, and no bucket is lost."""
     qbe, qm, mu, pi = c3
-    pre = qbe.Plan(qm, pi, mu, exec="per_step", fused_prefix=True)
-    seg = qbe.Plan(qm, pi, mu, exec="per_step", fused_prefix=True, fused_segments=True)
+    pre = qbe.Plan(qm, pi, mu, exec="per_step", fused_prefix=11)
+    seg = qbe.Plan(qm, pi, mu, exec="per_step", fused_prefix=11, fused_segments=True)
     seg.check()
     sp, sq = pre.stats(), seg.stats()
     assert sp["n_fused_segments"] == 1 and sq["n_fused_segments"] >= 2
@@ -118,6 +118,24 @@ def test_later_segments_take_runs_of_small_buckets(c3):
         assert l["n_buckets"] >= 3 and l["n_ops"] >= 1 and l["levels"] > 0 and 0 < l["lds_bytes"] <= 160 * 1024
     assert sum(l["bytes_per_slice"] for l in la[:-2]) == sq["step_bytes_per_slice"]
     assert [l["kind"] for l in la[-2:]] == ["finalize", "reduce"]
+
+
+def test_automatic_bound_with_segments_keeps_every_fused_launch_in_half_the_lds(c3):
+    """With fused segments the automatic bound is the largest R whose prefix
+    and every later run of small buckets fit in half a compute unit's LDS
+    (two workgroups per unit), when some R allows that: its launches all
+    do, and the explicit bound R gives the same launches."""
+    qbe, qm, mu, pi = c3
+    pair = 160 * 1024 // 2 - 16
+    fused = lambda p: [l for l in p.launches() if l["kind"] in ("prefix", "segment")]
+    auto = qbe.Plan(qm, pi, mu, exec="per_step", fused_prefix=True, fused_segments=True)
+    auto.check()
+    la = fused(auto)
+    R = la[0]["out_rank"]
+    assert la[0]["kind"] == "prefix" and all(l["lds_bytes"] <= pair for l in la)
+    assert auto.stats()["fused_buckets"] == sum(l["n_buckets"] for l in la)
+    same = qbe.Plan(qm, pi, mu, exec="per_step", fused_prefix=R, fused_segments=True)
+    assert [l["lds_bytes"] for l in fused(same)] == [l["lds_bytes"] for l in la]
 
 
 def test_segment_option_validation(c3):
