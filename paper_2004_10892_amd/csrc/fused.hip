@@ -259,7 +259,7 @@ __device__ __forceinline__ void level_step(gu32p prog, const u32x4& t, const u32
 // All levels of one item: three per trip, so that the record registers
 // rotate without copies (level l uses the records read at level l - 2 and
 // reads those of level l + 2; entries after the last level are zero).
-// lv is the LDS copy of the level table; t0, t1 and the first two levels'
+// lv is the program's level table; t0, t1 and the first two levels'
 // records were read before the inputs were copied.
 // Export rows of a segment program and where they go (one-plan mode: the
 // arena of the launch's slice group, item = the slice's place in it).
@@ -296,10 +296,13 @@ __device__ __forceinline__ void level_sync(const u32x4& t) {
   if (!((uni(t.z) >> 24) & kLevelCont)) __syncthreads();
 }
 
+// The level table in device memory as constant data: read with scalar
+// loads at a uniform index, its entries arrive in scalar registers.
+typedef const __attribute__((address_space(4))) u32x4* cu32x4p;
+
 template <bool kBytes>
-__device__ __forceinline__ uint32_t run_levels(gu32p prog, const __attribute__((address_space(3))) u32x4* lv,
-                                               uint32_t n_levels, u32x4 t0, u32x4 t1, Rec& ra, Rec& rb,
-                                               const ExportCtx& xc, uint32_t tid) {
+__device__ __forceinline__ uint32_t run_levels(gu32p prog, cu32x4p lv, uint32_t n_levels, u32x4 t0, u32x4 t1,
+                                               Rec& ra, Rec& rb, const ExportCtx& xc, uint32_t tid) {
   u32x4 t2 = lv[2];
   Rec rc;
   uint32_t xn = 0;  // next export row
@@ -449,8 +452,9 @@ __global__ __launch_bounds__(kFusedBlock) __attribute__((amdgpu_waves_per_eu(kFu
     }
     __syncthreads();
     const ExportCtx xc{lv + mt.levels + kFusedLevelPad, a.arena, a.G, item};
-    const uint32_t xn = mt.bytes ? run_levels<true>(prog, lv, mt.levels, t0, t1, ra, rb, xc, tid)
-                                 : run_levels<false>(prog, lv, mt.levels, t0, t1, ra, rb, xc, tid);
+    const cu32x4p lt = (cu32x4p)(size_t)(gprog + kHdr);
+    const uint32_t xn = mt.bytes ? run_levels<true>(prog, lt, mt.levels, t0, t1, ra, rb, xc, tid)
+                                 : run_levels<false>(prog, lt, mt.levels, t0, t1, ra, rb, xc, tid);
     if (mt.exports) {
       // the last levels' results; the next item's LDS fill waits at the
       // loop head's barrier
