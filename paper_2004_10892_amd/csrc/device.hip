@@ -247,7 +247,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch a) {
 // entry for summed value u sits sum_b bit_b(u) uw[i][b] bytes above its
 // u = 0 entry, the same for every lane and tile: the term loop adds scalar
 // offsets, worked out without memory reads, to a scalar base.
-template <int K, int EPT>
+template <int K, int EPT, bool LEAD>
 __global__ __launch_bounds__(kBlock) void msum_kernel(StepLaunch a) {
   const int tid = threadIdx.x, lane = tid & 63;
   const TileSetup<K, EPT> ts(a, (uint32_t)tid);
@@ -288,10 +288,10 @@ __global__ __launch_bounds__(kBlock) void msum_kernel(StepLaunch a) {
         for (int e = 0; e < EPT; ++e) {
           cm[e] = make_float2(1.f, 0.f);
 #pragma unroll
-          for (int du = 0; du < 4; ++du) pr[du][e] = make_float2(1.f, 0.f);
+          for (int du = 0; du < 4; ++du) pr[du][e] = LEAD ? v[du][e][0] : make_float2(1.f, 0.f);
         }
 #pragma unroll
-        for (int i = 0; i < K; ++i) {
+        for (int i = LEAD ? 1 : 0; i < K; ++i) {
           const uint32_t c = a.uhold[i] & 3u;
           if (c == 0u) {
 #pragma unroll
@@ -389,7 +389,7 @@ __global__ __launch_bounds__(kBlock) void step_pair_kernel(StepLaunch a) {
 // one 16-byte load; the others have the same entry for both tiles and are
 // read once.  Results are written in 16-byte pairs.  Every load and store
 // instruction thus serves two result entries.
-template <int K, int NP>
+template <int K, int NP, bool LEAD>
 __global__ __launch_bounds__(kBlock) void msum_pair_kernel(StepLaunch a) {
   const int tid = threadIdx.x, lane = tid & 63;
   const TileSetup<K, 2, true> ts(a, (uint32_t)tid);
@@ -429,10 +429,10 @@ __global__ __launch_bounds__(kBlock) void msum_pair_kernel(StepLaunch a) {
         for (int e = 0; e < 2; ++e) {
           cm[e] = make_float2(1.f, 0.f);
 #pragma unroll
-          for (int du = 0; du < 4; ++du) pr[du][e] = make_float2(1.f, 0.f);
+          for (int du = 0; du < 4; ++du) pr[du][e] = LEAD ? v[du][e][0] : make_float2(1.f, 0.f);
         }
 #pragma unroll
-        for (int i = 0; i < K; ++i) {
+        for (int i = LEAD ? 1 : 0; i < K; ++i) {
           const uint32_t c = a.uhold[i] & 3u;
           if (c == 0u) {
 #pragma unroll
@@ -1626,13 +1626,19 @@ static int launch_step(const Plan& p, const StepProg& sp, float2* arena, int64_t
   }
   // VALU kernels: operands holding x bit 0 first (the paired kernels read
   // them with 16-byte loads and need that order at compile time), so that
-  // every tile shape, paired or not, multiplies in the same order
+  // every tile shape, paired or not, multiplies in the same order; within
+  // each part, merged launches put the operands that hold both of a trip's
+  // summed bits first, so that the four term products can start from
+  // operand 0's entries (LEAD) instead of the constant 1 -- the same bits,
+  // as 1 * v is exact
+  const uint32_t trip_bits = sp.n_sum > 1 ? ((1u << sp.sum_bit[0]) | (1u << sp.sum_bit[1])) << r : 0u;
+  auto holds_trip = [&](int i) { return trip_bits != 0 && (a.mask[i] & trip_bits) == trip_bits; };
   {
     StepLaunch b = a;
     int at = 0;
-    for (int pass = 0; pass < 2; ++pass)
+    for (int pass = 0; pass < 4; ++pass)
       for (int i = 0; i < sp.n_ops; ++i) {
-        if (((a.mask[i] & 1u) != 0) != (pass == 0)) continue;
+        if (((a.mask[i] & 1u) != 0) != (pass < 2) || holds_trip(i) != (pass % 2 == 0)) continue;
         b.src[at] = a.src[i];
         b.gstride[at] = a.gstride[i];
         b.mask[at] = a.mask[i];
@@ -1642,6 +1648,7 @@ static int launch_step(const Plan& p, const StepProg& sp, float2* arena, int64_t
       }
     a = b;
   }
+  const bool lead = holds_trip(0);
   if (sp.n_sum > 1) {
     if (sp.n_sum > 4) {
       set_error("merged launch with more than four summed variables");
@@ -1710,8 +1717,10 @@ static int launch_step(const Plan& p, const StepProg& sp, float2* arena, int64_t
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)n_cus() * wg_per_cu));
 #define QBE_PAIR(KK, NN)                                                      \
   case KK * 16 + NN:                                                          \
-    if (sp.n_sum > 1)                                                         \
-      msum_pair_kernel<KK, NN><<<grid, kBlock, 0, st>>>(b);                   \
+    if (sp.n_sum > 1 && lead)                                                 \
+      msum_pair_kernel<KK, NN, true><<<grid, kBlock, 0, st>>>(b);             \
+    else if (sp.n_sum > 1)                                                    \
+      msum_pair_kernel<KK, NN, false><<<grid, kBlock, 0, st>>>(b);            \
     else                                                                      \
       step_pair_kernel<KK, NN><<<grid, kBlock, 0, st>>>(b);                   \
     break;
@@ -1735,8 +1744,10 @@ static int launch_step(const Plan& p, const StepProg& sp, float2* arena, int64_t
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)n_cus() * wg_per_cu));
 #define QBE_CASE(KK, EE)                                                      \
   case KK * 16 + EE:                                                          \
-    if (sp.n_sum > 1)                                                         \
-      msum_kernel<KK, EE><<<grid, kBlock, 0, st>>>(a);                        \
+    if (sp.n_sum > 1 && lead)                                                 \
+      msum_kernel<KK, EE, true><<<grid, kBlock, 0, st>>>(a);                  \
+    else if (sp.n_sum > 1)                                                    \
+      msum_kernel<KK, EE, false><<<grid, kBlock, 0, st>>>(a);                 \
     else                                                                      \
       step_kernel<KK, EE><<<grid, kBlock, 0, st>>>(a);                        \
     break;
