@@ -40,10 +40,10 @@ FP32_PEAK_TFLOPS = 157.3
 SEEDS = {"grid4x4_d10_m0": 0, "grid5x5_d16_m6": 1, "grid7x7_d24_m10": 0}
 # Memory traffic of one 5x5 depth-16 fused_kernel launch from the FETCH_SIZE
 # and WRITE_SIZE counter runs in profiles/fused_kernel_grid5x5_d16_m6.md
-# (722.06 KiB x 2.000 + 6.06 KiB x 1.000, the factors from a 256 MiB device copy),
+# (588.50 KiB x 2.000 + 6.06 KiB x 1.000, the factors from a 256 MiB device copy),
 # valid while the fused kernel's sources have the digest they were measured on.
-FUSED_TRAFFIC = {"bytes": int(round((722.0625 * 2.000 + 6.0625 * 1.000) * 1024)),
-                 "sources_sha256": "6d2ebd8c1828c4f5c14865302cd4e39fbc3a8934798ee7c8f13482e0d335d840"}
+FUSED_TRAFFIC = {"bytes": int(round((588.5 * 2.000 + 6.0625 * 1.000) * 1024)),
+                 "sources_sha256": "da104f58e3ae33c0569361dde8102b76026f92bdd7436b1bc9ec00abd429b7e8"}
 
 
 def log(*a):
@@ -233,7 +233,7 @@ C3 = "grid7x7_d24_m10"
 # Sources that decide the per-step form's kernels and launches: counters
 # taken on other sources describe other code and are not reported.
 STEP_SOURCES = ("device.hip", "device_common.hpp", "qbe_internal.hpp", "program.cpp", "planner.cpp", "fused.hip",
-                "fused_format.hpp")
+                "fused_format.hpp", "api.cpp")
 # Hardware counters of one contraction of the headline plan
 # (profiles/fused_and_step_kernels_grid7x7_d24_m10.md): per precision, summed over the
 # contraction's dispatches.  mfma_busy: SQ_VALU_MFMA_BUSY_CYCLES; capacity:
@@ -242,7 +242,7 @@ STEP_SOURCES = ("device.hip", "device_common.hpp", "qbe_internal.hpp", "program.
 # dominant: the same for the dominant kernel's launch.  Keyed by the
 # sources' digest and the plan's sliced set.
 C3_COUNTERS = {
-    "sources_sha256": "6b6ec7ca833d57a992a01d52fbeab77f32e26719d9255b1d9434e4b3d016f758",
+    "sources_sha256": "3231495057274d2720033eb1f42e6102ff920b41f9cb54902ea9c9748e00d232",
     "plan": "min_fill+tt_rec1_t16_s2+segments",
     "mu": [
         119,
@@ -257,29 +257,29 @@ C3_COUNTERS = {
         289
     ],
     "fp32": {
-        "mfma_util": 0.0017440396189937666,
-        "mfma_busy_cycles": 2097152.0,
-        "gui_active": 9394282.0,
+        "mfma_util": 0.0,
+        "mfma_busy_cycles": 0.0,
+        "gui_active": 7079060.0,
         "amplitude": {
-            "bytes": 578582816,
-            "fetch_kib": 166887.125,
-            "write_kib": 231248.03125
+            "bytes": 535542048,
+            "fetch_kib": 162255.125,
+            "write_kib": 198480.03125
         },
         "dominant": {
             "launch": 0,
             "kernel": "qbe::fused_kernel",
-            "bytes": 64882816,
-            "fetch_kib": 6193.0625,
+            "bytes": 64255744,
+            "fetch_kib": 5886.875,
             "write_kib": 50976.0
         }
     },
     "bf16x6": {
-        "mfma_util": 0.0017001317851176208,
+        "mfma_util": 0.0021675814017176336,
         "mfma_busy_cycles": 2097152.0,
-        "gui_active": 9636900.0
+        "gui_active": 7558655.0
     },
     "plain_fp32": {
-        "mfma_util": 0.0003731293005150303
+        "mfma_util": 0.00037809744690914373
     }
 }
 
