@@ -141,9 +141,15 @@ __device__ __forceinline__ uint32_t slot(uint32_t w, int j) {
   if (kBytes) return (j & 1) ? w >> 16 : w & 0xFFFFu;
   return (j & 1) ? (w >> 13) & 0x7FFF8u : (w << 3) & 0x7FFF8u;
 }
-template <bool kBytes>
+// Slot j of a record held in registers, from word w0 on: 16-bit slots
+// (element indices or LDS byte addresses), or the 32-bit LDS byte
+// addresses of a wide level (flag W: at most three factors, the same
+// 16-byte rows, nothing to unpack).
+enum { kSlotElem = 0, kSlotBytes = 1, kSlotWide = 2 };
+template <int kMode>
 __device__ __forceinline__ uint32_t rec_slot(const Rec& c, int w0, int j) {
-  return slot<kBytes>(word(c, w0 + (j >> 1)), j);
+  if (kMode == kSlotWide) return word(c, w0 + j);
+  return slot<kMode == kSlotBytes>(word(c, w0 + (j >> 1)), j);
 }
 
 // Product of N complex values as a balanced tree (short dependent chain).
@@ -169,40 +175,40 @@ __device__ __forceinline__ float2 dpp_add(float2 v) {
 // tid >> lgT); the T lanes of an entry add their products and the first
 // writes the result.  Every lane runs the same code (the DPP partners must
 // be active); only the writes are guarded.
-template <int K, bool kBytes>
+template <int K, int kMode>
 __device__ __forceinline__ void level_split(const Rec& c, uint32_t E, uint32_t lgT, uint32_t tid) {
   float2 v[K];
 #pragma unroll
-  for (int i = 0; i < K; ++i) v[i] = lds_entry(rec_slot<kBytes>(c, 0, 1 + i));
+  for (int i = 0; i < K; ++i) v[i] = lds_entry(rec_slot<kMode>(c, 0, 1 + i));
   __builtin_amdgcn_sched_barrier(0);  // every read in flight before the first product
   float2 p = dpp_add<0xB1>(tree_prod<K>(v));
   if (lgT >= 2) p = dpp_add<0x4E>(p);
   if (lgT >= 3) p = dpp_add<0x141>(p);
-  if ((tid & ((1u << lgT) - 1)) == 0 && tid < (E << lgT)) lds_store(rec_slot<kBytes>(c, 0, 0), p);
+  if ((tid & ((1u << lgT) - 1)) == 0 && tid < (E << lgT)) lds_store(rec_slot<kMode>(c, 0, 0), p);
 }
 
 // Whole-record level (half-records of one row): lane tid holds record tid;
 // records past the first kFusedBlock are read here.
-template <int K, bool kBytes>
+template <int K, int kMode>
 __device__ __forceinline__ float2 record_value(const Rec& c) {
   float2 x[K], y[K];
 #pragma unroll
   for (int i = 0; i < K; ++i) {
-    x[i] = lds_entry(rec_slot<kBytes>(c, 0, 1 + i));
-    y[i] = lds_entry(rec_slot<kBytes>(c, 4, 1 + i));
+    x[i] = lds_entry(rec_slot<kMode>(c, 0, 1 + i));
+    y[i] = lds_entry(rec_slot<kMode>(c, 4, 1 + i));
   }
   __builtin_amdgcn_sched_barrier(0);  // every read in flight before the first product
   return cadd(tree_prod<K>(x), tree_prod<K>(y));
 }
 
-template <int K, bool kBytes>
+template <int K, int kMode>
 __device__ __forceinline__ void level_whole(gu32p prog, const Rec& c, uint32_t base, uint32_t E, uint32_t tid) {
-  const float2 v = record_value<K, kBytes>(c);
-  if (tid < E) lds_store(rec_slot<kBytes>(c, 0, 0), v);
+  const float2 v = record_value<K, kMode>(c);
+  if (tid < E) lds_store(rec_slot<kMode>(c, 0, 0), v);
   for (uint32_t f = tid + kFusedBlock; f < E; f += kFusedBlock) {
     Rec d;
     load_rec(prog, base + f * 8, d);
-    lds_store(rec_slot<kBytes>(d, 0, 0), record_value<K, kBytes>(d));
+    lds_store(rec_slot<kMode>(d, 0, 0), record_value<K, kMode>(d));
   }
 }
 
@@ -234,10 +240,28 @@ __device__ __forceinline__ void level_step(gu32p prog, const u32x4& t, const u32
   load_rec(prog, rec_word(uni(tn.x), uni(tn.y), ntz & 0xFFFFu, (ntz >> 16) & 0xFFu, tid), pf);
   const uint32_t base = uni(t.x), E = uni(t.y), tz = uni(t.z), K = uni(t.w) & 0xFFFFu;
   const uint32_t R = tz & 0xFFFFu, lgT = (tz >> 16) & 0xFFu;
-  if (split_level(E, lgT) && K <= (uint32_t)kSplitOpsMax) {
+  constexpr int kMode = kBytes ? kSlotBytes : kSlotElem;
+  if ((tz >> 24) & kLevelWide) {
+    // at most three factors, one row a term, split or whole (host-checked)
+    if (split_level(E, lgT)) {
+      switch (K) {
+        case 1: level_split<1, kSlotWide>(c, E, lgT, tid); break;
+        case 2: level_split<2, kSlotWide>(c, E, lgT, tid); break;
+        case 3: level_split<3, kSlotWide>(c, E, lgT, tid); break;
+        default: break;
+      }
+    } else {
+      switch (K) {
+        case 1: level_whole<1, kSlotWide>(prog, c, base, E, tid); break;
+        case 2: level_whole<2, kSlotWide>(prog, c, base, E, tid); break;
+        case 3: level_whole<3, kSlotWide>(prog, c, base, E, tid); break;
+        default: break;
+      }
+    }
+  } else if (split_level(E, lgT) && K <= (uint32_t)kSplitOpsMax) {
     switch (K) {
 #define QBE_SPLIT(KK) \
-  case KK: level_split<KK, kBytes>(c, E, lgT, tid); break;
+  case KK: level_split<KK, kMode>(c, E, lgT, tid); break;
       QBE_SPLIT(1) QBE_SPLIT(2) QBE_SPLIT(3) QBE_SPLIT(4) QBE_SPLIT(5) QBE_SPLIT(6) QBE_SPLIT(7) QBE_SPLIT(8)
       QBE_SPLIT(9) QBE_SPLIT(10) QBE_SPLIT(11) QBE_SPLIT(12) QBE_SPLIT(13) QBE_SPLIT(14) QBE_SPLIT(15)
 #undef QBE_SPLIT
@@ -246,7 +270,7 @@ __device__ __forceinline__ void level_step(gu32p prog, const u32x4& t, const u32
   } else if (lgT == 1 && K <= (uint32_t)kWholeOpsMax) {
     switch (K) {
 #define QBE_WHOLE(KK) \
-  case KK: level_whole<KK, kBytes>(prog, c, base, E, tid); break;
+  case KK: level_whole<KK, kMode>(prog, c, base, E, tid); break;
       QBE_WHOLE(1) QBE_WHOLE(2) QBE_WHOLE(3) QBE_WHOLE(4) QBE_WHOLE(5) QBE_WHOLE(6) QBE_WHOLE(7)
 #undef QBE_WHOLE
       default: break;

@@ -40,11 +40,14 @@ constexpr int64_t kInKernelReduceMax = 8192;
 //                               (record base, entries E, R | lgT << 16 |
 //                               C << 24, factors K | X << 16), then zero
 //                               entries; R = rows of a term record, T =
-//                               2^lgT terms per entry, C = kLevelCont when
-//                               the next level is another part of the same
-//                               dependency level (no barrier between the
-//                               two), X = export rows copied as the level
-//                               starts (the results of earlier levels)
+//                               2^lgT terms per entry, C = flags: kLevelCont
+//                               when the next level is another part of the
+//                               same dependency level (no barrier between
+//                               the two), kLevelWide when the level's slots
+//                               are 32-bit LDS byte addresses (at most three
+//                               factors: one row a term either way), X =
+//                               export rows copied as the level starts (the
+//                               results of earlier levels)
 //   exports[4 * n_exports]      a segment program's results for other
 //                               launches: (LDS element, rank, arena offset
 //                               lo, hi) in the order levels copy them; rows
@@ -73,6 +76,13 @@ constexpr int kFusedTailRows = 2;
 // results take fresh arena space), so the workgroup needs no barrier
 // between them.
 constexpr uint32_t kLevelCont = 1u;
+// C of a level entry: its records' slots are 32-bit LDS byte addresses
+// (1 + K <= 4 of them fill the 16-byte row that 16-bit slots would), so the
+// executor uses them as they are.  Only on levels of at most kWideOpsMax
+// factors that run in one pass: 2 terms an entry, or all term records
+// within the workgroup's lanes.
+constexpr uint32_t kLevelWide = 2u;
+constexpr uint32_t kWideOpsMax = 3;
 constexpr int kFusedLevelPad = 3;
 // A level runs in one pass when every lane holds what it computes in the
 // kFusedTailRows rows it read ahead: E x T <= kFusedBlock term records of

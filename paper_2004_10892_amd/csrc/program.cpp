@@ -583,6 +583,7 @@ static FusedCode build_fused(const Plan& p, const std::vector<InputInfo>& in, co
     const int64_t E = lvE[l], cap = lvCap[l];
     const uint32_t R = (1 + F + 7) / 8;  // 16-byte rows of a term record
     int64_t done = 0;                    // entries of the level written
+    bool wide = false;                   // the current part's slots are 32-bit
     uint32_t X = 0;                      // exports of the previous level
     for (int64_t e = 0; e < n_exp; ++e) X += exp_level[e] == l - 1;
     for (int i : by_level[l]) {
@@ -595,18 +596,26 @@ static FusedCode build_fused(const Plan& p, const std::vector<InputInfo>& in, co
           // a later part of the level: the part before it runs on without
           // a barrier (both read earlier levels only and write fresh space)
           if (done > 0) prog[lvl_at + 4 * (tab - 1) + 2] |= kLevelCont << 24;
+          const int64_t part = std::min(cap, E - done);
+          wide = F <= kWideOpsMax && (T == 2 || part * T <= kFusedBlock);
           prog[lvl_at + 4 * tab + 0] = (uint32_t)prog.size();
-          prog[lvl_at + 4 * tab + 1] = (uint32_t)std::min(cap, E - done);
-          prog[lvl_at + 4 * tab + 2] = R | ((uint32_t)__builtin_ctz(T) << 16);
+          prog[lvl_at + 4 * tab + 1] = (uint32_t)part;
+          prog[lvl_at + 4 * tab + 2] = R | ((uint32_t)__builtin_ctz(T) << 16) | (wide ? kLevelWide << 24 : 0u);
           prog[lvl_at + 4 * tab + 3] = F | (done == 0 ? X << 16 : 0u);
           ++tab;
         }
-        // T term records of 8R halfwords: [result (term 0) or 0, the
-        // factors' entries for that assignment of the summed variables]
+        // T term records of 8R halfwords (4R words on a wide level):
+        // [result (term 0) or 0, the factors' entries for that assignment
+        // of the summed variables]
         for (uint32_t t = 0; t < T; ++t) {
           const size_t at = prog.size();
           prog.resize(at + 4 * R, 0);
-          auto put = [&](uint32_t j, uint32_t v) { prog[at + j / 2] |= (v * unit) << (16 * (j % 2)); };
+          auto put = [&](uint32_t j, uint32_t v) {
+            if (wide)
+              prog[at + j] = v * 8u;
+            else
+              prog[at + j / 2] |= (v * unit) << (16 * (j % 2));
+          };
           if (t == 0) put(0, (uint32_t)(lds_out[nd.members[0]] + x));
           if (t >= Tn) {
             put(1, kFusedZero);  // padding term: a factor 0

@@ -58,18 +58,20 @@ static std::string check_fused_liveness(const std::vector<uint32_t>& w, uint32_t
   std::vector<uint32_t> writes;
   for (uint32_t l = 0; l < nl; ++l) {
     const uint32_t base = lv[4 * l], E = lv[4 * l + 1], R = lv[4 * l + 2] & 0xFFFFu,
-                   lgT = (lv[4 * l + 2] >> 16) & 0xFFu, C = lv[4 * l + 2] >> 24, K = lv[4 * l + 3] & 0xFFFFu,
-                   X = lv[4 * l + 3] >> 16;
+                   lgT = (lv[4 * l + 2] >> 16) & 0xFFu, C = (lv[4 * l + 2] >> 24) & kLevelCont,
+                   K = lv[4 * l + 3] & 0xFFFFu, X = lv[4 * l + 3] >> 16;
+    const bool wide = ((lv[4 * l + 2] >> 24) & kLevelWide) != 0;
+    const uint32_t su = wide ? 8u : unit;
     for (uint32_t e = 0; e < X; ++e, ++xn)
       for (uint32_t i = 0; i < (1u << xr[4 * xn + 1]); ++i)
         if (!read(xr[4 * xn] + i, g)) return "fused export row reads an element not written before it";
     for (uint32_t f = 0; f < E; ++f)
       for (uint32_t t = 0; t < (1u << lgT); ++t) {
         const uint32_t* rec = w.data() + base + ((size_t)f * (1u << lgT) + t) * 4 * R;
-        auto hw = [&](uint32_t j) { return (rec[j / 2] >> (16 * (j % 2))) & 0xFFFFu; };
+        auto hw = [&](uint32_t j) { return wide ? rec[j] : (rec[j / 2] >> (16 * (j % 2))) & 0xFFFFu; };
         for (uint32_t j = 1; j <= K; ++j)
-          if (!read(hw(j) / unit, g)) return "fused operand read before it is written, or after it is overwritten";
-        if (t == 0) writes.push_back(hw(0) / unit);
+          if (!read(hw(j) / su, g)) return "fused operand read before it is written, or after it is overwritten";
+        if (t == 0) writes.push_back(hw(0) / su);
       }
     if (!C) {
       for (uint32_t e : writes)
@@ -127,8 +129,9 @@ static std::string check_fused_program(const std::vector<uint32_t>& w, int64_t l
   const bool bytes = w[FH_BYTE_OFFSETS] != 0;
   if (w[FH_BYTE_OFFSETS] > 1 || bytes != ((int64_t)data * 8 <= 65536)) return "fused offset unit";
   const uint32_t unit = bytes ? 8u : 1u;
-  // results may take the space of inputs their level no longer needs
-  const uint32_t arena_lo = kFusedConsts * unit, data_hi = data * unit;
+  // results may take the space of inputs their level no longer needs (any
+  // slot above the constants); 16-bit slots must reach all the data
+  const uint32_t data_hi = data * unit;
   if (data_hi > 65536) return "fused offsets above 16 bits";
   // levels the executor runs without a barrier between them (flag C): the
   // group's reads (its operands and the export rows it copies) and writes
@@ -138,10 +141,14 @@ static std::string check_fused_program(const std::vector<uint32_t>& w, int64_t l
   bool cont_prev = false;
   for (uint32_t l = 0; l < nl; ++l) {
     const uint32_t base = lv[4 * l], E = lv[4 * l + 1], R = lv[4 * l + 2] & 0xFFFFu,
-                   lgT = (lv[4 * l + 2] >> 16) & 0xFFu, C = lv[4 * l + 2] >> 24, K = lv[4 * l + 3] & 0xFFFFu,
+                   lgT = (lv[4 * l + 2] >> 16) & 0xFFu, flags = lv[4 * l + 2] >> 24, K = lv[4 * l + 3] & 0xFFFFu,
                    X = lv[4 * l + 3] >> 16;
+    const uint32_t C = flags & kLevelCont;
+    const bool wide = (flags & kLevelWide) != 0;
     if (base != expect_base) return fail("fused record base", base, expect_base);
-    if (C > kLevelCont || (C && l + 1 == nl)) return "fused level continuation flag";
+    if ((flags & ~(kLevelCont | kLevelWide)) || (C && l + 1 == nl)) return "fused level flags";
+    if (wide && (K > kWideOpsMax || R != 1 || !(lgT == 1 || ((int64_t)E << lgT) <= kFusedBlock)))
+      return "fused wide level not of at most three factors in one pass";
     if (cont_prev && X) return "fused level copies export rows without a barrier before it";
     for (int64_t e = x_copied; e < x_copied + X && e < nx; ++e)
       for (uint32_t i = 0; i < (1u << xr[4 * e + 1]); ++i) g_reads.push_back(xr[4 * e] + i);
@@ -154,19 +161,23 @@ static std::string check_fused_program(const std::vector<uint32_t>& w, int64_t l
     for (uint32_t f = 0; f < E; ++f)
       for (uint32_t t = 0; t < T; ++t) {
         const uint32_t* rec = w.data() + base + ((size_t)f * T + t) * 4 * R;
-        auto hw = [&](uint32_t j) { return (rec[j / 2] >> (16 * (j % 2))) & 0xFFFFu; };
+        // slot j: 16-bit (element or byte offsets), or 32-bit bytes on a
+        // wide level
+        const uint32_t su = wide ? 8u : unit, n_slots = wide ? 4 * R : 8 * R;
+        const uint64_t s_hi = wide ? (uint64_t)data * 8 : data_hi;
+        auto hw = [&](uint32_t j) { return wide ? rec[j] : (rec[j / 2] >> (16 * (j % 2))) & 0xFFFFu; };
         if (t == 0) {
           const uint32_t out = hw(0);
-          if (out % unit || out < arena_lo || out >= data_hi) return "fused result outside the arena";
-          g_writes.push_back(out / unit);
+          if (out % su || out < kFusedConsts * su || out >= s_hi) return "fused result outside the arena";
+          g_writes.push_back(out / su);
         } else if (hw(0) != 0) {
           return "fused term's result slot not zero";
         }
-        for (uint32_t j = 1; j < 8 * R; ++j) {
+        for (uint32_t j = 1; j < n_slots; ++j) {
           const uint32_t v = hw(j);
-          if (v % unit || v >= data_hi) return "fused operand outside LDS data";
+          if (v % su || v >= s_hi) return "fused operand outside LDS data";
           if (j > K && v != 0) return "fused padding slot not the constant";
-          if (j <= K) g_reads.push_back(v / unit);
+          if (j <= K) g_reads.push_back(v / su);
         }
       }
     expect_base += (int64_t)E * T * 4 * R;
