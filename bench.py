@@ -337,10 +337,10 @@ def plan_candidates(qbe, qm, m, net):
     the anytime heuristic standing in for the paper's tree-decomposition
     solver; with a network, min-fill with learned tie-breaking) times sliced
     sets of m variables (tree-trimming; tree-trimming with Alg. 2's order
-    recomputation after every k-th removal, k = 1..3, with two try counts
-    and seeds of the anytime heuristic; with a network, the learned score
-    with and without it).  Returns {name: (mu, reduced_order,
-    planning_ms)}, duplicates dropped."""
+    recomputation after every k-th removal, k = 1..3, with 4 tries of the
+    anytime heuristic and seeds 1-2 or 16 tries and seeds 1-8; with a
+    network, the learned score with and without it).  Returns {name: (mu,
+    reduced_order, planning_ms)}, duplicates dropped."""
     orders = {}
     t0 = time.perf_counter()
     orders["min_fill"] = (qbe.qbe_order_min_fill(qm), (time.perf_counter() - t0) * 1e3)
@@ -351,8 +351,8 @@ def plan_candidates(qbe, qm, m, net):
         orders["learned_order"] = (qbe.qbe_order_learned(qm, net, 16)[0], (time.perf_counter() - t0) * 1e3)
     slicings = {"tt": dict()}
     for k in (1, 2, 3):
-        for tries in (4, 16):
-            for seed in (1, 2):
+        for tries, seeds in ((4, (1, 2)), (16, range(1, 9))):
+            for seed in seeds:
                 slicings[f"tt_rec{k}_t{tries}_s{seed}"] = dict(recompute_every=k, tries=tries, seed=seed)
     if net is not None:
         slicings["learned"] = dict(score="learned", net=net)
@@ -441,7 +441,7 @@ def time_precisions(torch, qbe, ctx, qm, mu, pi, precisions, steps, warmup, want
     return forms
 
 
-def bench_headline(torch, qbe, ctx, steps, warmup, net, n_timed=6):
+def bench_headline(torch, qbe, ctx, steps, warmup, net, n_timed=12, n_forms=3):
     from paper_2004_10892_amd import learned as L
     qm, m = c3_model(qbe)
     want = golden(C3)
@@ -449,8 +449,10 @@ def bench_headline(torch, qbe, ctx, steps, warmup, net, n_timed=6):
     cands = plan_candidates(qbe, qm, m, net)
     # every candidate's schedule on the host; the most promising by a rough
     # estimate (bytes at 2.5 TB/s plus 6 us a launch) are built on the
-    # device, autotuned and timed in FP32, and the fastest is kept: the
-    # cost model's FLOPs do not rank plans for this executor
+    # device with fused segments, autotuned and timed in FP32, the fastest
+    # few also without segments and without the prefix, and the fastest of
+    # all is kept: the cost model's FLOPs do not rank plans for this
+    # executor
     plans_info = {}
     for k, (mu_k, pi_k, ms_k) in cands.items():
         st_k = qbe.Plan(qm, pi_k, mu_k, exec="per_step").stats()
@@ -465,13 +467,17 @@ def bench_headline(torch, qbe, ctx, steps, warmup, net, n_timed=6):
                   next((k for k in ranked if k.startswith("anytime8")), None)):
         if extra and extra not in to_time:
             to_time.append(extra)
-    # each in the plain per-step form, with the fused prefix (first small
-    # buckets in one LDS-resident launch) and with fused segments (later
-    # runs of small buckets too)
+    # each with fused segments (first small buckets in one LDS-resident
+    # launch, later runs of small buckets too); the fastest n_forms also in
+    # the plain per-step form and with the fused prefix only
     timed_ms = {}
-    for k in to_time:
+
+    def time_forms(k, forms):
+        """Times plan k in the given fused forms; the forms that exist."""
         mu_k, pi_k, _ = cands[k]
-        for suffix, (pre, seg) in FUSED_FORMS.items():
+        done = []
+        for suffix in forms:
+            pre, seg = FUSED_FORMS[suffix]
             plan_k = qbe.Plan(qm, pi_k, mu_k, ctx=ctx, exec="per_step", fused_prefix=pre, fused_segments=seg)
             st_k = plan_k.stats()
             if (pre and st_k["prefix_buckets"] == 0) or (seg and st_k["n_fused_segments"] < 2):
@@ -487,7 +493,17 @@ def bench_headline(torch, qbe, ctx, steps, warmup, net, n_timed=6):
             plans_info[k][f"{tag}launches"] = st_k["n_launches"]
             if err_k <= 1e-5:
                 timed_ms[k + suffix] = ev_k
+            done.append(suffix)
             del ws_k, plan_k
+        return done
+
+    others = [f for f in FUSED_FORMS if f != "+segments"]
+    for k in to_time:
+        if not time_forms(k, ["+segments"]):
+            time_forms(k, others)  # no segments in this plan: its other forms
+    best = sorted((b for b in to_time if b + "+segments" in timed_ms), key=lambda b: timed_ms[b + "+segments"])
+    for k in best[:n_forms]:
+        time_forms(k, others)
     src = min(timed_ms, key=timed_ms.get)
     base, use_prefix, use_segments = split_plan_name(src)
     mu, pi, _ = cands[base]
@@ -851,7 +867,7 @@ def main():
     ap.add_argument("--pmc-c3", choices=["fp32", "bf16x6", "bf16x3", "plain_fp32"],
                     help="for hardware-counter runs: the copy calibration, then the headline plan in this form "
                          "(sliced set from --mu, else tree-trimming), autotuned, and two contractions")
-    ap.add_argument("--plan", default="min_fill+tt_rec1_t16_s2+segments",
+    ap.add_argument("--plan", default="min_fill+tt_rec2_t16_s5+segments",
                     help="for --pmc-c3: a candidate plan of the headline search without the network "
                          "(min_fill or anytime8, + tt or tt_rec<k>_t<tries>_s<seed>), optionally followed by "
                          "+prefix or +segments")
