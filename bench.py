@@ -40,10 +40,10 @@ FP32_PEAK_TFLOPS = 157.3
 SEEDS = {"grid4x4_d10_m0": 0, "grid5x5_d16_m6": 1, "grid7x7_d24_m10": 0}
 # Memory traffic of one 5x5 depth-16 fused_kernel launch from the FETCH_SIZE
 # and WRITE_SIZE counter runs in profiles/fused_kernel_grid5x5_d16_m6.md
-# (588.50 KiB x 2.000 + 6.06 KiB x 1.000, the factors from a 256 MiB device copy),
+# (621.44 KiB x 2.000 + 6.06 KiB x 1.000, the factors from a 256 MiB device copy),
 # valid while the fused kernel's sources have the digest they were measured on.
-FUSED_TRAFFIC = {"bytes": int(round((588.5 * 2.000 + 6.0625 * 1.000) * 1024)),
-                 "sources_sha256": "da104f58e3ae33c0569361dde8102b76026f92bdd7436b1bc9ec00abd429b7e8"}
+FUSED_TRAFFIC = {"bytes": int(round((621.4375 * 2.000 + 6.0625 * 1.000) * 1024)),
+                 "sources_sha256": "dce4a58e10174e97b58fe8adf8806c4edd0dcb09de6f694622fa320f77cfe96d"}
 
 
 def log(*a):
@@ -242,44 +242,44 @@ STEP_SOURCES = ("device.hip", "device_common.hpp", "qbe_internal.hpp", "program.
 # dominant: the same for the dominant kernel's launch.  Keyed by the
 # sources' digest and the plan's sliced set.
 C3_COUNTERS = {
-    "sources_sha256": "3231495057274d2720033eb1f42e6102ff920b41f9cb54902ea9c9748e00d232",
-    "plan": "min_fill+tt_rec1_t16_s2+segments",
+    "sources_sha256": "a49be2ba65d037a8c903974205316ace22e0e2f843e920eaf068be2450abc11b",
+    "plan": "min_fill+tt_rec2_t16_s5+segments",
     "mu": [
         119,
-        154,
-        406,
-        113,
+        353,
+        183,
+        220,
+        335,
         66,
-        308,
-        385,
-        150,
-        169,
-        289
+        486,
+        359,
+        490,
+        169
     ],
     "fp32": {
-        "mfma_util": 0.0,
-        "mfma_busy_cycles": 0.0,
-        "gui_active": 7079060.0,
+        "mfma_util": 0.01013710051021158,
+        "mfma_busy_cycles": 8388608.0,
+        "gui_active": 6464965.0,
         "amplitude": {
-            "bytes": 535542048,
-            "fetch_kib": 162255.125,
-            "write_kib": 198480.03125
+            "bytes": 424542496,
+            "fetch_kib": 127880.125,
+            "write_kib": 158832.03125
         },
         "dominant": {
             "launch": 0,
             "kernel": "qbe::fused_kernel",
-            "bytes": 64255744,
-            "fetch_kib": 5886.875,
-            "write_kib": 50976.0
+            "bytes": 39785600,
+            "fetch_kib": 5570.5625,
+            "write_kib": 27712.0
         }
     },
     "bf16x6": {
-        "mfma_util": 0.0021675814017176336,
-        "mfma_busy_cycles": 2097152.0,
-        "gui_active": 7558655.0
+        "mfma_util": 0.010261037978143522,
+        "mfma_busy_cycles": 9437184.0,
+        "gui_active": 7185238.0
     },
     "plain_fp32": {
-        "mfma_util": 0.00037809744690914373
+        "mfma_util": 0.0
     }
 }
 
