@@ -580,6 +580,16 @@ def bench_headline(torch, qbe, ctx, steps, warmup, net, n_timed=12, n_forms=3):
             "bytes_per_slice": dom["bytes_per_slice"], "slices_per_launch": plan.n_slices,
             "launch_share_of_amplitude": dom["ms"] / total_ms,
             "copy_peak": copy_peak_gbs(torch), "frac_vs_copy": gbs / copy_peak_gbs(torch),
+            # the same launch against the vector ALU: its algorithmic flops
+            # (the cost model's: 6 per complex product of factors, 2 per
+            # complex addition of the sum) per second, against the FP32
+            # vector peak (157.3 TFLOP/s counts packed FP32 pairs; these
+            # kernels issue one FP32 operation a lane, whose peak is half
+            # that)
+            "alu_view": {"achieved_tflops": dom["flops"] / (dom["ms"] * 1e-3) / 1e12, "peak": FP32_PEAK_TFLOPS,
+                         "frac": dom["flops"] / (dom["ms"] * 1e-3) / 1e12 / FP32_PEAK_TFLOPS,
+                         "frac_of_unpacked_peak": dom["flops"] / (dom["ms"] * 1e-3) / 1e12 / (FP32_PEAK_TFLOPS / 2),
+                         "flops_per_launch": dom["flops"]},
             "amplitude": {"algorithmic_bytes": amp_bytes, "cost_model_bytes": st["bytes_per_slice"] * plan.n_slices,
                           "ms": forms[chosen]["ms_per_amplitude"],
                           "achieved_GB_per_s": amp_bytes / (forms[chosen]["ms_per_amplitude"] * 1e-3) / 1e9,
