@@ -409,22 +409,27 @@ FUSED_FORMS = {"": (False, False), "+prefix": (True, False), "+segments": (True,
 def split_plan_name(name):
     """A timed plan's name: a candidate's, with "+prefix" appended when the
     plan runs its first small buckets in a fused prefix, "+segments" when
-    later runs of small buckets are fused launches too.  Returns
-    (candidate, fused_prefix, fused_segments)."""
+    later runs of small buckets are fused launches too, then "+sums<N>" when
+    its merged per-step launches sum at most N variables.  Returns
+    (candidate, fused_prefix, fused_segments, max_sums)."""
+    sums = 0
+    head, _, tail = name.rpartition("+sums")
+    if head and tail.isdigit():
+        name, sums = head, int(tail)
     for suffix, (pre, seg) in FUSED_FORMS.items():
         if suffix and name.endswith(suffix):
-            return name[:-len(suffix)], pre, seg
-    return name, False, False
+            return name[:-len(suffix)], pre, seg, sums
+    return name, False, False, sums
 
 
 def time_precisions(torch, qbe, ctx, qm, mu, pi, precisions, steps, warmup, want, keep=True, prefix=False,
-                    segments=False):
+                    segments=False, max_sums=0):
     """The plan (mu, pi) in each precision: autotuned, then timed issued
     directly and from a HIP graph; error against the oracle amplitude."""
     forms = {}
     for prec in precisions:
         plan = qbe.Plan(qm, pi, mu, ctx=ctx, exec="per_step", precision=prec, fused_prefix=prefix,
-                        fused_segments=segments)
+                        fused_segments=segments, max_sums=max_sums)
         ws0 = plan.workspace()
         t0 = time.perf_counter()
         plan.autotune(ws0)
@@ -472,13 +477,15 @@ def bench_headline(torch, qbe, ctx, steps, warmup, net, n_timed=12, n_forms=3):
     # the plain per-step form and with the fused prefix only
     timed_ms = {}
 
-    def time_forms(k, forms):
-        """Times plan k in the given fused forms; the forms that exist."""
+    def time_forms(k, forms, max_sums=0):
+        """Times plan k in the given fused forms (merged launches of at most
+        max_sums summed variables when > 0); the forms that exist."""
         mu_k, pi_k, _ = cands[k]
         done = []
         for suffix in forms:
             pre, seg = FUSED_FORMS[suffix]
-            plan_k = qbe.Plan(qm, pi_k, mu_k, ctx=ctx, exec="per_step", fused_prefix=pre, fused_segments=seg)
+            plan_k = qbe.Plan(qm, pi_k, mu_k, ctx=ctx, exec="per_step", fused_prefix=pre, fused_segments=seg,
+                              max_sums=max_sums)
             st_k = plan_k.stats()
             if (pre and st_k["prefix_buckets"] == 0) or (seg and st_k["n_fused_segments"] < 2):
                 continue
@@ -487,12 +494,13 @@ def bench_headline(torch, qbe, ctx, steps, warmup, net, n_timed=12, n_forms=3):
             out_k = torch.zeros(2, dtype=torch.float64, device="cuda")
             _, ev_k = timed(torch, lambda: qbe.qbe_contract_async(ctx, plan_k, ws_k, out_k), max(3, steps // 2), 1)
             err_k = abs(complex(*out_k.cpu().numpy()) - want) / abs(want)
-            tag = suffix.lstrip("+") + "_" if suffix else ""
+            name = suffix + (f"+sums{max_sums}" if max_sums else "")
+            tag = name.replace("+", "_").strip("_") + "_" if name else ""
             plans_info[k][f"fp32_{tag}ms_per_amplitude"] = ev_k
             plans_info[k][f"rel_err_fp32_{tag}".rstrip("_")] = err_k
             plans_info[k][f"{tag}launches"] = st_k["n_launches"]
             if err_k <= 1e-5:
-                timed_ms[k + suffix] = ev_k
+                timed_ms[k + name] = ev_k
             done.append(suffix)
             del ws_k, plan_k
         return done
@@ -504,13 +512,17 @@ def bench_headline(torch, qbe, ctx, steps, warmup, net, n_timed=12, n_forms=3):
     best = sorted((b for b in to_time if b + "+segments" in timed_ms), key=lambda b: timed_ms[b + "+segments"])
     for k in best[:n_forms]:
         time_forms(k, others)
+        # merged launches of fewer summed variables: more launches and
+        # round trips, fewer terms an entry -- which wins depends on the plan
+        for cap in (2, 3):
+            time_forms(k, ["+segments"], max_sums=cap)
     src = min(timed_ms, key=timed_ms.get)
-    base, use_prefix, use_segments = split_plan_name(src)
+    base, use_prefix, use_segments, use_sums = split_plan_name(src)
     mu, pi, _ = cands[base]
     search_s = time.perf_counter() - t_search
     log(f"[bench] {C3}: plan {src}; " + ", ".join(f"{k} {v:.3f} ms" for k, v in sorted(timed_ms.items())))
     forms = time_precisions(torch, qbe, ctx, qm, mu, pi, ("fp32", "bf16x6", "bf16x3"), steps, warmup, want,
-                            prefix=use_prefix, segments=use_segments)
+                            prefix=use_prefix, segments=use_segments, max_sums=use_sums)
     ok = [p for p in forms if forms[p]["within_1e-5"]]
     if not ok:
         raise SystemExit("no form of the headline workload met the 1e-5 bound")
@@ -546,11 +558,11 @@ def bench_headline(torch, qbe, ctx, steps, warmup, net, n_timed=12, n_forms=3):
     lk = [k for k in timed_ms if "learned" in k]
     if lk:
         kb = min(lk, key=timed_ms.get)
-        kb_base, kb_prefix, kb_segments = split_plan_name(kb)
+        kb_base, kb_prefix, kb_segments, kb_sums = split_plan_name(kb)
         mu_c, pi_c, _ = cands[kb_base]
         fc = forms if kb == src else time_precisions(torch, qbe, ctx, qm, mu_c, pi_c, ("bf16x3", "bf16x6", "fp32"),
                                                      max(3, steps // 2), 1, want, keep=False, prefix=kb_prefix,
-                                                     segments=kb_segments)
+                                                     segments=kb_segments, max_sums=kb_sums)
         combined = {"plan": kb, "forms": {p: {k: v for k, v in f.items() if not k.startswith("_")}
                                           for p, f in fc.items()},
                     "speedup_vs_plain": {p: ev_p / f["ms_per_amplitude"] for p, f in fc.items()},
@@ -916,14 +928,16 @@ def main():
     if args.pmc_c3:
         qm, m = c3_model(qbe)
         cands = plan_candidates(qbe, qm, m, None)
-        base, use_prefix, use_segments = split_plan_name(args.plan)
+        base, use_prefix, use_segments, use_sums = split_plan_name(args.plan)
         if base not in cands:
-            raise SystemExit(f"--plan must be one of {sorted(cands)}, optionally followed by +prefix or +segments")
+            raise SystemExit(f"--plan must be one of {sorted(cands)}, optionally followed by +prefix or +segments "
+                             "and +sums<N>")
         mu, pi, _ = cands[base]
         plain = args.pmc_c3 == "plain_fp32"
         plan = qbe.Plan(qm, pi, mu, ctx=ctx, exec="per_step", precision="fp32" if plain else args.pmc_c3,
                         merge=not plain, fused_prefix=use_prefix and not plain,
-                        fused_segments=use_segments and not plain, fold_inputs=not plain)
+                        fused_segments=use_segments and not plain, fold_inputs=not plain,
+                        max_sums=0 if plain else use_sums)
         ws = plan.workspace()
         out = torch.zeros(2, dtype=torch.float64, device="cuda")
         if not plain:

@@ -135,7 +135,14 @@ typedef struct qbe_plan_opts {
                           regrouped); 1: every input tensor stays a factor
                           of its own.  The plan's schedule dump and cost
                           model are the caller's model's either way.       */
-  int32_t reserved[1]; /* must be zero                                       */
+  int32_t max_sums;    /* 0 (default): a merged per-step launch sums up to 4
+                          variables (2^4 terms per result entry); 1..4:
+                          at most that many (1: one launch per bucket, as
+                          no_merge for the per-step launches; fused levels
+                          still merge).  Fewer terms per entry cost more
+                          launches and device-memory round trips; which is
+                          faster depends on the plan.  Other values:
+                          QBE_ERR_INVALID_ARG                               */
 } qbe_plan_opts;
 
 typedef struct qbe_stats {

@@ -54,7 +54,7 @@ class QbeError(RuntimeError):
 class PlanOpts(C.Structure):
     _fields_ = [("exec", C.c_int32), ("precision", C.c_int32), ("block", C.c_int32),
                 ("no_merge", C.c_int32), ("fused_prefix", C.c_int32), ("fused_segments", C.c_int32),
-                ("no_fold", C.c_int32), ("reserved", C.c_int32 * 1)]
+                ("no_fold", C.c_int32), ("max_sums", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -486,7 +486,8 @@ class Plan:
 
     def __init__(self, model: Model, reduced_order: Sequence[int], mu: Sequence[int],
                  ctx: Optional[Context] = None, exec: str = "auto", precision: str = "fp32",
-                 merge: bool = True, fused_prefix=False, fused_segments: bool = False, fold_inputs: bool = True):
+                 merge: bool = True, fused_prefix=False, fused_segments: bool = False, fold_inputs: bool = True,
+                 max_sums: int = 0):
         o = _i32(reduced_order)
         u = _i32(mu)
         opts = PlanOpts()
@@ -498,6 +499,8 @@ class Plan:
         opts.fused_prefix = int(fused_prefix)
         opts.fused_segments = 1 if fused_segments else 0
         opts.no_fold = 0 if fold_inputs else 1
+        # summed variables a merged per-step launch may hold (0: default 4)
+        opts.max_sums = int(max_sums)
         h = _vp()
         _check(_lib.qbe_plan_create(ctx.handle if ctx else None, model.handle, _p32(o), len(o), _p32(u), len(u),
                                     C.byref(opts), C.byref(h)), "qbe_plan_create")

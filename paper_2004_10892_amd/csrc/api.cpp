@@ -678,7 +678,6 @@ int qbe_plan_create(qbe_ctx* ctx, const qbe_model* model, const int32_t* reduced
   *out = nullptr;
   qbe_plan_opts o{};
   if (opts) o = *opts;
-  for (int r : o.reserved) QBE_REQUIRE(r == 0, "reserved option fields must be zero");
   QBE_REQUIRE(o.exec >= QBE_EXEC_AUTO && o.exec <= QBE_EXEC_FUSED, "bad exec form");
   QBE_REQUIRE(o.precision >= QBE_PREC_FP32 && o.precision <= QBE_PREC_BF16X6, "bad precision");
   QBE_REQUIRE(o.block == 0 || o.block == qbe::kBlock, "unsupported block size");
@@ -687,6 +686,7 @@ int qbe_plan_create(qbe_ctx* ctx, const qbe_model* model, const int32_t* reduced
   QBE_REQUIRE(o.fused_segments == 0 || o.fused_segments == 1, "fused_segments must be 0 or 1");
   QBE_REQUIRE(o.fused_segments == 0 || o.fused_prefix > 0, "fused_segments needs fused_prefix > 0");
   QBE_REQUIRE(o.no_fold == 0 || o.no_fold == 1, "no_fold must be 0 or 1");
+  QBE_REQUIRE(o.max_sums >= 0 && o.max_sums <= 4, "max_sums must be in [0, 4]");
   auto* pl = new qbe_plan;
   std::unique_ptr<qbe_plan> guard(pl);
   qbe::Plan& p = pl->p;
@@ -711,6 +711,7 @@ int qbe_plan_create(qbe_ctx* ctx, const qbe_model* model, const int32_t* reduced
   if (o.no_fold == 0) (void)qbe::push_inputs(p.sched);
   p.precision = o.precision;
   p.merge = o.no_merge == 0;
+  p.max_sums = o.max_sums;
   p.want_prefix = o.exec != QBE_EXEC_FUSED ? o.fused_prefix : 0;
   p.want_segments = o.fused_segments == 1;
   qbe::compile_plan(p);

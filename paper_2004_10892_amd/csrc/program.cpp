@@ -229,7 +229,7 @@ struct StepNode {
   std::vector<Operand> factors;  // operands of the members except absorbed results
 };
 
-std::vector<StepNode> merge_chains(const Schedule& s, bool merge, const std::vector<char>& skip) {
+std::vector<StepNode> merge_chains(const Schedule& s, bool merge, const std::vector<char>& skip, int max_sums) {
   const int n = (int)s.steps.size();
   std::vector<StepNode> nd(n);
   std::vector<char> alive(n, 1);
@@ -244,7 +244,7 @@ std::vector<StepNode> merge_chains(const Schedule& s, bool merge, const std::vec
     if (c < 0 || !alive[k] || skip[c]) continue;
     const int rk = (int)s.steps[k].out.size(), rc = (int)s.steps[c].out.size();
     if (rk < kChainMinRank || rk < rc) continue;
-    if ((int)(nd[k].members.size() + nd[c].members.size()) > kChainSumMax) continue;
+    if ((int)(nd[k].members.size() + nd[c].members.size()) > std::min(max_sums, kChainSumMax)) continue;
     std::vector<Operand> f;
     for (const Operand& op : nd[c].factors)
       if (!(op.kind == 'r' && op.id == k)) f.push_back(op);
@@ -1001,7 +1001,7 @@ void compile_plan(Plan& p) {
     }
   // later segments: at their top bucket's place in schedule order, their
   // export placed like a launch's result, their imports then freed
-  const std::vector<StepNode> step_nodes = merge_chains(s, p.merge, fused_any);
+  const std::vector<StepNode> step_nodes = merge_chains(s, p.merge, fused_any, p.max_sums > 0 ? p.max_sums : kChainSumMax);
   std::vector<std::pair<int, int>> items;  // (schedule position, node index or -1 - segment)
   for (size_t i = 0; i < step_nodes.size(); ++i) items.push_back({step_nodes[i].members.back(), (int)i});
   for (size_t j = p.has_prefix ? 1 : 0; j < seg_code.size(); ++j) items.push_back({seg_last[j], -1 - (int)j});

@@ -143,6 +143,7 @@ struct Plan {
   int exec = 0;
   int precision = 0;
   bool merge = true;      // merge bucket chains (per-step launches, fused levels)
+  int max_sums = 0;       // summed variables a merged per-step launch may hold (0: the default, 4)
   int block = kBlock;
   int n_levels = 0;       // dependency depth of the buckets
   int fused_levels = 0;   // levels of the fused program (merged buckets)

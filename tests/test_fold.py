@@ -74,3 +74,27 @@ def test_no_fold_option_validation(c3):
                                   pm.ctypes.data_as(C.POINTER(C.c_int32)), len(pm), C.byref(o), C.byref(h))
     assert qbe.ERRORS[rc] == "INVALID_ARG"
     assert "no_fold" in qbe._lib.qbe_last_error().decode()
+
+
+def test_max_sums_caps_the_summed_variables_of_merged_launches(c3):
+    """qbe_plan_opts.max_sums: no per-step launch sums more variables than
+    the cap (1: one launch per bucket); the schedule and cost model stay."""
+    qbe, qm, mu, pi = c3
+    base = qbe.Plan(qm, pi, mu, exec="per_step")
+    assert max(l["n_sum"] for l in base.launches()) > 2
+    for cap in (1, 2, 3):
+        p = qbe.Plan(qm, pi, mu, exec="per_step", max_sums=cap)
+        p.check()
+        assert max(l["n_sum"] for l in p.launches()) <= cap
+        assert p.dump() == base.dump()
+        assert p.stats()["flops_per_slice"] == base.stats()["flops_per_slice"]
+    o = qbe.PlanOpts()
+    o.exec = qbe.EXEC["per_step"]
+    o.max_sums = 5
+    h = C.c_void_p()
+    po = np.asarray(pi, dtype=np.int32)
+    pm = np.asarray(mu, dtype=np.int32)
+    rc = qbe._lib.qbe_plan_create(None, qm.handle, po.ctypes.data_as(C.POINTER(C.c_int32)), len(po),
+                                  pm.ctypes.data_as(C.POINTER(C.c_int32)), len(pm), C.byref(o), C.byref(h))
+    assert qbe.ERRORS[rc] == "INVALID_ARG"
+    assert "max_sums" in qbe._lib.qbe_last_error().decode()
