@@ -242,8 +242,8 @@ STEP_SOURCES = ("device.hip", "device_common.hpp", "qbe_internal.hpp", "program.
 # dominant: the same for the dominant kernel's launch.  Keyed by the
 # sources' digest and the plan's sliced set.
 C3_COUNTERS = {
-    "sources_sha256": "a49be2ba65d037a8c903974205316ace22e0e2f843e920eaf068be2450abc11b",
-    "plan": "min_fill+tt_rec2_t16_s5+segments",
+    "sources_sha256": "646b28060a301cd2ef4e3166e9a337ccfadc6c9d2153da4d9fe639f4d27b9414",
+    "plan": "min_fill+tt_rec2_t16_s5+segments+sums2",
     "mu": [
         119,
         353,
@@ -257,26 +257,26 @@ C3_COUNTERS = {
         169
     ],
     "fp32": {
-        "mfma_util": 0.01013710051021158,
-        "mfma_busy_cycles": 8388608.0,
-        "gui_active": 6464965.0,
+        "mfma_util": 0.0,
+        "mfma_busy_cycles": 0.0,
+        "gui_active": 6523139.0,
         "amplitude": {
-            "bytes": 424542496,
-            "fetch_kib": 127880.125,
-            "write_kib": 158832.03125
+            "bytes": 518818336,
+            "fetch_kib": 141145.25,
+            "write_kib": 224368.03125
         },
         "dominant": {
             "launch": 0,
             "kernel": "qbe::fused_kernel",
-            "bytes": 39785600,
-            "fetch_kib": 5570.5625,
+            "bytes": 39787520,
+            "fetch_kib": 5571.5,
             "write_kib": 27712.0
         }
     },
     "bf16x6": {
-        "mfma_util": 0.010261037978143522,
-        "mfma_busy_cycles": 9437184.0,
-        "gui_active": 7185238.0
+        "mfma_util": 0.001160192865068805,
+        "mfma_busy_cycles": 1048576.0,
+        "gui_active": 7060895.0
     },
     "plain_fp32": {
         "mfma_util": 0.0
@@ -889,7 +889,7 @@ def main():
     ap.add_argument("--pmc-c3", choices=["fp32", "bf16x6", "bf16x3", "plain_fp32"],
                     help="for hardware-counter runs: the copy calibration, then the headline plan in this form "
                          "(sliced set from --mu, else tree-trimming), autotuned, and two contractions")
-    ap.add_argument("--plan", default="min_fill+tt_rec2_t16_s5+segments",
+    ap.add_argument("--plan", default="min_fill+tt_rec2_t16_s5+segments+sums2",
                     help="for --pmc-c3: a candidate plan of the headline search without the network "
                          "(min_fill or anytime8, + tt or tt_rec<k>_t<tries>_s<seed>), optionally followed by "
                          "+prefix or +segments")
