@@ -492,6 +492,58 @@ int qbe_contract_slices(qbe_ctx* ctx, const qbe_plan* plan, int64_t s_begin, int
 int qbe_contract_async(qbe_ctx* ctx, const qbe_plan* plan, void* d_workspace, size_t ws_bytes,
                        double* d_amp_out);
 
+/* ---------------------------------------------------------- slice ledger - */
+
+/* A host record of which slice ranges of one contraction are done and their
+ * FP64 partial sums, for recovery after a failure and for resuming an
+ * interrupted job.  The slices are independent subtasks (Sec. 2.4) whose
+ * sum is the result (Eq. 4), so a range whose result was lost or rejected is
+ * contracted again alone and the others are kept.  A ledger splits slices
+ * 0 .. n_slices-1 into ranges of range_size slices (the last one shorter):
+ * range i = [i * range_size, min(n_slices, (i + 1) * range_size)).  `tag` is
+ * the caller's 64-bit name of the work (circuit, bitstring, plan); the
+ * ledger stores it and never interprets it.  Host only: no call here except
+ * qbe_ledger_run touches a device. */
+typedef struct qbe_ledger qbe_ledger;
+/* QBE_ERR_INVALID_ARG unless n_slices >= 1 and range_size >= 1. */
+int qbe_ledger_create(int64_t n_slices, int64_t range_size, uint64_t tag, qbe_ledger** out);
+int qbe_ledger_destroy(qbe_ledger* ledger);
+/* Any output pointer may be NULL. */
+int qbe_ledger_info(const qbe_ledger* ledger, int64_t* n_slices, int64_t* range_size, uint64_t* tag,
+                    int64_t* n_ranges, int64_t* n_done);
+/* The lowest pending range: its index and slice bounds, or *idx_out = -1
+ * (bounds 0) when every range is done. */
+int qbe_ledger_next(const qbe_ledger* ledger, int64_t* idx_out, int64_t* s_begin_out, int64_t* s_end_out);
+/* Records range idx's partial sum partial[2] = (re, im).  QBE_ERR_INVALID_ARG
+ * (ledger unchanged) when idx is out of range, the range is already done, or
+ * a value is not finite (a failed contraction is not accepted as a result). */
+int qbe_ledger_record(qbe_ledger* ledger, int64_t idx, const double* partial);
+/* Marks range idx pending again (its result judged lost or wrong). */
+int qbe_ledger_drop(qbe_ledger* ledger, int64_t idx);
+/* *done_out = 1 and partial_out[2] = the recorded sum, or 0 and (0, 0). */
+int qbe_ledger_get(const qbe_ledger* ledger, int64_t idx, int32_t* done_out, double* partial_out);
+/* Contracts up to max_ranges pending ranges (all if max_ranges < 0), lowest
+ * first, each by qbe_contract_slices with the caller's workspace, recording
+ * each as it completes; *n_run_out (may be NULL) = ranges recorded by this
+ * call.  QBE_ERR_INVALID_ARG when the plan's 2^m differs from the ledger's
+ * n_slices.  When a range fails, the call returns that range's error code;
+ * the ranges recorded before it stay recorded, the failed one stays
+ * pending. */
+int qbe_ledger_run(qbe_ctx* ctx, const qbe_plan* plan, qbe_ledger* ledger, void* d_workspace, size_t ws_bytes,
+                   int64_t max_ranges, int64_t* n_run_out);
+/* amp_out[2] = the sum of the recorded partials in range order, in FP64.
+ * QBE_ERR_INVALID_ARG while any range is pending. */
+int qbe_ledger_sum(const qbe_ledger* ledger, double* amp_out);
+/* The ledger as a file at a caller path.  Layout (native little-endian): the
+ * 8 bytes "QBELDG01", int64 n_slices, int64 range_size, uint64 tag, then per
+ * range an int64 done flag (0 or 1) and two float64 (re, im).  Loading
+ * returns a new ledger; QBE_ERR_INVALID_ARG for a file that cannot be opened,
+ * written or read in full, has another magic or inconsistent sizes, a flag
+ * other than 0 or 1, or a non-finite recorded value, or has bytes after the
+ * last range. */
+int qbe_ledger_save(const qbe_ledger* ledger, const char* path);
+int qbe_ledger_load(const char* path, qbe_ledger** out);
+
 /* ------------------------------------------------ allocation-free entry - */
 
 /* For callers that cannot allocate device memory -- code under HIP graph

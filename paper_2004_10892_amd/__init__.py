@@ -160,6 +160,18 @@ _SIGS = {
                                           C.c_int32, _i32p, C.POINTER(C.c_float), C.c_float,
                                           C.POINTER(C.c_float), C.POINTER(C.c_float)]),
     "qbe_gnn_load": (C.c_int, [_vp, C.c_char_p]),
+    "qbe_ledger_create": (C.c_int, [C.c_int64, C.c_int64, C.c_uint64, C.POINTER(_vp)]),
+    "qbe_ledger_destroy": (C.c_int, [_vp]),
+    "qbe_ledger_info": (C.c_int, [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_uint64),
+                                  C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "qbe_ledger_next": (C.c_int, [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "qbe_ledger_record": (C.c_int, [_vp, C.c_int64, _f64p]),
+    "qbe_ledger_drop": (C.c_int, [_vp, C.c_int64]),
+    "qbe_ledger_get": (C.c_int, [_vp, C.c_int64, C.POINTER(C.c_int32), _f64p]),
+    "qbe_ledger_run": (C.c_int, [_vp, _vp, _vp, _vp, C.c_size_t, C.c_int64, C.POINTER(C.c_int64)]),
+    "qbe_ledger_sum": (C.c_int, [_vp, _f64p]),
+    "qbe_ledger_save": (C.c_int, [_vp, C.c_char_p]),
+    "qbe_ledger_load": (C.c_int, [C.c_char_p, C.POINTER(_vp)]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -670,6 +682,77 @@ class Batch:
     def close(self):
         if getattr(self, "handle", None) and _lib is not None:
             _lib.qbe_batch_destroy(self.handle)
+            self.handle = None
+
+    __del__ = close
+
+
+# ------------------------------------------------------------ slice ledger --
+
+class Ledger:
+    """Which slice ranges of one contraction are done, and their FP64
+    partial sums (the slices are independent, Sec. 2.4; their sum is the
+    result, Eq. 4): a lost range is contracted again alone, and an
+    interrupted job resumes from a saved ledger."""
+
+    def __init__(self, n_slices: int, range_size: int, tag: int = 0, _handle=None):
+        h = _handle
+        if h is None:
+            h = _vp()
+            _check(_lib.qbe_ledger_create(int(n_slices), int(range_size), int(tag), C.byref(h)), "qbe_ledger_create")
+        self.handle = h
+
+    @classmethod
+    def load(cls, path: str) -> "Ledger":
+        h = _vp()
+        _check(_lib.qbe_ledger_load(os.fsencode(path), C.byref(h)), "qbe_ledger_load")
+        return cls(0, 0, _handle=h)
+
+    def save(self, path: str):
+        _check(_lib.qbe_ledger_save(self.handle, os.fsencode(path)), "qbe_ledger_save")
+
+    def info(self) -> dict:
+        v = [C.c_int64(), C.c_int64(), C.c_uint64(), C.c_int64(), C.c_int64()]
+        _check(_lib.qbe_ledger_info(self.handle, *[C.byref(x) for x in v]), "qbe_ledger_info")
+        return dict(zip(("n_slices", "range_size", "tag", "n_ranges", "n_done"), (x.value for x in v)))
+
+    def next(self):
+        """(index, s_begin, s_end) of the lowest pending range, or None."""
+        v = [C.c_int64(), C.c_int64(), C.c_int64()]
+        _check(_lib.qbe_ledger_next(self.handle, *[C.byref(x) for x in v]), "qbe_ledger_next")
+        return None if v[0].value < 0 else tuple(x.value for x in v)
+
+    def record(self, idx: int, partial: complex):
+        p = np.array([partial.real, partial.imag], dtype=np.float64)
+        _check(_lib.qbe_ledger_record(self.handle, int(idx), p.ctypes.data_as(_f64p)), "qbe_ledger_record")
+
+    def drop(self, idx: int):
+        _check(_lib.qbe_ledger_drop(self.handle, int(idx)), "qbe_ledger_drop")
+
+    def get(self, idx: int):
+        """(done, partial sum) of range idx."""
+        d = C.c_int32()
+        p = np.zeros(2)
+        _check(_lib.qbe_ledger_get(self.handle, int(idx), C.byref(d), p.ctypes.data_as(_f64p)), "qbe_ledger_get")
+        return bool(d.value), complex(p[0], p[1])
+
+    def run(self, ctx: Context, plan: Plan, ws, max_ranges: int = -1) -> int:
+        """Contracts up to max_ranges pending ranges (all if < 0); returns
+        how many were recorded."""
+        n = C.c_int64()
+        w, nb = _workspace(ctx, ws)
+        _check(_lib.qbe_ledger_run(ctx.handle, plan.handle, self.handle, w, nb, int(max_ranges), C.byref(n)),
+               "qbe_ledger_run")
+        return n.value
+
+    def sum(self) -> complex:
+        out = np.zeros(2)
+        _check(_lib.qbe_ledger_sum(self.handle, out.ctypes.data_as(_f64p)), "qbe_ledger_sum")
+        return complex(out[0], out[1])
+
+    def close(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.qbe_ledger_destroy(self.handle)
             self.handle = None
 
     __del__ = close

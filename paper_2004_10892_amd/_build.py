@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqbe.so")
 
-SOURCES = ["planner.cpp", "program.cpp", "program_check.cpp", "api.cpp", "device.hip", "fused.hip", "gnn.hip", "permute.hip"]
+SOURCES = ["planner.cpp", "program.cpp", "program_check.cpp", "api.cpp", "ledger.cpp", "device.hip", "fused.hip", "gnn.hip", "permute.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950",
