@@ -6,8 +6,8 @@
 // shared by two linear heads s_h = H_3 w_h + c_h: head 0 scores variables
 // for slicing (Alg. 2), head 1 for elimination (ties of greedy min-fill).
 // The dense layers and their gradients run on MFMA (v_mfma_f32_16x16x4f32:
-// FP32 activations times the FP16 weights widened exactly to FP32, staged
-// in LDS).  Weights are FP16 in the forward and
+// FP32 activations times the FP16 weights widened exactly to FP32).
+// Weights are FP16 in the forward and
 // backward passes (FP32 master copies for the optimizer); every sum is
 // accumulated in FP32.  Training minimises the mean squared error between s
 // and a target at a set of candidate variables.  All reductions run in a
@@ -80,86 +80,77 @@ __global__ void gnn_agg_t(const float* __restrict__ dHs, const float* __restrict
 
 // The dense layer as matrix products on MFMA: [H | M] (n x 2 din, FP32)
 // times [Ws ; Wn] (2 din x 64, the FP16 weights widened to FP32 -- exact),
-// v_mfma_f32_16x16x4f32 with FP32 accumulation.  A workgroup stages the
-// layer's weights in LDS once and its four waves take 16 vertices each; a
-// wave accumulates its 16 x 64 block in four 16 x 16 tiles over K in steps
-// of 4.  Lane l supplies A[row l % 16][k = l / 16] and B[k][col l % 16] and
-// receives C[4 (l / 16) + j][l % 16], j = 0..3 (the layout mm_kernel uses).
+// v_mfma_f32_16x16x4f32 with FP32 accumulation.  A workgroup takes 16
+// vertices and each of its four waves one 16 x 16 tile of the 64 outputs,
+// accumulated over K in steps of 4; the weights are read straight from the
+// (cached) FP16 copy, so every workgroup starts at once and a layer of n
+// vertices runs n / 16 of them.  Lane l supplies A[row l % 16][k = l / 16]
+// and B[k][col l % 16] and receives C[4 (l / 16) + j][l % 16], j = 0..3
+// (the layout mm_kernel uses).
 typedef float gnn_f4 __attribute__((ext_vector_type(4)));
-constexpr int kGnnRows = 64;  // vertices per workgroup (4 waves x 16)
+constexpr int kGnnRows = 16;  // vertices per workgroup
 
 __global__ __launch_bounds__(256) void gnn_dense_mfma(const float* __restrict__ Hin, const float* __restrict__ Min,
                                                       const __half* __restrict__ w, int din, int n,
                                                       float* __restrict__ Z, float* __restrict__ Hout) {
-  __shared__ float wl[2 * kGnnHidden * kGnnHidden];  // [k][o], k < din: Ws, else Wn
-  __shared__ float bl[kGnnHidden];
-  const int tid = threadIdx.x;
-  for (int i = tid; i < 2 * din * kGnnHidden; i += 256) wl[i] = __half2float(w[i]);
-  if (tid < kGnnHidden) bl[tid] = __half2float(w[2 * din * kGnnHidden + tid]);
-  __syncthreads();
-  const int lane = tid & 63, row = lane & 15, grp = lane >> 4;
-  const int v0 = blockIdx.x * kGnnRows + (tid >> 6) * 16;
-  if (v0 >= n) return;
+  const int tid = threadIdx.x, lane = tid & 63, row = lane & 15, grp = lane >> 4, c = tid >> 6;
+  const int v0 = blockIdx.x * kGnnRows;
   const int vr = v0 + row;
   const bool ok = vr < n;
-  gnn_f4 acc[4];
-#pragma unroll
-  for (int c = 0; c < 4; ++c) acc[c] = gnn_f4{0.f, 0.f, 0.f, 0.f};
+  gnn_f4 acc = gnn_f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 8
   for (int kb = 0; kb < 2 * din; kb += 4) {
     const int k = kb + grp;
     const float a = ok ? (k < din ? Hin[(int64_t)vr * din + k] : Min[(int64_t)vr * din + (k - din)]) : 0.f;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, wl[k * kGnnHidden + c * 16 + row], acc[c], 0, 0, 0);
+    const float b = __half2float(w[k * kGnnHidden + c * 16 + row]);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
   }
+  const int o = c * 16 + row;
+  const float bias = __half2float(w[2 * din * kGnnHidden + o]);
 #pragma unroll
-  for (int c = 0; c < 4; ++c)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int v = v0 + 4 * grp + j;
-      if (v >= n) continue;
-      const int o = c * 16 + row;
-      const float z = acc[c][j] + bl[o];
-      Z[(int64_t)v * kGnnHidden + o] = z;
-      Hout[(int64_t)v * kGnnHidden + o] = z > 0.f ? z : 0.f;
-    }
+  for (int j = 0; j < 4; ++j) {
+    const int v = v0 + 4 * grp + j;
+    if (v >= n) continue;
+    const float z = acc[j] + bias;
+    Z[(int64_t)v * kGnnHidden + o] = z;
+    Hout[(int64_t)v * kGnnHidden + o] = z > 0.f ? z : 0.f;
+  }
 }
 
 // dHs = dZ Ws^T and dM = dZ Wn^T (din = 64) on MFMA: A = dZ (n x 64), B[o][k]
-// = the weight of input k to output o; a wave computes 16 vertices x 128
-// columns (64 of dHs, 64 of dM) in eight 16 x 16 tiles.
+// = the weight of input k to output o.  A workgroup takes 16 vertices x 128
+// columns (64 of dHs, 64 of dM) in eight 16 x 16 tiles, two per wave; the
+// weights are read from the FP16 copy as in the forward.
 __global__ __launch_bounds__(256) void gnn_dense_back_x_mfma(const float* __restrict__ dZ,
                                                              const __half* __restrict__ w, int n,
                                                              float* __restrict__ dHs, float* __restrict__ dM) {
-  __shared__ float wl[2 * kGnnHidden * kGnnHidden];  // [k][o] as in the forward
-  const int tid = threadIdx.x;
-  for (int i = tid; i < 2 * kGnnHidden * kGnnHidden; i += 256) wl[i] = __half2float(w[i]);
-  __syncthreads();
-  const int lane = tid & 63, row = lane & 15, grp = lane >> 4;
-  const int v0 = blockIdx.x * kGnnRows + (tid >> 6) * 16;
-  if (v0 >= n) return;
+  const int tid = threadIdx.x, lane = tid & 63, row = lane & 15, grp = lane >> 4, c0 = 2 * (tid >> 6);
+  const int v0 = blockIdx.x * kGnnRows;
   const int vr = v0 + row;
   const bool ok = vr < n;
-  gnn_f4 acc[8];
+  gnn_f4 acc[2];
 #pragma unroll
-  for (int c = 0; c < 8; ++c) acc[c] = gnn_f4{0.f, 0.f, 0.f, 0.f};
+  for (int t = 0; t < 2; ++t) acc[t] = gnn_f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
   for (int ob = 0; ob < kGnnHidden; ob += 4) {
     const int o = ob + grp;
     const float a = ok ? dZ[(int64_t)vr * kGnnHidden + o] : 0.f;
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
+    for (int t = 0; t < 2; ++t) {
       // column c * 16 + row: input k of Ws (c < 4) or of Wn (c >= 4)
-      const int k = (c & 3) * 16 + row;
-      acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, wl[((c >> 2) * kGnnHidden + k) * kGnnHidden + o], acc[c], 0, 0, 0);
+      const int c = c0 + t, k = (c & 3) * 16 + row;
+      const float b = __half2float(w[((c >> 2) * kGnnHidden + k) * kGnnHidden + o]);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
     }
   }
 #pragma unroll
-  for (int c = 0; c < 8; ++c)
+  for (int t = 0; t < 2; ++t)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int v = v0 + 4 * grp + j;
       if (v >= n) continue;
-      const int k = (c & 3) * 16 + row;
-      (c < 4 ? dHs : dM)[(int64_t)v * kGnnHidden + k] = acc[c][j];
+      const int c = c0 + t, k = (c & 3) * 16 + row;
+      (c < 4 ? dHs : dM)[(int64_t)v * kGnnHidden + k] = acc[t][j];
     }
 }
 
@@ -215,7 +206,10 @@ constexpr int kGnnChunk = 64;
 // Partial of layer l's gradient over chunk blockIdx.x: row k of [Ws ; Wn]
 // (input k of H for k < din, of M after), P[k][o] = sum_v X[v][k] dZ[v][o]
 // on MFMA (A = a 16 x 4 tile of X^T, B = a 4 x 16 tile of dZ, vertices as
-// the contraction), and the bias row P[2 din][o] = sum_v dZ[v][o].
+// the contraction), and the bias row P[2 din][o] = sum_v dZ[v][o].  The
+// (2 din / 16) x 4 tiles of 16 x 16 go one to a wave, four to a workgroup
+// along blockIdx.y (a chunk's tiles run side by side, not one after another
+// in a wave); the bias row is summed by the blockIdx.y = 0 workgroup.
 __global__ __launch_bounds__(256) void gnn_dense_back_w_part(const float* __restrict__ Hin,
                                                              const float* __restrict__ Min,
                                                              const float* __restrict__ dZ, int din, int n,
@@ -224,10 +218,12 @@ __global__ __launch_bounds__(256) void gnn_dense_back_w_part(const float* __rest
   const int vb0 = blockIdx.x * kGnnChunk, ve = min(n, vb0 + kGnnChunk);
   const int rows = 2 * din, len = (rows + 1) * kGnnHidden;
   float* P = part + (int64_t)blockIdx.x * len;
-  for (int tile = tid >> 6; tile < (rows / 16) * 4; tile += 4) {
+  const int tile = (int)blockIdx.y * 4 + (tid >> 6);
+  if (tile < (rows / 16) * 4) {
     const int rt = tile >> 2, ct = tile & 3;
     const int k = rt * 16 + row;
     gnn_f4 acc = gnn_f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
     for (int vb = vb0; vb < ve; vb += 4) {
       const int v = vb + grp;
       const bool ok = v < ve;
@@ -238,8 +234,9 @@ __global__ __launch_bounds__(256) void gnn_dense_back_w_part(const float* __rest
 #pragma unroll
     for (int j = 0; j < 4; ++j) P[(rt * 16 + 4 * grp + j) * kGnnHidden + ct * 16 + row] = acc[j];
   }
-  if (tid < kGnnHidden) {
+  if (blockIdx.y == 0 && tid < kGnnHidden) {
     float sb = 0.f;
+#pragma unroll 8
     for (int v = vb0; v < ve; ++v) sb += dZ[(int64_t)v * kGnnHidden + tid];
     P[rows * kGnnHidden + tid] = sb;
   }
@@ -254,6 +251,7 @@ __global__ __launch_bounds__(128) void gnn_head_back_w_part(const float* __restr
   if (o > kGnnHidden) return;
   const int vb0 = blockIdx.x * kGnnChunk, ve = min(n, vb0 + kGnnChunk);
   float a = 0.f;
+#pragma unroll 8
   for (int v = vb0; v < ve; ++v) a += dS[v] * (o < kGnnHidden ? H[(int64_t)v * kGnnHidden + o] : 1.f);
   part[(int64_t)blockIdx.x * (kGnnHidden + 1) + o] = a;
 }
@@ -263,6 +261,7 @@ __global__ void gnn_sum_parts(const float* __restrict__ part, int n_parts, int l
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= len) return;
   float a = 0.f;
+#pragma unroll 8
   for (int c = 0; c < n_parts; ++c) a += part[(int64_t)c * len + i];
   g[i] = a;
 }
@@ -477,7 +476,8 @@ int gnn_train_step(Gnn& g, void* stream, int head, int n, const int* rp, const i
   for (int l = kGnnLayers - 1; l >= 0; --l) {
     const int din = gnn_din(l);
     gnn_relu_back<<<blocks((int64_t)n * kGnnHidden), 256, 0, st>>>(dH, b.Z[l], (int64_t)n * kGnnHidden);
-    gnn_dense_back_w_part<<<n_parts, 256, 0, st>>>(b.H[l], b.M[l], dH, din, n, b.part);
+    gnn_dense_back_w_part<<<dim3(n_parts, (2 * din / 16 * 4 + 3) / 4), 256, 0, st>>>(b.H[l], b.M[l], dH, din, n,
+                                                                                    b.part);
     gnn_sum_parts<<<blocks(gnn_layer_size(l)), 256, 0, st>>>(b.part, n_parts, gnn_layer_size(l),
                                                            grad + gnn_layer_off(l));
     if (l > 0) {
