@@ -121,17 +121,31 @@ __device__ __forceinline__ uint32_t pdep32(uint32_t v, uint32_t m) {
   return r;
 }
 
+// XCDs of the chip (workgroups are dealt to them round robin)
+constexpr uint32_t kXcds = 8;
+
+// The workgroup's number with one XCD's workgroups (each XCD has its own
+// L2) numbered consecutively: workgroup b becomes (b mod 8) * (grid / 8) +
+// b / 8; the last (grid mod 8) workgroups keep their own number.  Loops
+// that start at this number and step by the grid give neighbouring work --
+// the tiles of one slice, which read the same factor lines -- to one L2 at
+// the same time.
+__device__ __forceinline__ uint32_t xcd_major_block() {
+  const uint32_t n_wg = gridDim.x, per_xcd = n_wg / kXcds;
+  return blockIdx.x < per_xcd * kXcds ? (blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds : blockIdx.x;
+}
+
 // Tiling of step_kernel and msum_kernel (r >= kLoBits).  A tile is 256
 // consecutive result entries of one slice: the lane supplies x_lo (the low 8
 // bits of x), the tile the slice g and x_hi.  A super-tile is EPT tiles that
-// differ only in the lowest bits of x_hi (EPT divides 2^hib); the block takes
-// super-tiles q = blockIdx.x + j * gridDim.x.  An operand's entry offset is
-// linear over disjoint bit sets, so it splits into a per-lane part (x_lo and
-// the sub-tile bits, fixed for the kernel) and a per-super-tile part (slice
-// and the rest of x_hi).  The per-super-tile addresses of 64 super-tiles at a
-// time are worked out in vector code, lane l taking the l-th of them, and the
-// tile loop reads them back with readlane: the per-tile index work is off
-// the scalar unit.
+// differ only in the lowest bits of x_hi (EPT divides 2^hib); the block
+// takes super-tiles q = xcd_major_block() + j * gridDim.x.  An operand's
+// entry offset is linear over disjoint bit sets, so it splits into a
+// per-lane part (x_lo and the sub-tile bits, fixed for the kernel) and a
+// per-super-tile part (slice and the rest of x_hi).  The per-super-tile
+// addresses of 64 super-tiles at a time are worked out in vector code, lane
+// l taking the l-th of them, and the tile loop reads them back with
+// readlane: the per-tile index work is off the scalar unit.
 // PAIR (EPT = 2): the two tiles differ in x bit 0 instead and the lane
 // supplies bits 1-8; the super-tile bits are the same.
 template <int K, int EPT, bool PAIR = false>
@@ -207,7 +221,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepLaunch a) {
 #pragma unroll
   for (int i = 0; i < K; ++i)
     ustep[i] = (a.sum_u && ((a.mask[i] >> r) & 1u)) ? (uint64_t(1) << (a.rank[i] - 1)) * 8u : 0u;
-  for (int64_t q0 = blockIdx.x; q0 < ts.n_super; q0 += 64 * (int64_t)gridDim.x) {
+  for (int64_t q0 = xcd_major_block(); q0 < ts.n_super; q0 += 64 * (int64_t)gridDim.x) {
     uint64_t pl[K], ol;
     ts.decode(a, q0, lane, pl, ol);
     const int n_here = ts.count(q0);
@@ -252,7 +266,7 @@ __global__ __launch_bounds__(kBlock) void msum_kernel(StepLaunch a) {
   const int tid = threadIdx.x, lane = tid & 63;
   const TileSetup<K, EPT> ts(a, (uint32_t)tid);
   const int nu = 1 << a.n_sum;
-  for (int64_t q0 = blockIdx.x; q0 < ts.n_super; q0 += 64 * (int64_t)gridDim.x) {
+  for (int64_t q0 = xcd_major_block(); q0 < ts.n_super; q0 += 64 * (int64_t)gridDim.x) {
     uint64_t pl[K], ol;
     ts.decode(a, q0, lane, pl, ol);
     const int n_here = ts.count(q0);
@@ -342,7 +356,7 @@ __global__ __launch_bounds__(kBlock) void step_pair_kernel(StepLaunch a) {
 #pragma unroll
   for (int i = 0; i < K; ++i)
     ustep[i] = (a.sum_u && ((a.mask[i] >> r) & 1u)) ? (uint64_t(1) << (a.rank[i] - 1)) * 8u : 0u;
-  for (int64_t q0 = blockIdx.x; q0 < ts.n_super; q0 += 64 * (int64_t)gridDim.x) {
+  for (int64_t q0 = xcd_major_block(); q0 < ts.n_super; q0 += 64 * (int64_t)gridDim.x) {
     uint64_t pl[K], ol;
     ts.decode(a, q0, lane, pl, ol);
     const int n_here = ts.count(q0);
@@ -394,7 +408,7 @@ __global__ __launch_bounds__(kBlock) void msum_pair_kernel(StepLaunch a) {
   const int tid = threadIdx.x, lane = tid & 63;
   const TileSetup<K, 2, true> ts(a, (uint32_t)tid);
   const int nu = 1 << a.n_sum;
-  for (int64_t q0 = blockIdx.x; q0 < ts.n_super; q0 += 64 * (int64_t)gridDim.x) {
+  for (int64_t q0 = xcd_major_block(); q0 < ts.n_super; q0 += 64 * (int64_t)gridDim.x) {
     uint64_t pl[K], ol;
     ts.decode(a, q0, lane, pl, ol);
     const int n_here = ts.count(q0);
@@ -941,8 +955,6 @@ __global__ __launch_bounds__(kBlock) void mmk_kernel(MmkLaunch a) {
 // weights.  LDS rows are padded by 16 entries so that the four term groups
 // of an MFMA operand read fall in different banks.
 constexpr int kMmbMaxM = 7, kMmbMaxN = 6, kMmbPad = 16, kMmbBig = 4;
-// XCDs of the chip (workgroups are dealt to them round robin)
-constexpr uint32_t kXcds = 8;
 // entries a thread stages per block: 2^(J + MB) / 256 <= 2^(4 + 7 - 8) of
 // A', 2^(J + NB) / 256 <= 2^(4 + 6 - 8) of B'
 constexpr int kMmbStageA = 8, kMmbStageB = 4;
@@ -1021,14 +1033,9 @@ __global__ __launch_bounds__(kBlock) void mmb_kernel(MmbLaunch a) {
   for (int i = 0; i < NA + NBF; ++i)
     part[i] = pext32(i >= NA ? pdep32((uint32_t)nb, a.bn) : pdep32((uint32_t)ma, a.bm), a.big[i].mk);
   const int tiles_m = Mn >> 4, n_tiles = tiles_m * (Nn >> 4);
-  // workgroups are dealt to the XCDs (each with its own L2) round robin:
-  // renumber them so that one XCD's workgroups hold consecutive numbers;
   // step i takes block number + i * grid, so that neighbouring blocks, whose
   // factor entries share cache lines, run at the same time behind one L2
-  const uint32_t n_wg = gridDim.x, per_xcd = n_wg / kXcds;
-  const uint32_t wnum = blockIdx.x < per_xcd * kXcds ? (blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds
-                                                     : blockIdx.x;
-  for (int64_t blk = wnum; blk < a.n_blocks; blk += n_wg) {
+  for (int64_t blk = xcd_major_block(); blk < a.n_blocks; blk += gridDim.x) {
     const int64_t g = blk >> a.rest_bits;
     const uint32_t xt = pdep32((uint32_t)(blk & ((int64_t(1) << a.rest_bits) - 1)), a.rest);
     const uint32_t sl = (uint32_t)(a.s0 + g);
