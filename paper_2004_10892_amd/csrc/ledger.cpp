@@ -88,59 +88,69 @@ int qbe_ledger_destroy(qbe_ledger* ledger) {
 
 int qbe_ledger_info(const qbe_ledger* l, int64_t* n_slices, int64_t* range_size, uint64_t* tag, int64_t* n_ranges,
                     int64_t* n_done) {
-  LEDGER_REQUIRE(l, "NULL ledger");
-  if (n_slices) *n_slices = l->n_slices;
-  if (range_size) *range_size = l->range_size;
-  if (tag) *tag = l->tag;
-  if (n_ranges) *n_ranges = l->n_ranges();
-  if (n_done) {
-    int64_t k = 0;
-    for (uint8_t d : l->done) k += d;
-    *n_done = k;
-  }
-  return QBE_OK;
+  return guarded([&]() -> int {
+    LEDGER_REQUIRE(l, "NULL ledger");
+    if (n_slices) *n_slices = l->n_slices;
+    if (range_size) *range_size = l->range_size;
+    if (tag) *tag = l->tag;
+    if (n_ranges) *n_ranges = l->n_ranges();
+    if (n_done) {
+      int64_t k = 0;
+      for (uint8_t d : l->done) k += d;
+      *n_done = k;
+    }
+    return (int)QBE_OK;
+  });
 }
 
 int qbe_ledger_next(const qbe_ledger* l, int64_t* idx_out, int64_t* s_begin_out, int64_t* s_end_out) {
-  LEDGER_REQUIRE(l && idx_out && s_begin_out && s_end_out, "NULL argument");
-  *idx_out = -1;
-  *s_begin_out = *s_end_out = 0;
-  for (int64_t i = 0; i < l->n_ranges(); ++i)
-    if (!l->done[i]) {
-      *idx_out = i;
-      bounds(*l, i, s_begin_out, s_end_out);
-      break;
-    }
-  return QBE_OK;
+  return guarded([&]() -> int {
+    LEDGER_REQUIRE(l && idx_out && s_begin_out && s_end_out, "NULL argument");
+    *idx_out = -1;
+    *s_begin_out = *s_end_out = 0;
+    for (int64_t i = 0; i < l->n_ranges(); ++i)
+      if (!l->done[i]) {
+        *idx_out = i;
+        bounds(*l, i, s_begin_out, s_end_out);
+        break;
+      }
+    return (int)QBE_OK;
+  });
 }
 
 int qbe_ledger_record(qbe_ledger* l, int64_t idx, const double* partial) {
-  LEDGER_REQUIRE(l && partial, "NULL argument");
-  LEDGER_REQUIRE(0 <= idx && idx < l->n_ranges(), "range index out of range");
-  LEDGER_REQUIRE(!l->done[idx], "range " + std::to_string(idx) + " is already recorded");
-  LEDGER_REQUIRE(std::isfinite(partial[0]) && std::isfinite(partial[1]),
-                 "partial sum of range " + std::to_string(idx) + " is not finite");
-  l->partial[2 * idx] = partial[0];
-  l->partial[2 * idx + 1] = partial[1];
-  l->done[idx] = 1;
-  return QBE_OK;
+  return guarded([&]() -> int {
+    LEDGER_REQUIRE(l && partial, "NULL argument");
+    LEDGER_REQUIRE(0 <= idx && idx < l->n_ranges(), "range index out of range");
+    LEDGER_REQUIRE(!l->done[idx], "range " + std::to_string(idx) + " is already recorded");
+    LEDGER_REQUIRE(std::isfinite(partial[0]) && std::isfinite(partial[1]),
+                   "partial sum of range " + std::to_string(idx) + " is not finite");
+    l->partial[2 * idx] = partial[0];
+    l->partial[2 * idx + 1] = partial[1];
+    l->done[idx] = 1;
+    return (int)QBE_OK;
+  });
 }
 
 int qbe_ledger_drop(qbe_ledger* l, int64_t idx) {
-  LEDGER_REQUIRE(l, "NULL ledger");
-  LEDGER_REQUIRE(0 <= idx && idx < l->n_ranges(), "range index out of range");
-  l->done[idx] = 0;
-  l->partial[2 * idx] = l->partial[2 * idx + 1] = 0.0;
-  return QBE_OK;
+  return guarded([&]() -> int {
+    LEDGER_REQUIRE(l, "NULL ledger");
+    LEDGER_REQUIRE(0 <= idx && idx < l->n_ranges(), "range index out of range");
+    l->done[idx] = 0;
+    l->partial[2 * idx] = l->partial[2 * idx + 1] = 0.0;
+    return (int)QBE_OK;
+  });
 }
 
 int qbe_ledger_get(const qbe_ledger* l, int64_t idx, int32_t* done_out, double* partial_out) {
-  LEDGER_REQUIRE(l && done_out && partial_out, "NULL argument");
-  LEDGER_REQUIRE(0 <= idx && idx < l->n_ranges(), "range index out of range");
-  *done_out = l->done[idx];
-  partial_out[0] = l->partial[2 * idx];
-  partial_out[1] = l->partial[2 * idx + 1];
-  return QBE_OK;
+  return guarded([&]() -> int {
+    LEDGER_REQUIRE(l && done_out && partial_out, "NULL argument");
+    LEDGER_REQUIRE(0 <= idx && idx < l->n_ranges(), "range index out of range");
+    *done_out = l->done[idx];
+    partial_out[0] = l->partial[2 * idx];
+    partial_out[1] = l->partial[2 * idx + 1];
+    return (int)QBE_OK;
+  });
 }
 
 int qbe_ledger_run(qbe_ctx* ctx, const qbe_plan* plan, qbe_ledger* l, void* d_workspace, size_t ws_bytes,
@@ -171,18 +181,20 @@ int qbe_ledger_run(qbe_ctx* ctx, const qbe_plan* plan, qbe_ledger* l, void* d_wo
 }
 
 int qbe_ledger_sum(const qbe_ledger* l, double* amp_out) {
-  LEDGER_REQUIRE(l && amp_out, "NULL argument");
-  int64_t pending = 0;
-  for (uint8_t d : l->done) pending += !d;
-  LEDGER_REQUIRE(pending == 0, std::to_string(pending) + " ranges pending");
-  double re = 0.0, im = 0.0;
-  for (int64_t i = 0; i < l->n_ranges(); ++i) {
-    re += l->partial[2 * i];
-    im += l->partial[2 * i + 1];
-  }
-  amp_out[0] = re;
-  amp_out[1] = im;
-  return QBE_OK;
+  return guarded([&]() -> int {
+    LEDGER_REQUIRE(l && amp_out, "NULL argument");
+    int64_t pending = 0;
+    for (uint8_t d : l->done) pending += !d;
+    LEDGER_REQUIRE(pending == 0, std::to_string(pending) + " ranges pending");
+    double re = 0.0, im = 0.0;
+    for (int64_t i = 0; i < l->n_ranges(); ++i) {
+      re += l->partial[2 * i];
+      im += l->partial[2 * i + 1];
+    }
+    amp_out[0] = re;
+    amp_out[1] = im;
+    return (int)QBE_OK;
+  });
 }
 
 int qbe_ledger_save(const qbe_ledger* l, const char* path) {
