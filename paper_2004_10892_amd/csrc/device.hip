@@ -2066,6 +2066,9 @@ int launch_reduce(const double2* v, const int64_t* ranges, int64_t n_single, dou
 // Largest log2(slices x result entries) of a step that the batch runs in
 // its level's group launch although the plan launches it alone.
 constexpr int kWideGroupMaxLog2 = 22;
+// Side streams over which a level's launches of per-step batch instances
+// are dealt (with the caller's stream: four, the process's hardware queues).
+constexpr size_t kWideSideStreams = 3;
 
 int step_batch_build(Batch& b) {
   b.wide_off.clear();
@@ -2082,7 +2085,9 @@ int step_batch_build(Batch& b) {
     for (int lv : p.step_level) n_lv = std::max(n_lv, lv + 1);
   }
   b.wide_ws = off;
+  b.wide_level.clear();
   for (int L = 0; L < n_lv; ++L) {
+    const int32_t lv0 = (int32_t)b.wide_order.size();
     std::vector<WideGroupStep> grp;
     for (size_t q = 0; q < b.wide.size(); ++q) {
       const Plan& p = *b.plans[b.wide[q]];
@@ -2124,18 +2129,21 @@ int step_batch_build(Batch& b) {
         }
       }
     }
-    if (grp.empty()) continue;
-    const int g = (int)b.wide_first.size() - 1;
-    uint64_t units = 0;
-    b.wide_prefix.push_back(0);
-    for (const WideGroupStep& d : grp) {
-      units += (uint64_t)d.tiles * (uint64_t)((d.G + d.sb - 1) / d.sb);
-      b.wide_prefix.push_back(units);
-      b.wide_steps.push_back(d);
+    if (!grp.empty()) {
+      const int g = (int)b.wide_first.size() - 1;
+      uint64_t units = 0;
+      b.wide_prefix.push_back(0);
+      for (const WideGroupStep& d : grp) {
+        units += (uint64_t)d.tiles * (uint64_t)((d.G + d.sb - 1) / d.sb);
+        b.wide_prefix.push_back(units);
+        b.wide_steps.push_back(d);
+      }
+      b.wide_first.push_back((int32_t)b.wide_steps.size());
+      b.wide_order.push_back(WideItem{-1, -1, g});
     }
-    b.wide_first.push_back((int32_t)b.wide_steps.size());
-    b.wide_order.push_back(WideItem{-1, -1, g});
+    if ((int32_t)b.wide_order.size() > lv0) b.wide_level.push_back(lv0);
   }
+  b.wide_level.push_back((int32_t)b.wide_order.size());
   if (!b.wide.empty()) {
     std::vector<WideFinal> fin;
     for (size_t q = 0; q < b.wide.size(); ++q) {
@@ -2164,6 +2172,22 @@ int step_batch_build(Batch& b) {
     std::memcpy(buf.data() + sb, b.wide_prefix.data(), b.wide_prefix.size() * 8);
     int rc = upload(&b.d_wide, buf.data(), buf.size());
     if (rc) return rc;
+  }
+  size_t widest = 0;
+  for (size_t v = 0; v + 1 < b.wide_level.size(); ++v)
+    widest = std::max<size_t>(widest, (size_t)(b.wide_level[v + 1] - b.wide_level[v]));
+  const size_t n_side = std::min<size_t>(kWideSideStreams, widest > 0 ? widest - 1 : 0);
+  if (n_side > 0) {
+    hipEvent_t e = nullptr;
+    QBE_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    b.ev_fork = e;
+    for (size_t i = 0; i < n_side; ++i) {
+      hipStream_t s = nullptr;
+      QBE_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+      b.side.push_back(s);
+      QBE_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      b.ev_join.push_back(e);
+    }
   }
   return QBE_OK;
 }
@@ -2198,16 +2222,34 @@ int dev_batch_contract(const Batch& b, void* stream, void* ws, size_t ws_bytes, 
     if (rc) return rc;
   }
   char* wide_ws = w + ws_head(b.n_items);
-  for (const WideItem& it : b.wide_order) {
-    int rc;
-    if (it.group < 0) {
-      const Plan& p = *b.plans[b.wide[it.plan]];
-      float2* arena = (float2*)(wide_ws + b.wide_off[it.plan] + ws_head(p.n_slices));
-      rc = launch_step(p, p.steps[it.step], arena, p.n_slices, 0, st);
-    } else {
-      rc = launch_wide_group(b, it.group, wide_ws, st);
+  for (size_t v = 0; v + 1 < b.wide_level.size(); ++v) {
+    // a level's launches have no memory hazard with one another: deal them
+    // over the caller's stream and up to n side streams, which start after
+    // everything the caller's stream holds and rejoin it at the level's end
+    const int32_t i0 = b.wide_level[v], i1 = b.wide_level[v + 1];
+    const int n = (int)std::min<size_t>(b.side.size(), (size_t)(i1 - i0 - 1));
+    if (n > 0) {
+      QBE_HIP(hipEventRecord((hipEvent_t)b.ev_fork, st));
+      for (int s = 0; s < n; ++s) QBE_HIP(hipStreamWaitEvent((hipStream_t)b.side[s], (hipEvent_t)b.ev_fork, 0));
     }
-    if (rc) return rc;
+    for (int32_t j = i0; j < i1; ++j) {
+      const int k = (j - i0) % (n + 1);
+      hipStream_t sj = k == 0 ? st : (hipStream_t)b.side[k - 1];
+      const WideItem& it = b.wide_order[j];
+      int rc;
+      if (it.group < 0) {
+        const Plan& p = *b.plans[b.wide[it.plan]];
+        float2* arena = (float2*)(wide_ws + b.wide_off[it.plan] + ws_head(p.n_slices));
+        rc = launch_step(p, p.steps[it.step], arena, p.n_slices, 0, sj);
+      } else {
+        rc = launch_wide_group(b, it.group, wide_ws, sj);
+      }
+      if (rc) return rc;
+    }
+    for (int s = 0; s < n; ++s) {
+      QBE_HIP(hipEventRecord((hipEvent_t)b.ev_join[s], (hipStream_t)b.side[s]));
+      QBE_HIP(hipStreamWaitEvent(st, (hipEvent_t)b.ev_join[s], 0));
+    }
   }
   if (!b.wide.empty()) {
     wide_final_kernel<<<(unsigned)b.wide.size(), 256, 0, st>>>((const WideFinal*)b.d_wide_final,

@@ -691,6 +691,12 @@ void dev_batch_free(Batch& b) {
     if (*q) (void)hipFree(*q);
     *q = nullptr;
   }
+  for (void* s : b.side) (void)hipStreamDestroy((hipStream_t)s);
+  for (void* e : b.ev_join) (void)hipEventDestroy((hipEvent_t)e);
+  if (b.ev_fork) (void)hipEventDestroy((hipEvent_t)b.ev_fork);
+  b.side.clear();
+  b.ev_join.clear();
+  b.ev_fork = nullptr;
 }
 
 int fused_batch_launch(const Batch& b, hipStream_t st, double2* per_item, double2* amps) {

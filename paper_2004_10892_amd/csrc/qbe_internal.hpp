@@ -203,6 +203,7 @@ struct Batch {
   size_t wide_ws = 0;               // workspace those need (all at once)
   std::vector<size_t> wide_off;     // per wide plan: its workspace region
   std::vector<WideItem> wide_order; // their launches, level by level
+  std::vector<int32_t> wide_level;  // level v: wide_order [wide_level[v], wide_level[v + 1])
   std::vector<WideGroupStep> wide_steps;
   std::vector<int32_t> wide_first;  // group g: wide_steps [first[g], first[g + 1])
   std::vector<uint64_t> wide_prefix;  // group g: count + 1 unit offsets from first[g] + g
@@ -215,6 +216,12 @@ struct Batch {
   void* d_ranges = nullptr;  // int64 (begin, end) per plan
   void* d_state = nullptr;   // uint32[2 + n_plans]: work, exits, items done per plan
   bool reduce_here = true;   // the fused kernel sums each plan's items itself
+  // the launches of one level of the per-step plans are independent: they
+  // are dealt over the caller's stream and these (default priority),
+  // forked from and joined back to the caller's stream by the events
+  std::vector<void*> side;     // hipStream_t
+  void* ev_fork = nullptr;     // hipEvent_t
+  std::vector<void*> ev_join;  // hipEvent_t, one per side stream
 };
 
 // -------------------------------------------------- learned proposal (GNN) --
