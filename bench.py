@@ -686,6 +686,7 @@ def cpu_baseline_slices(name, budget_s=10.0, max_workers=16):
 
 def bench_batch(torch, qbe, ctx, steps):
     """512 uneven instances: one batched call vs one launch per bucket."""
+    import numpy as np
     from circuitgen import batch_instances, circuit_model, random_grid_circuit
     t0 = time.perf_counter()
     plans_b, plans_p, scale = [], [], []
@@ -699,6 +700,10 @@ def bench_batch(torch, qbe, ctx, steps):
     batch = qbe.Batch(ctx, plans_b)
     ws = batch.workspace()
     amps = torch.zeros(2 * len(plans_b), dtype=torch.float64, device="cuda")
+    # issued directly (host enqueues every launch and event of the call),
+    # then replayed from a HIP graph of the same call
+    wall_d, ev_d = timed(torch, lambda: batch.contract_async(ws, amps), steps, 2)
+    res_d = amps.cpu().numpy().copy()
     g = graph_of(torch, qbe, ctx, lambda: batch.contract_async(ws, amps))
     wall_b, ev_b = timed(torch, g.replay, steps, 2)
     res_b = amps.cpu().numpy().copy()
@@ -710,11 +715,12 @@ def bench_batch(torch, qbe, ctx, steps):
             qbe.qbe_contract_async(ctx, p, wsp, outp[2 * i:])
     wall_p, ev_p = timed(torch, plain, max(1, steps // 4), 1)
     res_p = outp.cpu().numpy()
-    import numpy as np
     a, b = res_b.view(np.complex128), res_p.view(np.complex128)
     n_fused = sum(p.stats()["exec"] == 2 for p in plans_b)
     return {"workload": "batch512_grid4-6_d10-20_m0-6", "instances": len(plans_b), "fused_instances": n_fused,
             "batched_ms": ev_b, "batched_amplitudes_per_s": len(plans_b) / (ev_b * 1e-3),
+            "issue": {"graph": {"ms": ev_b, "wall_ms": wall_b}, "direct": {"ms": ev_d, "wall_ms": wall_d},
+                      "same_bits": bool(np.array_equal(res_d, res_b))},
             "plain_ms": ev_p, "plain_amplitudes_per_s": len(plans_p) / (ev_p * 1e-3),
             "speedup": ev_p / ev_b, "planning_ms_total": plan_ms,
             "max_diff_batched_vs_plain": float(np.max(np.abs(a - b) / np.maximum(np.abs(b), np.asarray(scale)))),
