@@ -578,15 +578,24 @@ int qbe_plan_profile(qbe_ctx* ctx, const qbe_plan* plan, void* d_workspace, size
  * contracted together.  Plans in the fused form share one persistent
  * launch: its (instance, slice) work items are pulled by a grid of
  * workgroups from a counter, biggest instances first.  Plans in the
- * per-step form (too wide for LDS) follow on the same stream.  The plans
- * must outlive the batch.  The work-item table is uploaded here. */
+ * per-step form (too wide for LDS) follow it level by level (Sec. 2.4: the
+ * instances are independent; within a plan, launches of one level share no
+ * memory): a level's launches are dealt over the context's stream and up to
+ * three side streams that the batch creates here (default priority) and
+ * owns until qbe_batch_destroy.  The plans must outlive the batch.  The
+ * work-item table is uploaded here. */
 int qbe_batch_create(qbe_ctx* ctx, const qbe_plan* const* plans, int32_t n_plans, qbe_batch** out);
 int qbe_batch_destroy(qbe_batch* batch);
 /* Workspace bytes qbe_batch_contract_async needs. */
 int qbe_batch_workspace(const qbe_batch* batch, size_t* ws_bytes_out);
 /* Enqueues the batch: instance i's slices are summed in FP64 into
  * d_amps_out[2 i], d_amps_out[2 i + 1] (device memory).  No allocation, copy
- * or synchronisation inside, so the call may be captured into a HIP graph. */
+ * or synchronisation inside, so the call may be captured into a HIP graph.
+ * Work on the batch's side streams starts after everything enqueued on the
+ * context's stream before the call, and the context's stream waits for it
+ * (events) before the call's last launch: later work on the context's
+ * stream sees every result.  Calls on one batch must not overlap (they share
+ * its side streams and events). */
 int qbe_batch_contract_async(qbe_ctx* ctx, const qbe_batch* batch, void* d_workspace, size_t ws_bytes,
                              double* d_amps_out);
 /* The batch in one synchronous call (Sec. 2.4: the subtasks of all plans
