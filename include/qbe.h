@@ -580,9 +580,10 @@ int qbe_plan_profile(qbe_ctx* ctx, const qbe_plan* plan, void* d_workspace, size
  * workgroups from a counter, biggest instances first.  Plans in the
  * per-step form (too wide for LDS) follow it level by level (Sec. 2.4: the
  * instances are independent; within a plan, launches of one level share no
- * memory): a level's launches are dealt over the context's stream and up to
- * three side streams that the batch creates here (default priority) and
- * owns until qbe_batch_destroy.  The plans must outlive the batch.  The
+ * memory): when the call is captured into a HIP graph, a level's launches
+ * are dealt over the context's stream and up to three side streams that the
+ * batch creates here (default priority) and owns until qbe_batch_destroy;
+ * issued directly, they run on the context's stream.  The plans must outlive the batch.  The
  * work-item table is uploaded here. */
 int qbe_batch_create(qbe_ctx* ctx, const qbe_plan* const* plans, int32_t n_plans, qbe_batch** out);
 int qbe_batch_destroy(qbe_batch* batch);

@@ -2222,12 +2222,18 @@ int dev_batch_contract(const Batch& b, void* stream, void* ws, size_t ws_bytes, 
     if (rc) return rc;
   }
   char* wide_ws = w + ws_head(b.n_items);
+  // levels are dealt over the side streams when the call is captured into a
+  // graph (branches replayed without host work); issued directly, the
+  // events per level would cost more host time than the overlap saves
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  QBE_HIP(hipStreamIsCapturing(st, &cap));
+  const size_t n_side = cap == hipStreamCaptureStatusActive ? b.side.size() : 0;
   for (size_t v = 0; v + 1 < b.wide_level.size(); ++v) {
     // a level's launches have no memory hazard with one another: deal them
     // over the caller's stream and up to n side streams, which start after
     // everything the caller's stream holds and rejoin it at the level's end
     const int32_t i0 = b.wide_level[v], i1 = b.wide_level[v + 1];
-    const int n = (int)std::min<size_t>(b.side.size(), (size_t)(i1 - i0 - 1));
+    const int n = (int)std::min<size_t>(n_side, (size_t)(i1 - i0 - 1));
     if (n > 0) {
       QBE_HIP(hipEventRecord((hipEvent_t)b.ev_fork, st));
       for (int s = 0; s < n; ++s) QBE_HIP(hipStreamWaitEvent((hipStream_t)b.side[s], (hipEvent_t)b.ev_fork, 0));
