@@ -242,7 +242,7 @@ STEP_SOURCES = ("device.hip", "device_common.hpp", "qbe_internal.hpp", "program.
 # dominant: the same for the dominant kernel's launch.  Keyed by the
 # sources' digest and the plan's sliced set.
 C3_COUNTERS = {
-    "sources_sha256": "d9913ec56775dfd08fc81c5facaf4db5efe9e61689c6d9fa71f6bd6c37f75f4f",
+    "sources_sha256": "63b1d349e053d6e9c26ee8c457492ad0801ed582060a62bd57813c3a7660407b",
     "plan": "min_fill+tt_rec2_t16_s5+segments+sums2",
     "mu": [
         119,
@@ -259,24 +259,24 @@ C3_COUNTERS = {
     "fp32": {
         "mfma_util": 0.0,
         "mfma_busy_cycles": 0.0,
-        "gui_active": 6356006.0,
+        "gui_active": 6689689.0,
         "amplitude": {
-            "bytes": 472954016,
-            "fetch_kib": 118750.5625,
+            "bytes": 472980128,
+            "fetch_kib": 118763.3125,
             "write_kib": 224368.03125
         },
         "dominant": {
             "launch": 0,
             "kernel": "qbe::fused_kernel",
-            "bytes": 39787520,
-            "fetch_kib": 5571.5,
+            "bytes": 39785984,
+            "fetch_kib": 5570.75,
             "write_kib": 27712.0
         }
     },
     "bf16x6": {
-        "mfma_util": 0.0011577967263975957,
+        "mfma_util": 0.0011520879907202912,
         "mfma_busy_cycles": 1048576.0,
-        "gui_active": 7075508.0
+        "gui_active": 7110568.0
     },
     "plain_fp32": {
         "mfma_util": 0.0
